@@ -1,0 +1,140 @@
+"""O2: FP64 oracle over the per-state successor lists of Def. 3 (test
+infrastructure).
+
+Def. 3 represents the model of each state s as the list of its tensor
+components (s, s', P(s'|s,a)) with P(s'|s,a) > 0.  Here the lists are built by
+enumerating the non-zeros of every rank term's Kronecker product (the product
+of the per-dimension factor entries, times lambda), merging repeated
+successors, and dropping the rows of terminal states (the interaction ends
+there, Sec. 3.2).  They are stored as one CSR matrix per action.  Value
+iteration and policy iteration then run by plain sweeps of Eq. 1.
+
+Reach: factors with few non-zeros per row (identity and shift factors);
+a dense m x m factor multiplies the list length by m per dimension.
+"""
+import numpy as np
+import scipy.sparse as sp
+
+from .common import greedy, improve
+
+MAX_TRIPLES = 400_000_000
+
+
+def component_lists(inst, a: int):
+    """Def. 3 triples of action a as arrays (s, s', p), before merging."""
+    S_list, Sp_list, p_list = [], [], []
+    for t in inst.terms_of(a):
+        s = np.zeros(1, np.int64)
+        sp_ = np.zeros(1, np.int64)
+        p = np.array([inst.lambdas[t]])
+        count = 1
+        for k in range(inst.n_dims):
+            T = inst.factor(t, k)
+            m = T.shape[0]
+            i_k, j_k = np.nonzero(T)
+            v_k = T[i_k, j_k]
+            count *= len(v_k)
+            if count > MAX_TRIPLES:
+                raise ValueError("successor lists too long for the sparse oracle")
+            s = (s[:, None] * m + i_k[None, :]).ravel()
+            sp_ = (sp_[:, None] * m + j_k[None, :]).ravel()
+            p = (p[:, None] * v_k[None, :]).ravel()
+        S_list.append(s)
+        Sp_list.append(sp_)
+        p_list.append(p)
+    return np.concatenate(S_list), np.concatenate(Sp_list), np.concatenate(p_list)
+
+
+def transition_csr(inst):
+    """List of A CSR matrices, row s = the merged Def. 3 list of state s;
+    terminal rows are empty."""
+    S = inst.n_states
+    live = inst.terminal == 0
+    mats = []
+    for a in range(inst.n_actions):
+        s, s2, p = component_lists(inst, a)
+        keep = live[s] & (p > 0)
+        M = sp.coo_matrix((p[keep], (s[keep], s2[keep])), shape=(S, S)).tocsr()
+        M.sum_duplicates()
+        mats.append(M)
+    return mats
+
+
+def q_values(inst, mats, V) -> np.ndarray:
+    """Q[a, s] = R(s) + gamma * (P_a V)(s); terminal rows are empty so their
+    continuation is zero."""
+    Q = np.empty((len(mats), inst.n_states))
+    for a, M in enumerate(mats):
+        Q[a] = inst.rewards + inst.gamma * (M @ V)
+    return Q
+
+
+def backup(inst, V, mats=None):
+    """One Bellman backup: (max_a Q_a, greedy pi, Q)."""
+    if mats is None:
+        mats = transition_csr(inst)
+    Q = q_values(inst, mats, np.asarray(V, np.float64))
+    return Q.max(axis=0), greedy(Q, V), Q
+
+
+def value_iteration(inst, eps=1e-13, max_iter=100000, V0=None, mats=None,
+                    callback=None):
+    """Sweeps until ||V' - V||_inf <= eps.  Returns (V, pi, sweeps, residual)
+    as the dense oracle does."""
+    if mats is None:
+        mats = transition_csr(inst)
+    V = np.zeros(inst.n_states) if V0 is None else np.array(V0, np.float64)
+    sweeps = 0
+    while sweeps < max_iter:
+        Vn = q_values(inst, mats, V).max(axis=0)
+        sweeps += 1
+        res = float(np.max(np.abs(Vn - V)))
+        V = Vn
+        if callback is not None:
+            callback(sweeps, res)
+        if res <= eps:
+            break
+    Q = q_values(inst, mats, V)
+    res = float(np.max(np.abs(Q.max(axis=0) - V)))
+    return V, greedy(Q, V), sweeps, res
+
+
+def policy_matrix(inst, mats, pi):
+    """CSR P_pi whose row s is row s of P_{pi(s)}."""
+    S = inst.n_states
+    out = None
+    for a, M in enumerate(mats):
+        sel = sp.diags((pi == a).astype(np.float64), shape=(S, S), format="csr")
+        part = sel @ M
+        out = part if out is None else out + part
+    return out.tocsr()
+
+
+def evaluate(inst, mats, pi, V0=None, eps=1e-13, max_iter=1000000):
+    """V_pi by sweeps V <- R + gamma P_pi V until the change is <= eps."""
+    P_pi = policy_matrix(inst, mats, pi)
+    V = np.zeros(inst.n_states) if V0 is None else np.array(V0, np.float64)
+    for _ in range(max_iter):
+        Vn = inst.rewards + inst.gamma * (P_pi @ V)
+        res = float(np.max(np.abs(Vn - V)))
+        V = Vn
+        if res <= eps:
+            break
+    return V
+
+
+def policy_iteration(inst, pi0=None, eps=1e-13, max_outer=10000, mats=None):
+    """Evaluation by sweeps + greedy improvement with the incumbent rule, until
+    the policy is unchanged.  Returns (V, pi, outer_iterations)."""
+    if mats is None:
+        mats = transition_csr(inst)
+    pi = np.zeros(inst.n_states, np.int32) if pi0 is None else \
+        np.array(pi0, np.int32)
+    V = None
+    for it in range(1, max_outer + 1):
+        V = evaluate(inst, mats, pi, V0=V, eps=eps)
+        pi_new = improve(q_values(inst, mats, V), V, pi)
+        if np.array_equal(pi_new, pi):
+            return V, pi, it
+        pi = pi_new
+    return V, pi, max_outer

@@ -1,0 +1,102 @@
+"""O3: FP64 oracle that applies each rank term as a chain of mode products
+(test infrastructure).
+
+For the CP form P_a = sum_r lambda_{a,r} kron_k T^(k)_{a,r} (a sum of rank-one
+terms, Sec. 2.2), applying P_a to the value vector reshaped as an n-way tensor
+(row-major order, Def. 2) is, term by term, the mode-k product of V with every
+factor: U[.., i_k, ..] = sum_j T^(k)[i_k, j] V[.., j, ..].  The Q-values are
+those of Eq. 1: Q_a = R + gamma (1 - tau) sum_r lambda_{a,r} U_{a,r}.  Each mode
+product is one numpy tensordot; nothing is blocked or fused.  Works for dense
+factors too; the cost per backup is 2 * sum_a R_a * sum_k m_k flops per state.
+"""
+import numpy as np
+
+from .common import greedy, improve
+
+
+def mode_product(X: np.ndarray, T: np.ndarray, k: int) -> np.ndarray:
+    """(X x_k T)[.., i, ..] = sum_j T[i, j] X[.., j, ..]."""
+    Y = np.tensordot(T, X, axes=([1], [k]))   # new axis 0 = i
+    return np.moveaxis(Y, 0, k)
+
+
+def apply_term(inst, t: int, Vt: np.ndarray) -> np.ndarray:
+    U = Vt
+    for k in range(inst.n_dims):
+        U = mode_product(U, inst.factor(t, k), k)
+    return U
+
+
+def apply_action(inst, a: int, V: np.ndarray) -> np.ndarray:
+    """(P_a V) as a flat vector, by mode-product chains."""
+    shape = tuple(int(m) for m in inst.sizes)
+    Vt = np.asarray(V, np.float64).reshape(shape)
+    acc = np.zeros(shape)
+    for t in inst.terms_of(a):
+        acc += inst.lambdas[t] * apply_term(inst, t, Vt)
+    return acc.ravel()
+
+
+def q_values(inst, V) -> np.ndarray:
+    c = inst.gamma * (1.0 - inst.terminal.astype(np.float64))
+    Q = np.empty((inst.n_actions, inst.n_states))
+    for a in range(inst.n_actions):
+        Q[a] = inst.rewards + c * apply_action(inst, a, V)
+    return Q
+
+
+def backup(inst, V):
+    """One Bellman backup: (max_a Q_a, greedy pi, Q)."""
+    Q = q_values(inst, V)
+    return Q.max(axis=0), greedy(Q, V), Q
+
+
+def policy_apply(inst, V, pi) -> np.ndarray:
+    """(P_pi V)(s) = (P_{pi(s)} V)(s), evaluated for every action then
+    selected per state."""
+    out = np.zeros(inst.n_states)
+    for a in range(inst.n_actions):
+        sel = pi == a
+        if np.any(sel):
+            out[sel] = apply_action(inst, a, V)[sel]
+    return out
+
+
+def value_iteration(inst, eps=1e-13, max_iter=100000, V0=None):
+    V = np.zeros(inst.n_states) if V0 is None else np.array(V0, np.float64)
+    sweeps = 0
+    while sweeps < max_iter:
+        Vn = q_values(inst, V).max(axis=0)
+        sweeps += 1
+        res = float(np.max(np.abs(Vn - V)))
+        V = Vn
+        if res <= eps:
+            break
+    Q = q_values(inst, V)
+    res = float(np.max(np.abs(Q.max(axis=0) - V)))
+    return V, greedy(Q, V), sweeps, res
+
+
+def evaluate(inst, pi, V0=None, eps=1e-13, max_iter=1000000):
+    c = inst.gamma * (1.0 - inst.terminal.astype(np.float64))
+    V = np.zeros(inst.n_states) if V0 is None else np.array(V0, np.float64)
+    for _ in range(max_iter):
+        Vn = inst.rewards + c * policy_apply(inst, V, pi)
+        res = float(np.max(np.abs(Vn - V)))
+        V = Vn
+        if res <= eps:
+            break
+    return V
+
+
+def policy_iteration(inst, pi0=None, eps=1e-13, max_outer=10000):
+    pi = np.zeros(inst.n_states, np.int32) if pi0 is None else \
+        np.array(pi0, np.int32)
+    V = None
+    for it in range(1, max_outer + 1):
+        V = evaluate(inst, pi, V0=V, eps=eps)
+        pi_new = improve(q_values(inst, V), V, pi)
+        if np.array_equal(pi_new, pi):
+            return V, pi, it
+        pi = pi_new
+    return V, pi, max_outer

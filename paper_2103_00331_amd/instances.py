@@ -1,0 +1,333 @@
+"""Seeded synthetic MDP instances: the one module that both the CPU oracle and
+the GPU path read.
+
+It builds inputs only -- sizes, transition factors, mixture weights, rewards,
+terminal masks and discount factors as FP64 host arrays -- and performs none
+of the solver's arithmetic (no backup, no mode product, no max).
+
+Problem statement followed (Kuinchtner, Sales & Meneguzzi, CP-MDP):
+  * the MDP tuple <S, A, P, R, gamma> of Sec. 2.1;
+  * dimensions d_1..d_D each with its own number of states (Def. 1) and the
+    state space as their Cartesian product, enumerated with the LAST
+    dimension varying fastest (Def. 2), i.e. row-major:
+    s = sum_k i_k * prod_{j>k} m_j;
+  * GridWorld with two actions per axis, |A| = 2|D| (Sec. 3.2), and terminal
+    states that end the interaction (Sec. 3.2).
+
+The transition model of action a is a rank-R_a Kronecker/CP sum over the
+dimensions, P_a = sum_r lambda_{a,r} kron_k T^{(k)}_{a,r}, each factor an
+m_k x m_k row-stochastic matrix with T[i, j] = P(next coordinate j | current
+coordinate i).  The paper does not state a slip model, reward noise, goal
+placement or seeds; the readings used here are:
+  * action index a = 2k + (0 for a +1 move along dim k, 1 for a -1 move);
+  * an action moves as intended with probability 1 - slip, and the slip mass
+    is split evenly over the 2(n-1) perpendicular unit moves, giving rank
+    2n - 1; a move off the grid stays put (clamped shift);
+  * terminal states take V(s) = R(s) and no continuation;
+  * rewards are per state, i.i.d. normal with the stated standard deviation,
+    with the goal corner (m-1, ..., m-1) set to +1 and made terminal.
+
+Flat factor layout (shared with the C ABI): for term t = 0..sum_a R_a - 1
+(action-major: all terms of action 0, then action 1, ...), for dim k, one
+m_k x m_k row-major block.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+# Seeds of the named workloads.
+SEED_GRID4 = 20210002        # 32^4 GridWorld
+SEED_GRID4_LARGE = 20210012  # 96^4 GridWorld (HBM-resident supplement)
+SEED_DENSE6 = 20210003       # 16^6 dense-factor grid
+SEED_DENSE6_SMALL = 20210013  # 12^6 dense-factor grid (parity instance)
+SEED_BATCH = 20210004        # 512 mixed GridWorlds
+SEED_WARM = 20210005         # 64^3 warm-start instances
+
+
+@dataclass
+class Instance:
+    """One MDP, all arrays FP64 / integer host arrays."""
+
+    sizes: np.ndarray            # int64 [n]
+    ranks: np.ndarray            # int32 [A]
+    factors: np.ndarray          # float64 flat, layout described above
+    lambdas: np.ndarray          # float64 [sum R]
+    rewards: np.ndarray          # float64 [S], row-major state order
+    gamma: float
+    terminal: np.ndarray         # uint8 [S], 1 = terminal
+    name: str = ""
+    meta: Dict[str, float] = field(default_factory=dict)
+
+    @property
+    def n_dims(self) -> int:
+        return int(self.sizes.shape[0])
+
+    @property
+    def n_states(self) -> int:
+        return int(np.prod(self.sizes))
+
+    @property
+    def n_actions(self) -> int:
+        return int(self.ranks.shape[0])
+
+    @property
+    def n_terms(self) -> int:
+        return int(self.ranks.sum())
+
+    @property
+    def term_stride(self) -> int:
+        return int(sum(int(m) * int(m) for m in self.sizes))
+
+    def term_index(self, a: int, r: int) -> int:
+        return int(self.ranks[:a].sum()) + r
+
+    def factor(self, t: int, k: int) -> np.ndarray:
+        """View of T^{(k)} of flat term t as an m_k x m_k matrix."""
+        off = t * self.term_stride + sum(int(m) * int(m) for m in self.sizes[:k])
+        m = int(self.sizes[k])
+        return self.factors[off:off + m * m].reshape(m, m)
+
+    def terms_of(self, a: int) -> List[int]:
+        start = int(self.ranks[:a].sum())
+        return list(range(start, start + int(self.ranks[a])))
+
+
+def _pack(sizes: Sequence[int], per_action: List[List[tuple]]) -> tuple:
+    """per_action[a] = list of (lambda, [T_0, ..., T_{n-1}]) -> flat arrays."""
+    blocks, lams, ranks = [], [], []
+    for terms in per_action:
+        ranks.append(len(terms))
+        for lam, mats in terms:
+            lams.append(float(lam))
+            for k, T in enumerate(mats):
+                assert T.shape == (sizes[k], sizes[k])
+                blocks.append(np.ascontiguousarray(T, dtype=np.float64).ravel())
+    return (np.concatenate(blocks), np.asarray(lams, np.float64),
+            np.asarray(ranks, np.int32))
+
+
+def shift_matrix(m: int, step: int) -> np.ndarray:
+    """Clamped unit move along one axis: row i has a single 1 at i+step,
+    clamped to [0, m-1] (a move off the grid stays put)."""
+    T = np.zeros((m, m))
+    for i in range(m):
+        T[i, min(max(i + step, 0), m - 1)] = 1.0
+    return T
+
+
+def gridworld_terms(sizes: Sequence[int], slip: float) -> List[List[tuple]]:
+    """Per-action CP terms of the slip GridWorld: 2n actions, rank 2n-1
+    (n >= 2) or 1 (n == 1).  Term order inside an action: the intended move,
+    then for every other dim j in ascending order the +1 and the -1 slip."""
+    n = len(sizes)
+    eye = [np.eye(m) for m in sizes]
+    per_action = []
+    for k in range(n):
+        for step in (+1, -1):
+            mats = list(eye)
+            mats[k] = shift_matrix(sizes[k], step)
+            if n == 1:
+                terms = [(1.0, mats)]
+            else:
+                terms = [(1.0 - slip, mats)]
+                w = slip / (2 * (n - 1))
+                for j in range(n):
+                    if j == k:
+                        continue
+                    for s2 in (+1, -1):
+                        mj = list(eye)
+                        mj[j] = shift_matrix(sizes[j], s2)
+                        terms.append((w, mj))
+            per_action.append(terms)
+    return per_action
+
+
+def flat_index(sizes: Sequence[int], coords: Sequence[int]) -> int:
+    """Row-major (last dimension fastest) state index of Def. 2."""
+    s = 0
+    for m, i in zip(sizes, coords):
+        s = s * int(m) + int(i)
+    return s
+
+
+def make_gridworld(sizes, slip, rewards, gamma, terminals=(), name="",
+                   meta=None) -> Instance:
+    sizes = [int(m) for m in sizes]
+    S = int(np.prod(sizes))
+    factors, lams, ranks = _pack(sizes, gridworld_terms(sizes, slip))
+    rewards = np.asarray(rewards, np.float64).reshape(S).copy()
+    term = np.zeros(S, np.uint8)
+    for coords, rv in terminals:
+        s = flat_index(sizes, coords)
+        rewards[s] = rv
+        term[s] = 1
+    m = {"slip": float(slip)}
+    if meta:
+        m.update(meta)
+    return Instance(np.asarray(sizes, np.int64), ranks, factors, lams, rewards,
+                    float(gamma), term, name, m)
+
+
+# ---------------------------------------------------------------- workloads
+
+def grid2d_16() -> Instance:
+    """16x16 GridWorld, 4 actions, rank 3 (0.8 / 0.1 / 0.1), step reward
+    -0.04, terminal goal +1 at (15,15) and terminal pit -1 at (8,8),
+    gamma = 0.95."""
+    sizes = [16, 16]
+    return make_gridworld(sizes, 0.2, np.full(256, -0.04), 0.95,
+                          terminals=[((15, 15), 1.0), ((8, 8), -1.0)],
+                          name="grid2d_16x16")
+
+
+def _noisy_goal_grid(sizes, slip, gamma, rng, name, meta=None) -> Instance:
+    S = int(np.prod(sizes))
+    R = rng.normal(0.0, 0.1, S)
+    goal = tuple(int(m) - 1 for m in sizes)
+    return make_gridworld(sizes, slip, R, gamma, terminals=[(goal, 1.0)],
+                          name=name, meta=meta)
+
+
+def grid4d(m: int = 32, seed: int = SEED_GRID4) -> Instance:
+    """m^4 GridWorld, 8 actions, slip 0.1 over the 6 perpendicular moves
+    (rank 7), rewards N(0, 0.1) per state, +1 terminal goal corner,
+    gamma = 0.99."""
+    rng = np.random.default_rng(seed)
+    return _noisy_goal_grid([m] * 4, 0.1, 0.99, rng, f"grid4d_{m}^4")
+
+
+def grid_small(sizes, slip=0.1, gamma=0.99, seed=0) -> Instance:
+    """Same generator as grid4d at arbitrary sizes (tests)."""
+    rng = np.random.default_rng(seed)
+    return _noisy_goal_grid(list(sizes), slip, gamma, rng,
+                            "grid_" + "x".join(map(str, sizes)))
+
+
+def dense_grid(m: int = 16, n: int = 6, n_actions: int = 12, rank: int = 8,
+               seed: int = SEED_DENSE6, gamma: float = 0.95,
+               alpha: float = 0.5) -> Instance:
+    """n-D grid with dense factors: lambda_a ~ Dirichlet(1), each factor row
+    ~ Dirichlet(alpha), rewards N(0, 0.1), no terminals."""
+    rng = np.random.default_rng(seed)
+    sizes = [m] * n
+    per_action = []
+    for _a in range(n_actions):
+        lam = rng.dirichlet(np.ones(rank))
+        lam = lam / lam.sum()
+        terms = []
+        for r in range(rank):
+            mats = []
+            for k in range(n):
+                T = rng.dirichlet(alpha * np.ones(sizes[k]), size=sizes[k])
+                T = T / T.sum(axis=1, keepdims=True)
+                mats.append(T)
+            terms.append((lam[r], mats))
+        per_action.append(terms)
+    factors, lams, ranks = _pack(sizes, per_action)
+    S = int(np.prod(sizes))
+    R = rng.normal(0.0, 0.1, S)
+    return Instance(np.asarray(sizes, np.int64), ranks, factors, lams, R,
+                    float(gamma), np.zeros(S, np.uint8),
+                    f"dense_{m}^{n}", {"alpha": alpha})
+
+
+def batch_instance(i: int, base: int = SEED_BATCH) -> Instance:
+    """Instance i of the 512-instance mixed batch: n ~ U{2,3,4},
+    m ~ U{8..48}, slip ~ U[0.05, 0.3], gamma ~ U[0.9, 0.99], rewards
+    N(0, 0.1) plus a +1 terminal goal corner."""
+    rng = np.random.default_rng(np.random.SeedSequence([base, i]))
+    n = int(rng.integers(2, 5))
+    m = int(rng.integers(8, 49))
+    slip = float(rng.uniform(0.05, 0.3))
+    gamma = float(rng.uniform(0.9, 0.99))
+    return _noisy_goal_grid([m] * n, slip, gamma, rng, f"batch{i}_{m}^{n}",
+                            meta={"index": i})
+
+
+def batch_shapes(count: int = 512, base: int = SEED_BATCH):
+    """(n, m) of each batch instance without building the arrays."""
+    out = []
+    for i in range(count):
+        rng = np.random.default_rng(np.random.SeedSequence([base, i]))
+        out.append((int(rng.integers(2, 5)), int(rng.integers(8, 49))))
+    return out
+
+
+def warm_instance(split: int, i: int, m: int = 64,
+                  base: int = SEED_WARM) -> Instance:
+    """64^3 instance for the learned warm start; split 0 = train,
+    1 = validation, 2 = test.  Slip and gamma drawn as in the batch."""
+    rng = np.random.default_rng(np.random.SeedSequence([base, split, i]))
+    slip = float(rng.uniform(0.05, 0.3))
+    gamma = float(rng.uniform(0.9, 0.99))
+    return _noisy_goal_grid([m] * 3, slip, gamma, rng,
+                            f"warm{split}_{i}_{m}^3",
+                            meta={"split": split, "index": i})
+
+
+# ------------------------------------------------------- small test builders
+
+def random_dense(sizes, n_actions, rank, seed, gamma=0.9, alpha=1.0,
+                 n_terminal=0, reward_scale=1.0) -> Instance:
+    """Tiny random instance with dense factors (and optional terminals)."""
+    rng = np.random.default_rng(seed)
+    sizes = [int(m) for m in sizes]
+    S = int(np.prod(sizes))
+    ranks = np.atleast_1d(rank)
+    if ranks.size == 1:
+        ranks = np.full(n_actions, int(ranks[0]))
+    per_action = []
+    for a in range(n_actions):
+        lam = rng.dirichlet(np.ones(int(ranks[a])))
+        terms = []
+        for r in range(int(ranks[a])):
+            mats = [rng.dirichlet(alpha * np.ones(m), size=m) for m in sizes]
+            mats = [T / T.sum(axis=1, keepdims=True) for T in mats]
+            terms.append((lam[r] / lam.sum(), mats))
+        per_action.append(terms)
+    factors, lams, rk = _pack(sizes, per_action)
+    R = rng.normal(0.0, reward_scale, S)
+    term = np.zeros(S, np.uint8)
+    if n_terminal:
+        term[rng.choice(S, n_terminal, replace=False)] = 1
+    return Instance(np.asarray(sizes, np.int64), rk, factors, lams, R,
+                    float(gamma), term, "random_dense")
+
+
+def chain_1d(m: int, step_reward: float, goal_reward: float,
+             gamma: float) -> Instance:
+    """Deterministic 1-D chain (slip 0), goal at i = m-1, terminal."""
+    R = np.full(m, step_reward)
+    return make_gridworld([m], 0.0, R, gamma,
+                          terminals=[((m - 1,), goal_reward)], name="chain")
+
+
+def with_rewards(inst: Instance, rewards, terminal=None) -> Instance:
+    """Copy of inst with other rewards (and optionally another mask)."""
+    S = inst.n_states
+    term = inst.terminal.copy() if terminal is None else \
+        np.asarray(terminal, np.uint8).reshape(S)
+    return Instance(inst.sizes.copy(), inst.ranks.copy(), inst.factors.copy(),
+                    inst.lambdas.copy(),
+                    np.asarray(rewards, np.float64).reshape(S).copy(),
+                    inst.gamma, term, inst.name, dict(inst.meta))
+
+
+def seeded_values(n: int, seed: int, scale: float = 1.0) -> np.ndarray:
+    """A seeded FP64 value vector (e.g. the common V fed to one backup)."""
+    return np.random.default_rng(seed).normal(0.0, scale, n)
+
+
+def named(name: str) -> Instance:
+    """Workloads by name."""
+    table = {
+        "grid2d_16x16": grid2d_16,
+        "grid4d_32": lambda: grid4d(32, SEED_GRID4),
+        "grid4d_96": lambda: grid4d(96, SEED_GRID4_LARGE),
+        "dense6_16": lambda: dense_grid(16, seed=SEED_DENSE6),
+        "dense6_12": lambda: dense_grid(12, seed=SEED_DENSE6_SMALL),
+    }
+    return table[name]()

@@ -1,0 +1,310 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle:
+the elementwise definition of the CP/Kronecker operator, stochasticity,
+brute-force policy enumeration, closed forms of special cases, the Bellman
+fixed point, the paper's state order (Def. 2) and its action count (Sec. 3.2,
+Table 1).  CPU only."""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import dense, sparse, structured
+from paper_2103_00331_amd import instances as I
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _coords(sizes, s):
+    out = []
+    for m in reversed(list(sizes)):
+        out.append(s % m)
+        s //= m
+    return list(reversed(out))
+
+
+# ------------------------------------------------------------ operator form
+
+def test_kron_equals_elementwise_definition():
+    """P_a[s, s'] = sum_r lambda_r prod_k T_k[i_k, j_k], evaluated entry by
+    entry with plain loops, equals the dense, sparse and structured forms."""
+    inst = I.random_dense([2, 3, 2], n_actions=2, rank=3, seed=1)
+    S = inst.n_states
+    P = dense.transition_matrices(inst)
+    mats = sparse.transition_csr(inst)
+    for a in range(inst.n_actions):
+        ref = np.zeros((S, S))
+        for s in range(S):
+            ci = _coords(inst.sizes, s)
+            for s2 in range(S):
+                cj = _coords(inst.sizes, s2)
+                tot = 0.0
+                for t in inst.terms_of(a):
+                    prod = inst.lambdas[t]
+                    for k in range(inst.n_dims):
+                        prod *= inst.factor(t, k)[ci[k], cj[k]]
+                    tot += prod
+                ref[s, s2] = tot
+        np.testing.assert_allclose(P[a], ref, rtol=0, atol=1e-15)
+        np.testing.assert_allclose(mats[a].toarray(), ref, rtol=0, atol=1e-15)
+        # structured: apply to each basis vector -> columns of P_a
+        cols = np.stack([structured.apply_action(inst, a, e)
+                         for e in np.eye(S)], axis=1)
+        np.testing.assert_allclose(cols, ref, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("maker", [
+    lambda: I.random_dense([3, 4], 3, 2, seed=2, n_terminal=2),
+    lambda: I.grid_small([3, 4, 2], seed=3),
+    lambda: I.grid2d_16(),
+])
+def test_rows_stochastic(maker):
+    """Factor rows sum to 1 and sum_r lambda = 1, so every non-terminal row
+    of P_a sums to 1 in all three representations."""
+    inst = maker()
+    live = inst.terminal == 0
+    ones = np.ones(inst.n_states)
+    mats = sparse.transition_csr(inst)
+    for a in range(inst.n_actions):
+        np.testing.assert_allclose(mats[a] @ ones, live.astype(float),
+                                   atol=1e-14)
+        np.testing.assert_allclose(structured.apply_action(inst, a, ones),
+                                   ones, atol=1e-14)
+    if inst.n_states <= 512:
+        P = dense.transition_matrices(inst)
+        np.testing.assert_allclose(P.sum(axis=2), 1.0, atol=1e-14)
+
+
+# ------------------------------------------------------------- brute force
+
+@pytest.mark.parametrize("maker", [
+    lambda: I.random_dense([2, 3], 3, 2, seed=4, gamma=0.9),
+    lambda: I.random_dense([2, 3], 2, [1, 3], seed=5, gamma=0.8, n_terminal=1),
+    lambda: I.grid_small([2, 3], slip=0.2, gamma=0.95, seed=6),
+    lambda: I.make_gridworld([2, 3], 0.2, [-0.04] * 6, 0.9,
+                             terminals=[((1, 2), 1.0), ((0, 2), -1.0)]),
+])
+def test_brute_force_enumeration(maker):
+    """V* = elementwise max over all A^S deterministic policies; VI and PI
+    reach it and pick actions that some optimal policy takes."""
+    inst = maker()
+    vstar, optimal = dense.brute_force(inst)
+    V, pi, _, res = dense.value_iteration(inst)
+    assert res <= 1e-12
+    np.testing.assert_allclose(V, vstar, atol=1e-10)
+    for s in range(inst.n_states):
+        assert int(pi[s]) in optimal[s]
+    Vp, pip, _ = dense.policy_iteration(inst)
+    np.testing.assert_allclose(Vp, vstar, atol=1e-10)
+    for s in range(inst.n_states):
+        assert int(pip[s]) in optimal[s]
+    V2, pi2, _, _ = sparse.value_iteration(inst)
+    np.testing.assert_allclose(V2, vstar, atol=1e-10)
+    V3, pi3, _, _ = structured.value_iteration(inst)
+    np.testing.assert_allclose(V3, vstar, atol=1e-10)
+
+
+# ------------------------------------------------------------ closed forms
+
+@pytest.mark.parametrize("tier", ["dense", "sparse", "structured"])
+def test_deterministic_chain_closed_form(tier):
+    """1-D chain, no slip, step reward c, terminal goal G at distance d:
+    V(s) = c (1 - gamma^d) / (1 - gamma) + gamma^d G, optimal move = +1."""
+    m, c, G, g = 12, -0.04, 1.0, 0.9
+    inst = I.chain_1d(m, c, G, g)
+    mod = {"dense": dense, "sparse": sparse, "structured": structured}[tier]
+    V, pi, _, _ = mod.value_iteration(inst)
+    d = (m - 1) - np.arange(m)
+    closed = c * (1 - g ** d) / (1 - g) + g ** d * G
+    np.testing.assert_allclose(V, closed, atol=1e-11)
+    assert np.all(pi[:-1] == 0)      # action 0 = +1 along the only axis
+
+
+@pytest.mark.parametrize("tier", ["dense", "sparse", "structured"])
+def test_deterministic_grid_manhattan_closed_form(tier):
+    """2-D/3-D grid with slip 0 (the slip terms keep lambda = 0): the value is
+    the chain formula with d = Manhattan distance to the goal corner."""
+    sizes, c, G, g = [4, 5, 3], -0.1, 2.0, 0.85
+    if tier == "dense":
+        sizes = [4, 5]
+    S = int(np.prod(sizes))
+    goal = tuple(m - 1 for m in sizes)
+    inst = I.make_gridworld(sizes, 0.0, np.full(S, c), g,
+                            terminals=[(goal, G)])
+    mod = {"dense": dense, "sparse": sparse, "structured": structured}[tier]
+    V, _, _, _ = mod.value_iteration(inst)
+    d = np.array([sum(m - 1 - x for m, x in zip(sizes, _coords(sizes, s)))
+                  for s in range(S)])
+    closed = c * (1 - g ** d) / (1 - g) + g ** d * G
+    np.testing.assert_allclose(V, closed, atol=1e-11)
+
+
+@pytest.mark.parametrize("tier", ["dense", "sparse", "structured"])
+def test_constant_reward_any_factors(tier):
+    """No terminals and R = c everywhere: V* = c / (1 - gamma) for any
+    stochastic factors and ranks."""
+    base = I.random_dense([3, 2, 3], 3, [2, 1, 4], seed=7, gamma=0.93)
+    inst = I.with_rewards(base, np.full(base.n_states, 0.37))
+    mod = {"dense": dense, "sparse": sparse, "structured": structured}[tier]
+    V, _, _, _ = mod.value_iteration(inst)
+    np.testing.assert_allclose(V, 0.37 / (1 - 0.93), atol=1e-10)
+
+
+@pytest.mark.parametrize("tier", ["dense", "sparse", "structured"])
+def test_separable_reward_fixed_policy(tier):
+    """R(s) = sum_k f_k(i_k), no terminals, a fixed action a:
+    V_pi = sum_k (I - gamma M_k)^{-1} f_k with M_k = sum_r lambda_r T^(k)_r.
+    Sensitive to transposed factors and to the dimension order."""
+    base = I.random_dense([4, 3, 5], 2, 3, seed=8, gamma=0.9)
+    rng = np.random.default_rng(9)
+    f = [rng.normal(size=int(m)) for m in base.sizes]
+    grids = np.meshgrid(*[np.arange(int(m)) for m in base.sizes],
+                        indexing="ij")
+    R = sum(f[k][grids[k]] for k in range(base.n_dims)).ravel()
+    inst = I.with_rewards(base, R)
+    a = 1
+    pi = np.full(inst.n_states, a, np.int32)
+    closed = np.zeros(tuple(int(m) for m in inst.sizes))
+    for k in range(inst.n_dims):
+        M = sum(inst.lambdas[t] * inst.factor(t, k) for t in inst.terms_of(a))
+        v = np.linalg.solve(np.eye(int(inst.sizes[k])) - inst.gamma * M, f[k])
+        shape = [1] * inst.n_dims
+        shape[k] = -1
+        closed = closed + v.reshape(shape)
+    closed = closed.ravel()
+    if tier == "dense":
+        Vpi = dense.evaluate(inst, dense.transition_matrices(inst), pi)
+    elif tier == "sparse":
+        Vpi = sparse.evaluate(inst, sparse.transition_csr(inst), pi)
+    else:
+        Vpi = structured.evaluate(inst, pi)
+    np.testing.assert_allclose(Vpi, closed, atol=1e-11)
+
+
+# ------------------------------------------------- fixed point, VI vs PI
+
+def test_fixed_point_and_vi_pi_agree_grid16():
+    inst = I.grid2d_16()
+    P = dense.transition_matrices(inst)
+    V, pi, sweeps, res = dense.value_iteration(inst, P=P)
+    assert res <= 1e-13
+    Vp, _, _ = dense.policy_iteration(inst, P=P)
+    # ||V - V*|| <= res / (1 - gamma) (contraction bound)
+    assert np.max(np.abs(V - Vp)) <= res / (1 - inst.gamma) + 1e-12
+    Qp = dense.q_values(inst, P, Vp)
+    assert np.array_equal(oracle.greedy(Qp, Vp), pi)
+    # the 14 exact diagonal ties +x / +y and the two terminals
+    srt = np.sort(dense.q_values(inst, P, V), axis=0)
+    assert int(np.sum(srt[-1] - srt[-2] < 1e-12)) == 16
+
+
+def test_sparse_and_structured_pi_match_dense():
+    inst = I.random_dense([3, 3], 4, 2, seed=10, gamma=0.95, n_terminal=1)
+    Vd, pid, _ = dense.policy_iteration(inst)
+    Vs, pis, _ = sparse.policy_iteration(inst)
+    Vt, pit, _ = structured.policy_iteration(inst)
+    np.testing.assert_allclose(Vs, Vd, atol=1e-10)
+    np.testing.assert_allclose(Vt, Vd, atol=1e-10)
+
+
+@pytest.mark.parametrize("maker", [
+    lambda: I.grid_small([3, 4, 2], seed=11),
+    lambda: I.random_dense([2, 3, 2], 3, 3, seed=12, n_terminal=2),
+])
+def test_one_backup_tiers_agree(maker):
+    inst = maker()
+    V = I.seeded_values(inst.n_states, 13)
+    P = dense.transition_matrices(inst)
+    Qd = dense.q_values(inst, P, V)
+    _, _, Qs = sparse.backup(inst, V)
+    _, _, Qt = structured.backup(inst, V)
+    np.testing.assert_allclose(Qs, Qd, atol=1e-14)
+    np.testing.assert_allclose(Qt, Qd, atol=1e-14)
+
+
+def test_greedy_rule_ties_and_incumbent():
+    Q = np.array([[1.0, 2.0, 3.0], [1.0, 2.5, 3.0 - 1e-13], [0.5, 2.5, 2.0]])
+    V = np.zeros(3)
+    assert oracle.greedy(Q, V).tolist() == [0, 1, 0]
+    assert oracle.improve(Q, V, np.array([1, 2, 1])).tolist() == [1, 2, 1]
+    assert oracle.improve(Q, V, np.array([2, 0, 2])).tolist() == [0, 1, 0]
+
+
+# ------------------------------------------------------------- paper pins
+
+def test_def2_state_order_golden():
+    g = json.load(open(os.path.join(GOLDEN, "def2_state_order.json")))
+    sizes = g["sizes"]
+    for s, c1 in enumerate(g["states_in_order"]):
+        c0 = [x - 1 for x in c1]
+        assert I.flat_index(sizes, c0) == s
+        assert list(oracle.common.coords_of(sizes, s)) == c0
+    # a +1 move along the last dimension goes to the next listed state
+    inst = I.make_gridworld(sizes, 0.0, np.zeros(6), 0.9)
+    P = dense.transition_matrices(inst)
+    a_plus_last = 2 * (len(sizes) - 1)
+    assert P[a_plus_last, 0, 1] == 1.0
+    assert P[0, 0, 3] == 1.0           # +1 along d1 jumps |d2| states
+
+
+def test_table1_action_counts_golden():
+    g = json.load(open(os.path.join(GOLDEN, "table1_actions.json")))
+    for D, A in g["dims_to_actions"].items():
+        D = int(D)
+        inst = I.make_gridworld([2] * D, 0.1, np.zeros(2 ** D), 0.9)
+        assert inst.n_actions == A
+        assert all(int(r) == 2 * D - 1 for r in inst.ranks)
+    ex = g["states_2d_example"]
+    assert int(np.prod(ex["sizes"])) == ex["states"]
+
+
+# ------------------------------------------- pins catch planted mistakes
+
+def test_pins_catch_transposed_mode_product(monkeypatch):
+    """Contracting the factor on the wrong index must fail the separable
+    closed form (the mistake is planted in the oracle, on the CPU)."""
+    def wrong(X, T, k):
+        return np.moveaxis(np.tensordot(T.T, X, axes=([1], [k])), 0, k)
+    monkeypatch.setattr(structured, "mode_product", wrong)
+    with pytest.raises(AssertionError):
+        test_separable_reward_fixed_policy("structured")
+
+
+def test_pins_catch_reversed_dimension_order(monkeypatch):
+    """Building the Kronecker product in the reverse dimension order must
+    fail the elementwise-definition pin."""
+    orig = dense.transition_matrices
+
+    def reversed_kron(inst):
+        P = np.zeros((inst.n_actions, inst.n_states, inst.n_states))
+        for a in range(inst.n_actions):
+            for t in inst.terms_of(a):
+                K = np.ones((1, 1))
+                for k in reversed(range(inst.n_dims)):
+                    K = np.kron(K, inst.factor(t, k))
+                P[a] += inst.lambdas[t] * K
+        return P
+    monkeypatch.setattr(dense, "transition_matrices", reversed_kron)
+    with pytest.raises(AssertionError):
+        test_kron_equals_elementwise_definition()
+    monkeypatch.setattr(dense, "transition_matrices", orig)
+
+
+def test_pins_catch_missing_discount(monkeypatch):
+    """Dropping gamma from the continuation must fail the chain closed form."""
+    monkeypatch.setattr(dense, "continuation",
+                        lambda inst: 1.0 - inst.terminal.astype(np.float64))
+    with pytest.raises(AssertionError):
+        test_deterministic_chain_closed_form("dense")
+
+
+def test_pins_catch_wrong_argmax(monkeypatch):
+    """Picking the worst action must fail brute-force enumeration."""
+    def worst(Q, V):
+        return np.argmin(Q, axis=0).astype(np.int32)
+    monkeypatch.setattr(dense, "greedy", worst)
+    with pytest.raises(AssertionError):
+        test_brute_force_enumeration(
+            lambda: I.random_dense([2, 3], 3, 2, seed=4, gamma=0.9))
