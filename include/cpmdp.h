@@ -1,0 +1,239 @@
+/*
+ * cpmdp.h -- C ABI of the MI355X (gfx950) CP-structured Bellman backup.
+ *
+ * Problem (Kuinchtner, Sales & Meneguzzi, CP-MDP, Sec. 2.1 and Sec. 3):
+ *   an MDP <S, A, P, R, gamma> over an n-dimensional grid whose state space
+ *   is the Cartesian product of the per-dimension state sets (Def. 1), listed
+ *   with the LAST dimension varying fastest (Def. 2): for sizes m_0..m_{n-1}
+ *   the state with coordinates (i_0..i_{n-1}) has flat index
+ *   s = sum_k i_k * prod_{j>k} m_j.
+ *
+ *   Each action's transition model is held in CP (sum of rank-one terms,
+ *   Sec. 2.2) / Kronecker form and never expanded:
+ *       P_a = sum_{r < R_a} lambda_{a,r} kron_k T^{(k)}_{a,r},
+ *   with T^{(k)}_{a,r} an m_k x m_k row-stochastic matrix,
+ *   T[i][j] = P(next coordinate j | current coordinate i) along dim k.
+ *
+ *   Backup (Eq. 1), with a per-state reward outside the max and a terminal
+ *   mask tau (terminal states end the interaction, Sec. 3.2):
+ *       Q_a(s) = R(s) + gamma * (1 - tau(s)) * (P_a V)(s)
+ *       V'(s)  = max_a Q_a(s)
+ *   Value iteration repeats the backup; policy iteration alternates
+ *   evaluation of a fixed policy with greedy improvement and stops when the
+ *   policy no longer changes (Sec. 2.1).
+ *
+ * Tie rule for reported policies: the lowest action index whose Q is within
+ *   tol = 1e-12 * max(1, ||V||_inf) of the maximum; policy improvement keeps
+ *   the incumbent action unless another beats it by more than tol.
+ *
+ * Conventions
+ *   - Every call returns a status code (cpmdp_status); no C++ exception
+ *     crosses this boundary.  The message of the last failure is available
+ *     from cpmdp_last_error().
+ *   - Host arrays passed in are copied; the library never keeps a caller's
+ *     host pointer.
+ *   - Device buffers (V, pi, workspace) are owned by the caller (allocated
+ *     e.g. as torch tensors) and are never freed by the library.
+ *   - All device work is enqueued on the stream given to cpmdp_bind (a
+ *     hipStream_t passed as void*).  Calls that return host scalars
+ *     synchronize that stream before returning.
+ *   - A handle is not thread-safe: use it from one host thread, with one
+ *     stream at a time.
+ */
+#ifndef CPMDP_H
+#define CPMDP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cpmdp cpmdp_t;
+typedef struct cpmdp_batch cpmdp_batch_t;
+
+typedef enum cpmdp_status {
+  CPMDP_OK = 0,
+  CPMDP_NOT_CONVERGED = 1,     /* warning: max_iter reached, outputs valid */
+  CPMDP_E_ARG = -1,            /* bad argument (null, size, range)          */
+  CPMDP_E_NOT_STOCHASTIC = -2, /* factor row or lambda sum != 1 (1e-12)     */
+  CPMDP_E_DEVICE = -3,         /* a HIP runtime call failed                 */
+  CPMDP_E_WORKSPACE = -4,      /* workspace missing or too small            */
+  CPMDP_E_NONFINITE = -5,      /* NaN / Inf in inputs or produced values    */
+  CPMDP_E_UNSUPPORTED = -6,    /* valid request this build does not do      */
+  CPMDP_E_STATE = -7           /* call out of order (e.g. not bound)        */
+} cpmdp_status;
+
+typedef enum cpmdp_precision {
+  CPMDP_FP64 = 0, /* mode products in FP64                                     */
+  CPMDP_FP32 = 1, /* mode products in FP32 (FP64 master, residual, certificate
+                     in the solvers)                                           */
+  CPMDP_BF16 = 2  /* dense mode products with BF16 operands on MFMA and FP32
+                     accumulation; shift/identity factors run as FP32          */
+} cpmdp_precision;
+
+typedef enum cpmdp_path {
+  CPMDP_PATH_STENCIL = 0, /* every rank term has at most one non-identity
+                             factor and it is a clamped +-1 shift           */
+  CPMDP_PATH_DENSE = 1    /* general factors: mode-product chains           */
+} cpmdp_path;
+
+/*
+ * cpmdp_create -- validate and copy one MDP (Sec. 2.1 tuple; Def. 1-2 sizes).
+ *   n_dims   : number of dimensions n, 1 <= n <= 8.
+ *   sizes    : [n_dims] states per dimension m_k >= 1 (Def. 1); the product
+ *              S must be < 2^31.
+ *   n_actions: A, 1 <= A <= 255.
+ *   ranks    : [A] rank R_a >= 1 of each action's CP form.
+ *   factors  : FP64, for each term t = 0 .. sum_a R_a - 1 (all terms of
+ *              action 0 first, then action 1, ...), for each dim k, the
+ *              m_k x m_k matrix T^{(k)}_t row-major (row i = current
+ *              coordinate, column j = next coordinate).  Entries must be
+ *              finite and >= 0, every row must sum to 1 within 1e-12.
+ *   lambdas  : FP64 [sum_a R_a], >= 0, summing to 1 within 1e-12 per action.
+ *   rewards  : FP64 [S] per-state reward R(s) of Eq. 1, row-major (Def. 2).
+ *   gamma    : discount, 0 <= gamma < 1 (the contraction needs gamma < 1).
+ * Returns CPMDP_OK and *out, or an error (CPMDP_E_ARG, CPMDP_E_NONFINITE,
+ * CPMDP_E_NOT_STOCHASTIC) with *out = NULL.  Nothing is sent to the device.
+ */
+int cpmdp_create(cpmdp_t** out, int32_t n_dims, const int64_t* sizes,
+                 int32_t n_actions, const int32_t* ranks,
+                 const double* factors, const double* lambdas,
+                 const double* rewards, double gamma);
+
+/* Terminal states (Sec. 3.2): mask [S], nonzero = terminal (V(s) = R(s), no
+ * continuation).  Must be called before cpmdp_bind; default: none. */
+int cpmdp_set_terminal(cpmdp_t* h, const uint8_t* mask);
+
+/* Obstacles (Sec. 3.2, states the agent cannot enter) break the pure
+ * Kronecker form; this build rejects them with CPMDP_E_UNSUPPORTED. */
+int cpmdp_set_obstacles(cpmdp_t* h, const uint8_t* mask);
+
+/* Which kernel family the instance runs on (cpmdp_path), via *path. */
+int cpmdp_get_path(const cpmdp_t* h, int32_t* path);
+
+/* Device workspace size in bytes that cpmdp_bind needs for this instance
+ * (all precisions). */
+int cpmdp_workspace_bytes(const cpmdp_t* h, size_t* bytes);
+
+/*
+ * cpmdp_bind -- attach a caller-owned device workspace (>= workspace_bytes,
+ * 256-byte aligned) and a stream, and upload the packed model to it (the only
+ * bulk host-to-device copy).  May be called again to move to another
+ * workspace or stream; the workspace must stay allocated while the handle
+ * is used.
+ */
+int cpmdp_bind(cpmdp_t* h, void* dev_workspace, size_t bytes,
+               void* hip_stream);
+
+/* Switch the stream used by later calls (workspace unchanged). */
+int cpmdp_set_stream(cpmdp_t* h, void* hip_stream);
+
+/*
+ * cpmdp_backup -- one Bellman backup (Eq. 1) on the device.
+ *   V_in, V_out : device [S]; FP64 for CPMDP_FP64, FP32 otherwise.  Must not
+ *                 alias.
+ *   pi_out      : device int32 [S] greedy actions (tie rule above, applied
+ *                 in the backup's precision) or NULL.
+ *   residual_host: if non-NULL, the stream is synchronized and
+ *                 ||V_out - V_in||_inf is written there (as FP64).
+ *   precision   : cpmdp_precision.
+ */
+int cpmdp_backup(cpmdp_t* h, const void* V_in, void* V_out, int32_t* pi_out,
+                 double* residual_host, int precision);
+
+/*
+ * cpmdp_policy_backup -- one fixed-policy backup (policy evaluation step of
+ * Sec. 2.1): V_out(s) = R(s) + gamma (1 - tau(s)) (P_{pi(s)} V_in)(s).
+ *   pi : device int32 [S], each in [0, A).  Other arguments as cpmdp_backup.
+ */
+int cpmdp_policy_backup(cpmdp_t* h, const void* V_in, void* V_out,
+                        const int32_t* pi, double* residual_host,
+                        int precision);
+
+/*
+ * cpmdp_value_iteration -- repeat the backup until the Bellman residual
+ * ||B V - V||_inf <= eps (Sec. 2.1), then certify in FP64.
+ *   V_dev     : device FP64 [S]; in: V0 (warm start), out: the solution.
+ *   pi_out    : device int32 [S] greedy policy of the returned V, or NULL.
+ *   eps       : absolute residual target (> 0).
+ *   max_iter  : cap on backup sweeps (>= 1).
+ *   precision : sweep arithmetic; FP32/BF16 sweeps are followed by FP64
+ *               sweeps until the FP64 residual meets eps.
+ *   sweeps_out, residual_out : nullable; sweeps run, and the FP64 residual
+ *               ||B V - V||_inf of the returned V.
+ * Returns CPMDP_OK, or CPMDP_NOT_CONVERGED (outputs valid, best iterate),
+ * or an error.
+ */
+int cpmdp_value_iteration(cpmdp_t* h, double* V_dev, int32_t* pi_out,
+                          double eps, int64_t max_iter, int precision,
+                          int64_t* sweeps_out, double* residual_out);
+
+/*
+ * cpmdp_policy_iteration -- policy iteration (Sec. 2.1): evaluate pi, improve
+ * greedily keeping the incumbent on ties, stop when pi is unchanged and the
+ * FP64 residual ||B V - V||_inf <= eps.  Evaluation runs as FP64 residual
+ * r = R + gamma P_pi V - V, correction sweeps e <- r + gamma P_pi e in the
+ * requested precision, and V += e in FP64.
+ *   V_dev  : device FP64 [S]; in: initial V (any), out: the solution.
+ *   pi_dev : device int32 [S]; in: initial policy, out: the final policy.
+ *   max_iter: cap on the total number of sweeps of any kind.
+ *   outer_iters_out, sweeps_out, residual_out: nullable statistics.
+ */
+int cpmdp_policy_iteration(cpmdp_t* h, double* V_dev, int32_t* pi_dev,
+                           double eps, int64_t max_iter, int precision,
+                           int64_t* outer_iters_out, int64_t* sweeps_out,
+                           double* residual_out);
+
+/* Release the handle (host memory only; device buffers stay the caller's). */
+void cpmdp_destroy(cpmdp_t* h);
+
+/* Message of the last failure on h (h == NULL: of the last failed create or
+ * batch call in this thread).  Valid until the next call on h. */
+const char* cpmdp_last_error(const cpmdp_t* h);
+
+/* ------------------------------------------------------------ batched ---
+ * Many independent instances (each a created handle, stencil path) solved
+ * together: every sweep is one persistent launch over a table of tiles of
+ * all still-active instances, chunks of sweeps are captured as HIP graphs,
+ * and the tile size / sweeps per graph come from a small autotuner.
+ */
+
+/* Collect count created handles (not necessarily bound); the handles must
+ * outlive the batch. */
+int cpmdp_batch_create(cpmdp_batch_t** out, cpmdp_t* const* handles,
+                       int32_t count);
+int cpmdp_batch_workspace_bytes(const cpmdp_batch_t* b, size_t* bytes);
+int cpmdp_batch_bind(cpmdp_batch_t* b, void* dev_workspace, size_t bytes,
+                     void* hip_stream);
+
+/*
+ * cpmdp_batch_solve -- solve every instance to ||B V - V||_inf <= eps.
+ *   V_devs : [count] device FP64 [S_i] buffers; in: V0_i, out: solution.
+ *   pi_devs: [count] device int32 [S_i] buffers (policy out; for PI also in)
+ *            or NULL.
+ *   method : 0 = value iteration, 1 = policy iteration.
+ *   sweeps_out   : [count] int64 sweeps per instance, or NULL.
+ *   residual_out : [count] FP64 certificate per instance, or NULL.
+ * Returns CPMDP_OK, CPMDP_NOT_CONVERGED if any instance hit max_iter, or an
+ * error.
+ */
+int cpmdp_batch_solve(cpmdp_batch_t* b, double* const* V_devs,
+                      int32_t* const* pi_devs, double eps, int64_t max_iter,
+                      int precision, int method, int64_t* sweeps_out,
+                      double* residual_out);
+
+/* Autotuner control: tune = 1 times candidate tile sizes and sweeps per graph
+ * on the bound batch and keeps the fastest; cache_path (nullable) is a text
+ * file of size class -> choice read before and written after tuning. */
+int cpmdp_batch_autotune(cpmdp_batch_t* b, int tune, const char* cache_path);
+int cpmdp_batch_config(const cpmdp_batch_t* b, int32_t* tile_states,
+                       int32_t* sweeps_per_graph);
+void cpmdp_batch_destroy(cpmdp_batch_t* b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CPMDP_H */

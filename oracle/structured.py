@@ -100,3 +100,26 @@ def policy_iteration(inst, pi0=None, eps=1e-13, max_outer=10000):
             return V, pi, it
         pi = pi_new
     return V, pi, max_outer
+
+
+def q_at_states(inst, V, states):
+    """Q[a, i] for the listed states only, straight from the definition
+    (P_a V)(s) = sum_r lambda_{a,r} sum_j prod_k T^(k)_{a,r}[i_k, j_k] V[j]:
+    V is contracted with row i_k of every factor, one dimension at a time.
+    For spot checks of instances too large for a full oracle backup."""
+    shape = tuple(int(m) for m in inst.sizes)
+    Vt = np.asarray(V, np.float64).reshape(shape)
+    states = np.asarray(states, np.int64)
+    Q = np.empty((inst.n_actions, states.size))
+    for col, s in enumerate(states):
+        coords = np.unravel_index(int(s), shape)   # row-major, Def. 2
+        cont = inst.gamma * (1.0 - float(inst.terminal[s]))
+        for a in range(inst.n_actions):
+            tot = 0.0
+            for t in inst.terms_of(a):
+                U = Vt
+                for k in range(inst.n_dims):
+                    U = np.tensordot(inst.factor(t, k)[coords[k]], U, axes=([0], [0]))
+                tot += inst.lambdas[t] * float(U)
+            Q[a, col] = inst.rewards[s] + cont * tot
+    return Q

@@ -1,0 +1,272 @@
+"""ctypes binding of libcpmdp.so (the C ABI declared in include/cpmdp.h).
+
+Argument marshalling only: every step of a backup or a solve runs in the HIP
+kernels of the library.  PyTorch provides device memory (workspace, V, pi)
+and the stream.  The library must have been built (``build.py``); importing
+this module without it raises, so no caller can silently run elsewhere.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcpmdp.so")
+
+CPMDP_OK = 0
+CPMDP_NOT_CONVERGED = 1
+CPMDP_E_ARG = -1
+CPMDP_E_NOT_STOCHASTIC = -2
+CPMDP_E_DEVICE = -3
+CPMDP_E_WORKSPACE = -4
+CPMDP_E_NONFINITE = -5
+CPMDP_E_UNSUPPORTED = -6
+CPMDP_E_STATE = -7
+
+CPMDP_FP64, CPMDP_FP32, CPMDP_BF16 = 0, 1, 2
+CPMDP_PATH_STENCIL, CPMDP_PATH_DENSE = 0, 1
+PRECISIONS = {"fp64": CPMDP_FP64, "fp32": CPMDP_FP32, "bf16": CPMDP_BF16}
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run paper_2103_00331_amd/build.py "
+                      "(or __graft_entry__.build())")
+lib = C.CDLL(LIB_PATH)
+
+_p = C.c_void_p
+_i32p = C.POINTER(C.c_int32)
+_i64p = C.POINTER(C.c_int64)
+_dp = C.POINTER(C.c_double)
+_u8p = C.POINTER(C.c_uint8)
+_szp = C.POINTER(C.c_size_t)
+
+_SIGS = {
+    "cpmdp_create": (C.c_int, [C.POINTER(_p), C.c_int32, _i64p, C.c_int32, _i32p, _dp, _dp,
+                                _dp, C.c_double]),
+    "cpmdp_set_terminal": (C.c_int, [_p, _u8p]),
+    "cpmdp_set_obstacles": (C.c_int, [_p, _u8p]),
+    "cpmdp_get_path": (C.c_int, [_p, _i32p]),
+    "cpmdp_workspace_bytes": (C.c_int, [_p, _szp]),
+    "cpmdp_bind": (C.c_int, [_p, _p, C.c_size_t, _p]),
+    "cpmdp_set_stream": (C.c_int, [_p, _p]),
+    "cpmdp_backup": (C.c_int, [_p, _p, _p, _p, _dp, C.c_int]),
+    "cpmdp_policy_backup": (C.c_int, [_p, _p, _p, _p, _dp, C.c_int]),
+    "cpmdp_value_iteration": (C.c_int, [_p, _p, _p, C.c_double, C.c_int64, C.c_int, _i64p,
+                                        _dp]),
+    "cpmdp_policy_iteration": (C.c_int, [_p, _p, _p, C.c_double, C.c_int64, C.c_int, _i64p,
+                                         _i64p, _dp]),
+    "cpmdp_destroy": (None, [_p]),
+    "cpmdp_last_error": (C.c_char_p, [_p]),
+    "cpmdp_batch_create": (C.c_int, [C.POINTER(_p), C.POINTER(_p), C.c_int32]),
+    "cpmdp_batch_workspace_bytes": (C.c_int, [_p, _szp]),
+    "cpmdp_batch_bind": (C.c_int, [_p, _p, C.c_size_t, _p]),
+    "cpmdp_batch_solve": (C.c_int, [_p, C.POINTER(_p), C.POINTER(_p), C.c_double, C.c_int64,
+                                    C.c_int, C.c_int, _i64p, _dp]),
+    "cpmdp_batch_autotune": (C.c_int, [_p, C.c_int, C.c_char_p]),
+    "cpmdp_batch_config": (C.c_int, [_p, _i32p, _i32p]),
+    "cpmdp_batch_destroy": (None, [_p]),
+}
+
+EXPORTED = sorted(_SIGS)
+for _name, (_res, _args) in _SIGS.items():
+    fn = getattr(lib, _name)
+    fn.restype = _res
+    fn.argtypes = _args
+
+
+class CpmdpError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"cpmdp error {code}: {msg}")
+        self.code = code
+
+
+def _check(code, handle=None):
+    if code < 0:
+        msg = lib.cpmdp_last_error(handle)
+        raise CpmdpError(code, msg.decode() if msg else "")
+    return code
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream_ptr(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+# ----------------------------------------------------- C-named thin wrappers
+
+def cpmdp_create(sizes: Sequence[int], ranks: Sequence[int], factors, lambdas, rewards,
+                 gamma: float):
+    sizes = np.ascontiguousarray(sizes, np.int64)
+    ranks = np.ascontiguousarray(ranks, np.int32)
+    factors = np.ascontiguousarray(factors, np.float64)
+    lambdas = np.ascontiguousarray(lambdas, np.float64)
+    rewards = np.ascontiguousarray(rewards, np.float64)
+    h = _p()
+    _check(lib.cpmdp_create(C.byref(h), int(sizes.size), sizes.ctypes.data_as(_i64p),
+                            int(ranks.size), ranks.ctypes.data_as(_i32p),
+                            factors.ctypes.data_as(_dp), lambdas.ctypes.data_as(_dp),
+                            rewards.ctypes.data_as(_dp), float(gamma)))
+    return h
+
+
+def cpmdp_set_terminal(h, mask):
+    mask = np.ascontiguousarray(mask, np.uint8)
+    return _check(lib.cpmdp_set_terminal(h, mask.ctypes.data_as(_u8p)), h)
+
+
+def cpmdp_set_obstacles(h, mask):
+    mask = np.ascontiguousarray(mask, np.uint8)
+    return _check(lib.cpmdp_set_obstacles(h, mask.ctypes.data_as(_u8p)), h)
+
+
+def cpmdp_get_path(h) -> int:
+    out = C.c_int32()
+    _check(lib.cpmdp_get_path(h, C.byref(out)), h)
+    return out.value
+
+
+def cpmdp_workspace_bytes(h) -> int:
+    out = C.c_size_t()
+    _check(lib.cpmdp_workspace_bytes(h, C.byref(out)), h)
+    return out.value
+
+
+def cpmdp_bind(h, workspace, stream=None):
+    return _check(lib.cpmdp_bind(h, workspace.data_ptr(), workspace.numel() *
+                                 workspace.element_size(), _stream_ptr(stream)), h)
+
+
+def cpmdp_set_stream(h, stream=None):
+    return _check(lib.cpmdp_set_stream(h, _stream_ptr(stream)), h)
+
+
+def cpmdp_backup(h, V_in, V_out, pi_out=None, residual=False, precision=CPMDP_FP64):
+    r = C.c_double(0.0)
+    _check(lib.cpmdp_backup(h, _ptr(V_in), _ptr(V_out), _ptr(pi_out),
+                            C.byref(r) if residual else None, int(precision)), h)
+    return r.value if residual else None
+
+
+def cpmdp_policy_backup(h, V_in, V_out, pi, residual=False, precision=CPMDP_FP64):
+    r = C.c_double(0.0)
+    _check(lib.cpmdp_policy_backup(h, _ptr(V_in), _ptr(V_out), _ptr(pi),
+                                   C.byref(r) if residual else None, int(precision)), h)
+    return r.value if residual else None
+
+
+def cpmdp_value_iteration(h, V, pi_out=None, eps=1e-6, max_iter=100000,
+                          precision=CPMDP_FP64):
+    sw = C.c_int64(0)
+    res = C.c_double(0.0)
+    code = _check(lib.cpmdp_value_iteration(h, _ptr(V), _ptr(pi_out), float(eps),
+                                            int(max_iter), int(precision), C.byref(sw),
+                                            C.byref(res)), h)
+    return code, sw.value, res.value
+
+
+def cpmdp_policy_iteration(h, V, pi, eps=1e-6, max_iter=100000, precision=CPMDP_FP64):
+    outer = C.c_int64(0)
+    sw = C.c_int64(0)
+    res = C.c_double(0.0)
+    code = _check(lib.cpmdp_policy_iteration(h, _ptr(V), _ptr(pi), float(eps), int(max_iter),
+                                             int(precision), C.byref(outer), C.byref(sw),
+                                             C.byref(res)), h)
+    return code, outer.value, sw.value, res.value
+
+
+def cpmdp_destroy(h):
+    lib.cpmdp_destroy(h)
+
+
+def cpmdp_last_error(h=None) -> str:
+    m = lib.cpmdp_last_error(h)
+    return m.decode() if m else ""
+
+
+def cpmdp_batch_create(handles):
+    arr = (_p * len(handles))(*[h.value if isinstance(h, _p) else h for h in handles])
+    b = _p()
+    _check(lib.cpmdp_batch_create(C.byref(b), arr, len(handles)))
+    return b
+
+
+def cpmdp_batch_workspace_bytes(b) -> int:
+    out = C.c_size_t()
+    _check(lib.cpmdp_batch_workspace_bytes(b, C.byref(out)))
+    return out.value
+
+
+def cpmdp_batch_bind(b, workspace, stream=None):
+    return _check(lib.cpmdp_batch_bind(b, workspace.data_ptr(), workspace.numel() *
+                                       workspace.element_size(), _stream_ptr(stream)))
+
+
+def cpmdp_batch_solve(b, Vs, pis=None, eps=1e-6, max_iter=100000, precision=CPMDP_FP32,
+                      method=0):
+    n = len(Vs)
+    varr = (_p * n)(*[v.data_ptr() for v in Vs])
+    parr = (_p * n)(*[p.data_ptr() for p in pis]) if pis is not None else None
+    sweeps = np.zeros(n, np.int64)
+    res = np.zeros(n, np.float64)
+    code = _check(lib.cpmdp_batch_solve(b, varr, parr, float(eps), int(max_iter),
+                                        int(precision), int(method),
+                                        sweeps.ctypes.data_as(_i64p), res.ctypes.data_as(_dp)))
+    return code, sweeps, res
+
+
+def cpmdp_batch_autotune(b, tune=True, cache_path=None):
+    return _check(lib.cpmdp_batch_autotune(b, int(bool(tune)),
+                                           cache_path.encode() if cache_path else None))
+
+
+def cpmdp_batch_config(b):
+    t = C.c_int32()
+    k = C.c_int32()
+    _check(lib.cpmdp_batch_config(b, C.byref(t), C.byref(k)))
+    return t.value, k.value
+
+
+def cpmdp_batch_destroy(b):
+    lib.cpmdp_batch_destroy(b)
+
+
+# ------------------------------------------------------------ convenience
+
+class Model:
+    """One MDP on the GPU: creates the handle from an instance (sizes,
+    ranks, factors, lambdas, rewards, gamma, terminal mask), allocates the
+    workspace as a torch uint8 tensor and binds it with the current stream."""
+
+    def __init__(self, inst, device="cuda", stream=None):
+        import torch
+        self.inst = inst
+        self.h = cpmdp_create(inst.sizes, inst.ranks, inst.factors, inst.lambdas,
+                              inst.rewards, inst.gamma)
+        if np.any(inst.terminal):
+            cpmdp_set_terminal(self.h, inst.terminal)
+        self.path = cpmdp_get_path(self.h)
+        nbytes = cpmdp_workspace_bytes(self.h)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        off = (-self.workspace.data_ptr()) % 256
+        self.ws_view = self.workspace[off:off + nbytes]
+        cpmdp_bind(self.h, self.ws_view, stream)
+        self.S = inst.n_states
+        self.device = device
+
+    def close(self):
+        if self.h is not None:
+            cpmdp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,891 @@
+// Host runtime behind include/cpmdp.h: validation, factor classification,
+// packing, workspace layout, and the value- / policy-iteration drivers.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "cpmdp_internal.h"
+#include "handle.h"
+
+namespace cpm {
+
+FastDiv make_fastdiv(uint32_t d) {
+  FastDiv f{};
+  uint32_t l = 0;
+  while ((1ull << l) < d) ++l;
+  const uint64_t m = ((1ull << 32) * ((1ull << l) - d)) / d + 1;
+  f.magic = static_cast<uint32_t>(m);
+  f.shift = l;
+  return f;
+}
+
+thread_local std::string g_last_error;
+
+int fail(cpmdp_t* h, int code, const std::string& msg) {
+  if (h) h->err = msg;
+  g_last_error = msg;
+  return code;
+}
+
+#define HIP_TRY(h, call)                                                           \
+  do {                                                                             \
+    hipError_t e_ = (call);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return fail((h), CPMDP_E_DEVICE,                                             \
+                  std::string(#call) + ": " + hipGetErrorString(e_));              \
+  } while (0)
+
+// ------------------------------------------------------------ validation
+
+static int classify(const double* T, int m) {
+  bool ident = true, sp = true, sm = true;
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) {
+      const double v = T[i * m + j];
+      const double e_id = (i == j) ? 1.0 : 0.0;
+      const double e_sp = (j == std::min(i + 1, m - 1)) ? 1.0 : 0.0;
+      const double e_sm = (j == std::max(i - 1, 0)) ? 1.0 : 0.0;
+      ident = ident && v == e_id;
+      sp = sp && v == e_sp;
+      sm = sm && v == e_sm;
+    }
+  if (ident) return F_IDENT;
+  if (sp) return F_SHIFT_P;
+  if (sm) return F_SHIFT_M;
+  return F_DENSE;
+}
+
+// LDS per workgroup on gfx950 (160 KiB); a little is kept for the kernels'
+// static arrays.
+constexpr int64_t kLdsBytes = 160 * 1024;
+
+// LDS bytes the chain kernels of geometry g request per workgroup.
+int64_t chain_lds_bytes(const ChainGeom& g, size_t b) {
+  const int64_t TE = static_cast<int64_t>(g.Rr) * g.CT;
+  const int64_t p2 = static_cast<int64_t>(b) * (TE + (TE >> 5) + 1) + 1024 + 256;
+  const int64_t p1 = (g.n1 < g.n) ? static_cast<int64_t>(b) *
+                                        (2 * (g.C + (g.C >> 5) + 1) + 2) + 256
+                                  : 0;
+  return std::max(p1, p2);
+}
+
+// Split the dims into a row group [0, n1) and a column group [n1, n) so that
+// a pass-1 row slab (two copies) and a pass-2 tile (rows x CT) fit in LDS;
+// prefer balanced groups.  te_max also bounds the per-thread register state
+// of pass 2 (16384 / 512 threads = 32 elements; FP64: 16).
+static bool choose_split(const std::vector<int64_t>& sizes, int64_t S, size_t b,
+                         ChainGeom& g) {
+  const int n = static_cast<int>(sizes.size());
+  const int64_t te_max = std::min<int64_t>(b == 8 ? 8192 : 16384,
+                                           (kLdsBytes - 4096) / static_cast<int64_t>(b));
+  const int64_t c_max =
+      static_cast<int64_t>((kLdsBytes - 4096) / (2.0 * b * (1.0 + 1.0 / 32.0))) - 4;
+  int64_t mmax = 0;
+  for (auto m : sizes) mmax = std::max(mmax, m);
+  if (mmax > 32) return false;
+  int best_n1 = -1;
+  double best_score = 1e30;
+  if (S <= 4096) {
+    best_n1 = n;
+  } else {
+    int64_t Rr = 1;
+    for (int n1 = 1; n1 < n; ++n1) {
+      Rr *= sizes[n1 - 1];
+      const int64_t C = S / Rr;
+      if (C > c_max || Rr > te_max) continue;
+      const double score = std::fabs(std::log2(static_cast<double>(Rr)) -
+                                     std::log2(static_cast<double>(C)));
+      if (score < best_score - 1e-9) {
+        best_score = score;
+        best_n1 = n1;
+      }
+    }
+    if (best_n1 < 0 && S <= te_max) best_n1 = n;
+  }
+  if (best_n1 < 0) return false;
+  std::memset(&g, 0, sizeof(g));
+  g.n = n;
+  g.n1 = best_n1;
+  g.S = static_cast<int32_t>(S);
+  int64_t Rr = 1;
+  for (int k = 0; k < best_n1; ++k) Rr *= sizes[k];
+  g.Rr = static_cast<int32_t>(Rr);
+  g.C = static_cast<int32_t>(S / Rr);
+  int ct = 1, sh = 0;
+  while (ct < 64 && Rr * ct * 2 <= te_max && ct < g.C) {
+    ct *= 2;
+    ++sh;
+  }
+  g.CT = ct;
+  g.ct_shift = sh;
+  g.ntiles = (g.C + ct - 1) / ct;
+  int off = 0;
+  for (int k = 0; k < n; ++k) {
+    g.size[k] = static_cast<int32_t>(sizes[k]);
+    g.fac_off[k] = off;
+    off += static_cast<int32_t>(sizes[k] * sizes[k]);
+  }
+  g.term_stride = off;
+  g.mmax_row = 0;
+  g.mmax_col = 0;
+  for (int k = 0; k < n; ++k) {
+    if (k < best_n1) g.mmax_row = std::max<int32_t>(g.mmax_row, g.size[k]);
+    else g.mmax_col = std::max<int32_t>(g.mmax_col, g.size[k]);
+  }
+  g.w_term_stride = (best_n1 == n) ? 0 : static_cast<int64_t>(g.ntiles) * g.Rr * g.CT;
+  return true;
+}
+
+// ------------------------------------------------------------- workspace
+
+static size_t align_up(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <typename P>
+  P* take(size_t count) {
+    P* p = base ? reinterpret_cast<P*>(base + off) : nullptr;
+    off = align_up(off + count * sizeof(P));
+    return p;
+  }
+};
+
+void layout(const cpmdp_t* h, DevPtrs* dp, char* base, size_t* total) {
+  Carver cv{base};
+  const size_t S = static_cast<size_t>(h->S);
+  const size_t A = static_cast<size_t>(h->A);
+  const size_t T = h->lambdas.size();
+  DevPtrs& d = *dp;
+  d.R64 = cv.take<double>(S);
+  d.R32 = cv.take<float>(S);
+  d.tbits = cv.take<uint32_t>((S + 31) / 32 + 1);
+  d.slots = cv.take<unsigned long long>(kSlots);
+  d.vmax = cv.take<unsigned long long>(4);
+  d.counters = cv.take<unsigned int>(8);
+  d.Va64 = cv.take<double>(S);
+  d.Va32 = cv.take<float>(S);
+  d.Vb32 = cv.take<float>(S);
+  d.E0 = cv.take<float>(S);
+  d.E1 = cv.take<float>(S);
+  d.r32 = cv.take<float>(S);
+  d.piA = cv.take<int32_t>(S);
+  if (h->path == CPMDP_PATH_STENCIL) {
+    const size_t P = 2 * static_cast<size_t>(h->n) + 1;
+    d.w64 = cv.take<double>(A * P);
+    d.w32 = cv.take<float>(A * P);
+    d.fac64 = nullptr;
+    d.fac32 = nullptr;
+    d.facbf = nullptr;
+    d.W = nullptr;
+  } else {
+    const size_t F = T * static_cast<size_t>(h->cg64.term_stride);
+    d.fac64 = cv.take<double>(F);
+    d.fac32 = cv.take<float>(F);
+    d.facbf = cv.take<uint16_t>(F);
+    d.lam64 = cv.take<double>(T);
+    d.lam32 = cv.take<float>(T);
+    d.kinds = cv.take<uint8_t>(T * h->n);
+    d.term_start = cv.take<int32_t>(A + 1);
+    const size_t w64 = T * static_cast<size_t>(h->cg64.w_term_stride) * sizeof(double);
+    const size_t w32 = T * static_cast<size_t>(h->cg32.w_term_stride) * sizeof(float);
+    d.W = cv.take<char>(std::max<size_t>(std::max(w64, w32), 256));
+  }
+  *total = cv.off;
+}
+
+// ---------------------------------------------------------------- sweeps
+
+GridGeom make_geom(const cpmdp_t* h) {
+  GridGeom g{};
+  g.n = h->n;
+  g.S = static_cast<int32_t>(h->S);
+  int64_t st = 1;
+  for (int k = h->n - 1; k >= 0; --k) {
+    g.size[k] = static_cast<int32_t>(h->sizes[k]);
+    g.stride[k] = static_cast<int32_t>(st);
+    g.div[k] = make_fastdiv(static_cast<uint32_t>(h->sizes[k]));
+    st *= h->sizes[k];
+  }
+  return g;
+}
+
+// One sweep on the bound stream.  prec64 selects FP64 buffers (T = double)
+// or FP32 (T = float).  V, Vout, R are typed by that choice.
+void sweep(cpmdp_t* h, bool prec64, int mode, const void* V, void* Vout, const void* R,
+           const int32_t* pi_in, int32_t* pi_out, float* r_out,
+           unsigned long long* slot, unsigned int* ctr, bool bf16) {
+  const hipStream_t st = h->stream;
+  if (h->path == CPMDP_PATH_STENCIL) {
+    const int nblocks = static_cast<int>((h->S + kBlock - 1) / kBlock);
+    if (prec64) {
+      StencilArgs<double> a{};
+      a.g = h->geom;
+      a.A = h->A;
+      a.npts = 2 * h->n + 1;
+      a.w = h->d.w64;
+      a.V = static_cast<const double*>(V);
+      a.Vout = static_cast<double*>(Vout);
+      a.R = static_cast<const double*>(R);
+      a.term_bits = h->d.tbits;
+      a.gamma = h->gamma;
+      a.pi_in = pi_in;
+      a.pi_out = pi_out;
+      a.r_out = r_out;
+      a.vmax_bits = h->d.vmax;
+      a.res_slot = slot;
+      a.change_count = ctr;
+      a.nblocks = nblocks;
+      launch_stencil<double>(a, mode, st);
+    } else {
+      StencilArgs<float> a{};
+      a.g = h->geom;
+      a.A = h->A;
+      a.npts = 2 * h->n + 1;
+      a.w = h->d.w32;
+      a.V = static_cast<const float*>(V);
+      a.Vout = static_cast<float*>(Vout);
+      a.R = static_cast<const float*>(R);
+      a.term_bits = h->d.tbits;
+      a.gamma = static_cast<float>(h->gamma);
+      a.pi_in = pi_in;
+      a.pi_out = pi_out;
+      a.r_out = r_out;
+      a.vmax_bits = h->d.vmax;
+      a.res_slot = slot;
+      a.change_count = ctr;
+      a.nblocks = nblocks;
+      launch_stencil<float>(a, mode, st);
+    }
+    return;
+  }
+  if (prec64) {
+    ChainArgs<double> a{};
+    a.g = h->cg64;
+    a.A = h->A;
+    a.nterms = static_cast<int32_t>(h->lambdas.size());
+    a.term_start = h->d.term_start;
+    a.fac = h->d.fac64;
+    a.lam = h->d.lam64;
+    a.kinds = h->d.kinds;
+    a.V = static_cast<const double*>(V);
+    a.W = (a.g.n1 == a.g.n) ? const_cast<double*>(a.V) : reinterpret_cast<double*>(h->d.W);
+    a.Vout = static_cast<double*>(Vout);
+    a.R = static_cast<const double*>(R);
+    a.term_bits = h->d.tbits;
+    a.gamma = h->gamma;
+    a.pi_in = pi_in;
+    a.pi_out = pi_out;
+    a.r_out = r_out;
+    a.vmax_bits = h->d.vmax;
+    a.res_slot = slot;
+    a.change_count = ctr;
+    launch_chain<double>(a, mode, st);
+  } else {
+    ChainArgs<float> a{};
+    a.g = h->cg32;
+    a.A = h->A;
+    a.nterms = static_cast<int32_t>(h->lambdas.size());
+    a.term_start = h->d.term_start;
+    a.fac = h->d.fac32;
+    a.lam = h->d.lam32;
+    a.kinds = h->d.kinds;
+    a.V = static_cast<const float*>(V);
+    a.W = (a.g.n1 == a.g.n) ? const_cast<float*>(a.V) : reinterpret_cast<float*>(h->d.W);
+    a.Vout = static_cast<float*>(Vout);
+    a.R = static_cast<const float*>(R);
+    a.term_bits = h->d.tbits;
+    a.gamma = static_cast<float>(h->gamma);
+    a.pi_in = pi_in;
+    a.pi_out = pi_out;
+    a.r_out = r_out;
+    a.vmax_bits = h->d.vmax;
+    a.res_slot = slot;
+    a.change_count = ctr;
+    if (bf16 && chain_bf16_supported(a.g))
+      launch_chain_bf16(a, h->d.facbf, reinterpret_cast<uint16_t*>(h->d.W), mode, st);
+    else
+      launch_chain<float>(a, mode, st);
+  }
+}
+
+static double bits_to_double(unsigned long long b) {
+  double v;
+  std::memcpy(&v, &b, sizeof(v));
+  return v;
+}
+
+// Read n slots (and optionally the counters) back to the host.
+static int read_slots(cpmdp_t* h, int n, std::vector<double>& out, unsigned* ctr0) {
+  HIP_TRY(h, hipMemcpyAsync(h->host_slots, h->d.slots, sizeof(unsigned long long) * n,
+                            hipMemcpyDeviceToHost, h->stream));
+  if (ctr0)
+    HIP_TRY(h, hipMemcpyAsync(h->host_ctr, h->d.counters, sizeof(unsigned) * 2,
+                              hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  out.resize(n);
+  for (int i = 0; i < n; ++i) out[i] = bits_to_double(h->host_slots[i]);
+  if (ctr0) *ctr0 = h->host_ctr[0];
+  return CPMDP_OK;
+}
+
+static int check_device(cpmdp_t* h) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess)
+    return fail(h, CPMDP_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+  return CPMDP_OK;
+}
+
+// Chunk size for the next run of sweeps: enough to reach eps at the
+// observed contraction rate, bounded to keep overshoot and host reads small.
+static int next_chunk(double res_first, double res_last, int k_prev, double gamma,
+                      double eps, int64_t left) {
+  double rate = gamma;
+  if (k_prev > 1 && res_first > 0 && res_last > 0 && std::isfinite(res_first) &&
+      std::isfinite(res_last)) {
+    rate = std::pow(res_last / res_first, 1.0 / (k_prev - 1));
+    rate = std::min(std::max(rate, 0.3), 0.999999);
+  }
+  double need = 8;
+  if (res_last > eps && std::isfinite(res_last))
+    need = std::ceil(std::log(eps / res_last) / std::log(rate));
+  int k = static_cast<int>(std::min(std::max(need, 4.0), 128.0));
+  if (k > left) k = static_cast<int>(left);
+  return std::max(k, 1);
+}
+
+// Chunked sweeps of one mode until the residual of a sweep <= tol.
+// cur/alt: ping-pong buffers (cur holds the input on entry and the result on
+// exit).  Returns status; *done = reached tol.
+template <typename P>
+static int run_sweeps(cpmdp_t* h, bool prec64, int mode, P*& cur, P*& alt, const void* R,
+                      const int32_t* pi, double tol, double stall_floor, int64_t budget,
+                      int64_t* sweeps, bool* done, double* last_res, bool bf16) {
+  *done = false;
+  double rf = INFINITY, rl = INFINITY;
+  int kprev = 0;
+  std::vector<double> res;
+  while (*sweeps < budget) {
+    const int k = kprev == 0 ? 4 : next_chunk(rf, rl, kprev, h->gamma, tol, budget - *sweeps);
+    launch_fill_u64(h->d.slots, k, 0ull, h->stream);
+    for (int j = 0; j < k; ++j) {
+      sweep(h, prec64, mode, cur, alt, R, pi, nullptr, nullptr, h->d.slots + j, nullptr, bf16);
+      std::swap(cur, alt);
+    }
+    int rc = check_device(h);
+    if (rc) return rc;
+    rc = read_slots(h, k, res, nullptr);
+    if (rc) return rc;
+    *sweeps += k;
+    for (int j = 0; j < k; ++j)
+      if (!std::isfinite(res[j]))
+        return fail(h, CPMDP_E_NONFINITE, "non-finite value produced during sweeps");
+    rf = res[0];
+    rl = res[k - 1];
+    kprev = k;
+    *last_res = rl;
+    if (rl <= tol) {
+      *done = true;
+      return CPMDP_OK;
+    }
+    if (stall_floor > 0 && rl <= stall_floor && k >= 8 && rl >= 0.9 * rf) return CPMDP_OK;
+  }
+  return CPMDP_OK;
+}
+
+// Greedy / certificate pass in FP64 over V: residual ||BV - V|| and policy.
+static int certify(cpmdp_t* h, const double* V, int32_t* pi_out, const int32_t* pi_in,
+                   double* res, unsigned* changes) {
+  launch_fill_u64(h->d.slots, 1, 0ull, h->stream);
+  launch_fill_u64(h->d.vmax, 1, 0ull, h->stream);
+  launch_fill_u32(h->d.counters, 2, 0u, h->stream);
+  launch_maxabs_f64(V, h->S, h->d.vmax, h->stream);
+  sweep(h, true, MODE_GREEDY, V, nullptr, h->d.R64, pi_in, pi_out ? pi_out : h->d.piA,
+        nullptr, h->d.slots, h->d.counters, false);
+  int rc = check_device(h);
+  if (rc) return rc;
+  std::vector<double> r;
+  unsigned c = 0;
+  rc = read_slots(h, 1, r, &c);
+  if (rc) return rc;
+  *res = r[0];
+  if (changes) *changes = c;
+  if (!std::isfinite(*res)) return fail(h, CPMDP_E_NONFINITE, "non-finite Bellman residual");
+  return CPMDP_OK;
+}
+
+}  // namespace cpm
+
+using namespace cpm;
+
+// =================================================================== C ABI
+
+extern "C" {
+
+int cpmdp_create(cpmdp_t** out, int32_t n_dims, const int64_t* sizes, int32_t n_actions,
+                 const int32_t* ranks, const double* factors, const double* lambdas,
+                 const double* rewards, double gamma) {
+  if (!out) return fail(nullptr, CPMDP_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (!sizes || !ranks || !factors || !lambdas || !rewards)
+    return fail(nullptr, CPMDP_E_ARG, "NULL input array");
+  if (n_dims < 1 || n_dims > kMaxDims) return fail(nullptr, CPMDP_E_ARG, "n_dims must be in [1, 8]");
+  if (n_actions < 1 || n_actions > kMaxActions)
+    return fail(nullptr, CPMDP_E_ARG, "n_actions must be in [1, 255]");
+  int64_t S = 1;
+  for (int k = 0; k < n_dims; ++k) {
+    if (sizes[k] < 1) return fail(nullptr, CPMDP_E_ARG, "sizes must be >= 1");
+    if (sizes[k] > (1 << 30)) return fail(nullptr, CPMDP_E_ARG, "size too large");
+    S *= sizes[k];
+    if (S >= (int64_t(1) << 31)) return fail(nullptr, CPMDP_E_ARG, "state count must be < 2^31");
+  }
+  int64_t T = 0;
+  for (int a = 0; a < n_actions; ++a) {
+    if (ranks[a] < 1) return fail(nullptr, CPMDP_E_ARG, "ranks must be >= 1");
+    T += ranks[a];
+  }
+  if (T > (1 << 20)) return fail(nullptr, CPMDP_E_ARG, "too many rank terms");
+  if (!std::isfinite(gamma)) return fail(nullptr, CPMDP_E_NONFINITE, "gamma is not finite");
+  if (gamma < 0.0 || gamma >= 1.0) return fail(nullptr, CPMDP_E_ARG, "gamma must be in [0, 1)");
+  int64_t term_stride = 0;
+  for (int k = 0; k < n_dims; ++k) term_stride += sizes[k] * sizes[k];
+  const int64_t F = T * term_stride;
+  for (int64_t i = 0; i < F; ++i)
+    if (!std::isfinite(factors[i])) return fail(nullptr, CPMDP_E_NONFINITE, "non-finite factor entry");
+  for (int64_t i = 0; i < T; ++i)
+    if (!std::isfinite(lambdas[i])) return fail(nullptr, CPMDP_E_NONFINITE, "non-finite lambda");
+  for (int64_t s = 0; s < S; ++s)
+    if (!std::isfinite(rewards[s])) return fail(nullptr, CPMDP_E_NONFINITE, "non-finite reward");
+  // stochasticity of every factor row and of every action's lambdas
+  for (int64_t t = 0; t < T; ++t) {
+    int64_t off = t * term_stride;
+    for (int k = 0; k < n_dims; ++k) {
+      const int64_t m = sizes[k];
+      for (int64_t i = 0; i < m; ++i) {
+        double sum = 0.0;
+        for (int64_t j = 0; j < m; ++j) {
+          const double v = factors[off + i * m + j];
+          if (v < 0.0) {
+            char buf[160];
+            std::snprintf(buf, sizeof buf, "negative probability in term %lld dim %d row %lld",
+                          (long long)t, k, (long long)i);
+            return fail(nullptr, CPMDP_E_NOT_STOCHASTIC, buf);
+          }
+          sum += v;
+        }
+        if (std::fabs(sum - 1.0) > 1e-12) {
+          char buf[160];
+          std::snprintf(buf, sizeof buf, "row %lld of factor (term %lld, dim %d) sums to %.17g",
+                        (long long)i, (long long)t, k, sum);
+          return fail(nullptr, CPMDP_E_NOT_STOCHASTIC, buf);
+        }
+      }
+      off += m * m;
+    }
+  }
+  {
+    int64_t t = 0;
+    for (int a = 0; a < n_actions; ++a) {
+      double sum = 0.0;
+      for (int r = 0; r < ranks[a]; ++r, ++t) {
+        if (lambdas[t] < 0.0) return fail(nullptr, CPMDP_E_NOT_STOCHASTIC, "negative lambda");
+        sum += lambdas[t];
+      }
+      if (std::fabs(sum - 1.0) > 1e-12) {
+        char buf[128];
+        std::snprintf(buf, sizeof buf, "lambdas of action %d sum to %.17g", a, sum);
+        return fail(nullptr, CPMDP_E_NOT_STOCHASTIC, buf);
+      }
+    }
+  }
+
+  cpmdp_t* h = new (std::nothrow) cpmdp_t();
+  if (!h) return fail(nullptr, CPMDP_E_ARG, "out of host memory");
+  h->n = n_dims;
+  h->S = S;
+  h->A = n_actions;
+  h->gamma = gamma;
+  h->sizes.assign(sizes, sizes + n_dims);
+  h->ranks.assign(ranks, ranks + n_actions);
+  h->factors.assign(factors, factors + F);
+  h->lambdas.assign(lambdas, lambdas + T);
+  h->rewards.assign(rewards, rewards + S);
+  h->terminal.assign(static_cast<size_t>(S), 0);
+  h->term_start.resize(n_actions + 1);
+  h->term_start[0] = 0;
+  for (int a = 0; a < n_actions; ++a) h->term_start[a + 1] = h->term_start[a] + ranks[a];
+  h->kinds.resize(static_cast<size_t>(T) * n_dims);
+  bool stencil = true;
+  for (int64_t t = 0; t < T; ++t) {
+    int64_t off = t * term_stride;
+    int non_id = 0;
+    for (int k = 0; k < n_dims; ++k) {
+      const int kind = classify(factors + off, static_cast<int>(sizes[k]));
+      h->kinds[t * n_dims + k] = static_cast<uint8_t>(kind);
+      if (kind != F_IDENT) ++non_id;
+      if (kind == F_DENSE) stencil = false;
+      off += sizes[k] * sizes[k];
+    }
+    if (non_id > 1) stencil = false;
+  }
+  h->path = stencil ? CPMDP_PATH_STENCIL : CPMDP_PATH_DENSE;
+  h->geom = make_geom(h);
+  if (stencil) {
+    const int P = 2 * n_dims + 1;
+    h->w.assign(static_cast<size_t>(n_actions) * P, 0.0);
+    for (int a = 0; a < n_actions; ++a)
+      for (int t = h->term_start[a]; t < h->term_start[a + 1]; ++t) {
+        int p = 0;
+        for (int k = 0; k < n_dims; ++k) {
+          const int kind = h->kinds[t * n_dims + k];
+          if (kind == F_SHIFT_P) p = 1 + 2 * k;
+          if (kind == F_SHIFT_M) p = 2 + 2 * k;
+        }
+        h->w[a * P + p] += lambdas[t];
+      }
+  } else {
+    if (!choose_split(h->sizes, S, sizeof(double), h->cg64) ||
+        !choose_split(h->sizes, S, sizeof(float), h->cg32)) {
+      delete h;
+      return fail(nullptr, CPMDP_E_UNSUPPORTED,
+                  "dense factors need every m_k <= 32 and a row/column split of the "
+                  "dimensions that fits LDS");
+    }
+  }
+  *out = h;
+  return CPMDP_OK;
+}
+
+int cpmdp_set_terminal(cpmdp_t* h, const uint8_t* mask) {
+  if (!h) return fail(nullptr, CPMDP_E_ARG, "handle is NULL");
+  if (!mask) return fail(h, CPMDP_E_ARG, "mask is NULL");
+  if (h->bound) return fail(h, CPMDP_E_STATE, "set_terminal must precede bind");
+  for (int64_t s = 0; s < h->S; ++s) h->terminal[s] = mask[s] ? 1 : 0;
+  return CPMDP_OK;
+}
+
+int cpmdp_set_obstacles(cpmdp_t* h, const uint8_t* mask) {
+  if (!h) return fail(nullptr, CPMDP_E_ARG, "handle is NULL");
+  if (!mask) return fail(h, CPMDP_E_ARG, "mask is NULL");
+  for (int64_t s = 0; s < h->S; ++s)
+    if (mask[s])
+      return fail(h, CPMDP_E_UNSUPPORTED,
+                  "obstacles break the Kronecker form of P_a and are not supported");
+  return CPMDP_OK;
+}
+
+int cpmdp_get_path(const cpmdp_t* h, int32_t* path) {
+  if (!h || !path) return fail(nullptr, CPMDP_E_ARG, "NULL argument");
+  *path = h->path;
+  return CPMDP_OK;
+}
+
+int cpmdp_workspace_bytes(const cpmdp_t* h, size_t* bytes) {
+  if (!h || !bytes) return fail(nullptr, CPMDP_E_ARG, "NULL argument");
+  DevPtrs tmp;
+  layout(h, &tmp, nullptr, bytes);
+  return CPMDP_OK;
+}
+
+int cpmdp_bind(cpmdp_t* h, void* ws, size_t bytes, void* stream) {
+  if (!h) return fail(nullptr, CPMDP_E_ARG, "handle is NULL");
+  if (!ws) return fail(h, CPMDP_E_WORKSPACE, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0)
+    return fail(h, CPMDP_E_WORKSPACE, "workspace must be 256-byte aligned");
+  size_t need = 0;
+  DevPtrs tmp;
+  layout(h, &tmp, nullptr, &need);
+  if (bytes < need) {
+    char buf[128];
+    std::snprintf(buf, sizeof buf, "workspace has %zu bytes, %zu needed", bytes, need);
+    return fail(h, CPMDP_E_WORKSPACE, buf);
+  }
+  h->stream = static_cast<hipStream_t>(stream);
+  if (h->path == CPMDP_PATH_DENSE) {
+    int dev = 0, lds = 0;
+    HIP_TRY(h, hipGetDevice(&dev));
+    HIP_TRY(h, hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    const int64_t need_lds = std::max(chain_lds_bytes(h->cg64, 8), chain_lds_bytes(h->cg32, 4));
+    if (need_lds > lds) {
+      char buf[160];
+      std::snprintf(buf, sizeof buf, "chain kernels need %lld bytes of LDS per block, device has %d",
+                    (long long)need_lds, lds);
+      return fail(h, CPMDP_E_UNSUPPORTED, buf);
+    }
+  }
+  layout(h, &h->d, static_cast<char*>(ws), &need);
+  h->ws = static_cast<char*>(ws);
+  h->ws_bytes = bytes;
+  if (!h->host_slots) {
+    HIP_TRY(h, hipHostMalloc(reinterpret_cast<void**>(&h->host_slots),
+                             sizeof(unsigned long long) * kSlots, hipHostMallocDefault));
+    HIP_TRY(h, hipHostMalloc(reinterpret_cast<void**>(&h->host_ctr), sizeof(unsigned) * 8,
+                             hipHostMallocDefault));
+  }
+  const size_t S = static_cast<size_t>(h->S);
+  std::vector<float> f32(S);
+  for (size_t s = 0; s < S; ++s) f32[s] = static_cast<float>(h->rewards[s]);
+  std::vector<uint32_t> bits((S + 31) / 32 + 1, 0u);
+  for (size_t s = 0; s < S; ++s)
+    if (h->terminal[s]) bits[s >> 5] |= 1u << (s & 31);
+  const hipStream_t st = h->stream;
+  HIP_TRY(h, hipMemcpyAsync(h->d.R64, h->rewards.data(), S * 8, hipMemcpyHostToDevice, st));
+  HIP_TRY(h, hipMemcpyAsync(h->d.R32, f32.data(), S * 4, hipMemcpyHostToDevice, st));
+  HIP_TRY(h, hipMemcpyAsync(h->d.tbits, bits.data(), bits.size() * 4, hipMemcpyHostToDevice, st));
+  std::vector<float> w32;
+  std::vector<float> fac32, lam32;
+  std::vector<uint16_t> facbf;
+  std::vector<int32_t> ts;
+  if (h->path == CPMDP_PATH_STENCIL) {
+    w32.resize(h->w.size());
+    for (size_t i = 0; i < h->w.size(); ++i) w32[i] = static_cast<float>(h->w[i]);
+    HIP_TRY(h, hipMemcpyAsync(h->d.w64, h->w.data(), h->w.size() * 8, hipMemcpyHostToDevice, st));
+    HIP_TRY(h, hipMemcpyAsync(h->d.w32, w32.data(), w32.size() * 4, hipMemcpyHostToDevice, st));
+  } else {
+    const size_t F = h->factors.size();
+    fac32.resize(F);
+    facbf.resize(F);
+    for (size_t i = 0; i < F; ++i) {
+      const float f = static_cast<float>(h->factors[i]);
+      fac32[i] = f;
+      uint32_t u;
+      std::memcpy(&u, &f, 4);
+      const uint32_t rounding = 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
+      facbf[i] = static_cast<uint16_t>((u + rounding) >> 16);
+    }
+    lam32.resize(h->lambdas.size());
+    for (size_t i = 0; i < lam32.size(); ++i) lam32[i] = static_cast<float>(h->lambdas[i]);
+    ts.assign(h->term_start.begin(), h->term_start.end());
+    HIP_TRY(h, hipMemcpyAsync(h->d.fac64, h->factors.data(), F * 8, hipMemcpyHostToDevice, st));
+    HIP_TRY(h, hipMemcpyAsync(h->d.fac32, fac32.data(), F * 4, hipMemcpyHostToDevice, st));
+    HIP_TRY(h, hipMemcpyAsync(h->d.facbf, facbf.data(), F * 2, hipMemcpyHostToDevice, st));
+    HIP_TRY(h, hipMemcpyAsync(h->d.lam64, h->lambdas.data(), lam32.size() * 8,
+                              hipMemcpyHostToDevice, st));
+    HIP_TRY(h, hipMemcpyAsync(h->d.lam32, lam32.data(), lam32.size() * 4, hipMemcpyHostToDevice, st));
+    HIP_TRY(h, hipMemcpyAsync(h->d.kinds, h->kinds.data(), h->kinds.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(h, hipMemcpyAsync(h->d.term_start, ts.data(), ts.size() * 4, hipMemcpyHostToDevice, st));
+  }
+  HIP_TRY(h, hipStreamSynchronize(st));
+  h->bound = true;
+  return CPMDP_OK;
+}
+
+int cpmdp_set_stream(cpmdp_t* h, void* stream) {
+  if (!h) return fail(nullptr, CPMDP_E_ARG, "handle is NULL");
+  h->stream = static_cast<hipStream_t>(stream);
+  return CPMDP_OK;
+}
+
+static int check_common(cpmdp_t* h, int precision) {
+  if (!h) return fail(nullptr, CPMDP_E_ARG, "handle is NULL");
+  if (!h->bound) return fail(h, CPMDP_E_STATE, "handle is not bound to a workspace");
+  if (precision < CPMDP_FP64 || precision > CPMDP_BF16)
+    return fail(h, CPMDP_E_ARG, "unknown precision");
+  return CPMDP_OK;
+}
+
+static int check_policy(cpmdp_t* h, const int32_t* pi) {
+  launch_fill_u32(h->d.counters + 4, 1, 0u, h->stream);
+  launch_check_policy(pi, h->S, h->A, h->d.counters + 4, h->stream);
+  HIP_TRY(h, hipMemcpyAsync(h->host_ctr + 4, h->d.counters + 4, 4, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  if (h->host_ctr[4] != 0) return fail(h, CPMDP_E_ARG, "policy holds actions outside [0, A)");
+  return CPMDP_OK;
+}
+
+int cpmdp_backup(cpmdp_t* h, const void* V_in, void* V_out, int32_t* pi_out,
+                 double* residual_host, int precision) {
+  int rc = check_common(h, precision);
+  if (rc) return rc;
+  if (!V_in || !V_out) return fail(h, CPMDP_E_ARG, "NULL value buffer");
+  if (V_in == V_out) return fail(h, CPMDP_E_ARG, "V_in and V_out must not alias");
+  const bool p64 = precision == CPMDP_FP64;
+  launch_fill_u64(h->d.slots, 1, 0ull, h->stream);
+  if (pi_out) {
+    launch_fill_u64(h->d.vmax, 1, 0ull, h->stream);
+    if (p64) {
+      launch_maxabs_f64(static_cast<const double*>(V_in), h->S, h->d.vmax, h->stream);
+    } else {
+      launch_f32_to_f64(static_cast<const float*>(V_in), h->d.Va64, h->S, h->stream);
+      launch_maxabs_f64(h->d.Va64, h->S, h->d.vmax, h->stream);
+    }
+  }
+  const int mode = pi_out ? MODE_GREEDY : MODE_MAX;
+  sweep(h, p64, mode, V_in, V_out, p64 ? static_cast<const void*>(h->d.R64) : h->d.R32, nullptr,
+        pi_out, nullptr, h->d.slots, nullptr, precision == CPMDP_BF16);
+  rc = check_device(h);
+  if (rc) return rc;
+  if (residual_host) {
+    std::vector<double> r;
+    rc = read_slots(h, 1, r, nullptr);
+    if (rc) return rc;
+    *residual_host = r[0];
+    if (!std::isfinite(r[0])) return fail(h, CPMDP_E_NONFINITE, "non-finite residual");
+  }
+  return CPMDP_OK;
+}
+
+int cpmdp_policy_backup(cpmdp_t* h, const void* V_in, void* V_out, const int32_t* pi,
+                        double* residual_host, int precision) {
+  int rc = check_common(h, precision);
+  if (rc) return rc;
+  if (!V_in || !V_out || !pi) return fail(h, CPMDP_E_ARG, "NULL buffer");
+  if (V_in == V_out) return fail(h, CPMDP_E_ARG, "V_in and V_out must not alias");
+  rc = check_policy(h, pi);
+  if (rc) return rc;
+  const bool p64 = precision == CPMDP_FP64;
+  launch_fill_u64(h->d.slots, 1, 0ull, h->stream);
+  sweep(h, p64, MODE_EVAL, V_in, V_out, p64 ? static_cast<const void*>(h->d.R64) : h->d.R32, pi,
+        nullptr, nullptr, h->d.slots, nullptr, precision == CPMDP_BF16);
+  rc = check_device(h);
+  if (rc) return rc;
+  if (residual_host) {
+    std::vector<double> r;
+    rc = read_slots(h, 1, r, nullptr);
+    if (rc) return rc;
+    *residual_host = r[0];
+  }
+  return CPMDP_OK;
+}
+
+int cpmdp_value_iteration(cpmdp_t* h, double* V, int32_t* pi_out, double eps, int64_t max_iter,
+                          int precision, int64_t* sweeps_out, double* residual_out) {
+  int rc = check_common(h, precision);
+  if (rc) return rc;
+  if (!V) return fail(h, CPMDP_E_ARG, "V is NULL");
+  if (!(eps > 0.0) || !std::isfinite(eps)) return fail(h, CPMDP_E_ARG, "eps must be > 0");
+  if (max_iter < 1) return fail(h, CPMDP_E_ARG, "max_iter must be >= 1");
+  int64_t sweeps = 0;
+  bool done = false;
+  double last = INFINITY;
+  const hipStream_t st = h->stream;
+  if (precision != CPMDP_FP64) {
+    // Low-precision sweeps until their own rounding floor, then FP64.
+    double rmax = 0.0;
+    for (double r : h->rewards) rmax = std::max(rmax, std::fabs(r));
+    const double vbound = rmax / (1.0 - h->gamma);
+    const double floor32 = 8.0 * std::ldexp(1.0, -24) * std::max(1.0, vbound);
+    launch_f64_to_f32(V, h->d.Va32, h->S, st);
+    float* cur = h->d.Va32;
+    float* alt = h->d.Vb32;
+    rc = run_sweeps<float>(h, false, MODE_MAX, cur, alt, h->d.R32, nullptr,
+                           std::max(eps, floor32), floor32 * 4, max_iter - 1, &sweeps, &done,
+                           &last, precision == CPMDP_BF16);
+    if (rc) return rc;
+    launch_f32_to_f64(cur, V, h->S, st);
+  }
+  double cert = INFINITY;
+  for (;;) {
+    double* cur = V;
+    double* alt = h->d.Va64;
+    rc = run_sweeps<double>(h, true, MODE_MAX, cur, alt, h->d.R64, nullptr, eps, 0.0,
+                            max_iter - 1, &sweeps, &done, &last, false);
+    if (rc) return rc;
+    if (cur != V) HIP_TRY(h, hipMemcpyAsync(V, cur, h->S * 8, hipMemcpyDeviceToDevice, st));
+    rc = certify(h, V, pi_out, nullptr, &cert, nullptr);
+    if (rc) return rc;
+    ++sweeps;
+    if (cert <= eps || sweeps >= max_iter) break;
+  }
+  if (sweeps_out) *sweeps_out = sweeps;
+  if (residual_out) *residual_out = cert;
+  return cert <= eps ? CPMDP_OK : CPMDP_NOT_CONVERGED;
+}
+
+int cpmdp_policy_iteration(cpmdp_t* h, double* V, int32_t* pi, double eps, int64_t max_iter,
+                           int precision, int64_t* outer_out, int64_t* sweeps_out,
+                           double* residual_out) {
+  int rc = check_common(h, precision);
+  if (rc) return rc;
+  if (!V || !pi) return fail(h, CPMDP_E_ARG, "NULL buffer");
+  if (!(eps > 0.0) || !std::isfinite(eps)) return fail(h, CPMDP_E_ARG, "eps must be > 0");
+  if (max_iter < 1) return fail(h, CPMDP_E_ARG, "max_iter must be >= 1");
+  rc = check_policy(h, pi);
+  if (rc) return rc;
+  const hipStream_t st = h->stream;
+  int64_t sweeps = 0, outer = 0;
+  double rmax = 0.0;
+  for (double r : h->rewards) rmax = std::max(rmax, std::fabs(r));
+  const double eps_floor = 0.5 * eps * (1.0 - h->gamma);
+  double eps_eval = std::max(eps_floor, 1e-2 * std::max(rmax, 1e-300));
+  double cert = INFINITY;
+  bool converged = false;
+  const bool low = precision != CPMDP_FP64;
+  const double floor32 =
+      8.0 * std::ldexp(1.0, -24) * std::max(1.0, rmax / (1.0 - h->gamma));
+  while (sweeps < max_iter) {
+    ++outer;
+    // ---- evaluation of pi
+    if (!low) {
+      double* cur = V;
+      double* alt = h->d.Va64;
+      bool done = false;
+      double last = 0;
+      rc = run_sweeps<double>(h, true, MODE_EVAL, cur, alt, h->d.R64, pi, eps_eval, 0.0,
+                              max_iter - 1, &sweeps, &done, &last, false);
+      if (rc) return rc;
+      if (cur != V) HIP_TRY(h, hipMemcpyAsync(V, cur, h->S * 8, hipMemcpyDeviceToDevice, st));
+    } else {
+      for (;;) {
+        if (sweeps >= max_iter - 1) break;
+        // FP64 residual of the evaluation equation: r = R + g P_pi V - V
+        launch_fill_u64(h->d.slots, 1, 0ull, st);
+        sweep(h, true, MODE_RESID, V, nullptr, h->d.R64, pi, nullptr, h->d.r32, h->d.slots,
+              nullptr, false);
+        rc = check_device(h);
+        if (rc) return rc;
+        std::vector<double> r;
+        rc = read_slots(h, 1, r, nullptr);
+        if (rc) return rc;
+        ++sweeps;
+        if (!std::isfinite(r[0])) return fail(h, CPMDP_E_NONFINITE, "non-finite residual");
+        if (r[0] <= eps_eval) break;
+        // correction e <- r + g P_pi e, from e = 0, in the low precision
+        launch_fill_f32(h->d.E0, h->S, 0.0f, st);
+        float* cur = h->d.E0;
+        float* alt = h->d.E1;
+        bool done = false;
+        double last = 0;
+        const double tol_e = std::max(1e-3 * r[0], floor32 * 1e-3);
+        rc = run_sweeps<float>(h, false, MODE_EVAL, cur, alt, h->d.r32, pi, tol_e, 0.0,
+                               max_iter - 1, &sweeps, &done, &last, precision == CPMDP_BF16);
+        if (rc) return rc;
+        launch_add_f32_to_f64(V, cur, h->S, st);
+      }
+    }
+    // ---- improvement (FP64), keeping the incumbent on ties
+    unsigned changes = 0;
+    rc = certify(h, V, pi, pi, &cert, &changes);
+    if (rc) return rc;
+    ++sweeps;
+    if (changes == 0 && cert <= eps) {
+      converged = true;
+      break;
+    }
+    if (changes == 0) eps_eval = std::max(eps_floor, 0.05 * cert);
+    else eps_eval = std::max(eps_floor, std::min(eps_eval, 0.05 * cert));
+  }
+  if (outer_out) *outer_out = outer;
+  if (sweeps_out) *sweeps_out = sweeps;
+  if (residual_out) *residual_out = cert;
+  return converged ? CPMDP_OK : CPMDP_NOT_CONVERGED;
+}
+
+void cpmdp_destroy(cpmdp_t* h) {
+  if (!h) return;
+  if (h->host_slots) (void)hipHostFree(h->host_slots);
+  if (h->host_ctr) (void)hipHostFree(h->host_ctr);
+  delete h;
+}
+
+const char* cpmdp_last_error(const cpmdp_t* h) {
+  if (h) return h->err.c_str();
+  return g_last_error.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,80 @@
+// Device helpers shared by the cpmdp kernels.
+#pragma once
+
+#include "cpmdp_internal.h"
+
+namespace cpm {
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, FastDiv d) {
+  return (__umulhi(n, d.magic) + n) >> d.shift;
+}
+
+// Blocks are dispatched to the 8 XCDs round-robin (block b -> XCD b % 8).
+// Renumber them so that each XCD walks one contiguous range of the logical
+// block space: neighbouring tiles then share that XCD's L2.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int q = nb / kXcds, rem = nb % kXcds;
+  const int x = b % kXcds, j = b / kXcds;
+  return x * q + (x < rem ? x : rem) + j;
+}
+
+// max that keeps NaN (so a non-finite residual is reported, not hidden).
+__device__ __forceinline__ double nanmax(double a, double b) {
+  return (a != a || a > b) ? a : b;
+}
+
+// Block-wide max of v, folded into *slot (FP64 bit pattern; non-negative
+// doubles order like their bits, NaN sorts above +inf).
+__device__ __forceinline__ void block_max_to_slot(double v, unsigned long long* slot) {
+  __shared__ double part[16];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = nanmax(v, __shfl_xor(v, off));
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) part[wid] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = part[0];
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int i = 1; i < nw; ++i) m = nanmax(m, part[i]);
+    atomicMax(slot, static_cast<unsigned long long>(__double_as_longlong(m)));
+  }
+}
+
+__device__ __forceinline__ void block_sum_to_counter(unsigned v, unsigned int* ctr) {
+  __shared__ unsigned part[16];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) part[wid] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned m = 0;
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int i = 0; i < nw; ++i) m += part[i];
+    if (m) atomicAdd(ctr, m);
+  }
+}
+
+__device__ __forceinline__ bool is_terminal(const uint32_t* bits, int s) {
+  return (bits[s >> 5] >> (s & 31)) & 1u;
+}
+
+__device__ __forceinline__ double tie_tol(const unsigned long long* vmax_bits) {
+  const double vm = __longlong_as_double(static_cast<long long>(*vmax_bits));
+  return kTieRel * (vm > 1.0 ? vm : 1.0);
+}
+
+// Running tie rule over actions visited in increasing index order: the
+// candidate changes only when a later action exceeds the running maximum by
+// more than tol, so among near-equal maxima the lowest index is kept.
+template <typename T>
+__device__ __forceinline__ void tie_update(T q, int act, T tol, T& best, int& bi) {
+  if (q > best + tol || best != best) {
+    best = q;
+    bi = act;
+  } else if (q > best) {
+    best = q;
+  }
+}
+
+}  // namespace cpm

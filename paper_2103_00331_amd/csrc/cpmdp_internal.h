@@ -1,0 +1,132 @@
+// Internal declarations of the cpmdp GPU library (host runtime <-> kernels).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "cpmdp.h"
+
+namespace cpm {
+
+constexpr int kMaxDims = 8;
+constexpr int kMaxActions = 255;
+constexpr int kSlots = 256;        // residual slots (one per sweep of a chunk)
+constexpr int kBlock = 256;        // threads per block of the streaming kernels
+constexpr int kXcds = 8;           // MI355X: 8 XCDs, 32 CUs each
+constexpr double kTieRel = 1e-12;  // tie tolerance relative to max(1,||V||)
+
+// Kind of one factor T^{(k)}_{a,r}.
+enum FactorKind : uint8_t { F_IDENT = 0, F_SHIFT_P = 1, F_SHIFT_M = 2, F_DENSE = 3 };
+
+// What a sweep writes.
+//   MAX    : V'(s) = max_a Q_a(s); residual max |V' - V|.
+//   GREEDY : as MAX, plus pi(s) by the tie rule; with an incumbent policy the
+//            incumbent is kept unless beaten by more than tol, and the number
+//            of changed states is counted.
+//   EVAL   : V'(s) = R(s) + gamma (1 - tau(s)) (P_{pi(s)} V)(s).
+//   RESID  : as EVAL but writes r(s) = V'(s) - V(s) as FP32 (refinement
+//            right-hand side); residual max |r|.
+enum Mode : int { MODE_MAX = 0, MODE_GREEDY = 1, MODE_EVAL = 2, MODE_RESID = 3 };
+
+// Division by a runtime constant d < 2^31 for numerators < 2^31:
+// q = (umulhi(n, magic) + n) >> shift   (Granlund & Montgomery, PLDI 1994).
+struct FastDiv {
+  uint32_t magic;
+  uint32_t shift;
+};
+
+FastDiv make_fastdiv(uint32_t d);
+
+struct GridGeom {
+  int32_t n;
+  int32_t S;
+  int32_t size[kMaxDims];
+  int32_t stride[kMaxDims];
+  FastDiv div[kMaxDims];
+};
+
+// ---------------------------------------------------------------- stencil
+template <typename T>
+struct StencilArgs {
+  GridGeom g;
+  int32_t A;
+  int32_t npts;                 // 2n + 1: centre, then (+e_k, -e_k) per dim
+  const T* w;                   // [A][npts] summed rank weights
+  const T* V;                   // input values
+  T* Vout;                      // MAX / GREEDY / EVAL output (nullable for GREEDY)
+  const T* R;                   // rewards, or the right-hand side of a correction sweep
+  const float* Rf;              // EVAL on a T=float sweep with FP32 rhs (== R) -- unused otherwise
+  const uint32_t* term_bits;    // terminal mask, 1 bit per state
+  T gamma;
+  const int32_t* pi_in;         // EVAL: policy; GREEDY: incumbent (nullable)
+  int32_t* pi_out;              // GREEDY output (nullable)
+  float* r_out;                 // RESID output
+  const unsigned long long* vmax_bits;  // GREEDY: ||V||_inf as FP64 bits
+  unsigned long long* res_slot; // max |out - V| as FP64 bits (atomic max)
+  unsigned int* change_count;   // GREEDY with incumbent
+  int32_t nblocks;
+};
+
+template <typename T>
+void launch_stencil(const StencilArgs<T>& a, int mode, hipStream_t st);
+
+// ----------------------------------------------------------- dense chains
+struct ChainGeom {
+  int32_t n, n1;                // dims [0, n1) = row group, [n1, n) = column group
+  int32_t S, Rr, C;             // rows (prod of row dims), columns (prod of col dims)
+  int32_t CT, ct_shift;         // columns per pass-2 tile (power of two)
+  int32_t ntiles;               // ceil(C / CT)
+  int32_t size[kMaxDims];
+  int32_t fac_off[kMaxDims];    // offset of dim k's block inside one term
+  int32_t term_stride;          // sum_k m_k^2
+  int32_t mmax_row, mmax_col;
+  int64_t w_term_stride;        // elements per term in the intermediate buffer
+};
+
+template <typename T>
+struct ChainArgs {
+  ChainGeom g;
+  int32_t A;
+  int32_t nterms;
+  const int32_t* term_start;    // [A+1] first term of each action
+  const T* fac;                 // packed factors in T
+  const T* lam;                 // [nterms]
+  const uint8_t* kinds;         // [nterms][n]
+  const T* V;
+  T* W;                         // intermediates [nterms][ntiles][Rr][CT]
+  T* Vout;
+  const T* R;
+  const uint32_t* term_bits;
+  T gamma;
+  const int32_t* pi_in;
+  int32_t* pi_out;
+  float* r_out;
+  const unsigned long long* vmax_bits;
+  unsigned long long* res_slot;
+  unsigned int* change_count;
+};
+
+template <typename T>
+void launch_chain(const ChainArgs<T>& a, int mode, hipStream_t st);
+
+// BF16 operands on MFMA, FP32 accumulation; only 16^n1 x 16^(n-n1) splits.
+bool chain_bf16_supported(const ChainGeom& g);
+void launch_chain_bf16(const ChainArgs<float>& a, const uint16_t* fac_bf16,
+                       uint16_t* W_bf16, int mode, hipStream_t st);
+
+// ---------------------------------------------------------------- helpers
+void launch_fill_u64(unsigned long long* p, int n, unsigned long long v, hipStream_t st);
+void launch_fill_u32(unsigned int* p, int n, unsigned int v, hipStream_t st);
+void launch_f64_to_f32(const double* src, float* dst, int64_t n, hipStream_t st);
+void launch_f32_to_f64(const float* src, double* dst, int64_t n, hipStream_t st);
+void launch_add_f32_to_f64(double* dst, const float* e, int64_t n, hipStream_t st);
+void launch_fill_f32(float* p, int64_t n, float v, hipStream_t st);
+void launch_copy_i32(const int32_t* src, int32_t* dst, int64_t n, hipStream_t st);
+void launch_maxabs_f64(const double* v, int64_t n, unsigned long long* slot, hipStream_t st);
+void launch_check_policy(const int32_t* pi, int64_t n, int32_t A, unsigned int* bad, hipStream_t st);
+
+}  // namespace cpm

@@ -1,0 +1,71 @@
+// The opaque handle behind cpmdp_t (host side only).
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "cpmdp_internal.h"
+
+namespace cpm {
+
+// Device arrays carved out of the caller's workspace.
+struct DevPtrs {
+  double* R64 = nullptr;
+  float* R32 = nullptr;
+  uint32_t* tbits = nullptr;
+  unsigned long long* slots = nullptr;   // per-sweep residuals (FP64 bits)
+  unsigned long long* vmax = nullptr;    // ||V||_inf (FP64 bits) for the tie rule
+  unsigned int* counters = nullptr;      // [0] policy changes, [4] bad actions
+  double* Va64 = nullptr;                // FP64 ping-pong partner of the caller's V
+  float* Va32 = nullptr;
+  float* Vb32 = nullptr;
+  float* E0 = nullptr;                   // refinement correction ping-pong
+  float* E1 = nullptr;
+  float* r32 = nullptr;                  // refinement right-hand side
+  int32_t* piA = nullptr;                // policy scratch
+  double* w64 = nullptr;                 // stencil weights [A][2n+1]
+  float* w32 = nullptr;
+  double* fac64 = nullptr;               // dense factors, packed per term
+  float* fac32 = nullptr;
+  uint16_t* facbf = nullptr;             // BF16 bit patterns
+  double* lam64 = nullptr;
+  float* lam32 = nullptr;
+  uint8_t* kinds = nullptr;
+  int32_t* term_start = nullptr;
+  char* W = nullptr;                     // dense-chain intermediates
+};
+
+}  // namespace cpm
+
+struct cpmdp {
+  int n = 0;
+  int64_t S = 0;
+  int A = 0;
+  double gamma = 0.0;
+  std::vector<int64_t> sizes;
+  std::vector<int32_t> ranks;
+  std::vector<int32_t> term_start;
+  std::vector<double> factors, lambdas, rewards;
+  std::vector<uint8_t> terminal;
+  std::vector<uint8_t> kinds;
+  int path = 0;
+  std::vector<double> w;                 // stencil weights [A][2n+1]
+  cpm::GridGeom geom{};
+  cpm::ChainGeom cg64{}, cg32{};
+  bool bound = false;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  hipStream_t stream = nullptr;
+  cpm::DevPtrs d;
+  unsigned long long* host_slots = nullptr;  // pinned
+  unsigned* host_ctr = nullptr;              // pinned
+  std::string err;
+};
+
+namespace cpm {
+int fail(cpmdp_t* h, int code, const std::string& msg);
+void layout(const cpmdp_t* h, DevPtrs* d, char* base, size_t* total);
+void sweep(cpmdp_t* h, bool prec64, int mode, const void* V, void* Vout, const void* R,
+           const int32_t* pi_in, int32_t* pi_out, float* r_out, unsigned long long* slot,
+           unsigned int* ctr, bool bf16);
+}  // namespace cpm

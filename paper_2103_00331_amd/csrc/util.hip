@@ -1,0 +1,86 @@
+// Small streaming kernels: fills (used instead of hipMemsetAsync so that the
+// same launches can be captured into HIP graphs), precision conversions, the
+// FP64 refinement update V += e, a sup-norm reduction and a policy check.
+#include "common.cuh"
+
+namespace cpm {
+
+namespace {
+
+constexpr int kUtilBlock = 256;
+
+int util_grid(int64_t n) {
+  int64_t b = (n + kUtilBlock - 1) / kUtilBlock;
+  if (b > 65536) b = 65536;
+  return static_cast<int>(b < 1 ? 1 : b);
+}
+
+__global__ void fill_u64_kernel(unsigned long long* p, int n, unsigned long long v) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ void fill_u32_kernel(unsigned int* p, int n, unsigned int v) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ void fill_f32_kernel(float* p, int64_t n, float v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ void f64_to_f32_kernel(const double* s, float* d, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    d[i] = static_cast<float>(s[i]);
+}
+__global__ void f32_to_f64_kernel(const float* s, double* d, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    d[i] = static_cast<double>(s[i]);
+}
+__global__ void add_f32_to_f64_kernel(double* d, const float* e, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    d[i] += static_cast<double>(e[i]);
+}
+__global__ void copy_i32_kernel(const int32_t* s, int32_t* d, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    d[i] = s[i];
+}
+__global__ void maxabs_f64_kernel(const double* v, int64_t n, unsigned long long* slot) {
+  double m = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    m = nanmax(m, fabs(v[i]));
+  block_max_to_slot(m, slot);
+}
+__global__ void check_policy_kernel(const int32_t* pi, int64_t n, int32_t A, unsigned int* bad) {
+  unsigned c = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    c += (pi[i] < 0 || pi[i] >= A) ? 1u : 0u;
+  block_sum_to_counter(c, bad);
+}
+
+}  // namespace
+
+void launch_fill_u64(unsigned long long* p, int n, unsigned long long v, hipStream_t st) {
+  hipLaunchKernelGGL(fill_u64_kernel, dim3(util_grid(n)), dim3(kUtilBlock), 0, st, p, n, v);
+}
+void launch_fill_u32(unsigned int* p, int n, unsigned int v, hipStream_t st) {
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(util_grid(n)), dim3(kUtilBlock), 0, st, p, n, v);
+}
+void launch_fill_f32(float* p, int64_t n, float v, hipStream_t st) {
+  hipLaunchKernelGGL(fill_f32_kernel, dim3(util_grid(n)), dim3(kUtilBlock), 0, st, p, n, v);
+}
+void launch_f64_to_f32(const double* s, float* d, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(f64_to_f32_kernel, dim3(util_grid(n)), dim3(kUtilBlock), 0, st, s, d, n);
+}
+void launch_f32_to_f64(const float* s, double* d, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(f32_to_f64_kernel, dim3(util_grid(n)), dim3(kUtilBlock), 0, st, s, d, n);
+}
+void launch_add_f32_to_f64(double* d, const float* e, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(add_f32_to_f64_kernel, dim3(util_grid(n)), dim3(kUtilBlock), 0, st, d, e, n);
+}
+void launch_copy_i32(const int32_t* s, int32_t* d, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(copy_i32_kernel, dim3(util_grid(n)), dim3(kUtilBlock), 0, st, s, d, n);
+}
+void launch_maxabs_f64(const double* v, int64_t n, unsigned long long* slot, hipStream_t st) {
+  hipLaunchKernelGGL(maxabs_f64_kernel, dim3(util_grid(n)), dim3(kUtilBlock), 0, st, v, n, slot);
+}
+void launch_check_policy(const int32_t* pi, int64_t n, int32_t A, unsigned int* bad, hipStream_t st) {
+  hipLaunchKernelGGL(check_policy_kernel, dim3(util_grid(n)), dim3(kUtilBlock), 0, st, pi, n, A, bad);
+}
+
+}  // namespace cpm

@@ -1,0 +1,110 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function
+that include/cpmdp.h declares, and rejects invalid problems in cpmdp_create
+(host-only validation, no device work)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2103_00331_amd import binding as B
+from paper_2103_00331_amd import instances as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(cpmdp_[a-z0-9_]+)\s*\(", txt))
+    return names
+
+
+def test_exports_every_declared_symbol():
+    declared = _declared()
+    assert "cpmdp_create" in declared and "cpmdp_value_iteration" in declared
+    for name in sorted(declared):
+        assert hasattr(B.lib, name), name
+    assert declared <= set(B.EXPORTED)
+
+
+def _args(inst):
+    return (inst.sizes, inst.ranks, inst.factors, inst.lambdas, inst.rewards, inst.gamma)
+
+
+def test_create_valid_and_path_classification():
+    g = I.grid2d_16()
+    h = B.cpmdp_create(*_args(g))
+    assert B.cpmdp_get_path(h) == B.CPMDP_PATH_STENCIL
+    assert B.cpmdp_workspace_bytes(h) > 0
+    B.cpmdp_set_terminal(h, g.terminal)
+    B.cpmdp_destroy(h)
+    d = I.random_dense([3, 4], 2, 2, seed=1)
+    h = B.cpmdp_create(*_args(d))
+    assert B.cpmdp_get_path(h) == B.CPMDP_PATH_DENSE
+    B.cpmdp_destroy(h)
+
+
+def _expect(code, **changes):
+    g = I.grid_small([3, 4], seed=0)
+    a = dict(sizes=g.sizes.copy(), ranks=g.ranks.copy(), factors=g.factors.copy(),
+             lambdas=g.lambdas.copy(), rewards=g.rewards.copy(), gamma=g.gamma)
+    for k, v in changes.items():
+        a[k] = v(a[k]) if callable(v) else v
+    with pytest.raises(B.CpmdpError) as e:
+        B.cpmdp_create(a["sizes"], a["ranks"], a["factors"], a["lambdas"], a["rewards"],
+                       a["gamma"])
+    assert e.value.code == code, str(e.value)
+
+
+def _bump(i, by):
+    def f(x):
+        x = x.copy()
+        x[i] += by
+        return x
+    return f
+
+
+def test_create_rejects_invalid():
+    _expect(B.CPMDP_E_ARG, gamma=1.0)
+    _expect(B.CPMDP_E_ARG, gamma=-0.1)
+    _expect(B.CPMDP_E_NONFINITE, gamma=float("nan"))
+    _expect(B.CPMDP_E_NONFINITE, rewards=_bump(3, float("nan")))
+    _expect(B.CPMDP_E_NONFINITE, factors=_bump(0, float("inf")))
+    _expect(B.CPMDP_E_NOT_STOCHASTIC, factors=_bump(0, 1e-9))       # row sum off
+    _expect(B.CPMDP_E_NOT_STOCHASTIC, lambdas=_bump(0, 1e-9))       # lambda sum off
+    _expect(B.CPMDP_E_ARG, sizes=np.array([3, 0]))                   # size 0
+    _expect(B.CPMDP_E_ARG, ranks=lambda r: np.where(np.arange(r.size) == 0, 0, r))
+
+
+def test_negative_probability_rejected():
+    g = I.grid_small([3, 4], seed=0)
+    f = g.factors.copy()
+    f[0:3] = [1.5, -0.5, 0.0]    # row 0 of the first factor still sums to 1
+    with pytest.raises(B.CpmdpError) as e:
+        B.cpmdp_create(g.sizes, g.ranks, f, g.lambdas, g.rewards, g.gamma)
+    assert e.value.code == B.CPMDP_E_NOT_STOCHASTIC
+
+
+def test_obstacles_unsupported_and_calls_before_bind():
+    g = I.grid_small([3, 4], seed=0)
+    h = B.cpmdp_create(*_args(g))
+    mask = np.zeros(g.n_states, np.uint8)
+    B.cpmdp_set_obstacles(h, mask)          # no obstacle: fine
+    mask[5] = 1
+    with pytest.raises(B.CpmdpError) as e:
+        B.cpmdp_set_obstacles(h, mask)
+    assert e.value.code == B.CPMDP_E_UNSUPPORTED
+    code = B.lib.cpmdp_value_iteration(h, None, None, 1e-6, 10, 0, None, None)
+    assert code == B.CPMDP_E_STATE          # not bound to a workspace yet
+    B.cpmdp_destroy(h)
+
+
+def test_dense_factor_size_limit():
+    d = I.random_dense([40, 2], 1, 1, seed=3)
+    with pytest.raises(B.CpmdpError) as e:
+        B.cpmdp_create(*_args(d))
+    assert e.value.code == B.CPMDP_E_UNSUPPORTED

@@ -1,0 +1,140 @@
+"""GPU parity of the dense mode-product-chain path against the FP64 oracle,
+through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2103_00331_amd import instances as I
+from tests.parity import assert_close, compare_policy, log, tol_for
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2103_00331_amd import binding
+    assert torch.cuda.is_available(), "GPU test run without a GPU"
+    return binding
+
+
+def _dt(prec):
+    return torch.float64 if prec == 0 else torch.float32
+
+
+def _backup(B, model, V, prec, with_pi=True):
+    Vin = torch.as_tensor(np.asarray(V), dtype=_dt(prec), device="cuda")
+    Vout = torch.empty_like(Vin)
+    pi = torch.full((model.S,), -7, dtype=torch.int32, device="cuda") if with_pi else None
+    r = B.cpmdp_backup(model.h, Vin, Vout, pi, residual=True, precision=prec)
+    torch.cuda.synchronize()
+    return (Vout.cpu().numpy().astype(np.float64),
+            None if pi is None else pi.cpu().numpy(), r)
+
+
+def _solve(B, model, method, prec, eps, max_iter=200000):
+    V = torch.zeros(model.S, dtype=torch.float64, device="cuda")
+    pi = torch.zeros(model.S, dtype=torch.int32, device="cuda")
+    if method == "vi":
+        code, sweeps, res = B.cpmdp_value_iteration(model.h, V, pi, eps, max_iter, prec)
+    else:
+        code, _, sweeps, res = B.cpmdp_policy_iteration(model.h, V, pi, eps, max_iter, prec)
+    torch.cuda.synchronize()
+    return V.cpu().numpy(), pi.cpu().numpy(), code, sweeps, res
+
+
+CASES = {
+    # single pass (S <= 4096): every mode in pass 2
+    "dense_5x4x6_term": lambda: I.random_dense([5, 4, 6], 3, [2, 1, 3], seed=31, gamma=0.9,
+                                               alpha=0.5, n_terminal=2),
+    # two passes with a ragged last column tile
+    "dense_9x8x7x10": lambda: I.random_dense([9, 8, 7, 10], 2, 2, seed=32, gamma=0.95,
+                                             alpha=0.5),
+    # mixed: shifts and dense factors in one term, odd sizes
+    "dense_13x11x3x7": lambda: I.random_dense([13, 11, 3, 7], 4, [1, 3, 2, 1], seed=33,
+                                              gamma=0.9, alpha=2.0, n_terminal=5),
+    # 1-D and sizes up to 32
+    "dense_1d_32": lambda: I.random_dense([32], 3, 2, seed=34, gamma=0.8),
+    "dense_32x17x9": lambda: I.random_dense([32, 17, 9], 2, 3, seed=35, gamma=0.9),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("prec", [0, 1])
+def test_one_backup_matches_oracle(B, name, prec):
+    inst = CASES[name]()
+    log(f"[dense backup] {name} prec={prec}")
+    model = B.Model(inst)
+    assert model.path == B.CPMDP_PATH_DENSE
+    V = I.seeded_values(inst.n_states, 8, scale=2.0)
+    if prec == 1:
+        V = V.astype(np.float32).astype(np.float64)
+    Q = oracle.structured.q_values(inst, V)
+    Vg, pig, r = _backup(B, model, V, prec)
+    tol = 1e-12 * max(1, np.abs(V).max()) if prec == 0 else tol_for(1, Q.max(0))
+    assert_close(Vg, Q.max(0), tol, "V'")
+    compare_policy(pig, Q, tol)
+    model.close()
+
+
+@pytest.mark.parametrize("method", ["vi", "pi"])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_dense_solve_matches_oracle(B, method, prec):
+    inst = I.random_dense([6, 7, 5, 4], 3, 2, seed=36, gamma=0.95, alpha=0.5, n_terminal=3)
+    log(f"[dense solve] 6x7x5x4 {method} prec={prec}")
+    Vs, _, _, _ = oracle.structured.value_iteration(inst)
+    model = B.Model(inst)
+    eps = 0.5 * tol_for(prec, Vs) * (1 - inst.gamma)
+    V, pi, code, sweeps, res = _solve(B, model, method, prec, eps)
+    assert code == B.CPMDP_OK and res <= eps
+    tol = eps / (1 - inst.gamma) + 1e-12
+    assert_close(V, Vs, tol_for(prec, Vs), "V*")
+    compare_policy(pi, oracle.structured.q_values(inst, Vs), tol)
+    model.close()
+
+
+def test_dense12_6_one_backup_full(B):
+    """The 12^6 instance of the 16^6 generator (2,985,984 states, A = 12,
+    R = 8): one FP32 and one FP64 backup against the structured oracle."""
+    inst = I.dense_grid(12, seed=I.SEED_DENSE6_SMALL)
+    log("[dense 12^6] oracle backup")
+    V = I.seeded_values(inst.n_states, 9, scale=3.0).astype(np.float32).astype(np.float64)
+    Q = oracle.structured.q_values(inst, V)
+    model = B.Model(inst)
+    for prec in (1, 0):
+        log(f"[dense 12^6] gpu backup prec={prec}")
+        Vg, pig, r = _backup(B, model, V, prec)
+        tol = 1e-12 * np.abs(V).max() if prec == 0 else tol_for(1, Q.max(0))
+        assert_close(Vg, Q.max(0), tol, f"V' prec={prec}")
+        compare_policy(pig, Q, tol)
+    model.close()
+
+
+def test_dense16_6_sampled_states_and_closed_form(B):
+    """Full 16^6 instance (16,777,216 states): sampled states of one backup
+    against the per-state oracle, and the constant-reward closed form
+    V* = c / (1 - gamma) after a full FP32 solve."""
+    inst = I.dense_grid(16, seed=I.SEED_DENSE6)
+    model = B.Model(inst)
+    V = I.seeded_values(inst.n_states, 10, scale=3.0).astype(np.float32).astype(np.float64)
+    rng = np.random.default_rng(11)
+    states = np.concatenate([[0, inst.n_states - 1], rng.integers(0, inst.n_states, 6)])
+    log("[dense 16^6] per-state oracle")
+    Qs = oracle.structured.q_at_states(inst, V, states)
+    for prec in (1, 0):
+        log(f"[dense 16^6] gpu backup prec={prec}")
+        Vg, pig, _ = _backup(B, model, V, prec)
+        tol = 1e-12 * np.abs(V).max() if prec == 0 else tol_for(1, Qs.max(0))
+        assert_close(Vg[states], Qs.max(0), tol, f"sampled V' prec={prec}")
+        compare_policy(pig[states], Qs, tol)
+    model.close()
+    c = 0.05
+    cinst = I.with_rewards(inst, np.full(inst.n_states, c))
+    cmodel = B.Model(cinst)
+    log("[dense 16^6] constant-reward VI fp32")
+    Vc, _, code, sweeps, res = _solve(B, cmodel, "vi", 1, 1e-6)
+    assert code == B.CPMDP_OK
+    assert_close(Vc, np.full(inst.n_states, c / (1 - inst.gamma)),
+                 1e-6 / (1 - inst.gamma) + 1e-9, "c / (1 - gamma)")
+    cmodel.close()
