@@ -1,0 +1,296 @@
+#!/usr/bin/env python3
+"""Benchmark of the CP-structured Bellman backup on one MI355X.
+
+Default workload: the 4-D GridWorld 32^4 (1,048,576 states, 8 actions, CP rank
+7 per action, rewards N(0, 0.1) plus a +1 terminal goal corner, gamma = 0.99).
+One step = one complete solve from V0 = 0 to a certified FP64 Bellman
+residual <= 1e-6 by the chosen form (FP32 value-iteration sweeps, FP64 tail
+sweeps, FP64 certificate).  The metric is state-action backups per second over
+the timed steps; time-to-eps of the chosen form and of plain FP64 value
+iteration from V0 = 0 on the same instance are reported beside it.
+
+Also printed (one JSON line): the roofline of the dominant kernel (the FP32
+stencil sweep), timed live with HIP events on the library's stream, and the
+FP64 CPU oracle timed on a bounded sample of the same workload.
+
+Other workloads (--workload): grid4d_96 (96^4, HBM-resident) and dense6_16
+(16^6, dense 16x16 factors, 12 actions of rank 8).
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("state-action Bellman backups/s; time to ε=1e-6 residual, chosen vs "
+          "plain GPU VI")
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _sha(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+STENCIL_SRC = ["paper_2103_00331_amd/csrc/stencil.hip", "paper_2103_00331_amd/csrc/common.cuh"]
+CHAIN_SRC = ["paper_2103_00331_amd/csrc/chain.hip", "paper_2103_00331_amd/csrc/common.cuh"]
+
+
+def _traffic(profile_md, src):
+    """HBM bytes per launch measured by rocprofv3 counters, if the kernel
+    sources still hash to what was profiled; else None."""
+    path = os.path.join(ROOT, "profiles", profile_md)
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m_sha = re.search(r"kernel_source_sha256:\s*([0-9a-f]+)", txt)
+    m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m_sha or not m_b or m_sha.group(1) != _sha(src):
+        return None
+    return float(m_b.group(1))
+
+
+def _cpu_baseline_grid(inst, budget_s=15.0):
+    """FP64 value-iteration sweeps of the Def. 3 successor-list oracle."""
+    import numpy as np
+
+    import oracle
+    _log("cpu baseline: building the oracle's successor lists")
+    mats = oracle.sparse.transition_csr(inst)
+    V = np.zeros(inst.n_states)
+    t0 = time.perf_counter()
+    V = oracle.sparse.q_values(inst, mats, V).max(axis=0)
+    t1 = time.perf_counter() - t0
+    n = int(max(1, min(200, budget_s / max(t1, 1e-6)))) - 1
+    t0 = time.perf_counter()
+    for _ in range(n):
+        V = oracle.sparse.q_values(inst, mats, V).max(axis=0)
+    tn = time.perf_counter() - t0
+    sweeps, secs = n + 1, tn + t1
+    rate = sweeps * inst.n_states * inst.n_actions / secs
+    return {"value": rate, "unit": "state-action backups/s", "cores": 1, "kind": "oracle",
+            "sample": f"{sweeps} FP64 value-iteration sweeps of the successor-list (Def. 3) "
+                      f"oracle on the same {inst.name} instance from V0 = 0, {secs:.1f} s; "
+                      "successor-list construction excluded; scipy CSR matvec, one thread"}
+
+
+def bench_grid(args, m):
+    import numpy as np
+    import torch
+
+    from paper_2103_00331_amd import binding as B
+    from paper_2103_00331_amd import instances as I
+
+    seed = I.SEED_GRID4 if m == 32 else I.SEED_GRID4_LARGE
+    _log(f"building {m}^4 instance")
+    inst = I.grid4d(m, seed)
+    S, A = inst.n_states, inst.n_actions
+    model = B.Model(inst)
+    eps = 1e-6
+    V = torch.zeros(S, dtype=torch.float64, device="cuda")
+    pi = torch.zeros(S, dtype=torch.int32, device="cuda")
+    prec = {"fp32": B.CPMDP_FP32, "fp64": B.CPMDP_FP64}[args.precision]
+
+    def solve():
+        V.zero_()
+        pi.zero_()
+        if args.method == "vi":
+            code, sweeps, res = B.cpmdp_value_iteration(model.h, V, pi, eps, 100000, prec)
+            backups = sweeps * S * A
+        else:
+            code, outer, sweeps, res = B.cpmdp_policy_iteration(model.h, V, pi, eps, 100000,
+                                                                prec)
+            backups = sweeps * S          # evaluation sweeps dominate; counted as 1 action
+        assert code == B.CPMDP_OK and res <= eps, (code, res)
+        return sweeps, backups, res
+
+    for i in range(args.warmup):
+        solve()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tot_sweeps = tot_backups = 0
+    res = None
+    for i in range(args.steps):
+        sw, bk, res = solve()
+        tot_sweeps += sw
+        tot_backups += bk
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    _log(f"chosen: {ms_per_step:.2f} ms/solve, {tot_sweeps / args.steps:.0f} sweeps, res {res:.2e}")
+
+    # plain GPU VI: FP64 sweeps from V0 = 0 on the same instance
+    V.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    code, plain_sweeps, plain_res = B.cpmdp_value_iteration(model.h, V, pi, eps, 100000,
+                                                            B.CPMDP_FP64)
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t0
+    _log(f"plain FP64 VI: {plain_s * 1e3:.2f} ms, {plain_sweeps} sweeps")
+
+    # dominant kernel: the FP32 stencil max sweep, timed per launch with events
+    Va = torch.zeros(S, dtype=torch.float32, device="cuda")
+    Vb = torch.zeros(S, dtype=torch.float32, device="cuda")
+    ms = B.cpmdp_time_sweeps(model.h, Va, Vb, 400, B.CPMDP_FP32, 0)
+    algo_bytes = S * (4 + 4 + 4) + S / 8.0          # V, R, V' words + terminal bit
+    achieved = algo_bytes / (ms * 1e-3) / 1e9
+    traffic = _traffic(f"stencil_fp32_grid4d_{m}.md", STENCIL_SRC)
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": "stencil_kernel<float, 4, MODE_MAX>",
+            "kernel_ms": ms, "algorithmic_bytes_per_launch": algo_bytes}
+
+    out = {
+        "metric": METRIC,
+        "value": tot_backups / elapsed,
+        "unit": "state-action backups/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == B.CPMDP_FP32 else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"gridworld_{m}^4: {S} states, {A} actions, CP rank 7, "
+                               "slip 0.1, rewards N(0,0.1) + terminal goal corner, gamma 0.99",
+                   "method": f"{args.method} {args.precision} sweeps + FP64 certificate",
+                   "eps": eps, "sweeps_per_solve": tot_sweeps / args.steps},
+        "time_to_eps_s": ms_per_step / 1e3,
+        "plain_vi_time_to_eps_s": plain_s,
+        "plain_vi_sweeps": plain_sweeps,
+        "speedup_vs_plain_vi": plain_s / (ms_per_step / 1e3),
+        "roofline": roof,
+    }
+    model.close()
+    return out, inst
+
+
+def bench_dense(args):
+    import numpy as np
+    import torch
+
+    from paper_2103_00331_amd import binding as B
+    from paper_2103_00331_amd import instances as I
+
+    _log("building 16^6 dense instance")
+    inst = I.dense_grid(16, seed=I.SEED_DENSE6)
+    S, A = inst.n_states, inst.n_actions
+    model = B.Model(inst)
+    prec = {"fp32": B.CPMDP_FP32, "fp64": B.CPMDP_FP64, "bf16": B.CPMDP_BF16}[args.precision]
+    Va = torch.zeros(S, dtype=torch.float32 if prec else torch.float64, device="cuda")
+    Vb = torch.zeros_like(Va)
+    ms = B.cpmdp_time_sweeps(model.h, Va, Vb, 10, prec, 0)
+    flops = 2.0 * inst.n_terms * sum(int(m) for m in inst.sizes) * S
+    eps = 1e-6
+    V = torch.zeros(S, dtype=torch.float64, device="cuda")
+    pi = torch.zeros(S, dtype=torch.int32, device="cuda")
+    for _ in range(args.warmup):
+        V.zero_()
+        B.cpmdp_value_iteration(model.h, V, pi, eps, 100000, prec)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tot = 0
+    for _ in range(args.steps):
+        V.zero_()
+        code, sweeps, res = B.cpmdp_value_iteration(model.h, V, pi, eps, 100000, prec)
+        tot += sweeps
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    out = {"metric": METRIC, "value": tot * S * A / el, "unit": "state-action backups/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": 1e3 * el / args.steps, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": args.precision, "data": "synthetic",
+           "config": {"workload": f"dense_16^6: {S} states, {A} actions, CP rank 8, dense "
+                                  "16x16 Dirichlet(0.5) factors, gamma 0.95",
+                      "eps": eps, "sweeps_per_solve": tot / args.steps},
+           "roofline": {"bound": "valu", "achieved": flops / (ms * 1e-3) / 1e12,
+                        "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": flops / (ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS,
+                        "traffic": None, "kernel": "chain_pass1 + chain_pass2 (one sweep)",
+                        "kernel_ms": ms}}
+    model.close()
+    return out
+
+
+def kernel_only(args):
+    """Short run for hardware-counter passes: n sweeps of the dominant kernel
+    on the workload, then one plain device copy of a known size (1 GiB) whose
+    counter readings calibrate the byte counters."""
+    import torch
+
+    from paper_2103_00331_amd import binding as B
+    from paper_2103_00331_amd import instances as I
+
+    if args.workload == "dense6_16":
+        inst = I.dense_grid(16, seed=I.SEED_DENSE6)
+    else:
+        m = 32 if args.workload == "grid4d_32" else 96
+        inst = I.grid4d(m, I.SEED_GRID4 if m == 32 else I.SEED_GRID4_LARGE)
+    model = B.Model(inst)
+    prec = {"fp32": B.CPMDP_FP32, "fp64": B.CPMDP_FP64, "bf16": B.CPMDP_BF16}[args.precision]
+    dt = torch.float64 if prec == B.CPMDP_FP64 else torch.float32
+    Va = torch.zeros(inst.n_states, dtype=dt, device="cuda")
+    Vb = torch.zeros_like(Va)
+    ms = B.cpmdp_time_sweeps(model.h, Va, Vb, args.sweeps, prec, 0)
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
+    dst = torch.empty_like(src)
+    torch.mul(src, 2.0, out=dst)       # plain elementwise copy: reads 1 GiB, writes 1 GiB
+    torch.cuda.synchronize()
+    print(json.dumps({"kernel_only": args.workload, "sweeps": args.sweeps, "kernel_ms": ms,
+                      "copy_bytes": src.numel() * 4}), flush=True)
+    model.close()
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="grid4d_32",
+                    choices=["grid4d_32", "grid4d_96", "dense6_16"])
+    ap.add_argument("--method", default="vi", choices=["vi", "pi"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="only the dominant kernel and a 1 GiB copy (counter passes)")
+    ap.add_argument("--sweeps", type=int, default=20)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE "
+              f"{world}); this build has no multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    if args.kernel_only:
+        kernel_only(args)
+        return
+    if args.workload == "dense6_16":
+        out = bench_dense(args)
+    else:
+        out, inst = bench_grid(args, 32 if args.workload == "grid4d_32" else 96)
+        if args.workload == "grid4d_32" and not args.no_cpu_baseline:
+            out["cpu_baseline"] = _cpu_baseline_grid(inst)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

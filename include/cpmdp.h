@@ -186,6 +186,16 @@ int cpmdp_policy_iteration(cpmdp_t* h, double* V_dev, int32_t* pi_dev,
                            int64_t* outer_iters_out, int64_t* sweeps_out,
                            double* residual_out);
 
+/*
+ * cpmdp_time_sweeps -- measurement helper: run n backup sweeps ping-ponging
+ * between the device buffers V_a and V_b (dtype of the precision, starting
+ * from V_a), each bracketed by a HIP event pair on the bound stream, and
+ * return the mean time of one sweep's kernels in milliseconds.
+ *   mode: 0 = Bellman max sweep (Eq. 1), 1 = fixed-policy sweep with pi.
+ */
+int cpmdp_time_sweeps(cpmdp_t* h, void* V_a, void* V_b, int32_t n, int precision, int mode,
+                      const int32_t* pi, double* mean_ms);
+
 /* Release the handle (host memory only; device buffers stay the caller's). */
 void cpmdp_destroy(cpmdp_t* h);
 

@@ -57,6 +57,7 @@ _SIGS = {
                                         _dp]),
     "cpmdp_policy_iteration": (C.c_int, [_p, _p, _p, C.c_double, C.c_int64, C.c_int, _i64p,
                                          _i64p, _dp]),
+    "cpmdp_time_sweeps": (C.c_int, [_p, _p, _p, C.c_int32, C.c_int, C.c_int, _p, _dp]),
     "cpmdp_destroy": (None, [_p]),
     "cpmdp_last_error": (C.c_char_p, [_p]),
     "cpmdp_batch_create": (C.c_int, [C.POINTER(_p), C.POINTER(_p), C.c_int32]),
@@ -179,6 +180,13 @@ def cpmdp_policy_iteration(h, V, pi, eps=1e-6, max_iter=100000, precision=CPMDP_
                                              int(precision), C.byref(outer), C.byref(sw),
                                              C.byref(res)), h)
     return code, outer.value, sw.value, res.value
+
+
+def cpmdp_time_sweeps(h, V_a, V_b, n, precision=CPMDP_FP32, mode=0, pi=None) -> float:
+    ms = C.c_double(0.0)
+    _check(lib.cpmdp_time_sweeps(h, _ptr(V_a), _ptr(V_b), int(n), int(precision), int(mode),
+                                 _ptr(pi), C.byref(ms)), h)
+    return ms.value
 
 
 def cpmdp_destroy(h):

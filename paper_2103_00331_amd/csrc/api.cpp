@@ -165,7 +165,7 @@ void layout(const cpmdp_t* h, DevPtrs* dp, char* base, size_t* total) {
   d.R64 = cv.take<double>(S);
   d.R32 = cv.take<float>(S);
   d.tbits = cv.take<uint32_t>((S + 31) / 32 + 1);
-  d.slots = cv.take<unsigned long long>(kSlots);
+  d.slots = cv.take<unsigned long long>(static_cast<size_t>(kSlots) * kSpread);
   d.vmax = cv.take<unsigned long long>(4);
   d.counters = cv.take<unsigned int>(8);
   d.Va64 = cv.take<double>(S);
@@ -177,8 +177,8 @@ void layout(const cpmdp_t* h, DevPtrs* dp, char* base, size_t* total) {
   d.piA = cv.take<int32_t>(S);
   if (h->path == CPMDP_PATH_STENCIL) {
     const size_t P = 2 * static_cast<size_t>(h->n) + 1;
-    d.w64 = cv.take<double>(A * P);
-    d.w32 = cv.take<float>(A * P);
+    d.w64 = cv.take<double>(3 * A * P);   // w, wdiff [A][P], then wbase [P]
+    d.w32 = cv.take<float>(3 * A * P);
     d.fac64 = nullptr;
     d.fac32 = nullptr;
     d.facbf = nullptr;
@@ -222,13 +222,23 @@ void sweep(cpmdp_t* h, bool prec64, int mode, const void* V, void* Vout, const v
            unsigned long long* slot, unsigned int* ctr, bool bf16) {
   const hipStream_t st = h->stream;
   if (h->path == CPMDP_PATH_STENCIL) {
-    const int nblocks = static_cast<int>((h->S + kBlock - 1) / kBlock);
+    const int nblocks = h->st_blocks;
+    const size_t AP = static_cast<size_t>(h->A) * (2 * h->n + 1);
     if (prec64) {
       StencilArgs<double> a{};
       a.g = h->geom;
       a.A = h->A;
       a.npts = 2 * h->n + 1;
       a.w = h->d.w64;
+      a.wdiff = h->d.w64 + AP;
+      a.wbase = h->d.w64 + 2 * AP;
+      a.states_per_block = h->st_states_per_block;
+      a.vec = h->st_vec;
+      a.axis = h->st_axis;
+      if (a.axis) {
+        std::copy(h->kw64.begin(), h->kw64.begin() + 2 * h->n + 1, a.kw_base);
+        std::copy(h->kw64.begin() + 2 * h->n + 1, h->kw64.end(), a.kw_axis);
+      }
       a.V = static_cast<const double*>(V);
       a.Vout = static_cast<double*>(Vout);
       a.R = static_cast<const double*>(R);
@@ -248,6 +258,15 @@ void sweep(cpmdp_t* h, bool prec64, int mode, const void* V, void* Vout, const v
       a.A = h->A;
       a.npts = 2 * h->n + 1;
       a.w = h->d.w32;
+      a.wdiff = h->d.w32 + AP;
+      a.wbase = h->d.w32 + 2 * AP;
+      a.states_per_block = h->st_states_per_block;
+      a.vec = h->st_vec;
+      a.axis = h->st_axis;
+      if (a.axis) {
+        std::copy(h->kw32.begin(), h->kw32.begin() + 2 * h->n + 1, a.kw_base);
+        std::copy(h->kw32.begin() + 2 * h->n + 1, h->kw32.end(), a.kw_axis);
+      }
       a.V = static_cast<const float*>(V);
       a.Vout = static_cast<float*>(Vout);
       a.R = static_cast<const float*>(R);
@@ -320,16 +339,29 @@ static double bits_to_double(unsigned long long b) {
   return v;
 }
 
-// Read n slots (and optionally the counters) back to the host.
+// Residual slot j of a chunk = kSpread words starting at slots + j * kSpread.
+static unsigned long long* slot_of(cpmdp_t* h, int j) { return h->d.slots + static_cast<size_t>(j) * kSpread; }
+
+static void zero_slots(cpmdp_t* h, int n) {
+  launch_fill_u64(h->d.slots, n * kSpread, 0ull, h->stream);
+}
+
+// Read n residual slots (max over each slot's words) and optionally the
+// counters back to the host.
 static int read_slots(cpmdp_t* h, int n, std::vector<double>& out, unsigned* ctr0) {
-  HIP_TRY(h, hipMemcpyAsync(h->host_slots, h->d.slots, sizeof(unsigned long long) * n,
+  HIP_TRY(h, hipMemcpyAsync(h->host_slots, h->d.slots,
+                            sizeof(unsigned long long) * static_cast<size_t>(n) * kSpread,
                             hipMemcpyDeviceToHost, h->stream));
   if (ctr0)
     HIP_TRY(h, hipMemcpyAsync(h->host_ctr, h->d.counters, sizeof(unsigned) * 2,
                               hipMemcpyDeviceToHost, h->stream));
   HIP_TRY(h, hipStreamSynchronize(h->stream));
   out.resize(n);
-  for (int i = 0; i < n; ++i) out[i] = bits_to_double(h->host_slots[i]);
+  for (int i = 0; i < n; ++i) {
+    unsigned long long m = 0;
+    for (int j = 0; j < kSpread; ++j) m = std::max(m, h->host_slots[static_cast<size_t>(i) * kSpread + j]);
+    out[i] = bits_to_double(m);
+  }
   if (ctr0) *ctr0 = h->host_ctr[0];
   return CPMDP_OK;
 }
@@ -372,9 +404,9 @@ static int run_sweeps(cpmdp_t* h, bool prec64, int mode, P*& cur, P*& alt, const
   std::vector<double> res;
   while (*sweeps < budget) {
     const int k = kprev == 0 ? 4 : next_chunk(rf, rl, kprev, h->gamma, tol, budget - *sweeps);
-    launch_fill_u64(h->d.slots, k, 0ull, h->stream);
+    zero_slots(h, k);
     for (int j = 0; j < k; ++j) {
-      sweep(h, prec64, mode, cur, alt, R, pi, nullptr, nullptr, h->d.slots + j, nullptr, bf16);
+      sweep(h, prec64, mode, cur, alt, R, pi, nullptr, nullptr, slot_of(h, j), nullptr, bf16);
       std::swap(cur, alt);
     }
     int rc = check_device(h);
@@ -401,7 +433,7 @@ static int run_sweeps(cpmdp_t* h, bool prec64, int mode, P*& cur, P*& alt, const
 // Greedy / certificate pass in FP64 over V: residual ||BV - V|| and policy.
 static int certify(cpmdp_t* h, const double* V, int32_t* pi_out, const int32_t* pi_in,
                    double* res, unsigned* changes) {
-  launch_fill_u64(h->d.slots, 1, 0ull, h->stream);
+  zero_slots(h, 1);
   launch_fill_u64(h->d.vmax, 1, 0ull, h->stream);
   launch_fill_u32(h->d.counters, 2, 0u, h->stream);
   launch_maxabs_f64(V, h->S, h->d.vmax, h->stream);
@@ -535,6 +567,16 @@ int cpmdp_create(cpmdp_t** out, int32_t n_dims, const int64_t* sizes, int32_t n_
   }
   h->path = stencil ? CPMDP_PATH_STENCIL : CPMDP_PATH_DENSE;
   h->geom = make_geom(h);
+  {
+    // persistent stencil grid: contiguous ranges of whole 256 x vec chunks
+    h->st_vec = (sizes[n_dims - 1] % 4 == 0) ? 4 : 1;
+    const int64_t chunk = static_cast<int64_t>(kBlock) * h->st_vec;
+    const int64_t units = (S + chunk - 1) / chunk;
+    int64_t nb = std::min<int64_t>(units, kMaxBlocks);
+    const int64_t per = (units + nb - 1) / nb;
+    h->st_states_per_block = static_cast<int32_t>(per * chunk);
+    h->st_blocks = static_cast<int32_t>((units + per - 1) / per);
+  }
   if (stencil) {
     const int P = 2 * n_dims + 1;
     h->w.assign(static_cast<size_t>(n_actions) * P, 0.0);
@@ -623,7 +665,8 @@ int cpmdp_bind(cpmdp_t* h, void* ws, size_t bytes, void* stream) {
   h->ws_bytes = bytes;
   if (!h->host_slots) {
     HIP_TRY(h, hipHostMalloc(reinterpret_cast<void**>(&h->host_slots),
-                             sizeof(unsigned long long) * kSlots, hipHostMallocDefault));
+                             sizeof(unsigned long long) * kSlots * kSpread,
+                             hipHostMallocDefault));
     HIP_TRY(h, hipHostMalloc(reinterpret_cast<void**>(&h->host_ctr), sizeof(unsigned) * 8,
                              hipHostMallocDefault));
   }
@@ -642,9 +685,48 @@ int cpmdp_bind(cpmdp_t* h, void* ws, size_t bytes, void* stream) {
   std::vector<uint16_t> facbf;
   std::vector<int32_t> ts;
   if (h->path == CPMDP_PATH_STENCIL) {
-    w32.resize(h->w.size());
-    for (size_t i = 0; i < h->w.size(); ++i) w32[i] = static_cast<float>(h->w[i]);
-    HIP_TRY(h, hipMemcpyAsync(h->d.w64, h->w.data(), h->w.size() * 8, hipMemcpyHostToDevice, st));
+    // [w | wdiff | wbase]: wbase[p] = the value most actions share at point p
+    const int P = 2 * h->n + 1, A = h->A;
+    std::vector<double> w64(3 * static_cast<size_t>(A) * P, 0.0);
+    std::copy(h->w.begin(), h->w.end(), w64.begin());
+    double* wdiff = w64.data() + static_cast<size_t>(A) * P;
+    double* wbase = w64.data() + 2 * static_cast<size_t>(A) * P;
+    for (int p = 0; p < P; ++p) {
+      int best_count = 0;
+      for (int a = 0; a < A; ++a) {
+        int cnt = 0;
+        for (int b = 0; b < A; ++b) cnt += h->w[b * P + p] == h->w[a * P + p];
+        if (cnt > best_count) {
+          best_count = cnt;
+          wbase[p] = h->w[a * P + p];
+        }
+      }
+      for (int a = 0; a < A; ++a) wdiff[a * P + p] = h->w[a * P + p] - wbase[p];
+    }
+    w32.resize(w64.size());
+    for (size_t i = 0; i < w64.size(); ++i) w32[i] = static_cast<float>(w64[i]);
+    // Axis structure: A == 2n and action a = 2k + d differs from wbase only
+    // at the centre and the two axis-k points.  Kernel-argument copy:
+    // [wbase (P) | per action (diff centre, diff +e_k, diff -e_k)].
+    bool axis = (A == 2 * h->n);
+    for (int a = 0; a < A && axis; ++a)
+      for (int p = 0; p < P; ++p) {
+        const int k = a / 2;
+        if (p != 0 && p != 1 + 2 * k && p != 2 + 2 * k && wdiff[a * P + p] != 0.0) axis = false;
+      }
+    h->st_axis = axis ? 1 : 0;
+    h->kw64.clear();
+    if (axis) {
+      for (int p = 0; p < P; ++p) h->kw64.push_back(wbase[p]);
+      for (int a = 0; a < A; ++a) {
+        const int k = a / 2;
+        h->kw64.push_back(wdiff[a * P]);
+        h->kw64.push_back(wdiff[a * P + 1 + 2 * k]);
+        h->kw64.push_back(wdiff[a * P + 2 + 2 * k]);
+      }
+    }
+    h->kw32.assign(h->kw64.begin(), h->kw64.end());
+    HIP_TRY(h, hipMemcpyAsync(h->d.w64, w64.data(), w64.size() * 8, hipMemcpyHostToDevice, st));
     HIP_TRY(h, hipMemcpyAsync(h->d.w32, w32.data(), w32.size() * 4, hipMemcpyHostToDevice, st));
   } else {
     const size_t F = h->factors.size();
@@ -705,7 +787,7 @@ int cpmdp_backup(cpmdp_t* h, const void* V_in, void* V_out, int32_t* pi_out,
   if (!V_in || !V_out) return fail(h, CPMDP_E_ARG, "NULL value buffer");
   if (V_in == V_out) return fail(h, CPMDP_E_ARG, "V_in and V_out must not alias");
   const bool p64 = precision == CPMDP_FP64;
-  launch_fill_u64(h->d.slots, 1, 0ull, h->stream);
+  zero_slots(h, 1);
   if (pi_out) {
     launch_fill_u64(h->d.vmax, 1, 0ull, h->stream);
     if (p64) {
@@ -739,7 +821,7 @@ int cpmdp_policy_backup(cpmdp_t* h, const void* V_in, void* V_out, const int32_t
   rc = check_policy(h, pi);
   if (rc) return rc;
   const bool p64 = precision == CPMDP_FP64;
-  launch_fill_u64(h->d.slots, 1, 0ull, h->stream);
+  zero_slots(h, 1);
   sweep(h, p64, MODE_EVAL, V_in, V_out, p64 ? static_cast<const void*>(h->d.R64) : h->d.R32, pi,
         nullptr, nullptr, h->d.slots, nullptr, precision == CPMDP_BF16);
   rc = check_device(h);
@@ -834,7 +916,7 @@ int cpmdp_policy_iteration(cpmdp_t* h, double* V, int32_t* pi, double eps, int64
       for (;;) {
         if (sweeps >= max_iter - 1) break;
         // FP64 residual of the evaluation equation: r = R + g P_pi V - V
-        launch_fill_u64(h->d.slots, 1, 0ull, st);
+        zero_slots(h, 1);
         sweep(h, true, MODE_RESID, V, nullptr, h->d.R64, pi, nullptr, h->d.r32, h->d.slots,
               nullptr, false);
         rc = check_device(h);
@@ -874,6 +956,47 @@ int cpmdp_policy_iteration(cpmdp_t* h, double* V, int32_t* pi, double eps, int64
   if (sweeps_out) *sweeps_out = sweeps;
   if (residual_out) *residual_out = cert;
   return converged ? CPMDP_OK : CPMDP_NOT_CONVERGED;
+}
+
+int cpmdp_time_sweeps(cpmdp_t* h, void* V_a, void* V_b, int32_t n, int precision, int mode,
+                      const int32_t* pi, double* mean_ms) {
+  int rc = check_common(h, precision);
+  if (rc) return rc;
+  if (!V_a || !V_b || V_a == V_b || n < 1 || !mean_ms)
+    return fail(h, CPMDP_E_ARG, "bad time_sweeps arguments");
+  if (mode != 0 && mode != 1) return fail(h, CPMDP_E_ARG, "mode must be 0 (max) or 1 (policy)");
+  if (mode == 1) {
+    if (!pi) return fail(h, CPMDP_E_ARG, "policy sweeps need pi");
+    rc = check_policy(h, pi);
+    if (rc) return rc;
+  }
+  const bool p64 = precision == CPMDP_FP64;
+  const hipStream_t st = h->stream;
+  std::vector<hipEvent_t> ev(2 * static_cast<size_t>(n));
+  for (auto& e : ev) HIP_TRY(h, hipEventCreate(&e));
+  zero_slots(h, 1);
+  void* cur = V_a;
+  void* alt = V_b;
+  for (int i = 0; i < n; ++i) {
+    HIP_TRY(h, hipEventRecord(ev[2 * i], st));
+    sweep(h, p64, mode == 0 ? MODE_MAX : MODE_EVAL, cur, alt,
+          p64 ? static_cast<const void*>(h->d.R64) : h->d.R32, pi, nullptr, nullptr, h->d.slots,
+          nullptr, precision == CPMDP_BF16);
+    HIP_TRY(h, hipEventRecord(ev[2 * i + 1], st));
+    std::swap(cur, alt);
+  }
+  rc = check_device(h);
+  HIP_TRY(h, hipStreamSynchronize(st));
+  double tot = 0.0;
+  for (int i = 0; i < n && rc == 0; ++i) {
+    float ms = 0.f;
+    HIP_TRY(h, hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]));
+    tot += ms;
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  if (rc) return rc;
+  *mean_ms = tot / n;
+  return CPMDP_OK;
 }
 
 void cpmdp_destroy(cpmdp_t* h) {

@@ -23,9 +23,12 @@ __device__ __forceinline__ double nanmax(double a, double b) {
   return (a != a || a > b) ? a : b;
 }
 
-// Block-wide max of v, folded into *slot (FP64 bit pattern; non-negative
-// doubles order like their bits, NaN sorts above +inf).
-__device__ __forceinline__ void block_max_to_slot(double v, unsigned long long* slot) {
+// Block-wide max of v, folded into slot[blockIdx.x & spread_mask] (FP64 bit
+// pattern; non-negative doubles order like their bits, NaN sorts above +inf).
+// Spreading the atomics of a sweep over kSpread words keeps thousands of
+// blocks from serialising on one address; the reader takes the max.
+__device__ __forceinline__ void block_max_to_slot(double v, unsigned long long* slot,
+                                                  unsigned spread_mask = kSpread - 1) {
   __shared__ double part[16];
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v = nanmax(v, __shfl_xor(v, off));
@@ -36,7 +39,8 @@ __device__ __forceinline__ void block_max_to_slot(double v, unsigned long long* 
     double m = part[0];
     const int nw = (blockDim.x + 63) >> 6;
     for (int i = 1; i < nw; ++i) m = nanmax(m, part[i]);
-    atomicMax(slot, static_cast<unsigned long long>(__double_as_longlong(m)));
+    atomicMax(slot + (blockIdx.x & spread_mask),
+              static_cast<unsigned long long>(__double_as_longlong(m)));
   }
 }
 

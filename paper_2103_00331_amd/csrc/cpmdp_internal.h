@@ -15,6 +15,8 @@ namespace cpm {
 constexpr int kMaxDims = 8;
 constexpr int kMaxActions = 255;
 constexpr int kSlots = 256;        // residual slots (one per sweep of a chunk)
+constexpr int kSpread = 64;        // words per residual slot (atomics spread)
+constexpr int kMaxBlocks = 2048;   // persistent grid: 256 CUs x 8 blocks
 constexpr int kBlock = 256;        // threads per block of the streaming kernels
 constexpr int kXcds = 8;           // MI355X: 8 XCDs, 32 CUs each
 constexpr double kTieRel = 1e-12;  // tie tolerance relative to max(1,||V||)
@@ -56,6 +58,9 @@ struct StencilArgs {
   int32_t A;
   int32_t npts;                 // 2n + 1: centre, then (+e_k, -e_k) per dim
   const T* w;                   // [A][npts] summed rank weights
+  const T* wbase;               // [npts] weight shared by most actions per point
+  const T* wdiff;               // [A][npts] w - wbase (mostly zero)
+  int32_t states_per_block;     // contiguous states per block (multiple of 256*VEC)
   const T* V;                   // input values
   T* Vout;                      // MAX / GREEDY / EVAL output (nullable for GREEDY)
   const T* R;                   // rewards, or the right-hand side of a correction sweep
@@ -69,6 +74,12 @@ struct StencilArgs {
   unsigned long long* res_slot; // max |out - V| as FP64 bits (atomic max)
   unsigned int* change_count;   // GREEDY with incumbent
   int32_t nblocks;
+  int32_t vec;                  // states per thread along the last dim (1 or 4)
+  int32_t axis;                 // 1: axis-structured weights (see stencil.hip)
+  // Weights by value: kernel arguments are scalar-loaded, so the
+  // wave-uniform weights sit in SGPRs.
+  T kw_base[2 * kMaxDims + 1];
+  T kw_axis[2 * kMaxDims * 3];  // per action: diff at centre, +axis, -axis
 };
 
 template <typename T>

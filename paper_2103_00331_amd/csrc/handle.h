@@ -50,6 +50,12 @@ struct cpmdp {
   std::vector<uint8_t> kinds;
   int path = 0;
   std::vector<double> w;                 // stencil weights [A][2n+1]
+  std::vector<double> kw64;              // stencil [wdiff | wbase] for kernel args
+  std::vector<float> kw32;
+  int32_t st_vec = 1;                    // stencil: states per thread (1 or 4)
+  int32_t st_axis = 0;                   // stencil: axis-structured weights
+  int32_t st_blocks = 1;                 // stencil: persistent grid size
+  int32_t st_states_per_block = 256;
   cpm::GridGeom geom{};
   cpm::ChainGeom cg64{}, cg32{};
   bool bound = false;

@@ -11,7 +11,7 @@ constexpr int kUtilBlock = 256;
 
 int util_grid(int64_t n) {
   int64_t b = (n + kUtilBlock - 1) / kUtilBlock;
-  if (b > 65536) b = 65536;
+  if (b > kMaxBlocks) b = kMaxBlocks;
   return static_cast<int>(b < 1 ? 1 : b);
 }
 
@@ -44,7 +44,7 @@ __global__ void maxabs_f64_kernel(const double* v, int64_t n, unsigned long long
   double m = 0.0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     m = nanmax(m, fabs(v[i]));
-  block_max_to_slot(m, slot);
+  block_max_to_slot(m, slot, 0u);
 }
 __global__ void check_policy_kernel(const int32_t* pi, int64_t n, int32_t A, unsigned int* bad) {
   unsigned c = 0;
