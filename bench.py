@@ -229,6 +229,74 @@ def bench_dense(args):
     return out
 
 
+def bench_batch(args):
+    """512 mixed GridWorlds solved together (FP32 sweeps, FP64 tail and
+    certificate per instance, autotuned tiles / sweeps per graph) vs plain
+    FP64 value iteration of each instance on its own."""
+    import numpy as np
+    import torch
+
+    from paper_2103_00331_amd import binding as B
+    from paper_2103_00331_amd import instances as I
+
+    _log("building the 512-instance batch")
+    insts = [I.batch_instance(i) for i in range(512)]
+    tot_states = sum(x.n_states for x in insts)
+    eps = 1e-6
+    bm = B.BatchModel(insts)
+    t0 = time.perf_counter()
+    B.cpmdp_batch_autotune(bm.b, True, None)
+    tune_s = time.perf_counter() - t0
+    ts, k = B.cpmdp_batch_config(bm.b)
+    Vs = [torch.zeros(x.n_states, dtype=torch.float64, device="cuda") for x in insts]
+    pis = [torch.zeros(x.n_states, dtype=torch.int32, device="cuda") for x in insts]
+
+    def solve():
+        for V in Vs:
+            V.zero_()
+        code, sweeps, res = B.cpmdp_batch_solve(bm.b, Vs, pis, eps, 100000, B.CPMDP_FP32, 0)
+        assert code == B.CPMDP_OK and np.all(res <= eps)
+        return sweeps
+
+    for _ in range(args.warmup):
+        solve()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    backups = 0
+    for _ in range(args.steps):
+        sw = solve()
+        backups += sum(int(s) * x.n_states * x.n_actions for s, x in zip(sw, insts))
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    bm.close()
+    _log(f"batched: {1e3 * el / args.steps:.1f} ms per batch solve (tile {ts}, k {k})")
+    # plain GPU VI: each instance alone, FP64 sweeps from V0 = 0
+    plain = 0.0
+    plain_sweeps = 0
+    for x in insts:
+        m = B.Model(x)
+        V = torch.zeros(x.n_states, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        code, sw, res = B.cpmdp_value_iteration(m.h, V, None, eps, 100000, B.CPMDP_FP64)
+        torch.cuda.synchronize()
+        plain += time.perf_counter() - t1
+        plain_sweeps += sw
+        m.close()
+    _log(f"plain per-instance FP64 VI: {plain * 1e3:.1f} ms total")
+    return {"metric": METRIC, "value": backups / el, "unit": "state-action backups/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": 1e3 * el / args.steps, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"batch of 512 GridWorlds, n in {{2,3,4}}, m in [8,48], "
+                                   f"{tot_states} states in total, slip U[0.05,0.3], "
+                                   "gamma U[0.9,0.99]", "eps": eps,
+                       "tile_states": ts, "sweeps_per_graph": k, "autotune_s": tune_s},
+            "time_to_eps_s": el / args.steps, "plain_vi_time_to_eps_s": plain,
+            "plain_vi_sweeps": plain_sweeps,
+            "speedup_vs_plain_vi": plain / (el / args.steps)}
+
+
 def kernel_only(args):
     """Short run for hardware-counter passes: n sweeps of the dominant kernel
     on the workload, then one plain device copy of a known size (1 GiB) whose
@@ -264,7 +332,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="grid4d_32",
-                    choices=["grid4d_32", "grid4d_96", "dense6_16"])
+                    choices=["grid4d_32", "grid4d_96", "dense6_16", "batch512"])
     ap.add_argument("--method", default="vi", choices=["vi", "pi"])
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -285,6 +353,8 @@ def main():
         return
     if args.workload == "dense6_16":
         out = bench_dense(args)
+    elif args.workload == "batch512":
+        out = bench_batch(args)
     else:
         out, inst = bench_grid(args, 32 if args.workload == "grid4d_32" else 96)
         if args.workload == "grid4d_32" and not args.no_cpu_baseline:

@@ -278,3 +278,40 @@ class Model:
             self.close()
         except Exception:
             pass
+
+
+class BatchModel:
+    """Many instances solved together: creates one handle per instance (host
+    data only), the batch, and its workspace (torch uint8 tensor)."""
+
+    def __init__(self, insts, device="cuda", stream=None):
+        import torch
+        self.insts = list(insts)
+        self.handles = []
+        for inst in self.insts:
+            h = cpmdp_create(inst.sizes, inst.ranks, inst.factors, inst.lambdas,
+                             inst.rewards, inst.gamma)
+            if np.any(inst.terminal):
+                cpmdp_set_terminal(h, inst.terminal)
+            self.handles.append(h)
+        self.b = cpmdp_batch_create(self.handles)
+        nbytes = cpmdp_batch_workspace_bytes(self.b)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        off = (-self.workspace.data_ptr()) % 256
+        self.ws_view = self.workspace[off:off + nbytes]
+        cpmdp_batch_bind(self.b, self.ws_view, stream)
+        self.device = device
+
+    def close(self):
+        if self.b is not None:
+            cpmdp_batch_destroy(self.b)
+            self.b = None
+        for h in self.handles:
+            cpmdp_destroy(h)
+        self.handles = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

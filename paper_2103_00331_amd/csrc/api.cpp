@@ -451,6 +451,45 @@ static int certify(cpmdp_t* h, const double* V, int32_t* pi_out, const int32_t* 
   return CPMDP_OK;
 }
 
+// Axis structure of the stencil weights: A == 2n and action a = 2k + d
+// differs from a shared vector wbase (per point, the value most actions have)
+// only at the centre and its two axis-k points.  Stores the kernel-argument
+// copy [wbase (2n+1) | per action: diff at centre, +e_k, -e_k].
+void split_axis_weights(cpmdp_t* h) {
+  const int P = 2 * h->n + 1, A = h->A;
+  std::vector<double> wbase(P, 0.0), wdiff(static_cast<size_t>(A) * P, 0.0);
+  for (int p = 0; p < P; ++p) {
+    int best_count = 0;
+    for (int a = 0; a < A; ++a) {
+      int cnt = 0;
+      for (int b = 0; b < A; ++b) cnt += h->w[b * P + p] == h->w[a * P + p];
+      if (cnt > best_count) {
+        best_count = cnt;
+        wbase[p] = h->w[a * P + p];
+      }
+    }
+    for (int a = 0; a < A; ++a) wdiff[a * P + p] = h->w[a * P + p] - wbase[p];
+  }
+  bool axis = (A == 2 * h->n);
+  for (int a = 0; a < A && axis; ++a)
+    for (int p = 0; p < P; ++p) {
+      const int k = a / 2;
+      if (p != 0 && p != 1 + 2 * k && p != 2 + 2 * k && wdiff[a * P + p] != 0.0) axis = false;
+    }
+  h->st_axis = axis ? 1 : 0;
+  h->kw64.clear();
+  if (axis) {
+    for (int p = 0; p < P; ++p) h->kw64.push_back(wbase[p]);
+    for (int a = 0; a < A; ++a) {
+      const int k = a / 2;
+      h->kw64.push_back(wdiff[a * P]);
+      h->kw64.push_back(wdiff[a * P + 1 + 2 * k]);
+      h->kw64.push_back(wdiff[a * P + 2 + 2 * k]);
+    }
+  }
+  h->kw32.assign(h->kw64.begin(), h->kw64.end());
+}
+
 }  // namespace cpm
 
 using namespace cpm;
@@ -590,6 +629,7 @@ int cpmdp_create(cpmdp_t** out, int32_t n_dims, const int64_t* sizes, int32_t n_
         }
         h->w[a * P + p] += lambdas[t];
       }
+    split_axis_weights(h);
   } else {
     if (!choose_split(h->sizes, S, sizeof(double), h->cg64) ||
         !choose_split(h->sizes, S, sizeof(float), h->cg32)) {
@@ -685,47 +725,11 @@ int cpmdp_bind(cpmdp_t* h, void* ws, size_t bytes, void* stream) {
   std::vector<uint16_t> facbf;
   std::vector<int32_t> ts;
   if (h->path == CPMDP_PATH_STENCIL) {
-    // [w | wdiff | wbase]: wbase[p] = the value most actions share at point p
     const int P = 2 * h->n + 1, A = h->A;
     std::vector<double> w64(3 * static_cast<size_t>(A) * P, 0.0);
     std::copy(h->w.begin(), h->w.end(), w64.begin());
-    double* wdiff = w64.data() + static_cast<size_t>(A) * P;
-    double* wbase = w64.data() + 2 * static_cast<size_t>(A) * P;
-    for (int p = 0; p < P; ++p) {
-      int best_count = 0;
-      for (int a = 0; a < A; ++a) {
-        int cnt = 0;
-        for (int b = 0; b < A; ++b) cnt += h->w[b * P + p] == h->w[a * P + p];
-        if (cnt > best_count) {
-          best_count = cnt;
-          wbase[p] = h->w[a * P + p];
-        }
-      }
-      for (int a = 0; a < A; ++a) wdiff[a * P + p] = h->w[a * P + p] - wbase[p];
-    }
     w32.resize(w64.size());
     for (size_t i = 0; i < w64.size(); ++i) w32[i] = static_cast<float>(w64[i]);
-    // Axis structure: A == 2n and action a = 2k + d differs from wbase only
-    // at the centre and the two axis-k points.  Kernel-argument copy:
-    // [wbase (P) | per action (diff centre, diff +e_k, diff -e_k)].
-    bool axis = (A == 2 * h->n);
-    for (int a = 0; a < A && axis; ++a)
-      for (int p = 0; p < P; ++p) {
-        const int k = a / 2;
-        if (p != 0 && p != 1 + 2 * k && p != 2 + 2 * k && wdiff[a * P + p] != 0.0) axis = false;
-      }
-    h->st_axis = axis ? 1 : 0;
-    h->kw64.clear();
-    if (axis) {
-      for (int p = 0; p < P; ++p) h->kw64.push_back(wbase[p]);
-      for (int a = 0; a < A; ++a) {
-        const int k = a / 2;
-        h->kw64.push_back(wdiff[a * P]);
-        h->kw64.push_back(wdiff[a * P + 1 + 2 * k]);
-        h->kw64.push_back(wdiff[a * P + 2 + 2 * k]);
-      }
-    }
-    h->kw32.assign(h->kw64.begin(), h->kw64.end());
     HIP_TRY(h, hipMemcpyAsync(h->d.w64, w64.data(), w64.size() * 8, hipMemcpyHostToDevice, st));
     HIP_TRY(h, hipMemcpyAsync(h->d.w32, w32.data(), w32.size() * 4, hipMemcpyHostToDevice, st));
   } else {

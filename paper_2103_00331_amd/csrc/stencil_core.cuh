@@ -1,0 +1,227 @@
+// Per-state work of the shift/identity (stencil) backup, shared by the
+// single-instance kernel (stencil.hip) and the batched kernel (batch.hip).
+//
+// With every rank term of the form I (x) ... (x) shift (x) ... (x) I, the mode
+// products of V with the factors reduce to reading V at the state itself or
+// at one axis neighbour (clamped at the grid edge: a move off the grid stays
+// put).  Terms of one action that read the same neighbour are summed into one
+// weight, so an action is a (2n+1)-point stencil
+//     (P_a V)(s) = sum_p w[a][p] V(nbr_p(s)),
+// points p: 0 = the state, 1 + 2k = +e_k, 2 + 2k = -e_k.
+#pragma once
+
+#include "common.cuh"
+
+namespace cpm {
+
+template <typename T, int VEC>
+struct VecOf;
+template <>
+struct VecOf<float, 4> { using type = float4; };
+template <>
+struct VecOf<double, 4> { using type = double4; };
+
+template <typename T>
+__device__ __forceinline__ T comp(const typename VecOf<T, 4>::type& v, int q) {
+  return q == 0 ? v.x : (q == 1 ? v.y : (q == 2 ? v.z : v.w));
+}
+
+template <typename T>
+__device__ __forceinline__ T tnanmax(T a, T b) {
+  return (a != a || a > b) ? a : b;
+}
+
+// Weights of one instance.
+//   axis form: action a = 2k + d differs from the shared vector base[] only at
+//     the centre and its own axis-k points (axis[3a..3a+2] = differences at
+//     centre, +e_k, -e_k): P_a V = base . nb + 3 terms.  Holds for any axis
+//     move whose slip does not depend on the action (the slip GridWorld).
+//   full form: full[a * P + p].
+//   eval: full table in LDS for per-state action selection.
+template <typename T>
+struct StencilW {
+  const T* base;
+  const T* axis;
+  const T* full;
+  const T* eval;
+  int A;
+  T gamma;
+};
+
+template <typename T>
+struct StencilIO {
+  const T* V;
+  T* Vout;
+  const T* R;
+  const uint32_t* tbits;
+  const int32_t* pi_in;
+  int32_t* pi_out;
+  float* r_out;
+};
+
+// One state: Q-values of Eq. 1, max / argmax (tie rule) or the fixed-policy
+// value, and the residual term.
+template <typename T, int N, int MODE, bool AXIS>
+__device__ __forceinline__ void stencil_state(const StencilW<T>& W, const T (&nb)[2 * N + 1],
+                                              T rs, bool term, int pold, T tol, T& out,
+                                              int& pnew, T& res, unsigned& changed) {
+  constexpr int P = 2 * N + 1;
+  const T g = term ? T(0) : W.gamma;
+  const T c = nb[0];
+  if (MODE == MODE_MAX || MODE == MODE_GREEDY) {
+    T best = -INFINITY, qold = -INFINITY;
+    int bi = 0;
+    auto visit = [&](int act, T acc) {
+      if (MODE == MODE_MAX) {
+        best = fmax(best, acc);   // a NaN in V still shows in the residual via c
+      } else {
+        const T q = fma(g, acc, rs);
+        tie_update(q, act, tol, best, bi);
+        if (act == pold) qold = q;
+      }
+    };
+    if (AXIS) {
+      T base = T(0);
+#pragma unroll
+      for (int p = 0; p < P; ++p) base = fma(W.base[p], nb[p], base);
+#pragma unroll
+      for (int act = 0; act < 2 * N; ++act) {
+        const int k = act >> 1;
+        const T* w3 = W.axis + 3 * act;
+        T acc = fma(w3[0], nb[0], base);
+        acc = fma(w3[1], nb[1 + 2 * k], acc);
+        acc = fma(w3[2], nb[2 + 2 * k], acc);
+        visit(act, acc);
+      }
+    } else {
+      for (int act = 0; act < W.A; ++act) {
+        const T* wa = W.full + act * P;
+        T acc = T(0);
+#pragma unroll
+        for (int p = 0; p < P; ++p) acc = fma(wa[p], nb[p], acc);
+        visit(act, acc);
+      }
+    }
+    if (MODE == MODE_MAX) {
+      out = fma(g, best, rs);
+    } else {
+      pnew = bi;
+      if (pold >= 0 && qold >= best - tol) pnew = pold;
+      changed += (pold >= 0 && pnew != pold) ? 1u : 0u;
+      out = best;
+    }
+  } else {
+    const T* wa = W.eval + pold * P;
+    T acc = T(0);
+#pragma unroll
+    for (int p = 0; p < P; ++p) acc = fma(wa[p], nb[p], acc);
+    out = fma(g, acc, rs);
+  }
+  if (MODE != MODE_RESID) res = tnanmax(res, fabs(out - c));
+}
+
+// The VEC states s .. s+VEC-1 (VEC = 4 needs m_last % 4 == 0 and s % 4 == 0):
+// loads, per-state work, stores.  Loads use clamped addresses (at the grid
+// edge the neighbour is the state itself), so every load is unconditional.
+template <typename T, int N, int MODE, int VEC, bool AXIS>
+__device__ __forceinline__ void stencil_chunk(const GridGeom& g, const StencilIO<T>& io,
+                                              const StencilW<T>& W, int s, T tol, T& res,
+                                              double& res_d, unsigned& changed) {
+  constexpr int P = 2 * N + 1;
+  int idx[N];
+  uint32_t rem = static_cast<uint32_t>(s);
+#pragma unroll
+  for (int k = N - 1; k > 0; --k) {
+    const uint32_t q = fdiv(rem, g.div[k]);
+    idx[k] = static_cast<int>(rem - q * static_cast<uint32_t>(g.size[k]));
+    rem = q;
+  }
+  idx[0] = static_cast<int>(rem);
+
+  if (VEC == 1) {
+    T nb[P];
+    const T c = io.V[s];
+    nb[0] = c;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      const int st = g.stride[k];
+      nb[1 + 2 * k] = io.V[s + ((idx[k] < g.size[k] - 1) ? st : 0)];
+      nb[2 + 2 * k] = io.V[s - ((idx[k] > 0) ? st : 0)];
+    }
+    const bool term = is_terminal(io.tbits, s);
+    const int pold = (MODE == MODE_MAX) ? -1 : (io.pi_in ? io.pi_in[s] : -1);
+    T out;
+    int pnew = 0;
+    stencil_state<T, N, MODE, AXIS>(W, nb, io.R[s], term, pold, tol, out, pnew, res, changed);
+    if (MODE == MODE_RESID) {
+      const double d = static_cast<double>(out) - static_cast<double>(c);
+      io.r_out[s] = static_cast<float>(d);
+      res_d = nanmax(res_d, fabs(d));
+    } else {
+      if (io.Vout) io.Vout[s] = out;
+      if (MODE == MODE_GREEDY && io.pi_out) io.pi_out[s] = pnew;
+    }
+  } else {
+    using V4 = typename VecOf<T, 4>::type;
+    const V4 c4 = *reinterpret_cast<const V4*>(io.V + s);
+    V4 plus4[N > 1 ? N - 1 : 1], minus4[N > 1 ? N - 1 : 1];
+#pragma unroll
+    for (int k = 0; k < N - 1; ++k) {
+      const int st = g.stride[k];
+      plus4[k] = *reinterpret_cast<const V4*>(io.V + s + ((idx[k] < g.size[k] - 1) ? st : 0));
+      minus4[k] = *reinterpret_cast<const V4*>(io.V + s - ((idx[k] > 0) ? st : 0));
+    }
+    const int il = idx[N - 1];
+    const T left = io.V[s - ((il > 0) ? 1 : 0)];
+    const T right = io.V[s + ((il + 4 < g.size[N - 1]) ? 4 : 3)];
+    const V4 r4 = *reinterpret_cast<const V4*>(io.R + s);
+    const uint32_t tw = io.tbits[s >> 5] >> (s & 31);
+    int4 p4 = make_int4(-1, -1, -1, -1);
+    if (MODE != MODE_MAX && io.pi_in) p4 = *reinterpret_cast<const int4*>(io.pi_in + s);
+    T outv[4];
+    int pnv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      T nb[P];
+      nb[0] = comp<T>(c4, q);
+#pragma unroll
+      for (int k = 0; k < N - 1; ++k) {
+        nb[1 + 2 * k] = comp<T>(plus4[k], q);
+        nb[2 + 2 * k] = comp<T>(minus4[k], q);
+      }
+      nb[1 + 2 * (N - 1)] = q < 3 ? comp<T>(c4, q + 1) : right;
+      nb[2 + 2 * (N - 1)] = q > 0 ? comp<T>(c4, q - 1) : left;
+      const int pold = q == 0 ? p4.x : (q == 1 ? p4.y : (q == 2 ? p4.z : p4.w));
+      pnv[q] = 0;
+      stencil_state<T, N, MODE, AXIS>(W, nb, comp<T>(r4, q), (tw >> q) & 1u, pold, tol,
+                                      outv[q], pnv[q], res, changed);
+    }
+    if (MODE == MODE_RESID) {
+      float4 r;
+      double d[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        d[q] = static_cast<double>(outv[q]) - static_cast<double>(comp<T>(c4, q));
+        res_d = nanmax(res_d, fabs(d[q]));
+      }
+      r.x = static_cast<float>(d[0]);
+      r.y = static_cast<float>(d[1]);
+      r.z = static_cast<float>(d[2]);
+      r.w = static_cast<float>(d[3]);
+      *reinterpret_cast<float4*>(io.r_out + s) = r;
+    } else {
+      if (io.Vout) {
+        V4 o;
+        o.x = outv[0];
+        o.y = outv[1];
+        o.z = outv[2];
+        o.w = outv[3];
+        *reinterpret_cast<V4*>(io.Vout + s) = o;
+      }
+      if (MODE == MODE_GREEDY && io.pi_out)
+        *reinterpret_cast<int4*>(io.pi_out + s) = make_int4(pnv[0], pnv[1], pnv[2], pnv[3]);
+    }
+  }
+}
+
+}  // namespace cpm

@@ -1,0 +1,131 @@
+"""GPU parity of the batched solver: every instance of a batch against the
+FP64 oracle and against its own single-instance solve, through the C ABI."""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2103_00331_amd import instances as I
+from tests.parity import assert_close, compare_policy, log, tol_for
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2103_00331_amd import binding
+    assert torch.cuda.is_available(), "GPU test run without a GPU"
+    return binding
+
+
+def _small_batch(count=14, seed=7):
+    """Instances of the batch generator at small sizes: n in {1..4}, odd and
+    even side lengths (both thread layouts), several terminals."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        n = int(rng.integers(1, 5))
+        sizes = [int(rng.integers(3, 13 if n > 2 else 40)) for _ in range(n)]
+        out.append(I.grid_small(sizes, slip=float(rng.uniform(0.05, 0.3)),
+                                gamma=float(rng.uniform(0.9, 0.99)), seed=100 + i))
+    return out
+
+
+def _solve_batch(B, insts, prec, eps, tune=False, max_iter=200000, V0=None):
+    bm = B.BatchModel(insts)
+    if tune:
+        B.cpmdp_batch_autotune(bm.b, True, None)
+    Vs = [torch.zeros(x.n_states, dtype=torch.float64, device="cuda") if V0 is None else
+          torch.as_tensor(V0[i], dtype=torch.float64, device="cuda").clone()
+          for i, x in enumerate(insts)]
+    pis = [torch.zeros(x.n_states, dtype=torch.int32, device="cuda") for x in insts]
+    code, sweeps, res = B.cpmdp_batch_solve(bm.b, Vs, pis, eps, max_iter, prec, 0)
+    torch.cuda.synchronize()
+    out = [(V.cpu().numpy(), p.cpu().numpy()) for V, p in zip(Vs, pis)]
+    bm.close()
+    return code, out, sweeps, res
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_small_batch_matches_oracle(B, prec):
+    insts = _small_batch()
+    log(f"[batch] small batch prec={prec}")
+    refs = []
+    for x in insts:
+        mats = oracle.sparse.transition_csr(x)
+        Vs, _, _, _ = oracle.sparse.value_iteration(x, mats=mats)
+        refs.append((mats, Vs))
+    eps = min(0.5 * tol_for(prec, Vs) * (1 - x.gamma) for x, (_, Vs) in zip(insts, refs))
+    code, out, sweeps, res = _solve_batch(B, insts, prec, eps)
+    assert code == B.CPMDP_OK
+    assert np.all(res <= eps)
+    for x, (mats, Vs), (V, pi) in zip(insts, refs, out):
+        assert_close(V, Vs, tol_for(prec, Vs), x.name)
+        compare_policy(pi, oracle.sparse.q_values(x, mats, Vs), eps / (1 - x.gamma) + 1e-12)
+
+
+def test_batch_equals_single_solves_and_autotune(B):
+    insts = _small_batch(count=9, seed=11)
+    log("[batch] vs single-instance solves, autotuned")
+    eps = 1e-9
+    code, out, sweeps, res = _solve_batch(B, insts, 1, eps, tune=True)
+    assert code == B.CPMDP_OK
+    for x, (V, pi) in zip(insts, out):
+        m = B.Model(x)
+        Vs = torch.zeros(x.n_states, dtype=torch.float64, device="cuda")
+        ps = torch.zeros(x.n_states, dtype=torch.int32, device="cuda")
+        c, sw, r = B.cpmdp_value_iteration(m.h, Vs, ps, eps, 200000, 1)
+        assert c == B.CPMDP_OK
+        assert_close(V, Vs.cpu().numpy(), 2 * eps / (1 - x.gamma), x.name)
+        m.close()
+
+
+def test_autotune_cache_roundtrip(B):
+    insts = _small_batch(count=5, seed=13)
+    log("[batch] autotune cache")
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "tune.txt")
+        bm = B.BatchModel(insts)
+        B.cpmdp_batch_autotune(bm.b, True, path)
+        cfg = B.cpmdp_batch_config(bm.b)
+        bm.close()
+        assert os.path.exists(path)
+        bm2 = B.BatchModel(insts)
+        B.cpmdp_batch_autotune(bm2.b, False, path)
+        assert B.cpmdp_batch_config(bm2.b) == cfg
+        bm2.close()
+
+
+def test_batch_max_iter_and_rejects_dense(B):
+    insts = _small_batch(count=3, seed=17)
+    code, out, sweeps, res = _solve_batch(B, insts, 1, 1e-12, max_iter=10)
+    assert code == B.CPMDP_NOT_CONVERGED and np.all(sweeps <= 12)
+    d = I.random_dense([3, 4], 2, 2, seed=1)
+    h = B.cpmdp_create(d.sizes, d.ranks, d.factors, d.lambdas, d.rewards, d.gamma)
+    with pytest.raises(B.CpmdpError) as e:
+        B.cpmdp_batch_create([h])
+    assert e.value.code == B.CPMDP_E_UNSUPPORTED
+    B.cpmdp_destroy(h)
+
+
+def test_batch512_full_certified(B):
+    """The 512-instance mixed batch (sum of states ~2.3e8): every instance
+    certified to eps = 1e-6 in FP64; a sample checked against the oracle."""
+    insts = [I.batch_instance(i) for i in range(512)]
+    log(f"[batch512] total states {sum(x.n_states for x in insts)}")
+    code, out, sweeps, res = _solve_batch(B, insts, 1, 1e-6, tune=True)
+    assert code == B.CPMDP_OK and np.all(res <= 1e-6)
+    order = np.argsort([x.n_states for x in insts])
+    for i in list(order[:4]) + [int(order[len(order) // 2])]:
+        x = insts[i]
+        V, pi = out[i]
+        mats = oracle.sparse.transition_csr(x)
+        Q = oracle.sparse.q_values(x, mats, V)
+        r_or = float(np.max(np.abs(Q.max(0) - V)))
+        assert abs(r_or - res[i]) <= 1e-12
+        assert r_or / (1 - x.gamma) <= tol_for(1, V)
+        compare_policy(pi, Q, 1e-9)
