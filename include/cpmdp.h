@@ -187,6 +187,19 @@ int cpmdp_policy_iteration(cpmdp_t* h, double* V_dev, int32_t* pi_dev,
                            double* residual_out);
 
 /*
+ * cpmdp_bound_shift -- one FP64 backup of V followed by the constant shift of
+ * McQueen's error bounds (McQueen 1966, "A modified dynamic programming method
+ * for Markovian decision problems"): with r = BV - V over the non-terminal
+ * states, V* lies within BV + gamma/(1-gamma) [min r, max r] when every
+ * factor row sums to 1; V is replaced by BV + gamma/(1-gamma) (min r + max r)/2
+ * on non-terminal states and by BV = R on terminal ones.  Used to start value
+ * iteration from a predicted V0 without its global offset.
+ *   V      : device FP64 [S], in/out.
+ *   lo_out, hi_out: nullable; gamma/(1-gamma) min r and gamma/(1-gamma) max r.
+ */
+int cpmdp_bound_shift(cpmdp_t* h, double* V, double* lo_out, double* hi_out);
+
+/*
  * cpmdp_time_sweeps -- measurement helper: run n backup sweeps ping-ponging
  * between the device buffers V_a and V_b (dtype of the precision, starting
  * from V_a), each bracketed by a HIP event pair on the bound stream, and
@@ -241,6 +254,61 @@ int cpmdp_batch_autotune(cpmdp_batch_t* b, int tune, const char* cache_path);
 int cpmdp_batch_config(const cpmdp_batch_t* b, int32_t* tile_states,
                        int32_t* sweeps_per_graph);
 void cpmdp_batch_destroy(cpmdp_batch_t* b);
+
+/* ------------------------------------------------------- learned warm start
+ * A 130 -> 256 -> 256 -> 1 ReLU MLP for 3-D GridWorlds (m^3 states) whose
+ * output y predicts (1 - gamma) V(s) = 0.2 + 0.05 y from per-state features;
+ * V0 = (0.2 + 0.05 y) / (1 - gamma) starts value iteration, whose FP64
+ * certificate is unchanged (plain VI from V0 = 0 stays the fallback).  All
+ * buffers are device buffers owned by the caller; work goes to `stream`.
+ *
+ * Parameters (FP32, 99,585): W1 [130][256] (input-major), b1 [256],
+ * W2 [256][256], b2 [256], w3 [256], b3 [1], in that order.
+ * Features of state s = (i0, i1, i2) (last index fastest, Def. 2):
+ *   [0..2]   i_k / (m - 1)
+ *   [3..127] 10 * R(clamp(i + d)), d in {-2..2}^3, d_0 slowest, each
+ *            coordinate clamped to [0, m - 1]
+ *   [128]    (gamma - 0.945) / 0.026
+ *   [129]    (slip - 0.175) / 0.072
+ * Random numbers: SplitMix64 (Steele, Lea & Flood 2014); normals by
+ * Box-Muller.  Loss: mean squared error of y against
+ * ((1 - gamma) V* - 0.2) / 0.05.
+ */
+int cpmdp_mlp_param_count(int64_t* count);
+/* Workspace bytes for `batch` rows (train step, loss_grad, forward) or for
+ * a predict chunk of that many states. */
+int cpmdp_mlp_workspace_bytes(int32_t batch, size_t* bytes);
+/* He-normal hidden weights from `seed`; zero biases and output layer. */
+int cpmdp_mlp_init(float* params, uint64_t seed, void* stream);
+/* X [count][130] for states s0 .. s0+count-1 of an m^3 grid with rewards R
+ * [m^3] (FP32). */
+int cpmdp_mlp_features(const float* R, int32_t m, double gamma, double slip, int32_t s0,
+                       int32_t count, float* X, void* stream);
+/* y [count] = MLP(X). */
+int cpmdp_mlp_forward(const float* params, const float* X, int32_t count, float* y, void* ws,
+                      size_t ws_bytes, void* stream);
+/* Gradient of mean((MLP(X) - t)^2) into grad [99,585]; loss_out (nullable,
+ * synchronizes the stream). */
+int cpmdp_mlp_loss_grad(const float* params, const float* X, const float* t, int32_t count,
+                        float* grad, double* loss_out, void* ws, size_t ws_bytes, void* stream);
+/* Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) at step >= 1. */
+int cpmdp_mlp_adam(float* params, float* m, float* v, const float* grad, int64_t step, double lr,
+                   void* stream);
+/* One training step on `batch` samples drawn from n_inst solved instances:
+ * R_ptrs / Vstar_ptrs are DEVICE arrays of n_inst device pointers (FP32
+ * rewards, FP64 solutions), gammas / slips device FP64 [n_inst]; sample i
+ * of step k is SplitMix64(seed ^ SplitMix64(k * 0x100000001B3 + i)) ->
+ * (instance = high 32 bits mod n_inst, state = low 32 bits mod m^3).
+ * Then forward, backward and Adam.  loss_out nullable (synchronizes). */
+int cpmdp_mlp_train_step(float* params, float* adam_m, float* adam_v, float* grad, int64_t step,
+                         const float* const* R_ptrs, const double* const* Vstar_ptrs,
+                         const double* gammas, const double* slips, int32_t n_inst, int32_t m,
+                         int32_t batch, uint64_t seed, double lr, void* ws, size_t ws_bytes,
+                         void* stream, double* loss_out);
+/* V0 [m^3] (FP64) = MLP prediction / (1 - gamma), in chunks of `chunk`
+ * states (workspace sized for chunk). */
+int cpmdp_mlp_predict(const float* params, const float* R, int32_t m, double gamma, double slip,
+                      double* V0, int32_t chunk, void* ws, size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

@@ -28,5 +28,5 @@ Readings of the paper that the oracle fixes (the paper is silent on them):
     it by more than tol; policy iteration stops when the policy is unchanged
     (Sec. 2.1).
 """
-from . import common, dense, sparse, structured  # noqa: F401
+from . import common, dense, mlp, sparse, structured  # noqa: F401
 from .common import greedy, improve, tie_tolerance  # noqa: F401

@@ -58,6 +58,7 @@ _SIGS = {
     "cpmdp_policy_iteration": (C.c_int, [_p, _p, _p, C.c_double, C.c_int64, C.c_int, _i64p,
                                          _i64p, _dp]),
     "cpmdp_time_sweeps": (C.c_int, [_p, _p, _p, C.c_int32, C.c_int, C.c_int, _p, _dp]),
+    "cpmdp_bound_shift": (C.c_int, [_p, _p, _dp, _dp]),
     "cpmdp_destroy": (None, [_p]),
     "cpmdp_last_error": (C.c_char_p, [_p]),
     "cpmdp_batch_create": (C.c_int, [C.POINTER(_p), C.POINTER(_p), C.c_int32]),
@@ -68,6 +69,19 @@ _SIGS = {
     "cpmdp_batch_autotune": (C.c_int, [_p, C.c_int, C.c_char_p]),
     "cpmdp_batch_config": (C.c_int, [_p, _i32p, _i32p]),
     "cpmdp_batch_destroy": (None, [_p]),
+    "cpmdp_mlp_param_count": (C.c_int, [_i64p]),
+    "cpmdp_mlp_workspace_bytes": (C.c_int, [C.c_int32, _szp]),
+    "cpmdp_mlp_init": (C.c_int, [_p, C.c_uint64, _p]),
+    "cpmdp_mlp_features": (C.c_int, [_p, C.c_int32, C.c_double, C.c_double, C.c_int32,
+                                     C.c_int32, _p, _p]),
+    "cpmdp_mlp_forward": (C.c_int, [_p, _p, C.c_int32, _p, _p, C.c_size_t, _p]),
+    "cpmdp_mlp_loss_grad": (C.c_int, [_p, _p, _p, C.c_int32, _p, _dp, _p, C.c_size_t, _p]),
+    "cpmdp_mlp_adam": (C.c_int, [_p, _p, _p, _p, C.c_int64, C.c_double, _p]),
+    "cpmdp_mlp_train_step": (C.c_int, [_p, _p, _p, _p, C.c_int64, _p, _p, _p, _p, C.c_int32,
+                                       C.c_int32, C.c_int32, C.c_uint64, C.c_double, _p,
+                                       C.c_size_t, _p, _dp]),
+    "cpmdp_mlp_predict": (C.c_int, [_p, _p, C.c_int32, C.c_double, C.c_double, _p, C.c_int32,
+                                    _p, C.c_size_t, _p]),
 }
 
 EXPORTED = sorted(_SIGS)
@@ -187,6 +201,13 @@ def cpmdp_time_sweeps(h, V_a, V_b, n, precision=CPMDP_FP32, mode=0, pi=None) -> 
     _check(lib.cpmdp_time_sweeps(h, _ptr(V_a), _ptr(V_b), int(n), int(precision), int(mode),
                                  _ptr(pi), C.byref(ms)), h)
     return ms.value
+
+
+def cpmdp_bound_shift(h, V):
+    lo = C.c_double(0.0)
+    hi = C.c_double(0.0)
+    _check(lib.cpmdp_bound_shift(h, _ptr(V), C.byref(lo), C.byref(hi)), h)
+    return lo.value, hi.value
 
 
 def cpmdp_destroy(h):
@@ -315,3 +336,61 @@ class BatchModel:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------ warm-start MLP
+
+def cpmdp_mlp_param_count() -> int:
+    n = C.c_int64()
+    _check(lib.cpmdp_mlp_param_count(C.byref(n)))
+    return n.value
+
+
+def cpmdp_mlp_workspace_bytes(batch) -> int:
+    b = C.c_size_t()
+    _check(lib.cpmdp_mlp_workspace_bytes(int(batch), C.byref(b)))
+    return b.value
+
+
+def cpmdp_mlp_init(params, seed, stream=None):
+    return _check(lib.cpmdp_mlp_init(_ptr(params), int(seed), _stream_ptr(stream)))
+
+
+def cpmdp_mlp_features(R, m, gamma, slip, s0, count, X, stream=None):
+    return _check(lib.cpmdp_mlp_features(_ptr(R), int(m), float(gamma), float(slip), int(s0),
+                                         int(count), _ptr(X), _stream_ptr(stream)))
+
+
+def cpmdp_mlp_forward(params, X, count, y, ws, stream=None):
+    return _check(lib.cpmdp_mlp_forward(_ptr(params), _ptr(X), int(count), _ptr(y), _ptr(ws),
+                                        ws.numel() * ws.element_size(), _stream_ptr(stream)))
+
+
+def cpmdp_mlp_loss_grad(params, X, t, count, grad, ws, stream=None):
+    loss = C.c_double(0.0)
+    _check(lib.cpmdp_mlp_loss_grad(_ptr(params), _ptr(X), _ptr(t), int(count), _ptr(grad),
+                                   C.byref(loss), _ptr(ws), ws.numel() * ws.element_size(),
+                                   _stream_ptr(stream)))
+    return loss.value
+
+
+def cpmdp_mlp_adam(params, m, v, grad, step, lr, stream=None):
+    return _check(lib.cpmdp_mlp_adam(_ptr(params), _ptr(m), _ptr(v), _ptr(grad), int(step),
+                                     float(lr), _stream_ptr(stream)))
+
+
+def cpmdp_mlp_train_step(params, adam_m, adam_v, grad, step, R_ptrs, V_ptrs, gammas, slips,
+                         n_inst, m, batch, seed, lr, ws, stream=None, want_loss=False):
+    loss = C.c_double(0.0)
+    _check(lib.cpmdp_mlp_train_step(_ptr(params), _ptr(adam_m), _ptr(adam_v), _ptr(grad),
+                                    int(step), _ptr(R_ptrs), _ptr(V_ptrs), _ptr(gammas),
+                                    _ptr(slips), int(n_inst), int(m), int(batch), int(seed),
+                                    float(lr), _ptr(ws), ws.numel() * ws.element_size(),
+                                    _stream_ptr(stream), C.byref(loss) if want_loss else None))
+    return loss.value if want_loss else None
+
+
+def cpmdp_mlp_predict(params, R, m, gamma, slip, V0, chunk, ws, stream=None):
+    return _check(lib.cpmdp_mlp_predict(_ptr(params), _ptr(R), int(m), float(gamma), float(slip),
+                                        _ptr(V0), int(chunk), _ptr(ws),
+                                        ws.numel() * ws.element_size(), _stream_ptr(stream)))

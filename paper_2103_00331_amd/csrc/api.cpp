@@ -962,6 +962,45 @@ int cpmdp_policy_iteration(cpmdp_t* h, double* V, int32_t* pi, double eps, int64
   return converged ? CPMDP_OK : CPMDP_NOT_CONVERGED;
 }
 
+int cpmdp_bound_shift(cpmdp_t* h, double* V, double* lo_out, double* hi_out) {
+  int rc = check_common(h, CPMDP_FP64);
+  if (rc) return rc;
+  if (!V) return fail(h, CPMDP_E_ARG, "V is NULL");
+  const hipStream_t st = h->stream;
+  zero_slots(h, 1);
+  sweep(h, true, MODE_MAX, V, h->d.Va64, h->d.R64, nullptr, nullptr, nullptr, h->d.slots, nullptr,
+        false);
+  launch_fill_u64(h->d.vmax + 2, 2, 0ull, st);
+  launch_shift_bounds(V, h->d.Va64, h->d.tbits, h->S, h->d.vmax + 2, st);
+  rc = check_device(h);
+  if (rc) return rc;
+  unsigned long long keys[2];
+  HIP_TRY(h, hipMemcpyAsync(h->host_slots, h->d.vmax + 2, 16, hipMemcpyDeviceToHost, st));
+  HIP_TRY(h, hipStreamSynchronize(st));
+  keys[0] = h->host_slots[0];
+  keys[1] = h->host_slots[1];
+  auto undo = [](unsigned long long k) {
+    const unsigned long long b = (k >> 63) ? (k & 0x7FFFFFFFFFFFFFFFull) : ~k;
+    return bits_to_double(b);
+  };
+  if (keys[0] == 0 && keys[1] == 0) {   // every state terminal: BV is exact
+    HIP_TRY(h, hipMemcpyAsync(V, h->d.Va64, h->S * 8, hipMemcpyDeviceToDevice, st));
+    if (lo_out) *lo_out = 0.0;
+    if (hi_out) *hi_out = 0.0;
+    return CPMDP_OK;
+  }
+  const double rmax = undo(keys[0]), rmin = -undo(keys[1]);
+  if (!std::isfinite(rmax) || !std::isfinite(rmin))
+    return fail(h, CPMDP_E_NONFINITE, "non-finite residual in bound_shift");
+  const double c = h->gamma / (1.0 - h->gamma);
+  launch_apply_shift(V, h->d.Va64, h->d.tbits, h->S, 0.5 * c * (rmin + rmax), st);
+  rc = check_device(h);
+  if (rc) return rc;
+  if (lo_out) *lo_out = c * rmin;
+  if (hi_out) *hi_out = c * rmax;
+  return CPMDP_OK;
+}
+
 int cpmdp_time_sweeps(cpmdp_t* h, void* V_a, void* V_b, int32_t n, int precision, int mode,
                       const int32_t* pi, double* mean_ms) {
   int rc = check_common(h, precision);

@@ -138,6 +138,10 @@ void launch_add_f32_to_f64(double* dst, const float* e, int64_t n, hipStream_t s
 void launch_fill_f32(float* p, int64_t n, float v, hipStream_t st);
 void launch_copy_i32(const int32_t* src, int32_t* dst, int64_t n, hipStream_t st);
 void launch_maxabs_f64(const double* v, int64_t n, unsigned long long* slot, hipStream_t st);
+void launch_shift_bounds(const double* V, const double* BV, const uint32_t* tbits, int64_t n,
+                         unsigned long long* keys, hipStream_t st);
+void launch_apply_shift(double* V, const double* BV, const uint32_t* tbits, int64_t n, double shift,
+                        hipStream_t st);
 void launch_check_policy(const int32_t* pi, int64_t n, int32_t A, unsigned int* bad, hipStream_t st);
 
 }  // namespace cpm

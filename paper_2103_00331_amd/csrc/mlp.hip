@@ -1,0 +1,419 @@
+// Learned warm start: a 130 -> 256 -> 256 -> 1 ReLU MLP that maps per-state
+// features of a 3-D GridWorld (normalised coordinates, the 5x5x5 window of
+// rewards around the state, gamma and slip) to y with (1 - gamma) V(s) =
+// 0.2 + 0.05 y.  The prediction divided by (1 - gamma) is the initial V of value iteration;
+// the solver itself, its FP64 certificate and plain VI from zero are
+// unchanged.
+//
+// Kernels: feature gather, one tiled FP32 GEMM (64x64 block tile, 4x4 per
+// thread, LDS-staged 16-deep K slices) with fused epilogues (bias, bias+ReLU,
+// ReLU-mask multiply), MSE loss/gradient, Adam, parameter init.  Random
+// numbers (minibatch indices, initial weights) come from SplitMix64 (Steele,
+// Lea & Flood, OOPSLA 2014) with the Box-Muller transform for normals.
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "cpmdp_internal.h"
+#include "handle.h"
+
+namespace cpm {
+
+constexpr int kF = 130;        // features
+constexpr int kH = 256;        // hidden width
+constexpr int64_t kOffW1 = 0;
+constexpr int64_t kOffB1 = kOffW1 + kF * kH;
+constexpr int64_t kOffW2 = kOffB1 + kH;
+constexpr int64_t kOffB2 = kOffW2 + kH * kH;
+constexpr int64_t kOffW3 = kOffB2 + kH;
+constexpr int64_t kOffB3 = kOffW3 + kH;
+constexpr int64_t kParams = kOffB3 + 1;   // 99,585
+
+// Feature normalisation constants (fixed, part of the model definition).
+constexpr float kRScale = 10.0f;              // rewards ~ N(0, 0.1) -> unit scale
+constexpr float kGammaMean = 0.945f, kGammaScale = 1.0f / 0.026f;
+constexpr float kSlipMean = 0.175f, kSlipScale = 1.0f / 0.072f;
+// Output: (1 - gamma) V = kOutMean + kOutScale * y.
+constexpr double kOutMean = 0.2, kOutScale = 0.05;
+
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
+__device__ __forceinline__ float u01(uint64_t r) {   // (0, 1]
+  return (static_cast<float>(r >> 40) + 1.0f) * (1.0f / 16777216.0f);
+}
+
+// ------------------------------------------------------------------ GEMM
+enum { EPI_NONE = 0, EPI_BIAS = 1, EPI_BIAS_RELU = 2, EPI_MASK = 3 };
+
+// C[M x N] = op(A) op(B) (+ epilogue).  op(A) is M x K: A[m*lda + k], or
+// A[k*lda + m] when TA.  op(B) is K x N: B[k*ldb + n], or B[n*ldb + k] when TB.
+template <bool TA, bool TB, int EPI>
+__global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, const float* __restrict__ A,
+                                                   int lda, const float* __restrict__ B, int ldb,
+                                                   float* __restrict__ C, int ldc,
+                                                   const float* __restrict__ bias,
+                                                   const float* __restrict__ mask, int ldm) {
+  __shared__ float As[16][64 + 4];
+  __shared__ float Bs[16][64 + 4];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  float acc[4][4] = {};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    for (int i = threadIdx.x; i < 64 * 16; i += 256) {
+      const int r = TA ? (i & 63) : (i >> 4);      // m within tile
+      const int c = TA ? (i >> 6) : (i & 15);      // k within tile
+      const int gm = m0 + r, gk = k0 + c;
+      float v = 0.f;
+      if (gm < M && gk < K) v = TA ? A[static_cast<int64_t>(gk) * lda + gm] : A[static_cast<int64_t>(gm) * lda + gk];
+      As[c][r] = v;
+    }
+    for (int i = threadIdx.x; i < 64 * 16; i += 256) {
+      const int r = TB ? (i & 15) : (i >> 6);      // k within tile
+      const int c = TB ? (i >> 4) : (i & 63);      // n within tile
+      const int gk = k0 + r, gn = n0 + c;
+      float v = 0.f;
+      if (gk < K && gn < N) v = TB ? B[static_cast<int64_t>(gn) * ldb + gk] : B[static_cast<int64_t>(gk) * ldb + gn];
+      Bs[r][c] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      float a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty * 4 + i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx * 4 + j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(a[i], b[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int gm = m0 + ty * 4 + i;
+    if (gm >= M) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int gn = n0 + tx * 4 + j;
+      if (gn >= N) continue;
+      float v = acc[i][j];
+      if (EPI == EPI_BIAS || EPI == EPI_BIAS_RELU) v += bias[gn];
+      if (EPI == EPI_BIAS_RELU) v = fmaxf(v, 0.f);
+      if (EPI == EPI_MASK) v = mask[static_cast<int64_t>(gm) * ldm + gn] > 0.f ? v : 0.f;
+      C[static_cast<int64_t>(gm) * ldc + gn] = v;
+    }
+  }
+}
+
+template <bool TA, bool TB, int EPI>
+static void gemm(int M, int N, int K, const float* A, int lda, const float* B, int ldb, float* C,
+                 int ldc, const float* bias, const float* mask, int ldm, hipStream_t st) {
+  const dim3 grid((N + 63) / 64, (M + 63) / 64);
+  hipLaunchKernelGGL((gemm_kernel<TA, TB, EPI>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb,
+                     C, ldc, bias, mask, ldm);
+}
+
+// -------------------------------------------------------------- features
+// Row i of X for state s of an m^3 grid:
+//   [0..2]    i_k / (m - 1)
+//   [3..127]  10 * R(clamp(i + d)) for d in {-2..2}^3, d_0 slowest
+//   [128]     (gamma - 0.945) / 0.026
+//   [129]     (slip - 0.175) / 0.072
+__device__ __forceinline__ void feature_row(const float* R, int m, float gamma, float slip, int s,
+                                            float* x) {
+  const int i2 = s % m, i1 = (s / m) % m, i0 = s / (m * m);
+  const float inv = m > 1 ? 1.0f / static_cast<float>(m - 1) : 0.f;
+  x[0] = i0 * inv;
+  x[1] = i1 * inv;
+  x[2] = i2 * inv;
+  int f = 3;
+  for (int d0 = -2; d0 <= 2; ++d0) {
+    const int j0 = min(max(i0 + d0, 0), m - 1);
+    for (int d1 = -2; d1 <= 2; ++d1) {
+      const int j1 = min(max(i1 + d1, 0), m - 1);
+      for (int d2 = -2; d2 <= 2; ++d2) {
+        const int j2 = min(max(i2 + d2, 0), m - 1);
+        x[f++] = kRScale * R[(j0 * m + j1) * m + j2];
+      }
+    }
+  }
+  x[128] = (gamma - kGammaMean) * kGammaScale;
+  x[129] = (slip - kSlipMean) * kSlipScale;
+}
+
+// All states s0 .. s0+count-1 of one instance.
+__global__ void features_range_kernel(const float* R, int m, float gamma, float slip, int s0,
+                                      int count, float* X) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) feature_row(R, m, gamma, slip, s0 + i, X + static_cast<int64_t>(i) * kF);
+}
+
+// Minibatch: sample i -> (instance, state) drawn with SplitMix64 from
+// (seed, step, i); features and the target (1 - gamma) V*(s).
+__global__ void features_sample_kernel(const float* const* R_ptrs, const double* const* V_ptrs,
+                                       const double* gammas, const double* slips, int n_inst,
+                                       int m, uint64_t seed, int64_t step, int count, float* X,
+                                       float* t) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const uint64_t r = splitmix64(seed ^ splitmix64(static_cast<uint64_t>(step) * 0x100000001B3ull +
+                                                  static_cast<uint64_t>(i)));
+  const int S = m * m * m;
+  const int inst = static_cast<int>((r >> 32) % static_cast<uint64_t>(n_inst));
+  const int s = static_cast<int>((r & 0xFFFFFFFFull) % static_cast<uint64_t>(S));
+  const float g = static_cast<float>(gammas[inst]);
+  feature_row(R_ptrs[inst], m, g, static_cast<float>(slips[inst]), s, X + static_cast<int64_t>(i) * kF);
+  t[i] = static_cast<float>(((1.0 - gammas[inst]) * V_ptrs[inst][s] - kOutMean) / kOutScale);
+}
+
+// -------------------------------------------------------------- loss, misc
+__global__ void mse_kernel(const float* y, const float* t, int count, float* dy, double* loss) {
+  __shared__ double part[4];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double l = 0.0;
+  if (i < count) {
+    const float d = y[i] - t[i];
+    dy[i] = 2.0f * d / static_cast<float>(count);
+    l = static_cast<double>(d) * d / count;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) l += __shfl_xor(l, off);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = l;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(loss, part[0] + part[1] + part[2] + part[3]);
+}
+
+__global__ void fill_kernel(float* p, int64_t n, float v) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void adam_kernel(float* p, float* m, float* v, const float* g, int64_t n, float lr,
+                            float b1, float b2, float eps, float c1, float c2) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// He-normal hidden weights (std sqrt(2 / fan_in)); zero biases and a zero
+// output layer, so training starts from the constant prediction kOutMean.
+__global__ void init_kernel(float* p, uint64_t seed) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= kParams) return;
+  float fan_in = 0.f;
+  if (i < kOffB1) fan_in = kF;
+  else if (i >= kOffW2 && i < kOffB2) fan_in = kH;
+  if (fan_in == 0.f) {
+    p[i] = 0.f;
+    return;
+  }
+  const uint64_t r1 = splitmix64(seed ^ splitmix64(2 * static_cast<uint64_t>(i)));
+  const uint64_t r2 = splitmix64(seed ^ splitmix64(2 * static_cast<uint64_t>(i) + 1));
+  const float z = sqrtf(-2.f * logf(u01(r1))) * cosf(6.2831853f * u01(r2));
+  p[i] = z * sqrtf(2.f / fan_in);
+}
+
+__global__ void to_values_kernel(const float* y, int count, double inv_scale, double* V) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) V[i] = (kOutMean + kOutScale * static_cast<double>(y[i])) * inv_scale;
+}
+
+// ----------------------------------------------------------- workspace
+struct MlpWs {
+  float *X, *H1, *H2, *y, *t, *dy, *dH1, *dH2, *ones;
+  double* loss;
+};
+
+static size_t al(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+size_t mlp_ws_bytes(int B) {
+  const size_t b = static_cast<size_t>(B);
+  return al(b * kF * 4) + 4 * al(b * kH * 4) + 4 * al(b * 4) + al(b * 4) + al(64);
+}
+
+MlpWs carve(void* ws, int B) {
+  char* p = static_cast<char*>(ws);
+  auto take = [&](size_t sz) {
+    char* q = p;
+    p += al(sz);
+    return q;
+  };
+  const size_t b = static_cast<size_t>(B);
+  MlpWs w{};
+  w.X = reinterpret_cast<float*>(take(b * kF * 4));
+  w.H1 = reinterpret_cast<float*>(take(b * kH * 4));
+  w.H2 = reinterpret_cast<float*>(take(b * kH * 4));
+  w.dH1 = reinterpret_cast<float*>(take(b * kH * 4));
+  w.dH2 = reinterpret_cast<float*>(take(b * kH * 4));
+  w.y = reinterpret_cast<float*>(take(b * 4));
+  w.t = reinterpret_cast<float*>(take(b * 4));
+  w.dy = reinterpret_cast<float*>(take(b * 4));
+  w.ones = reinterpret_cast<float*>(take(b * 4));
+  w.loss = reinterpret_cast<double*>(take(64));
+  return w;
+}
+
+void forward(const float* P, const float* X, int B, const MlpWs& w, hipStream_t st) {
+  gemm<false, false, EPI_BIAS_RELU>(B, kH, kF, X, kF, P + kOffW1, kH, w.H1, kH, P + kOffB1, nullptr, 0, st);
+  gemm<false, false, EPI_BIAS_RELU>(B, kH, kH, w.H1, kH, P + kOffW2, kH, w.H2, kH, P + kOffB2, nullptr, 0, st);
+  gemm<false, false, EPI_BIAS>(B, 1, kH, w.H2, kH, P + kOffW3, 1, w.y, 1, P + kOffB3, nullptr, 0, st);
+}
+
+// Gradient of the mean squared error (y - t)^2 over the B rows of X.
+void backward(const float* P, const float* X, int B, const MlpWs& w, float* G, hipStream_t st) {
+  const int nb = (B + 255) / 256;
+  hipLaunchKernelGGL(fill_kernel, dim3(nb), dim3(256), 0, st, w.ones, static_cast<int64_t>(B), 1.0f);
+  hipLaunchKernelGGL(mse_kernel, dim3(nb), dim3(256), 0, st, w.y, w.t, B, w.dy, w.loss);
+  // layer 3: dw3 = H2^T dy, db3 = 1^T dy, dH2 = (dy w3^T) .* [H2 > 0]
+  gemm<true, false, EPI_NONE>(kH, 1, B, w.H2, kH, w.dy, 1, G + kOffW3, 1, nullptr, nullptr, 0, st);
+  gemm<false, false, EPI_NONE>(1, 1, B, w.ones, B, w.dy, 1, G + kOffB3, 1, nullptr, nullptr, 0, st);
+  gemm<false, false, EPI_MASK>(B, kH, 1, w.dy, 1, P + kOffW3, kH, w.dH2, kH, nullptr, w.H2, kH, st);
+  // layer 2: dW2 = H1^T dH2, db2 = 1^T dH2, dH1 = (dH2 W2^T) .* [H1 > 0]
+  gemm<true, false, EPI_NONE>(kH, kH, B, w.H1, kH, w.dH2, kH, G + kOffW2, kH, nullptr, nullptr, 0, st);
+  gemm<false, false, EPI_NONE>(1, kH, B, w.ones, B, w.dH2, kH, G + kOffB2, kH, nullptr, nullptr, 0, st);
+  gemm<false, true, EPI_MASK>(B, kH, kH, w.dH2, kH, P + kOffW2, kH, w.dH1, kH, nullptr, w.H1, kH, st);
+  // layer 1: dW1 = X^T dH1, db1 = 1^T dH1
+  gemm<true, false, EPI_NONE>(kF, kH, B, X, kF, w.dH1, kH, G + kOffW1, kH, nullptr, nullptr, 0, st);
+  gemm<false, false, EPI_NONE>(1, kH, B, w.ones, B, w.dH1, kH, G + kOffB1, kH, nullptr, nullptr, 0, st);
+}
+
+int mfail(const std::string& m) { return fail(nullptr, CPMDP_E_ARG, m); }
+
+}  // namespace cpm
+
+using namespace cpm;
+
+extern "C" {
+
+int cpmdp_mlp_param_count(int64_t* count) {
+  if (!count) return mfail("count is NULL");
+  *count = kParams;
+  return CPMDP_OK;
+}
+
+int cpmdp_mlp_workspace_bytes(int32_t batch, size_t* bytes) {
+  if (!bytes || batch < 1) return mfail("batch >= 1 and bytes non-NULL");
+  *bytes = mlp_ws_bytes(batch);
+  return CPMDP_OK;
+}
+
+int cpmdp_mlp_init(float* params, uint64_t seed, void* stream) {
+  if (!params) return mfail("params is NULL");
+  hipLaunchKernelGGL(init_kernel, dim3((kParams + 255) / 256), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), params, seed);
+  return hipGetLastError() == hipSuccess ? CPMDP_OK : fail(nullptr, CPMDP_E_DEVICE, "init launch");
+}
+
+int cpmdp_mlp_features(const float* R, int32_t m, double gamma, double slip, int32_t s0,
+                       int32_t count, float* X, void* stream) {
+  if (!R || !X || m < 1 || count < 0 || s0 < 0 ||
+      static_cast<int64_t>(s0) + count > static_cast<int64_t>(m) * m * m)
+    return mfail("bad feature arguments");
+  if (count == 0) return CPMDP_OK;
+  hipLaunchKernelGGL(features_range_kernel, dim3((count + 255) / 256), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), R, m, static_cast<float>(gamma),
+                     static_cast<float>(slip), s0, count, X);
+  return hipGetLastError() == hipSuccess ? CPMDP_OK : fail(nullptr, CPMDP_E_DEVICE, "features launch");
+}
+
+int cpmdp_mlp_forward(const float* params, const float* X, int32_t count, float* y, void* ws,
+                      size_t ws_bytes, void* stream) {
+  if (!params || !X || !y || !ws || count < 1) return mfail("bad forward arguments");
+  if (ws_bytes < mlp_ws_bytes(count)) return fail(nullptr, CPMDP_E_WORKSPACE, "MLP workspace too small");
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  MlpWs w = carve(ws, count);
+  forward(params, X, count, w, st);
+  (void)hipMemcpyAsync(y, w.y, count * 4, hipMemcpyDeviceToDevice, st);
+  return hipGetLastError() == hipSuccess ? CPMDP_OK : fail(nullptr, CPMDP_E_DEVICE, "forward launch");
+}
+
+int cpmdp_mlp_loss_grad(const float* params, const float* X, const float* t, int32_t count,
+                        float* grad, double* loss_out, void* ws, size_t ws_bytes, void* stream) {
+  if (!params || !X || !t || !grad || !ws || count < 1) return mfail("bad loss_grad arguments");
+  if (ws_bytes < mlp_ws_bytes(count)) return fail(nullptr, CPMDP_E_WORKSPACE, "MLP workspace too small");
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  MlpWs w = carve(ws, count);
+  (void)hipMemcpyAsync(w.t, t, count * 4, hipMemcpyDeviceToDevice, st);
+  hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, st, reinterpret_cast<float*>(w.loss), 2, 0.0f);
+  forward(params, X, count, w, st);
+  backward(params, X, count, w, grad, st);
+  if (hipGetLastError() != hipSuccess) return fail(nullptr, CPMDP_E_DEVICE, "loss_grad launch");
+  if (loss_out) {
+    if (hipMemcpyAsync(loss_out, w.loss, 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return fail(nullptr, CPMDP_E_DEVICE, "loss read");
+  }
+  return CPMDP_OK;
+}
+
+int cpmdp_mlp_adam(float* params, float* m, float* v, const float* grad, int64_t step, double lr,
+                   void* stream) {
+  if (!params || !m || !v || !grad || step < 1 || !(lr > 0)) return mfail("bad adam arguments");
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = 1.f - std::pow(b1, static_cast<float>(step));
+  const float c2 = 1.f - std::pow(b2, static_cast<float>(step));
+  hipLaunchKernelGGL(adam_kernel, dim3((kParams + 255) / 256), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), params, m, v, grad, kParams,
+                     static_cast<float>(lr), b1, b2, 1e-8f, c1, c2);
+  return hipGetLastError() == hipSuccess ? CPMDP_OK : fail(nullptr, CPMDP_E_DEVICE, "adam launch");
+}
+
+int cpmdp_mlp_train_step(float* params, float* adam_m, float* adam_v, float* grad, int64_t step,
+                         const float* const* R_ptrs, const double* const* Vstar_ptrs,
+                         const double* gammas, const double* slips, int32_t n_inst, int32_t m,
+                         int32_t batch, uint64_t seed, double lr, void* ws, size_t ws_bytes,
+                         void* stream, double* loss_out) {
+  if (!params || !adam_m || !adam_v || !grad || !R_ptrs || !Vstar_ptrs || !gammas || !slips ||
+      n_inst < 1 || m < 1 || batch < 1 || step < 1 || !ws)
+    return mfail("bad train_step arguments");
+  if (ws_bytes < mlp_ws_bytes(batch)) return fail(nullptr, CPMDP_E_WORKSPACE, "MLP workspace too small");
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  MlpWs w = carve(ws, batch);
+  hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, st, reinterpret_cast<float*>(w.loss), 2, 0.0f);
+  hipLaunchKernelGGL(features_sample_kernel, dim3((batch + 255) / 256), dim3(256), 0, st, R_ptrs,
+                     Vstar_ptrs, gammas, slips, n_inst, m, seed, step, batch, w.X, w.t);
+  forward(params, w.X, batch, w, st);
+  backward(params, w.X, batch, w, grad, st);
+  int rc = cpmdp_mlp_adam(params, adam_m, adam_v, grad, step, lr, stream);
+  if (rc) return rc;
+  if (hipGetLastError() != hipSuccess) return fail(nullptr, CPMDP_E_DEVICE, "train_step launch");
+  if (loss_out) {
+    if (hipMemcpyAsync(loss_out, w.loss, 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return fail(nullptr, CPMDP_E_DEVICE, "loss read");
+  }
+  return CPMDP_OK;
+}
+
+int cpmdp_mlp_predict(const float* params, const float* R, int32_t m, double gamma, double slip,
+                      double* V0, int32_t chunk, void* ws, size_t ws_bytes, void* stream) {
+  if (!params || !R || !V0 || m < 1 || chunk < 1 || !ws || !(gamma < 1.0))
+    return mfail("bad predict arguments");
+  if (ws_bytes < mlp_ws_bytes(chunk)) return fail(nullptr, CPMDP_E_WORKSPACE, "MLP workspace too small");
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  const int S = m * m * m;
+  MlpWs w = carve(ws, chunk);
+  for (int s0 = 0; s0 < S; s0 += chunk) {
+    const int cnt = std::min(chunk, S - s0);
+    hipLaunchKernelGGL(features_range_kernel, dim3((cnt + 255) / 256), dim3(256), 0, st, R, m,
+                       static_cast<float>(gamma), static_cast<float>(slip), s0, cnt, w.X);
+    forward(params, w.X, cnt, w, st);
+    hipLaunchKernelGGL(to_values_kernel, dim3((cnt + 255) / 256), dim3(256), 0, st, w.y, cnt,
+                       1.0 / (1.0 - gamma), V0 + s0);
+  }
+  return hipGetLastError() == hipSuccess ? CPMDP_OK : fail(nullptr, CPMDP_E_DEVICE, "predict launch");
+}
+
+}  // extern "C"

@@ -1,0 +1,167 @@
+"""GPU parity of the warm-start MLP kernels against the FP64 oracle, and the
+warm-start A/B test: value iteration from the trained network's V0 needs
+fewer sweeps than from V0 = 0 and reaches the same certified solution."""
+import numpy as np
+import pytest
+
+from oracle import mlp as OM
+from paper_2103_00331_amd import instances as I
+from tests.parity import log
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2103_00331_amd import binding
+    assert torch.cuda.is_available(), "GPU test run without a GPU"
+    return binding
+
+
+def _params(B, seed=3):
+    p = torch.empty(B.cpmdp_mlp_param_count(), dtype=torch.float32, device="cuda")
+    B.cpmdp_mlp_init(p, seed)
+    torch.cuda.synchronize()
+    return p
+
+
+def _ws(B, n):
+    return torch.empty(B.cpmdp_mlp_workspace_bytes(n), dtype=torch.uint8, device="cuda")
+
+
+def test_init_statistics(B):
+    p = _params(B).cpu().numpy().astype(np.float64)
+    q = OM.unpack(p)
+    assert np.all(q["b1"] == 0) and np.all(q["b2"] == 0) and q["b3"][0] == 0
+    assert np.all(q["w3"] == 0)
+    assert abs(q["W1"].std() - np.sqrt(2 / 130)) < 0.01 * np.sqrt(2 / 130) * 10
+    assert abs(q["W2"].std() - np.sqrt(2 / 256)) < 0.05 * np.sqrt(2 / 256)
+    assert abs(q["W2"].mean()) < 1e-3
+
+
+@pytest.mark.parametrize("m", [1, 4, 9])
+def test_features_match_oracle(B, m):
+    inst = I.warm_instance(1, 0, m=m)
+    log(f"[mlp] features m={m}")
+    R = torch.as_tensor(inst.rewards, dtype=torch.float32, device="cuda")
+    S = inst.n_states
+    X = torch.empty(S, 130, dtype=torch.float32, device="cuda")
+    B.cpmdp_mlp_features(R, m, inst.gamma, inst.meta["slip"], 0, S, X)
+    torch.cuda.synchronize()
+    Rf = inst.rewards.astype(np.float32).astype(np.float64)
+    ref = OM.features(Rf, m, np.float32(inst.gamma), np.float32(inst.meta["slip"]), np.arange(S))
+    np.testing.assert_allclose(X.cpu().numpy(), ref, rtol=2e-6, atol=2e-6)
+
+
+def test_forward_and_gradient_match_oracle(B):
+    rng = np.random.default_rng(4)
+    n = 700                                 # ragged against the 64-row tiles
+    X = rng.normal(0, 1, (n, 130)).astype(np.float32)
+    t = rng.normal(0, 1, n).astype(np.float32)
+    p = _params(B, 5)
+    p += 0.05 * torch.randn(p.numel(), device="cuda", generator=torch.Generator("cuda").manual_seed(1))
+    pd = p.cpu().numpy().astype(np.float64)
+    Xd, td = torch.as_tensor(X, device="cuda"), torch.as_tensor(t, device="cuda")
+    ws = _ws(B, n)
+    y = torch.empty(n, dtype=torch.float32, device="cuda")
+    B.cpmdp_mlp_forward(p, Xd, n, y, ws)
+    g = torch.empty_like(p)
+    loss = B.cpmdp_mlp_loss_grad(p, Xd, td, n, g, ws)
+    torch.cuda.synchronize()
+    y_ref, _ = OM.forward(pd, X.astype(np.float64))
+    np.testing.assert_allclose(y.cpu().numpy(), y_ref, rtol=1e-4, atol=1e-4 * np.abs(y_ref).max())
+    L_ref, g_ref = OM.loss_grad(pd, X.astype(np.float64), t.astype(np.float64))
+    assert abs(loss - L_ref) <= 1e-4 * L_ref
+    gg = g.cpu().numpy().astype(np.float64)
+    for name, sl in _slices().items():
+        ref = g_ref[sl]
+        np.testing.assert_allclose(gg[sl], ref, rtol=0, atol=2e-4 * np.abs(ref).max() + 1e-7,
+                                   err_msg=name)
+
+
+def _slices():
+    out, off = {}, 0
+    for name, shape in OM.SIZES:
+        k = int(np.prod(shape))
+        out[name] = slice(off, off + k)
+        off += k
+    return out
+
+
+def test_train_step_matches_oracle(B):
+    """One training step (SplitMix64 sampling, features, forward, backward,
+    Adam) against the oracle reproducing the same samples."""
+    m, n_inst, batch, seed, lr = 6, 3, 256, 99, 1e-3
+    insts = [I.warm_instance(1, i, m=m) for i in range(n_inst)]
+    rng = np.random.default_rng(5)
+    Vs = [rng.normal(0, 3, x.n_states) for x in insts]
+    R = [torch.as_tensor(x.rewards, dtype=torch.float32, device="cuda") for x in insts]
+    V = [torch.as_tensor(v, dtype=torch.float64, device="cuda") for v in Vs]
+    Rp = torch.tensor([r.data_ptr() for r in R], dtype=torch.int64, device="cuda")
+    Vp = torch.tensor([v.data_ptr() for v in V], dtype=torch.int64, device="cuda")
+    gam = torch.tensor([x.gamma for x in insts], dtype=torch.float64, device="cuda")
+    slp = torch.tensor([x.meta["slip"] for x in insts], dtype=torch.float64, device="cuda")
+    p = _params(B, 6)
+    p += 0.05 * torch.randn(p.numel(), device="cuda", generator=torch.Generator("cuda").manual_seed(2))
+    p0 = p.cpu().numpy().astype(np.float64)
+    mm, vv, gg = torch.zeros_like(p), torch.zeros_like(p), torch.zeros_like(p)
+    loss = B.cpmdp_mlp_train_step(p, mm, vv, gg, 1, Rp, Vp, gam, slp, n_inst, m, batch, seed, lr,
+                                  _ws(B, batch), want_loss=True)
+    torch.cuda.synchronize()
+    X = np.empty((batch, 130))
+    t = np.empty(batch)
+    for i in range(batch):
+        a, s = OM.sample(seed, 1, i, n_inst, m ** 3)
+        x = insts[a]
+        X[i] = OM.features(x.rewards.astype(np.float32).astype(np.float64), m,
+                           np.float32(x.gamma), np.float32(x.meta["slip"]), [s])[0]
+        t[i] = np.float32(OM.target(Vs[a][s], x.gamma))
+    L_ref, g_ref = OM.loss_grad(p0, X, t)
+    assert abs(loss - L_ref) <= 1e-4 * L_ref
+    p1_ref, _, _ = OM.adam(p0, np.zeros_like(p0), np.zeros_like(p0), g_ref, 1, lr)
+    p1 = p.cpu().numpy().astype(np.float64)
+    # first Adam step moves each weight by ~lr * sign(g); compare where |g| is
+    # not tiny (elsewhere the step's sign depends on rounding of g ~ 0)
+    big = np.abs(g_ref) > 1e-3 * np.abs(g_ref).max()
+    np.testing.assert_allclose(p1[big], p1_ref[big], rtol=0, atol=2e-6)
+
+
+def test_warm_start_reduces_sweeps(B):
+    """Train on solved instances of the generator (small grids), then solve
+    held-out instances from V0 = 0 and from the network's V0."""
+    from paper_2103_00331_amd.warmstart import WarmStart, training_instances
+    m = 12
+    log("[mlp] warm start: building training set")
+    w = WarmStart(m=m, batch=2048, seed=7)
+    w.add_instances(training_instances(96, m=m, split=0))
+    losses = w.train(800, lr=1e-3, lr_final=1e-4, log_every=100)
+    log(f"   losses {losses}")
+    assert losses[-1][1] < 0.6 * losses[0][1]
+    cold, shifted, warm = [], [], []
+    for i in range(6):
+        x = I.warm_instance(2, i, m=m)
+        model = B.Model(x)
+        runs = {}
+        for kind in ("cold", "shift", "warm"):
+            V = w.predict(x) if kind == "warm" else \
+                torch.zeros(x.n_states, dtype=torch.float64, device="cuda")
+            extra = 0
+            if kind != "cold":
+                B.cpmdp_bound_shift(model.h, V)       # one backup + McQueen shift
+                extra = 1
+            c, sw, r = B.cpmdp_value_iteration(model.h, V, None, 1e-6, 100000, B.CPMDP_FP64)
+            assert c == B.CPMDP_OK and r <= 1e-6
+            runs[kind] = (V, sw + extra)
+        for kind in ("shift", "warm"):
+            diff = float((runs["cold"][0] - runs[kind][0]).abs().max())
+            assert diff <= 2e-6 / (1 - x.gamma)
+        cold.append(runs["cold"][1])
+        shifted.append(runs["shift"][1])
+        warm.append(runs["warm"][1])
+        model.close()
+    log(f"   sweeps cold {cold} cold+shift {shifted} warm+shift {warm}")
+    # The gain is logarithmic in the start error (sweeps saved ~ ln(error
+    # ratio) / ln(1/gamma)); with this training set it is a few percent.
+    assert np.mean(warm) < np.mean(cold)
