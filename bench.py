@@ -297,6 +297,91 @@ def bench_batch(args):
             "speedup_vs_plain_vi": plain / (el / args.steps)}
 
 
+def bench_warm(args):
+    """64^3 GridWorlds: train the warm-start network on solver-generated
+    instances, then on held-out instances compare plain FP64 VI from V0 = 0
+    with the chosen form (network V0 + bound shift, batched FP32/FP64 solve)."""
+    import numpy as np
+    import torch
+
+    from paper_2103_00331_amd import binding as B
+    from paper_2103_00331_amd import instances as I
+    from paper_2103_00331_amd.warmstart import WarmStart, training_instances
+
+    eps = 1e-6
+    t0 = time.perf_counter()
+    w = WarmStart(m=64, batch=4096, seed=11)
+    train = training_instances(args.train_instances, m=64, split=0)
+    t_gen = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    w.add_instances(train, eps=eps)
+    torch.cuda.synchronize()
+    t_solve = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    losses = w.train(args.train_steps, lr=1e-3, lr_final=1e-4, log_every=max(1, args.train_steps // 5))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    _log(f"training: {len(train)} instances generated {t_gen:.1f}s solved {t_solve:.1f}s, "
+         f"{args.train_steps} steps {t_train:.1f}s, losses {losses}")
+    test = [I.warm_instance(2, i) for i in range(args.test_instances)]
+    # plain GPU VI from zero, each instance alone
+    plain_s, plain_sw, models = 0.0, [], []
+    for x in test:
+        m = B.Model(x)
+        models.append(m)
+        V = torch.zeros(x.n_states, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        code, sw, res = B.cpmdp_value_iteration(m.h, V, None, eps, 100000, B.CPMDP_FP64)
+        torch.cuda.synchronize()
+        plain_s += time.perf_counter() - t1
+        plain_sw.append(sw)
+    # warm start alone: network V0 + bound shift, FP64 VI per instance
+    warm_s, warm_sw = 0.0, []
+    for x, m in zip(test, models):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        V = w.predict(x)
+        B.cpmdp_bound_shift(m.h, V)
+        code, sw, res = B.cpmdp_value_iteration(m.h, V, None, eps, 100000, B.CPMDP_FP64)
+        torch.cuda.synchronize()
+        warm_s += time.perf_counter() - t1
+        warm_sw.append(sw + 1)
+        assert code == B.CPMDP_OK
+    for m in models:
+        m.close()
+    # chosen: network V0 for all, then one batched mixed-precision solve
+    bm = B.BatchModel(test)
+    B.cpmdp_batch_autotune(bm.b, True, None)
+    Vs = [torch.empty(x.n_states, dtype=torch.float64, device="cuda") for x in test]
+    for step in range(args.warmup + args.steps):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for x, V in zip(test, Vs):
+            V.copy_(w.predict(x))
+        code, sw, res = B.cpmdp_batch_solve(bm.b, Vs, None, eps, 100000, B.CPMDP_FP32, 0)
+        torch.cuda.synchronize()
+        if step == args.warmup:
+            chosen_s = time.perf_counter() - t1
+            chosen_sw = sw
+        assert code == B.CPMDP_OK and np.all(res <= eps)
+    bm.close()
+    S, A = test[0].n_states, test[0].n_actions
+    return {"metric": METRIC, "value": float(np.sum(chosen_sw)) * S * A / chosen_s,
+            "unit": "state-action backups/s", "n_gpus": 1, "steps": 1, "warmup": args.warmup,
+            "ms_per_step": chosen_s * 1e3, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"warm start on 64^3 GridWorlds ({S} states, {A} actions): "
+                                   f"{len(train)} training instances, {args.train_steps} Adam "
+                                   f"steps of 4096 samples, {len(test)} held-out instances",
+                       "eps": eps, "train_loss": losses[-1][1],
+                       "train_seconds": {"generate": t_gen, "solve": t_solve, "train": t_train}},
+            "time_to_eps_s": chosen_s, "plain_vi_time_to_eps_s": plain_s,
+            "speedup_vs_plain_vi": plain_s / chosen_s,
+            "sweeps_plain": plain_sw, "sweeps_warm_fp64": warm_sw,
+            "warm_fp64_time_s": warm_s, "sweeps_chosen": [int(v) for v in chosen_sw]}
+
+
 def kernel_only(args):
     """Short run for hardware-counter passes: n sweeps of the dominant kernel
     on the workload, then one plain device copy of a known size (1 GiB) whose
@@ -332,13 +417,16 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="grid4d_32",
-                    choices=["grid4d_32", "grid4d_96", "dense6_16", "batch512"])
+                    choices=["grid4d_32", "grid4d_96", "dense6_16", "batch512", "warm64"])
     ap.add_argument("--method", default="vi", choices=["vi", "pi"])
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only the dominant kernel and a 1 GiB copy (counter passes)")
     ap.add_argument("--sweeps", type=int, default=20)
+    ap.add_argument("--train-instances", type=int, default=512)
+    ap.add_argument("--train-steps", type=int, default=3000)
+    ap.add_argument("--test-instances", type=int, default=16)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -355,6 +443,8 @@ def main():
         out = bench_dense(args)
     elif args.workload == "batch512":
         out = bench_batch(args)
+    elif args.workload == "warm64":
+        out = bench_warm(args)
     else:
         out, inst = bench_grid(args, 32 if args.workload == "grid4d_32" else 96)
         if args.workload == "grid4d_32" and not args.no_cpu_baseline:

@@ -569,7 +569,16 @@ int cpmdp_batch_solve(cpmdp_batch_t* b, double* const* V_devs, int32_t* const* p
   const size_t n = b->hs.size();
   for (size_t i = 0; i < n; ++i)
     if (!V_devs[i]) return bfail(b, CPMDP_E_ARG, "NULL V buffer");
-  if (b->user_stream) BHIP(b, hipStreamSynchronize(b->user_stream));
+  // The caller's buffers are written on its stream (possibly the null
+  // stream, which a non-blocking stream does not wait for): order the
+  // private stream after everything enqueued there so far.
+  {
+    hipEvent_t ready;
+    BHIP(b, hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    BHIP(b, hipEventRecord(ready, b->user_stream));
+    BHIP(b, hipStreamWaitEvent(b->stream, ready, 0));
+    (void)hipEventDestroy(ready);
+  }
   // inputs -> internal FP64 buffer 0
   std::vector<int64_t> sweeps(n, 0);
   std::vector<double> cert(n, INFINITY);

@@ -129,3 +129,21 @@ def test_batch512_full_certified(B):
         assert abs(r_or - res[i]) <= 1e-12
         assert r_or / (1 - x.gamma) <= tol_for(1, V)
         compare_policy(pi, Q, 1e-9)
+
+
+def test_batch_orders_after_callers_stream(B):
+    """V0 written on the caller's (default) stream right before the call must
+    be what the batch starts from: repeated solves from a fresh V0 = 0 run
+    the same number of sweeps for every instance."""
+    insts = _small_batch(count=6, seed=19)
+    bm = B.BatchModel(insts)
+    Vs = [torch.zeros(x.n_states, dtype=torch.float64, device="cuda") for x in insts]
+    runs = []
+    for _ in range(3):
+        for V in Vs:
+            V.zero_()
+        code, sweeps, res = B.cpmdp_batch_solve(bm.b, Vs, None, 1e-9, 200000, 1, 0)
+        assert code == B.CPMDP_OK
+        runs.append(list(sweeps))
+    bm.close()
+    assert runs[0] == runs[1] == runs[2], runs
