@@ -69,8 +69,11 @@ typedef enum cpmdp_precision {
   CPMDP_FP64 = 0, /* mode products in FP64                                     */
   CPMDP_FP32 = 1, /* mode products in FP32 (FP64 master, residual, certificate
                      in the solvers)                                           */
-  CPMDP_BF16 = 2  /* dense mode products with BF16 operands on MFMA and FP32
-                     accumulation; shift/identity factors run as FP32          */
+  CPMDP_BF16 = 2  /* dense modes with m_k <= 16: mode products on the matrix
+                     cores with BF16 operands (each value split into hi + lo
+                     BF16 parts, products hi*hi + hi*lo + lo*hi) and FP32
+                     accumulation, on V - c (c = midrange of V; exact since
+                     P_a 1 = 1); other modes run as FP32                       */
 } cpmdp_precision;
 
 typedef enum cpmdp_path {

@@ -166,7 +166,7 @@ void layout(const cpmdp_t* h, DevPtrs* dp, char* base, size_t* total) {
   d.R32 = cv.take<float>(S);
   d.tbits = cv.take<uint32_t>((S + 31) / 32 + 1);
   d.slots = cv.take<unsigned long long>(static_cast<size_t>(kSlots) * kSpread);
-  d.vmax = cv.take<unsigned long long>(4);
+  d.vmax = cv.take<unsigned long long>(8);   // [0] max|V|, [2..3] bound shift, [4..5] chain shift
   d.counters = cv.take<unsigned int>(8);
   d.Va64 = cv.take<double>(S);
   d.Va32 = cv.take<float>(S);
@@ -187,7 +187,7 @@ void layout(const cpmdp_t* h, DevPtrs* dp, char* base, size_t* total) {
     const size_t F = T * static_cast<size_t>(h->cg64.term_stride);
     d.fac64 = cv.take<double>(F);
     d.fac32 = cv.take<float>(F);
-    d.facbf = cv.take<uint16_t>(F);
+    d.facbf = cv.take<uint16_t>(2 * F);   // BF16 split: hi [F], then lo [F]
     d.lam64 = cv.take<double>(T);
     d.lam32 = cv.take<float>(T);
     d.kinds = cv.take<uint8_t>(T * h->n);
@@ -304,7 +304,9 @@ void sweep(cpmdp_t* h, bool prec64, int mode, const void* V, void* Vout, const v
     a.vmax_bits = h->d.vmax;
     a.res_slot = slot;
     a.change_count = ctr;
-    launch_chain<double>(a, mode, st);
+    a.facbf = nullptr;
+    a.facbf_lo = nullptr;
+    launch_chain<double>(a, mode, CHAIN_VALU, st);
   } else {
     ChainArgs<float> a{};
     a.g = h->cg32;
@@ -326,10 +328,16 @@ void sweep(cpmdp_t* h, bool prec64, int mode, const void* V, void* Vout, const v
     a.vmax_bits = h->d.vmax;
     a.res_slot = slot;
     a.change_count = ctr;
-    if (bf16 && chain_bf16_supported(a.g))
-      launch_chain_bf16(a, h->d.facbf, reinterpret_cast<uint16_t*>(h->d.W), mode, st);
-    else
-      launch_chain<float>(a, mode, st);
+    a.facbf = h->d.facbf;
+    a.facbf_lo = h->d.facbf + h->factors.size();
+    if (bf16) {
+      // BF16 operands: run the chain on V - midrange(V) (Sec. 2.2 operators
+      // are row-stochastic, so P (V - c) + c = P V) to keep rounding small.
+      launch_fill_u64(h->d.vmax + 4, 2, 0ull, st);
+      launch_minmax_keys_f32(a.V, h->S, h->d.vmax + 4, st);
+      a.shift_keys = h->d.vmax + 4;
+    }
+    launch_chain<float>(a, mode, bf16 ? CHAIN_BF16 : CHAIN_F32_MFMA, st);
   }
 }
 
@@ -425,7 +433,11 @@ static int run_sweeps(cpmdp_t* h, bool prec64, int mode, P*& cur, P*& alt, const
       *done = true;
       return CPMDP_OK;
     }
-    if (stall_floor > 0 && rl <= stall_floor && k >= 8 && rl >= 0.9 * rf) return CPMDP_OK;
+    // stalled at the precision's rounding floor: over the chunk the residual
+    // fell by less than half of the contraction gamma^(k-1) guarantees
+    if (stall_floor > 0 && rl <= stall_floor && k >= 8 &&
+        rl >= rf * std::max(0.9, std::pow(h->gamma, 0.5 * (k - 1))))
+      return CPMDP_OK;
   }
   return CPMDP_OK;
 }
@@ -735,21 +747,30 @@ int cpmdp_bind(cpmdp_t* h, void* ws, size_t bytes, void* stream) {
   } else {
     const size_t F = h->factors.size();
     fac32.resize(F);
-    facbf.resize(F);
+    facbf.resize(2 * F);
+    auto to_bf16 = [](float f) {          // round to nearest even
+      uint32_t u;
+      std::memcpy(&u, &f, 4);
+      return static_cast<uint16_t>((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+    };
+    auto from_bf16 = [](uint16_t b) {
+      const uint32_t u = static_cast<uint32_t>(b) << 16;
+      float f;
+      std::memcpy(&f, &u, 4);
+      return f;
+    };
     for (size_t i = 0; i < F; ++i) {
       const float f = static_cast<float>(h->factors[i]);
       fac32[i] = f;
-      uint32_t u;
-      std::memcpy(&u, &f, 4);
-      const uint32_t rounding = 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
-      facbf[i] = static_cast<uint16_t>((u + rounding) >> 16);
+      facbf[i] = to_bf16(f);                          // hi
+      facbf[F + i] = to_bf16(f - from_bf16(facbf[i]));  // lo (the difference is exact)
     }
     lam32.resize(h->lambdas.size());
     for (size_t i = 0; i < lam32.size(); ++i) lam32[i] = static_cast<float>(h->lambdas[i]);
     ts.assign(h->term_start.begin(), h->term_start.end());
     HIP_TRY(h, hipMemcpyAsync(h->d.fac64, h->factors.data(), F * 8, hipMemcpyHostToDevice, st));
     HIP_TRY(h, hipMemcpyAsync(h->d.fac32, fac32.data(), F * 4, hipMemcpyHostToDevice, st));
-    HIP_TRY(h, hipMemcpyAsync(h->d.facbf, facbf.data(), F * 2, hipMemcpyHostToDevice, st));
+    HIP_TRY(h, hipMemcpyAsync(h->d.facbf, facbf.data(), 2 * F * 2, hipMemcpyHostToDevice, st));
     HIP_TRY(h, hipMemcpyAsync(h->d.lam64, h->lambdas.data(), lam32.size() * 8,
                               hipMemcpyHostToDevice, st));
     HIP_TRY(h, hipMemcpyAsync(h->d.lam32, lam32.data(), lam32.size() * 4, hipMemcpyHostToDevice, st));
@@ -859,10 +880,18 @@ int cpmdp_value_iteration(cpmdp_t* h, double* V, int32_t* pi_out, double eps, in
     launch_f64_to_f32(V, h->d.Va32, h->S, st);
     float* cur = h->d.Va32;
     float* alt = h->d.Vb32;
-    rc = run_sweeps<float>(h, false, MODE_MAX, cur, alt, h->d.R32, nullptr,
-                           std::max(eps, floor32), floor32 * 4, max_iter - 1, &sweeps, &done,
-                           &last, precision == CPMDP_BF16);
-    if (rc) return rc;
+    if (precision == CPMDP_BF16) {   // BF16 sweeps until they stall, then FP32
+      rc = run_sweeps<float>(h, false, MODE_MAX, cur, alt, h->d.R32, nullptr,
+                             std::max(eps, floor32), INFINITY, max_iter - 1, &sweeps, &done,
+                             &last, true);
+      if (rc) return rc;
+    }
+    if (!done) {
+      rc = run_sweeps<float>(h, false, MODE_MAX, cur, alt, h->d.R32, nullptr,
+                             std::max(eps, floor32), floor32 * 4, max_iter - 1, &sweeps, &done,
+                             &last, false);
+      if (rc) return rc;
+    }
     launch_f32_to_f64(cur, V, h->S, st);
   }
   double cert = INFINITY;
@@ -938,8 +967,9 @@ int cpmdp_policy_iteration(cpmdp_t* h, double* V, int32_t* pi, double eps, int64
         bool done = false;
         double last = 0;
         const double tol_e = std::max(1e-3 * r[0], floor32 * 1e-3);
-        rc = run_sweeps<float>(h, false, MODE_EVAL, cur, alt, h->d.r32, pi, tol_e, 0.0,
-                               max_iter - 1, &sweeps, &done, &last, precision == CPMDP_BF16);
+        rc = run_sweeps<float>(h, false, MODE_EVAL, cur, alt, h->d.r32, pi, tol_e,
+                               precision == CPMDP_BF16 ? INFINITY : 0.0, max_iter - 1, &sweeps,
+                               &done, &last, precision == CPMDP_BF16);
         if (rc) return rc;
         launch_add_f32_to_f64(V, cur, h->S, st);
       }

@@ -21,6 +21,8 @@
 // hold whole fibers in registers: load fiber, barrier, write the m outputs.
 // LDS indices are padded by one word per 32 to break bank conflicts of
 // strided fibers.
+#include <type_traits>
+
 #include "common.cuh"
 
 namespace cpm {
@@ -61,10 +63,112 @@ __device__ __forceinline__ void mode_product_lds(T* X, int outer, int m, int inn
   }
 }
 
+// ------------------------------------------------------------ MFMA path
+// For m_k <= 16 a mode product is a batch of 16 x 16 matrix-vector products
+// T (16 x 16, zero-padded) times 16-element fibers: one 16 x 16 x 16 matrix
+// product per block of 16 fibers.  Matrix-core layout (wave of 64 lanes,
+// lane l: column c = l % 16, group g = l / 16):
+//   fp32 16x16x4 : A[i = c][k = 4q + g], B[k = 4q + g][fiber c], q = 0..3
+//   bf16 16x16x16: A[i = c][k = 4g + r], B[k = 4g + r][fiber c], r = 0..3
+//   result       : D[i = 4g + r][fiber c], r = 0..3 (FP32 accumulation)
+// The BF16 unit splits factor and fiber values into hi + lo BF16 parts
+// (x_hi = bf16(x), x_lo = bf16(x - x_hi)) and accumulates lo*hi, hi*lo,
+// hi*hi; the dropped lo*lo term and the lo rounding leave a relative error
+// of a few 2^-16 per mode product instead of 2^-8.
+// A wave owns whole blocks: it reads all 16 x 16 inputs of a block before its
+// matrix products and writes the outputs to the same LDS slots afterwards, so
+// the product is in place without a barrier between blocks.
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef short s4v __attribute__((ext_vector_type(4)));
+
+enum { MM_VALU = 0, MM_F32 = 1, MM_BF16 = 2 };
+
+__device__ __forceinline__ uint32_t bf16_bits(float x) {   // round to nearest even
+  const uint32_t u = __float_as_uint(x);
+  return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ __forceinline__ float bf16_value(uint32_t b) { return __uint_as_float(b << 16); }
+
+template <int MM>
+__device__ __forceinline__ void mode_product_mfma(float* X, int outer, int m, int inner,
+                                                  const float* __restrict__ Tk,
+                                                  const uint16_t* __restrict__ Th,
+                                                  const uint16_t* __restrict__ Tl) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int c = lane & 15, g = lane >> 4;
+  const int F = outer * inner;
+  const int nblk = (F + 15) >> 4;
+  float a32[4];
+  s4v ahi, alo;
+  if (MM == MM_F32) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k = 4 * q + g;
+      a32[q] = (c < m && k < m) ? Tk[c * m + k] : 0.f;
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int k = 4 * g + r;
+      const bool in = c < m && k < m;
+      ahi[r] = in ? static_cast<short>(Th[c * m + k]) : static_cast<short>(0);
+      alo[r] = in ? static_cast<short>(Tl[c * m + k]) : static_cast<short>(0);
+    }
+  }
+  for (int b = wave; b < nblk; b += nw) {
+    const int f = b * 16 + c;
+    const bool ok = f < F;
+    int base = 0;
+    if (ok) {
+      const int o = f / inner;
+      base = o * m * inner + (f - o * inner);
+    }
+    f4v acc = {0.f, 0.f, 0.f, 0.f};
+    if (MM == MM_F32) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = 4 * q + g;
+        const float bv = (ok && k < m) ? X[lpad(base + k * inner)] : 0.f;
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a32[q], bv, acc, 0, 0, 0);
+      }
+    } else {
+      s4v bhi, blo;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int k = 4 * g + r;
+        const float x = (ok && k < m) ? X[lpad(base + k * inner)] : 0.f;
+        const uint32_t h = bf16_bits(x);
+        bhi[r] = static_cast<short>(h);
+        blo[r] = static_cast<short>(bf16_bits(x - bf16_value(h)));
+      }
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo, bhi, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, blo, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, bhi, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 4 * g + r;
+      if (ok && i < m) X[lpad(base + i * inner)] = acc[r];
+    }
+  }
+  __syncthreads();
+}
+
+// Mode product of one term's factor along one mode, on the chosen unit.
+template <typename T, int MMAX, int MM>
+__device__ __forceinline__ void mode_product(T* X, int outer, int m, int inner, const T* Tk,
+                                             const uint16_t* Th, const uint16_t* Tl) {
+  if constexpr (MM == MM_VALU) {
+    mode_product_lds<T, MMAX>(X, outer, m, inner, Tk);
+  } else {
+    mode_product_mfma<MM>(X, outer, m, inner, Tk, Th, Tl);
+  }
+}
+
 constexpr int kPass1Block = 256;
 constexpr int kPass2Block = 512;
 
-template <typename T, int MMAX>
+template <typename T, int MMAX, int MM>
 __global__ __launch_bounds__(kPass1Block) void chain_pass1(ChainArgs<T> a) {
   extern __shared__ unsigned char smem_raw[];
   const int C = a.g.C;
@@ -72,7 +176,8 @@ __global__ __launch_bounds__(kPass1Block) void chain_pass1(ChainArgs<T> a) {
   T* ws = vs + lpad(C) + 1;
   const int r = xcd_block(blockIdx.x, gridDim.x);
   const T* Vrow = a.V + static_cast<int64_t>(r) * C;
-  for (int c = threadIdx.x; c < C; c += blockDim.x) vs[lpad(c)] = Vrow[c];
+  const T cs = a.shift_keys ? static_cast<T>(midrange(a.shift_keys)) : T(0);
+  for (int c = threadIdx.x; c < C; c += blockDim.x) vs[lpad(c)] = Vrow[c] - cs;
   __syncthreads();
   const int n = a.g.n;
   for (int t = 0; t < a.nterms; ++t) {
@@ -82,9 +187,10 @@ __global__ __launch_bounds__(kPass1Block) void chain_pass1(ChainArgs<T> a) {
     for (int k = a.g.n1; k < n; ++k) {
       const int m = a.g.size[k];
       inner /= m;
-      if (a.kinds[t * n + k] != F_IDENT)
-        mode_product_lds<T, MMAX>(ws, outer, m, inner,
-                                  a.fac + static_cast<int64_t>(t) * a.g.term_stride + a.g.fac_off[k]);
+      if (a.kinds[t * n + k] != F_IDENT) {
+        const int64_t fo = static_cast<int64_t>(t) * a.g.term_stride + a.g.fac_off[k];
+        mode_product<T, MMAX, MM>(ws, outer, m, inner, a.fac + fo, a.facbf + fo, a.facbf_lo + fo);
+      }
       outer *= m;
     }
     T* Wt = a.W + static_cast<int64_t>(t) * a.g.w_term_stride;
@@ -96,7 +202,7 @@ __global__ __launch_bounds__(kPass1Block) void chain_pass1(ChainArgs<T> a) {
   }
 }
 
-template <typename T, int MMAX, int MODE, int EPT>
+template <typename T, int MMAX, int MODE, int EPT, int MM>
 __global__ __launch_bounds__(kPass2Block) void chain_pass2(ChainArgs<T> a) {
   extern __shared__ unsigned char smem_raw[];
   T* X = reinterpret_cast<T*>(smem_raw);
@@ -124,6 +230,9 @@ __global__ __launch_bounds__(kPass2Block) void chain_pass2(ChainArgs<T> a) {
 
   T tol = T(0);
   if (MODE == MODE_GREEDY) tol = static_cast<T>(tie_tol(a.vmax_bits));
+  // shift c: pass 1 (or, with a single pass, the load below) works on V - c
+  const T cs = a.shift_keys ? static_cast<T>(midrange(a.shift_keys)) : T(0);
+  const T cs_in = (n1 == n) ? cs : T(0);
   const bool need_pi = (MODE == MODE_EVAL || MODE == MODE_RESID) ||
                        (MODE == MODE_GREEDY && a.pi_in != nullptr);
   if (MODE == MODE_EVAL || MODE == MODE_RESID) {
@@ -155,16 +264,17 @@ __global__ __launch_bounds__(kPass2Block) void chain_pass2(ChainArgs<T> a) {
 #pragma unroll
       for (int j = 0; j < EPT; ++j) {
         const int e = threadIdx.x + j * kPass2Block;
-        if (e < TE) X[lpad(e)] = Wt[e];
+        if (e < TE) X[lpad(e)] = Wt[e] - cs_in;
       }
       __syncthreads();
       int outer = 1, inner = TE;
       for (int k = 0; k < n1; ++k) {
         const int m = a.g.size[k];
         inner /= m;
-        if (a.kinds[t * n + k] != F_IDENT)
-          mode_product_lds<T, MMAX>(X, outer, m, inner,
-                                    a.fac + static_cast<int64_t>(t) * a.g.term_stride + a.g.fac_off[k]);
+        if (a.kinds[t * n + k] != F_IDENT) {
+          const int64_t fo = static_cast<int64_t>(t) * a.g.term_stride + a.g.fac_off[k];
+          mode_product<T, MMAX, MM>(X, outer, m, inner, a.fac + fo, a.facbf + fo, a.facbf_lo + fo);
+        }
         outer *= m;
       }
       const T lam = a.lam[t];
@@ -192,7 +302,7 @@ __global__ __launch_bounds__(kPass2Block) void chain_pass2(ChainArgs<T> a) {
         const int s = state_of(threadIdx.x + j * kPass2Block, v);
         if (v) {
           const T g = is_terminal(a.term_bits, s) ? T(0) : a.gamma;
-          const T q = fma(g, acc[j], a.R[s]);
+          const T q = fma(g, acc[j] + cs, a.R[s]);
           tie_update(q, act, tol, best[j], bi[j]);
           if (act == pold[j]) qold[j] = q;
         }
@@ -217,7 +327,7 @@ __global__ __launch_bounds__(kPass2Block) void chain_pass2(ChainArgs<T> a) {
       res = nanmax(res, fabs(static_cast<double>(best[j]) - static_cast<double>(c)));
     } else {
       const T g = is_terminal(a.term_bits, s) ? T(0) : a.gamma;
-      const T vnew = fma(g, MODE == MODE_MAX ? best[j] : acc[j], a.R[s]);
+      const T vnew = fma(g, (MODE == MODE_MAX ? best[j] : acc[j]) + cs, a.R[s]);
       const double d = static_cast<double>(vnew) - static_cast<double>(c);
       if (MODE == MODE_RESID) {
         a.r_out[s] = static_cast<float>(d);
@@ -239,51 +349,76 @@ static int pick_mmax(int m) {
   return 32;
 }
 
-template <typename T, int MMAX>
+template <typename T, int MMAX, int MM>
 static void launch_pass1_m(const ChainArgs<T>& a, hipStream_t st) {
   const size_t sh = sizeof(T) * (2 * (static_cast<size_t>(a.g.C) + (a.g.C >> 5) + 1) + 2);
-  hipLaunchKernelGGL((chain_pass1<T, MMAX>), dim3(a.g.Rr), dim3(kPass1Block), sh, st, a);
+  hipLaunchKernelGGL((chain_pass1<T, MMAX, MM>), dim3(a.g.Rr), dim3(kPass1Block), sh, st, a);
 }
 
-template <typename T, int MMAX, int MODE>
+template <typename T, int MMAX, int MODE, int MM>
 static void launch_pass2_mm(const ChainArgs<T>& a, hipStream_t st) {
   const int TE = a.g.Rr * a.g.CT;
   const int ept = (TE + kPass2Block - 1) / kPass2Block;
   const size_t sh = sizeof(T) * (static_cast<size_t>(TE) + (TE >> 5) + 1);
   const dim3 grid(a.g.ntiles), block(kPass2Block);
-  if (ept <= 2) hipLaunchKernelGGL((chain_pass2<T, MMAX, MODE, 2>), grid, block, sh, st, a);
-  else if (ept <= 8) hipLaunchKernelGGL((chain_pass2<T, MMAX, MODE, 8>), grid, block, sh, st, a);
-  else if (ept <= 16) hipLaunchKernelGGL((chain_pass2<T, MMAX, MODE, 16>), grid, block, sh, st, a);
-  else hipLaunchKernelGGL((chain_pass2<T, MMAX, MODE, 32>), grid, block, sh, st, a);
+  if (ept <= 2) hipLaunchKernelGGL((chain_pass2<T, MMAX, MODE, 2, MM>), grid, block, sh, st, a);
+  else if (ept <= 8) hipLaunchKernelGGL((chain_pass2<T, MMAX, MODE, 8, MM>), grid, block, sh, st, a);
+  else if (ept <= 16) hipLaunchKernelGGL((chain_pass2<T, MMAX, MODE, 16, MM>), grid, block, sh, st, a);
+  else hipLaunchKernelGGL((chain_pass2<T, MMAX, MODE, 32, MM>), grid, block, sh, st, a);
 }
 
-template <typename T, int MMAX>
+template <typename T, int MMAX, int MM>
 static void launch_pass2_m(const ChainArgs<T>& a, int mode, hipStream_t st) {
   switch (mode) {
-    case MODE_MAX: launch_pass2_mm<T, MMAX, MODE_MAX>(a, st); break;
-    case MODE_GREEDY: launch_pass2_mm<T, MMAX, MODE_GREEDY>(a, st); break;
-    case MODE_EVAL: launch_pass2_mm<T, MMAX, MODE_EVAL>(a, st); break;
-    default: launch_pass2_mm<T, MMAX, MODE_RESID>(a, st); break;
+    case MODE_MAX: launch_pass2_mm<T, MMAX, MODE_MAX, MM>(a, st); break;
+    case MODE_GREEDY: launch_pass2_mm<T, MMAX, MODE_GREEDY, MM>(a, st); break;
+    case MODE_EVAL: launch_pass2_mm<T, MMAX, MODE_EVAL, MM>(a, st); break;
+    default: launch_pass2_mm<T, MMAX, MODE_RESID, MM>(a, st); break;
+  }
+}
+
+// Unit of one group's mode products: matrix cores when every mode of the
+// group has m_k <= 16 (FP32 from 5 up, BF16 always), vector ALUs otherwise.
+static int pick_unit(int mmax, int unit) {
+  if (unit == CHAIN_BF16) return mmax <= 16 ? MM_BF16 : MM_VALU;
+  if (unit == CHAIN_F32_MFMA) return (mmax > 4 && mmax <= 16) ? MM_F32 : MM_VALU;
+  return MM_VALU;
+}
+
+template <typename T>
+static void launch_pass1(const ChainArgs<T>& a, int mm, hipStream_t st) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (mm == MM_F32) return launch_pass1_m<T, 16, MM_F32>(a, st);
+    if (mm == MM_BF16) return launch_pass1_m<T, 16, MM_BF16>(a, st);
+  }
+  switch (pick_mmax(a.g.mmax_col)) {
+    case 4: return launch_pass1_m<T, 4, MM_VALU>(a, st);
+    case 16: return launch_pass1_m<T, 16, MM_VALU>(a, st);
+    default: return launch_pass1_m<T, 32, MM_VALU>(a, st);
   }
 }
 
 template <typename T>
-void launch_chain(const ChainArgs<T>& a, int mode, hipStream_t st) {
-  if (a.g.n1 < a.g.n) {
-    switch (pick_mmax(a.g.mmax_col)) {
-      case 4: launch_pass1_m<T, 4>(a, st); break;
-      case 16: launch_pass1_m<T, 16>(a, st); break;
-      default: launch_pass1_m<T, 32>(a, st); break;
-    }
+static void launch_pass2(const ChainArgs<T>& a, int mode, int mm, hipStream_t st) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (mm == MM_F32) return launch_pass2_m<T, 16, MM_F32>(a, mode, st);
+    if (mm == MM_BF16) return launch_pass2_m<T, 16, MM_BF16>(a, mode, st);
   }
   switch (pick_mmax(a.g.mmax_row)) {
-    case 4: launch_pass2_m<T, 4>(a, mode, st); break;
-    case 16: launch_pass2_m<T, 16>(a, mode, st); break;
-    default: launch_pass2_m<T, 32>(a, mode, st); break;
+    case 4: return launch_pass2_m<T, 4, MM_VALU>(a, mode, st);
+    case 16: return launch_pass2_m<T, 16, MM_VALU>(a, mode, st);
+    default: return launch_pass2_m<T, 32, MM_VALU>(a, mode, st);
   }
 }
 
-template void launch_chain<double>(const ChainArgs<double>&, int, hipStream_t);
-template void launch_chain<float>(const ChainArgs<float>&, int, hipStream_t);
+template <typename T>
+void launch_chain(const ChainArgs<T>& a, int mode, int unit, hipStream_t st) {
+  const bool f32 = std::is_same<T, float>::value;
+  if (a.g.n1 < a.g.n) launch_pass1(a, f32 ? pick_unit(a.g.mmax_col, unit) : MM_VALU, st);
+  launch_pass2(a, mode, f32 ? pick_unit(a.g.mmax_row, unit) : MM_VALU, st);
+}
+
+template void launch_chain<double>(const ChainArgs<double>&, int, int, hipStream_t);
+template void launch_chain<float>(const ChainArgs<float>&, int, int, hipStream_t);
 
 }  // namespace cpm

@@ -63,6 +63,22 @@ __device__ __forceinline__ bool is_terminal(const uint32_t* bits, int s) {
   return (bits[s >> 5] >> (s & 31)) & 1u;
 }
 
+// Order-preserving map of doubles to unsigned 64-bit keys (so that an
+// unsigned atomic max gives the max of signed values), and its inverse.
+__device__ __forceinline__ unsigned long long dkey(double v) {
+  const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double dkey_value(unsigned long long k) {
+  const unsigned long long b = (k >> 63) ? (k & 0x7FFFFFFFFFFFFFFFull) : ~k;
+  return __longlong_as_double(static_cast<long long>(b));
+}
+
+// Midrange (max V + min V) / 2 from the keys [max V, max -V].
+__device__ __forceinline__ float midrange(const unsigned long long* keys) {
+  return static_cast<float>(0.5 * (dkey_value(keys[0]) - dkey_value(keys[1])));
+}
+
 __device__ __forceinline__ double tie_tol(const unsigned long long* vmax_bits) {
   const double vm = __longlong_as_double(static_cast<long long>(*vmax_bits));
   return kTieRel * (vm > 1.0 ? vm : 1.0);

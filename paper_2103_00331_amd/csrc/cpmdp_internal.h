@@ -105,6 +105,8 @@ struct ChainArgs {
   int32_t nterms;
   const int32_t* term_start;    // [A+1] first term of each action
   const T* fac;                 // packed factors in T
+  const uint16_t* facbf;        // the same factors split into BF16 hi + lo
+  const uint16_t* facbf_lo;     // (bit patterns; hi + lo = the FP32 factor)
   const T* lam;                 // [nterms]
   const uint8_t* kinds;         // [nterms][n]
   const T* V;
@@ -119,15 +121,21 @@ struct ChainArgs {
   const unsigned long long* vmax_bits;
   unsigned long long* res_slot;
   unsigned int* change_count;
+  // Keys [max V, max -V] of the input, or null.  When set, the chain runs on
+  // V - c with c the midrange of V and adds c back (exact for stochastic
+  // operators, and it keeps low-precision operands small).
+  const unsigned long long* shift_keys;
 };
 
-template <typename T>
-void launch_chain(const ChainArgs<T>& a, int mode, hipStream_t st);
+// Unit for FP32 chains: vector ALUs, FP32 matrix cores, or BF16 operands on
+// matrix cores with FP32 accumulation (modes with m_k <= 16 only; larger
+// modes run on vector ALUs in FP32).  The BF16 unit splits every operand
+// into hi + lo BF16 parts and sums the products hi*hi + hi*lo + lo*hi.
+// FP64 chains always use vector ALUs.
+enum ChainUnit { CHAIN_VALU = 0, CHAIN_F32_MFMA = 1, CHAIN_BF16 = 2 };
 
-// BF16 operands on MFMA, FP32 accumulation; only 16^n1 x 16^(n-n1) splits.
-bool chain_bf16_supported(const ChainGeom& g);
-void launch_chain_bf16(const ChainArgs<float>& a, const uint16_t* fac_bf16,
-                       uint16_t* W_bf16, int mode, hipStream_t st);
+template <typename T>
+void launch_chain(const ChainArgs<T>& a, int mode, int unit, hipStream_t st);
 
 // ---------------------------------------------------------------- helpers
 void launch_fill_u64(unsigned long long* p, int n, unsigned long long v, hipStream_t st);
@@ -140,6 +148,7 @@ void launch_copy_i32(const int32_t* src, int32_t* dst, int64_t n, hipStream_t st
 void launch_maxabs_f64(const double* v, int64_t n, unsigned long long* slot, hipStream_t st);
 void launch_shift_bounds(const double* V, const double* BV, const uint32_t* tbits, int64_t n,
                          unsigned long long* keys, hipStream_t st);
+void launch_minmax_keys_f32(const float* V, int64_t n, unsigned long long* keys, hipStream_t st);
 void launch_apply_shift(double* V, const double* BV, const uint32_t* tbits, int64_t n, double shift,
                         hipStream_t st);
 void launch_check_policy(const int32_t* pi, int64_t n, int32_t A, unsigned int* bad, hipStream_t st);

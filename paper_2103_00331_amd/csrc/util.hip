@@ -53,11 +53,23 @@ __global__ void check_policy_kernel(const int32_t* pi, int64_t n, int32_t A, uns
   block_sum_to_counter(c, bad);
 }
 
-// Order-preserving map of doubles to unsigned 64-bit keys (so that an
-// unsigned atomic max gives the max of signed values).
-__device__ __forceinline__ unsigned long long dkey(double v) {
-  const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
-  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+// keys[0] = ordered key of max V, keys[1] = ordered key of max(-V).
+__global__ void minmax_keys_f32_kernel(const float* V, int64_t n, unsigned long long* keys) {
+  unsigned long long hi = 0, lo = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double v = static_cast<double>(V[i]);
+    hi = max(hi, dkey(v));
+    lo = max(lo, dkey(-v));
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    hi = max(hi, static_cast<unsigned long long>(__shfl_xor(static_cast<long long>(hi), off)));
+    lo = max(lo, static_cast<unsigned long long>(__shfl_xor(static_cast<long long>(lo), off)));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(keys, hi);
+    atomicMax(keys + 1, lo);
+  }
 }
 
 // keys[0] = max over non-terminal states of (BV - V), keys[1] = max of (V - BV).
@@ -92,6 +104,9 @@ __global__ void apply_shift_kernel(double* V, const double* BV, const uint32_t* 
 void launch_shift_bounds(const double* V, const double* BV, const uint32_t* tbits, int64_t n,
                          unsigned long long* keys, hipStream_t st) {
   hipLaunchKernelGGL(shift_bounds_kernel, dim3(util_grid(n)), dim3(kUtilBlock), 0, st, V, BV, tbits, n, keys);
+}
+void launch_minmax_keys_f32(const float* V, int64_t n, unsigned long long* keys, hipStream_t st) {
+  hipLaunchKernelGGL(minmax_keys_f32_kernel, dim3(util_grid(n)), dim3(kUtilBlock), 0, st, V, n, keys);
 }
 void launch_apply_shift(double* V, const double* BV, const uint32_t* tbits, int64_t n, double shift,
                         hipStream_t st) {

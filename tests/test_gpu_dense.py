@@ -78,18 +78,44 @@ def test_one_backup_matches_oracle(B, name, prec):
     model.close()
 
 
+@pytest.mark.parametrize("name", list(CASES))
+def test_bf16_one_backup_matches_oracle(B, name):
+    """BF16 operands on the matrix cores, FP32 accumulation: one backup within
+    1e-3 max(1, ||V||) of the FP64 oracle, and within the bound
+    gamma ((1 + 3 2^-16 + 64 2^-24)^n - 1) ||V - c|| (c = midrange of V) that
+    the hi + lo split (three dropped or rounded parts of size 2^-16 per
+    product) and FP32 accumulation allow over n mode products."""
+    inst = CASES[name]()
+    log(f"[dense backup] {name} bf16")
+    model = B.Model(inst)
+    V = I.seeded_values(inst.n_states, 12, scale=2.0).astype(np.float32).astype(np.float64)
+    Q = oracle.structured.q_values(inst, V)
+    Vg, pig, r = _backup(B, model, V, 2)
+    n = len(inst.sizes)
+    spread = 0.5 * (V.max() - V.min())
+    bound = inst.gamma * ((1 + 3 * 2.0 ** -16 + 64 * 2.0 ** -24) ** n - 1) * spread \
+        + tol_for(1, Q)
+    tol = tol_for(2, np.abs(V).max())
+    err = assert_close(Vg, Q.max(0), min(tol, bound), "V' bf16")
+    log(f"   bf16 error {err:.3e} (tolerance {tol:.3e}, bound {bound:.3e})")
+    compare_policy(pig, Q, tol)
+    model.close()
+
+
 @pytest.mark.parametrize("method", ["vi", "pi"])
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 def test_dense_solve_matches_oracle(B, method, prec):
+    """Solves in FP64, FP32 and BF16 (FP64 refinement and certificate): the
+    low-precision solves still reach the FP32 tolerance or better."""
     inst = I.random_dense([6, 7, 5, 4], 3, 2, seed=36, gamma=0.95, alpha=0.5, n_terminal=3)
     log(f"[dense solve] 6x7x5x4 {method} prec={prec}")
     Vs, _, _, _ = oracle.structured.value_iteration(inst)
     model = B.Model(inst)
-    eps = 0.5 * tol_for(prec, Vs) * (1 - inst.gamma)
+    eps = 0.5 * tol_for(min(prec, 1), Vs) * (1 - inst.gamma)
     V, pi, code, sweeps, res = _solve(B, model, method, prec, eps)
     assert code == B.CPMDP_OK and res <= eps
     tol = eps / (1 - inst.gamma) + 1e-12
-    assert_close(V, Vs, tol_for(prec, Vs), "V*")
+    assert_close(V, Vs, tol_for(min(prec, 1), Vs), "V*")
     compare_policy(pi, oracle.structured.q_values(inst, Vs), tol)
     model.close()
 
@@ -102,10 +128,10 @@ def test_dense12_6_one_backup_full(B):
     V = I.seeded_values(inst.n_states, 9, scale=3.0).astype(np.float32).astype(np.float64)
     Q = oracle.structured.q_values(inst, V)
     model = B.Model(inst)
-    for prec in (1, 0):
+    for prec in (1, 2, 0):
         log(f"[dense 12^6] gpu backup prec={prec}")
         Vg, pig, r = _backup(B, model, V, prec)
-        tol = 1e-12 * np.abs(V).max() if prec == 0 else tol_for(1, Q.max(0))
+        tol = 1e-12 * np.abs(V).max() if prec == 0 else tol_for(prec, Q.max(0))
         assert_close(Vg, Q.max(0), tol, f"V' prec={prec}")
         compare_policy(pig, Q, tol)
     model.close()
@@ -122,19 +148,40 @@ def test_dense16_6_sampled_states_and_closed_form(B):
     states = np.concatenate([[0, inst.n_states - 1], rng.integers(0, inst.n_states, 6)])
     log("[dense 16^6] per-state oracle")
     Qs = oracle.structured.q_at_states(inst, V, states)
-    for prec in (1, 0):
+    for prec in (1, 2, 0):
         log(f"[dense 16^6] gpu backup prec={prec}")
         Vg, pig, _ = _backup(B, model, V, prec)
-        tol = 1e-12 * np.abs(V).max() if prec == 0 else tol_for(1, Qs.max(0))
+        tol = 1e-12 * np.abs(V).max() if prec == 0 else tol_for(prec, Qs.max(0))
         assert_close(Vg[states], Qs.max(0), tol, f"sampled V' prec={prec}")
         compare_policy(pig[states], Qs, tol)
     model.close()
     c = 0.05
     cinst = I.with_rewards(inst, np.full(inst.n_states, c))
     cmodel = B.Model(cinst)
-    log("[dense 16^6] constant-reward VI fp32")
-    Vc, _, code, sweeps, res = _solve(B, cmodel, "vi", 1, 1e-6)
-    assert code == B.CPMDP_OK
-    assert_close(Vc, np.full(inst.n_states, c / (1 - inst.gamma)),
-                 1e-6 / (1 - inst.gamma) + 1e-9, "c / (1 - gamma)")
+    for prec in (1, 2):
+        log(f"[dense 16^6] constant-reward VI prec={prec}")
+        Vc, _, code, sweeps, res = _solve(B, cmodel, "vi", prec, 1e-6)
+        assert code == B.CPMDP_OK
+        assert_close(Vc, np.full(inst.n_states, c / (1 - inst.gamma)),
+                     1e-6 / (1 - inst.gamma) + 1e-9, "c / (1 - gamma)")
     cmodel.close()
+
+
+def test_bf16_dense12_6_vi_iterate(B):
+    """12^6: one BF16 backup from an iterate of value iteration (three
+    oracle sweeps from zero) against the oracle, at 1e-3 max(1, ||V||)."""
+    inst = I.dense_grid(12, seed=I.SEED_DENSE6_SMALL)
+    log("[dense 12^6] three oracle sweeps")
+    V = np.zeros(inst.n_states)
+    for _ in range(3):
+        V = oracle.structured.backup(inst, V)[0]
+    V = V.astype(np.float32).astype(np.float64)
+    Q = oracle.structured.q_values(inst, V)
+    model = B.Model(inst)
+    log("[dense 12^6] gpu backup bf16")
+    Vg, pig, _ = _backup(B, model, V, 2)
+    tol = tol_for(2, np.abs(V).max())
+    err = assert_close(Vg, Q.max(0), tol, "V' bf16")
+    log(f"   bf16 error {err:.3e} (tolerance {tol:.3e})")
+    compare_policy(pig, Q, tol)
+    model.close()
