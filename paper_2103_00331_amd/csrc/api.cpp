@@ -7,6 +7,7 @@
 #include <limits>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "cpmdp_internal.h"
@@ -215,6 +216,46 @@ GridGeom make_geom(const cpmdp_t* h) {
   return g;
 }
 
+// Kernel arguments of one stencil sweep in precision T (FP64 or FP32 copies
+// of R and of the weights).
+template <typename T>
+static StencilArgs<T> stencil_args(cpmdp_t* h, const void* V, void* Vout, const void* R,
+                                   const int32_t* pi_in, int32_t* pi_out, float* r_out,
+                                   unsigned long long* slot, unsigned int* ctr) {
+  constexpr bool f64 = std::is_same<T, double>::value;
+  const size_t AP = static_cast<size_t>(h->A) * (2 * h->n + 1);
+  const T* w = f64 ? reinterpret_cast<const T*>(h->d.w64) : reinterpret_cast<const T*>(h->d.w32);
+  StencilArgs<T> a{};
+  a.g = h->geom;
+  a.A = h->A;
+  a.npts = 2 * h->n + 1;
+  a.w = w;
+  a.wdiff = w + AP;
+  a.wbase = w + 2 * AP;
+  a.states_per_block = h->st_states_per_block;
+  a.vec = h->st_vec;
+  a.axis = h->st_axis;
+  if (a.axis) {
+    for (int i = 0; i < 2 * h->n + 1; ++i) a.kw_base[i] = static_cast<T>(f64 ? h->kw64[i] : h->kw32[i]);
+    const size_t na = (f64 ? h->kw64.size() : h->kw32.size()) - (2 * h->n + 1);
+    for (size_t i = 0; i < na; ++i)
+      a.kw_axis[i] = static_cast<T>(f64 ? h->kw64[2 * h->n + 1 + i] : h->kw32[2 * h->n + 1 + i]);
+  }
+  a.V = static_cast<const T*>(V);
+  a.Vout = static_cast<T*>(Vout);
+  a.R = static_cast<const T*>(R);
+  a.term_bits = h->d.tbits;
+  a.gamma = static_cast<T>(h->gamma);
+  a.pi_in = pi_in;
+  a.pi_out = pi_out;
+  a.r_out = r_out;
+  a.vmax_bits = h->d.vmax;
+  a.res_slot = slot;
+  a.change_count = ctr;
+  a.nblocks = h->st_blocks;
+  return a;
+}
+
 // One sweep on the bound stream.  prec64 selects FP64 buffers (T = double)
 // or FP32 (T = float).  V, Vout, R are typed by that choice.
 void sweep(cpmdp_t* h, bool prec64, int mode, const void* V, void* Vout, const void* R,
@@ -222,63 +263,11 @@ void sweep(cpmdp_t* h, bool prec64, int mode, const void* V, void* Vout, const v
            unsigned long long* slot, unsigned int* ctr, bool bf16) {
   const hipStream_t st = h->stream;
   if (h->path == CPMDP_PATH_STENCIL) {
-    const int nblocks = h->st_blocks;
-    const size_t AP = static_cast<size_t>(h->A) * (2 * h->n + 1);
     if (prec64) {
-      StencilArgs<double> a{};
-      a.g = h->geom;
-      a.A = h->A;
-      a.npts = 2 * h->n + 1;
-      a.w = h->d.w64;
-      a.wdiff = h->d.w64 + AP;
-      a.wbase = h->d.w64 + 2 * AP;
-      a.states_per_block = h->st_states_per_block;
-      a.vec = h->st_vec;
-      a.axis = h->st_axis;
-      if (a.axis) {
-        std::copy(h->kw64.begin(), h->kw64.begin() + 2 * h->n + 1, a.kw_base);
-        std::copy(h->kw64.begin() + 2 * h->n + 1, h->kw64.end(), a.kw_axis);
-      }
-      a.V = static_cast<const double*>(V);
-      a.Vout = static_cast<double*>(Vout);
-      a.R = static_cast<const double*>(R);
-      a.term_bits = h->d.tbits;
-      a.gamma = h->gamma;
-      a.pi_in = pi_in;
-      a.pi_out = pi_out;
-      a.r_out = r_out;
-      a.vmax_bits = h->d.vmax;
-      a.res_slot = slot;
-      a.change_count = ctr;
-      a.nblocks = nblocks;
+      StencilArgs<double> a = stencil_args<double>(h, V, Vout, R, pi_in, pi_out, r_out, slot, ctr);
       launch_stencil<double>(a, mode, st);
     } else {
-      StencilArgs<float> a{};
-      a.g = h->geom;
-      a.A = h->A;
-      a.npts = 2 * h->n + 1;
-      a.w = h->d.w32;
-      a.wdiff = h->d.w32 + AP;
-      a.wbase = h->d.w32 + 2 * AP;
-      a.states_per_block = h->st_states_per_block;
-      a.vec = h->st_vec;
-      a.axis = h->st_axis;
-      if (a.axis) {
-        std::copy(h->kw32.begin(), h->kw32.begin() + 2 * h->n + 1, a.kw_base);
-        std::copy(h->kw32.begin() + 2 * h->n + 1, h->kw32.end(), a.kw_axis);
-      }
-      a.V = static_cast<const float*>(V);
-      a.Vout = static_cast<float*>(Vout);
-      a.R = static_cast<const float*>(R);
-      a.term_bits = h->d.tbits;
-      a.gamma = static_cast<float>(h->gamma);
-      a.pi_in = pi_in;
-      a.pi_out = pi_out;
-      a.r_out = r_out;
-      a.vmax_bits = h->d.vmax;
-      a.res_slot = slot;
-      a.change_count = ctr;
-      a.nblocks = nblocks;
+      StencilArgs<float> a = stencil_args<float>(h, V, Vout, R, pi_in, pi_out, r_out, slot, ctr);
       launch_stencil<float>(a, mode, st);
     }
     return;
