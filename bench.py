@@ -100,6 +100,8 @@ def bench_grid(args, m):
     inst = I.grid4d(m, seed)
     S, A = inst.n_states, inst.n_actions
     model = B.Model(inst)
+    if args.one_pass:
+        B.cpmdp_set_option(model.h, B.CPMDP_OPT_MARCH, 0)
     eps = 1e-6
     V = torch.zeros(S, dtype=torch.float64, device="cuda")
     pi = torch.zeros(S, dtype=torch.int32, device="cuda")
@@ -397,6 +399,8 @@ def kernel_only(args):
         m = 32 if args.workload == "grid4d_32" else 96
         inst = I.grid4d(m, I.SEED_GRID4 if m == 32 else I.SEED_GRID4_LARGE)
     model = B.Model(inst)
+    if args.one_pass and model.path == B.CPMDP_PATH_STENCIL:
+        B.cpmdp_set_option(model.h, B.CPMDP_OPT_MARCH, 0)
     prec = {"fp32": B.CPMDP_FP32, "fp64": B.CPMDP_FP64, "bf16": B.CPMDP_BF16}[args.precision]
     dt = torch.float64 if prec == B.CPMDP_FP64 else torch.float32
     Va = torch.zeros(inst.n_states, dtype=dt, device="cuda")
@@ -424,6 +428,8 @@ def main():
     ap.add_argument("--kernel-only", action="store_true",
                     help="only the dominant kernel and a 1 GiB copy (counter passes)")
     ap.add_argument("--sweeps", type=int, default=20)
+    ap.add_argument("--one-pass", action="store_true",
+                    help="shift/identity grids: force the one-pass stencil form (no marching)")
     ap.add_argument("--train-instances", type=int, default=512)
     ap.add_argument("--train-steps", type=int, default=3000)
     ap.add_argument("--test-instances", type=int, default=16)

@@ -134,6 +134,18 @@ int cpmdp_bind(cpmdp_t* h, void* dev_workspace, size_t bytes,
 int cpmdp_set_stream(cpmdp_t* h, void* hip_stream);
 
 /*
+ * cpmdp_set_option -- execution options; results are the same with either
+ * setting (each state's arithmetic is unchanged).
+ *   CPMDP_OPT_MARCH (value 0 or 1, default 1): on the shift/identity path,
+ *     walk large grids plane by plane along dimension 0 with the dim-0
+ *     neighbours kept in registers (used when n >= 2, m_{n-1} % 4 == 0, at
+ *     least 8 planes of at least 65,536 states); 0 forces the one-pass form.
+ * Returns CPMDP_E_ARG for an unknown option or value.
+ */
+enum { CPMDP_OPT_MARCH = 1 };
+int cpmdp_set_option(cpmdp_t* h, int option, int64_t value);
+
+/*
  * cpmdp_backup -- one Bellman backup (Eq. 1) on the device.
  *   V_in, V_out : device [S]; FP64 for CPMDP_FP64, FP32 otherwise.  Must not
  *                 alias.

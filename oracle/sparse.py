@@ -138,3 +138,32 @@ def policy_iteration(inst, pi0=None, eps=1e-13, max_outer=10000, mats=None):
             return V, pi, it
         pi = pi_new
     return V, pi, max_outer
+
+
+def q_at_states(inst, V, states):
+    """Q[a, i] for the listed states only, from their own Def. 3 lists: for
+    state s with coordinates i, term t of action a reaches s' with
+    probability lambda_t prod_k T_k[i_k, j_k] for every combination of
+    non-zero entries of the rows T_k[i_k, :]; Q_a(s) = R(s) + gamma (1 -
+    tau(s)) sum over those successors of probability times V(s').  For spot
+    checks of instances too large for whole-matrix oracles."""
+    sizes = [int(m) for m in inst.sizes]
+    V = np.asarray(V, np.float64)
+    states = np.asarray(states, np.int64)
+    Q = np.empty((inst.n_actions, states.size))
+    for col, s in enumerate(states):
+        coords = np.unravel_index(int(s), sizes)      # row-major, Def. 2
+        cont = inst.gamma * (1.0 - float(inst.terminal[s]))
+        for a in range(inst.n_actions):
+            tot = 0.0
+            for t in inst.terms_of(a):
+                succ = np.zeros(1, np.int64)
+                prob = np.array([inst.lambdas[t]])
+                for k in range(inst.n_dims):
+                    row = inst.factor(t, k)[coords[k]]
+                    j = np.nonzero(row)[0]
+                    succ = (succ[:, None] * sizes[k] + j[None, :]).ravel()
+                    prob = (prob[:, None] * row[j][None, :]).ravel()
+                tot += float(prob @ V[succ])
+            Q[a, col] = inst.rewards[s] + cont * tot
+    return Q

@@ -51,6 +51,7 @@ _SIGS = {
     "cpmdp_workspace_bytes": (C.c_int, [_p, _szp]),
     "cpmdp_bind": (C.c_int, [_p, _p, C.c_size_t, _p]),
     "cpmdp_set_stream": (C.c_int, [_p, _p]),
+    "cpmdp_set_option": (C.c_int, [_p, C.c_int, C.c_int64]),
     "cpmdp_backup": (C.c_int, [_p, _p, _p, _p, _dp, C.c_int]),
     "cpmdp_policy_backup": (C.c_int, [_p, _p, _p, _p, _dp, C.c_int]),
     "cpmdp_value_iteration": (C.c_int, [_p, _p, _p, C.c_double, C.c_int64, C.c_int, _i64p,
@@ -160,6 +161,13 @@ def cpmdp_bind(h, workspace, stream=None):
 
 def cpmdp_set_stream(h, stream=None):
     return _check(lib.cpmdp_set_stream(h, _stream_ptr(stream)), h)
+
+
+CPMDP_OPT_MARCH = 1
+
+
+def cpmdp_set_option(h, option, value):
+    return _check(lib.cpmdp_set_option(h, int(option), int(value)), h)
 
 
 def cpmdp_backup(h, V_in, V_out, pi_out=None, residual=False, precision=CPMDP_FP64):

@@ -253,6 +253,12 @@ static StencilArgs<T> stencil_args(cpmdp_t* h, const void* V, void* Vout, const 
   a.res_slot = slot;
   a.change_count = ctr;
   a.nblocks = h->st_blocks;
+  if (h->st_march && h->opt_march) {
+    a.march = 1;
+    a.march_tiles = h->st_march_tiles;
+    a.march_seg = h->st_march_seg;
+    a.nblocks = h->st_march_blocks;
+  }
   return a;
 }
 
@@ -616,6 +622,18 @@ int cpmdp_create(cpmdp_t** out, int32_t n_dims, const int64_t* sizes, int32_t n_
     const int64_t per = (units + nb - 1) / nb;
     h->st_states_per_block = static_cast<int32_t>(per * chunk);
     h->st_blocks = static_cast<int32_t>((units + per - 1) / per);
+    // marching form when the planes of fixed i_0 are large (the dim-0
+    // neighbours then sit far apart in memory) and there are enough planes
+    const int64_t plane = S / sizes[0];
+    if (n_dims >= 2 && h->st_vec == 4 && plane >= kMarchMinPlane && sizes[0] >= 8) {
+      const int64_t tiles = (plane + 4 * kBlock - 1) / (4 * kBlock);
+      const int64_t nseg = std::max<int64_t>(1, std::min<int64_t>(kMaxBlocks / tiles, sizes[0] / 8));
+      const int64_t seg = (sizes[0] + nseg - 1) / nseg;
+      h->st_march = 1;
+      h->st_march_tiles = static_cast<int32_t>(tiles);
+      h->st_march_seg = static_cast<int32_t>(seg);
+      h->st_march_blocks = static_cast<int32_t>(tiles * ((sizes[0] + seg - 1) / seg));
+    }
   }
   if (stencil) {
     const int P = 2 * n_dims + 1;
@@ -673,6 +691,16 @@ int cpmdp_workspace_bytes(const cpmdp_t* h, size_t* bytes) {
   DevPtrs tmp;
   layout(h, &tmp, nullptr, bytes);
   return CPMDP_OK;
+}
+
+int cpmdp_set_option(cpmdp_t* h, int option, int64_t value) {
+  if (!h) return fail(nullptr, CPMDP_E_ARG, "handle is NULL");
+  if (option == CPMDP_OPT_MARCH) {
+    if (value != 0 && value != 1) return fail(h, CPMDP_E_ARG, "option value must be 0 or 1");
+    h->opt_march = value != 0;
+    return CPMDP_OK;
+  }
+  return fail(h, CPMDP_E_ARG, "unknown option");
 }
 
 int cpmdp_bind(cpmdp_t* h, void* ws, size_t bytes, void* stream) {

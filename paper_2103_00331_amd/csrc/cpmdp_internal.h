@@ -20,6 +20,7 @@ constexpr int kMaxBlocks = 2048;   // persistent grid: 256 CUs x 8 blocks
 constexpr int kBlock = 256;        // threads per block of the streaming kernels
 constexpr int kXcds = 8;           // MI355X: 8 XCDs, 32 CUs each
 constexpr double kTieRel = 1e-12;  // tie tolerance relative to max(1,||V||)
+constexpr int64_t kMarchMinPlane = 65536;  // plane size (states) from which the stencil marches
 
 // Kind of one factor T^{(k)}_{a,r}.
 enum FactorKind : uint8_t { F_IDENT = 0, F_SHIFT_P = 1, F_SHIFT_M = 2, F_DENSE = 3 };
@@ -75,6 +76,9 @@ struct StencilArgs {
   unsigned int* change_count;   // GREEDY with incumbent
   int32_t nblocks;
   int32_t vec;                  // states per thread along the last dim (1 or 4)
+  int32_t march;                // 1: marching form (needs n >= 2 and vec == 4)
+  int32_t march_tiles;          // plane tiles of 4 * kBlock states
+  int32_t march_seg;            // planes per block
   int32_t axis;                 // 1: axis-structured weights (see stencil.hip)
   // Weights by value: kernel arguments are scalar-loaded, so the
   // wave-uniform weights sit in SGPRs.

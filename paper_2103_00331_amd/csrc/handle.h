@@ -56,6 +56,9 @@ struct cpmdp {
   int32_t st_axis = 0;                   // stencil: axis-structured weights
   int32_t st_blocks = 1;                 // stencil: persistent grid size
   int32_t st_states_per_block = 256;
+  int32_t st_march = 0;                  // stencil: marching form (see stencil.hip)
+  int32_t st_march_tiles = 0, st_march_seg = 0, st_march_blocks = 0;
+  bool opt_march = true;                 // CPMDP_OPT_MARCH
   cpm::GridGeom geom{};
   cpm::ChainGeom cg64{}, cg32{};
   bool bound = false;

@@ -48,6 +48,97 @@ __global__ __launch_bounds__(kBlock) void stencil_kernel(StencilArgs<T> a) {
   if (MODE == MODE_GREEDY && a.change_count) block_sum_to_counter(changed, a.change_count);
 }
 
+// Marching form for large grids (n >= 2, m_last % 4 == 0): the state space
+// is a stack of m_0 planes (fixed i_0, S / m_0 contiguous states).  Block b
+// owns a tile of 4 * kBlock consecutive plane offsets and walks a segment of
+// planes in order, keeping the previous, current and next plane's values of
+// its tile in registers, so each value is read from HBM about once per sweep
+// (the one-launch form reads the dim-0 neighbours of every state again,
+// S / m_0 states away).  Neighbours along the other dims are loaded and hit
+// the caches (adjacent tiles run on the same XCD at the same time).
+template <typename T, int N, int MODE, bool AXIS>
+__global__ __launch_bounds__(kBlock) void stencil_march_kernel(StencilArgs<T> a) {
+  using V4 = typename VecOf<T, 4>::type;
+  constexpr int P = 2 * N + 1;
+  extern __shared__ unsigned char smem_raw[];
+  T* wsh = reinterpret_cast<T*>(smem_raw);
+  if (MODE == MODE_EVAL || MODE == MODE_RESID) {
+    const int nw = a.A * P;
+    for (int i = threadIdx.x; i < nw; i += blockDim.x) wsh[i] = a.w[i];
+    __syncthreads();
+  }
+  T tol = T(0);
+  if (MODE == MODE_GREEDY) tol = static_cast<T>(tie_tol(a.vmax_bits));
+  const StencilW<T> W{a.kw_base, a.kw_axis, a.w, wsh, a.A, a.gamma};
+  const StencilIO<T> io{a.V, a.Vout, a.R, a.term_bits, a.pi_in, a.pi_out, a.r_out};
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const int tile = lb % a.march_tiles, seg = lb / a.march_tiles;
+  const int PL = a.g.stride[0], m0 = a.g.size[0];
+  const int p = tile * (kBlock * 4) + threadIdx.x * 4;
+  const int i_begin = seg * a.march_seg;
+  const int i_end = min(i_begin + a.march_seg, m0);
+  T res = T(0);
+  double res_d = 0.0;
+  unsigned changed = 0;
+  if (p < PL && i_begin < i_end) {
+    int idx[N];
+    uint32_t rem = static_cast<uint32_t>(p);
+#pragma unroll
+    for (int k = N - 1; k > 0; --k) {
+      const uint32_t q = fdiv(rem, a.g.div[k]);
+      idx[k] = static_cast<int>(rem - q * static_cast<uint32_t>(a.g.size[k]));
+      rem = q;
+    }
+    idx[0] = 0;
+    const T* Vp = a.V + p;
+    V4 prev = *reinterpret_cast<const V4*>(Vp + max(i_begin - 1, 0) * PL);
+    V4 cur = *reinterpret_cast<const V4*>(Vp + i_begin * PL);
+    V4 nxt = *reinterpret_cast<const V4*>(Vp + min(i_begin + 1, m0 - 1) * PL);
+    for (int i0 = i_begin; i0 < i_end; ++i0) {
+      const V4 nn = *reinterpret_cast<const V4*>(Vp + min(i0 + 2, m0 - 1) * PL);   // prefetch
+      const int s = i0 * PL + p;
+      V4 plus4[N - 1], minus4[N - 1];
+      plus4[0] = nxt;
+      minus4[0] = prev;
+#pragma unroll
+      for (int k = 1; k < N - 1; ++k) {
+        const int st = a.g.stride[k];
+        plus4[k] = *reinterpret_cast<const V4*>(a.V + s + ((idx[k] < a.g.size[k] - 1) ? st : 0));
+        minus4[k] = *reinterpret_cast<const V4*>(a.V + s - ((idx[k] > 0) ? st : 0));
+      }
+      stencil_vec4<T, N, MODE, AXIS>(a.g, io, W, s, idx[N - 1], cur, plus4, minus4, tol, res,
+                                     res_d, changed);
+      prev = cur;
+      cur = nxt;
+      nxt = nn;
+    }
+  }
+  block_max_to_slot(MODE == MODE_RESID ? res_d : static_cast<double>(res), a.res_slot);
+  if (MODE == MODE_GREEDY && a.change_count) block_sum_to_counter(changed, a.change_count);
+}
+
+template <typename T, int N>
+static void launch_march_n(const StencilArgs<T>& a, int mode, hipStream_t st) {
+  if constexpr (N >= 2) {
+    const dim3 grid(a.nblocks), block(kBlock);
+    const size_t sh = (mode == MODE_EVAL || mode == MODE_RESID)
+                          ? sizeof(T) * static_cast<size_t>(a.A) * (2 * N + 1)
+                          : 0;
+    switch (mode) {
+      case MODE_MAX:
+        if (a.axis) hipLaunchKernelGGL((stencil_march_kernel<T, N, MODE_MAX, true>), grid, block, sh, st, a);
+        else hipLaunchKernelGGL((stencil_march_kernel<T, N, MODE_MAX, false>), grid, block, sh, st, a);
+        break;
+      case MODE_GREEDY:
+        if (a.axis) hipLaunchKernelGGL((stencil_march_kernel<T, N, MODE_GREEDY, true>), grid, block, sh, st, a);
+        else hipLaunchKernelGGL((stencil_march_kernel<T, N, MODE_GREEDY, false>), grid, block, sh, st, a);
+        break;
+      case MODE_EVAL: hipLaunchKernelGGL((stencil_march_kernel<T, N, MODE_EVAL, false>), grid, block, sh, st, a); break;
+      default: hipLaunchKernelGGL((stencil_march_kernel<T, N, MODE_RESID, false>), grid, block, sh, st, a); break;
+    }
+  }
+}
+
 template <typename T, int N, int VEC>
 static void launch_stencil_nv(const StencilArgs<T>& a, int mode, hipStream_t st) {
   const dim3 grid(a.nblocks), block(kBlock);
@@ -70,7 +161,8 @@ static void launch_stencil_nv(const StencilArgs<T>& a, int mode, hipStream_t st)
 
 template <typename T, int N>
 static void launch_stencil_n(const StencilArgs<T>& a, int mode, hipStream_t st) {
-  if (a.vec == 4) launch_stencil_nv<T, N, 4>(a, mode, st);
+  if (a.march) launch_march_n<T, N>(a, mode, st);
+  else if (a.vec == 4) launch_stencil_nv<T, N, 4>(a, mode, st);
   else launch_stencil_nv<T, N, 1>(a, mode, st);
 }
 

@@ -120,6 +120,70 @@ __device__ __forceinline__ void stencil_state(const StencilW<T>& W, const T (&nb
   if (MODE != MODE_RESID) res = tnanmax(res, fabs(out - c));
 }
 
+// States s .. s+3 along the last dimension (m_last % 4 == 0, s % 4 == 0)
+// given their values c4 and the vectors of their +-e_k neighbours for
+// k < n-1 (clamped): the last-dimension neighbours come from c4 and the two
+// adjacent scalars; then per-state work and stores.
+template <typename T, int N, int MODE, bool AXIS>
+__device__ __forceinline__ void stencil_vec4(const GridGeom& g, const StencilIO<T>& io,
+                                             const StencilW<T>& W, int s, int il,
+                                             const typename VecOf<T, 4>::type& c4,
+                                             const typename VecOf<T, 4>::type (&plus4)[N > 1 ? N - 1 : 1],
+                                             const typename VecOf<T, 4>::type (&minus4)[N > 1 ? N - 1 : 1],
+                                             T tol, T& res, double& res_d, unsigned& changed) {
+  using V4 = typename VecOf<T, 4>::type;
+  constexpr int P = 2 * N + 1;
+  const T left = io.V[s - ((il > 0) ? 1 : 0)];
+  const T right = io.V[s + ((il + 4 < g.size[N - 1]) ? 4 : 3)];
+  const V4 r4 = *reinterpret_cast<const V4*>(io.R + s);
+  const uint32_t tw = io.tbits[s >> 5] >> (s & 31);
+  int4 p4 = make_int4(-1, -1, -1, -1);
+  if (MODE != MODE_MAX && io.pi_in) p4 = *reinterpret_cast<const int4*>(io.pi_in + s);
+  T outv[4];
+  int pnv[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    T nb[P];
+    nb[0] = comp<T>(c4, q);
+#pragma unroll
+    for (int k = 0; k < N - 1; ++k) {
+      nb[1 + 2 * k] = comp<T>(plus4[k], q);
+      nb[2 + 2 * k] = comp<T>(minus4[k], q);
+    }
+    nb[1 + 2 * (N - 1)] = q < 3 ? comp<T>(c4, q + 1) : right;
+    nb[2 + 2 * (N - 1)] = q > 0 ? comp<T>(c4, q - 1) : left;
+    const int pold = q == 0 ? p4.x : (q == 1 ? p4.y : (q == 2 ? p4.z : p4.w));
+    pnv[q] = 0;
+    stencil_state<T, N, MODE, AXIS>(W, nb, comp<T>(r4, q), (tw >> q) & 1u, pold, tol, outv[q],
+                                    pnv[q], res, changed);
+  }
+  if (MODE == MODE_RESID) {
+    float4 r;
+    double d[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      d[q] = static_cast<double>(outv[q]) - static_cast<double>(comp<T>(c4, q));
+      res_d = nanmax(res_d, fabs(d[q]));
+    }
+    r.x = static_cast<float>(d[0]);
+    r.y = static_cast<float>(d[1]);
+    r.z = static_cast<float>(d[2]);
+    r.w = static_cast<float>(d[3]);
+    *reinterpret_cast<float4*>(io.r_out + s) = r;
+  } else {
+    if (io.Vout) {
+      V4 o;
+      o.x = outv[0];
+      o.y = outv[1];
+      o.z = outv[2];
+      o.w = outv[3];
+      *reinterpret_cast<V4*>(io.Vout + s) = o;
+    }
+    if (MODE == MODE_GREEDY && io.pi_out)
+      *reinterpret_cast<int4*>(io.pi_out + s) = make_int4(pnv[0], pnv[1], pnv[2], pnv[3]);
+  }
+}
+
 // The VEC states s .. s+VEC-1 (VEC = 4 needs m_last % 4 == 0 and s % 4 == 0):
 // loads, per-state work, stores.  Loads use clamped addresses (at the grid
 // edge the neighbour is the state itself), so every load is unconditional.
@@ -171,56 +235,8 @@ __device__ __forceinline__ void stencil_chunk(const GridGeom& g, const StencilIO
       plus4[k] = *reinterpret_cast<const V4*>(io.V + s + ((idx[k] < g.size[k] - 1) ? st : 0));
       minus4[k] = *reinterpret_cast<const V4*>(io.V + s - ((idx[k] > 0) ? st : 0));
     }
-    const int il = idx[N - 1];
-    const T left = io.V[s - ((il > 0) ? 1 : 0)];
-    const T right = io.V[s + ((il + 4 < g.size[N - 1]) ? 4 : 3)];
-    const V4 r4 = *reinterpret_cast<const V4*>(io.R + s);
-    const uint32_t tw = io.tbits[s >> 5] >> (s & 31);
-    int4 p4 = make_int4(-1, -1, -1, -1);
-    if (MODE != MODE_MAX && io.pi_in) p4 = *reinterpret_cast<const int4*>(io.pi_in + s);
-    T outv[4];
-    int pnv[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      T nb[P];
-      nb[0] = comp<T>(c4, q);
-#pragma unroll
-      for (int k = 0; k < N - 1; ++k) {
-        nb[1 + 2 * k] = comp<T>(plus4[k], q);
-        nb[2 + 2 * k] = comp<T>(minus4[k], q);
-      }
-      nb[1 + 2 * (N - 1)] = q < 3 ? comp<T>(c4, q + 1) : right;
-      nb[2 + 2 * (N - 1)] = q > 0 ? comp<T>(c4, q - 1) : left;
-      const int pold = q == 0 ? p4.x : (q == 1 ? p4.y : (q == 2 ? p4.z : p4.w));
-      pnv[q] = 0;
-      stencil_state<T, N, MODE, AXIS>(W, nb, comp<T>(r4, q), (tw >> q) & 1u, pold, tol,
-                                      outv[q], pnv[q], res, changed);
-    }
-    if (MODE == MODE_RESID) {
-      float4 r;
-      double d[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        d[q] = static_cast<double>(outv[q]) - static_cast<double>(comp<T>(c4, q));
-        res_d = nanmax(res_d, fabs(d[q]));
-      }
-      r.x = static_cast<float>(d[0]);
-      r.y = static_cast<float>(d[1]);
-      r.z = static_cast<float>(d[2]);
-      r.w = static_cast<float>(d[3]);
-      *reinterpret_cast<float4*>(io.r_out + s) = r;
-    } else {
-      if (io.Vout) {
-        V4 o;
-        o.x = outv[0];
-        o.y = outv[1];
-        o.z = outv[2];
-        o.w = outv[3];
-        *reinterpret_cast<V4*>(io.Vout + s) = o;
-      }
-      if (MODE == MODE_GREEDY && io.pi_out)
-        *reinterpret_cast<int4*>(io.pi_out + s) = make_int4(pnv[0], pnv[1], pnv[2], pnv[3]);
-    }
+    stencil_vec4<T, N, MODE, AXIS>(g, io, W, s, idx[N - 1], c4, plus4, minus4, tol, res, res_d,
+                                   changed);
   }
 }
 

@@ -212,3 +212,90 @@ def test_grid4d_32_fp32_solve_certified_by_oracle(B, grid4d, method):
     assert np.array_equal(pi, oracle.greedy(Q, V)) or method == "pi"
     compare_policy(pi, Q, 1e-9)
     model.close()
+
+
+MARCH_CASES = {
+    # two segments of 10 planes, ragged last plane tile (76,032 = 74.25 x 1024)
+    "march_20x64x33x36": lambda: I.grid_small([20, 64, 33, 36], slip=0.1, gamma=0.99, seed=28),
+    # n = 3, three segments
+    "march_24x300x224": lambda: I.grid_small([24, 300, 224], slip=0.2, gamma=0.95, seed=29),
+    # n = 5, one segment of 8 planes
+    "march_8x16x24x16x12": lambda: I.grid_small([8, 16, 24, 16, 12], slip=0.1, gamma=0.9,
+                                                seed=30),
+}
+
+
+def _march_sample(inst, rng, n_random=96):
+    """States at plane / segment / tile boundaries and grid corners, plus
+    random ones."""
+    sizes = [int(m) for m in inst.sizes]
+    plane = inst.n_states // sizes[0]
+    picks = [0, inst.n_states - 1, plane - 1, plane, 2 * plane - 1]
+    for i0 in (0, 1, sizes[0] // 2 - 1, sizes[0] // 2, sizes[0] - 2, sizes[0] - 1):
+        for off in (0, 1, 3, 4, 1023, 1024, plane - 4, plane - 1):
+            picks.append(i0 * plane + min(off, plane - 1))
+    picks += list(rng.integers(0, inst.n_states, n_random))
+    return np.unique(np.asarray(picks, np.int64))
+
+
+def _backup_forms(B, model, V, prec, pi_in=None):
+    """One backup with the marching form on and off: (V', pi) per form."""
+    out = []
+    for march in (1, 0):
+        B.cpmdp_set_option(model.h, B.CPMDP_OPT_MARCH, march)
+        if pi_in is None:
+            out.append(_backup(B, model, V, prec))
+        else:
+            Vin = torch.as_tensor(V, dtype=_dt(prec), device="cuda")
+            Vout = torch.empty_like(Vin)
+            B.cpmdp_policy_backup(model.h, Vin, Vout, torch.as_tensor(pi_in, device="cuda"),
+                                  residual=False, precision=prec)
+            torch.cuda.synchronize()
+            out.append((Vout.cpu().numpy().astype(np.float64), None, None))
+    B.cpmdp_set_option(model.h, B.CPMDP_OPT_MARCH, 1)
+    return out
+
+
+@pytest.mark.parametrize("name", list(MARCH_CASES))
+@pytest.mark.parametrize("prec", [0, 1])
+def test_march_backup_matches_oracle(B, name, prec):
+    """Marching form: sampled states against the per-state Def. 3 oracle,
+    every state equal to the one-pass form (same arithmetic per state)."""
+    inst = MARCH_CASES[name]()
+    log(f"[stencil march] {name} prec={prec}")
+    model = B.Model(inst)
+    V = I.seeded_values(inst.n_states, 31, scale=2.0)
+    if prec == 1:
+        V = V.astype(np.float32).astype(np.float64)
+    (Vm, pim, _), (Vo, pio, _) = _backup_forms(B, model, V, prec)
+    assert np.array_equal(Vm, Vo) and np.array_equal(pim, pio)
+    states = _march_sample(inst, np.random.default_rng(32))
+    Q = oracle.sparse.q_at_states(inst, V, states)
+    tol = 1e-13 * max(1.0, np.abs(V).max()) if prec == 0 else tol_for(1, Q.max(0))
+    assert_close(Vm[states], Q.max(0), tol, "sampled V'")
+    compare_policy(pim[states], Q, tol)
+    # fixed-policy backup (evaluation sweep) in both forms
+    pi = np.random.default_rng(33).integers(0, inst.n_actions, inst.n_states).astype(np.int32)
+    (Em, _, _), (Eo, _, _) = _backup_forms(B, model, V, prec, pi_in=pi)
+    assert np.array_equal(Em, Eo)
+    ref = Q[pi[states], np.arange(states.size)]
+    assert_close(Em[states], ref, tol, "sampled P_pi V")
+    model.close()
+
+
+def test_march_grid4d_96_backup(B):
+    """96^4 (84,934,656 states, the HBM-resident workload): one FP32 backup in
+    the marching form, equal to the one-pass form everywhere and to the
+    oracle on sampled states."""
+    inst = I.grid4d(96, I.SEED_GRID4_LARGE)
+    log("[stencil 96^4] march vs one-pass, fp32")
+    model = B.Model(inst)
+    V = I.seeded_values(inst.n_states, 34, scale=5.0).astype(np.float32).astype(np.float64)
+    (Vm, pim, _), (Vo, pio, _) = _backup_forms(B, model, V, 1)
+    assert np.array_equal(Vm, Vo) and np.array_equal(pim, pio)
+    states = _march_sample(inst, np.random.default_rng(35), n_random=32)
+    Q = oracle.sparse.q_at_states(inst, V, states)
+    tol = tol_for(1, Q.max(0))
+    assert_close(Vm[states], Q.max(0), tol, "sampled V'")
+    compare_policy(pim[states], Q, tol)
+    model.close()

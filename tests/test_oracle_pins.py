@@ -224,6 +224,22 @@ def test_one_backup_tiers_agree(maker):
     np.testing.assert_allclose(Qt, Qd, atol=1e-14)
 
 
+@pytest.mark.parametrize("maker", [
+    lambda: I.grid_small([3, 4, 2], seed=11),
+    lambda: I.random_dense([2, 3, 2], 3, 3, seed=12, n_terminal=2),
+])
+def test_per_state_q_matches_dense(maker):
+    """The per-state spot-check functions (structured contraction with one row
+    of every factor, and the state's own Def. 3 list) against O1's
+    reconstructed dense P_a on every state."""
+    inst = maker()
+    V = I.seeded_values(inst.n_states, 14)
+    Qd = dense.q_values(inst, dense.transition_matrices(inst), V)
+    states = np.arange(inst.n_states)
+    np.testing.assert_allclose(structured.q_at_states(inst, V, states), Qd, atol=1e-14)
+    np.testing.assert_allclose(sparse.q_at_states(inst, V, states), Qd, atol=1e-14)
+
+
 def test_greedy_rule_ties_and_incumbent():
     Q = np.array([[1.0, 2.0, 3.0], [1.0, 2.5, 3.0 - 1e-13], [0.5, 2.5, 2.0]])
     V = np.zeros(3)
