@@ -68,17 +68,23 @@ constexpr int64_t kLdsBytes = 160 * 1024;
 // LDS bytes the chain kernels of geometry g request per workgroup.
 int64_t chain_lds_bytes(const ChainGeom& g, size_t b) {
   const int64_t TE = static_cast<int64_t>(g.Rr) * g.CT;
-  const int64_t p2 = static_cast<int64_t>(b) * (TE + (TE >> 5) + 1) + 1024 + 256;
-  const int64_t p1 = (g.n1 < g.n) ? static_cast<int64_t>(b) *
-                                        (2 * (g.C + (g.C >> 5) + 1) + 2) + 256
-                                  : 0;
+  // pass 2: the tile, plus (FP32 chains on the matrix cores) the row-group
+  // factors of one term staged as FP32 or as BF16 hi + lo
+  const int64_t rows_len = (g.n1 < g.n) ? g.fac_off[g.n1] : g.term_stride;
+  const int64_t p2 = static_cast<int64_t>(b) * (TE + (TE >> 5) + 2) + (b == 4 ? 4 * rows_len : 0) +
+                     1024 + 256;
+  const int64_t cols_len = g.term_stride - ((g.n1 < g.n) ? g.fac_off[g.n1] : g.term_stride);
+  const int64_t p1 = (g.n1 == g.n) ? 0
+                     : (g.r1 > 0) ? static_cast<int64_t>(b) * g.r1 * (g.C + (g.C >> 5) + 1) +
+                                        4 * cols_len + 512
+                                  : static_cast<int64_t>(b) * (2 * (g.C + (g.C >> 5) + 1) + 2) + 256;
   return std::max(p1, p2);
 }
 
 // Split the dims into a row group [0, n1) and a column group [n1, n) so that
 // a pass-1 row slab (two copies) and a pass-2 tile (rows x CT) fit in LDS;
 // prefer balanced groups.  te_max also bounds the per-thread register state
-// of pass 2 (16384 / 512 threads = 32 elements; FP64: 16).
+// of pass 2 (16384 / 1024 threads = 16 elements; FP64: 8).
 static bool choose_split(const std::vector<int64_t>& sizes, int64_t S, size_t b,
                          ChainGeom& g) {
   const int n = static_cast<int>(sizes.size());
@@ -139,6 +145,29 @@ static bool choose_split(const std::vector<int64_t>& sizes, int64_t S, size_t b,
     else g.mmax_col = std::max<int32_t>(g.mmax_col, g.size[k]);
   }
   g.w_term_stride = (best_n1 == n) ? 0 : static_cast<int64_t>(g.ntiles) * g.Rr * g.CT;
+  int64_t inner = g.CT;               // pass 2: X is [row dims][CT]
+  for (int k = best_n1 - 1; k >= 0; --k) {
+    g.idiv[k] = make_fastdiv(static_cast<uint32_t>(inner));
+    inner *= sizes[k];
+  }
+  inner = 1;                          // pass 1: the slab is [column dims]
+  for (int k = n - 1; k >= best_n1; --k) {
+    g.idiv[k] = make_fastdiv(static_cast<uint32_t>(inner));
+    inner *= sizes[k];
+  }
+  // pass 1 with one row per wave: as many rows (<= 8, a power of two) as
+  // fit in LDS, the row kept in registers (at most 64 values per lane)
+  g.r1 = 0;
+  if (best_n1 < n && g.C <= 64 * 64) {
+    const int64_t cols_len = g.term_stride - g.fac_off[best_n1];
+    for (int r1 = 8; r1 >= 2; r1 /= 2) {
+      const int64_t lds = static_cast<int64_t>(b) * r1 * (g.C + (g.C >> 5) + 1) + 4 * cols_len + 512;
+      if (lds <= kLdsBytes && r1 <= g.Rr) {
+        g.r1 = r1;
+        break;
+      }
+    }
+  }
   return true;
 }
 

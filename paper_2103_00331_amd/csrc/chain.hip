@@ -29,38 +29,43 @@ namespace cpm {
 
 __device__ __forceinline__ int lpad(int i) { return i + (i >> 5); }
 
+// Order the LDS accesses of one wave across the lanes (a wave-local mode
+// product reads values that other lanes of the same wave wrote).
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // In-place mode product on an LDS array viewed as [outer][m][inner]:
-// X[o, i, in] <- sum_j Tk[i, j] X[o, j, in].
-template <typename T, int MMAX>
-__device__ __forceinline__ void mode_product_lds(T* X, int outer, int m, int inner,
-                                                 const T* __restrict__ Tk) {
+// X[o, i, in] <- sum_j Tk[i, j] X[o, j, in].  Each thread owns whole fibers
+// (o, in), so in-place needs no barrier between its reads and writes.
+// WAVE: the calling wave alone works on X (else the whole block).
+template <typename T, int MMAX, bool WAVE>
+__device__ __forceinline__ void mode_product_lds(const T* Xs, T* X, int outer, int m, int inner,
+                                                 FastDiv dv, const T* __restrict__ Tk) {
   const int F = outer * inner;
-  for (int f0 = 0; f0 < F; f0 += blockDim.x) {
-    const int f = f0 + threadIdx.x;
-    const bool act = f < F;
+  const int gid = WAVE ? (threadIdx.x & 63) : threadIdx.x;
+  const int gsize = WAVE ? 64 : blockDim.x;
+  for (int f = gid; f < F; f += gsize) {
+    const int o = static_cast<int>(fdiv(static_cast<uint32_t>(f), dv));
+    const int in = f - o * inner;
+    const int base = o * m * inner + in;
     T x[MMAX];
-    int base = 0;
-    if (act) {
-      const int o = f / inner;
-      const int in = f - o * inner;
-      base = o * m * inner + in;
+#pragma unroll
+    for (int j = 0; j < MMAX; ++j)
+      if (j < m) x[j] = Xs[lpad(base + j * inner)];
+    for (int i = 0; i < m; ++i) {
+      const T* Ti = Tk + i * m;
+      T acc = T(0);
 #pragma unroll
       for (int j = 0; j < MMAX; ++j)
-        if (j < m) x[j] = X[lpad(base + j * inner)];
+        if (j < m) acc = fma(Ti[j], x[j], acc);
+      X[lpad(base + i * inner)] = acc;
     }
-    __syncthreads();
-    if (act) {
-      for (int i = 0; i < m; ++i) {
-        const T* Ti = Tk + i * m;
-        T acc = T(0);
-#pragma unroll
-        for (int j = 0; j < MMAX; ++j)
-          if (j < m) acc = fma(Ti[j], x[j], acc);
-        X[lpad(base + i * inner)] = acc;
-      }
-    }
-    __syncthreads();
   }
+  if (WAVE) wave_lds_fence();
+  else __syncthreads();
 }
 
 // ------------------------------------------------------------ MFMA path
@@ -83,18 +88,43 @@ typedef short s4v __attribute__((ext_vector_type(4)));
 
 enum { MM_VALU = 0, MM_F32 = 1, MM_BF16 = 2 };
 
-__device__ __forceinline__ uint32_t bf16_bits(float x) {   // round to nearest even
-  const uint32_t u = __float_as_uint(x);
-  return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+// BF16 hi + lo split of four FP32 values (hardware round to nearest even).
+__device__ __forceinline__ void split_bf16(const float (&x)[4], s4v& hi, s4v& lo) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const __bf16 h = static_cast<__bf16>(x[r]);
+    hi[r] = __builtin_bit_cast(short, h);
+    lo[r] = __builtin_bit_cast(short, static_cast<__bf16>(x[r] - static_cast<float>(h)));
+  }
 }
-__device__ __forceinline__ float bf16_value(uint32_t b) { return __uint_as_float(b << 16); }
 
+// One 16 x 16 x 16 product: rows k of the B operand held by this lane are
+// x[0..3] (fp32: k = 4q + g for x[q]; bf16: k = 4g + r for x[r]).
 template <int MM>
-__device__ __forceinline__ void mode_product_mfma(float* X, int outer, int m, int inner,
+__device__ __forceinline__ f4v mfma_block(const float (&x)[4], const float (&a32)[4], s4v ahi,
+                                          s4v alo) {
+  f4v acc = {0.f, 0.f, 0.f, 0.f};
+  if (MM == MM_F32) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a32[q], x[q], acc, 0, 0, 0);
+  } else {
+    s4v bhi, blo;
+    split_bf16(x, bhi, blo);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo, bhi, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, blo, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, bhi, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+template <int MM, bool WAVE>
+__device__ __forceinline__ void mode_product_mfma(const float* Xs, float* X, int outer, int m,
+                                                  int inner, FastDiv dv,
                                                   const float* __restrict__ Tk,
                                                   const uint16_t* __restrict__ Th,
                                                   const uint16_t* __restrict__ Tl) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = WAVE ? 0 : (threadIdx.x >> 6), nw = WAVE ? 1 : (blockDim.x >> 6);
   const int c = lane & 15, g = lane >> 4;
   const int F = outer * inner;
   const int nblk = (F + 15) >> 4;
@@ -115,58 +145,73 @@ __device__ __forceinline__ void mode_product_mfma(float* X, int outer, int m, in
       alo[r] = in ? static_cast<short>(Tl[c * m + k]) : static_cast<short>(0);
     }
   }
-  for (int b = wave; b < nblk; b += nw) {
+  // row of the B operand held in x[j] / row of the result in acc[j]
+  auto rd_row = [&](int j) { return MM == MM_F32 ? 4 * j + g : 4 * g + j; };
+  auto block_base = [&](int b) {
     const int f = b * 16 + c;
-    const bool ok = f < F;
-    int base = 0;
-    if (ok) {
-      const int o = f / inner;
-      base = o * m * inner + (f - o * inner);
-    }
-    f4v acc = {0.f, 0.f, 0.f, 0.f};
-    if (MM == MM_F32) {
+    const int o = static_cast<int>(fdiv(static_cast<uint32_t>(f), dv));
+    return o * m * inner + (f - o * inner);
+  };
+  if (m == 16 && (F & 15) == 0) {
+    // full blocks: unguarded loads, two blocks per step so that the LDS
+    // reads of both are in flight before the first matrix product
+    for (int b0 = wave; b0 < nblk; b0 += 2 * nw) {
+      const bool two = b0 + nw < nblk;                 // wave-uniform
+      const int base0 = block_base(b0);
+      const int base1 = block_base(two ? b0 + nw : b0);
+      float x0[4], x1[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int k = 4 * q + g;
-        const float bv = (ok && k < m) ? X[lpad(base + k * inner)] : 0.f;
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a32[q], bv, acc, 0, 0, 0);
+      for (int j = 0; j < 4; ++j) {
+        x0[j] = Xs[lpad(base0 + rd_row(j) * inner)];
+        x1[j] = Xs[lpad(base1 + rd_row(j) * inner)];
       }
-    } else {
-      s4v bhi, blo;
+      const f4v d0 = mfma_block<MM>(x0, a32, ahi, alo);
+      const f4v d1 = mfma_block<MM>(x1, a32, ahi, alo);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) X[lpad(base0 + (4 * g + r) * inner)] = d0[r];
+      if (two) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) X[lpad(base1 + (4 * g + r) * inner)] = d1[r];
+      }
+    }
+  } else {
+    for (int b = wave; b < nblk; b += nw) {
+      const bool ok = b * 16 + c < F;
+      const int base = ok ? block_base(b) : 0;
+      float x[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = rd_row(j);
+        x[j] = (ok && k < m) ? Xs[lpad(base + k * inner)] : 0.f;
+      }
+      const f4v d = mfma_block<MM>(x, a32, ahi, alo);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int k = 4 * g + r;
-        const float x = (ok && k < m) ? X[lpad(base + k * inner)] : 0.f;
-        const uint32_t h = bf16_bits(x);
-        bhi[r] = static_cast<short>(h);
-        blo[r] = static_cast<short>(bf16_bits(x - bf16_value(h)));
+        const int i = 4 * g + r;
+        if (ok && i < m) X[lpad(base + i * inner)] = d[r];
       }
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo, bhi, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, blo, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, bhi, acc, 0, 0, 0);
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int i = 4 * g + r;
-      if (ok && i < m) X[lpad(base + i * inner)] = acc[r];
     }
   }
-  __syncthreads();
+  if (WAVE) wave_lds_fence();
+  else __syncthreads();
 }
 
-// Mode product of one term's factor along one mode, on the chosen unit.
-template <typename T, int MMAX, int MM>
-__device__ __forceinline__ void mode_product(T* X, int outer, int m, int inner, const T* Tk,
-                                             const uint16_t* Th, const uint16_t* Tl) {
+// Xs: input (may equal X, the output; both viewed as [outer][m][inner]).
+template <typename T, int MMAX, int MM, bool WAVE = false>
+__device__ __forceinline__ void mode_product(const T* Xs, T* X, int outer, int m, int inner,
+                                             FastDiv dv, const T* Tk, const uint16_t* Th,
+                                             const uint16_t* Tl) {
   if constexpr (MM == MM_VALU) {
-    mode_product_lds<T, MMAX>(X, outer, m, inner, Tk);
+    mode_product_lds<T, MMAX, WAVE>(Xs, X, outer, m, inner, dv, Tk);
   } else {
-    mode_product_mfma<MM>(X, outer, m, inner, Tk, Th, Tl);
+    mode_product_mfma<MM, WAVE>(Xs, X, outer, m, inner, dv, Tk, Th, Tl);
   }
 }
 
 constexpr int kPass1Block = 256;
-constexpr int kPass2Block = 512;
+constexpr int kPass1RowsBlock = 512;   // at most 8 rows (waves) per block
+constexpr int kPass2Block = 1024;
+constexpr int kStageRegs = 2;   // staged factor values per thread: n1 * 16^2 <= 2 * 1024
 
 template <typename T, int MMAX, int MM>
 __global__ __launch_bounds__(kPass1Block) void chain_pass1(ChainArgs<T> a) {
@@ -181,35 +226,187 @@ __global__ __launch_bounds__(kPass1Block) void chain_pass1(ChainArgs<T> a) {
   __syncthreads();
   const int n = a.g.n;
   for (int t = 0; t < a.nterms; ++t) {
-    for (int c = threadIdx.x; c < C; c += blockDim.x) ws[lpad(c)] = vs[lpad(c)];
-    __syncthreads();
+    // the first mode product reads the slab vs and writes ws, later ones
+    // work in place on ws
+    const T* src = vs;
     int outer = 1, inner = C;
     for (int k = a.g.n1; k < n; ++k) {
       const int m = a.g.size[k];
       inner /= m;
       if (a.kinds[t * n + k] != F_IDENT) {
         const int64_t fo = static_cast<int64_t>(t) * a.g.term_stride + a.g.fac_off[k];
-        mode_product<T, MMAX, MM>(ws, outer, m, inner, a.fac + fo, a.facbf + fo, a.facbf_lo + fo);
+        mode_product<T, MMAX, MM>(src, ws, outer, m, inner, a.g.idiv[k], a.fac + fo,
+                                  a.facbf + fo, a.facbf_lo + fo);
+        src = ws;
       }
       outer *= m;
     }
     T* Wt = a.W + static_cast<int64_t>(t) * a.g.w_term_stride;
     for (int c = threadIdx.x; c < C; c += blockDim.x) {
       const int tile = c >> a.g.ct_shift, clo = c & (a.g.CT - 1);
-      Wt[(static_cast<int64_t>(tile) * a.g.Rr + r) * a.g.CT + clo] = ws[lpad(c)];
+      Wt[(static_cast<int64_t>(tile) * a.g.Rr + r) * a.g.CT + clo] = src[lpad(c)];
     }
     __syncthreads();
   }
 }
 
+// Pass 1, one row per wave (R1 = blockDim / 64 consecutive rows per block).
+// Each wave keeps its row of V in registers (PV values per lane) and, per
+// term, writes it to its own LDS slab, runs the column-group mode products
+// there without block barriers, and then the block writes the R1 slabs out
+// as one contiguous run of R1 * CT values per tile of the intermediate
+// (whole cache lines, where one row per block writes CT values per tile).
+// The column-group factors of the term are staged in LDS for the matrix
+// cores.
+template <typename T, int MMAX, int MM, int PV>
+__global__ __launch_bounds__(kPass1RowsBlock) void chain_pass1_rows(ChainArgs<T> a) {
+  extern __shared__ unsigned char smem_raw[];
+  const int C = a.g.C, n = a.g.n, n1 = a.g.n1, Rr = a.g.Rr;
+  const int R1 = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int slab = lpad(C) + 1;
+  T* base = reinterpret_cast<T*>(smem_raw);
+  T* ws = base + w * slab;
+  constexpr bool STAGE = (MM != MM_VALU);
+  const int cols_off = a.g.fac_off[n1];
+  const int cols_len = a.g.term_stride - cols_off;
+  float* Fs = reinterpret_cast<float*>(base + R1 * slab);
+  uint16_t* Fh = reinterpret_cast<uint16_t*>(Fs);
+  uint16_t* Fl = Fh + cols_len;
+  const int r0 = xcd_block(blockIdx.x, gridDim.x) * R1;
+  const int r = r0 + w;
+  const bool row_ok = r < Rr;
+  const T cs = a.shift_keys ? static_cast<T>(midrange(a.shift_keys)) : T(0);
+  T vr[PV];
+  {
+    const T* Vrow = a.V + static_cast<int64_t>(row_ok ? r : 0) * C;
+#pragma unroll
+    for (int p = 0; p < PV; ++p) {
+      const int c = lane + p * 64;
+      vr[p] = (c < C) ? Vrow[c] - cs : T(0);
+    }
+  }
+  const int chunk_shift = a.g.ct_shift + (31 - __builtin_clz(R1));   // log2(R1 * CT)
+  const int total = a.g.ntiles << chunk_shift;
+  // factors of the next term, loaded before the write-out of the current one
+  // (cols_len <= 8 * 16^2 = 4 * kPass1RowsBlock)
+  float nf[4];
+  uint16_t nh[4], nl[4];
+  auto load_fac = [&](int t) {
+    if constexpr (STAGE) {
+      const int64_t fb = static_cast<int64_t>(t) * a.g.term_stride + cols_off;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int i = threadIdx.x + j * blockDim.x;
+        if (i < cols_len) {
+          if (MM == MM_F32) {
+            nf[j] = a.fac[fb + i];
+          } else {
+            nh[j] = a.facbf[fb + i];
+            nl[j] = a.facbf_lo[fb + i];
+          }
+        }
+      }
+    }
+  };
+  load_fac(0);
+  for (int t = 0; t < a.nterms; ++t) {
+    if constexpr (STAGE) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int i = threadIdx.x + j * blockDim.x;
+        if (i < cols_len) {
+          if (MM == MM_F32) {
+            Fs[i] = nf[j];
+          } else {
+            Fh[i] = nh[j];
+            Fl[i] = nl[j];
+          }
+        }
+      }
+    }
+    __syncthreads();   // staged factors visible; the slabs of the last term written out
+#pragma unroll
+    for (int p = 0; p < PV; ++p) {
+      const int c = lane + p * 64;
+      if (c < C) ws[lpad(c)] = vr[p];
+    }
+    wave_lds_fence();
+    int outer = 1, inner = C;
+    for (int k = n1; k < n; ++k) {
+      const int m = a.g.size[k];
+      inner /= m;
+      if (a.kinds[t * n + k] != F_IDENT) {
+        if constexpr (STAGE) {
+          const int fo = a.g.fac_off[k] - cols_off;
+          mode_product<T, MMAX, MM, true>(ws, ws, outer, m, inner, a.g.idiv[k], Fs + fo, Fh + fo,
+                                          Fl + fo);
+        } else {
+          const int64_t fo = static_cast<int64_t>(t) * a.g.term_stride + a.g.fac_off[k];
+          mode_product<T, MMAX, MM, true>(ws, ws, outer, m, inner, a.g.idiv[k], a.fac + fo,
+                                          a.facbf + fo, a.facbf_lo + fo);
+        }
+      }
+      outer *= m;
+    }
+    __syncthreads();   // all slabs of this term complete
+    if (t + 1 < a.nterms) load_fac(t + 1);
+    // W_t[tile][r0 .. r0 + R1)[0 .. CT): q runs over whole chunks of R1 * CT
+    T* Wt = a.W + static_cast<int64_t>(t) * a.g.w_term_stride;
+    for (int q = threadIdx.x; q < total; q += blockDim.x) {
+      const int tile = q >> chunk_shift;
+      const int rem = q & ((1 << chunk_shift) - 1);
+      const int i = rem >> a.g.ct_shift, clo = rem & (a.g.CT - 1);
+      const int c = tile * a.g.CT + clo;
+      if (r0 + i < Rr && c < C)
+        Wt[(static_cast<int64_t>(tile) * Rr + r0) * a.g.CT + rem] = base[i * slab + lpad(c)];
+    }
+  }
+}
+
+// EPT consecutive values from p (16-byte aligned) into registers.
+template <typename T, int EPT>
+__device__ __forceinline__ void load_run(const T* __restrict__ p, T (&d)[EPT]) {
+  constexpr int VW = 16 / sizeof(T);
+  if constexpr (EPT % VW == 0) {
+    using V = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+#pragma unroll
+    for (int q = 0; q < EPT / VW; ++q) {
+      const V v = reinterpret_cast<const V*>(p)[q];
+      const T* pv = reinterpret_cast<const T*>(&v);
+#pragma unroll
+      for (int i = 0; i < VW; ++i) d[q * VW + i] = pv[i];
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) d[j] = p[j];
+  }
+}
+
+// Thread i owns the EPT consecutive tile elements e0 = i * EPT ...; EPT
+// divides 32, so their padded LDS indices are lpad(e0) + j.
 template <typename T, int MMAX, int MODE, int EPT, int MM>
 __global__ __launch_bounds__(kPass2Block) void chain_pass2(ChainArgs<T> a) {
+  static_assert(32 % EPT == 0, "EPT must divide 32");
   extern __shared__ unsigned char smem_raw[];
   T* X = reinterpret_cast<T*>(smem_raw);
   __shared__ int act_used[kMaxActions + 1];
   const int tile = xcd_block(blockIdx.x, gridDim.x);
   const int CT = a.g.CT, C = a.g.C, n1 = a.g.n1, n = a.g.n;
   const int TE = a.g.Rr * CT;
+  const int e0 = threadIdx.x * EPT;
+  T* Xe = X + lpad(e0);
+  const bool full = e0 + EPT <= TE;                   // all EPT elements in the tile
+  // Matrix-core units read the row-group factors of the current term from
+  // LDS; they are fetched with the next tile, so no global load of the mode
+  // products waits behind the tile prefetch.
+  constexpr bool STAGE = (MM != MM_VALU);
+  const int rows_len = (n1 < n) ? a.g.fac_off[n1] : a.g.term_stride;
+  float* Fs = reinterpret_cast<float*>(X + lpad(TE) + 1);
+  uint16_t* Fh = reinterpret_cast<uint16_t*>(Fs);
+  uint16_t* Fl = Fh + rows_len;
+  float nf[kStageRegs];
+  uint16_t nh[kStageRegs], nl[kStageRegs];
 
   T acc[EPT], best[EPT], qold[EPT];
   int bi[EPT], pold[EPT];
@@ -243,7 +440,7 @@ __global__ __launch_bounds__(kPass2Block) void chain_pass2(ChainArgs<T> a) {
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
       bool v;
-      const int s = state_of(threadIdx.x + j * kPass2Block, v);
+      const int s = state_of(e0 + j, v);
       if (v) {
         pold[j] = a.pi_in[s];
         if (MODE == MODE_EVAL || MODE == MODE_RESID) act_used[pold[j]] = 1;
@@ -252,37 +449,116 @@ __global__ __launch_bounds__(kPass2Block) void chain_pass2(ChainArgs<T> a) {
   }
   if (MODE == MODE_EVAL || MODE == MODE_RESID) __syncthreads();
 
+  // Terms are visited action by action; the tile of the next term is loaded
+  // into registers while the current one is in the mode products, so the
+  // global loads overlap the LDS / matrix-core work.
   const int64_t tile_off = static_cast<int64_t>(tile) * TE;
-  for (int act = 0; act < a.A; ++act) {
-    if ((MODE == MODE_EVAL || MODE == MODE_RESID) && !act_used[act]) continue;
-    if (MODE == MODE_MAX || MODE == MODE_GREEDY) {
+  const bool vec_ok = (TE % (16 / sizeof(T)) == 0) &&
+                      (reinterpret_cast<uintptr_t>(a.W) % 16 == 0) &&
+                      ((a.g.w_term_stride * sizeof(T)) % 16 == 0);
+  const bool skip_unused = (MODE == MODE_EVAL || MODE == MODE_RESID);
+  auto used_from = [&](int act) {
+    while (skip_unused && act < a.A && !act_used[act]) ++act;
+    return act;
+  };
+  T nx[EPT];
+  auto load_tile = [&](int t) {
+    const T* Wt = a.W + static_cast<int64_t>(t) * a.g.w_term_stride + tile_off + e0;
+    if (full && vec_ok) {
+      load_run<T, EPT>(Wt, nx);
+    } else {
 #pragma unroll
-      for (int j = 0; j < EPT; ++j) acc[j] = T(0);
+      for (int j = 0; j < EPT; ++j) nx[j] = (e0 + j < TE) ? Wt[j] : T(0);
     }
-    for (int t = a.term_start[act]; t < a.term_start[act + 1]; ++t) {
-      const T* Wt = a.W + static_cast<int64_t>(t) * a.g.w_term_stride + tile_off;
+  };
+  auto load_fac = [&](int t) {
+    if constexpr (STAGE) {
+      const int64_t base = static_cast<int64_t>(t) * a.g.term_stride;
 #pragma unroll
-      for (int j = 0; j < EPT; ++j) {
-        const int e = threadIdx.x + j * kPass2Block;
-        if (e < TE) X[lpad(e)] = Wt[e] - cs_in;
-      }
-      __syncthreads();
-      int outer = 1, inner = TE;
-      for (int k = 0; k < n1; ++k) {
-        const int m = a.g.size[k];
-        inner /= m;
-        if (a.kinds[t * n + k] != F_IDENT) {
-          const int64_t fo = static_cast<int64_t>(t) * a.g.term_stride + a.g.fac_off[k];
-          mode_product<T, MMAX, MM>(X, outer, m, inner, a.fac + fo, a.facbf + fo, a.facbf_lo + fo);
+      for (int i = 0; i < kStageRegs; ++i) {
+        const int idx = threadIdx.x + i * kPass2Block;
+        if (idx < rows_len) {
+          if (MM == MM_F32) {
+            nf[i] = a.fac[base + idx];
+          } else {
+            nh[i] = a.facbf[base + idx];
+            nl[i] = a.facbf_lo[base + idx];
+          }
         }
-        outer *= m;
       }
-      const T lam = a.lam[t];
+    }
+  };
+  int act = used_from(0);
+  int t = act < a.A ? a.term_start[act] : 0;
+  if (act < a.A) {
+    load_fac(t);
+    load_tile(t);
+  }
+  while (act < a.A) {
+    if constexpr (STAGE) {
+#pragma unroll
+      for (int i = 0; i < kStageRegs; ++i) {
+        const int idx = threadIdx.x + i * kPass2Block;
+        if (idx < rows_len) {
+          if (MM == MM_F32) {
+            Fs[idx] = nf[i];
+          } else {
+            Fh[idx] = nh[i];
+            Fl[idx] = nl[i];
+          }
+        }
+      }
+    }
+    if (full) {
+#pragma unroll
+      for (int j = 0; j < EPT; ++j) Xe[j] = nx[j] - cs_in;
+    } else {
+#pragma unroll
+      for (int j = 0; j < EPT; ++j)
+        if (e0 + j < TE) Xe[j] = nx[j] - cs_in;
+    }
+    const bool last_of_act = (t + 1 == a.term_start[act + 1]);
+    const int act2 = last_of_act ? used_from(act + 1) : act;
+    const int t2 = last_of_act ? (act2 < a.A ? a.term_start[act2] : 0) : t + 1;
+    if (act2 < a.A) {
+      load_fac(t2);
+      load_tile(t2);
+    }
+    __syncthreads();
+    int outer = 1, inner = TE;
+    for (int k = 0; k < n1; ++k) {
+      const int m = a.g.size[k];
+      inner /= m;
+      if (a.kinds[t * n + k] != F_IDENT) {
+        if constexpr (STAGE) {
+          const int fo = a.g.fac_off[k];
+          mode_product<T, MMAX, MM>(X, X, outer, m, inner, a.g.idiv[k], Fs + fo, Fh + fo, Fl + fo);
+        } else {
+          const int64_t fo = static_cast<int64_t>(t) * a.g.term_stride + a.g.fac_off[k];
+          mode_product<T, MMAX, MM>(X, X, outer, m, inner, a.g.idiv[k], a.fac + fo,
+                                    a.facbf + fo, a.facbf_lo + fo);
+        }
+      }
+      outer *= m;
+    }
+    const T lam = a.lam[t];
+    if (full) {
+      T x[EPT];
+#pragma unroll
+      for (int j = 0; j < EPT; ++j) x[j] = Xe[j];
 #pragma unroll
       for (int j = 0; j < EPT; ++j) {
-        const int e = threadIdx.x + j * kPass2Block;
-        if (e < TE) {
-          const T x = X[lpad(e)];
+        if (MODE == MODE_EVAL || MODE == MODE_RESID) {
+          acc[j] = (pold[j] == act) ? fma(lam, x[j], acc[j]) : acc[j];
+        } else {
+          acc[j] = fma(lam, x[j], acc[j]);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < EPT; ++j) {
+        if (e0 + j < TE) {
+          const T x = Xe[j];
           if (MODE == MODE_EVAL || MODE == MODE_RESID) {
             if (pold[j] == act) acc[j] = fma(lam, x, acc[j]);
           } else {
@@ -290,24 +566,32 @@ __global__ __launch_bounds__(kPass2Block) void chain_pass2(ChainArgs<T> a) {
           }
         }
       }
-      __syncthreads();
     }
-    if (MODE == MODE_MAX) {
+    __syncthreads();
+    if (last_of_act) {
+      if (MODE == MODE_MAX) {
 #pragma unroll
-      for (int j = 0; j < EPT; ++j) best[j] = acc[j] > best[j] ? acc[j] : best[j];
-    } else if (MODE == MODE_GREEDY) {
+        for (int j = 0; j < EPT; ++j) {
+          best[j] = acc[j] > best[j] ? acc[j] : best[j];
+          acc[j] = T(0);
+        }
+      } else if (MODE == MODE_GREEDY) {
 #pragma unroll
-      for (int j = 0; j < EPT; ++j) {
-        bool v;
-        const int s = state_of(threadIdx.x + j * kPass2Block, v);
-        if (v) {
-          const T g = is_terminal(a.term_bits, s) ? T(0) : a.gamma;
-          const T q = fma(g, acc[j] + cs, a.R[s]);
-          tie_update(q, act, tol, best[j], bi[j]);
-          if (act == pold[j]) qold[j] = q;
+        for (int j = 0; j < EPT; ++j) {
+          bool v;
+          const int s = state_of(e0 + j, v);
+          if (v) {
+            const T g = is_terminal(a.term_bits, s) ? T(0) : a.gamma;
+            const T q = fma(g, acc[j] + cs, a.R[s]);
+            tie_update(q, act, tol, best[j], bi[j]);
+            if (act == pold[j]) qold[j] = q;
+          }
+          acc[j] = T(0);
         }
       }
     }
+    act = act2;
+    t = t2;
   }
 
   double res = 0.0;
@@ -315,7 +599,7 @@ __global__ __launch_bounds__(kPass2Block) void chain_pass2(ChainArgs<T> a) {
 #pragma unroll
   for (int j = 0; j < EPT; ++j) {
     bool v;
-    const int s = state_of(threadIdx.x + j * kPass2Block, v);
+    const int s = state_of(e0 + j, v);
     if (!v) continue;
     const T c = a.V[s];
     if (MODE == MODE_GREEDY) {
@@ -351,6 +635,18 @@ static int pick_mmax(int m) {
 
 template <typename T, int MMAX, int MM>
 static void launch_pass1_m(const ChainArgs<T>& a, hipStream_t st) {
+  if (a.g.r1 > 0) {
+    const int R1 = a.g.r1;
+    const int cols_len = a.g.term_stride - a.g.fac_off[a.g.n1];
+    const size_t sh = sizeof(T) * static_cast<size_t>(R1) * (a.g.C + (a.g.C >> 5) + 1) +
+                      (MM != MM_VALU ? 4 * static_cast<size_t>(cols_len) : 0);
+    const dim3 grid((a.g.Rr + R1 - 1) / R1), block(64 * R1);
+    const int pv = (a.g.C + 63) / 64;
+    if (pv <= 16) hipLaunchKernelGGL((chain_pass1_rows<T, MMAX, MM, 16>), grid, block, sh, st, a);
+    else if (pv <= 32) hipLaunchKernelGGL((chain_pass1_rows<T, MMAX, MM, 32>), grid, block, sh, st, a);
+    else hipLaunchKernelGGL((chain_pass1_rows<T, MMAX, MM, 64>), grid, block, sh, st, a);
+    return;
+  }
   const size_t sh = sizeof(T) * (2 * (static_cast<size_t>(a.g.C) + (a.g.C >> 5) + 1) + 2);
   hipLaunchKernelGGL((chain_pass1<T, MMAX, MM>), dim3(a.g.Rr), dim3(kPass1Block), sh, st, a);
 }
@@ -359,12 +655,14 @@ template <typename T, int MMAX, int MODE, int MM>
 static void launch_pass2_mm(const ChainArgs<T>& a, hipStream_t st) {
   const int TE = a.g.Rr * a.g.CT;
   const int ept = (TE + kPass2Block - 1) / kPass2Block;
-  const size_t sh = sizeof(T) * (static_cast<size_t>(TE) + (TE >> 5) + 1);
+  const int rows_len = (a.g.n1 < a.g.n) ? a.g.fac_off[a.g.n1] : a.g.term_stride;
+  const size_t sh = sizeof(T) * (static_cast<size_t>(TE) + (TE >> 5) + 2) +
+                    (MM != MM_VALU ? 4 * static_cast<size_t>(rows_len) : 0);
   const dim3 grid(a.g.ntiles), block(kPass2Block);
   if (ept <= 2) hipLaunchKernelGGL((chain_pass2<T, MMAX, MODE, 2, MM>), grid, block, sh, st, a);
+  else if (ept <= 4) hipLaunchKernelGGL((chain_pass2<T, MMAX, MODE, 4, MM>), grid, block, sh, st, a);
   else if (ept <= 8) hipLaunchKernelGGL((chain_pass2<T, MMAX, MODE, 8, MM>), grid, block, sh, st, a);
-  else if (ept <= 16) hipLaunchKernelGGL((chain_pass2<T, MMAX, MODE, 16, MM>), grid, block, sh, st, a);
-  else hipLaunchKernelGGL((chain_pass2<T, MMAX, MODE, 32, MM>), grid, block, sh, st, a);
+  else hipLaunchKernelGGL((chain_pass2<T, MMAX, MODE, 16, MM>), grid, block, sh, st, a);
 }
 
 template <typename T, int MMAX, int MM>

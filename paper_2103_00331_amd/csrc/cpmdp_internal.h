@@ -100,6 +100,10 @@ struct ChainGeom {
   int32_t term_stride;          // sum_k m_k^2
   int32_t mmax_row, mmax_col;
   int64_t w_term_stride;        // elements per term in the intermediate buffer
+  FastDiv idiv[kMaxDims];       // division by mode k's stride in its LDS array
+                                // (pass 2 for k < n1, pass 1 for k >= n1)
+  int32_t r1;                   // pass 1 rows per block (one per wave), 0: one
+                                // row per block with the slab in LDS
 };
 
 template <typename T>
