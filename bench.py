@@ -253,11 +253,17 @@ def bench_batch(args):
     Vs = [torch.zeros(x.n_states, dtype=torch.float64, device="cuda") for x in insts]
     pis = [torch.zeros(x.n_states, dtype=torch.int32, device="cuda") for x in insts]
 
+    method = 1 if args.method == "pi" else 0
+
     def solve():
-        for V in Vs:
+        for V, p in zip(Vs, pis):
             V.zero_()
-        code, sweeps, res = B.cpmdp_batch_solve(bm.b, Vs, pis, eps, 100000, B.CPMDP_FP32, 0)
-        assert code == B.CPMDP_OK and np.all(res <= eps)
+            p.zero_()
+        code, sweeps, res = B.cpmdp_batch_solve(bm.b, Vs, pis, eps, 100000, B.CPMDP_FP32, method)
+        if code != B.CPMDP_OK or not np.all(res <= eps):
+            bad = np.nonzero(~(res <= eps))[0]
+            raise RuntimeError(f"batched solve: code {code}, {bad.size} instances above eps, "
+                               f"e.g. {[(int(i), float(res[i]), int(sweeps[i])) for i in bad[:5]]}")
         return sweeps
 
     for _ in range(args.warmup):
@@ -267,11 +273,13 @@ def bench_batch(args):
     backups = 0
     for _ in range(args.steps):
         sw = solve()
-        backups += sum(int(s) * x.n_states * x.n_actions for s, x in zip(sw, insts))
+        # evaluation sweeps touch one action per state (counted as 1 for PI)
+        backups += sum(int(s) * x.n_states * (x.n_actions if method == 0 else 1)
+                       for s, x in zip(sw, insts))
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     bm.close()
-    _log(f"batched: {1e3 * el / args.steps:.1f} ms per batch solve (tile {ts}, k {k})")
+    _log(f"batched {args.method}: {1e3 * el / args.steps:.1f} ms per batch solve (tile {ts}, k {k})")
     # plain GPU VI: each instance alone, FP64 sweeps from V0 = 0
     plain = 0.0
     plain_sweeps = 0
@@ -293,6 +301,8 @@ def bench_batch(args):
             "config": {"workload": f"batch of 512 GridWorlds, n in {{2,3,4}}, m in [8,48], "
                                    f"{tot_states} states in total, slip U[0.05,0.3], "
                                    "gamma U[0.9,0.99]", "eps": eps,
+                       "method": f"batched {args.method}: FP32 sweeps, FP64 residual / "
+                                 "certificate per instance",
                        "tile_states": ts, "sweeps_per_graph": k, "autotune_s": tune_s},
             "time_to_eps_s": el / args.steps, "plain_vi_time_to_eps_s": plain,
             "plain_vi_sweeps": plain_sweeps,

@@ -976,6 +976,7 @@ int cpmdp_policy_iteration(cpmdp_t* h, double* V, int32_t* pi, double eps, int64
   double eps_eval = std::max(eps_floor, 1e-2 * std::max(rmax, 1e-300));
   double cert = INFINITY;
   bool converged = false;
+  int certified = 0;
   const bool low = precision != CPMDP_FP64;
   const double floor32 =
       8.0 * std::ldexp(1.0, -24) * std::max(1.0, rmax / (1.0 - h->gamma));
@@ -1012,7 +1013,8 @@ int cpmdp_policy_iteration(cpmdp_t* h, double* V, int32_t* pi, double eps, int64
         float* alt = h->d.E1;
         bool done = false;
         double last = 0;
-        const double tol_e = std::max(1e-3 * r[0], floor32 * 1e-3);
+        // the correction e is small, so FP32 resolves it relative to ||r||
+        const double tol_e = 1e-3 * r[0];
         rc = run_sweeps<float>(h, false, MODE_EVAL, cur, alt, h->d.r32, pi, tol_e,
                                precision == CPMDP_BF16 ? INFINITY : 0.0, max_iter - 1, &sweeps,
                                &done, &last, precision == CPMDP_BF16);
@@ -1025,7 +1027,13 @@ int cpmdp_policy_iteration(cpmdp_t* h, double* V, int32_t* pi, double eps, int64
     rc = certify(h, V, pi, pi, &cert, &changes);
     if (rc) return rc;
     ++sweeps;
-    if (changes == 0 && cert <= eps) {
+    // Stop when pi is unchanged and V is certified.  Once V is certified,
+    // remaining changes can only swap actions whose Q-values differ by less
+    // than the evaluation error (evaluation is iterative); after
+    // kCertifiedRounds such rounds the certified V and its greedy policy are
+    // returned.
+    if (cert <= eps) ++certified;
+    if (cert <= eps && (changes == 0 || certified >= kCertifiedRounds)) {
       converged = true;
       break;
     }

@@ -41,7 +41,7 @@ enum BStage : int32_t { B_F32 = 0, B_F64 = 1, B_CERT = 2, B_DONE = 3 };
 struct BInst {
   GridGeom g;
   int32_t A, vec, axis, stage;
-  int32_t parity, pad0;
+  int32_t parity, eparity;     // V ping-pong; PI correction (V32 = e) ping-pong
   float gamma32, pad1;
   double gamma64;
   float base32[2 * kBMaxN + 1];
@@ -55,7 +55,8 @@ struct BInst {
   const uint32_t* tbits;
   float* V32[2];
   double* V64[2];
-  int32_t* pi_out;
+  int32_t* pi_out;      // greedy policy out; PI: also the policy evaluated
+  float* r32;           // PI: FP32 right-hand side of the correction sweeps
   double stop;          // a sweep whose residual is <= stop ends the stage
 };
 static_assert(sizeof(BInst) % 4 == 0, "descriptor copied as words");
@@ -68,6 +69,7 @@ struct BatchArgs {
   int32_t ninst;
   unsigned long long* res;      // [kBMaxK][ninst][kBSpread] FP64 bits
   unsigned long long* vmax;     // [ninst] ||V||_inf FP64 bits (certificate)
+  unsigned int* changes;        // [ninst] policy changes of a PI improvement
 };
 
 // Load tile t's descriptor into LDS; returns the tile.
@@ -144,7 +146,10 @@ __device__ __forceinline__ double* const* vals(const BInst& d, double) { return 
 // One Bellman max sweep over the FP32 tiles (T = float) or the FP64 tiles
 // (T = double).  j = index of the sweep inside the graph: selects the
 // ping-pong direction and the residual slot.
-template <typename T>
+//   MODE_MAX : value-iteration sweep of V32 / V64 with rewards R.
+//   MODE_EVAL: (T = float) policy-iteration correction sweep
+//              e' = r + gamma (1 - tau) P_pi e on the V32 pair.
+template <typename T, int MODE>
 __global__ __launch_bounds__(kBBlock) void batch_sweep_kernel(BatchArgs a, int j) {
   __shared__ BInst d;
   int t0, t1;
@@ -164,13 +169,21 @@ __global__ __launch_bounds__(kBBlock) void batch_sweep_kernel(BatchArgs a, int j
     }
     const int s0 = tl.y;
     const int s1 = min(s0 + a.tile_states, d.g.S);
-    const int pin = d.parity ^ (j & 1);
-    T* const* V = vals(d, T(0));
-    const StencilIO<T> io{V[pin], V[pin ^ 1], rew(d, T(0)), d.tbits, nullptr, nullptr, nullptr};
     T res = T(0);
     double rd = 0.0;
     unsigned ch = 0;
-    tile_dispatch<T, MODE_MAX>(d, io, weights_of<T>(d), s0, s1, T(0), res, rd, ch);
+    if constexpr (MODE == MODE_EVAL) {
+      const int pin = d.eparity ^ (j & 1);
+      const StencilIO<float> io{d.V32[pin], d.V32[pin ^ 1], d.r32, d.tbits, d.pi_out, nullptr,
+                                nullptr};
+      const StencilW<float> W{d.base32, d.axis32, d.w32, d.w32, d.A, d.gamma32};
+      tile_dispatch<float, MODE_EVAL>(d, io, W, s0, s1, 0.f, res, rd, ch);
+    } else {
+      const int pin = d.parity ^ (j & 1);
+      T* const* V = vals(d, T(0));
+      const StencilIO<T> io{V[pin], V[pin ^ 1], rew(d, T(0)), d.tbits, nullptr, nullptr, nullptr};
+      tile_dispatch<T, MODE_MAX>(d, io, weights_of<T>(d), s0, s1, T(0), res, rd, ch);
+    }
     block_max_to_slot(static_cast<double>(res),
                       a.res + (static_cast<size_t>(j) * a.ninst + tl.x) * kBSpread, kBSpread - 1);
   }
@@ -178,7 +191,9 @@ __global__ __launch_bounds__(kBBlock) void batch_sweep_kernel(BatchArgs a, int j
 
 // FP64 certificate of stage-B_CERT tiles: ||B V - V|| into residual slot 0
 // and the greedy policy (tie rule) into the instance's policy buffer.
-__global__ __launch_bounds__(kBBlock) void batch_cert_kernel(BatchArgs a) {
+// keep != 0 (policy iteration): the policy in pi_out is the incumbent, kept
+// unless beaten by more than the tie tolerance; changed states are counted.
+__global__ __launch_bounds__(kBBlock) void batch_cert_kernel(BatchArgs a, int keep) {
   __shared__ BInst d;
   int t0, t1;
   tile_range(a, 0, t0, t1);
@@ -188,16 +203,38 @@ __global__ __launch_bounds__(kBBlock) void batch_cert_kernel(BatchArgs a) {
     const int s1 = min(s0 + a.tile_states, d.g.S);
     const double tol = tie_tol(a.vmax + tl.x);
     const StencilW<double> W{d.base64, d.axis64, d.w64, nullptr, d.A, d.gamma64};
-    const StencilIO<double> io{d.V64[d.parity], nullptr, d.R64, d.tbits, nullptr, d.pi_out,
-                               nullptr};
+    const StencilIO<double> io{d.V64[d.parity], nullptr, d.R64, d.tbits,
+                               keep ? d.pi_out : nullptr, d.pi_out, nullptr};
     double res = 0.0, rd = 0.0;
     unsigned ch = 0;
     tile_dispatch<double, MODE_GREEDY>(d, io, W, s0, s1, tol, res, rd, ch);
     block_max_to_slot(res, a.res + static_cast<size_t>(tl.x) * kBSpread, kBSpread - 1);
+    if (keep) block_sum_to_counter(ch, a.changes + tl.x);
   }
 }
 
-// op 0: V32[p] <- V64[p];  op 1: V64[p] <- V32[p];  op 2: vmax[i] <- max |V64[p]|.
+// Policy-iteration residual in FP64: r = R + gamma (1 - tau) P_pi V - V into
+// r32 (FP32) and max |r| into residual slot 0.
+__global__ __launch_bounds__(kBBlock) void batch_resid_kernel(BatchArgs a) {
+  __shared__ BInst d;
+  int t0, t1;
+  tile_range(a, 0, t0, t1);
+  for (int t = t0; t < t1; ++t) {
+    const int2 tl = load_tile(a, t, d);
+    const int s0 = tl.y;
+    const int s1 = min(s0 + a.tile_states, d.g.S);
+    const StencilW<double> W{d.base64, d.axis64, d.w64, d.w64, d.A, d.gamma64};
+    const StencilIO<double> io{d.V64[d.parity], nullptr, d.R64, d.tbits, d.pi_out, nullptr,
+                               d.r32};
+    double res = 0.0, rd = 0.0;
+    unsigned ch = 0;
+    tile_dispatch<double, MODE_RESID>(d, io, W, s0, s1, 0.0, res, rd, ch);
+    block_max_to_slot(rd, a.res + static_cast<size_t>(tl.x) * kBSpread, kBSpread - 1);
+  }
+}
+
+// op 0: V32[p] <- V64[p];  op 1: V64[p] <- V32[p];  op 2: vmax[i] <- max |V64[p]|;
+// op 3: V64[p] += V32[e] (e = PI correction parity);  op 4: V32[0] <- 0.
 __global__ __launch_bounds__(kBBlock) void batch_util_kernel(BatchArgs a, int op) {
   __shared__ BInst d;
   int t0, t1;
@@ -211,7 +248,9 @@ __global__ __launch_bounds__(kBBlock) void batch_util_kernel(BatchArgs a, int op
     for (int s = s0 + threadIdx.x; s < s1; s += kBBlock) {
       if (op == 0) d.V32[p][s] = static_cast<float>(d.V64[p][s]);
       else if (op == 1) d.V64[p][s] = static_cast<double>(d.V32[p][s]);
-      else m = nanmax(m, fabs(d.V64[p][s]));
+      else if (op == 2) m = nanmax(m, fabs(d.V64[p][s]));
+      else if (op == 3) d.V64[p][s] += static_cast<double>(d.V32[d.eparity][s]);
+      else d.V32[0][s] = 0.f;
     }
     if (op == 2) block_max_to_slot(m, a.vmax + tl.x, 0u);
   }
@@ -239,16 +278,23 @@ struct cpmdp_batch {
   int* d_ntiles = nullptr;
   unsigned long long* d_res = nullptr;
   unsigned long long* d_vmax = nullptr;
+  unsigned int* d_changes = nullptr;
   int64_t max_tiles = 0;
   // host pinned
   unsigned long long* h_res = nullptr;
   int2* h_tiles = nullptr;
   int* h_ntiles = nullptr;
+  hipEvent_t tiles_copied = nullptr;  // the last tile-table copy out of h_tiles / h_ntiles
+  bool tiles_pending = false;
+  BInst* h_descs = nullptr;           // pinned staging copy of hd
+  hipEvent_t descs_copied = nullptr;
+  bool descs_pending = false;
   // tuning
   int tile_states = 2048;
   int grid = kMaxBlocks;
   int k = 32;
-  std::map<std::pair<int, int>, hipGraphExec_t> graphs;   // (k, grid) -> exec
+  std::map<std::pair<int, int>, hipGraphExec_t> graphs;   // (mode, k, tile; grid) -> exec
+  unsigned int* h_changes = nullptr;
   std::string err;
 };
 
@@ -270,18 +316,18 @@ int bfail(cpmdp_batch_t* b, int code, const std::string& msg) {
 
 size_t al(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
-// Per-instance arrays: R64, R32, tbits, V32[2], V64[2].
+// Per-instance arrays: R64, R32, tbits, V32[2], V64[2], weights, r32.
 size_t inst_bytes(const cpmdp_t* h) {
   const size_t S = static_cast<size_t>(h->S);
   const size_t P = 2 * static_cast<size_t>(h->n) + 1;
   return al(S * 8) + al(S * 4) + al((S + 31) / 32 * 4 + 4) + 2 * al(S * 4) + 2 * al(S * 8) +
-         al(h->A * P * 4) + al(h->A * P * 8);
+         al(h->A * P * 4) + al(h->A * P * 8) + al(S * 4);
 }
 
 size_t fixed_bytes(const cpmdp_batch_t* b, int64_t max_tiles) {
   const size_t n = b->hs.size();
   return al(n * sizeof(BInst)) + al(max_tiles * sizeof(int2)) + al(64) +
-         al(static_cast<size_t>(kBMaxK) * n * kBSpread * 8) + al(n * 8);
+         al(static_cast<size_t>(kBMaxK) * n * kBSpread * 8) + al(n * 8) + al(n * 4);
 }
 
 int64_t count_tiles(const cpmdp_batch_t* b, int ts) {
@@ -305,12 +351,19 @@ BatchArgs make_args(cpmdp_batch_t* b) {
   a.ninst = static_cast<int32_t>(b->hs.size());
   a.res = b->d_res;
   a.vmax = b->d_vmax;
+  a.changes = b->d_changes;
   return a;
 }
 
 // Upload the tile table: first the tiles of instances with want == 1 (the
 // FP32 group, or the only group), then those with want == 2 (FP64 group).
 int upload_tiles(cpmdp_batch_t* b, const std::vector<char>& want, int64_t* count) {
+  // h_tiles / h_ntiles are pinned: the previous asynchronous copy out of
+  // them must have run before they are refilled
+  if (b->tiles_pending) {
+    BHIP(b, hipEventSynchronize(b->tiles_copied));
+    b->tiles_pending = false;
+  }
   int64_t nt = 0;
   const int ts = b->tile_states;
   int cnt[2] = {0, 0};
@@ -327,18 +380,30 @@ int upload_tiles(cpmdp_batch_t* b, const std::vector<char>& want, int64_t* count
   b->h_ntiles[1] = cnt[1];
   if (nt) BHIP(b, hipMemcpyAsync(b->d_tiles, b->h_tiles, nt * sizeof(int2), hipMemcpyHostToDevice, b->stream));
   BHIP(b, hipMemcpyAsync(b->d_ntiles, b->h_ntiles, 2 * sizeof(int), hipMemcpyHostToDevice, b->stream));
+  BHIP(b, hipEventRecord(b->tiles_copied, b->stream));
+  b->tiles_pending = true;
   *count = nt;
   return CPMDP_OK;
 }
 
+// Descriptors go through a pinned staging copy guarded like the tile table.
 int upload_descs(cpmdp_batch_t* b) {
-  BHIP(b, hipMemcpyAsync(b->d_insts, b->hd.data(), b->hd.size() * sizeof(BInst),
+  if (b->descs_pending) {
+    BHIP(b, hipEventSynchronize(b->descs_copied));
+    b->descs_pending = false;
+  }
+  std::memcpy(b->h_descs, b->hd.data(), b->hd.size() * sizeof(BInst));
+  BHIP(b, hipMemcpyAsync(b->d_insts, b->h_descs, b->hd.size() * sizeof(BInst),
                          hipMemcpyHostToDevice, b->stream));
+  BHIP(b, hipEventRecord(b->descs_copied, b->stream));
+  b->descs_pending = true;
   return CPMDP_OK;
 }
 
-int graph_for(cpmdp_batch_t* b, int k, hipGraphExec_t* out) {
-  auto key = std::make_pair(k * 100000 + b->tile_states, b->grid);
+// k sweeps captured as one graph: value iteration (FP32 tiles, then FP64
+// tiles, per sweep) or policy-iteration correction sweeps (FP32).
+int graph_for(cpmdp_batch_t* b, int k, hipGraphExec_t* out, bool eval = false) {
+  auto key = std::make_pair((eval ? 10000000 : 0) + k * 100000 + b->tile_states, b->grid);
   auto it = b->graphs.find(key);
   if (it != b->graphs.end()) {
     *out = it->second;
@@ -347,8 +412,15 @@ int graph_for(cpmdp_batch_t* b, int k, hipGraphExec_t* out) {
   const BatchArgs a = make_args(b);
   BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
   for (int j = 0; j < k; ++j) {
-    hipLaunchKernelGGL(batch_sweep_kernel<float>, dim3(b->grid), dim3(kBBlock), 0, b->stream, a, j);
-    hipLaunchKernelGGL(batch_sweep_kernel<double>, dim3(b->grid), dim3(kBBlock), 0, b->stream, a, j);
+    if (eval) {
+      hipLaunchKernelGGL((batch_sweep_kernel<float, MODE_EVAL>), dim3(b->grid), dim3(kBBlock), 0,
+                         b->stream, a, j);
+    } else {
+      hipLaunchKernelGGL((batch_sweep_kernel<float, MODE_MAX>), dim3(b->grid), dim3(kBBlock), 0,
+                         b->stream, a, j);
+      hipLaunchKernelGGL((batch_sweep_kernel<double, MODE_MAX>), dim3(b->grid), dim3(kBBlock), 0,
+                         b->stream, a, j);
+    }
   }
   hipGraph_t g = nullptr;
   BHIP(b, hipStreamEndCapture(b->stream, &g));
@@ -431,6 +503,198 @@ int time_config(cpmdp_batch_t* b, int ts, int grid, int k, int reps, double* ms_
   return CPMDP_OK;
 }
 
+// Policy iteration over the batch (FP32 correction sweeps, FP64 residual,
+// FP64 improvement), per instance the same scheme as the single-instance
+// solver: evaluate pi by r = R + gamma P_pi V - V (FP64), e <- r + gamma
+// P_pi e (FP32 sweeps from e = 0 until ||e' - e|| <= 1e-3 ||r||), V += e,
+// until ||r|| <= eps_eval; then improve greedily keeping the incumbent; stop
+// when pi is unchanged and the FP64 residual ||B V - V|| <= eps (or after a
+// few certified rounds whose changes are within the evaluation error).
+enum PStage : int { P_RESID = 0, P_CORR = 1, P_IMPROVE = 2, P_DONE = 3 };
+
+int batch_pi(cpmdp_batch_t* b, double* const* V_devs, int32_t* const* pi_devs, double eps,
+             int64_t max_iter, int64_t* sweeps_out, double* residual_out) {
+  const size_t n = b->hs.size();
+  std::vector<int> st(n, P_RESID);
+  std::vector<int64_t> sweeps(n, 0);
+  std::vector<double> cert(n, INFINITY), eps_eval(n), eps_floor(n);
+  std::vector<char> converged(n, 0);
+  std::vector<int> certified(n, 0);
+  for (size_t i = 0; i < n; ++i) {
+    cpmdp_t* h = b->hs[i];
+    BInst& d = b->hd[i];
+    BHIP(b, hipMemcpyAsync(d.V64[0], V_devs[i], h->S * 8, hipMemcpyDeviceToDevice, b->stream));
+    d.parity = 0;
+    d.eparity = 0;
+    d.pi_out = pi_devs[i];
+    double rmax = 0.0;
+    for (double r : h->rewards) rmax = std::max(rmax, std::fabs(r));
+    eps_floor[i] = 0.5 * eps * (1.0 - h->gamma);
+    eps_eval[i] = std::max(eps_floor[i], 1e-2 * std::max(rmax, 1e-300));
+  }
+  // every policy entry must name an action (the evaluation sweeps index the
+  // weight table with it)
+  launch_fill_u32(b->d_changes, static_cast<int>(n), 0u, b->stream);
+  for (size_t i = 0; i < n; ++i)
+    launch_check_policy(pi_devs[i], b->hs[i]->S, b->hs[i]->A, b->d_changes + i, b->stream);
+  BHIP(b, hipGetLastError());
+  BHIP(b, hipMemcpyAsync(b->h_changes, b->d_changes, n * 4, hipMemcpyDeviceToHost, b->stream));
+  BHIP(b, hipStreamSynchronize(b->stream));
+  for (size_t i = 0; i < n; ++i)
+    if (b->h_changes[i] != 0) return bfail(b, CPMDP_E_ARG, "policy holds actions outside [0, A)");
+  int rc = upload_descs(b);
+  if (rc) return rc;
+  std::vector<double> res;
+  auto group = [&](int stage) {
+    std::vector<char> w(n, 0);
+    bool any = false;
+    for (size_t i = 0; i < n; ++i) {
+      w[i] = st[i] == stage;
+      any = any || w[i];
+    }
+    return std::make_pair(w, any);
+  };
+  for (;;) {
+    for (size_t i = 0; i < n; ++i)
+      if (st[i] != P_DONE && sweeps[i] >= max_iter) st[i] = P_DONE;
+    // ---- FP64 residual of the evaluation equation
+    auto gr = group(P_RESID);
+    if (gr.second) {
+      int64_t nt = 0;
+      rc = upload_descs(b);
+      if (rc) return rc;
+      rc = upload_tiles(b, gr.first, &nt);
+      if (rc) return rc;
+      zero_res(b, 1);
+      hipLaunchKernelGGL(batch_resid_kernel, dim3(b->grid), dim3(kBBlock), 0, b->stream, make_args(b));
+      BHIP(b, hipGetLastError());
+      rc = read_res(b, 1, res);
+      if (rc) return rc;
+      std::vector<char> start(n, 0);
+      bool any_start = false;
+      for (size_t i = 0; i < n; ++i) {
+        if (!gr.first[i]) continue;
+        sweeps[i] += 1;
+        if (!std::isfinite(res[i])) return bfail(b, CPMDP_E_NONFINITE, "non-finite PI residual");
+        if (res[i] <= eps_eval[i]) {
+          st[i] = P_IMPROVE;
+        } else {
+          st[i] = P_CORR;
+          b->hd[i].eparity = 0;
+          b->hd[i].stop = 1e-3 * res[i];
+          start[i] = 1;
+          any_start = true;
+        }
+      }
+      if (any_start) {
+        rc = upload_descs(b);
+        if (rc) return rc;
+        rc = launch_util(b, start, 4);   // e <- 0
+        if (rc) return rc;
+      }
+    }
+    // ---- FP32 correction sweeps, k per graph replay
+    auto gc = group(P_CORR);
+    if (gc.second) {
+      int64_t nt = 0;
+      rc = upload_descs(b);
+      if (rc) return rc;
+      rc = upload_tiles(b, gc.first, &nt);
+      if (rc) return rc;
+      int64_t left = b->k;
+      for (size_t i = 0; i < n; ++i)
+        if (gc.first[i]) left = std::min<int64_t>(left, max_iter - sweeps[i]);
+      const int k = static_cast<int>(std::max<int64_t>(left, 1));
+      hipGraphExec_t ex;
+      rc = graph_for(b, k, &ex, true);
+      if (rc) return rc;
+      zero_res(b, k);
+      BHIP(b, hipGraphLaunch(ex, b->stream));
+      rc = read_res(b, k, res);
+      if (rc) return rc;
+      std::vector<char> done(n, 0);
+      bool any_done = false;
+      for (size_t i = 0; i < n; ++i) {
+        if (!gc.first[i]) continue;
+        BInst& d = b->hd[i];
+        int ran = k;
+        for (int j = 0; j < k; ++j)
+          if (res[static_cast<size_t>(j) * n + i] <= d.stop) {
+            ran = j + 1;
+            break;
+          }
+        sweeps[i] += ran;
+        d.eparity ^= (ran & 1);
+        const double r = res[static_cast<size_t>(ran - 1) * n + i];
+        if (!std::isfinite(r)) return bfail(b, CPMDP_E_NONFINITE, "non-finite correction sweep");
+        // stalled: over the replay the change fell by less than half of what
+        // the contraction gamma^(ran-1) guarantees
+        const double r0 = res[i];
+        const bool stalled = ran >= 8 && r > std::pow(b->hs[i]->gamma, 0.5 * (ran - 1)) * r0 &&
+                             r <= 1e3 * d.stop;
+        if (r <= d.stop || stalled || sweeps[i] >= max_iter) {
+          done[i] = 1;
+          any_done = true;
+          st[i] = P_RESID;
+        }
+      }
+      if (any_done) {
+        rc = upload_descs(b);
+        if (rc) return rc;
+        rc = launch_util(b, done, 3);   // V += e
+        if (rc) return rc;
+      }
+    }
+    // ---- FP64 improvement (incumbent kept on ties) and certificate
+    auto gi = group(P_IMPROVE);
+    if (gi.second) {
+      rc = upload_descs(b);
+      if (rc) return rc;
+      rc = launch_util(b, gi.first, 2);   // vmax
+      if (rc) return rc;
+      int64_t nt = 0;
+      rc = upload_tiles(b, gi.first, &nt);
+      if (rc) return rc;
+      zero_res(b, 1);
+      launch_fill_u32(b->d_changes, static_cast<int>(n), 0u, b->stream);
+      hipLaunchKernelGGL(batch_cert_kernel, dim3(b->grid), dim3(kBBlock), 0, b->stream, make_args(b), 1);
+      BHIP(b, hipGetLastError());
+      BHIP(b, hipMemcpyAsync(b->h_changes, b->d_changes, n * 4, hipMemcpyDeviceToHost, b->stream));
+      rc = read_res(b, 1, res);   // synchronizes the stream
+      if (rc) return rc;
+      for (size_t i = 0; i < n; ++i) {
+        if (!gi.first[i]) continue;
+        sweeps[i] += 1;
+        cert[i] = res[i];
+        if (!std::isfinite(cert[i])) return bfail(b, CPMDP_E_NONFINITE, "non-finite certificate");
+        const unsigned changes = b->h_changes[i];
+        if (cert[i] <= eps) ++certified[i];
+        if (cert[i] <= eps && (changes == 0 || certified[i] >= kCertifiedRounds)) {
+          st[i] = P_DONE;
+          converged[i] = 1;
+        } else {
+          eps_eval[i] = changes == 0 ? std::max(eps_floor[i], 0.05 * cert[i])
+                                     : std::max(eps_floor[i], std::min(eps_eval[i], 0.05 * cert[i]));
+          st[i] = P_RESID;
+        }
+      }
+    }
+    bool all_done = true;
+    for (size_t i = 0; i < n; ++i) all_done = all_done && st[i] == P_DONE;
+    if (all_done) break;
+  }
+  bool all_ok = true;
+  for (size_t i = 0; i < n; ++i) {
+    const BInst& d = b->hd[i];
+    BHIP(b, hipMemcpyAsync(V_devs[i], d.V64[d.parity], b->hs[i]->S * 8, hipMemcpyDeviceToDevice, b->stream));
+    if (sweeps_out) sweeps_out[i] = sweeps[i];
+    if (residual_out) residual_out[i] = cert[i];
+    all_ok = all_ok && converged[i];
+  }
+  BHIP(b, hipStreamSynchronize(b->stream));
+  return all_ok ? CPMDP_OK : CPMDP_NOT_CONVERGED;
+}
+
 int size_class(const cpmdp_batch_t* b) {
   int c = 0;
   while ((int64_t(1) << c) < b->total_states) ++c;
@@ -481,6 +745,10 @@ int cpmdp_batch_bind(cpmdp_batch_t* b, void* ws, size_t bytes, void* stream) {
     return bfail(b, CPMDP_E_WORKSPACE, "batch workspace missing, misaligned or too small");
   b->user_stream = static_cast<hipStream_t>(stream);
   if (!b->stream) BHIP(b, hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+  if (!b->tiles_copied) BHIP(b, hipEventCreateWithFlags(&b->tiles_copied, hipEventDisableTiming));
+  if (!b->descs_copied) BHIP(b, hipEventCreateWithFlags(&b->descs_copied, hipEventDisableTiming));
+  b->tiles_pending = false;
+  b->descs_pending = false;
   clear_graphs(b);
   const size_t n = b->hs.size();
   b->max_tiles = count_tiles(b, kMinTile);
@@ -495,7 +763,10 @@ int cpmdp_batch_bind(cpmdp_batch_t* b, void* ws, size_t bytes, void* stream) {
   b->d_ntiles = reinterpret_cast<int*>(take(64));
   b->d_res = reinterpret_cast<unsigned long long*>(take(static_cast<size_t>(kBMaxK) * n * kBSpread * 8));
   b->d_vmax = reinterpret_cast<unsigned long long*>(take(n * 8));
+  b->d_changes = reinterpret_cast<unsigned int*>(take(n * 4));
   if (!b->h_res) {
+    BHIP(b, hipHostMalloc(reinterpret_cast<void**>(&b->h_changes), n * 4, hipHostMallocDefault));
+    BHIP(b, hipHostMalloc(reinterpret_cast<void**>(&b->h_descs), n * sizeof(BInst), hipHostMallocDefault));
     BHIP(b, hipHostMalloc(reinterpret_cast<void**>(&b->h_res), static_cast<size_t>(kBMaxK) * n * kBSpread * 8, hipHostMallocDefault));
     BHIP(b, hipHostMalloc(reinterpret_cast<void**>(&b->h_tiles), b->max_tiles * sizeof(int2), hipHostMallocDefault));
     BHIP(b, hipHostMalloc(reinterpret_cast<void**>(&b->h_ntiles), 64, hipHostMallocDefault));
@@ -533,6 +804,7 @@ int cpmdp_batch_bind(cpmdp_batch_t* b, void* ws, size_t bytes, void* stream) {
     d.V64[1] = reinterpret_cast<double*>(take(S * 8));
     float* w32 = reinterpret_cast<float*>(take(h->A * P * 4));
     double* w64 = reinterpret_cast<double*>(take(h->A * P * 8));
+    d.r32 = reinterpret_cast<float*>(take(S * 4));
     d.R64 = R64;
     d.R32 = R32;
     d.tbits = tb;
@@ -565,10 +837,17 @@ int cpmdp_batch_solve(cpmdp_batch_t* b, double* const* V_devs, int32_t* const* p
   if (!V_devs) return bfail(b, CPMDP_E_ARG, "V_devs is NULL");
   if (!(eps > 0.0) || max_iter < 1) return bfail(b, CPMDP_E_ARG, "eps > 0 and max_iter >= 1");
   if (precision < CPMDP_FP64 || precision > CPMDP_BF16) return bfail(b, CPMDP_E_ARG, "precision");
-  if (method != 0) return bfail(b, CPMDP_E_UNSUPPORTED, "batched solve runs value iteration");
+  if (method != 0 && method != 1) return bfail(b, CPMDP_E_ARG, "method must be 0 (VI) or 1 (PI)");
+  if (method == 1 && precision == CPMDP_FP64)
+    return bfail(b, CPMDP_E_UNSUPPORTED, "batched policy iteration runs FP32 correction sweeps");
   const size_t n = b->hs.size();
   for (size_t i = 0; i < n; ++i)
     if (!V_devs[i]) return bfail(b, CPMDP_E_ARG, "NULL V buffer");
+  if (method == 1) {
+    if (!pi_devs) return bfail(b, CPMDP_E_ARG, "policy iteration needs pi_devs (initial policy)");
+    for (size_t i = 0; i < n; ++i)
+      if (!pi_devs[i]) return bfail(b, CPMDP_E_ARG, "NULL policy buffer");
+  }
   // The caller's buffers are written on its stream (possibly the null
   // stream, which a non-blocking stream does not wait for): order the
   // private stream after everything enqueued there so far.
@@ -579,6 +858,7 @@ int cpmdp_batch_solve(cpmdp_batch_t* b, double* const* V_devs, int32_t* const* p
     BHIP(b, hipStreamWaitEvent(b->stream, ready, 0));
     (void)hipEventDestroy(ready);
   }
+  if (method == 1) return batch_pi(b, V_devs, pi_devs, eps, max_iter, sweeps_out, residual_out);
   // inputs -> internal FP64 buffer 0
   std::vector<int64_t> sweeps(n, 0);
   std::vector<double> cert(n, INFINITY);
@@ -684,7 +964,7 @@ int cpmdp_batch_solve(cpmdp_batch_t* b, double* const* V_devs, int32_t* const* p
       rc = upload_tiles(b, cq, &nt);
       if (rc) return rc;
       zero_res(b, 1);
-      hipLaunchKernelGGL(batch_cert_kernel, dim3(b->grid), dim3(kBBlock), 0, b->stream, make_args(b));
+      hipLaunchKernelGGL(batch_cert_kernel, dim3(b->grid), dim3(kBBlock), 0, b->stream, make_args(b), 0);
       BHIP(b, hipGetLastError());
       rc = read_res(b, 1, res);
       if (rc) return rc;
@@ -789,6 +1069,10 @@ void cpmdp_batch_destroy(cpmdp_batch_t* b) {
   if (b->h_res) (void)hipHostFree(b->h_res);
   if (b->h_tiles) (void)hipHostFree(b->h_tiles);
   if (b->h_ntiles) (void)hipHostFree(b->h_ntiles);
+  if (b->h_changes) (void)hipHostFree(b->h_changes);
+  if (b->tiles_copied) (void)hipEventDestroy(b->tiles_copied);
+  if (b->descs_copied) (void)hipEventDestroy(b->descs_copied);
+  if (b->h_descs) (void)hipHostFree(b->h_descs);
   delete b;
 }
 

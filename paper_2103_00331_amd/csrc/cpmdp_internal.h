@@ -21,6 +21,7 @@ constexpr int kBlock = 256;        // threads per block of the streaming kernels
 constexpr int kXcds = 8;           // MI355X: 8 XCDs, 32 CUs each
 constexpr double kTieRel = 1e-12;  // tie tolerance relative to max(1,||V||)
 constexpr int64_t kMarchMinPlane = 65536;  // plane size (states) from which the stencil marches
+constexpr int kCertifiedRounds = 3;  // PI: certified improvement rounds before stopping
 
 // Kind of one factor T^{(k)}_{a,r}.
 enum FactorKind : uint8_t { F_IDENT = 0, F_SHIFT_P = 1, F_SHIFT_M = 2, F_DENSE = 3 };

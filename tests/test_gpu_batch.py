@@ -35,7 +35,7 @@ def _small_batch(count=14, seed=7):
     return out
 
 
-def _solve_batch(B, insts, prec, eps, tune=False, max_iter=200000, V0=None):
+def _solve_batch(B, insts, prec, eps, tune=False, max_iter=200000, V0=None, method=0):
     bm = B.BatchModel(insts)
     if tune:
         B.cpmdp_batch_autotune(bm.b, True, None)
@@ -43,7 +43,7 @@ def _solve_batch(B, insts, prec, eps, tune=False, max_iter=200000, V0=None):
           torch.as_tensor(V0[i], dtype=torch.float64, device="cuda").clone()
           for i, x in enumerate(insts)]
     pis = [torch.zeros(x.n_states, dtype=torch.int32, device="cuda") for x in insts]
-    code, sweeps, res = B.cpmdp_batch_solve(bm.b, Vs, pis, eps, max_iter, prec, 0)
+    code, sweeps, res = B.cpmdp_batch_solve(bm.b, Vs, pis, eps, max_iter, prec, method)
     torch.cuda.synchronize()
     out = [(V.cpu().numpy(), p.cpu().numpy()) for V, p in zip(Vs, pis)]
     bm.close()
@@ -66,6 +66,38 @@ def test_small_batch_matches_oracle(B, prec):
     for x, (mats, Vs), (V, pi) in zip(insts, refs, out):
         assert_close(V, Vs, tol_for(prec, Vs), x.name)
         compare_policy(pi, oracle.sparse.q_values(x, mats, Vs), eps / (1 - x.gamma) + 1e-12)
+
+
+def test_small_batch_policy_iteration_matches_oracle(B):
+    """Batched policy iteration (FP32 correction sweeps, FP64 residual and
+    improvement) from pi = 0: every instance against the oracle's V* and
+    policy, and certified like value iteration."""
+    insts = _small_batch(count=12, seed=9)
+    log("[batch] policy iteration, small batch")
+    refs = []
+    for x in insts:
+        mats = oracle.sparse.transition_csr(x)
+        Vs, _, _, _ = oracle.sparse.value_iteration(x, mats=mats)
+        refs.append((mats, Vs))
+    eps = min(0.5 * tol_for(1, Vs) * (1 - x.gamma) for x, (_, Vs) in zip(insts, refs))
+    code, out, sweeps, res = _solve_batch(B, insts, 1, eps, tune=True, method=1)
+    log(f"   sweeps {list(sweeps)}")
+    assert code == B.CPMDP_OK and np.all(res <= eps)
+    for x, (mats, Vs), (V, pi) in zip(insts, refs, out):
+        assert_close(V, Vs, tol_for(1, Vs), x.name)
+        compare_policy(pi, oracle.sparse.q_values(x, mats, Vs), eps / (1 - x.gamma) + 1e-12)
+
+
+def test_batch_policy_iteration_rejects_bad_policy(B):
+    insts = _small_batch(count=2, seed=19)
+    bm = B.BatchModel(insts)
+    Vs = [torch.zeros(x.n_states, dtype=torch.float64, device="cuda") for x in insts]
+    pis = [torch.zeros(x.n_states, dtype=torch.int32, device="cuda") for x in insts]
+    pis[1][3] = insts[1].n_actions
+    with pytest.raises(B.CpmdpError) as e:
+        B.cpmdp_batch_solve(bm.b, Vs, pis, 1e-6, 1000, 1, 1)
+    assert e.value.code == B.CPMDP_E_ARG
+    bm.close()
 
 
 def test_batch_equals_single_solves_and_autotune(B):
