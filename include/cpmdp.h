@@ -217,8 +217,10 @@ int cpmdp_bound_shift(cpmdp_t* h, double* V, double* lo_out, double* hi_out);
 /*
  * cpmdp_time_sweeps -- measurement helper: run n backup sweeps ping-ponging
  * between the device buffers V_a and V_b (dtype of the precision, starting
- * from V_a), each bracketed by a HIP event pair on the bound stream, and
- * return the mean time of one sweep's kernels in milliseconds.
+ * from V_a) on the bound stream, each launched with a HIP event pair that
+ * records its kernels' own start and stop (hipExtLaunchKernelGGL; from the
+ * first kernel of the sweep to the last), and return the mean time of one
+ * sweep's kernels in milliseconds.
  *   mode: 0 = Bellman max sweep (Eq. 1), 1 = fixed-policy sweep with pi.
  */
 int cpmdp_time_sweeps(cpmdp_t* h, void* V_a, void* V_b, int32_t n, int precision, int mode,

@@ -295,15 +295,15 @@ static StencilArgs<T> stencil_args(cpmdp_t* h, const void* V, void* Vout, const 
 // or FP32 (T = float).  V, Vout, R are typed by that choice.
 void sweep(cpmdp_t* h, bool prec64, int mode, const void* V, void* Vout, const void* R,
            const int32_t* pi_in, int32_t* pi_out, float* r_out,
-           unsigned long long* slot, unsigned int* ctr, bool bf16) {
+           unsigned long long* slot, unsigned int* ctr, bool bf16, const LaunchTiming* tm) {
   const hipStream_t st = h->stream;
   if (h->path == CPMDP_PATH_STENCIL) {
     if (prec64) {
       StencilArgs<double> a = stencil_args<double>(h, V, Vout, R, pi_in, pi_out, r_out, slot, ctr);
-      launch_stencil<double>(a, mode, st);
+      launch_stencil<double>(a, mode, st, tm);
     } else {
       StencilArgs<float> a = stencil_args<float>(h, V, Vout, R, pi_in, pi_out, r_out, slot, ctr);
-      launch_stencil<float>(a, mode, st);
+      launch_stencil<float>(a, mode, st, tm);
     }
     return;
   }
@@ -330,7 +330,7 @@ void sweep(cpmdp_t* h, bool prec64, int mode, const void* V, void* Vout, const v
     a.change_count = ctr;
     a.facbf = nullptr;
     a.facbf_lo = nullptr;
-    launch_chain<double>(a, mode, CHAIN_VALU, st);
+    launch_chain<double>(a, mode, CHAIN_VALU, st, tm);
   } else {
     ChainArgs<float> a{};
     a.g = h->cg32;
@@ -361,7 +361,7 @@ void sweep(cpmdp_t* h, bool prec64, int mode, const void* V, void* Vout, const v
       launch_minmax_keys_f32(a.V, h->S, h->d.vmax + 4, st);
       a.shift_keys = h->d.vmax + 4;
     }
-    launch_chain<float>(a, mode, bf16 ? CHAIN_BF16 : CHAIN_F32_MFMA, st);
+    launch_chain<float>(a, mode, bf16 ? CHAIN_BF16 : CHAIN_F32_MFMA, st, tm);
   }
 }
 
@@ -1104,12 +1104,13 @@ int cpmdp_time_sweeps(cpmdp_t* h, void* V_a, void* V_b, int32_t n, int precision
   zero_slots(h, 1);
   void* cur = V_a;
   void* alt = V_b;
+  // the events take the kernels' own start / stop times (first kernel of the
+  // sweep to last), as a kernel trace reports them
   for (int i = 0; i < n; ++i) {
-    HIP_TRY(h, hipEventRecord(ev[2 * i], st));
+    const LaunchTiming tm{ev[2 * i], ev[2 * i + 1]};
     sweep(h, p64, mode == 0 ? MODE_MAX : MODE_EVAL, cur, alt,
           p64 ? static_cast<const void*>(h->d.R64) : h->d.R32, pi, nullptr, nullptr, h->d.slots,
-          nullptr, precision == CPMDP_BF16);
-    HIP_TRY(h, hipEventRecord(ev[2 * i + 1], st));
+          nullptr, precision == CPMDP_BF16, &tm);
     std::swap(cur, alt);
   }
   rc = check_device(h);

@@ -634,7 +634,7 @@ static int pick_mmax(int m) {
 }
 
 template <typename T, int MMAX, int MM>
-static void launch_pass1_m(const ChainArgs<T>& a, hipStream_t st) {
+static void launch_pass1_m(const ChainArgs<T>& a, hipStream_t st, const LaunchTiming* tm) {
   if (a.g.r1 > 0) {
     const int R1 = a.g.r1;
     const int cols_len = a.g.term_stride - a.g.fac_off[a.g.n1];
@@ -642,36 +642,37 @@ static void launch_pass1_m(const ChainArgs<T>& a, hipStream_t st) {
                       (MM != MM_VALU ? 4 * static_cast<size_t>(cols_len) : 0);
     const dim3 grid((a.g.Rr + R1 - 1) / R1), block(64 * R1);
     const int pv = (a.g.C + 63) / 64;
-    if (pv <= 16) hipLaunchKernelGGL((chain_pass1_rows<T, MMAX, MM, 16>), grid, block, sh, st, a);
-    else if (pv <= 32) hipLaunchKernelGGL((chain_pass1_rows<T, MMAX, MM, 32>), grid, block, sh, st, a);
-    else hipLaunchKernelGGL((chain_pass1_rows<T, MMAX, MM, 64>), grid, block, sh, st, a);
+    if (pv <= 16) klaunch(chain_pass1_rows<T, MMAX, MM, 16>, grid, block, sh, st, tm, a);
+    else if (pv <= 32) klaunch(chain_pass1_rows<T, MMAX, MM, 32>, grid, block, sh, st, tm, a);
+    else klaunch(chain_pass1_rows<T, MMAX, MM, 64>, grid, block, sh, st, tm, a);
     return;
   }
   const size_t sh = sizeof(T) * (2 * (static_cast<size_t>(a.g.C) + (a.g.C >> 5) + 1) + 2);
-  hipLaunchKernelGGL((chain_pass1<T, MMAX, MM>), dim3(a.g.Rr), dim3(kPass1Block), sh, st, a);
+  klaunch(chain_pass1<T, MMAX, MM>, dim3(a.g.Rr), dim3(kPass1Block), sh, st, tm, a);
 }
 
 template <typename T, int MMAX, int MODE, int MM>
-static void launch_pass2_mm(const ChainArgs<T>& a, hipStream_t st) {
+static void launch_pass2_mm(const ChainArgs<T>& a, hipStream_t st, const LaunchTiming* tm) {
   const int TE = a.g.Rr * a.g.CT;
   const int ept = (TE + kPass2Block - 1) / kPass2Block;
   const int rows_len = (a.g.n1 < a.g.n) ? a.g.fac_off[a.g.n1] : a.g.term_stride;
   const size_t sh = sizeof(T) * (static_cast<size_t>(TE) + (TE >> 5) + 2) +
                     (MM != MM_VALU ? 4 * static_cast<size_t>(rows_len) : 0);
   const dim3 grid(a.g.ntiles), block(kPass2Block);
-  if (ept <= 2) hipLaunchKernelGGL((chain_pass2<T, MMAX, MODE, 2, MM>), grid, block, sh, st, a);
-  else if (ept <= 4) hipLaunchKernelGGL((chain_pass2<T, MMAX, MODE, 4, MM>), grid, block, sh, st, a);
-  else if (ept <= 8) hipLaunchKernelGGL((chain_pass2<T, MMAX, MODE, 8, MM>), grid, block, sh, st, a);
-  else hipLaunchKernelGGL((chain_pass2<T, MMAX, MODE, 16, MM>), grid, block, sh, st, a);
+  if (ept <= 2) klaunch(chain_pass2<T, MMAX, MODE, 2, MM>, grid, block, sh, st, tm, a);
+  else if (ept <= 4) klaunch(chain_pass2<T, MMAX, MODE, 4, MM>, grid, block, sh, st, tm, a);
+  else if (ept <= 8) klaunch(chain_pass2<T, MMAX, MODE, 8, MM>, grid, block, sh, st, tm, a);
+  else klaunch(chain_pass2<T, MMAX, MODE, 16, MM>, grid, block, sh, st, tm, a);
 }
 
 template <typename T, int MMAX, int MM>
-static void launch_pass2_m(const ChainArgs<T>& a, int mode, hipStream_t st) {
+static void launch_pass2_m(const ChainArgs<T>& a, int mode, hipStream_t st,
+                           const LaunchTiming* tm) {
   switch (mode) {
-    case MODE_MAX: launch_pass2_mm<T, MMAX, MODE_MAX, MM>(a, st); break;
-    case MODE_GREEDY: launch_pass2_mm<T, MMAX, MODE_GREEDY, MM>(a, st); break;
-    case MODE_EVAL: launch_pass2_mm<T, MMAX, MODE_EVAL, MM>(a, st); break;
-    default: launch_pass2_mm<T, MMAX, MODE_RESID, MM>(a, st); break;
+    case MODE_MAX: launch_pass2_mm<T, MMAX, MODE_MAX, MM>(a, st, tm); break;
+    case MODE_GREEDY: launch_pass2_mm<T, MMAX, MODE_GREEDY, MM>(a, st, tm); break;
+    case MODE_EVAL: launch_pass2_mm<T, MMAX, MODE_EVAL, MM>(a, st, tm); break;
+    default: launch_pass2_mm<T, MMAX, MODE_RESID, MM>(a, st, tm); break;
   }
 }
 
@@ -684,39 +685,47 @@ static int pick_unit(int mmax, int unit) {
 }
 
 template <typename T>
-static void launch_pass1(const ChainArgs<T>& a, int mm, hipStream_t st) {
+static void launch_pass1(const ChainArgs<T>& a, int mm, hipStream_t st, const LaunchTiming* tm) {
   if constexpr (std::is_same<T, float>::value) {
-    if (mm == MM_F32) return launch_pass1_m<T, 16, MM_F32>(a, st);
-    if (mm == MM_BF16) return launch_pass1_m<T, 16, MM_BF16>(a, st);
+    if (mm == MM_F32) return launch_pass1_m<T, 16, MM_F32>(a, st, tm);
+    if (mm == MM_BF16) return launch_pass1_m<T, 16, MM_BF16>(a, st, tm);
   }
   switch (pick_mmax(a.g.mmax_col)) {
-    case 4: return launch_pass1_m<T, 4, MM_VALU>(a, st);
-    case 16: return launch_pass1_m<T, 16, MM_VALU>(a, st);
-    default: return launch_pass1_m<T, 32, MM_VALU>(a, st);
+    case 4: return launch_pass1_m<T, 4, MM_VALU>(a, st, tm);
+    case 16: return launch_pass1_m<T, 16, MM_VALU>(a, st, tm);
+    default: return launch_pass1_m<T, 32, MM_VALU>(a, st, tm);
   }
 }
 
 template <typename T>
-static void launch_pass2(const ChainArgs<T>& a, int mode, int mm, hipStream_t st) {
+static void launch_pass2(const ChainArgs<T>& a, int mode, int mm, hipStream_t st,
+                         const LaunchTiming* tm) {
   if constexpr (std::is_same<T, float>::value) {
-    if (mm == MM_F32) return launch_pass2_m<T, 16, MM_F32>(a, mode, st);
-    if (mm == MM_BF16) return launch_pass2_m<T, 16, MM_BF16>(a, mode, st);
+    if (mm == MM_F32) return launch_pass2_m<T, 16, MM_F32>(a, mode, st, tm);
+    if (mm == MM_BF16) return launch_pass2_m<T, 16, MM_BF16>(a, mode, st, tm);
   }
   switch (pick_mmax(a.g.mmax_row)) {
-    case 4: return launch_pass2_m<T, 4, MM_VALU>(a, mode, st);
-    case 16: return launch_pass2_m<T, 16, MM_VALU>(a, mode, st);
-    default: return launch_pass2_m<T, 32, MM_VALU>(a, mode, st);
+    case 4: return launch_pass2_m<T, 4, MM_VALU>(a, mode, st, tm);
+    case 16: return launch_pass2_m<T, 16, MM_VALU>(a, mode, st, tm);
+    default: return launch_pass2_m<T, 32, MM_VALU>(a, mode, st, tm);
   }
 }
 
+// tm: start recorded at the first pass, stop after the second.
 template <typename T>
-void launch_chain(const ChainArgs<T>& a, int mode, int unit, hipStream_t st) {
+void launch_chain(const ChainArgs<T>& a, int mode, int unit, hipStream_t st,
+                  const LaunchTiming* tm) {
   const bool f32 = std::is_same<T, float>::value;
-  if (a.g.n1 < a.g.n) launch_pass1(a, f32 ? pick_unit(a.g.mmax_col, unit) : MM_VALU, st);
-  launch_pass2(a, mode, f32 ? pick_unit(a.g.mmax_row, unit) : MM_VALU, st);
+  const bool two = a.g.n1 < a.g.n;
+  const LaunchTiming t1{tm ? tm->start : nullptr, nullptr};
+  const LaunchTiming t2{two ? nullptr : (tm ? tm->start : nullptr), tm ? tm->stop : nullptr};
+  if (two) launch_pass1(a, f32 ? pick_unit(a.g.mmax_col, unit) : MM_VALU, st, tm ? &t1 : nullptr);
+  launch_pass2(a, mode, f32 ? pick_unit(a.g.mmax_row, unit) : MM_VALU, st, tm ? &t2 : nullptr);
 }
 
-template void launch_chain<double>(const ChainArgs<double>&, int, int, hipStream_t);
-template void launch_chain<float>(const ChainArgs<float>&, int, int, hipStream_t);
+template void launch_chain<double>(const ChainArgs<double>&, int, int, hipStream_t,
+                                   const LaunchTiming*);
+template void launch_chain<float>(const ChainArgs<float>&, int, int, hipStream_t,
+                                  const LaunchTiming*);
 
 }  // namespace cpm

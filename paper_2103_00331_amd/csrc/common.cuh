@@ -1,9 +1,23 @@
 // Device helpers shared by the cpmdp kernels.
 #pragma once
 
+#include <hip/hip_ext.h>
+
 #include "cpmdp_internal.h"
 
 namespace cpm {
+
+// Kernel launch, with the kernel's start / stop times recorded in tm's
+// events when tm is given.
+template <typename F, typename... Args>
+inline void klaunch(F kernel, dim3 grid, dim3 block, size_t shmem, hipStream_t st,
+                    const LaunchTiming* tm, Args... args) {
+  if (tm)
+    hipExtLaunchKernelGGL(kernel, grid, block, static_cast<uint32_t>(shmem), st, tm->start,
+                          tm->stop, 0u, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, shmem, st, args...);
+}
 
 __device__ __forceinline__ uint32_t fdiv(uint32_t n, FastDiv d) {
   return (__umulhi(n, d.magic) + n) >> d.shift;

@@ -53,6 +53,13 @@ struct GridGeom {
   FastDiv div[kMaxDims];
 };
 
+// Optional events around one launch (hipExtLaunchKernelGGL records the
+// kernel's own start / stop times in them): used to time single kernels.
+struct LaunchTiming {
+  hipEvent_t start = nullptr;
+  hipEvent_t stop = nullptr;
+};
+
 // ---------------------------------------------------------------- stencil
 template <typename T>
 struct StencilArgs {
@@ -88,7 +95,8 @@ struct StencilArgs {
 };
 
 template <typename T>
-void launch_stencil(const StencilArgs<T>& a, int mode, hipStream_t st);
+void launch_stencil(const StencilArgs<T>& a, int mode, hipStream_t st,
+                    const LaunchTiming* tm = nullptr);
 
 // ----------------------------------------------------------- dense chains
 struct ChainGeom {
@@ -144,7 +152,8 @@ struct ChainArgs {
 enum ChainUnit { CHAIN_VALU = 0, CHAIN_F32_MFMA = 1, CHAIN_BF16 = 2 };
 
 template <typename T>
-void launch_chain(const ChainArgs<T>& a, int mode, int unit, hipStream_t st);
+void launch_chain(const ChainArgs<T>& a, int mode, int unit, hipStream_t st,
+                  const LaunchTiming* tm = nullptr);
 
 // ---------------------------------------------------------------- helpers
 void launch_fill_u64(unsigned long long* p, int n, unsigned long long v, hipStream_t st);

@@ -76,5 +76,5 @@ int fail(cpmdp_t* h, int code, const std::string& msg);
 void layout(const cpmdp_t* h, DevPtrs* d, char* base, size_t* total);
 void sweep(cpmdp_t* h, bool prec64, int mode, const void* V, void* Vout, const void* R,
            const int32_t* pi_in, int32_t* pi_out, float* r_out, unsigned long long* slot,
-           unsigned int* ctr, bool bf16);
+           unsigned int* ctr, bool bf16, const LaunchTiming* tm = nullptr);
 }  // namespace cpm

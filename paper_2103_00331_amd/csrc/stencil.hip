@@ -118,7 +118,8 @@ __global__ __launch_bounds__(kBlock) void stencil_march_kernel(StencilArgs<T> a)
 }
 
 template <typename T, int N>
-static void launch_march_n(const StencilArgs<T>& a, int mode, hipStream_t st) {
+static void launch_march_n(const StencilArgs<T>& a, int mode, hipStream_t st,
+                           const LaunchTiming* tm) {
   if constexpr (N >= 2) {
     const dim3 grid(a.nblocks), block(kBlock);
     const size_t sh = (mode == MODE_EVAL || mode == MODE_RESID)
@@ -126,61 +127,65 @@ static void launch_march_n(const StencilArgs<T>& a, int mode, hipStream_t st) {
                           : 0;
     switch (mode) {
       case MODE_MAX:
-        if (a.axis) hipLaunchKernelGGL((stencil_march_kernel<T, N, MODE_MAX, true>), grid, block, sh, st, a);
-        else hipLaunchKernelGGL((stencil_march_kernel<T, N, MODE_MAX, false>), grid, block, sh, st, a);
+        if (a.axis) klaunch(stencil_march_kernel<T, N, MODE_MAX, true>, grid, block, sh, st, tm, a);
+        else klaunch(stencil_march_kernel<T, N, MODE_MAX, false>, grid, block, sh, st, tm, a);
         break;
       case MODE_GREEDY:
-        if (a.axis) hipLaunchKernelGGL((stencil_march_kernel<T, N, MODE_GREEDY, true>), grid, block, sh, st, a);
-        else hipLaunchKernelGGL((stencil_march_kernel<T, N, MODE_GREEDY, false>), grid, block, sh, st, a);
+        if (a.axis) klaunch(stencil_march_kernel<T, N, MODE_GREEDY, true>, grid, block, sh, st, tm, a);
+        else klaunch(stencil_march_kernel<T, N, MODE_GREEDY, false>, grid, block, sh, st, tm, a);
         break;
-      case MODE_EVAL: hipLaunchKernelGGL((stencil_march_kernel<T, N, MODE_EVAL, false>), grid, block, sh, st, a); break;
-      default: hipLaunchKernelGGL((stencil_march_kernel<T, N, MODE_RESID, false>), grid, block, sh, st, a); break;
+      case MODE_EVAL: klaunch(stencil_march_kernel<T, N, MODE_EVAL, false>, grid, block, sh, st, tm, a); break;
+      default: klaunch(stencil_march_kernel<T, N, MODE_RESID, false>, grid, block, sh, st, tm, a); break;
     }
   }
 }
 
 template <typename T, int N, int VEC>
-static void launch_stencil_nv(const StencilArgs<T>& a, int mode, hipStream_t st) {
+static void launch_stencil_nv(const StencilArgs<T>& a, int mode, hipStream_t st,
+                              const LaunchTiming* tm) {
   const dim3 grid(a.nblocks), block(kBlock);
   const size_t sh = (mode == MODE_EVAL || mode == MODE_RESID)
                         ? sizeof(T) * static_cast<size_t>(a.A) * (2 * N + 1)
                         : 0;
   switch (mode) {
     case MODE_MAX:
-      if (a.axis) hipLaunchKernelGGL((stencil_kernel<T, N, MODE_MAX, VEC, true>), grid, block, sh, st, a);
-      else hipLaunchKernelGGL((stencil_kernel<T, N, MODE_MAX, VEC, false>), grid, block, sh, st, a);
+      if (a.axis) klaunch(stencil_kernel<T, N, MODE_MAX, VEC, true>, grid, block, sh, st, tm, a);
+      else klaunch(stencil_kernel<T, N, MODE_MAX, VEC, false>, grid, block, sh, st, tm, a);
       break;
     case MODE_GREEDY:
-      if (a.axis) hipLaunchKernelGGL((stencil_kernel<T, N, MODE_GREEDY, VEC, true>), grid, block, sh, st, a);
-      else hipLaunchKernelGGL((stencil_kernel<T, N, MODE_GREEDY, VEC, false>), grid, block, sh, st, a);
+      if (a.axis) klaunch(stencil_kernel<T, N, MODE_GREEDY, VEC, true>, grid, block, sh, st, tm, a);
+      else klaunch(stencil_kernel<T, N, MODE_GREEDY, VEC, false>, grid, block, sh, st, tm, a);
       break;
-    case MODE_EVAL: hipLaunchKernelGGL((stencil_kernel<T, N, MODE_EVAL, VEC, false>), grid, block, sh, st, a); break;
-    default: hipLaunchKernelGGL((stencil_kernel<T, N, MODE_RESID, VEC, false>), grid, block, sh, st, a); break;
+    case MODE_EVAL: klaunch(stencil_kernel<T, N, MODE_EVAL, VEC, false>, grid, block, sh, st, tm, a); break;
+    default: klaunch(stencil_kernel<T, N, MODE_RESID, VEC, false>, grid, block, sh, st, tm, a); break;
   }
 }
 
 template <typename T, int N>
-static void launch_stencil_n(const StencilArgs<T>& a, int mode, hipStream_t st) {
-  if (a.march) launch_march_n<T, N>(a, mode, st);
-  else if (a.vec == 4) launch_stencil_nv<T, N, 4>(a, mode, st);
-  else launch_stencil_nv<T, N, 1>(a, mode, st);
+static void launch_stencil_n(const StencilArgs<T>& a, int mode, hipStream_t st,
+                             const LaunchTiming* tm) {
+  if (a.march) launch_march_n<T, N>(a, mode, st, tm);
+  else if (a.vec == 4) launch_stencil_nv<T, N, 4>(a, mode, st, tm);
+  else launch_stencil_nv<T, N, 1>(a, mode, st, tm);
 }
 
 template <typename T>
-void launch_stencil(const StencilArgs<T>& a, int mode, hipStream_t st) {
+void launch_stencil(const StencilArgs<T>& a, int mode, hipStream_t st, const LaunchTiming* tm) {
   switch (a.g.n) {
-    case 1: launch_stencil_n<T, 1>(a, mode, st); break;
-    case 2: launch_stencil_n<T, 2>(a, mode, st); break;
-    case 3: launch_stencil_n<T, 3>(a, mode, st); break;
-    case 4: launch_stencil_n<T, 4>(a, mode, st); break;
-    case 5: launch_stencil_n<T, 5>(a, mode, st); break;
-    case 6: launch_stencil_n<T, 6>(a, mode, st); break;
-    case 7: launch_stencil_n<T, 7>(a, mode, st); break;
-    default: launch_stencil_n<T, 8>(a, mode, st); break;
+    case 1: launch_stencil_n<T, 1>(a, mode, st, tm); break;
+    case 2: launch_stencil_n<T, 2>(a, mode, st, tm); break;
+    case 3: launch_stencil_n<T, 3>(a, mode, st, tm); break;
+    case 4: launch_stencil_n<T, 4>(a, mode, st, tm); break;
+    case 5: launch_stencil_n<T, 5>(a, mode, st, tm); break;
+    case 6: launch_stencil_n<T, 6>(a, mode, st, tm); break;
+    case 7: launch_stencil_n<T, 7>(a, mode, st, tm); break;
+    default: launch_stencil_n<T, 8>(a, mode, st, tm); break;
   }
 }
 
-template void launch_stencil<double>(const StencilArgs<double>&, int, hipStream_t);
-template void launch_stencil<float>(const StencilArgs<float>&, int, hipStream_t);
+template void launch_stencil<double>(const StencilArgs<double>&, int, hipStream_t,
+                                     const LaunchTiming*);
+template void launch_stencil<float>(const StencilArgs<float>&, int, hipStream_t,
+                                    const LaunchTiming*);
 
 }  // namespace cpm
