@@ -46,8 +46,12 @@ def _sha(paths):
     return h.hexdigest()[:16]
 
 
-STENCIL_SRC = ["paper_2103_00331_amd/csrc/stencil.hip", "paper_2103_00331_amd/csrc/common.cuh"]
+STENCIL_SRC = ["paper_2103_00331_amd/csrc/stencil.hip", "paper_2103_00331_amd/csrc/stencil_core.cuh",
+               "paper_2103_00331_amd/csrc/common.cuh"]
 CHAIN_SRC = ["paper_2103_00331_amd/csrc/chain.hip", "paper_2103_00331_amd/csrc/common.cuh"]
+BATCH_SRC = ["paper_2103_00331_amd/csrc/batch.hip", "paper_2103_00331_amd/csrc/stencil_core.cuh",
+             "paper_2103_00331_amd/csrc/common.cuh"]
+PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp64": 78.6}
 
 
 def _traffic(profile_md, src):
@@ -152,10 +156,11 @@ def bench_grid(args, m):
     algo_bytes = S * (4 + 4 + 4) + S / 8.0          # V, R, V' words + terminal bit
     achieved = algo_bytes / (ms * 1e-3) / 1e9
     traffic = _traffic(f"stencil_fp32_grid4d_{m}.md", STENCIL_SRC)
+    kname = ("stencil_march_kernel<float, 4, MODE_MAX, AXIS>" if m >= 96 and not args.one_pass
+             else "stencil_kernel<float, 4, MODE_MAX, VEC=4, AXIS>")
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "kernel": "stencil_kernel<float, 4, MODE_MAX>",
-            "kernel_ms": ms, "algorithmic_bytes_per_launch": algo_bytes}
+            "kernel": kname, "kernel_ms": ms, "algorithmic_bytes_per_launch": algo_bytes}
 
     out = {
         "metric": METRIC,
@@ -200,6 +205,10 @@ def bench_dense(args):
     Vb = torch.zeros_like(Va)
     ms = B.cpmdp_time_sweeps(model.h, Va, Vb, 10, prec, 0)
     flops = 2.0 * inst.n_terms * sum(int(m) for m in inst.sizes) * S
+    # HBM: every term's intermediate written by pass 1 and read by pass 2,
+    # plus V (both passes), R and V'
+    w_bytes = (2.0 * inst.n_terms + 4.0) * S * (8 if prec == B.CPMDP_FP64 else 4)
+    peak = PEAK_TFLOPS[args.precision]
     eps = 1e-6
     V = torch.zeros(S, dtype=torch.float64, device="cuda")
     pi = torch.zeros(S, dtype=torch.int32, device="cuda")
@@ -222,11 +231,14 @@ def bench_dense(args):
            "config": {"workload": f"dense_16^6: {S} states, {A} actions, CP rank 8, dense "
                                   "16x16 Dirichlet(0.5) factors, gamma 0.95",
                       "eps": eps, "sweeps_per_solve": tot / args.steps},
-           "roofline": {"bound": "valu", "achieved": flops / (ms * 1e-3) / 1e12,
-                        "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                        "frac": flops / (ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS,
-                        "traffic": None, "kernel": "chain_pass1 + chain_pass2 (one sweep)",
-                        "kernel_ms": ms}}
+           "roofline": {"bound": "mfma", "achieved": flops / (ms * 1e-3) / 1e12,
+                        "peak": peak, "unit": "TFLOP/s",
+                        "frac": flops / (ms * 1e-3) / 1e12 / peak,
+                        "traffic": _traffic(f"chain_{args.precision}_dense6_16.md", CHAIN_SRC),
+                        "kernel": "chain_pass1_rows + chain_pass2 (one sweep)",
+                        "kernel_ms": ms, "algorithmic_flops_per_launch": flops,
+                        "intermediate_bytes_per_launch": w_bytes,
+                        "hbm_rate_gbs": w_bytes / (ms * 1e-3) / 1e9}}
     model.close()
     return out
 
@@ -250,6 +262,15 @@ def bench_batch(args):
     B.cpmdp_batch_autotune(bm.b, True, None)
     tune_s = time.perf_counter() - t0
     ts, k = B.cpmdp_batch_config(bm.b)
+    # dominant kernel: the FP32 sweep over the whole batch, per launch
+    sweep_ms = B.cpmdp_batch_time_sweeps(bm.b, 20)
+    algo_bytes = sum(12.0 * x.n_states + x.n_states / 8.0 for x in insts)
+    achieved = algo_bytes / (sweep_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": _traffic("batch_sweep_fp32_batch512.md", BATCH_SRC),
+            "kernel": "batch_sweep_kernel<float, MODE_MAX> (all 512 instances)",
+            "kernel_ms": sweep_ms, "algorithmic_bytes_per_launch": algo_bytes}
     Vs = [torch.zeros(x.n_states, dtype=torch.float64, device="cuda") for x in insts]
     pis = [torch.zeros(x.n_states, dtype=torch.int32, device="cuda") for x in insts]
 
@@ -306,7 +327,7 @@ def bench_batch(args):
                        "tile_states": ts, "sweeps_per_graph": k, "autotune_s": tune_s},
             "time_to_eps_s": el / args.steps, "plain_vi_time_to_eps_s": plain,
             "plain_vi_sweeps": plain_sweeps,
-            "speedup_vs_plain_vi": plain / (el / args.steps)}
+            "speedup_vs_plain_vi": plain / (el / args.steps), "roofline": roof}
 
 
 def bench_warm(args):
@@ -403,6 +424,20 @@ def kernel_only(args):
     from paper_2103_00331_amd import binding as B
     from paper_2103_00331_amd import instances as I
 
+    if args.workload == "batch512":
+        insts = [I.batch_instance(i) for i in range(512)]
+        bm = B.BatchModel(insts)
+        B.cpmdp_batch_autotune(bm.b, True, None)
+        ms = B.cpmdp_batch_time_sweeps(bm.b, args.sweeps)
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
+        dst = torch.empty_like(src)
+        torch.mul(src, 2.0, out=dst)
+        torch.cuda.synchronize()
+        print(json.dumps({"kernel_only": args.workload, "sweeps": args.sweeps, "kernel_ms": ms,
+                          "tile_states": B.cpmdp_batch_config(bm.b)[0],
+                          "copy_bytes": src.numel() * 4}), flush=True)
+        bm.close()
+        return
     if args.workload == "dense6_16":
         inst = I.dense_grid(16, seed=I.SEED_DENSE6)
     else:

@@ -270,6 +270,12 @@ int cpmdp_batch_solve(cpmdp_batch_t* b, double* const* V_devs,
 int cpmdp_batch_autotune(cpmdp_batch_t* b, int tune, const char* cache_path);
 int cpmdp_batch_config(const cpmdp_batch_t* b, int32_t* tile_states,
                        int32_t* sweeps_per_graph);
+/* Measurement helper: n FP32 value-iteration sweeps over the whole bound
+ * batch (every instance active, values in the internal FP32 buffers, so the
+ * results are meaningless), each launched with events that record the sweep
+ * kernel's own start and stop; *mean_ms = mean kernel time of one sweep.
+ * A later cpmdp_batch_solve starts from the caller's V as usual. */
+int cpmdp_batch_time_sweeps(cpmdp_batch_t* b, int32_t n, double* mean_ms);
 void cpmdp_batch_destroy(cpmdp_batch_t* b);
 
 /* ------------------------------------------------------- learned warm start

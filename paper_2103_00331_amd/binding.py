@@ -69,6 +69,7 @@ _SIGS = {
                                     C.c_int, C.c_int, _i64p, _dp]),
     "cpmdp_batch_autotune": (C.c_int, [_p, C.c_int, C.c_char_p]),
     "cpmdp_batch_config": (C.c_int, [_p, _i32p, _i32p]),
+    "cpmdp_batch_time_sweeps": (C.c_int, [_p, C.c_int32, _dp]),
     "cpmdp_batch_destroy": (None, [_p]),
     "cpmdp_mlp_param_count": (C.c_int, [_i64p]),
     "cpmdp_mlp_workspace_bytes": (C.c_int, [C.c_int32, _szp]),
@@ -256,6 +257,12 @@ def cpmdp_batch_solve(b, Vs, pis=None, eps=1e-6, max_iter=100000, precision=CPMD
                                         int(precision), int(method),
                                         sweeps.ctypes.data_as(_i64p), res.ctypes.data_as(_dp)))
     return code, sweeps, res
+
+
+def cpmdp_batch_time_sweeps(b, n):
+    ms = C.c_double(0.0)
+    _check(lib.cpmdp_batch_time_sweeps(b, int(n), C.byref(ms)))
+    return ms.value
 
 
 def cpmdp_batch_autotune(b, tune=True, cache_path=None):

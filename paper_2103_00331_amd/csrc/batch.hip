@@ -1055,6 +1055,40 @@ int cpmdp_batch_autotune(cpmdp_batch_t* b, int tune, const char* cache_path) {
   return CPMDP_OK;
 }
 
+int cpmdp_batch_time_sweeps(cpmdp_batch_t* b, int32_t n, double* mean_ms) {
+  if (!b || n < 1 || !mean_ms) return cpm::fail(nullptr, CPMDP_E_ARG, "bad batch_time_sweeps arguments");
+  if (!b->bound) return bfail(b, CPMDP_E_STATE, "batch is not bound");
+  for (auto& d : b->hd) {
+    d.stage = B_F32;
+    d.stop = -1.0;
+  }
+  int rc = upload_descs(b);
+  if (rc) return rc;
+  int64_t nt = 0;
+  rc = upload_tiles(b, std::vector<char>(b->hs.size(), 1), &nt);
+  if (rc) return rc;
+  zero_res(b, 1);
+  std::vector<hipEvent_t> ev(2 * static_cast<size_t>(n));
+  for (auto& e : ev) BHIP(b, hipEventCreate(&e));
+  const BatchArgs a = make_args(b);
+  for (int i = 0; i < n; ++i) {
+    const LaunchTiming tm{ev[2 * i], ev[2 * i + 1]};
+    klaunch(batch_sweep_kernel<float, MODE_MAX>, dim3(b->grid), dim3(kBBlock), 0, b->stream, &tm,
+            a, 0);
+  }
+  BHIP(b, hipGetLastError());
+  BHIP(b, hipStreamSynchronize(b->stream));
+  double tot = 0.0;
+  for (int i = 0; i < n; ++i) {
+    float ms = 0.f;
+    BHIP(b, hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]));
+    tot += ms;
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  *mean_ms = tot / n;
+  return CPMDP_OK;
+}
+
 int cpmdp_batch_config(const cpmdp_batch_t* b, int32_t* tile_states, int32_t* sweeps_per_graph) {
   if (!b || !tile_states || !sweeps_per_graph) return cpm::fail(nullptr, CPMDP_E_ARG, "NULL argument");
   *tile_states = b->tile_states;

@@ -88,6 +88,23 @@ def test_small_batch_policy_iteration_matches_oracle(B):
         compare_policy(pi, oracle.sparse.q_values(x, mats, Vs), eps / (1 - x.gamma) + 1e-12)
 
 
+def test_batch_time_sweeps_then_solve(B):
+    """The timing helper runs whole-batch sweeps on internal buffers; a solve
+    afterwards still starts from the caller's V and matches the oracle."""
+    insts = _small_batch(count=4, seed=21)
+    bm = B.BatchModel(insts)
+    ms = B.cpmdp_batch_time_sweeps(bm.b, 5)
+    assert ms > 0
+    Vs = [torch.zeros(x.n_states, dtype=torch.float64, device="cuda") for x in insts]
+    pis = [torch.zeros(x.n_states, dtype=torch.int32, device="cuda") for x in insts]
+    code, sweeps, res = B.cpmdp_batch_solve(bm.b, Vs, pis, 1e-9, 200000, 1, 0)
+    assert code == B.CPMDP_OK
+    for x, V in zip(insts, Vs):
+        Vo, _, _, _ = oracle.sparse.value_iteration(x)
+        assert_close(V.cpu().numpy(), Vo, 1e-9 / (1 - x.gamma) + tol_for(0, Vo), x.name)
+    bm.close()
+
+
 def test_batch_policy_iteration_rejects_bad_policy(B):
     insts = _small_batch(count=2, seed=19)
     bm = B.BatchModel(insts)
