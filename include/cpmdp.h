@@ -174,8 +174,12 @@ int cpmdp_policy_backup(cpmdp_t* h, const void* V_in, void* V_out,
  *   pi_out    : device int32 [S] greedy policy of the returned V, or NULL.
  *   eps       : absolute residual target (> 0).
  *   max_iter  : cap on backup sweeps (>= 1).
- *   precision : sweep arithmetic; FP32/BF16 sweeps are followed by FP64
- *               sweeps until the FP64 residual meets eps.
+ *   precision : sweep arithmetic; FP32/BF16 sweeps run until they reach their
+ *               rounding floor, then FP64 sweeps continue until the FP64
+ *               residual meets eps (shift/identity path); on the dense path,
+ *               whose FP64 chain runs on the vector ALUs, the tail instead
+ *               refines the greedy policy's evaluation: FP64 residual, low-
+ *               precision correction sweeps, V += e, FP64 certificate.
  *   sweeps_out, residual_out : nullable; sweeps run, and the FP64 residual
  *               ||B V - V||_inf of the returned V.
  * Returns CPMDP_OK, or CPMDP_NOT_CONVERGED (outputs valid, best iterate),

@@ -941,17 +941,53 @@ int cpmdp_value_iteration(cpmdp_t* h, double* V, int32_t* pi_out, double eps, in
     launch_f32_to_f64(cur, V, h->S, st);
   }
   double cert = INFINITY;
-  for (;;) {
-    double* cur = V;
-    double* alt = h->d.Va64;
-    rc = run_sweeps<double>(h, true, MODE_MAX, cur, alt, h->d.R64, nullptr, eps, 0.0,
-                            max_iter - 1, &sweeps, &done, &last, false);
-    if (rc) return rc;
-    if (cur != V) HIP_TRY(h, hipMemcpyAsync(V, cur, h->S * 8, hipMemcpyDeviceToDevice, st));
-    rc = certify(h, V, pi_out, nullptr, &cert, nullptr);
-    if (rc) return rc;
-    ++sweeps;
-    if (cert <= eps || sweeps >= max_iter) break;
+  if (precision != CPMDP_FP64 && h->path == CPMDP_PATH_DENSE) {
+    // Dense FP64 chains run on the vector ALUs, many times slower than the
+    // low-precision chain.  Finish instead by refining the evaluation of the
+    // greedy policy: FP64 certificate and policy, FP64 residual r of
+    // V = R + gamma P_pi V, low-precision correction sweeps
+    // e <- r + gamma P_pi e, V += e; repeat until certified.
+    int32_t* pol = pi_out ? pi_out : h->d.piA;
+    bool have_pol = false;
+    std::vector<double> r;
+    for (;;) {
+      rc = certify(h, V, pol, have_pol ? pol : nullptr, &cert, nullptr);
+      if (rc) return rc;
+      have_pol = true;
+      ++sweeps;
+      if (cert <= eps || sweeps >= max_iter) break;
+      zero_slots(h, 1);
+      sweep(h, true, MODE_RESID, V, nullptr, h->d.R64, pol, nullptr, h->d.r32, h->d.slots,
+            nullptr, false);
+      rc = check_device(h);
+      if (rc) return rc;
+      rc = read_slots(h, 1, r, nullptr);
+      if (rc) return rc;
+      ++sweeps;
+      if (!std::isfinite(r[0])) return fail(h, CPMDP_E_NONFINITE, "non-finite residual");
+      launch_fill_f32(h->d.E0, h->S, 0.0f, st);
+      float* cur = h->d.E0;
+      float* alt = h->d.E1;
+      const double tol_e = std::max(0.25 * eps, 1e-3 * r[0]);
+      rc = run_sweeps<float>(h, false, MODE_EVAL, cur, alt, h->d.r32, pol, tol_e,
+                             precision == CPMDP_BF16 ? INFINITY : 0.0, max_iter - 1, &sweeps,
+                             &done, &last, precision == CPMDP_BF16);
+      if (rc) return rc;
+      launch_add_f32_to_f64(V, cur, h->S, st);
+    }
+  } else {
+    for (;;) {
+      double* cur = V;
+      double* alt = h->d.Va64;
+      rc = run_sweeps<double>(h, true, MODE_MAX, cur, alt, h->d.R64, nullptr, eps, 0.0,
+                              max_iter - 1, &sweeps, &done, &last, false);
+      if (rc) return rc;
+      if (cur != V) HIP_TRY(h, hipMemcpyAsync(V, cur, h->S * 8, hipMemcpyDeviceToDevice, st));
+      rc = certify(h, V, pi_out, nullptr, &cert, nullptr);
+      if (rc) return rc;
+      ++sweeps;
+      if (cert <= eps || sweeps >= max_iter) break;
+    }
   }
   if (sweeps_out) *sweeps_out = sweeps;
   if (residual_out) *residual_out = cert;
