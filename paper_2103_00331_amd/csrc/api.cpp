@@ -71,12 +71,11 @@ int64_t chain_lds_bytes(const ChainGeom& g, size_t b) {
   // pass 2: the tile, plus (FP32 chains on the matrix cores) the row-group
   // factors of one term staged as FP32 or as BF16 hi + lo
   const int64_t rows_len = (g.n1 < g.n) ? g.fac_off[g.n1] : g.term_stride;
-  const int64_t p2 = static_cast<int64_t>(b) * (TE + (TE >> 5) + 2) + (b == 4 ? 4 * rows_len : 0) +
-                     1024 + 256;
+  const int64_t p2 = static_cast<int64_t>(b) * (TE + (TE >> 5) + 2 + rows_len) + 1024 + 256;
   const int64_t cols_len = g.term_stride - ((g.n1 < g.n) ? g.fac_off[g.n1] : g.term_stride);
   const int64_t p1 = (g.n1 == g.n) ? 0
-                     : (g.r1 > 0) ? static_cast<int64_t>(b) * g.r1 * (g.C + (g.C >> 5) + 1) +
-                                        4 * cols_len + 512
+                     : (g.r1 > 0) ? static_cast<int64_t>(b) * (g.r1 * (g.C + (g.C >> 5) + 1) +
+                                                               cols_len) + 512
                                   : static_cast<int64_t>(b) * (2 * (g.C + (g.C >> 5) + 1) + 2) + 256;
   return std::max(p1, p2);
 }
@@ -161,7 +160,7 @@ static bool choose_split(const std::vector<int64_t>& sizes, int64_t S, size_t b,
   if (best_n1 < n && g.C <= 64 * 64) {
     const int64_t cols_len = g.term_stride - g.fac_off[best_n1];
     for (int r1 = 8; r1 >= 2; r1 /= 2) {
-      const int64_t lds = static_cast<int64_t>(b) * r1 * (g.C + (g.C >> 5) + 1) + 4 * cols_len + 512;
+      const int64_t lds = static_cast<int64_t>(b) * (r1 * (g.C + (g.C >> 5) + 1) + cols_len) + 512;
       if (lds <= kLdsBytes && r1 <= g.Rr) {
         g.r1 = r1;
         break;
@@ -330,7 +329,7 @@ void sweep(cpmdp_t* h, bool prec64, int mode, const void* V, void* Vout, const v
     a.change_count = ctr;
     a.facbf = nullptr;
     a.facbf_lo = nullptr;
-    launch_chain<double>(a, mode, CHAIN_VALU, st, tm);
+    launch_chain<double>(a, mode, CHAIN_F64_MFMA, st, tm);
   } else {
     ChainArgs<float> a{};
     a.g = h->cg32;

@@ -84,9 +84,19 @@ __device__ __forceinline__ void mode_product_lds(const T* Xs, T* X, int outer, i
 // matrix products and writes the outputs to the same LDS slots afterwards, so
 // the product is in place without a barrier between blocks.
 typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d4v __attribute__((ext_vector_type(4)));
 typedef short s4v __attribute__((ext_vector_type(4)));
 
-enum { MM_VALU = 0, MM_F32 = 1, MM_BF16 = 2 };
+// MM_F64: FP64 chains on the FP64 16x16x4 matrix product: operands as the
+// FP32 one, but result register r of lane (g, c) holds D[i = g + 4r][fiber c].
+enum { MM_VALU = 0, MM_F32 = 1, MM_BF16 = 2, MM_F64 = 3 };
+
+template <typename T>
+struct AccOf;
+template <>
+struct AccOf<float> { using type = f4v; };
+template <>
+struct AccOf<double> { using type = d4v; };
 
 // BF16 hi + lo split of four FP32 values (hardware round to nearest even).
 __device__ __forceinline__ void split_bf16(const float (&x)[4], s4v& hi, s4v& lo) {
@@ -99,14 +109,17 @@ __device__ __forceinline__ void split_bf16(const float (&x)[4], s4v& hi, s4v& lo
 }
 
 // One 16 x 16 x 16 product: rows k of the B operand held by this lane are
-// x[0..3] (fp32: k = 4q + g for x[q]; bf16: k = 4g + r for x[r]).
-template <int MM>
-__device__ __forceinline__ f4v mfma_block(const float (&x)[4], const float (&a32)[4], s4v ahi,
-                                          s4v alo) {
-  f4v acc = {0.f, 0.f, 0.f, 0.f};
-  if (MM == MM_F32) {
+// x[0..3] (fp32 / fp64: k = 4q + g for x[q]; bf16: k = 4g + r for x[r]).
+template <typename T, int MM>
+__device__ __forceinline__ typename AccOf<T>::type mfma_block(const T (&x)[4], const T (&aw)[4],
+                                                              s4v ahi, s4v alo) {
+  typename AccOf<T>::type acc = {T(0), T(0), T(0), T(0)};
+  if constexpr (MM == MM_F64) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a32[q], x[q], acc, 0, 0, 0);
+    for (int q = 0; q < 4; ++q) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(aw[q], x[q], acc, 0, 0, 0);
+  } else if constexpr (MM == MM_F32) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(aw[q], x[q], acc, 0, 0, 0);
   } else {
     s4v bhi, blo;
     split_bf16(x, bhi, blo);
@@ -117,10 +130,9 @@ __device__ __forceinline__ f4v mfma_block(const float (&x)[4], const float (&a32
   return acc;
 }
 
-template <int MM, bool WAVE>
-__device__ __forceinline__ void mode_product_mfma(const float* Xs, float* X, int outer, int m,
-                                                  int inner, FastDiv dv,
-                                                  const float* __restrict__ Tk,
+template <typename T, int MM, bool WAVE>
+__device__ __forceinline__ void mode_product_mfma(const T* Xs, T* X, int outer, int m, int inner,
+                                                  FastDiv dv, const T* __restrict__ Tk,
                                                   const uint16_t* __restrict__ Th,
                                                   const uint16_t* __restrict__ Tl) {
   const int lane = threadIdx.x & 63;
@@ -128,13 +140,13 @@ __device__ __forceinline__ void mode_product_mfma(const float* Xs, float* X, int
   const int c = lane & 15, g = lane >> 4;
   const int F = outer * inner;
   const int nblk = (F + 15) >> 4;
-  float a32[4];
+  T aw[4];
   s4v ahi, alo;
-  if (MM == MM_F32) {
+  if (MM != MM_BF16) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int k = 4 * q + g;
-      a32[q] = (c < m && k < m) ? Tk[c * m + k] : 0.f;
+      aw[q] = (c < m && k < m) ? Tk[c * m + k] : T(0);
     }
   } else {
 #pragma unroll
@@ -145,8 +157,9 @@ __device__ __forceinline__ void mode_product_mfma(const float* Xs, float* X, int
       alo[r] = in ? static_cast<short>(Tl[c * m + k]) : static_cast<short>(0);
     }
   }
-  // row of the B operand held in x[j] / row of the result in acc[j]
-  auto rd_row = [&](int j) { return MM == MM_F32 ? 4 * j + g : 4 * g + j; };
+  // row of the B operand held in x[j] / row of the result in acc[r]
+  auto rd_row = [&](int j) { return MM != MM_BF16 ? 4 * j + g : 4 * g + j; };
+  auto wr_row = [&](int r) { return MM == MM_F64 ? g + 4 * r : 4 * g + r; };
   auto block_base = [&](int b) {
     const int f = b * 16 + c;
     const int o = static_cast<int>(fdiv(static_cast<uint32_t>(f), dv));
@@ -159,35 +172,35 @@ __device__ __forceinline__ void mode_product_mfma(const float* Xs, float* X, int
       const bool two = b0 + nw < nblk;                 // wave-uniform
       const int base0 = block_base(b0);
       const int base1 = block_base(two ? b0 + nw : b0);
-      float x0[4], x1[4];
+      T x0[4], x1[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         x0[j] = Xs[lpad(base0 + rd_row(j) * inner)];
         x1[j] = Xs[lpad(base1 + rd_row(j) * inner)];
       }
-      const f4v d0 = mfma_block<MM>(x0, a32, ahi, alo);
-      const f4v d1 = mfma_block<MM>(x1, a32, ahi, alo);
+      const auto d0 = mfma_block<T, MM>(x0, aw, ahi, alo);
+      const auto d1 = mfma_block<T, MM>(x1, aw, ahi, alo);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) X[lpad(base0 + (4 * g + r) * inner)] = d0[r];
+      for (int r = 0; r < 4; ++r) X[lpad(base0 + wr_row(r) * inner)] = d0[r];
       if (two) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) X[lpad(base1 + (4 * g + r) * inner)] = d1[r];
+        for (int r = 0; r < 4; ++r) X[lpad(base1 + wr_row(r) * inner)] = d1[r];
       }
     }
   } else {
     for (int b = wave; b < nblk; b += nw) {
       const bool ok = b * 16 + c < F;
       const int base = ok ? block_base(b) : 0;
-      float x[4];
+      T x[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int k = rd_row(j);
-        x[j] = (ok && k < m) ? Xs[lpad(base + k * inner)] : 0.f;
+        x[j] = (ok && k < m) ? Xs[lpad(base + k * inner)] : T(0);
       }
-      const f4v d = mfma_block<MM>(x, a32, ahi, alo);
+      const auto d = mfma_block<T, MM>(x, aw, ahi, alo);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = 4 * g + r;
+        const int i = wr_row(r);
         if (ok && i < m) X[lpad(base + i * inner)] = d[r];
       }
     }
@@ -204,7 +217,7 @@ __device__ __forceinline__ void mode_product(const T* Xs, T* X, int outer, int m
   if constexpr (MM == MM_VALU) {
     mode_product_lds<T, MMAX, WAVE>(Xs, X, outer, m, inner, dv, Tk);
   } else {
-    mode_product_mfma<MM, WAVE>(Xs, X, outer, m, inner, dv, Tk, Th, Tl);
+    mode_product_mfma<T, MM, WAVE>(Xs, X, outer, m, inner, dv, Tk, Th, Tl);
   }
 }
 
@@ -270,7 +283,7 @@ __global__ __launch_bounds__(kPass1RowsBlock) void chain_pass1_rows(ChainArgs<T>
   constexpr bool STAGE = (MM != MM_VALU);
   const int cols_off = a.g.fac_off[n1];
   const int cols_len = a.g.term_stride - cols_off;
-  float* Fs = reinterpret_cast<float*>(base + R1 * slab);
+  T* Fs = base + R1 * slab;
   uint16_t* Fh = reinterpret_cast<uint16_t*>(Fs);
   uint16_t* Fl = Fh + cols_len;
   const int r0 = xcd_block(blockIdx.x, gridDim.x) * R1;
@@ -290,7 +303,7 @@ __global__ __launch_bounds__(kPass1RowsBlock) void chain_pass1_rows(ChainArgs<T>
   const int total = a.g.ntiles << chunk_shift;
   // factors of the next term, loaded before the write-out of the current one
   // (cols_len <= 8 * 16^2 = 4 * kPass1RowsBlock)
-  float nf[4];
+  T nf[4];
   uint16_t nh[4], nl[4];
   auto load_fac = [&](int t) {
     if constexpr (STAGE) {
@@ -299,7 +312,7 @@ __global__ __launch_bounds__(kPass1RowsBlock) void chain_pass1_rows(ChainArgs<T>
       for (int j = 0; j < 4; ++j) {
         const int i = threadIdx.x + j * blockDim.x;
         if (i < cols_len) {
-          if (MM == MM_F32) {
+          if (MM != MM_BF16) {
             nf[j] = a.fac[fb + i];
           } else {
             nh[j] = a.facbf[fb + i];
@@ -316,7 +329,7 @@ __global__ __launch_bounds__(kPass1RowsBlock) void chain_pass1_rows(ChainArgs<T>
       for (int j = 0; j < 4; ++j) {
         const int i = threadIdx.x + j * blockDim.x;
         if (i < cols_len) {
-          if (MM == MM_F32) {
+          if (MM != MM_BF16) {
             Fs[i] = nf[j];
           } else {
             Fh[i] = nh[j];
@@ -402,10 +415,10 @@ __global__ __launch_bounds__(kPass2Block) void chain_pass2(ChainArgs<T> a) {
   // products waits behind the tile prefetch.
   constexpr bool STAGE = (MM != MM_VALU);
   const int rows_len = (n1 < n) ? a.g.fac_off[n1] : a.g.term_stride;
-  float* Fs = reinterpret_cast<float*>(X + lpad(TE) + 1);
+  T* Fs = X + lpad(TE) + 1;
   uint16_t* Fh = reinterpret_cast<uint16_t*>(Fs);
   uint16_t* Fl = Fh + rows_len;
-  float nf[kStageRegs];
+  T nf[kStageRegs];
   uint16_t nh[kStageRegs], nl[kStageRegs];
 
   T acc[EPT], best[EPT], qold[EPT];
@@ -478,7 +491,7 @@ __global__ __launch_bounds__(kPass2Block) void chain_pass2(ChainArgs<T> a) {
       for (int i = 0; i < kStageRegs; ++i) {
         const int idx = threadIdx.x + i * kPass2Block;
         if (idx < rows_len) {
-          if (MM == MM_F32) {
+          if (MM != MM_BF16) {
             nf[i] = a.fac[base + idx];
           } else {
             nh[i] = a.facbf[base + idx];
@@ -500,7 +513,7 @@ __global__ __launch_bounds__(kPass2Block) void chain_pass2(ChainArgs<T> a) {
       for (int i = 0; i < kStageRegs; ++i) {
         const int idx = threadIdx.x + i * kPass2Block;
         if (idx < rows_len) {
-          if (MM == MM_F32) {
+          if (MM != MM_BF16) {
             Fs[idx] = nf[i];
           } else {
             Fh[idx] = nh[i];
@@ -639,7 +652,7 @@ static void launch_pass1_m(const ChainArgs<T>& a, hipStream_t st, const LaunchTi
     const int R1 = a.g.r1;
     const int cols_len = a.g.term_stride - a.g.fac_off[a.g.n1];
     const size_t sh = sizeof(T) * static_cast<size_t>(R1) * (a.g.C + (a.g.C >> 5) + 1) +
-                      (MM != MM_VALU ? 4 * static_cast<size_t>(cols_len) : 0);
+                      (MM != MM_VALU ? sizeof(T) * static_cast<size_t>(cols_len) : 0);
     const dim3 grid((a.g.Rr + R1 - 1) / R1), block(64 * R1);
     const int pv = (a.g.C + 63) / 64;
     if (pv <= 16) klaunch(chain_pass1_rows<T, MMAX, MM, 16>, grid, block, sh, st, tm, a);
@@ -657,7 +670,7 @@ static void launch_pass2_mm(const ChainArgs<T>& a, hipStream_t st, const LaunchT
   const int ept = (TE + kPass2Block - 1) / kPass2Block;
   const int rows_len = (a.g.n1 < a.g.n) ? a.g.fac_off[a.g.n1] : a.g.term_stride;
   const size_t sh = sizeof(T) * (static_cast<size_t>(TE) + (TE >> 5) + 2) +
-                    (MM != MM_VALU ? 4 * static_cast<size_t>(rows_len) : 0);
+                    (MM != MM_VALU ? sizeof(T) * static_cast<size_t>(rows_len) : 0);
   const dim3 grid(a.g.ntiles), block(kPass2Block);
   if (ept <= 2) klaunch(chain_pass2<T, MMAX, MODE, 2, MM>, grid, block, sh, st, tm, a);
   else if (ept <= 4) klaunch(chain_pass2<T, MMAX, MODE, 4, MM>, grid, block, sh, st, tm, a);
@@ -681,6 +694,7 @@ static void launch_pass2_m(const ChainArgs<T>& a, int mode, hipStream_t st,
 static int pick_unit(int mmax, int unit) {
   if (unit == CHAIN_BF16) return mmax <= 16 ? MM_BF16 : MM_VALU;
   if (unit == CHAIN_F32_MFMA) return (mmax > 4 && mmax <= 16) ? MM_F32 : MM_VALU;
+  if (unit == CHAIN_F64_MFMA) return (mmax > 4 && mmax <= 16) ? MM_F64 : MM_VALU;
   return MM_VALU;
 }
 
@@ -689,6 +703,8 @@ static void launch_pass1(const ChainArgs<T>& a, int mm, hipStream_t st, const La
   if constexpr (std::is_same<T, float>::value) {
     if (mm == MM_F32) return launch_pass1_m<T, 16, MM_F32>(a, st, tm);
     if (mm == MM_BF16) return launch_pass1_m<T, 16, MM_BF16>(a, st, tm);
+  } else {
+    if (mm == MM_F64) return launch_pass1_m<T, 16, MM_F64>(a, st, tm);
   }
   switch (pick_mmax(a.g.mmax_col)) {
     case 4: return launch_pass1_m<T, 4, MM_VALU>(a, st, tm);
@@ -703,6 +719,8 @@ static void launch_pass2(const ChainArgs<T>& a, int mode, int mm, hipStream_t st
   if constexpr (std::is_same<T, float>::value) {
     if (mm == MM_F32) return launch_pass2_m<T, 16, MM_F32>(a, mode, st, tm);
     if (mm == MM_BF16) return launch_pass2_m<T, 16, MM_BF16>(a, mode, st, tm);
+  } else {
+    if (mm == MM_F64) return launch_pass2_m<T, 16, MM_F64>(a, mode, st, tm);
   }
   switch (pick_mmax(a.g.mmax_row)) {
     case 4: return launch_pass2_m<T, 4, MM_VALU>(a, mode, st, tm);
@@ -715,12 +733,11 @@ static void launch_pass2(const ChainArgs<T>& a, int mode, int mm, hipStream_t st
 template <typename T>
 void launch_chain(const ChainArgs<T>& a, int mode, int unit, hipStream_t st,
                   const LaunchTiming* tm) {
-  const bool f32 = std::is_same<T, float>::value;
   const bool two = a.g.n1 < a.g.n;
   const LaunchTiming t1{tm ? tm->start : nullptr, nullptr};
   const LaunchTiming t2{two ? nullptr : (tm ? tm->start : nullptr), tm ? tm->stop : nullptr};
-  if (two) launch_pass1(a, f32 ? pick_unit(a.g.mmax_col, unit) : MM_VALU, st, tm ? &t1 : nullptr);
-  launch_pass2(a, mode, f32 ? pick_unit(a.g.mmax_row, unit) : MM_VALU, st, tm ? &t2 : nullptr);
+  if (two) launch_pass1(a, pick_unit(a.g.mmax_col, unit), st, tm ? &t1 : nullptr);
+  launch_pass2(a, mode, pick_unit(a.g.mmax_row, unit), st, tm ? &t2 : nullptr);
 }
 
 template void launch_chain<double>(const ChainArgs<double>&, int, int, hipStream_t,

@@ -144,12 +144,12 @@ struct ChainArgs {
   const unsigned long long* shift_keys;
 };
 
-// Unit for FP32 chains: vector ALUs, FP32 matrix cores, or BF16 operands on
-// matrix cores with FP32 accumulation (modes with m_k <= 16 only; larger
-// modes run on vector ALUs in FP32).  The BF16 unit splits every operand
-// into hi + lo BF16 parts and sums the products hi*hi + hi*lo + lo*hi.
-// FP64 chains always use vector ALUs.
-enum ChainUnit { CHAIN_VALU = 0, CHAIN_F32_MFMA = 1, CHAIN_BF16 = 2 };
+// Unit of a chain's mode products: vector ALUs, FP32 or FP64 matrix cores,
+// or BF16 operands on matrix cores with FP32 accumulation (matrix cores for
+// modes with m_k <= 16 only; larger modes run on the vector ALUs in the
+// chain's precision).  The BF16 unit splits every operand into hi + lo BF16
+// parts and sums the products hi*hi + hi*lo + lo*hi.
+enum ChainUnit { CHAIN_VALU = 0, CHAIN_F32_MFMA = 1, CHAIN_BF16 = 2, CHAIN_F64_MFMA = 3 };
 
 template <typename T>
 void launch_chain(const ChainArgs<T>& a, int mode, int unit, hipStream_t st,
