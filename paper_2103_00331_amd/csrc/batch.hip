@@ -35,6 +35,7 @@ constexpr int kBMaxN = 4;        // dims supported by the batched kernels
 constexpr int kBSpread = 4;      // residual words per (sweep, instance)
 constexpr int kBMaxK = 64;       // sweeps per graph, at most
 constexpr int kBBlock = 256;
+constexpr int64_t kBMarchMinPlane = 16384;   // plane size from which instances march
 
 enum BStage : int32_t { B_F32 = 0, B_F64 = 1, B_CERT = 2, B_DONE = 3 };
 
@@ -42,6 +43,7 @@ struct BInst {
   GridGeom g;
   int32_t A, vec, axis, stage;
   int32_t parity, eparity;     // V ping-pong; PI correction (V32 = e) ping-pong
+  int32_t mtiles, pad_m;        // > 0: marching tiles of 1024 plane offsets per plane
   float gamma32, pad1;
   double gamma64;
   float base32[2 * kBMaxN + 1];
@@ -61,10 +63,14 @@ struct BInst {
 };
 static_assert(sizeof(BInst) % 4 == 0, "descriptor copied as words");
 
+// Tile (instance, y): y >= 0: states [y, y + tile_states) of the instance;
+// y < 0: marching tile q = -1 - y, plane offsets [1024 (q % mtiles), + 1024)
+// over all planes of the instance (see march_column).
 struct BatchArgs {
   const BInst* insts;
-  const int2* tiles;            // (instance, first state)
+  const int2* tiles;
   const int* ntiles;            // device-resident count (graphs stay valid)
+  const int* starts;            // [2][gridDim.x + 1] first tile of each block, per group
   int32_t tile_states;
   int32_t ninst;
   unsigned long long* res;      // [kBMaxK][ninst][kBSpread] FP64 bits
@@ -116,16 +122,37 @@ __device__ __forceinline__ void tile_dispatch(const BInst& d, const StencilIO<T>
   }
 }
 
-// Tiles [base, base + count) of the table, split into contiguous ranges per
-// block (numbered XCD-aware).  ntiles[0] = FP32 tiles, ntiles[1] = FP64
-// tiles (listed after the FP32 ones).
+// The tiles of one group (0: FP32 or the only group, 1: FP64, listed after
+// group 0) are split into contiguous ranges of about equal work, one per
+// block (numbered XCD-aware), by the host: starts[group][b].
 __device__ __forceinline__ void tile_range(const BatchArgs& a, int which, int& t0, int& t1) {
-  const int base = which ? a.ntiles[0] : 0;
-  const int nt = a.ntiles[which];
-  const int per = (nt + gridDim.x - 1) / gridDim.x;
   const int blk = xcd_block(blockIdx.x, gridDim.x);
-  t0 = base + blk * per;
-  t1 = base + min(blk * per + per, nt);
+  const int* st = a.starts + which * (gridDim.x + 1);
+  t0 = st[blk];
+  t1 = st[blk + 1];
+}
+
+template <typename T, int MODE, int N>
+__device__ __forceinline__ void march_dispatch_n(const BInst& d, const StencilIO<T>& io,
+                                                 const StencilW<T>& W, int p, T& res,
+                                                 double& res_d, unsigned& ch) {
+  if constexpr (N >= 2) {
+    if (d.axis) march_column<T, N, MODE, true>(d.g, io, W, p, 0, d.g.size[0], T(0), res, res_d, ch);
+    else march_column<T, N, MODE, false>(d.g, io, W, p, 0, d.g.size[0], T(0), res, res_d, ch);
+  }
+}
+
+// Marching tile: thread handles plane offset p for every plane.
+template <typename T, int MODE>
+__device__ __forceinline__ void march_dispatch(const BInst& d, const StencilIO<T>& io,
+                                               const StencilW<T>& W, int q, T& res, double& res_d,
+                                               unsigned& ch) {
+  const int p = (q % d.mtiles) * (kBBlock * 4) + threadIdx.x * 4;
+  switch (d.g.n) {
+    case 2: march_dispatch_n<T, MODE, 2>(d, io, W, p, res, res_d, ch); break;
+    case 3: march_dispatch_n<T, MODE, 3>(d, io, W, p, res, res_d, ch); break;
+    default: march_dispatch_n<T, MODE, 4>(d, io, W, p, res, res_d, ch); break;
+  }
 }
 
 template <typename T>
@@ -177,12 +204,14 @@ __global__ __launch_bounds__(kBBlock) void batch_sweep_kernel(BatchArgs a, int j
       const StencilIO<float> io{d.V32[pin], d.V32[pin ^ 1], d.r32, d.tbits, d.pi_out, nullptr,
                                 nullptr};
       const StencilW<float> W{d.base32, d.axis32, d.w32, d.w32, d.A, d.gamma32};
-      tile_dispatch<float, MODE_EVAL>(d, io, W, s0, s1, 0.f, res, rd, ch);
+      if (tl.y < 0) march_dispatch<float, MODE_EVAL>(d, io, W, -1 - tl.y, res, rd, ch);
+      else tile_dispatch<float, MODE_EVAL>(d, io, W, s0, s1, 0.f, res, rd, ch);
     } else {
       const int pin = d.parity ^ (j & 1);
       T* const* V = vals(d, T(0));
       const StencilIO<T> io{V[pin], V[pin ^ 1], rew(d, T(0)), d.tbits, nullptr, nullptr, nullptr};
-      tile_dispatch<T, MODE_MAX>(d, io, weights_of<T>(d), s0, s1, T(0), res, rd, ch);
+      if (tl.y < 0) march_dispatch<T, MODE_MAX>(d, io, weights_of<T>(d), -1 - tl.y, res, rd, ch);
+      else tile_dispatch<T, MODE_MAX>(d, io, weights_of<T>(d), s0, s1, T(0), res, rd, ch);
     }
     block_max_to_slot(static_cast<double>(res),
                       a.res + (static_cast<size_t>(j) * a.ninst + tl.x) * kBSpread, kBSpread - 1);
@@ -276,6 +305,7 @@ struct cpmdp_batch {
   BInst* d_insts = nullptr;
   int2* d_tiles = nullptr;
   int* d_ntiles = nullptr;
+  int* d_starts = nullptr;            // [2][kMaxBlocks + 1]
   unsigned long long* d_res = nullptr;
   unsigned long long* d_vmax = nullptr;
   unsigned int* d_changes = nullptr;
@@ -284,6 +314,7 @@ struct cpmdp_batch {
   unsigned long long* h_res = nullptr;
   int2* h_tiles = nullptr;
   int* h_ntiles = nullptr;
+  int* h_starts = nullptr;
   hipEvent_t tiles_copied = nullptr;  // the last tile-table copy out of h_tiles / h_ntiles
   bool tiles_pending = false;
   BInst* h_descs = nullptr;           // pinned staging copy of hd
@@ -327,7 +358,8 @@ size_t inst_bytes(const cpmdp_t* h) {
 size_t fixed_bytes(const cpmdp_batch_t* b, int64_t max_tiles) {
   const size_t n = b->hs.size();
   return al(n * sizeof(BInst)) + al(max_tiles * sizeof(int2)) + al(64) +
-         al(static_cast<size_t>(kBMaxK) * n * kBSpread * 8) + al(n * 8) + al(n * 4);
+         al(static_cast<size_t>(kBMaxK) * n * kBSpread * 8) + al(n * 8) + al(n * 4) +
+         al(2 * (kMaxBlocks + 1) * sizeof(int));
 }
 
 int64_t count_tiles(const cpmdp_batch_t* b, int ts) {
@@ -347,6 +379,7 @@ BatchArgs make_args(cpmdp_batch_t* b) {
   a.insts = b->d_insts;
   a.tiles = b->d_tiles;
   a.ntiles = b->d_ntiles;
+  a.starts = b->d_starts;
   a.tile_states = b->tile_states;
   a.ninst = static_cast<int32_t>(b->hs.size());
   a.res = b->d_res;
@@ -356,30 +389,62 @@ BatchArgs make_args(cpmdp_batch_t* b) {
 }
 
 // Upload the tile table: first the tiles of instances with want == 1 (the
-// FP32 group, or the only group), then those with want == 2 (FP64 group).
-int upload_tiles(cpmdp_batch_t* b, const std::vector<char>& want, int64_t* count) {
-  // h_tiles / h_ntiles are pinned: the previous asynchronous copy out of
-  // them must have run before they are refilled
+// FP32 group, or the only group), then those with want == 2 (FP64 group);
+// with march, instances that allow it get marching tiles.  Each group is
+// split into b->grid contiguous ranges of about equal state counts.
+int upload_tiles(cpmdp_batch_t* b, const std::vector<char>& want, int64_t* count,
+                 bool march = false) {
+  // h_tiles / h_ntiles / h_starts are pinned: the previous asynchronous copy
+  // out of them must have run before they are refilled
   if (b->tiles_pending) {
     BHIP(b, hipEventSynchronize(b->tiles_copied));
     b->tiles_pending = false;
   }
   int64_t nt = 0;
   const int ts = b->tile_states;
+  const int G = b->grid;
   int cnt[2] = {0, 0};
-  for (int grp = 1; grp <= 2; ++grp)
+  std::vector<int64_t> weight;
+  weight.reserve(static_cast<size_t>(b->max_tiles));
+  for (int grp = 1; grp <= 2; ++grp) {
+    const int64_t first = nt;
     for (size_t i = 0; i < b->hs.size(); ++i) {
       if (want[i] != grp) continue;
+      const BInst& d = b->hd[i];
       const int64_t S = b->hs[i]->S;
-      for (int64_t s = 0; s < S; s += ts) {
-        b->h_tiles[nt++] = make_int2(static_cast<int>(i), static_cast<int>(s));
-        ++cnt[grp - 1];
+      if (march && d.mtiles > 0) {
+        const int64_t planes = d.g.size[0];
+        for (int q = 0; q < d.mtiles; ++q) {
+          b->h_tiles[nt++] = make_int2(static_cast<int>(i), -1 - q);
+          weight.push_back(planes * kBBlock * 4);
+        }
+      } else {
+        for (int64_t s = 0; s < S; s += ts) {
+          b->h_tiles[nt++] = make_int2(static_cast<int>(i), static_cast<int>(s));
+          weight.push_back(std::min<int64_t>(ts, S - s));
+        }
       }
     }
+    cnt[grp - 1] = static_cast<int>(nt - first);
+    // contiguous ranges of about equal weight
+    int64_t total = 0;
+    for (int64_t t = first; t < nt; ++t) total += weight[t];
+    int* st = b->h_starts + (grp - 1) * (G + 1);
+    int64_t acc = 0, t = first;
+    st[0] = static_cast<int>(first);
+    for (int k = 1; k <= G; ++k) {
+      const int64_t target = total * k / G;
+      while (t < nt && acc + weight[t] / 2 < target) acc += weight[t++];
+      st[k] = static_cast<int>(t);
+    }
+    st[G] = static_cast<int>(nt);
+  }
   b->h_ntiles[0] = cnt[0];
   b->h_ntiles[1] = cnt[1];
   if (nt) BHIP(b, hipMemcpyAsync(b->d_tiles, b->h_tiles, nt * sizeof(int2), hipMemcpyHostToDevice, b->stream));
   BHIP(b, hipMemcpyAsync(b->d_ntiles, b->h_ntiles, 2 * sizeof(int), hipMemcpyHostToDevice, b->stream));
+  BHIP(b, hipMemcpyAsync(b->d_starts, b->h_starts, 2 * (G + 1) * sizeof(int), hipMemcpyHostToDevice,
+                         b->stream));
   BHIP(b, hipEventRecord(b->tiles_copied, b->stream));
   b->tiles_pending = true;
   *count = nt;
@@ -480,7 +545,7 @@ int time_config(cpmdp_batch_t* b, int ts, int grid, int k, int reps, double* ms_
   int rc = upload_descs(b);
   if (rc) return rc;
   int64_t nt = 0;
-  rc = upload_tiles(b, all, &nt);
+  rc = upload_tiles(b, all, &nt, true);
   if (rc) return rc;
   hipGraphExec_t ex;
   rc = graph_for(b, k, &ex);
@@ -599,7 +664,7 @@ int batch_pi(cpmdp_batch_t* b, double* const* V_devs, int32_t* const* pi_devs, d
       int64_t nt = 0;
       rc = upload_descs(b);
       if (rc) return rc;
-      rc = upload_tiles(b, gc.first, &nt);
+      rc = upload_tiles(b, gc.first, &nt, true);
       if (rc) return rc;
       int64_t left = b->k;
       for (size_t i = 0; i < n; ++i)
@@ -764,9 +829,11 @@ int cpmdp_batch_bind(cpmdp_batch_t* b, void* ws, size_t bytes, void* stream) {
   b->d_res = reinterpret_cast<unsigned long long*>(take(static_cast<size_t>(kBMaxK) * n * kBSpread * 8));
   b->d_vmax = reinterpret_cast<unsigned long long*>(take(n * 8));
   b->d_changes = reinterpret_cast<unsigned int*>(take(n * 4));
+  b->d_starts = reinterpret_cast<int*>(take(2 * (kMaxBlocks + 1) * sizeof(int)));
   if (!b->h_res) {
     BHIP(b, hipHostMalloc(reinterpret_cast<void**>(&b->h_changes), n * 4, hipHostMallocDefault));
     BHIP(b, hipHostMalloc(reinterpret_cast<void**>(&b->h_descs), n * sizeof(BInst), hipHostMallocDefault));
+    BHIP(b, hipHostMalloc(reinterpret_cast<void**>(&b->h_starts), 2 * (kMaxBlocks + 1) * sizeof(int), hipHostMallocDefault));
     BHIP(b, hipHostMalloc(reinterpret_cast<void**>(&b->h_res), static_cast<size_t>(kBMaxK) * n * kBSpread * 8, hipHostMallocDefault));
     BHIP(b, hipHostMalloc(reinterpret_cast<void**>(&b->h_tiles), b->max_tiles * sizeof(int2), hipHostMallocDefault));
     BHIP(b, hipHostMalloc(reinterpret_cast<void**>(&b->h_ntiles), 64, hipHostMallocDefault));
@@ -782,6 +849,11 @@ int cpmdp_batch_bind(cpmdp_batch_t* b, void* ws, size_t bytes, void* stream) {
     d.vec = h->st_vec;
     d.axis = h->st_axis;
     d.stage = B_F32;
+    // marching tiles when the planes of fixed i_0 are large
+    const int64_t plane = h->S / h->sizes[0];
+    d.mtiles = (h->n >= 2 && h->st_vec == 4 && plane >= kBMarchMinPlane && h->sizes[0] >= 8)
+                   ? static_cast<int32_t>((plane + kBBlock * 4 - 1) / (kBBlock * 4))
+                   : 0;
     d.parity = 0;
     d.gamma32 = static_cast<float>(h->gamma);
     d.gamma64 = h->gamma;
@@ -896,7 +968,7 @@ int cpmdp_batch_solve(cpmdp_batch_t* b, double* const* V_devs, int32_t* const* p
       int64_t nt = 0;
       rc = upload_descs(b);
       if (rc) return rc;
-      rc = upload_tiles(b, active, &nt);
+      rc = upload_tiles(b, active, &nt, true);
       if (rc) return rc;
       int64_t left = b->k;
       for (size_t i = 0; i < n; ++i)
@@ -1065,7 +1137,7 @@ int cpmdp_batch_time_sweeps(cpmdp_batch_t* b, int32_t n, double* mean_ms) {
   int rc = upload_descs(b);
   if (rc) return rc;
   int64_t nt = 0;
-  rc = upload_tiles(b, std::vector<char>(b->hs.size(), 1), &nt);
+  rc = upload_tiles(b, std::vector<char>(b->hs.size(), 1), &nt, true);
   if (rc) return rc;
   zero_res(b, 1);
   std::vector<hipEvent_t> ev(2 * static_cast<size_t>(n));
@@ -1107,6 +1179,7 @@ void cpmdp_batch_destroy(cpmdp_batch_t* b) {
   if (b->tiles_copied) (void)hipEventDestroy(b->tiles_copied);
   if (b->descs_copied) (void)hipEventDestroy(b->descs_copied);
   if (b->h_descs) (void)hipHostFree(b->h_descs);
+  if (b->h_starts) (void)hipHostFree(b->h_starts);
   delete b;
 }
 

@@ -58,7 +58,6 @@ __global__ __launch_bounds__(kBlock) void stencil_kernel(StencilArgs<T> a) {
 // the caches (adjacent tiles run on the same XCD at the same time).
 template <typename T, int N, int MODE, bool AXIS>
 __global__ __launch_bounds__(kBlock) void stencil_march_kernel(StencilArgs<T> a) {
-  using V4 = typename VecOf<T, 4>::type;
   constexpr int P = 2 * N + 1;
   extern __shared__ unsigned char smem_raw[];
   T* wsh = reinterpret_cast<T*>(smem_raw);
@@ -73,46 +72,13 @@ __global__ __launch_bounds__(kBlock) void stencil_march_kernel(StencilArgs<T> a)
   const StencilIO<T> io{a.V, a.Vout, a.R, a.term_bits, a.pi_in, a.pi_out, a.r_out};
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   const int tile = lb % a.march_tiles, seg = lb / a.march_tiles;
-  const int PL = a.g.stride[0], m0 = a.g.size[0];
-  const int p = tile * (kBlock * 4) + threadIdx.x * 4;
   const int i_begin = seg * a.march_seg;
-  const int i_end = min(i_begin + a.march_seg, m0);
+  const int i_end = min(i_begin + a.march_seg, a.g.size[0]);
   T res = T(0);
   double res_d = 0.0;
   unsigned changed = 0;
-  if (p < PL && i_begin < i_end) {
-    int idx[N];
-    uint32_t rem = static_cast<uint32_t>(p);
-#pragma unroll
-    for (int k = N - 1; k > 0; --k) {
-      const uint32_t q = fdiv(rem, a.g.div[k]);
-      idx[k] = static_cast<int>(rem - q * static_cast<uint32_t>(a.g.size[k]));
-      rem = q;
-    }
-    idx[0] = 0;
-    const T* Vp = a.V + p;
-    V4 prev = *reinterpret_cast<const V4*>(Vp + max(i_begin - 1, 0) * PL);
-    V4 cur = *reinterpret_cast<const V4*>(Vp + i_begin * PL);
-    V4 nxt = *reinterpret_cast<const V4*>(Vp + min(i_begin + 1, m0 - 1) * PL);
-    for (int i0 = i_begin; i0 < i_end; ++i0) {
-      const V4 nn = *reinterpret_cast<const V4*>(Vp + min(i0 + 2, m0 - 1) * PL);   // prefetch
-      const int s = i0 * PL + p;
-      V4 plus4[N - 1], minus4[N - 1];
-      plus4[0] = nxt;
-      minus4[0] = prev;
-#pragma unroll
-      for (int k = 1; k < N - 1; ++k) {
-        const int st = a.g.stride[k];
-        plus4[k] = *reinterpret_cast<const V4*>(a.V + s + ((idx[k] < a.g.size[k] - 1) ? st : 0));
-        minus4[k] = *reinterpret_cast<const V4*>(a.V + s - ((idx[k] > 0) ? st : 0));
-      }
-      stencil_vec4<T, N, MODE, AXIS>(a.g, io, W, s, idx[N - 1], cur, plus4, minus4, tol, res,
-                                     res_d, changed);
-      prev = cur;
-      cur = nxt;
-      nxt = nn;
-    }
-  }
+  march_column<T, N, MODE, AXIS>(a.g, io, W, tile * (kBlock * 4) + threadIdx.x * 4, i_begin, i_end,
+                                 tol, res, res_d, changed);
   block_max_to_slot(MODE == MODE_RESID ? res_d : static_cast<double>(res), a.res_slot);
   if (MODE == MODE_GREEDY && a.change_count) block_sum_to_counter(changed, a.change_count);
 }

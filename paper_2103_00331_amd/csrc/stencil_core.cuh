@@ -240,4 +240,49 @@ __device__ __forceinline__ void stencil_chunk(const GridGeom& g, const StencilIO
   }
 }
 
+// Marching form: the 4 states at plane offset p (p % 4 == 0) of planes
+// i_0 in [i_begin, i_end) (a plane = the S / m_0 states of one i_0), in
+// order, with the previous, current and next plane's values in registers so
+// that the dim-0 neighbours are not fetched again; the plane after next is
+// prefetched.  Needs n >= 2 and m_last % 4 == 0; p >= S / m_0 is a no-op.
+template <typename T, int N, int MODE, bool AXIS>
+__device__ __forceinline__ void march_column(const GridGeom& g, const StencilIO<T>& io,
+                                             const StencilW<T>& W, int p, int i_begin, int i_end,
+                                             T tol, T& res, double& res_d, unsigned& changed) {
+  using V4 = typename VecOf<T, 4>::type;
+  const int PL = g.stride[0], m0 = g.size[0];
+  if (p >= PL || i_begin >= i_end) return;
+  int idx[N];
+  uint32_t rem = static_cast<uint32_t>(p);
+#pragma unroll
+  for (int k = N - 1; k > 0; --k) {
+    const uint32_t q = fdiv(rem, g.div[k]);
+    idx[k] = static_cast<int>(rem - q * static_cast<uint32_t>(g.size[k]));
+    rem = q;
+  }
+  idx[0] = 0;
+  const T* Vp = io.V + p;
+  V4 prev = *reinterpret_cast<const V4*>(Vp + max(i_begin - 1, 0) * PL);
+  V4 cur = *reinterpret_cast<const V4*>(Vp + i_begin * PL);
+  V4 nxt = *reinterpret_cast<const V4*>(Vp + min(i_begin + 1, m0 - 1) * PL);
+  for (int i0 = i_begin; i0 < i_end; ++i0) {
+    const V4 nn = *reinterpret_cast<const V4*>(Vp + min(i0 + 2, m0 - 1) * PL);   // prefetch
+    const int s = i0 * PL + p;
+    V4 plus4[N - 1], minus4[N - 1];
+    plus4[0] = nxt;
+    minus4[0] = prev;
+#pragma unroll
+    for (int k = 1; k < N - 1; ++k) {
+      const int st = g.stride[k];
+      plus4[k] = *reinterpret_cast<const V4*>(io.V + s + ((idx[k] < g.size[k] - 1) ? st : 0));
+      minus4[k] = *reinterpret_cast<const V4*>(io.V + s - ((idx[k] > 0) ? st : 0));
+    }
+    stencil_vec4<T, N, MODE, AXIS>(g, io, W, s, idx[N - 1], cur, plus4, minus4, tol, res, res_d,
+                                   changed);
+    prev = cur;
+    cur = nxt;
+    nxt = nn;
+  }
+}
+
 }  // namespace cpm

@@ -117,6 +117,36 @@ def test_batch_policy_iteration_rejects_bad_policy(B):
     bm.close()
 
 
+@pytest.fixture(scope="module")
+def march_batch():
+    insts = [I.grid_small([8, 20, 24, 36], slip=0.15, gamma=0.9, seed=41),
+             I.grid_small([10, 16, 32, 32], slip=0.1, gamma=0.92, seed=42),
+             I.grid_small([9, 40, 44], slip=0.2, gamma=0.9, seed=43),
+             I.grid_small([6, 7, 5], slip=0.1, gamma=0.95, seed=44)]
+    log("[batch] oracle for the marching batch")
+    refs = []
+    for x in insts:
+        mats = oracle.sparse.transition_csr(x)
+        Vs, _, _, _ = oracle.sparse.value_iteration(x, mats=mats, eps=1e-12)
+        refs.append((mats, Vs))
+    return insts, refs
+
+
+@pytest.mark.parametrize("method", [0, 1])
+def test_batch_marching_tiles_match_oracle(B, march_batch, method):
+    """Instances whose planes of fixed i_0 hold >= 16384 states get marching
+    tiles (the whole dim-0 column of 1024 plane offsets per tile) next to
+    ordinary tiles of small instances: VI and PI against the oracle."""
+    insts, refs = march_batch
+    log(f"[batch] marching tiles, method {method}")
+    eps = 1e-7
+    code, out, sweeps, res = _solve_batch(B, insts, 1, eps, tune=True, method=method)
+    assert code == B.CPMDP_OK and np.all(res <= eps)
+    for x, (mats, Vs), (V, pi) in zip(insts, refs, out):
+        assert_close(V, Vs, eps / (1 - x.gamma) + 1e-10, x.name)
+        compare_policy(pi, oracle.sparse.q_values(x, mats, Vs), eps / (1 - x.gamma) + 1e-10)
+
+
 def test_batch_equals_single_solves_and_autotune(B):
     insts = _small_batch(count=9, seed=11)
     log("[batch] vs single-instance solves, autotuned")
