@@ -33,6 +33,12 @@ PRECISIONS = {"fp64": CPMDP_FP64, "fp32": CPMDP_FP32, "bf16": CPMDP_BF16}
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run paper_2103_00331_amd/build.py "
                       "(or __graft_entry__.build())")
+# torch must be loaded before the library.  torch ships its own libamdhip64
+# with the same soname as the system one, so loading torch first makes the
+# library bind to that runtime.  Loaded the other way round, the process holds
+# two HIP runtimes, and the one the library uses reports no device.
+import torch  # noqa: E402,F401
+
 lib = C.CDLL(LIB_PATH)
 
 _p = C.c_void_p

@@ -31,6 +31,21 @@ def test_exports_every_declared_symbol():
     assert declared <= set(B.EXPORTED)
 
 
+def test_binding_shares_torch_hip_runtime():
+    # Importing the binding on its own (no torch import before it) must leave
+    # one HIP runtime in the process, the one torch uses.
+    import ast
+    import subprocess
+    import sys
+    code = ("from paper_2103_00331_amd import binding\n"
+            "print(sorted({l.split()[-1] for l in open('/proc/self/maps')\n"
+            "              if 'libamdhip64' in l}))\n")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True,
+                         text=True, timeout=300, check=True).stdout.strip().splitlines()[-1]
+    libs = ast.literal_eval(out)
+    assert len(libs) == 1, libs
+
+
 def _args(inst):
     return (inst.sizes, inst.ranks, inst.factors, inst.lambdas, inst.rewards, inst.gamma)
 
