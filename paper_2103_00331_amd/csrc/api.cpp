@@ -208,6 +208,8 @@ void layout(const cpmdp_t* h, DevPtrs* dp, char* base, size_t* total) {
     const size_t P = 2 * static_cast<size_t>(h->n) + 1;
     d.w64 = cv.take<double>(3 * A * P);   // w, wdiff [A][P], then wbase [P]
     d.w32 = cv.take<float>(3 * A * P);
+    d.parts = cv.take<double>(static_cast<size_t>(kSlots) *
+                              std::max(h->st_blocks, h->st_march_blocks));
     d.fac64 = nullptr;
     d.fac32 = nullptr;
     d.facbf = nullptr;
@@ -249,7 +251,8 @@ GridGeom make_geom(const cpmdp_t* h) {
 template <typename T>
 static StencilArgs<T> stencil_args(cpmdp_t* h, const void* V, void* Vout, const void* R,
                                    const int32_t* pi_in, int32_t* pi_out, float* r_out,
-                                   unsigned long long* slot, unsigned int* ctr) {
+                                   unsigned long long* slot, unsigned int* ctr,
+                                   double* part) {
   constexpr bool f64 = std::is_same<T, double>::value;
   const size_t AP = static_cast<size_t>(h->A) * (2 * h->n + 1);
   const T* w = f64 ? reinterpret_cast<const T*>(h->d.w64) : reinterpret_cast<const T*>(h->d.w32);
@@ -279,6 +282,7 @@ static StencilArgs<T> stencil_args(cpmdp_t* h, const void* V, void* Vout, const 
   a.r_out = r_out;
   a.vmax_bits = h->d.vmax;
   a.res_slot = slot;
+  a.res_part = part;
   a.change_count = ctr;
   a.nblocks = h->st_blocks;
   if (h->st_march && h->opt_march) {
@@ -290,18 +294,25 @@ static StencilArgs<T> stencil_args(cpmdp_t* h, const void* V, void* Vout, const 
   return a;
 }
 
+int stencil_grid(const cpmdp_t* h) {
+  return (h->st_march && h->opt_march) ? h->st_march_blocks : h->st_blocks;
+}
+
 // One sweep on the bound stream.  prec64 selects FP64 buffers (T = double)
 // or FP32 (T = float).  V, Vout, R are typed by that choice.
 void sweep(cpmdp_t* h, bool prec64, int mode, const void* V, void* Vout, const void* R,
            const int32_t* pi_in, int32_t* pi_out, float* r_out,
-           unsigned long long* slot, unsigned int* ctr, bool bf16, const LaunchTiming* tm) {
+           unsigned long long* slot, unsigned int* ctr, bool bf16, const LaunchTiming* tm,
+           double* part) {
   const hipStream_t st = h->stream;
   if (h->path == CPMDP_PATH_STENCIL) {
     if (prec64) {
-      StencilArgs<double> a = stencil_args<double>(h, V, Vout, R, pi_in, pi_out, r_out, slot, ctr);
+      StencilArgs<double> a =
+          stencil_args<double>(h, V, Vout, R, pi_in, pi_out, r_out, slot, ctr, part);
       launch_stencil<double>(a, mode, st, tm);
     } else {
-      StencilArgs<float> a = stencil_args<float>(h, V, Vout, R, pi_in, pi_out, r_out, slot, ctr);
+      StencilArgs<float> a =
+          stencil_args<float>(h, V, Vout, R, pi_in, pi_out, r_out, slot, ctr, part);
       launch_stencil<float>(a, mode, st, tm);
     }
     return;
@@ -436,10 +447,15 @@ static int run_sweeps(cpmdp_t* h, bool prec64, int mode, P*& cur, P*& alt, const
   while (*sweeps < budget) {
     const int k = kprev == 0 ? 4 : next_chunk(rf, rl, kprev, h->gamma, tol, budget - *sweeps);
     zero_slots(h, k);
+    // stencil sweeps leave one residual word per block, reduced per chunk
+    const bool parts = h->path == CPMDP_PATH_STENCIL;
+    const int nb = parts ? stencil_grid(h) : 0;
     for (int j = 0; j < k; ++j) {
-      sweep(h, prec64, mode, cur, alt, R, pi, nullptr, nullptr, slot_of(h, j), nullptr, bf16);
+      sweep(h, prec64, mode, cur, alt, R, pi, nullptr, nullptr, slot_of(h, j), nullptr, bf16,
+            nullptr, parts ? h->d.parts + static_cast<size_t>(j) * nb : nullptr);
       std::swap(cur, alt);
     }
+    if (parts) launch_reduce_parts(h->d.parts, nb, k, h->d.slots, h->stream);
     int rc = check_device(h);
     if (rc) return rc;
     rc = read_slots(h, k, res, nullptr);
@@ -1145,7 +1161,8 @@ int cpmdp_time_sweeps(cpmdp_t* h, void* V_a, void* V_b, int32_t n, int precision
     const LaunchTiming tm{ev[2 * i], ev[2 * i + 1]};
     sweep(h, p64, mode == 0 ? MODE_MAX : MODE_EVAL, cur, alt,
           p64 ? static_cast<const void*>(h->d.R64) : h->d.R32, pi, nullptr, nullptr, h->d.slots,
-          nullptr, precision == CPMDP_BF16, &tm);
+          nullptr, precision == CPMDP_BF16, &tm,
+          h->path == CPMDP_PATH_STENCIL ? h->d.parts : nullptr);
     std::swap(cur, alt);
   }
   rc = check_device(h);

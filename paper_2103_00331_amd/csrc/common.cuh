@@ -58,6 +58,25 @@ __device__ __forceinline__ void block_max_to_slot(double v, unsigned long long* 
   }
 }
 
+// Block-wide max of v stored to *dst by a plain store (no atomic): sweeps
+// that run in chunks give each block its own word and reduce the words of a
+// chunk in one small kernel afterwards, which is cheaper than thousands of
+// atomics per sweep that serialise on the slot words.
+__device__ __forceinline__ void block_max_store(double v, double* dst) {
+  __shared__ double part[16];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = nanmax(v, __shfl_xor(v, off));
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) part[wid] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = part[0];
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int i = 1; i < nw; ++i) m = nanmax(m, part[i]);
+    *dst = m;
+  }
+}
+
 __device__ __forceinline__ void block_sum_to_counter(unsigned v, unsigned int* ctr) {
   __shared__ unsigned part[16];
 #pragma unroll

@@ -81,6 +81,8 @@ struct StencilArgs {
   float* r_out;                 // RESID output
   const unsigned long long* vmax_bits;  // GREEDY: ||V||_inf as FP64 bits
   unsigned long long* res_slot; // max |out - V| as FP64 bits (atomic max)
+  double* res_part;             // if set: block b stores its max at res_part[b]
+                                // instead (res_slot unused)
   unsigned int* change_count;   // GREEDY with incumbent
   int32_t nblocks;
   int32_t vec;                  // states per thread along the last dim (1 or 4)
@@ -163,6 +165,10 @@ void launch_f32_to_f64(const float* src, double* dst, int64_t n, hipStream_t st)
 void launch_add_f32_to_f64(double* dst, const float* e, int64_t n, hipStream_t st);
 void launch_fill_f32(float* p, int64_t n, float v, hipStream_t st);
 void launch_copy_i32(const int32_t* src, int32_t* dst, int64_t n, hipStream_t st);
+// slots[j * kSpread] = max of parts[j * nb .. j * nb + nb) as FP64 bits,
+// for j < k (the other words of each slot are left alone).
+void launch_reduce_parts(const double* parts, int nb, int k, unsigned long long* slots,
+                         hipStream_t st);
 void launch_maxabs_f64(const double* v, int64_t n, unsigned long long* slot, hipStream_t st);
 void launch_shift_bounds(const double* V, const double* BV, const uint32_t* tbits, int64_t n,
                          unsigned long long* keys, hipStream_t st);

@@ -33,6 +33,7 @@ struct DevPtrs {
   uint8_t* kinds = nullptr;
   int32_t* term_start = nullptr;
   char* W = nullptr;                     // dense-chain intermediates
+  double* parts = nullptr;               // stencil: per-block residuals [kSlots][blocks]
 };
 
 }  // namespace cpm
@@ -76,5 +77,8 @@ int fail(cpmdp_t* h, int code, const std::string& msg);
 void layout(const cpmdp_t* h, DevPtrs* d, char* base, size_t* total);
 void sweep(cpmdp_t* h, bool prec64, int mode, const void* V, void* Vout, const void* R,
            const int32_t* pi_in, int32_t* pi_out, float* r_out, unsigned long long* slot,
-           unsigned int* ctr, bool bf16, const LaunchTiming* tm = nullptr);
+           unsigned int* ctr, bool bf16, const LaunchTiming* tm = nullptr,
+           double* part = nullptr);
+// Blocks of one stencil sweep (the per-block residual words it needs).
+int stencil_grid(const cpmdp_t* h);
 }  // namespace cpm

@@ -42,9 +42,19 @@ __global__ __launch_bounds__(kBlock) void stencil_kernel(StencilArgs<T> a) {
   T res = T(0);
   double res_d = 0.0;   // RESID: the residual is taken in FP64
   unsigned changed = 0;
-  for (int s = static_cast<int>(s_begin) + threadIdx.x * VEC; s < s_end; s += kBlock * VEC)
+  // The first chunk is computed unconditionally (a thread past the block's
+  // end recomputes its last chunk and stores nothing): with no bounds branch
+  // before it, the kernel-argument loads and the first global loads are issued
+  // together instead of in dependent rounds.
+  const int s_first = static_cast<int>(s_begin) + threadIdx.x * VEC;
+  const int s_last = s_end - VEC;
+  stencil_chunk<T, N, MODE, VEC, AXIS>(a.g, io, W, min(s_first, s_last), tol, res, res_d, changed,
+                                       s_first <= s_last);
+  for (int s = s_first + kBlock * VEC; s < s_end; s += kBlock * VEC)
     stencil_chunk<T, N, MODE, VEC, AXIS>(a.g, io, W, s, tol, res, res_d, changed);
-  block_max_to_slot(MODE == MODE_RESID ? res_d : static_cast<double>(res), a.res_slot);
+  const double rv = MODE == MODE_RESID ? res_d : static_cast<double>(res);
+  if (a.res_part) block_max_store(rv, a.res_part + blk);
+  else block_max_to_slot(rv, a.res_slot);
   if (MODE == MODE_GREEDY && a.change_count) block_sum_to_counter(changed, a.change_count);
 }
 
@@ -79,7 +89,9 @@ __global__ __launch_bounds__(kBlock) void stencil_march_kernel(StencilArgs<T> a)
   unsigned changed = 0;
   march_column<T, N, MODE, AXIS>(a.g, io, W, tile * (kBlock * 4) + threadIdx.x * 4, i_begin, i_end,
                                  tol, res, res_d, changed);
-  block_max_to_slot(MODE == MODE_RESID ? res_d : static_cast<double>(res), a.res_slot);
+  const double rv = MODE == MODE_RESID ? res_d : static_cast<double>(res);
+  if (a.res_part) block_max_store(rv, a.res_part + lb);
+  else block_max_to_slot(rv, a.res_slot);
   if (MODE == MODE_GREEDY && a.change_count) block_sum_to_counter(changed, a.change_count);
 }
 

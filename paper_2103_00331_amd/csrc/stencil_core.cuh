@@ -130,7 +130,8 @@ __device__ __forceinline__ void stencil_vec4(const GridGeom& g, const StencilIO<
                                              const typename VecOf<T, 4>::type& c4,
                                              const typename VecOf<T, 4>::type (&plus4)[N > 1 ? N - 1 : 1],
                                              const typename VecOf<T, 4>::type (&minus4)[N > 1 ? N - 1 : 1],
-                                             T tol, T& res, double& res_d, unsigned& changed) {
+                                             T tol, T& res, double& res_d, unsigned& changed,
+                                             bool live = true) {
   using V4 = typename VecOf<T, 4>::type;
   constexpr int P = 2 * N + 1;
   const T left = io.V[s - ((il > 0) ? 1 : 0)];
@@ -141,6 +142,7 @@ __device__ __forceinline__ void stencil_vec4(const GridGeom& g, const StencilIO<
   if (MODE != MODE_MAX && io.pi_in) p4 = *reinterpret_cast<const int4*>(io.pi_in + s);
   T outv[4];
   int pnv[4];
+  unsigned ch = 0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     T nb[P];
@@ -155,8 +157,10 @@ __device__ __forceinline__ void stencil_vec4(const GridGeom& g, const StencilIO<
     const int pold = q == 0 ? p4.x : (q == 1 ? p4.y : (q == 2 ? p4.z : p4.w));
     pnv[q] = 0;
     stencil_state<T, N, MODE, AXIS>(W, nb, comp<T>(r4, q), (tw >> q) & 1u, pold, tol, outv[q],
-                                    pnv[q], res, changed);
+                                    pnv[q], res, ch);
   }
+  if (!live) return;   // a recomputed chunk: its residual terms repeat a live one's
+  changed += ch;
   if (MODE == MODE_RESID) {
     float4 r;
     double d[4];
@@ -190,7 +194,8 @@ __device__ __forceinline__ void stencil_vec4(const GridGeom& g, const StencilIO<
 template <typename T, int N, int MODE, int VEC, bool AXIS>
 __device__ __forceinline__ void stencil_chunk(const GridGeom& g, const StencilIO<T>& io,
                                               const StencilW<T>& W, int s, T tol, T& res,
-                                              double& res_d, unsigned& changed) {
+                                              double& res_d, unsigned& changed,
+                                              bool live = true) {
   constexpr int P = 2 * N + 1;
   int idx[N];
   uint32_t rem = static_cast<uint32_t>(s);
@@ -216,7 +221,10 @@ __device__ __forceinline__ void stencil_chunk(const GridGeom& g, const StencilIO
     const int pold = (MODE == MODE_MAX) ? -1 : (io.pi_in ? io.pi_in[s] : -1);
     T out;
     int pnew = 0;
-    stencil_state<T, N, MODE, AXIS>(W, nb, io.R[s], term, pold, tol, out, pnew, res, changed);
+    unsigned ch = 0;
+    stencil_state<T, N, MODE, AXIS>(W, nb, io.R[s], term, pold, tol, out, pnew, res, ch);
+    if (!live) return;
+    changed += ch;
     if (MODE == MODE_RESID) {
       const double d = static_cast<double>(out) - static_cast<double>(c);
       io.r_out[s] = static_cast<float>(d);
@@ -236,7 +244,7 @@ __device__ __forceinline__ void stencil_chunk(const GridGeom& g, const StencilIO
       minus4[k] = *reinterpret_cast<const V4*>(io.V + s - ((idx[k] > 0) ? st : 0));
     }
     stencil_vec4<T, N, MODE, AXIS>(g, io, W, s, idx[N - 1], c4, plus4, minus4, tol, res, res_d,
-                                   changed);
+                                   changed, live);
   }
 }
 

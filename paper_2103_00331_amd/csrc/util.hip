@@ -46,6 +46,22 @@ __global__ void maxabs_f64_kernel(const double* v, int64_t n, unsigned long long
     m = nanmax(m, fabs(v[i]));
   block_max_to_slot(m, slot, 0u);
 }
+__global__ void reduce_parts_kernel(const double* parts, int nb, unsigned long long* slots) {
+  const double* p = parts + static_cast<size_t>(blockIdx.x) * nb;
+  double m = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) m = nanmax(m, p[i]);
+  __shared__ double part[kUtilBlock / 64];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = nanmax(m, __shfl_xor(m, off));
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = part[0];
+    for (int i = 1; i < kUtilBlock / 64; ++i) r = nanmax(r, part[i]);
+    slots[static_cast<size_t>(blockIdx.x) * kSpread] =
+        static_cast<unsigned long long>(__double_as_longlong(r));
+  }
+}
 __global__ void check_policy_kernel(const int32_t* pi, int64_t n, int32_t A, unsigned int* bad) {
   unsigned c = 0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -136,6 +152,10 @@ void launch_copy_i32(const int32_t* s, int32_t* d, int64_t n, hipStream_t st) {
 }
 void launch_maxabs_f64(const double* v, int64_t n, unsigned long long* slot, hipStream_t st) {
   hipLaunchKernelGGL(maxabs_f64_kernel, dim3(util_grid(n)), dim3(kUtilBlock), 0, st, v, n, slot);
+}
+void launch_reduce_parts(const double* parts, int nb, int k, unsigned long long* slots,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(reduce_parts_kernel, dim3(k), dim3(kUtilBlock), 0, st, parts, nb, slots);
 }
 void launch_check_policy(const int32_t* pi, int64_t n, int32_t A, unsigned int* bad, hipStream_t st) {
   hipLaunchKernelGGL(check_policy_kernel, dim3(util_grid(n)), dim3(kUtilBlock), 0, st, pi, n, A, bad);
