@@ -35,6 +35,29 @@ def improve(Q: np.ndarray, V, pi_old: np.ndarray) -> np.ndarray:
     return np.where(keep, pi_old, pi_new).astype(np.int32)
 
 
+# Obstacles (Sec. 3.2: states the agent has no access to).  The paper does not
+# say what a move towards an obstacle does; the oracle's reading: the agent
+# stays where it is (as at the grid edge), and an obstacle state itself is
+# outside the problem, with value 0 (no reward, no continuation).
+
+def obstacle_mask(inst) -> np.ndarray:
+    """bool [S]: obstacle states (all False when the instance has none)."""
+    obs = getattr(inst, "obstacle", None)
+    if obs is None:
+        return np.zeros(inst.n_states, bool)
+    return np.asarray(obs).astype(bool)
+
+
+def rewards_of(inst) -> np.ndarray:
+    """R(s), with 0 at obstacle states."""
+    return np.where(obstacle_mask(inst), 0.0, inst.rewards)
+
+
+def ended(inst) -> np.ndarray:
+    """bool [S]: states with no continuation (terminal or obstacle)."""
+    return (inst.terminal != 0) | obstacle_mask(inst)
+
+
 def coords_of(sizes, s: int):
     """Multi-index of flat state s under the row-major order of Def. 2."""
     out = []

@@ -5,14 +5,16 @@ P_a is expanded as a sum of Kronecker products of the per-dimension factors,
 P_a = sum_r lambda_{a,r} kron(T^(1), kron(T^(2), ...)) -- the CP form, a sum of
 rank-one terms (Sec. 2.2), in the row-major state order of Def. 2 (np.kron
 makes its first operand the slowest index).  Terminal rows have no
-continuation (Sec. 3.2).  The backup is Eq. 1:
+continuation (Sec. 3.2).  With obstacles, the probability of every move into
+an obstacle is moved onto the source state itself (the agent stays put), and
+an obstacle state has value 0 (see ``common``).  The backup is Eq. 1:
     V(s) = R(s) + gamma * max_a sum_s' P(s'|s,a) V(s').
 """
 import itertools
 
 import numpy as np
 
-from .common import greedy, improve
+from .common import ended, greedy, improve, obstacle_mask, rewards_of
 
 MAX_DENSE_STATES = 8192
 
@@ -29,18 +31,25 @@ def transition_matrices(inst) -> np.ndarray:
             for k in range(inst.n_dims):
                 K = np.kron(K, inst.factor(t, k))
             P[a] += inst.lambdas[t] * K
+    obs = obstacle_mask(inst)
+    if obs.any():
+        # a move into an obstacle leaves the agent at s: column o's mass
+        # joins the diagonal, column o becomes zero
+        blocked = P[:, :, obs].sum(axis=2)               # [A, S]
+        P[:, :, obs] = 0.0
+        P[:, np.arange(S), np.arange(S)] += blocked
     return P
 
 
 def continuation(inst) -> np.ndarray:
-    """gamma * (1 - terminal(s)) per state."""
-    return inst.gamma * (1.0 - inst.terminal.astype(np.float64))
+    """gamma per state, 0 at terminal and obstacle states."""
+    return inst.gamma * (1.0 - ended(inst).astype(np.float64))
 
 
 def q_values(inst, P, V) -> np.ndarray:
     """Q[a, s] = R(s) + gamma (1 - tau(s)) (P_a V)(s)."""
     c = continuation(inst)
-    return inst.rewards[None, :] + c[None, :] * np.einsum("ast,t->as", P, V)
+    return rewards_of(inst)[None, :] + c[None, :] * np.einsum("ast,t->as", P, V)
 
 
 def value_iteration(inst, eps=1e-13, max_iter=100000, V0=None, P=None):
@@ -68,7 +77,7 @@ def evaluate(inst, P, pi) -> np.ndarray:
     S = inst.n_states
     P_pi = P[pi, np.arange(S), :]
     M = np.eye(S) - continuation(inst)[:, None] * P_pi
-    return np.linalg.solve(M, inst.rewards)
+    return np.linalg.solve(M, rewards_of(inst))
 
 
 def policy_iteration(inst, pi0=None, max_outer=10000, P=None):

@@ -6,7 +6,9 @@ components (s, s', P(s'|s,a)) with P(s'|s,a) > 0.  Here the lists are built by
 enumerating the non-zeros of every rank term's Kronecker product (the product
 of the per-dimension factor entries, times lambda), merging repeated
 successors, and dropping the rows of terminal states (the interaction ends
-there, Sec. 3.2).  They are stored as one CSR matrix per action.  Value
+there, Sec. 3.2).  A successor that is an obstacle is replaced by the state
+itself (the agent stays put) and obstacle rows are dropped too (value 0, see
+``common``).  They are stored as one CSR matrix per action.  Value
 iteration and policy iteration then run by plain sweeps of Eq. 1.
 
 Reach: factors with few non-zeros per row (identity and shift factors);
@@ -15,7 +17,7 @@ a dense m x m factor multiplies the list length by m per dimension.
 import numpy as np
 import scipy.sparse as sp
 
-from .common import greedy, improve
+from .common import ended, greedy, improve, obstacle_mask, rewards_of
 
 MAX_TRIPLES = 400_000_000
 
@@ -47,12 +49,14 @@ def component_lists(inst, a: int):
 
 def transition_csr(inst):
     """List of A CSR matrices, row s = the merged Def. 3 list of state s;
-    terminal rows are empty."""
+    terminal and obstacle rows are empty."""
     S = inst.n_states
-    live = inst.terminal == 0
+    live = ~ended(inst)
+    obs = obstacle_mask(inst)
     mats = []
     for a in range(inst.n_actions):
         s, s2, p = component_lists(inst, a)
+        s2 = np.where(obs[s2], s, s2)          # blocked move: stay at s
         keep = live[s] & (p > 0)
         M = sp.coo_matrix((p[keep], (s[keep], s2[keep])), shape=(S, S)).tocsr()
         M.sum_duplicates()
@@ -61,11 +65,12 @@ def transition_csr(inst):
 
 
 def q_values(inst, mats, V) -> np.ndarray:
-    """Q[a, s] = R(s) + gamma * (P_a V)(s); terminal rows are empty so their
-    continuation is zero."""
+    """Q[a, s] = R(s) + gamma * (P_a V)(s); terminal and obstacle rows are
+    empty so their continuation is zero."""
     Q = np.empty((len(mats), inst.n_states))
+    R = rewards_of(inst)
     for a, M in enumerate(mats):
-        Q[a] = inst.rewards + inst.gamma * (M @ V)
+        Q[a] = R + inst.gamma * (M @ V)
     return Q
 
 
@@ -113,9 +118,10 @@ def policy_matrix(inst, mats, pi):
 def evaluate(inst, mats, pi, V0=None, eps=1e-13, max_iter=1000000):
     """V_pi by sweeps V <- R + gamma P_pi V until the change is <= eps."""
     P_pi = policy_matrix(inst, mats, pi)
+    R = rewards_of(inst)
     V = np.zeros(inst.n_states) if V0 is None else np.array(V0, np.float64)
     for _ in range(max_iter):
-        Vn = inst.rewards + inst.gamma * (P_pi @ V)
+        Vn = R + inst.gamma * (P_pi @ V)
         res = float(np.max(np.abs(Vn - V)))
         V = Vn
         if res <= eps:
@@ -145,15 +151,19 @@ def q_at_states(inst, V, states):
     state s with coordinates i, term t of action a reaches s' with
     probability lambda_t prod_k T_k[i_k, j_k] for every combination of
     non-zero entries of the rows T_k[i_k, :]; Q_a(s) = R(s) + gamma (1 -
-    tau(s)) sum over those successors of probability times V(s').  For spot
-    checks of instances too large for whole-matrix oracles."""
+    tau(s)) sum over those successors of probability times V(s'), where a
+    successor that is an obstacle counts as s itself.  For spot checks of
+    instances too large for whole-matrix oracles."""
     sizes = [int(m) for m in inst.sizes]
     V = np.asarray(V, np.float64)
     states = np.asarray(states, np.int64)
+    obs = obstacle_mask(inst)
+    stop = ended(inst)
+    R = rewards_of(inst)
     Q = np.empty((inst.n_actions, states.size))
     for col, s in enumerate(states):
         coords = np.unravel_index(int(s), sizes)      # row-major, Def. 2
-        cont = inst.gamma * (1.0 - float(inst.terminal[s]))
+        cont = inst.gamma * (1.0 - float(stop[s]))
         for a in range(inst.n_actions):
             tot = 0.0
             for t in inst.terms_of(a):
@@ -164,6 +174,7 @@ def q_at_states(inst, V, states):
                     j = np.nonzero(row)[0]
                     succ = (succ[:, None] * sizes[k] + j[None, :]).ravel()
                     prob = (prob[:, None] * row[j][None, :]).ravel()
+                succ = np.where(obs[succ], s, succ)
                 tot += float(prob @ V[succ])
-            Q[a, col] = inst.rewards[s] + cont * tot
+            Q[a, col] = R[s] + cont * tot
     return Q

@@ -8,10 +8,17 @@ factor: U[.., i_k, ..] = sum_j T^(k)[i_k, j] V[.., j, ..].  The Q-values are
 those of Eq. 1: Q_a = R + gamma (1 - tau) sum_r lambda_{a,r} U_{a,r}.  Each mode
 product is one numpy tensordot; nothing is blocked or fused.  Works for dense
 factors too; the cost per backup is 2 * sum_a R_a * sum_k m_k flops per state.
+Obstacles break the Kronecker form, so instances with obstacles are refused
+here (the dense and successor-list oracles handle them).
 """
 import numpy as np
 
-from .common import greedy, improve
+from .common import greedy, improve, obstacle_mask
+
+
+def _refuse_obstacles(inst):
+    if obstacle_mask(inst).any():
+        raise ValueError("mode-product chains cannot express obstacles")
 
 
 def mode_product(X: np.ndarray, T: np.ndarray, k: int) -> np.ndarray:
@@ -29,6 +36,7 @@ def apply_term(inst, t: int, Vt: np.ndarray) -> np.ndarray:
 
 def apply_action(inst, a: int, V: np.ndarray) -> np.ndarray:
     """(P_a V) as a flat vector, by mode-product chains."""
+    _refuse_obstacles(inst)
     shape = tuple(int(m) for m in inst.sizes)
     Vt = np.asarray(V, np.float64).reshape(shape)
     acc = np.zeros(shape)
@@ -107,6 +115,7 @@ def q_at_states(inst, V, states):
     (P_a V)(s) = sum_r lambda_{a,r} sum_j prod_k T^(k)_{a,r}[i_k, j_k] V[j]:
     V is contracted with row i_k of every factor, one dimension at a time.
     For spot checks of instances too large for a full oracle backup."""
+    _refuse_obstacles(inst)
     shape = tuple(int(m) for m in inst.sizes)
     Vt = np.asarray(V, np.float64).reshape(shape)
     states = np.asarray(states, np.int64)

@@ -45,6 +45,7 @@ SEED_DENSE6 = 20210003       # 16^6 dense-factor grid
 SEED_DENSE6_SMALL = 20210013  # 12^6 dense-factor grid (parity instance)
 SEED_BATCH = 20210004        # 512 mixed GridWorlds
 SEED_WARM = 20210005         # 64^3 warm-start instances
+SEED_PAPER2D = 20210006      # 1000 x 1000 GridWorld of Table 1 (22 terminals, 800 obstacles)
 
 
 @dataclass
@@ -60,6 +61,7 @@ class Instance:
     terminal: np.ndarray         # uint8 [S], 1 = terminal
     name: str = ""
     meta: Dict[str, float] = field(default_factory=dict)
+    obstacle: Optional[np.ndarray] = None   # uint8 [S], 1 = obstacle (or None)
 
     @property
     def n_dims(self) -> int:
@@ -313,7 +315,44 @@ def with_rewards(inst: Instance, rewards, terminal=None) -> Instance:
     return Instance(inst.sizes.copy(), inst.ranks.copy(), inst.factors.copy(),
                     inst.lambdas.copy(),
                     np.asarray(rewards, np.float64).reshape(S).copy(),
-                    inst.gamma, term, inst.name, dict(inst.meta))
+                    inst.gamma, term, inst.name, dict(inst.meta),
+                    None if inst.obstacle is None else inst.obstacle.copy())
+
+
+def with_obstacles(inst: Instance, cells) -> Instance:
+    """Copy of inst with obstacles at the given flat state indices (an
+    obstacle must not be terminal)."""
+    obs = np.zeros(inst.n_states, np.uint8)
+    obs[np.asarray(list(cells), np.int64)] = 1
+    if np.any(obs & inst.terminal):
+        raise ValueError("a state cannot be both terminal and an obstacle")
+    out = with_rewards(inst, inst.rewards)
+    out.obstacle = obs
+    return out
+
+
+def paper_gridworld(sizes, n_terminal: int, n_obstacle: int, seed: int,
+                    slip: float = 0.2, gamma: float = 0.9,
+                    step_reward: float = -3.0) -> Instance:
+    """GridWorld of the paper's experiments (Sec. 4, Table 1): 2|D| actions,
+    step reward -3, randomly placed terminal states (+100 for the first half,
+    -100 for the rest) and obstacles, gamma = 0.9.  The paper does not give
+    the slip model or the placement seeds: moves go as intended with
+    probability 1 - slip and slip is spread over the perpendicular moves, as
+    in the other GridWorlds here."""
+    sizes = [int(m) for m in sizes]
+    S = int(np.prod(sizes))
+    rng = np.random.default_rng(seed)
+    cells = rng.choice(S, n_terminal + n_obstacle, replace=False)
+    terms = []
+    for j, s in enumerate(cells[:n_terminal]):
+        coords = np.unravel_index(int(s), sizes)
+        terms.append((tuple(int(c) for c in coords), 100.0 if j < (n_terminal + 1) // 2
+                      else -100.0))
+    inst = make_gridworld(sizes, slip, np.full(S, step_reward), gamma, terminals=terms,
+                          name="paper_grid_" + "x".join(map(str, sizes)),
+                          meta={"n_terminal": n_terminal, "n_obstacle": n_obstacle})
+    return with_obstacles(inst, cells[n_terminal:])
 
 
 def seeded_values(n: int, seed: int, scale: float = 1.0) -> np.ndarray:
@@ -329,5 +368,6 @@ def named(name: str) -> Instance:
         "grid4d_96": lambda: grid4d(96, SEED_GRID4_LARGE),
         "dense6_16": lambda: dense_grid(16, seed=SEED_DENSE6),
         "dense6_12": lambda: dense_grid(12, seed=SEED_DENSE6_SMALL),
+        "paper2d_1000": lambda: paper_gridworld([1000, 1000], 22, 800, SEED_PAPER2D),
     }
     return table[name]()
