@@ -13,8 +13,10 @@ Also printed (one JSON line): the roofline of the dominant kernel (the FP32
 stencil sweep), timed live with HIP events on the library's stream, and the
 FP64 CPU oracle timed on a bounded sample of the same workload.
 
-Other workloads (--workload): grid4d_96 (96^4, HBM-resident) and dense6_16
-(16^6, dense 16x16 factors, 12 actions of rank 8).
+Other workloads (--workload): grid4d_96 (96^4, HBM-resident), dense6_16
+(16^6, dense 16x16 factors, 12 actions of rank 8), batch512 (512 mixed
+GridWorlds), warm64 (learned warm start on 64^3) and paper2d_1000 (the
+1000 x 1000 GridWorld of Table 1 with 22 terminals and 800 obstacles).
 """
 import argparse
 import hashlib
@@ -68,6 +70,37 @@ def _traffic(profile_md, src):
     return float(m_b.group(1))
 
 
+def _copy_reference(nbytes):
+    """Achievable-bandwidth references measured here with torch: a 1 GiB
+    copy (GB/s counting read + write) and a copy that moves nbytes (half read,
+    half written) per launch, back to back (ms per launch); each the better of
+    copy_ and an elementwise multiply into the destination.
+    """
+    import torch
+    out = {}
+    for key, size in (("stream_copy", 1 << 29), ("same_bytes_copy", max(int(nbytes) // 2, 4))):
+        n = size // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        reps = 20 if key == "stream_copy" else 400
+        best = None
+        for op in (lambda: dst.copy_(src), lambda: torch.mul(src, 1.0, out=dst)):
+            for _ in range(5):
+                op()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                op()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            best = ms if best is None else min(best, ms)
+        out[key] = (2.0 * n * 4 / (best * 1e-3) / 1e9, best)
+        del src, dst
+    return {"stream_copy_GBps": out["stream_copy"][0],
+            "same_bytes_copy_ms": out["same_bytes_copy"][1]}
+
+
 def _cpu_baseline_grid(inst, budget_s=15.0):
     """FP64 value-iteration sweeps of the Def. 3 successor-list oracle."""
     import numpy as np
@@ -99,10 +132,16 @@ def bench_grid(args, m):
     from paper_2103_00331_amd import binding as B
     from paper_2103_00331_amd import instances as I
 
-    seed = I.SEED_GRID4 if m == 32 else I.SEED_GRID4_LARGE
-    _log(f"building {m}^4 instance")
-    inst = I.grid4d(m, seed)
+    if args.workload == "paper2d_1000":
+        _log("building the 1000 x 1000 GridWorld (22 terminals, 800 obstacles)")
+        inst = I.named("paper2d_1000")
+    else:
+        seed = I.SEED_GRID4 if m == 32 else I.SEED_GRID4_LARGE
+        _log(f"building {m}^4 instance")
+        inst = I.grid4d(m, seed)
     S, A = inst.n_states, inst.n_actions
+    n = inst.n_dims
+    obstacles = inst.obstacle is not None and bool(inst.obstacle.any())
     model = B.Model(inst)
     if args.one_pass:
         B.cpmdp_set_option(model.h, B.CPMDP_OPT_MARCH, 0)
@@ -153,16 +192,27 @@ def bench_grid(args, m):
     Va = torch.zeros(S, dtype=torch.float32, device="cuda")
     Vb = torch.zeros(S, dtype=torch.float32, device="cuda")
     ms = B.cpmdp_time_sweeps(model.h, Va, Vb, 400, B.CPMDP_FP32, 0)
-    algo_bytes = S * (4 + 4 + 4) + S / 8.0          # V, R, V' words + terminal bit
+    # V, R, V' words + terminal bit (+ the 16-bit blocked-direction mask)
+    algo_bytes = S * (4 + 4 + 4) + S / 8.0 + (2 * S if obstacles else 0)
     achieved = algo_bytes / (ms * 1e-3) / 1e9
-    march = m >= 96 and not args.one_pass
-    traffic = _traffic("stencil_march_fp32_grid4d_96.md" if march else f"stencil_fp32_grid4d_{m}.md",
-                       STENCIL_SRC)
-    kname = ("stencil_march_kernel<float, 4, MODE_MAX, AXIS>" if march
-             else "stencil_kernel<float, 4, MODE_MAX, VEC=4, AXIS>")
+    plane = S // int(inst.sizes[0])
+    march = (n >= 2 and plane >= 65536 and int(inst.sizes[0]) >= 8 and int(inst.sizes[-1]) % 4 == 0
+             and not args.one_pass)
+    if args.workload == "paper2d_1000":
+        traffic = None
+    else:
+        traffic = _traffic("stencil_march_fp32_grid4d_96.md" if march
+                           else f"stencil_fp32_grid4d_{m}.md", STENCIL_SRC)
+    vec = 4 if int(inst.sizes[-1]) % 4 == 0 else 1
+    kname = (f"stencil_march_kernel<float, {n}, MODE_MAX, AXIS>" if march
+             else f"stencil_kernel<float, {n}, MODE_MAX, VEC={vec}, AXIS>")
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "kernel": kname, "kernel_ms": ms, "algorithmic_bytes_per_launch": algo_bytes}
+    ref = _copy_reference(algo_bytes)
+    roof["stream_copy_GBps"] = ref["stream_copy_GBps"]
+    roof["frac_of_stream_copy"] = achieved / ref["stream_copy_GBps"]
+    roof["same_bytes_copy_ms"] = ref["same_bytes_copy_ms"]
 
     out = {
         "metric": METRIC,
@@ -177,8 +227,12 @@ def bench_grid(args, m):
         "vs_baseline": None,
         "dtype": "f32" if prec == B.CPMDP_FP32 else "f64",
         "data": "synthetic",
-        "config": {"workload": f"gridworld_{m}^4: {S} states, {A} actions, CP rank 7, "
-                               "slip 0.1, rewards N(0,0.1) + terminal goal corner, gamma 0.99",
+        "config": {"workload": (f"gridworld_{m}^4: {S} states, {A} actions, CP rank 7, "
+                                "slip 0.1, rewards N(0,0.1) + terminal goal corner, gamma 0.99")
+                   if args.workload != "paper2d_1000" else
+                   (f"gridworld_1000x1000 (Table 1, 2-D): {S} states, {A} actions, CP rank 3, "
+                    "slip 0.2, 22 terminals (+-100), 800 obstacles, step reward -3, "
+                    "gamma 0.9"),
                    "method": f"{args.method} {args.precision} sweeps + FP64 certificate",
                    "eps": eps, "sweeps_per_solve": tot_sweeps / args.steps},
         "time_to_eps_s": ms_per_step / 1e3,
@@ -454,6 +508,8 @@ def kernel_only(args):
         return
     if args.workload == "dense6_16":
         inst = I.dense_grid(16, seed=I.SEED_DENSE6)
+    elif args.workload == "paper2d_1000":
+        inst = I.named("paper2d_1000")
     else:
         m = 32 if args.workload == "grid4d_32" else 96
         inst = I.grid4d(m, I.SEED_GRID4 if m == 32 else I.SEED_GRID4_LARGE)
@@ -480,7 +536,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="grid4d_32",
-                    choices=["grid4d_32", "grid4d_96", "dense6_16", "batch512", "warm64"])
+                    choices=["grid4d_32", "grid4d_96", "dense6_16", "batch512", "warm64",
+                             "paper2d_1000"])
     ap.add_argument("--method", default="vi", choices=["vi", "pi"])
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -512,7 +569,7 @@ def main():
         out = bench_warm(args)
     else:
         out, inst = bench_grid(args, 32 if args.workload == "grid4d_32" else 96)
-        if args.workload == "grid4d_32" and not args.no_cpu_baseline:
+        if args.workload in ("grid4d_32", "paper2d_1000") and not args.no_cpu_baseline:
             out["cpu_baseline"] = _cpu_baseline_grid(inst)
     print(json.dumps(out), flush=True)
 

@@ -109,8 +109,19 @@ int cpmdp_create(cpmdp_t** out, int32_t n_dims, const int64_t* sizes,
  * continuation).  Must be called before cpmdp_bind; default: none. */
 int cpmdp_set_terminal(cpmdp_t* h, const uint8_t* mask);
 
-/* Obstacles (Sec. 3.2, states the agent cannot enter) break the pure
- * Kronecker form; this build rejects them with CPMDP_E_UNSUPPORTED. */
+/* Obstacles (Sec. 3.2: states the agent has no access to): mask [S], host
+ * memory read during the call, nonzero = obstacle.  The paper does not say
+ * what a move towards an obstacle does; here it is blocked and the agent
+ * stays where it is, as at the grid edge, and an obstacle state is outside
+ * the problem: its reward is taken as 0 and it has no continuation, so its
+ * value is 0 and its reported action 0.  Supported for shift/identity
+ * factors (path CPMDP_PATH_STENCIL): with dense factors the blocked moves
+ * are no sparse correction of the Kronecker form, and a mask with any
+ * obstacle returns CPMDP_E_UNSUPPORTED.  A state may not be both terminal
+ * and an obstacle (cpmdp_bind returns CPMDP_E_ARG).  Must be called before
+ * cpmdp_workspace_bytes and cpmdp_bind (obstacles add 2 bytes per state to
+ * the workspace); CPMDP_E_STATE after bind.  An all-zero mask removes the
+ * obstacles.  Batched solves do not take instances with obstacles. */
 int cpmdp_set_obstacles(cpmdp_t* h, const uint8_t* mask);
 
 /* Which kernel family the instance runs on (cpmdp_path), via *path. */

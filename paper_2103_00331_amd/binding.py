@@ -291,8 +291,9 @@ def cpmdp_batch_destroy(b):
 
 class Model:
     """One MDP on the GPU: creates the handle from an instance (sizes,
-    ranks, factors, lambdas, rewards, gamma, terminal mask), allocates the
-    workspace as a torch uint8 tensor and binds it with the current stream."""
+    ranks, factors, lambdas, rewards, gamma, terminal and obstacle masks),
+    allocates the workspace as a torch uint8 tensor and binds it with the
+    current stream."""
 
     def __init__(self, inst, device="cuda", stream=None):
         import torch
@@ -301,6 +302,9 @@ class Model:
                               inst.rewards, inst.gamma)
         if np.any(inst.terminal):
             cpmdp_set_terminal(self.h, inst.terminal)
+        obstacle = getattr(inst, "obstacle", None)
+        if obstacle is not None and np.any(obstacle):
+            cpmdp_set_obstacles(self.h, obstacle)
         self.path = cpmdp_get_path(self.h)
         nbytes = cpmdp_workspace_bytes(self.h)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
@@ -335,6 +339,9 @@ class BatchModel:
                              inst.rewards, inst.gamma)
             if np.any(inst.terminal):
                 cpmdp_set_terminal(h, inst.terminal)
+            obstacle = getattr(inst, "obstacle", None)
+            if obstacle is not None and np.any(obstacle):
+                cpmdp_set_obstacles(h, obstacle)
             self.handles.append(h)
         self.b = cpmdp_batch_create(self.handles)
         nbytes = cpmdp_batch_workspace_bytes(self.b)

@@ -210,6 +210,7 @@ void layout(const cpmdp_t* h, DevPtrs* dp, char* base, size_t* total) {
     d.w32 = cv.take<float>(3 * A * P);
     d.parts = cv.take<double>(static_cast<size_t>(kSlots) *
                               std::max(h->st_blocks, h->st_march_blocks));
+    d.obs = h->obstacle.empty() ? nullptr : cv.take<uint16_t>(S);
     d.fac64 = nullptr;
     d.fac32 = nullptr;
     d.facbf = nullptr;
@@ -276,6 +277,7 @@ static StencilArgs<T> stencil_args(cpmdp_t* h, const void* V, void* Vout, const 
   a.Vout = static_cast<T*>(Vout);
   a.R = static_cast<const T*>(R);
   a.term_bits = h->d.tbits;
+  a.obs = h->d.obs;
   a.gamma = static_cast<T>(h->gamma);
   a.pi_in = pi_in;
   a.pi_out = pi_out;
@@ -717,10 +719,19 @@ int cpmdp_set_terminal(cpmdp_t* h, const uint8_t* mask) {
 int cpmdp_set_obstacles(cpmdp_t* h, const uint8_t* mask) {
   if (!h) return fail(nullptr, CPMDP_E_ARG, "handle is NULL");
   if (!mask) return fail(h, CPMDP_E_ARG, "mask is NULL");
-  for (int64_t s = 0; s < h->S; ++s)
-    if (mask[s])
-      return fail(h, CPMDP_E_UNSUPPORTED,
-                  "obstacles break the Kronecker form of P_a and are not supported");
+  if (h->bound) return fail(h, CPMDP_E_STATE, "set_obstacles must precede bind");
+  bool any = false;
+  for (int64_t s = 0; s < h->S && !any; ++s) any = mask[s] != 0;
+  if (!any) {
+    h->obstacle.clear();
+    return CPMDP_OK;
+  }
+  if (h->path != CPMDP_PATH_STENCIL)
+    return fail(h, CPMDP_E_UNSUPPORTED,
+                "obstacles need shift/identity factors: with dense factors the blocked "
+                "moves are not a sparse correction of the Kronecker form");
+  h->obstacle.assign(static_cast<size_t>(h->S), 0);
+  for (int64_t s = 0; s < h->S; ++s) h->obstacle[s] = mask[s] ? 1 : 0;
   return CPMDP_OK;
 }
 
@@ -784,15 +795,44 @@ int cpmdp_bind(cpmdp_t* h, void* ws, size_t bytes, void* stream) {
                              hipHostMallocDefault));
   }
   const size_t S = static_cast<size_t>(h->S);
+  const bool obst = !h->obstacle.empty();
+  if (obst)
+    for (size_t s = 0; s < S; ++s)
+      if (h->obstacle[s] && h->terminal[s])
+        return fail(h, CPMDP_E_ARG, "a state is both terminal and an obstacle");
+  // An obstacle state is outside the problem: reward 0 and no continuation
+  // (so V = 0 there); moves into it are blocked (the obs masks below).
+  std::vector<double> r64(h->rewards);
   std::vector<float> f32(S);
-  for (size_t s = 0; s < S; ++s) f32[s] = static_cast<float>(h->rewards[s]);
   std::vector<uint32_t> bits((S + 31) / 32 + 1, 0u);
-  for (size_t s = 0; s < S; ++s)
-    if (h->terminal[s]) bits[s >> 5] |= 1u << (s & 31);
+  for (size_t s = 0; s < S; ++s) {
+    const bool ob = obst && h->obstacle[s];
+    if (ob) r64[s] = 0.0;
+    f32[s] = static_cast<float>(r64[s]);
+    if (h->terminal[s] || ob) bits[s >> 5] |= 1u << (s & 31);
+  }
+  std::vector<uint16_t> blocked;
+  if (obst) {
+    // bit 2k (2k + 1) of state s: its +e_k (-e_k) neighbour is an obstacle
+    blocked.assign(S, 0);
+    for (size_t o = 0; o < S; ++o) {
+      if (!h->obstacle[o]) continue;
+      int64_t rem = static_cast<int64_t>(o), stride = 1;
+      for (int k = h->n - 1; k >= 0; --k) {
+        const int64_t i = rem % h->sizes[k];
+        rem /= h->sizes[k];
+        if (i > 0) blocked[o - stride] |= static_cast<uint16_t>(1u << (2 * k));
+        if (i < h->sizes[k] - 1) blocked[o + stride] |= static_cast<uint16_t>(1u << (2 * k + 1));
+        stride *= h->sizes[k];
+      }
+    }
+  }
   const hipStream_t st = h->stream;
-  HIP_TRY(h, hipMemcpyAsync(h->d.R64, h->rewards.data(), S * 8, hipMemcpyHostToDevice, st));
+  HIP_TRY(h, hipMemcpyAsync(h->d.R64, r64.data(), S * 8, hipMemcpyHostToDevice, st));
   HIP_TRY(h, hipMemcpyAsync(h->d.R32, f32.data(), S * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(h, hipMemcpyAsync(h->d.tbits, bits.data(), bits.size() * 4, hipMemcpyHostToDevice, st));
+  if (obst)
+    HIP_TRY(h, hipMemcpyAsync(h->d.obs, blocked.data(), S * 2, hipMemcpyHostToDevice, st));
   std::vector<float> w32;
   std::vector<float> fac32, lam32;
   std::vector<uint16_t> facbf;

@@ -787,6 +787,11 @@ int cpmdp_batch_create(cpmdp_batch_t** out, cpmdp_t* const* handles, int32_t cou
       return cpm::fail(nullptr, CPMDP_E_UNSUPPORTED,
                        "batched solve needs shift/identity factors and at most 4 dims");
     }
+    if (!h->obstacle.empty()) {
+      delete b;
+      return cpm::fail(nullptr, CPMDP_E_UNSUPPORTED,
+                       "batched solve does not take instances with obstacles");
+    }
     b->hs.push_back(h);
     b->total_states += h->S;
   }

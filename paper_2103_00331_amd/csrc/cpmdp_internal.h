@@ -75,6 +75,8 @@ struct StencilArgs {
   const T* R;                   // rewards, or the right-hand side of a correction sweep
   const float* Rf;              // EVAL on a T=float sweep with FP32 rhs (== R) -- unused otherwise
   const uint32_t* term_bits;    // terminal mask, 1 bit per state
+  const uint16_t* obs;          // per state, bit 2k / 2k+1: the +e_k / -e_k
+                                // neighbour is an obstacle (nullptr: none)
   T gamma;
   const int32_t* pi_in;         // EVAL: policy; GREEDY: incumbent (nullable)
   int32_t* pi_out;              // GREEDY output (nullable)

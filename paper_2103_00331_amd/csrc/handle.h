@@ -34,6 +34,7 @@ struct DevPtrs {
   int32_t* term_start = nullptr;
   char* W = nullptr;                     // dense-chain intermediates
   double* parts = nullptr;               // stencil: per-block residuals [kSlots][blocks]
+  uint16_t* obs = nullptr;               // stencil with obstacles: blocked directions [S]
 };
 
 }  // namespace cpm
@@ -48,6 +49,7 @@ struct cpmdp {
   std::vector<int32_t> term_start;
   std::vector<double> factors, lambdas, rewards;
   std::vector<uint8_t> terminal;
+  std::vector<uint8_t> obstacle;         // empty: no obstacles
   std::vector<uint8_t> kinds;
   int path = 0;
   std::vector<double> w;                 // stencil weights [A][2n+1]

@@ -34,7 +34,7 @@ __global__ __launch_bounds__(kBlock) void stencil_kernel(StencilArgs<T> a) {
   T tol = T(0);
   if (MODE == MODE_GREEDY) tol = static_cast<T>(tie_tol(a.vmax_bits));
   const StencilW<T> W{a.kw_base, a.kw_axis, a.w, wsh, a.A, a.gamma};
-  const StencilIO<T> io{a.V, a.Vout, a.R, a.term_bits, a.pi_in, a.pi_out, a.r_out};
+  const StencilIO<T> io{a.V, a.Vout, a.R, a.term_bits, a.pi_in, a.pi_out, a.r_out, a.obs};
   const int blk = xcd_block(blockIdx.x, gridDim.x);
   const int64_t s_begin = static_cast<int64_t>(blk) * a.states_per_block;
   const int64_t s_end0 = s_begin + a.states_per_block;
@@ -79,7 +79,7 @@ __global__ __launch_bounds__(kBlock) void stencil_march_kernel(StencilArgs<T> a)
   T tol = T(0);
   if (MODE == MODE_GREEDY) tol = static_cast<T>(tie_tol(a.vmax_bits));
   const StencilW<T> W{a.kw_base, a.kw_axis, a.w, wsh, a.A, a.gamma};
-  const StencilIO<T> io{a.V, a.Vout, a.R, a.term_bits, a.pi_in, a.pi_out, a.r_out};
+  const StencilIO<T> io{a.V, a.Vout, a.R, a.term_bits, a.pi_in, a.pi_out, a.r_out, a.obs};
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   const int tile = lb % a.march_tiles, seg = lb / a.march_tiles;
   const int i_begin = seg * a.march_seg;

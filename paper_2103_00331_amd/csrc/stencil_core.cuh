@@ -8,6 +8,8 @@
 // weight, so an action is a (2n+1)-point stencil
 //     (P_a V)(s) = sum_p w[a][p] V(nbr_p(s)),
 // points p: 0 = the state, 1 + 2k = +e_k, 2 + 2k = -e_k.
+// A neighbour that is an obstacle counts as the state itself (the move is
+// blocked, as at the grid edge): per state, bit p - 1 of obs[s] marks point p.
 #pragma once
 
 #include "common.cuh"
@@ -57,7 +59,15 @@ struct StencilIO {
   const int32_t* pi_in;
   int32_t* pi_out;
   float* r_out;
+  const uint16_t* obs;   // blocked-direction bits per state, or nullptr
 };
+
+// Points of a state whose neighbour is an obstacle read the state itself.
+template <typename T, int P>
+__device__ __forceinline__ void block_points(T (&nb)[P], unsigned m) {
+#pragma unroll
+  for (int p = 1; p < P; ++p) nb[p] = ((m >> (p - 1)) & 1u) ? nb[0] : nb[p];
+}
 
 // One state: Q-values of Eq. 1, max / argmax (tie rule) or the fixed-policy
 // value, and the residual term.
@@ -140,6 +150,8 @@ __device__ __forceinline__ void stencil_vec4(const GridGeom& g, const StencilIO<
   const uint32_t tw = io.tbits[s >> 5] >> (s & 31);
   int4 p4 = make_int4(-1, -1, -1, -1);
   if (MODE != MODE_MAX && io.pi_in) p4 = *reinterpret_cast<const int4*>(io.pi_in + s);
+  uint2 ob = make_uint2(0u, 0u);   // 4 x 16-bit blocked-direction masks
+  if (io.obs) ob = *reinterpret_cast<const uint2*>(io.obs + s);
   T outv[4];
   int pnv[4];
   unsigned ch = 0;
@@ -154,6 +166,7 @@ __device__ __forceinline__ void stencil_vec4(const GridGeom& g, const StencilIO<
     }
     nb[1 + 2 * (N - 1)] = q < 3 ? comp<T>(c4, q + 1) : right;
     nb[2 + 2 * (N - 1)] = q > 0 ? comp<T>(c4, q - 1) : left;
+    if (io.obs) block_points<T, P>(nb, ((q < 2 ? ob.x : ob.y) >> (16 * (q & 1))) & 0xFFFFu);
     const int pold = q == 0 ? p4.x : (q == 1 ? p4.y : (q == 2 ? p4.z : p4.w));
     pnv[q] = 0;
     stencil_state<T, N, MODE, AXIS>(W, nb, comp<T>(r4, q), (tw >> q) & 1u, pold, tol, outv[q],
@@ -217,6 +230,7 @@ __device__ __forceinline__ void stencil_chunk(const GridGeom& g, const StencilIO
       nb[1 + 2 * k] = io.V[s + ((idx[k] < g.size[k] - 1) ? st : 0)];
       nb[2 + 2 * k] = io.V[s - ((idx[k] > 0) ? st : 0)];
     }
+    if (io.obs) block_points<T, P>(nb, io.obs[s]);
     const bool term = is_terminal(io.tbits, s);
     const int pold = (MODE == MODE_MAX) ? -1 : (io.pi_in ? io.pi_in[s] : -1);
     T out;

@@ -104,17 +104,35 @@ def test_negative_probability_rejected():
     assert e.value.code == B.CPMDP_E_NOT_STOCHASTIC
 
 
-def test_obstacles_unsupported_and_calls_before_bind():
+def test_obstacles_and_calls_before_bind():
     g = I.grid_small([3, 4], seed=0)
     h = B.cpmdp_create(*_args(g))
     mask = np.zeros(g.n_states, np.uint8)
     B.cpmdp_set_obstacles(h, mask)          # no obstacle: fine
+    base = B.cpmdp_workspace_bytes(h)
     mask[5] = 1
-    with pytest.raises(B.CpmdpError) as e:
-        B.cpmdp_set_obstacles(h, mask)
-    assert e.value.code == B.CPMDP_E_UNSUPPORTED
+    B.cpmdp_set_obstacles(h, mask)          # shift/identity factors: accepted
+    assert B.cpmdp_workspace_bytes(h) >= base + 2 * g.n_states
     code = B.lib.cpmdp_value_iteration(h, None, None, 1e-6, 10, 0, None, None)
     assert code == B.CPMDP_E_STATE          # not bound to a workspace yet
+    B.cpmdp_destroy(h)
+    d = I.random_dense([3, 4], 2, 2, seed=1)
+    h = B.cpmdp_create(*_args(d))
+    with pytest.raises(B.CpmdpError) as e:
+        B.cpmdp_set_obstacles(h, mask)      # dense factors: not a sparse fix-up
+    assert e.value.code == B.CPMDP_E_UNSUPPORTED
+    B.cpmdp_destroy(h)
+
+
+def test_batch_rejects_obstacles():
+    g = I.grid_small([4, 8], seed=0)
+    h = B.cpmdp_create(*_args(g))
+    mask = np.zeros(g.n_states, np.uint8)
+    mask[3] = 1
+    B.cpmdp_set_obstacles(h, mask)
+    with pytest.raises(B.CpmdpError) as e:
+        B.cpmdp_batch_create([h])
+    assert e.value.code == B.CPMDP_E_UNSUPPORTED
     B.cpmdp_destroy(h)
 
 
