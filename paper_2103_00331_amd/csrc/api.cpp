@@ -419,67 +419,156 @@ static int check_device(cpmdp_t* h) {
 
 // Chunk size for the next run of sweeps: enough to reach eps at the
 // observed contraction rate, bounded to keep overshoot and host reads small.
-static int next_chunk(double res_first, double res_last, int k_prev, double gamma,
-                      double eps, int64_t left) {
+// Sweeps still needed to bring res_last down to eps at the contraction rate
+// observed over the last chunk (gamma until one is observed).
+static double predict_need(double res_first, double res_last, int k_prev, double gamma,
+                           double eps) {
   double rate = gamma;
   if (k_prev > 1 && res_first > 0 && res_last > 0 && std::isfinite(res_first) &&
       std::isfinite(res_last)) {
     rate = std::pow(res_last / res_first, 1.0 / (k_prev - 1));
     rate = std::min(std::max(rate, 0.3), 0.999999);
   }
-  double need = 8;
   if (res_last > eps && std::isfinite(res_last))
-    need = std::ceil(std::log(eps / res_last) / std::log(rate));
-  int k = static_cast<int>(std::min(std::max(need, 4.0), 128.0));
-  if (k > left) k = static_cast<int>(left);
-  return std::max(k, 1);
+    return std::ceil(std::log(eps / res_last) / std::log(rate));
+  return 8.0;
 }
 
 // Chunked sweeps of one mode until the residual of a sweep <= tol.
 // cur/alt: ping-pong buffers (cur holds the input on entry and the result on
-// exit).  Returns status; *done = reached tol.
+// exit).  Returns status; *done = the last sweep's residual <= tol.
+//
+// Two chunks are kept in flight: while the host waits for one chunk's
+// residuals (copied to pinned memory behind an event), the next chunk is
+// already queued, so the device does not idle during the host's turnaround.
+// The residual slots and per-block words are split in two halves, one per
+// chunk in flight.  A chunk queued behind one that reached tol only runs
+// more sweeps of the contraction; the reported residual is that of the last
+// sweep run.
+// Residual trend of a run of sweeps (first and last residual of its last
+// chunk of k sweeps), handed from one stage of a solve to the next so that
+// the next stage's first chunk is sized from it instead of probed.
+struct SweepTrend {
+  double rf = INFINITY, rl = INFINITY;
+  int k = 0;
+};
+
 template <typename P>
 static int run_sweeps(cpmdp_t* h, bool prec64, int mode, P*& cur, P*& alt, const void* R,
                       const int32_t* pi, double tol, double stall_floor, int64_t budget,
-                      int64_t* sweeps, bool* done, double* last_res, bool bf16) {
+                      int64_t* sweeps, bool* done, double* last_res, bool bf16,
+                      SweepTrend* trend = nullptr) {
+  constexpr int kHalf = kSlots / 2;   // chunks hold at most 128 sweeps
   *done = false;
-  double rf = INFINITY, rl = INFINITY;
-  int kprev = 0;
-  std::vector<double> res;
-  while (*sweeps < budget) {
-    const int k = kprev == 0 ? 4 : next_chunk(rf, rl, kprev, h->gamma, tol, budget - *sweeps);
-    zero_slots(h, k);
-    // stencil sweeps leave one residual word per block, reduced per chunk
-    const bool parts = h->path == CPMDP_PATH_STENCIL;
-    const int nb = parts ? stencil_grid(h) : 0;
+  // stencil sweeps leave one residual word per block, reduced per chunk
+  const bool parts = h->path == CPMDP_PATH_STENCIL;
+  const int nb = parts ? stencil_grid(h) : 0;
+  struct Chunk {
+    int half, k;
+  };
+  Chunk q[2];
+  int nq = 0, next_half = 0;
+  int64_t issued = *sweeps;
+  auto issue = [&](int k) -> int {
+    const int half = next_half;
+    next_half ^= 1;
+    unsigned long long* sl = h->d.slots + static_cast<size_t>(half) * kHalf * kSpread;
+    double* pt = parts ? h->d.parts + static_cast<size_t>(half) * kHalf * nb : nullptr;
+    launch_fill_u64(sl, k * kSpread, 0ull, h->stream);
     for (int j = 0; j < k; ++j) {
-      sweep(h, prec64, mode, cur, alt, R, pi, nullptr, nullptr, slot_of(h, j), nullptr, bf16,
-            nullptr, parts ? h->d.parts + static_cast<size_t>(j) * nb : nullptr);
+      sweep(h, prec64, mode, cur, alt, R, pi, nullptr, nullptr, sl + static_cast<size_t>(j) * kSpread,
+            nullptr, bf16, nullptr, pt ? pt + static_cast<size_t>(j) * nb : nullptr);
       std::swap(cur, alt);
     }
-    if (parts) launch_reduce_parts(h->d.parts, nb, k, h->d.slots, h->stream);
+    if (parts) launch_reduce_parts(pt, nb, k, sl, h->stream);
     int rc = check_device(h);
     if (rc) return rc;
-    rc = read_slots(h, k, res, nullptr);
-    if (rc) return rc;
-    *sweeps += k;
-    for (int j = 0; j < k; ++j)
-      if (!std::isfinite(res[j]))
+    HIP_TRY(h, hipMemcpyAsync(h->host_slots + static_cast<size_t>(half) * kHalf * kSpread, sl,
+                              sizeof(unsigned long long) * static_cast<size_t>(k) * kSpread,
+                              hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipEventRecord(h->chunk_ev[half], h->stream));
+    q[nq++] = Chunk{half, k};
+    issued += k;
+    return CPMDP_OK;
+  };
+  // Wait for the oldest chunk in flight; its first and last residuals.
+  double rf = INFINITY, rl = INFINITY;
+  int kprev = 0;
+  auto collect = [&]() -> int {
+    const Chunk c = q[0];
+    q[0] = q[1];
+    --nq;
+    HIP_TRY(h, hipEventSynchronize(h->chunk_ev[c.half]));
+    const unsigned long long* hs = h->host_slots + static_cast<size_t>(c.half) * kHalf * kSpread;
+    for (int j = 0; j < c.k; ++j) {
+      unsigned long long m = 0;
+      for (int w = 0; w < kSpread; ++w) m = std::max(m, hs[static_cast<size_t>(j) * kSpread + w]);
+      const double r = bits_to_double(m);
+      if (!std::isfinite(r))
         return fail(h, CPMDP_E_NONFINITE, "non-finite value produced during sweeps");
-    rf = res[0];
-    rl = res[k - 1];
-    kprev = k;
-    *last_res = rl;
-    if (rl <= tol) {
-      *done = true;
-      return CPMDP_OK;
+      if (j == 0) rf = r;
+      if (j == c.k - 1) rl = r;
     }
-    // stalled at the precision's rounding floor: over the chunk the residual
-    // fell by less than half of the contraction gamma^(k-1) guarantees
-    if (stall_floor > 0 && rl <= stall_floor && k >= 8 &&
-        rl >= rf * std::max(0.9, std::pow(h->gamma, 0.5 * (k - 1))))
-      return CPMDP_OK;
+    *sweeps += c.k;
+    kprev = c.k;
+    *last_res = rl;
+    return CPMDP_OK;
+  };
+  auto drain = [&]() -> int {
+    while (nq > 0) {
+      const int rc = collect();
+      if (rc) return rc;
+    }
+    return CPMDP_OK;
+  };
+  int rc = CPMDP_OK;
+  auto keep_trend = [&]() {
+    if (trend && kprev > 0) *trend = SweepTrend{rf, rl, kprev};
+  };
+  if (trend && trend->k > 1 && std::isfinite(trend->rl) && trend->rl > tol) {
+    // first chunks sized from the previous stage's contraction
+    double need = predict_need(trend->rf, trend->rl, trend->k, h->gamma, tol);
+    for (int c = 0; c < 2 && need > 0 && issued < budget && !rc; ++c) {
+      const int64_t k = static_cast<int64_t>(std::min(std::max(need, 4.0), 128.0));
+      rc = issue(static_cast<int>(std::min<int64_t>(k, budget - issued)));
+      need -= static_cast<double>(k);
+    }
+  } else {
+    if (issued < budget) rc = issue(static_cast<int>(std::min<int64_t>(4, budget - issued)));
+    if (!rc && issued < budget) rc = issue(static_cast<int>(std::min<int64_t>(8, budget - issued)));
   }
+  while (!rc && nq > 0) {
+    rc = collect();
+    if (rc) break;
+    const bool stalled = stall_floor > 0 && rl <= stall_floor && kprev >= 8 &&
+                         rl >= rf * std::max(0.9, std::pow(h->gamma, 0.5 * (kprev - 1)));
+    if (rl <= tol || stalled) {
+      rc = drain();
+      if (rc) break;
+      keep_trend();
+      if (rl <= tol) {
+        *done = true;
+        return CPMDP_OK;
+      }
+      if (stalled) return CPMDP_OK;
+    }
+    // queue the next chunk (4..128 sweeps, bounded to keep the overshoot
+    // past tol small) unless the one in flight is predicted to finish
+    int64_t inflight = 0;
+    for (int i = 0; i < nq; ++i) inflight += q[i].k;
+    if (issued < budget) {
+      const double need = predict_need(rf, rl, kprev, h->gamma, tol) - static_cast<double>(inflight);
+      if (need > 0 || nq == 0) {
+        const int64_t k = static_cast<int64_t>(std::min(std::max(need, 4.0), 128.0));
+        rc = issue(static_cast<int>(std::min<int64_t>(k, budget - issued)));
+      }
+    }
+  }
+  if (rc) {
+    (void)hipStreamSynchronize(h->stream);   // leave no chunk running on error
+    return rc;
+  }
+  keep_trend();
   return CPMDP_OK;
 }
 
@@ -639,6 +728,7 @@ int cpmdp_create(cpmdp_t** out, int32_t n_dims, const int64_t* sizes, int32_t n_
   h->factors.assign(factors, factors + F);
   h->lambdas.assign(lambdas, lambdas + T);
   h->rewards.assign(rewards, rewards + S);
+  for (int64_t s = 0; s < S; ++s) h->rmax = std::max(h->rmax, std::fabs(rewards[s]));
   h->terminal.assign(static_cast<size_t>(S), 0);
   h->term_start.resize(n_actions + 1);
   h->term_start[0] = 0;
@@ -793,6 +883,7 @@ int cpmdp_bind(cpmdp_t* h, void* ws, size_t bytes, void* stream) {
                              hipHostMallocDefault));
     HIP_TRY(h, hipHostMalloc(reinterpret_cast<void**>(&h->host_ctr), sizeof(unsigned) * 8,
                              hipHostMallocDefault));
+    for (auto& e : h->chunk_ev) HIP_TRY(h, hipEventCreateWithFlags(&e, hipEventDisableTiming));
   }
   const size_t S = static_cast<size_t>(h->S);
   const bool obst = !h->obstacle.empty();
@@ -972,11 +1063,10 @@ int cpmdp_value_iteration(cpmdp_t* h, double* V, int32_t* pi_out, double eps, in
   bool done = false;
   double last = INFINITY;
   const hipStream_t st = h->stream;
+  SweepTrend trend;   // carried across the precision stages
   if (precision != CPMDP_FP64) {
     // Low-precision sweeps until their own rounding floor, then FP64.
-    double rmax = 0.0;
-    for (double r : h->rewards) rmax = std::max(rmax, std::fabs(r));
-    const double vbound = rmax / (1.0 - h->gamma);
+    const double vbound = h->rmax / (1.0 - h->gamma);
     const double floor32 = 8.0 * std::ldexp(1.0, -24) * std::max(1.0, vbound);
     launch_f64_to_f32(V, h->d.Va32, h->S, st);
     float* cur = h->d.Va32;
@@ -984,13 +1074,13 @@ int cpmdp_value_iteration(cpmdp_t* h, double* V, int32_t* pi_out, double eps, in
     if (precision == CPMDP_BF16) {   // BF16 sweeps until they stall, then FP32
       rc = run_sweeps<float>(h, false, MODE_MAX, cur, alt, h->d.R32, nullptr,
                              std::max(eps, floor32), INFINITY, max_iter - 1, &sweeps, &done,
-                             &last, true);
+                             &last, true, &trend);
       if (rc) return rc;
     }
     if (!done) {
       rc = run_sweeps<float>(h, false, MODE_MAX, cur, alt, h->d.R32, nullptr,
                              std::max(eps, floor32), floor32 * 4, max_iter - 1, &sweeps, &done,
-                             &last, false);
+                             &last, false, &trend);
       if (rc) return rc;
     }
     launch_f32_to_f64(cur, V, h->S, st);
@@ -1035,7 +1125,7 @@ int cpmdp_value_iteration(cpmdp_t* h, double* V, int32_t* pi_out, double eps, in
       double* cur = V;
       double* alt = h->d.Va64;
       rc = run_sweeps<double>(h, true, MODE_MAX, cur, alt, h->d.R64, nullptr, eps, 0.0,
-                              max_iter - 1, &sweeps, &done, &last, false);
+                              max_iter - 1, &sweeps, &done, &last, false, &trend);
       if (rc) return rc;
       if (cur != V) HIP_TRY(h, hipMemcpyAsync(V, cur, h->S * 8, hipMemcpyDeviceToDevice, st));
       rc = certify(h, V, pi_out, nullptr, &cert, nullptr);
@@ -1061,8 +1151,7 @@ int cpmdp_policy_iteration(cpmdp_t* h, double* V, int32_t* pi, double eps, int64
   if (rc) return rc;
   const hipStream_t st = h->stream;
   int64_t sweeps = 0, outer = 0;
-  double rmax = 0.0;
-  for (double r : h->rewards) rmax = std::max(rmax, std::fabs(r));
+  const double rmax = h->rmax;
   const double eps_floor = 0.5 * eps * (1.0 - h->gamma);
   double eps_eval = std::max(eps_floor, 1e-2 * std::max(rmax, 1e-300));
   double cert = INFINITY;
@@ -1223,6 +1312,8 @@ void cpmdp_destroy(cpmdp_t* h) {
   if (!h) return;
   if (h->host_slots) (void)hipHostFree(h->host_slots);
   if (h->host_ctr) (void)hipHostFree(h->host_ctr);
+  for (auto e : h->chunk_ev)
+    if (e) (void)hipEventDestroy(e);
   delete h;
 }
 

@@ -592,8 +592,7 @@ int batch_pi(cpmdp_batch_t* b, double* const* V_devs, int32_t* const* pi_devs, d
     d.parity = 0;
     d.eparity = 0;
     d.pi_out = pi_devs[i];
-    double rmax = 0.0;
-    for (double r : h->rewards) rmax = std::max(rmax, std::fabs(r));
+    const double rmax = h->rmax;
     eps_floor[i] = 0.5 * eps * (1.0 - h->gamma);
     eps_eval[i] = std::max(eps_floor[i], 1e-2 * std::max(rmax, 1e-300));
   }
@@ -947,8 +946,7 @@ int cpmdp_batch_solve(cpmdp_batch_t* b, double* const* V_devs, int32_t* const* p
     d.parity = 0;
     d.stage = precision == CPMDP_FP64 ? B_F64 : B_F32;
     d.pi_out = pi_devs ? pi_devs[i] : nullptr;
-    double rmax = 0.0;
-    for (double r : h->rewards) rmax = std::max(rmax, std::fabs(r));
+    const double rmax = h->rmax;
     floor32[i] = 8.0 * std::ldexp(1.0, -24) * std::max(1.0, rmax / (1.0 - h->gamma));
     d.stop = d.stage == B_F32 ? std::max(eps, floor32[i]) : eps;
   }

@@ -48,6 +48,7 @@ struct cpmdp {
   std::vector<int32_t> ranks;
   std::vector<int32_t> term_start;
   std::vector<double> factors, lambdas, rewards;
+  double rmax = 0.0;                     // max_s |R(s)| (set at create)
   std::vector<uint8_t> terminal;
   std::vector<uint8_t> obstacle;         // empty: no obstacles
   std::vector<uint8_t> kinds;
@@ -71,6 +72,7 @@ struct cpmdp {
   cpm::DevPtrs d;
   unsigned long long* host_slots = nullptr;  // pinned
   unsigned* host_ctr = nullptr;              // pinned
+  hipEvent_t chunk_ev[2] = {nullptr, nullptr};  // chunk residuals copied (per slot half)
   std::string err;
 };
 
