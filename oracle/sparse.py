@@ -64,6 +64,26 @@ def transition_csr(inst):
     return mats
 
 
+def lists_csr(mdp):
+    """A CSR matrices of an MDP given directly as Def. 3 lists (action-major
+    rows a * S + s, see ``instances.ListsMDP``); terminal rows are empty.
+    The other functions of this module take the result as ``mats`` together
+    with the MDP (which carries rewards, gamma and the terminal mask)."""
+    S, A = mdp.n_states, mdp.n_actions
+    live = mdp.terminal == 0
+    mats = []
+    for a in range(A):
+        lo, hi = mdp.row_ptr[a * S], mdp.row_ptr[(a + 1) * S]
+        counts = np.diff(mdp.row_ptr[a * S:(a + 1) * S + 1])
+        rows = np.repeat(np.arange(S), counts)
+        p = mdp.prob[lo:hi]
+        keep = live[rows]
+        M = sp.coo_matrix((p[keep], (rows[keep], mdp.succ[lo:hi][keep])), shape=(S, S)).tocsr()
+        M.sum_duplicates()
+        mats.append(M)
+    return mats
+
+
 def q_values(inst, mats, V) -> np.ndarray:
     """Q[a, s] = R(s) + gamma * (P_a V)(s); terminal and obstacle rows are
     empty so their continuation is zero."""

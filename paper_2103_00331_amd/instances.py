@@ -355,6 +355,130 @@ def paper_gridworld(sizes, n_terminal: int, n_obstacle: int, seed: int,
     return with_obstacles(inst, cells[n_terminal:])
 
 
+# ------------------------------------------- Def. 3 successor lists (no CP form)
+
+@dataclass
+class ListsMDP:
+    """An MDP given directly by the per-state successor lists of Def. 3: for
+    each action a and state s, the successors s' with P(s'|s,a) > 0.  Stored
+    as one CSR matrix per action, stacked: row a * S + s holds
+    succ[row_ptr[r]:row_ptr[r+1]] and prob[...] (the C ABI's layout)."""
+
+    n_states: int
+    n_actions: int
+    row_ptr: np.ndarray          # int64 [A*S + 1]
+    succ: np.ndarray             # int64 [nnz]
+    prob: np.ndarray             # float64 [nnz]
+    rewards: np.ndarray          # float64 [S]
+    gamma: float
+    terminal: np.ndarray         # uint8 [S]
+    name: str = ""
+    obstacle: Optional[np.ndarray] = None   # always None: lists encode any blocking
+
+
+def _lists_from_rows(S, A, rows, rewards, gamma, terminal, name) -> ListsMDP:
+    """rows[a][s] = dict successor -> probability."""
+    ptr, succ, prob = [0], [], []
+    for a in range(A):
+        for s in range(S):
+            items = sorted(rows[a][s].items())
+            succ += [k for k, _ in items]
+            prob += [v for _, v in items]
+            ptr.append(len(succ))
+    return ListsMDP(S, A, np.asarray(ptr, np.int64), np.asarray(succ, np.int64),
+                    np.asarray(prob, np.float64), np.asarray(rewards, np.float64).copy(),
+                    float(gamma), np.asarray(terminal, np.uint8).copy(), name)
+
+
+def gridworld_lists(sizes, slip, rewards, gamma, terminal=None, obstacle=None,
+                    name="") -> ListsMDP:
+    """The slip GridWorld written directly as Def. 3 lists by moving an agent
+    (no Kronecker factors): action a = 2k + d moves along dim k (d = 0: +1,
+    d = 1: -1) with probability 1 - slip, or one step along another dim with
+    slip / (2(n-1)) each; a move that leaves the grid or lands on an obstacle
+    keeps the agent in place.  Obstacle states get reward 0 and are made
+    terminal (their value is 0)."""
+    sizes = [int(m) for m in sizes]
+    n = len(sizes)
+    S = int(np.prod(sizes))
+    term = np.zeros(S, np.uint8) if terminal is None else np.asarray(terminal, np.uint8).copy()
+    obs = np.zeros(S, bool) if obstacle is None else np.asarray(obstacle).astype(bool)
+    R = np.asarray(rewards, np.float64).reshape(S).copy()
+    R[obs] = 0.0
+    term[obs] = 1
+    strides = [int(np.prod(sizes[k + 1:])) for k in range(n)]
+    coords = np.stack(np.unravel_index(np.arange(S), sizes), axis=1)
+    src = np.arange(S, dtype=np.int64)
+    ptr, succ, prob = [np.zeros(1, np.int64)], [], []
+    base = 0
+    for a in range(2 * n):
+        k, step = a // 2, (1 if a % 2 == 0 else -1)
+        moves = [(k, step, 1.0 if n == 1 else 1.0 - slip)]
+        if n > 1:
+            for j in range(n):
+                if j != k:
+                    w = slip / (2 * (n - 1))
+                    moves += [(j, +1, w), (j, -1, w)]
+        ss, tt, pp = [], [], []
+        for dim, st, p in moves:
+            if p == 0.0:
+                continue
+            c = coords[:, dim] + st
+            ok = (c >= 0) & (c < sizes[dim])
+            tgt = np.where(ok, src + st * strides[dim], src)
+            tgt = np.where(obs[tgt], src, tgt)
+            ss.append(src)
+            tt.append(tgt)
+            pp.append(np.full(S, p))
+        ss, tt, pp = np.concatenate(ss), np.concatenate(tt), np.concatenate(pp)
+        # merge moves that reach the same successor, rows in state order,
+        # successors ascending inside a row
+        key, inv = np.unique(ss * S + tt, return_inverse=True)
+        merged = np.zeros(key.size)
+        np.add.at(merged, inv, pp)
+        counts = np.bincount(key // S, minlength=S)
+        ptr.append(base + np.cumsum(counts))
+        base += key.size
+        succ.append(key % S)
+        prob.append(merged)
+    return ListsMDP(S, 2 * n, np.concatenate(ptr), np.concatenate(succ), np.concatenate(prob),
+                    R, float(gamma), term, name or "lists_grid")
+
+
+def random_lists(S: int, A: int, k_max: int, seed: int, gamma: float = 0.9,
+                 n_terminal: int = 0, locality: int = 0) -> ListsMDP:
+    """A random MDP with no structure: each (s, a) has 1..k_max distinct
+    successors (near s when locality > 0, else anywhere) with Dirichlet(1)
+    probabilities; rewards N(0, 1)."""
+    rng = np.random.default_rng(seed)
+    rows = []
+    for a in range(A):
+        per_state = []
+        for s in range(S):
+            k = int(rng.integers(1, k_max + 1))
+            if locality > 0:
+                cand = np.arange(max(0, s - locality), min(S, s + locality + 1))
+            else:
+                cand = np.arange(S)
+            k = min(k, cand.size)
+            tg = rng.choice(cand, k, replace=False)
+            p = rng.dirichlet(np.ones(k))
+            per_state.append({int(t): float(v) for t, v in zip(tg, p)})
+        rows.append(per_state)
+    term = np.zeros(S, np.uint8)
+    if n_terminal:
+        term[rng.choice(S, n_terminal, replace=False)] = 1
+    return _lists_from_rows(S, A, rows, rng.normal(0.0, 1.0, S), gamma, term, "random_lists")
+
+
+def paper_gridworld_lists(inst: Instance) -> ListsMDP:
+    """The Table 1 GridWorld instance (CP form, with obstacles) rewritten as
+    Def. 3 lists by move simulation, for the same problem on both paths."""
+    return gridworld_lists([int(m) for m in inst.sizes], float(inst.meta["slip"]),
+                           inst.rewards, inst.gamma, inst.terminal, inst.obstacle,
+                           name=inst.name + "_lists")
+
+
 def seeded_values(n: int, seed: int, scale: float = 1.0) -> np.ndarray:
     """A seeded FP64 value vector (e.g. the common V fed to one backup)."""
     return np.random.default_rng(seed).normal(0.0, scale, n)

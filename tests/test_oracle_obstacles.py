@@ -150,3 +150,47 @@ def test_pins_catch_obstacle_reward(monkeypatch):
     monkeypatch.setattr(od, "continuation", lambda inst: inst.gamma * (1.0 - inst.terminal))
     with pytest.raises(AssertionError):
         test_obstacle_corridor_closed_form("dense")
+
+
+# ------------------------------------------------ Def. 3 lists given directly
+
+@pytest.mark.parametrize("case", ["plain", "walls"])
+def test_lists_by_move_simulation_equal_cp_successor_lists(case):
+    """The GridWorld written as Def. 3 lists by moving an agent equals the
+    successor lists that O2 enumerates from the Kronecker factors (two
+    independent constructions of the same operator)."""
+    inst = I.grid_small([5, 4, 6], slip=0.2, gamma=0.95, seed=8)
+    if case == "walls":
+        inst = I.with_obstacles(inst, [3, 17, 40, 41, 42, 77])
+    lists = I.gridworld_lists([5, 4, 6], 0.2, inst.rewards, inst.gamma, inst.terminal,
+                              inst.obstacle)
+    A = sparse.lists_csr(lists)
+    Bm = sparse.transition_csr(inst)
+    for a in range(inst.n_actions):
+        assert abs(A[a] - Bm[a]).max() <= 1e-15
+    V1, pi1, _, _ = sparse.value_iteration(lists, mats=A)
+    V2, pi2, _, _ = sparse.value_iteration(inst, mats=Bm)
+    np.testing.assert_allclose(V1, V2, atol=1e-12)
+    assert np.array_equal(pi1, pi2)
+
+
+def test_lists_random_mdp_brute_force():
+    """A random MDP with no structure, as lists: VI and PI of O2 reach the
+    elementwise maximum over all A^S deterministic policies (each evaluated
+    by an exact linear solve)."""
+    mdp = I.random_lists(7, 3, 3, seed=9, gamma=0.85, n_terminal=1)
+    mats = sparse.lists_csr(mdp)
+    P = np.stack([M.toarray() for M in mats])
+    S = mdp.n_states
+    live = mdp.terminal == 0
+    np.testing.assert_allclose(P[:, live].sum(axis=2), 1.0, atol=1e-14)
+    best = np.full(S, -np.inf)
+    for pol in itertools.product(range(mdp.n_actions), repeat=S):
+        P_pi = P[np.asarray(pol), np.arange(S), :]
+        V = np.linalg.solve(np.eye(S) - mdp.gamma * P_pi, mdp.rewards)
+        best = np.maximum(best, V)
+    V, _, _, res = sparse.value_iteration(mdp, mats=mats)
+    assert res <= 1e-12
+    np.testing.assert_allclose(V, best, atol=1e-10)
+    Vp, _, _ = sparse.policy_iteration(mdp, mats=mats)
+    np.testing.assert_allclose(Vp, best, atol=1e-10)
