@@ -16,7 +16,8 @@ FP64 CPU oracle timed on a bounded sample of the same workload.
 Other workloads (--workload): grid4d_96 (96^4, HBM-resident), dense6_16
 (16^6, dense 16x16 factors, 12 actions of rank 8), batch512 (512 mixed
 GridWorlds), warm64 (learned warm start on 64^3) and paper2d_1000 (the
-1000 x 1000 GridWorld of Table 1 with 22 terminals and 800 obstacles).
+1000 x 1000 GridWorld of Table 1 with 22 terminals and 800 obstacles) and
+paper2d_lists (the same problem given as Def. 3 successor lists).
 """
 import argparse
 import hashlib
@@ -249,6 +250,77 @@ def bench_grid(args, m):
     }
     model.close()
     return out, inst
+
+
+def bench_lists(args):
+    """The 1000 x 1000 Table 1 GridWorld given as Def. 3 successor lists
+    (cpmdp_create_lists): the same problem as paper2d_1000 without its
+    Kronecker structure."""
+    import torch
+
+    from paper_2103_00331_amd import binding as B
+    from paper_2103_00331_amd import instances as I
+
+    _log("building the 1000 x 1000 GridWorld as successor lists")
+    mdp = I.paper_gridworld_lists(I.named("paper2d_1000"))
+    S, A = mdp.n_states, mdp.n_actions
+    nnz = int(mdp.row_ptr[-1])
+    model = B.Model(mdp)
+    eps = 1e-6
+    V = torch.zeros(S, dtype=torch.float64, device="cuda")
+    pi = torch.zeros(S, dtype=torch.int32, device="cuda")
+    prec = {"fp32": B.CPMDP_FP32, "fp64": B.CPMDP_FP64}[args.precision]
+
+    def vi(p):
+        V.zero_()
+        code, sweeps, res = B.cpmdp_value_iteration(model.h, V, pi, eps, 100000, p)
+        assert code == B.CPMDP_OK and res <= eps, (code, res)
+        return sweeps
+
+    times = {}
+    for key, p in (("chosen", prec), ("plain", B.CPMDP_FP64)):
+        for _ in range(max(1, args.warmup)):
+            vi(p)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sw = 0
+        for _ in range(args.steps):
+            sw += vi(p)
+        torch.cuda.synchronize()
+        times[key] = ((time.perf_counter() - t0) / args.steps, sw / args.steps)
+    _log(f"chosen: {times['chosen'][0] * 1e3:.2f} ms ({times['chosen'][1]:.0f} sweeps); "
+         f"plain FP64 VI {times['plain'][0] * 1e3:.2f} ms")
+    Va = torch.zeros(S, dtype=torch.float32, device="cuda")
+    Vb = torch.zeros_like(Va)
+    ms = B.cpmdp_time_sweeps(model.h, Va, Vb, 200, B.CPMDP_FP32, 0)
+    # V, R, V' words + terminal bit + one (successor, probability) pair of
+    # 4 + 4 bytes per list entry
+    algo_bytes = S * 12.0 + S / 8.0 + nnz * 8.0
+    achieved = algo_bytes / (ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "kernel": "lists_kernel<float, MODE_MAX>", "kernel_ms": ms,
+            "algorithmic_bytes_per_launch": algo_bytes, "list_entries": nnz}
+    ref = _copy_reference(algo_bytes)
+    roof.update(ref)
+    roof["frac_of_stream_copy"] = achieved / ref["stream_copy_GBps"]
+    chosen_s, chosen_sw = times["chosen"]
+    out = {
+        "metric": METRIC, "value": chosen_sw * S * A / chosen_s, "unit": "state-action backups/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": chosen_s * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if prec == B.CPMDP_FP32 else "f64", "data": "synthetic",
+        "config": {"workload": f"gridworld_1000x1000 (Table 1, 2-D) as Def. 3 successor lists: "
+                               f"{S} states, {A} actions, {nnz} list entries, 22 terminals, "
+                               "800 obstacles, gamma 0.9",
+                   "method": f"vi {args.precision} sweeps + FP64 certificate", "eps": eps,
+                   "sweeps_per_solve": chosen_sw},
+        "time_to_eps_s": chosen_s, "plain_vi_time_to_eps_s": times["plain"][0],
+        "plain_vi_sweeps": times["plain"][1], "speedup_vs_plain_vi": times["plain"][0] / chosen_s,
+        "roofline": roof,
+    }
+    model.close()
+    return out
 
 
 def bench_dense(args):
@@ -516,6 +588,8 @@ def kernel_only(args):
         inst = I.dense_grid(16, seed=I.SEED_DENSE6)
     elif args.workload == "paper2d_1000":
         inst = I.named("paper2d_1000")
+    elif args.workload == "paper2d_lists":
+        inst = I.paper_gridworld_lists(I.named("paper2d_1000"))
     else:
         m = 32 if args.workload == "grid4d_32" else 96
         inst = I.grid4d(m, I.SEED_GRID4 if m == 32 else I.SEED_GRID4_LARGE)
@@ -543,7 +617,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="grid4d_32",
                     choices=["grid4d_32", "grid4d_96", "dense6_16", "batch512", "warm64",
-                             "paper2d_1000"])
+                             "paper2d_1000", "paper2d_lists"])
     ap.add_argument("--method", default="vi", choices=["vi", "pi"])
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -573,6 +647,8 @@ def main():
         out = bench_batch(args)
     elif args.workload == "warm64":
         out = bench_warm(args)
+    elif args.workload == "paper2d_lists":
+        out = bench_lists(args)
     else:
         out, inst = bench_grid(args, 32 if args.workload == "grid4d_32" else 96)
         if args.workload in ("grid4d_32", "paper2d_1000") and not args.no_cpu_baseline:

@@ -79,7 +79,8 @@ typedef enum cpmdp_precision {
 typedef enum cpmdp_path {
   CPMDP_PATH_STENCIL = 0, /* every rank term has at most one non-identity
                              factor and it is a clamped +-1 shift           */
-  CPMDP_PATH_DENSE = 1    /* general factors: mode-product chains           */
+  CPMDP_PATH_DENSE = 1,   /* general factors: mode-product chains           */
+  CPMDP_PATH_LISTS = 2    /* successor lists of Def. 3 (cpmdp_create_lists) */
 } cpmdp_path;
 
 /*
@@ -104,6 +105,36 @@ int cpmdp_create(cpmdp_t** out, int32_t n_dims, const int64_t* sizes,
                  int32_t n_actions, const int32_t* ranks,
                  const double* factors, const double* lambdas,
                  const double* rewards, double gamma);
+
+/*
+ * cpmdp_create_lists -- an MDP given directly by the per-state successor
+ * lists of Def. 3 (the components (s, s', P(s'|s,a)) of every state), for
+ * transition models with no Kronecker / CP structure.  The backup is Eq. 1
+ * over those lists.
+ *
+ *   n_states  S >= 1 (at most 2^30), states numbered 0..S-1
+ *   n_actions A in [1, 255]
+ *   row_ptr   [A*S + 1] int64, row r = a*S + s (action-major): the list of
+ *             (s, a) is entries row_ptr[r] .. row_ptr[r+1]-1; row_ptr[0] = 0,
+ *             non-decreasing
+ *   succ      [row_ptr[A*S]] int64 successor states s' in [0, S)
+ *   prob      [row_ptr[A*S]] FP64 P(s'|s,a) >= 0; every list sums to 1
+ *             within 1e-9 (repeated successors are allowed and add up)
+ *   rewards   [S] FP64 R(s);  gamma in [0, 1)
+ *
+ * Host arrays, read during the call (the library keeps its own copy, laid
+ * out for the device: 64-state slices, one per wave, each action's entries
+ * padded to the slice's longest list).  Terminal states are set with
+ * cpmdp_set_terminal; obstacles are not taken (the lists express blocked
+ * moves themselves).  Solvers run in FP64 or FP32 (BF16 returns
+ * CPMDP_E_UNSUPPORTED); batched solves do not take such handles.
+ * Returns CPMDP_OK and *out, or CPMDP_E_ARG (sizes, pointers, ranges),
+ * CPMDP_E_NONFINITE, CPMDP_E_NOT_STOCHASTIC (negative probability, list sum)
+ * or CPMDP_E_UNSUPPORTED (more than 2^31 padded entries), with *out = NULL.
+ */
+int cpmdp_create_lists(cpmdp_t** out, int64_t n_states, int32_t n_actions,
+                       const int64_t* row_ptr, const int64_t* succ, const double* prob,
+                       const double* rewards, double gamma);
 
 /* Terminal states (Sec. 3.2): mask [S], nonzero = terminal (V(s) = R(s), no
  * continuation).  Must be called before cpmdp_bind; default: none. */

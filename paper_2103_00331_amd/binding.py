@@ -27,7 +27,7 @@ CPMDP_E_UNSUPPORTED = -6
 CPMDP_E_STATE = -7
 
 CPMDP_FP64, CPMDP_FP32, CPMDP_BF16 = 0, 1, 2
-CPMDP_PATH_STENCIL, CPMDP_PATH_DENSE = 0, 1
+CPMDP_PATH_STENCIL, CPMDP_PATH_DENSE, CPMDP_PATH_LISTS = 0, 1, 2
 PRECISIONS = {"fp64": CPMDP_FP64, "fp32": CPMDP_FP32, "bf16": CPMDP_BF16}
 
 if not os.path.exists(LIB_PATH):
@@ -51,6 +51,8 @@ _szp = C.POINTER(C.c_size_t)
 _SIGS = {
     "cpmdp_create": (C.c_int, [C.POINTER(_p), C.c_int32, _i64p, C.c_int32, _i32p, _dp, _dp,
                                 _dp, C.c_double]),
+    "cpmdp_create_lists": (C.c_int, [C.POINTER(_p), C.c_int64, C.c_int32, _i64p, _i64p, _dp,
+                                      _dp, C.c_double]),
     "cpmdp_set_terminal": (C.c_int, [_p, _u8p]),
     "cpmdp_set_obstacles": (C.c_int, [_p, _u8p]),
     "cpmdp_get_path": (C.c_int, [_p, _i32p]),
@@ -136,6 +138,20 @@ def cpmdp_create(sizes: Sequence[int], ranks: Sequence[int], factors, lambdas, r
                             int(ranks.size), ranks.ctypes.data_as(_i32p),
                             factors.ctypes.data_as(_dp), lambdas.ctypes.data_as(_dp),
                             rewards.ctypes.data_as(_dp), float(gamma)))
+    return h
+
+
+def cpmdp_create_lists(n_states: int, n_actions: int, row_ptr, succ, prob, rewards,
+                       gamma: float):
+    row_ptr = np.ascontiguousarray(row_ptr, np.int64)
+    succ = np.ascontiguousarray(succ, np.int64)
+    prob = np.ascontiguousarray(prob, np.float64)
+    rewards = np.ascontiguousarray(rewards, np.float64)
+    h = _p()
+    _check(lib.cpmdp_create_lists(C.byref(h), int(n_states), int(n_actions),
+                                  row_ptr.ctypes.data_as(_i64p), succ.ctypes.data_as(_i64p),
+                                  prob.ctypes.data_as(_dp), rewards.ctypes.data_as(_dp),
+                                  float(gamma)))
     return h
 
 
@@ -298,8 +314,12 @@ class Model:
     def __init__(self, inst, device="cuda", stream=None):
         import torch
         self.inst = inst
-        self.h = cpmdp_create(inst.sizes, inst.ranks, inst.factors, inst.lambdas,
-                              inst.rewards, inst.gamma)
+        if hasattr(inst, "row_ptr"):          # an MDP given as Def. 3 lists
+            self.h = cpmdp_create_lists(inst.n_states, inst.n_actions, inst.row_ptr,
+                                        inst.succ, inst.prob, inst.rewards, inst.gamma)
+        else:
+            self.h = cpmdp_create(inst.sizes, inst.ranks, inst.factors, inst.lambdas,
+                                  inst.rewards, inst.gamma)
         if np.any(inst.terminal):
             cpmdp_set_terminal(self.h, inst.terminal)
         obstacle = getattr(inst, "obstacle", None)

@@ -204,7 +204,15 @@ void layout(const cpmdp_t* h, DevPtrs* dp, char* base, size_t* total) {
   d.E1 = cv.take<float>(S);
   d.r32 = cv.take<float>(S);
   d.piA = cv.take<int32_t>(S);
-  if (h->path == CPMDP_PATH_STENCIL) {
+  if (h->path == CPMDP_PATH_LISTS) {
+    const size_t ent = h->l_succ.size();
+    d.l_cols = cv.take<int32_t>(h->l_cols.size());
+    d.l_succ = cv.take<int32_t>(ent);
+    d.l_p64 = cv.take<double>(ent);
+    d.l_p32 = cv.take<float>(ent);
+    d.parts = cv.take<double>(static_cast<size_t>(kSlots) * h->l_blocks);
+    d.W = nullptr;
+  } else if (h->path == CPMDP_PATH_STENCIL) {
     const size_t P = 2 * static_cast<size_t>(h->n) + 1;
     d.w64 = cv.take<double>(3 * A * P);   // w, wdiff [A][P], then wbase [P]
     d.w32 = cv.take<float>(3 * A * P);
@@ -297,6 +305,7 @@ static StencilArgs<T> stencil_args(cpmdp_t* h, const void* V, void* Vout, const 
 }
 
 int stencil_grid(const cpmdp_t* h) {
+  if (h->path == CPMDP_PATH_LISTS) return h->l_blocks;
   return (h->st_march && h->opt_march) ? h->st_march_blocks : h->st_blocks;
 }
 
@@ -307,6 +316,41 @@ void sweep(cpmdp_t* h, bool prec64, int mode, const void* V, void* Vout, const v
            unsigned long long* slot, unsigned int* ctr, bool bf16, const LaunchTiming* tm,
            double* part) {
   const hipStream_t st = h->stream;
+  if (h->path == CPMDP_PATH_LISTS) {
+    auto fill = [&](auto& a, auto* prob) {
+      using T = std::remove_pointer_t<decltype(prob)>;
+      a.S = static_cast<int32_t>(h->S);
+      a.A = h->A;
+      a.nslices = h->l_nslices;
+      a.slices_per_block = h->l_slices_per_block;
+      a.col_ptr = h->d.l_cols;
+      a.succ = h->d.l_succ;
+      a.prob = prob;
+      a.V = static_cast<const T*>(V);
+      a.Vout = static_cast<T*>(Vout);
+      a.R = static_cast<const T*>(R);
+      a.term_bits = h->d.tbits;
+      a.gamma = static_cast<T>(h->gamma);
+      a.pi_in = pi_in;
+      a.pi_out = pi_out;
+      a.r_out = r_out;
+      a.vmax_bits = h->d.vmax;
+      a.res_slot = slot;
+      a.res_part = part;
+      a.change_count = ctr;
+      a.nblocks = h->l_blocks;
+    };
+    if (prec64) {
+      ListsArgs<double> a{};
+      fill(a, h->d.l_p64);
+      launch_lists<double>(a, mode, st, tm);
+    } else {
+      ListsArgs<float> a{};
+      fill(a, h->d.l_p32);
+      launch_lists<float>(a, mode, st, tm);
+    }
+    return;
+  }
   if (h->path == CPMDP_PATH_STENCIL) {
     if (prec64) {
       StencilArgs<double> a =
@@ -460,8 +504,9 @@ static int run_sweeps(cpmdp_t* h, bool prec64, int mode, P*& cur, P*& alt, const
                       SweepTrend* trend = nullptr) {
   constexpr int kHalf = kSlots / 2;   // chunks hold at most 128 sweeps
   *done = false;
-  // stencil sweeps leave one residual word per block, reduced per chunk
-  const bool parts = h->path == CPMDP_PATH_STENCIL;
+  // stencil and list sweeps leave one residual word per block, reduced per
+  // chunk
+  const bool parts = h->path != CPMDP_PATH_DENSE;
   const int nb = parts ? stencil_grid(h) : 0;
   struct Chunk {
     int half, k;
@@ -798,6 +843,100 @@ int cpmdp_create(cpmdp_t** out, int32_t n_dims, const int64_t* sizes, int32_t n_
   return CPMDP_OK;
 }
 
+int cpmdp_create_lists(cpmdp_t** out, int64_t n_states, int32_t n_actions,
+                       const int64_t* row_ptr, const int64_t* succ, const double* prob,
+                       const double* rewards, double gamma) {
+  if (!out) return fail(nullptr, CPMDP_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (!row_ptr || !rewards) return fail(nullptr, CPMDP_E_ARG, "NULL input array");
+  if (n_states < 1 || n_states > (int64_t{1} << 30))
+    return fail(nullptr, CPMDP_E_ARG, "n_states must be in [1, 2^30]");
+  if (n_actions < 1 || n_actions > kMaxActions)
+    return fail(nullptr, CPMDP_E_ARG, "n_actions must be in [1, 255]");
+  if (!std::isfinite(gamma)) return fail(nullptr, CPMDP_E_NONFINITE, "gamma is not finite");
+  if (!(gamma >= 0.0 && gamma < 1.0)) return fail(nullptr, CPMDP_E_ARG, "gamma must be in [0, 1)");
+  const int64_t S = n_states, A = n_actions, rows = S * A;
+  if (row_ptr[0] != 0) return fail(nullptr, CPMDP_E_ARG, "row_ptr[0] must be 0");
+  for (int64_t r = 0; r < rows; ++r)
+    if (row_ptr[r + 1] < row_ptr[r]) return fail(nullptr, CPMDP_E_ARG, "row_ptr must not decrease");
+  const int64_t nnz = row_ptr[rows];
+  if (nnz > 0 && (!succ || !prob)) return fail(nullptr, CPMDP_E_ARG, "NULL succ / prob");
+  for (int64_t s = 0; s < S; ++s)
+    if (!std::isfinite(rewards[s])) return fail(nullptr, CPMDP_E_NONFINITE, "non-finite reward");
+  for (int64_t r = 0; r < rows; ++r) {
+    double sum = 0.0;
+    for (int64_t e = row_ptr[r]; e < row_ptr[r + 1]; ++e) {
+      if (succ[e] < 0 || succ[e] >= S) return fail(nullptr, CPMDP_E_ARG, "successor out of range");
+      if (!std::isfinite(prob[e])) return fail(nullptr, CPMDP_E_NONFINITE, "non-finite probability");
+      if (prob[e] < 0.0) return fail(nullptr, CPMDP_E_NOT_STOCHASTIC, "negative probability");
+      sum += prob[e];
+    }
+    if (std::fabs(sum - 1.0) > 1e-9) {
+      char buf[160];
+      std::snprintf(buf, sizeof buf, "list of action %lld, state %lld sums to %.17g",
+                    (long long)(r / S), (long long)(r % S), sum);
+      return fail(nullptr, CPMDP_E_NOT_STOCHASTIC, buf);
+    }
+  }
+  cpmdp_t* h = new (std::nothrow) cpmdp_t();
+  if (!h) return fail(nullptr, CPMDP_E_ARG, "out of host memory");
+  h->n = 1;
+  h->S = S;
+  h->A = n_actions;
+  h->gamma = gamma;
+  h->sizes.assign(1, S);
+  h->rewards.assign(rewards, rewards + S);
+  for (int64_t s = 0; s < S; ++s) h->rmax = std::max(h->rmax, std::fabs(rewards[s]));
+  h->terminal.assign(static_cast<size_t>(S), 0);
+  h->path = CPMDP_PATH_LISTS;
+  // Sliced layout: per 64-state slice and action, as many columns as the
+  // slice's longest list; entry of lane l in column c at c * 64 + l.
+  const int64_t nsl = (S + kSlice - 1) / kSlice;
+  h->l_nslices = static_cast<int32_t>(nsl);
+  h->l_cols.assign(static_cast<size_t>(nsl * A + 1), 0);
+  int64_t cols = 0;
+  for (int64_t q = 0; q < nsl; ++q)
+    for (int64_t a = 0; a < A; ++a) {
+      int64_t w = 0;
+      for (int64_t s = q * kSlice; s < std::min(S, (q + 1) * kSlice); ++s)
+        w = std::max(w, row_ptr[a * S + s + 1] - row_ptr[a * S + s]);
+      cols += w;
+      if (cols * kSlice >= (int64_t{1} << 31)) {
+        delete h;
+        return fail(nullptr, CPMDP_E_UNSUPPORTED, "successor lists too long (2^31 padded entries)");
+      }
+      h->l_cols[q * A + a + 1] = static_cast<int32_t>(cols);
+    }
+  h->l_succ.assign(static_cast<size_t>(cols * kSlice), 0);
+  h->l_prob.assign(static_cast<size_t>(cols * kSlice), 0.0);
+  for (int64_t q = 0; q < nsl; ++q)
+    for (int64_t a = 0; a < A; ++a) {
+      const int64_t c0 = h->l_cols[q * A + a];
+      const int64_t w = h->l_cols[q * A + a + 1] - c0;
+      for (int64_t l = 0; l < kSlice; ++l) {
+        const int64_t s = q * kSlice + l;
+        const int64_t r0 = s < S ? row_ptr[a * S + s] : 0, len = s < S ? row_ptr[a * S + s + 1] - r0 : 0;
+        for (int64_t j = 0; j < w; ++j) {
+          const size_t e = static_cast<size_t>((c0 + j) * kSlice + l);
+          if (j < len) {
+            h->l_succ[e] = static_cast<int32_t>(succ[r0 + j]);
+            h->l_prob[e] = prob[r0 + j];
+          } else {
+            h->l_succ[e] = static_cast<int32_t>(s < S ? s : 0);   // padding: weight 0
+          }
+        }
+      }
+    }
+  // blocks of 4 waves, each block a contiguous range of slices
+  const int64_t units = (nsl + kBlock / kSlice - 1) / (kBlock / kSlice);
+  const int64_t nb = std::min<int64_t>(units, kMaxBlocks);
+  const int64_t per_units = (units + nb - 1) / nb;
+  h->l_slices_per_block = static_cast<int32_t>(per_units * (kBlock / kSlice));
+  h->l_blocks = static_cast<int32_t>((nsl + h->l_slices_per_block - 1) / h->l_slices_per_block);
+  *out = h;
+  return CPMDP_OK;
+}
+
 int cpmdp_set_terminal(cpmdp_t* h, const uint8_t* mask) {
   if (!h) return fail(nullptr, CPMDP_E_ARG, "handle is NULL");
   if (!mask) return fail(h, CPMDP_E_ARG, "mask is NULL");
@@ -819,7 +958,8 @@ int cpmdp_set_obstacles(cpmdp_t* h, const uint8_t* mask) {
   if (h->path != CPMDP_PATH_STENCIL)
     return fail(h, CPMDP_E_UNSUPPORTED,
                 "obstacles need shift/identity factors: with dense factors the blocked "
-                "moves are not a sparse correction of the Kronecker form");
+                "moves are not a sparse correction of the Kronecker form, and successor "
+                "lists encode blocked moves themselves");
   h->obstacle.assign(static_cast<size_t>(h->S), 0);
   for (int64_t s = 0; s < h->S; ++s) h->obstacle[s] = mask[s] ? 1 : 0;
   return CPMDP_OK;
@@ -928,7 +1068,17 @@ int cpmdp_bind(cpmdp_t* h, void* ws, size_t bytes, void* stream) {
   std::vector<float> fac32, lam32;
   std::vector<uint16_t> facbf;
   std::vector<int32_t> ts;
-  if (h->path == CPMDP_PATH_STENCIL) {
+  std::vector<float> lp32;
+  if (h->path == CPMDP_PATH_LISTS) {
+    const size_t ent = h->l_succ.size();
+    lp32.resize(ent);
+    for (size_t i = 0; i < ent; ++i) lp32[i] = static_cast<float>(h->l_prob[i]);
+    HIP_TRY(h, hipMemcpyAsync(h->d.l_cols, h->l_cols.data(), h->l_cols.size() * 4,
+                              hipMemcpyHostToDevice, st));
+    HIP_TRY(h, hipMemcpyAsync(h->d.l_succ, h->l_succ.data(), ent * 4, hipMemcpyHostToDevice, st));
+    HIP_TRY(h, hipMemcpyAsync(h->d.l_p64, h->l_prob.data(), ent * 8, hipMemcpyHostToDevice, st));
+    HIP_TRY(h, hipMemcpyAsync(h->d.l_p32, lp32.data(), ent * 4, hipMemcpyHostToDevice, st));
+  } else if (h->path == CPMDP_PATH_STENCIL) {
     const int P = 2 * h->n + 1, A = h->A;
     std::vector<double> w64(3 * static_cast<size_t>(A) * P, 0.0);
     std::copy(h->w.begin(), h->w.end(), w64.begin());
@@ -985,6 +1135,8 @@ static int check_common(cpmdp_t* h, int precision) {
   if (!h->bound) return fail(h, CPMDP_E_STATE, "handle is not bound to a workspace");
   if (precision < CPMDP_FP64 || precision > CPMDP_BF16)
     return fail(h, CPMDP_E_ARG, "unknown precision");
+  if (precision == CPMDP_BF16 && h->path == CPMDP_PATH_LISTS)
+    return fail(h, CPMDP_E_UNSUPPORTED, "successor lists run in FP64 or FP32 (no matrix product)");
   return CPMDP_OK;
 }
 
@@ -1291,7 +1443,7 @@ int cpmdp_time_sweeps(cpmdp_t* h, void* V_a, void* V_b, int32_t n, int precision
     sweep(h, p64, mode == 0 ? MODE_MAX : MODE_EVAL, cur, alt,
           p64 ? static_cast<const void*>(h->d.R64) : h->d.R32, pi, nullptr, nullptr, h->d.slots,
           nullptr, precision == CPMDP_BF16, &tm,
-          h->path == CPMDP_PATH_STENCIL ? h->d.parts : nullptr);
+          h->path != CPMDP_PATH_DENSE ? h->d.parts : nullptr);
     std::swap(cur, alt);
   }
   rc = check_device(h);

@@ -102,6 +102,39 @@ template <typename T>
 void launch_stencil(const StencilArgs<T>& a, int mode, hipStream_t st,
                     const LaunchTiming* tm = nullptr);
 
+// ---------------------------------------------------- Def. 3 successor lists
+// Sliced layout with 64-state slices (one slice per wave): for slice q and
+// action a the columns col_ptr[q*A + a] .. col_ptr[q*A + a + 1] hold the
+// slice's lists for a, entry of lane l in column c at c * 64 + l (padding:
+// probability 0).
+constexpr int kSlice = 64;
+
+template <typename T>
+struct ListsArgs {
+  int32_t S, A, nslices;
+  int32_t slices_per_block;     // contiguous slices per block
+  const int32_t* col_ptr;       // [nslices * A + 1]
+  const int32_t* succ;          // [columns * 64]
+  const T* prob;                // [columns * 64]
+  const T* V;
+  T* Vout;
+  const T* R;
+  const uint32_t* term_bits;
+  T gamma;
+  const int32_t* pi_in;
+  int32_t* pi_out;
+  float* r_out;
+  const unsigned long long* vmax_bits;
+  unsigned long long* res_slot;
+  double* res_part;             // if set: per-block residual words (no atomics)
+  unsigned int* change_count;
+  int32_t nblocks;
+};
+
+template <typename T>
+void launch_lists(const ListsArgs<T>& a, int mode, hipStream_t st,
+                  const LaunchTiming* tm = nullptr);
+
 // ----------------------------------------------------------- dense chains
 struct ChainGeom {
   int32_t n, n1;                // dims [0, n1) = row group, [n1, n) = column group

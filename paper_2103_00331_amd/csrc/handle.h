@@ -35,6 +35,10 @@ struct DevPtrs {
   char* W = nullptr;                     // dense-chain intermediates
   double* parts = nullptr;               // stencil: per-block residuals [kSlots][blocks]
   uint16_t* obs = nullptr;               // stencil with obstacles: blocked directions [S]
+  int32_t* l_cols = nullptr;             // lists: column ranges [nslices * A + 1]
+  int32_t* l_succ = nullptr;             // lists: successors [columns * 64]
+  double* l_p64 = nullptr;               // lists: probabilities [columns * 64]
+  float* l_p32 = nullptr;
 };
 
 }  // namespace cpm
@@ -62,6 +66,10 @@ struct cpmdp {
   int32_t st_states_per_block = 256;
   int32_t st_march = 0;                  // stencil: marching form (see stencil.hip)
   int32_t st_march_tiles = 0, st_march_seg = 0, st_march_blocks = 0;
+  // Def. 3 lists path: sliced layout built at create (see lists.hip)
+  int32_t l_nslices = 0, l_blocks = 0, l_slices_per_block = 0;
+  std::vector<int32_t> l_cols, l_succ;
+  std::vector<double> l_prob;
   bool opt_march = true;                 // CPMDP_OPT_MARCH
   cpm::GridGeom geom{};
   cpm::ChainGeom cg64{}, cg32{};
@@ -83,6 +91,7 @@ void sweep(cpmdp_t* h, bool prec64, int mode, const void* V, void* Vout, const v
            const int32_t* pi_in, int32_t* pi_out, float* r_out, unsigned long long* slot,
            unsigned int* ctr, bool bf16, const LaunchTiming* tm = nullptr,
            double* part = nullptr);
-// Blocks of one stencil sweep (the per-block residual words it needs).
+// Blocks of one stencil or lists sweep (the per-block residual words it
+// needs).
 int stencil_grid(const cpmdp_t* h);
 }  // namespace cpm

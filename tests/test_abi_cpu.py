@@ -141,3 +141,51 @@ def test_dense_factor_size_limit():
     with pytest.raises(B.CpmdpError) as e:
         B.cpmdp_create(*_args(d))
     assert e.value.code == B.CPMDP_E_UNSUPPORTED
+
+
+def _lists_args(m):
+    return (m.n_states, m.n_actions, m.row_ptr, m.succ, m.prob, m.rewards, m.gamma)
+
+
+def test_create_lists_valid_and_rejects_invalid():
+    m = I.random_lists(100, 3, 4, seed=2, gamma=0.9)
+    h = B.cpmdp_create_lists(*_lists_args(m))
+    assert B.cpmdp_get_path(h) == B.CPMDP_PATH_LISTS
+    assert B.cpmdp_workspace_bytes(h) > 0
+    mask = np.zeros(m.n_states, np.uint8)
+    mask[3] = 1
+    B.cpmdp_set_terminal(h, mask)
+    with pytest.raises(B.CpmdpError) as e:
+        B.cpmdp_set_obstacles(h, mask)        # lists express blocked moves themselves
+    assert e.value.code == B.CPMDP_E_UNSUPPORTED
+    B.cpmdp_destroy(h)
+
+    def expect(code, **kw):
+        a = dict(zip(["S", "A", "row_ptr", "succ", "prob", "rewards", "gamma"],
+                     [x.copy() if isinstance(x, np.ndarray) else x for x in _lists_args(m)]))
+        a.update(kw)
+        with pytest.raises(B.CpmdpError) as e:
+            B.cpmdp_create_lists(a["S"], a["A"], a["row_ptr"], a["succ"], a["prob"],
+                                 a["rewards"], a["gamma"])
+        assert e.value.code == code, str(e.value)
+
+    p = m.prob.copy()
+    p[0] += 1e-6
+    expect(B.CPMDP_E_NOT_STOCHASTIC, prob=p)                   # list sum off
+    p = m.prob.copy()
+    i = int(np.nonzero(np.diff(m.row_ptr) >= 2)[0][0])
+    lo = m.row_ptr[i]
+    p[lo], p[lo + 1] = p[lo] + p[lo + 1] + 0.5, -0.5
+    expect(B.CPMDP_E_NOT_STOCHASTIC, prob=p)                   # negative entry
+    s = m.succ.copy()
+    s[5] = m.n_states
+    expect(B.CPMDP_E_ARG, succ=s)                              # successor out of range
+    r = m.row_ptr.copy()
+    r[10], r[11] = r[11], r[10]
+    if r[10] != r[11]:
+        expect(B.CPMDP_E_ARG, row_ptr=r)                       # decreasing offsets
+    expect(B.CPMDP_E_ARG, gamma=1.0)
+    expect(B.CPMDP_E_ARG, A=0)
+    rw = m.rewards.copy()
+    rw[1] = np.inf
+    expect(B.CPMDP_E_NONFINITE, rewards=rw)
