@@ -54,6 +54,7 @@ STENCIL_SRC = ["paper_2103_00331_amd/csrc/stencil.hip", "paper_2103_00331_amd/cs
 CHAIN_SRC = ["paper_2103_00331_amd/csrc/chain.hip", "paper_2103_00331_amd/csrc/common.cuh"]
 BATCH_SRC = ["paper_2103_00331_amd/csrc/batch.hip", "paper_2103_00331_amd/csrc/stencil_core.cuh",
              "paper_2103_00331_amd/csrc/common.cuh"]
+LISTS_SRC = ["paper_2103_00331_amd/csrc/lists.hip", "paper_2103_00331_amd/csrc/common.cuh"]
 PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp64": 78.6}
 
 
@@ -298,7 +299,8 @@ def bench_lists(args):
     algo_bytes = S * 12.0 + S / 8.0 + nnz * 8.0
     achieved = algo_bytes / (ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": _traffic("lists_fp32_paper2d_1000.md", LISTS_SRC),
             "kernel": "lists_kernel<float, MODE_MAX>", "kernel_ms": ms,
             "algorithmic_bytes_per_launch": algo_bytes, "list_entries": nnz}
     ref = _copy_reference(algo_bytes)
