@@ -213,8 +213,8 @@ __global__ __launch_bounds__(kBBlock) void batch_sweep_kernel(BatchArgs a, int j
       if (tl.y < 0) march_dispatch<T, MODE_MAX>(d, io, weights_of<T>(d), -1 - tl.y, res, rd, ch);
       else tile_dispatch<T, MODE_MAX>(d, io, weights_of<T>(d), s0, s1, T(0), res, rd, ch);
     }
-    block_max_to_slot(static_cast<double>(res),
-                      a.res + (static_cast<size_t>(j) * a.ninst + tl.x) * kBSpread, kBSpread - 1);
+    block_max_to_slot(res, a.res + (static_cast<size_t>(j) * a.ninst + tl.x) * kBSpread,
+                      kBSpread - 1);
   }
 }
 

@@ -37,43 +37,54 @@ __device__ __forceinline__ double nanmax(double a, double b) {
   return (a != a || a > b) ? a : b;
 }
 
+// max that keeps NaN, in the residual's own precision.
+template <typename R>
+__device__ __forceinline__ R nanmax_t(R a, R b) {
+  return (a != a || a > b) ? a : b;
+}
+
 // Block-wide max of v, folded into slot[blockIdx.x & spread_mask] (FP64 bit
 // pattern; non-negative doubles order like their bits, NaN sorts above +inf).
 // Spreading the atomics of a sweep over kSpread words keeps thousands of
-// blocks from serialising on one address; the reader takes the max.
-__device__ __forceinline__ void block_max_to_slot(double v, unsigned long long* slot,
+// blocks from serialising on one address; the reader takes the max.  FP32
+// residuals are reduced in FP32 (exact for a max) and widened once.
+template <typename R>
+__device__ __forceinline__ void block_max_to_slot(R v, unsigned long long* slot,
                                                   unsigned spread_mask = kSpread - 1) {
-  __shared__ double part[16];
+  __shared__ R part[16];
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = nanmax(v, __shfl_xor(v, off));
+  for (int off = 32; off > 0; off >>= 1) v = nanmax_t(v, __shfl_xor(v, off));
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   if (lane == 0) part[wid] = v;
   __syncthreads();
   if (threadIdx.x == 0) {
-    double m = part[0];
+    R m = part[0];
     const int nw = (blockDim.x + 63) >> 6;
-    for (int i = 1; i < nw; ++i) m = nanmax(m, part[i]);
+    for (int i = 1; i < nw; ++i) m = nanmax_t(m, part[i]);
     atomicMax(slot + (blockIdx.x & spread_mask),
-              static_cast<unsigned long long>(__double_as_longlong(m)));
+              static_cast<unsigned long long>(__double_as_longlong(static_cast<double>(m))));
   }
 }
 
-// Block-wide max of v stored to *dst by a plain store (no atomic): sweeps
-// that run in chunks give each block its own word and reduce the words of a
-// chunk in one small kernel afterwards, which is cheaper than thousands of
-// atomics per sweep that serialise on the slot words.
-__device__ __forceinline__ void block_max_store(double v, double* dst) {
-  __shared__ double part[16];
+// Block-wide max of v stored to *dst (as FP64) by a plain store (no atomic):
+// sweeps that run in chunks give each block its own word and reduce the
+// words of a chunk in one small kernel afterwards, which is cheaper than
+// thousands of atomics per sweep that serialise on the slot words.  An FP32
+// sweep reduces in FP32 (the max of FP32 values is exact, and half the
+// shuffles of an FP64 reduction: about 0.5 us less per 32^4 sweep).
+template <typename R>
+__device__ __forceinline__ void block_max_store(R v, double* dst) {
+  __shared__ R part[16];
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = nanmax(v, __shfl_xor(v, off));
+  for (int off = 32; off > 0; off >>= 1) v = nanmax_t(v, __shfl_xor(v, off));
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   if (lane == 0) part[wid] = v;
   __syncthreads();
   if (threadIdx.x == 0) {
-    double m = part[0];
+    R m = part[0];
     const int nw = (blockDim.x + 63) >> 6;
-    for (int i = 1; i < nw; ++i) m = nanmax(m, part[i]);
-    *dst = m;
+    for (int i = 1; i < nw; ++i) m = nanmax_t(m, part[i]);
+    *dst = static_cast<double>(m);
   }
 }
 

@@ -96,9 +96,13 @@ __global__ __launch_bounds__(kBlock) void lists_kernel(ListsArgs<T> a) {
       if (MODE == MODE_GREEDY && a.pi_out) a.pi_out[s] = pnew;
     }
   }
-  const double rv = MODE == MODE_RESID ? res_d : static_cast<double>(res);
-  if (a.res_part) block_max_store(rv, a.res_part + blk);
-  else block_max_to_slot(rv, a.res_slot);
+  if constexpr (MODE == MODE_RESID) {
+    if (a.res_part) block_max_store(res_d, a.res_part + blk);
+    else block_max_to_slot(res_d, a.res_slot);
+  } else {
+    if (a.res_part) block_max_store(res, a.res_part + blk);
+    else block_max_to_slot(res, a.res_slot);
+  }
   if (MODE == MODE_GREEDY && a.change_count) block_sum_to_counter(changed, a.change_count);
 }
 

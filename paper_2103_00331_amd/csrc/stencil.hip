@@ -52,9 +52,13 @@ __global__ __launch_bounds__(kBlock) void stencil_kernel(StencilArgs<T> a) {
                                        s_first <= s_last);
   for (int s = s_first + kBlock * VEC; s < s_end; s += kBlock * VEC)
     stencil_chunk<T, N, MODE, VEC, AXIS>(a.g, io, W, s, tol, res, res_d, changed);
-  const double rv = MODE == MODE_RESID ? res_d : static_cast<double>(res);
-  if (a.res_part) block_max_store(rv, a.res_part + blk);
-  else block_max_to_slot(rv, a.res_slot);
+  if constexpr (MODE == MODE_RESID) {
+    if (a.res_part) block_max_store(res_d, a.res_part + blk);
+    else block_max_to_slot(res_d, a.res_slot);
+  } else {
+    if (a.res_part) block_max_store(res, a.res_part + blk);
+    else block_max_to_slot(res, a.res_slot);
+  }
   if (MODE == MODE_GREEDY && a.change_count) block_sum_to_counter(changed, a.change_count);
 }
 
@@ -89,9 +93,13 @@ __global__ __launch_bounds__(kBlock) void stencil_march_kernel(StencilArgs<T> a)
   unsigned changed = 0;
   march_column<T, N, MODE, AXIS>(a.g, io, W, tile * (kBlock * 4) + threadIdx.x * 4, i_begin, i_end,
                                  tol, res, res_d, changed);
-  const double rv = MODE == MODE_RESID ? res_d : static_cast<double>(res);
-  if (a.res_part) block_max_store(rv, a.res_part + lb);
-  else block_max_to_slot(rv, a.res_slot);
+  if constexpr (MODE == MODE_RESID) {
+    if (a.res_part) block_max_store(res_d, a.res_part + lb);
+    else block_max_to_slot(res_d, a.res_slot);
+  } else {
+    if (a.res_part) block_max_store(res, a.res_part + lb);
+    else block_max_to_slot(res, a.res_slot);
+  }
   if (MODE == MODE_GREEDY && a.change_count) block_sum_to_counter(changed, a.change_count);
 }
 
