@@ -71,12 +71,12 @@ int64_t chain_lds_bytes(const ChainGeom& g, size_t b) {
   // pass 2: the tile, plus (FP32 chains on the matrix cores) the row-group
   // factors of one term staged as FP32 or as BF16 hi + lo
   const int64_t rows_len = (g.n1 < g.n) ? g.fac_off[g.n1] : g.term_stride;
-  const int64_t p2 = static_cast<int64_t>(b) * (TE + (TE >> 5) + 2 + rows_len) + 1024 + 256;
+  const int64_t p2 = static_cast<int64_t>(b) * (TE + (TE >> 4) + 2 + rows_len) + 1024 + 256;
   const int64_t cols_len = g.term_stride - ((g.n1 < g.n) ? g.fac_off[g.n1] : g.term_stride);
   const int64_t p1 = (g.n1 == g.n) ? 0
-                     : (g.r1 > 0) ? static_cast<int64_t>(b) * (g.r1 * (g.C + (g.C >> 5) + 1) +
+                     : (g.r1 > 0) ? static_cast<int64_t>(b) * (g.r1 * (g.C + (g.C >> 4) + 1) +
                                                                cols_len) + 512
-                                  : static_cast<int64_t>(b) * (2 * (g.C + (g.C >> 5) + 1) + 2) + 256;
+                                  : static_cast<int64_t>(b) * (2 * (g.C + (g.C >> 4) + 1) + 2) + 256;
   return std::max(p1, p2);
 }
 
@@ -90,7 +90,7 @@ static bool choose_split(const std::vector<int64_t>& sizes, int64_t S, size_t b,
   const int64_t te_max = std::min<int64_t>(b == 8 ? 8192 : 16384,
                                            (kLdsBytes - 4096) / static_cast<int64_t>(b));
   const int64_t c_max =
-      static_cast<int64_t>((kLdsBytes - 4096) / (2.0 * b * (1.0 + 1.0 / 32.0))) - 4;
+      static_cast<int64_t>((kLdsBytes - 4096) / (2.0 * b * (1.0 + 1.0 / 16.0))) - 4;
   int64_t mmax = 0;
   for (auto m : sizes) mmax = std::max(mmax, m);
   if (mmax > 32) return false;
@@ -160,7 +160,7 @@ static bool choose_split(const std::vector<int64_t>& sizes, int64_t S, size_t b,
   if (best_n1 < n && g.C <= 64 * 64) {
     const int64_t cols_len = g.term_stride - g.fac_off[best_n1];
     for (int r1 = 8; r1 >= 2; r1 /= 2) {
-      const int64_t lds = static_cast<int64_t>(b) * (r1 * (g.C + (g.C >> 5) + 1) + cols_len) + 512;
+      const int64_t lds = static_cast<int64_t>(b) * (r1 * (g.C + (g.C >> 4) + 1) + cols_len) + 512;
       if (lds <= kLdsBytes && r1 <= g.Rr) {
         g.r1 = r1;
         break;

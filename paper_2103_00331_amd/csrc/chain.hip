@@ -19,7 +19,7 @@
 //
 // Identity factors are skipped.  An in-place mode product lets each thread
 // hold whole fibers in registers: load fiber, barrier, write the m outputs.
-// LDS indices are padded by one word per 32 to break bank conflicts of
+// LDS indices are padded by one word per 16 to break bank conflicts of
 // strided fibers.
 #include <type_traits>
 
@@ -27,7 +27,10 @@
 
 namespace cpm {
 
-__device__ __forceinline__ int lpad(int i) { return i + (i >> 5); }
+// One pad word per 16: the 16 fibers of a stride-16 block land on distinct
+// banks, and for a base B that is a multiple of 16 the padded index splits,
+// lpad(B + v) = lpad(B) + lpad(v).
+__device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
 
 // Order the LDS accesses of one wave across the lanes (a wave-local mode
 // product reads values that other lanes of the same wave wrote).
@@ -209,6 +212,84 @@ __device__ __forceinline__ void mode_product_mfma(const T* Xs, T* X, int outer, 
   else __syncthreads();
 }
 
+// Matrix-core mode product with m = 16 and an inner stride IN known at
+// compile time (IN in {1, 4, 16, 64, 256, 1024}: the pass-1 and pass-2 modes
+// of 16^n grids).  The 16 fibers of block b start at B + u with B
+// wave-uniform and a multiple of 16, and lpad(B + v) = lpad(B) + lpad(v):
+//   IN = 1        : u = 16 c,            lpad(u + k)    = 17 c + k
+//   IN % 16 == 0  : u = c,               lpad(u + k IN) = c + k lpad(IN)
+//   IN = 4        : u = 64 (c/4) + c%4,  lpad(u + 4 k)  = 68 (c/4) + c%4
+//                                                        + 17 (k/4) + 4 (k%4)
+// Each row k a lane touches is 4x + y with one of x, y its lane group g
+// and the other the register index, so its padded offset is a per-lane part
+// plus a compile-time multiple of the register index: one address add per
+// block for the four reads and one for the four writes (the rest become LDS
+// instruction offsets).
+template <typename T, int MM, bool WAVE, int IN>
+__device__ __forceinline__ void mode_product_mfma16(const T* Xs, T* X, int outer,
+                                                    const T* __restrict__ Tk,
+                                                    const uint16_t* __restrict__ Th,
+                                                    const uint16_t* __restrict__ Tl) {
+  const int lane = threadIdx.x & 63;
+  const int wave = WAVE ? 0 : __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nw = WAVE ? 1 : (blockDim.x >> 6);
+  const int c = lane & 15, g = lane >> 4;
+  const int nblk = (outer * IN) >> 4;
+  T aw[4];
+  s4v ahi, alo;
+  if (MM != MM_BF16) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) aw[q] = Tk[c * 16 + 4 * q + g];
+  } else {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      ahi[r] = static_cast<short>(Th[c * 16 + 4 * g + r]);
+      alo[r] = static_cast<short>(Tl[c * 16 + 4 * g + r]);
+    }
+  }
+  // rd_row(j) = 4j + g (FP32, FP64) | 4g + j (BF16);
+  // wr_row(r) = g + 4r (FP64)        | 4g + r (FP32, BF16)
+  constexpr bool RD_J_HIGH = MM != MM_BF16, WR_R_HIGH = MM == MM_F64;
+  constexpr int KS = IN == 1 ? 1 : IN + IN / 16;   // lpad step per row (IN != 4)
+  // padded offset of row 4x + y: IN = 4: 17 x + 4 y; else (4 x + y) KS
+  constexpr int HI = IN == 4 ? 17 : 4 * KS, LO = IN == 4 ? 4 : KS;
+  constexpr int RD_STEP = RD_J_HIGH ? HI : LO, WR_STEP = WR_R_HIGH ? HI : LO;
+  const int lu = IN == 1 ? 17 * c : (IN == 4 ? 68 * (c >> 2) + (c & 3) : c);
+  const int rd_lane = lu + g * (RD_J_HIGH ? LO : HI);
+  const int wr_lane = lu + g * (WR_R_HIGH ? LO : HI);
+  auto base_of = [](int b) {
+    if (IN == 1) return 256 * b;
+    const int o = (16 * b) / IN;
+    return o * 16 * IN + (16 * b - o * IN);
+  };
+  // two blocks per step so that the LDS reads of both are in flight before
+  // the first matrix product
+  for (int b0 = wave; b0 < nblk; b0 += 2 * nw) {
+    const bool two = b0 + nw < nblk;   // wave-uniform
+    const int lb0 = lpad(base_of(b0)), lb1 = lpad(base_of(two ? b0 + nw : b0));
+    const T* s0 = Xs + lb0 + rd_lane;
+    const T* s1 = Xs + lb1 + rd_lane;
+    T x0[4], x1[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      x0[j] = s0[j * RD_STEP];
+      x1[j] = s1[j * RD_STEP];
+    }
+    const auto d0 = mfma_block<T, MM>(x0, aw, ahi, alo);
+    const auto d1 = mfma_block<T, MM>(x1, aw, ahi, alo);
+    T* t0 = X + lb0 + wr_lane;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) t0[r * WR_STEP] = d0[r];
+    if (two) {
+      T* t1 = X + lb1 + wr_lane;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) t1[r * WR_STEP] = d1[r];
+    }
+  }
+  if (WAVE) wave_lds_fence();
+  else __syncthreads();
+}
+
 // Xs: input (may equal X, the output; both viewed as [outer][m][inner]).
 template <typename T, int MMAX, int MM, bool WAVE = false>
 __device__ __forceinline__ void mode_product(const T* Xs, T* X, int outer, int m, int inner,
@@ -217,6 +298,14 @@ __device__ __forceinline__ void mode_product(const T* Xs, T* X, int outer, int m
   if constexpr (MM == MM_VALU) {
     mode_product_lds<T, MMAX, WAVE>(Xs, X, outer, m, inner, dv, Tk);
   } else {
+    if (m == 16 && ((outer * inner) & 15) == 0) {
+      if (inner == 1) return mode_product_mfma16<T, MM, WAVE, 1>(Xs, X, outer, Tk, Th, Tl);
+      if (inner == 4) return mode_product_mfma16<T, MM, WAVE, 4>(Xs, X, outer, Tk, Th, Tl);
+      if (inner == 16) return mode_product_mfma16<T, MM, WAVE, 16>(Xs, X, outer, Tk, Th, Tl);
+      if (inner == 64) return mode_product_mfma16<T, MM, WAVE, 64>(Xs, X, outer, Tk, Th, Tl);
+      if (inner == 256) return mode_product_mfma16<T, MM, WAVE, 256>(Xs, X, outer, Tk, Th, Tl);
+      if (inner == 1024) return mode_product_mfma16<T, MM, WAVE, 1024>(Xs, X, outer, Tk, Th, Tl);
+    }
     mode_product_mfma<T, MM, WAVE>(Xs, X, outer, m, inner, dv, Tk, Th, Tl);
   }
 }
@@ -651,7 +740,7 @@ static void launch_pass1_m(const ChainArgs<T>& a, hipStream_t st, const LaunchTi
   if (a.g.r1 > 0) {
     const int R1 = a.g.r1;
     const int cols_len = a.g.term_stride - a.g.fac_off[a.g.n1];
-    const size_t sh = sizeof(T) * static_cast<size_t>(R1) * (a.g.C + (a.g.C >> 5) + 1) +
+    const size_t sh = sizeof(T) * static_cast<size_t>(R1) * (a.g.C + (a.g.C >> 4) + 1) +
                       (MM != MM_VALU ? sizeof(T) * static_cast<size_t>(cols_len) : 0);
     const dim3 grid((a.g.Rr + R1 - 1) / R1), block(64 * R1);
     const int pv = (a.g.C + 63) / 64;
@@ -660,7 +749,7 @@ static void launch_pass1_m(const ChainArgs<T>& a, hipStream_t st, const LaunchTi
     else klaunch(chain_pass1_rows<T, MMAX, MM, 64>, grid, block, sh, st, tm, a);
     return;
   }
-  const size_t sh = sizeof(T) * (2 * (static_cast<size_t>(a.g.C) + (a.g.C >> 5) + 1) + 2);
+  const size_t sh = sizeof(T) * (2 * (static_cast<size_t>(a.g.C) + (a.g.C >> 4) + 1) + 2);
   klaunch(chain_pass1<T, MMAX, MM>, dim3(a.g.Rr), dim3(kPass1Block), sh, st, tm, a);
 }
 
@@ -669,7 +758,7 @@ static void launch_pass2_mm(const ChainArgs<T>& a, hipStream_t st, const LaunchT
   const int TE = a.g.Rr * a.g.CT;
   const int ept = (TE + kPass2Block - 1) / kPass2Block;
   const int rows_len = (a.g.n1 < a.g.n) ? a.g.fac_off[a.g.n1] : a.g.term_stride;
-  const size_t sh = sizeof(T) * (static_cast<size_t>(TE) + (TE >> 5) + 2) +
+  const size_t sh = sizeof(T) * (static_cast<size_t>(TE) + (TE >> 4) + 2) +
                     (MM != MM_VALU ? sizeof(T) * static_cast<size_t>(rows_len) : 0);
   const dim3 grid(a.g.ntiles), block(kPass2Block);
   if (ept <= 2) klaunch(chain_pass2<T, MMAX, MODE, 2, MM>, grid, block, sh, st, tm, a);
