@@ -455,13 +455,35 @@ __global__ __launch_bounds__(kPass1RowsBlock) void chain_pass1_rows(ChainArgs<T>
     if (t + 1 < a.nterms) load_fac(t + 1);
     // W_t[tile][r0 .. r0 + R1)[0 .. CT): q runs over whole chunks of R1 * CT
     T* Wt = a.W + static_cast<int64_t>(t) * a.g.w_term_stride;
-    for (int q = threadIdx.x; q < total; q += blockDim.x) {
-      const int tile = q >> chunk_shift;
-      const int rem = q & ((1 << chunk_shift) - 1);
-      const int i = rem >> a.g.ct_shift, clo = rem & (a.g.CT - 1);
-      const int c = tile * a.g.CT + clo;
-      if (r0 + i < Rr && c < C)
-        Wt[(static_cast<int64_t>(tile) * Rr + r0) * a.g.CT + rem] = base[i * slab + lpad(c)];
+    constexpr int VW = 16 / sizeof(T), LOG_VW = sizeof(T) == 4 ? 2 : 1;
+    if (a.g.CT >= VW && C % a.g.CT == 0) {
+      // 16-byte units: VW consecutive columns of one row of one tile, one
+      // vector store (the units never cross a tile, and with one pad word per
+      // 16 never a pad word in LDS)
+      using V = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+      const int vshift = chunk_shift - LOG_VW;
+      for (int qv = threadIdx.x; qv < (total >> LOG_VW); qv += blockDim.x) {
+        const int tile = qv >> vshift;
+        const int rem = (qv & ((1 << vshift) - 1)) << LOG_VW;
+        const int i = rem >> a.g.ct_shift;
+        if (r0 + i < Rr) {
+          const T* src = base + i * slab + lpad(tile * a.g.CT + (rem & (a.g.CT - 1)));
+          V v;
+          T* pv = reinterpret_cast<T*>(&v);
+#pragma unroll
+          for (int e = 0; e < VW; ++e) pv[e] = src[e];
+          *reinterpret_cast<V*>(Wt + (static_cast<int64_t>(tile) * Rr + r0) * a.g.CT + rem) = v;
+        }
+      }
+    } else {
+      for (int q = threadIdx.x; q < total; q += blockDim.x) {
+        const int tile = q >> chunk_shift;
+        const int rem = q & ((1 << chunk_shift) - 1);
+        const int i = rem >> a.g.ct_shift, clo = rem & (a.g.CT - 1);
+        const int c = tile * a.g.CT + clo;
+        if (r0 + i < Rr && c < C)
+          Wt[(static_cast<int64_t>(tile) * Rr + r0) * a.g.CT + rem] = base[i * slab + lpad(c)];
+      }
     }
   }
 }
