@@ -1345,8 +1345,9 @@ int cpmdp_policy_iteration(cpmdp_t* h, double* V, int32_t* pi, double eps, int64
         float* alt = h->d.E1;
         bool done = false;
         double last = 0;
-        // the correction e is small, so FP32 resolves it relative to ||r||
-        const double tol_e = 1e-3 * r[0];
+        // the correction e is small, so FP32 resolves it relative to ||r||;
+        // it need not go further than a quarter of the evaluation target
+        const double tol_e = std::max(1e-3 * r[0], 0.25 * eps_eval);
         rc = run_sweeps<float>(h, false, MODE_EVAL, cur, alt, h->d.r32, pi, tol_e,
                                precision == CPMDP_BF16 ? INFINITY : 0.0, max_iter - 1, &sweeps,
                                &done, &last, precision == CPMDP_BF16);

@@ -571,8 +571,9 @@ int time_config(cpmdp_batch_t* b, int ts, int grid, int k, int reps, double* ms_
 // Policy iteration over the batch (FP32 correction sweeps, FP64 residual,
 // FP64 improvement), per instance the same scheme as the single-instance
 // solver: evaluate pi by r = R + gamma P_pi V - V (FP64), e <- r + gamma
-// P_pi e (FP32 sweeps from e = 0 until ||e' - e|| <= 1e-3 ||r||), V += e,
-// until ||r|| <= eps_eval; then improve greedily keeping the incumbent; stop
+// P_pi e (FP32 sweeps from e = 0 until ||e' - e|| <= max(1e-3 ||r||,
+// eps_eval / 4)), V += e, until ||r|| <= eps_eval; then improve greedily
+// keeping the incumbent; stop
 // when pi is unchanged and the FP64 residual ||B V - V|| <= eps (or after a
 // few certified rounds whose changes are within the evaluation error).
 enum PStage : int { P_RESID = 0, P_CORR = 1, P_IMPROVE = 2, P_DONE = 3 };
@@ -645,7 +646,7 @@ int batch_pi(cpmdp_batch_t* b, double* const* V_devs, int32_t* const* pi_devs, d
         } else {
           st[i] = P_CORR;
           b->hd[i].eparity = 0;
-          b->hd[i].stop = 1e-3 * res[i];
+          b->hd[i].stop = std::max(1e-3 * res[i], 0.25 * eps_eval[i]);
           start[i] = 1;
           any_start = true;
         }
