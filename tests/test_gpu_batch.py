@@ -122,7 +122,10 @@ def march_batch():
     insts = [I.grid_small([8, 20, 24, 36], slip=0.15, gamma=0.9, seed=41),
              I.grid_small([10, 16, 32, 32], slip=0.1, gamma=0.92, seed=42),
              I.grid_small([9, 40, 44], slip=0.2, gamma=0.9, seed=43),
-             I.grid_small([6, 7, 5], slip=0.1, gamma=0.95, seed=44)]
+             I.grid_small([6, 7, 5], slip=0.1, gamma=0.95, seed=44),
+             # last side not a multiple of 4: one state per lane, one-pass tiles
+             I.grid_small([8, 21, 25, 35], slip=0.1, gamma=0.9, seed=45),
+             I.grid_small([9, 130, 131], slip=0.2, gamma=0.9, seed=46)]
     log("[batch] oracle for the marching batch")
     refs = []
     for x in insts:
@@ -134,9 +137,10 @@ def march_batch():
 
 @pytest.mark.parametrize("method", [0, 1])
 def test_batch_marching_tiles_match_oracle(B, march_batch, method):
-    """Instances whose planes of fixed i_0 hold >= 16384 states get marching
-    tiles (the whole dim-0 column of 1024 plane offsets per tile) next to
-    ordinary tiles of small instances: VI and PI against the oracle."""
+    """Instances whose planes of fixed i_0 hold >= 16384 states and whose
+    last side is a multiple of 4 get marching tiles (the whole dim-0 column of
+    1024 plane offsets per tile) next to ordinary tiles of small instances and
+    of large ones with one state per lane: VI and PI against the oracle."""
     insts, refs = march_batch
     log(f"[batch] marching tiles, method {method}")
     eps = 1e-7
