@@ -6,7 +6,7 @@ code with the GPU library: the only common module is the seeded instance
 generator (``paper_2103_00331_amd.instances``), which builds inputs and holds
 none of the solver's arithmetic.
 
-Three representations of the same operator P_a, all in FP64:
+Representations of the operator P_a, all in FP64:
   * ``dense``      (O1) -- P_a expanded to an explicit S x S matrix as the sum
                     of Kronecker products of the factors; value iteration,
                     policy iteration with an exact linear solve, brute-force
@@ -17,6 +17,8 @@ Three representations of the same operator P_a, all in FP64:
                     factors (GridWorld) up to millions of states.
   * ``structured`` (O3) -- mode products of the value tensor with each factor
                     (numpy tensordot), one rank term at a time; any factors.
+  * ``tt``         (O4) -- Tensor-Train and Tucker transition models (Sec. 5)
+                    expanded to dense P_a from their definitions, for O1.
 
 Readings of the paper that the oracle fixes (the paper is silent on them):
   * state order of Def. 2 = row-major, last dimension fastest;
@@ -28,5 +30,5 @@ Readings of the paper that the oracle fixes (the paper is silent on them):
     it by more than tol; policy iteration stops when the policy is unchanged
     (Sec. 2.1).
 """
-from . import common, dense, mlp, sparse, structured  # noqa: F401
+from . import common, dense, mlp, sparse, structured, tt  # noqa: F401
 from .common import greedy, improve, tie_tolerance  # noqa: F401

@@ -495,3 +495,182 @@ def named(name: str) -> Instance:
         "paper2d_1000": lambda: paper_gridworld([1000, 1000], 22, 800, SEED_PAPER2D),
     }
     return table[name]()
+
+
+# ------------------------------- Tensor-Train and Tucker transition models
+
+SEED_TT6 = 20210007          # 16^6 grid with Tensor-Train transitions
+
+
+@dataclass
+class TTInstance:
+    """An MDP whose transition operator of each action is a Tensor-Train
+    (matrix-product) operator over the dimensions:
+        P_a[s, s'] = G_0[:, s_0, s'_0, :] G_1[:, s_1, s'_1, :] ... G_{n-1}[...]
+    a product of b_k x b_{k+1} matrices with b_0 = b_n = 1 (the Tensor-Train
+    form that Sec. 5 names as a future transition model; a CP term is the
+    special case of diagonal bonds).  Flat core layout (the C ABI's):
+    action-major, then k = 0..n-1, one block [b_k][m_k][m_k][b_{k+1}]
+    row-major."""
+
+    sizes: np.ndarray            # int64 [n]
+    bonds: np.ndarray            # int32 [A, n + 1]
+    cores: np.ndarray            # float64 flat
+    rewards: np.ndarray          # float64 [S]
+    gamma: float
+    terminal: np.ndarray         # uint8 [S]
+    name: str = ""
+    meta: Dict[str, float] = field(default_factory=dict)
+    obstacle: Optional[np.ndarray] = None   # always None
+
+    @property
+    def n_dims(self) -> int:
+        return int(self.sizes.shape[0])
+
+    @property
+    def n_states(self) -> int:
+        return int(np.prod(self.sizes))
+
+    @property
+    def n_actions(self) -> int:
+        return int(self.bonds.shape[0])
+
+    def core_offset(self, a: int, k: int) -> int:
+        off = 0
+        for b in range(self.n_actions):
+            for j in range(self.n_dims):
+                if b == a and j == k:
+                    return off
+                m = int(self.sizes[j])
+                off += int(self.bonds[b, j]) * m * m * int(self.bonds[b, j + 1])
+        raise IndexError((a, k))
+
+    def core(self, a: int, k: int) -> np.ndarray:
+        """View of G_k of action a as [b_k, m_k, m_k, b_{k+1}]."""
+        m = int(self.sizes[k])
+        bl, br = int(self.bonds[a, k]), int(self.bonds[a, k + 1])
+        off = self.core_offset(a, k)
+        return self.cores[off:off + bl * m * m * br].reshape(bl, m, m, br)
+
+
+def random_tt(sizes, n_actions: int, bond: int, seed: int, gamma: float = 0.9,
+              alpha: float = 1.0, n_terminal: int = 0, reward_scale: float = 1.0,
+              name: str = "random_tt") -> TTInstance:
+    """Row-stochastic Tensor-Train operators: core k is
+    G[l, i, j, r] = w[l, i, r] * T[l, r, i, j] with w[l, i, :] ~ Dirichlet(1)
+    over the right bond and T[l, r, i, :] ~ Dirichlet(alpha) over the next
+    coordinate.  Then sum_{j, r} G[l, i, j, r] = 1 for every (l, i), so the
+    bond matrices sum_j G[:, i, j, :] are row-stochastic and so is every
+    P_a (a hidden chain over the bond index moving along the dimensions).
+    Internal bonds are all `bond` (clipped to 1 at both ends)."""
+    rng = np.random.default_rng(seed)
+    sizes = [int(m) for m in sizes]
+    n = len(sizes)
+    S = int(np.prod(sizes))
+    bonds = np.full((n_actions, n + 1), int(bond), np.int32)
+    bonds[:, 0] = 1
+    bonds[:, n] = 1
+    blocks = []
+    for a in range(n_actions):
+        for k in range(n):
+            m, bl, br = sizes[k], int(bonds[a, k]), int(bonds[a, k + 1])
+            w = rng.dirichlet(np.ones(br), size=(bl, m))                  # [l, i, r]
+            T = rng.dirichlet(alpha * np.ones(m), size=(bl, br, m))       # [l, r, i, j]
+            T = T / T.sum(axis=-1, keepdims=True)
+            G = w[:, :, None, :] * np.transpose(T, (0, 2, 3, 1))           # [l, i, j, r]
+            blocks.append(np.ascontiguousarray(G).ravel())
+    R = rng.normal(0.0, reward_scale, S)
+    term = np.zeros(S, np.uint8)
+    if n_terminal:
+        term[rng.choice(S, n_terminal, replace=False)] = 1
+    return TTInstance(np.asarray(sizes, np.int64), bonds, np.concatenate(blocks), R,
+                      float(gamma), term, name, {"alpha": alpha, "bond": bond})
+
+
+def tt_grid(m: int = 16, n: int = 6, n_actions: int = 12, bond: int = 4,
+            seed: int = SEED_TT6, gamma: float = 0.95, alpha: float = 0.5) -> TTInstance:
+    """The dense-factor grid's shape (m^n states, 12 actions, Dirichlet(alpha)
+    coordinate rows, rewards N(0, 0.1), no terminals) with Tensor-Train
+    transitions of internal bond `bond`."""
+    return random_tt([m] * n, n_actions, bond, seed, gamma=gamma, alpha=alpha,
+                     reward_scale=0.1, name=f"tt_{m}^{n}_b{bond}")
+
+
+@dataclass
+class TuckerInstance:
+    """An MDP whose transition operator of each action is in Tucker form over
+    the dimensions (Sec. 5 names Tucker as a future transition model):
+        P_a = sum_{r_0..r_{n-1}} C_a[r_0, .., r_{n-1}] kron_k U^{(k)}_{a, r_k}
+    with a core C_a of shape R_{a,0} x .. x R_{a,n-1} and R_{a,k} row-stochastic
+    m_k x m_k factors per dimension.  The CP form is the special case of a
+    diagonal core.  Flat layouts (the C ABI's): cores action-major, each
+    row-major; factors action-major, then k, then r_k, one m_k x m_k
+    row-major block each."""
+
+    sizes: np.ndarray            # int64 [n]
+    core_ranks: np.ndarray       # int32 [A, n]
+    cores: np.ndarray            # float64 flat
+    factors: np.ndarray          # float64 flat
+    rewards: np.ndarray          # float64 [S]
+    gamma: float
+    terminal: np.ndarray         # uint8 [S]
+    name: str = ""
+    meta: Dict[str, float] = field(default_factory=dict)
+    obstacle: Optional[np.ndarray] = None   # always None
+
+    @property
+    def n_dims(self) -> int:
+        return int(self.sizes.shape[0])
+
+    @property
+    def n_states(self) -> int:
+        return int(np.prod(self.sizes))
+
+    @property
+    def n_actions(self) -> int:
+        return int(self.core_ranks.shape[0])
+
+    def core(self, a: int) -> np.ndarray:
+        off = sum(int(np.prod(self.core_ranks[b])) for b in range(a))
+        shape = tuple(int(r) for r in self.core_ranks[a])
+        return self.cores[off:off + int(np.prod(shape))].reshape(shape)
+
+    def factor(self, a: int, k: int, r: int) -> np.ndarray:
+        off = 0
+        for b in range(self.n_actions):
+            for j in range(self.n_dims):
+                m = int(self.sizes[j])
+                for q in range(int(self.core_ranks[b, j])):
+                    if (b, j, q) == (a, k, r):
+                        return self.factors[off:off + m * m].reshape(m, m)
+                    off += m * m
+        raise IndexError((a, k, r))
+
+
+def random_tucker(sizes, n_actions: int, core_ranks, seed: int, gamma: float = 0.9,
+                  alpha: float = 1.0, n_terminal: int = 0,
+                  name: str = "random_tucker") -> TuckerInstance:
+    """Tucker operators with a Dirichlet(1) core over all its entries (a
+    probability mixture) and Dirichlet(alpha) factor rows: every P_a is
+    row-stochastic.  core_ranks: one rank per dimension (all actions) or an
+    [A, n] array."""
+    rng = np.random.default_rng(seed)
+    sizes = [int(m) for m in sizes]
+    n = len(sizes)
+    S = int(np.prod(sizes))
+    cr = np.asarray(core_ranks, np.int32)
+    if cr.ndim == 1:
+        cr = np.tile(cr, (n_actions, 1))
+    cores, facs = [], []
+    for a in range(n_actions):
+        cores.append(rng.dirichlet(np.ones(int(np.prod(cr[a])))))
+        for k in range(n):
+            for _r in range(int(cr[a, k])):
+                U = rng.dirichlet(alpha * np.ones(sizes[k]), size=sizes[k])
+                facs.append((U / U.sum(axis=1, keepdims=True)).ravel())
+    term = np.zeros(S, np.uint8)
+    if n_terminal:
+        term[rng.choice(S, n_terminal, replace=False)] = 1
+    return TuckerInstance(np.asarray(sizes, np.int64), cr, np.concatenate(cores),
+                          np.concatenate(facs), rng.normal(0.0, 1.0, S), float(gamma), term,
+                          name)
