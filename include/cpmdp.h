@@ -80,7 +80,10 @@ typedef enum cpmdp_path {
   CPMDP_PATH_STENCIL = 0, /* every rank term has at most one non-identity
                              factor and it is a clamped +-1 shift           */
   CPMDP_PATH_DENSE = 1,   /* general factors: mode-product chains           */
-  CPMDP_PATH_LISTS = 2    /* successor lists of Def. 3 (cpmdp_create_lists) */
+  CPMDP_PATH_LISTS = 2,   /* successor lists of Def. 3 (cpmdp_create_lists) */
+  CPMDP_PATH_TT = 3       /* Tensor-Train cores (cpmdp_create_tt, and Tucker
+                             models rewritten as Tensor-Trains by
+                             cpmdp_create_tucker)                            */
 } cpmdp_path;
 
 /*
@@ -135,6 +138,64 @@ int cpmdp_create(cpmdp_t** out, int32_t n_dims, const int64_t* sizes,
 int cpmdp_create_lists(cpmdp_t** out, int64_t n_states, int32_t n_actions,
                        const int64_t* row_ptr, const int64_t* succ, const double* prob,
                        const double* rewards, double gamma);
+
+/*
+ * cpmdp_create_tt -- an MDP whose transition operators are Tensor-Trains
+ * (matrix-product operators) over the dimensions, the first of the two
+ * decompositions that Sec. 5 proposes beyond the CP form of Sec. 2.2.
+ * Action a has cores G_k (k = 0..n-1) of shape [b_k][m_k][m_k][b_{k+1}]
+ * with b_0 = b_n = 1, and
+ *     P_a[s, s'] = G_0[:, s_0, s'_0, :] G_1[:, s_1, s'_1, :] ... G_{n-1}[:, s_{n-1}, s'_{n-1}, :]
+ * (a product of b_k x b_{k+1} matrices; states in the order of Def. 2).  A
+ * CP term with rank R is the special case of diagonal cores with bond R.
+ * The backup is Eq. 1 with these operators (terminal masks as for
+ * cpmdp_create).
+ *
+ *   n_dims, sizes, n_actions : as cpmdp_create, and every m_k <= 16
+ *   bonds  : int32 [A][n_dims + 1]; bonds[a][0] = bonds[a][n] = 1, every
+ *            bond in [1, 8]
+ *   cores  : FP64, action-major, then k = 0..n-1, one block
+ *            [b_k][m_k][m_k][b_{k+1}] row-major each (index i = current
+ *            coordinate, j = next coordinate); entries finite and >= 0, and
+ *            every row of every P_a must sum to 1 within 1e-9 (checked from
+ *            the cores at create)
+ *   rewards, gamma : as cpmdp_create
+ * Returns CPMDP_OK and *out, or CPMDP_E_ARG, CPMDP_E_NONFINITE,
+ * CPMDP_E_NOT_STOCHASTIC, or CPMDP_E_UNSUPPORTED (m_k > 16, bond > 8), with
+ * *out = NULL.  Sweeps run in FP64 or FP32 (CPMDP_BF16: CPMDP_E_UNSUPPORTED);
+ * obstacles and batched solves do not take such handles.  The workspace holds
+ * two buffers of max-bond x S and one of A x S FP64 words besides the values.
+ */
+int cpmdp_create_tt(cpmdp_t** out, int32_t n_dims, const int64_t* sizes,
+                    int32_t n_actions, const int32_t* bonds, const double* cores,
+                    const double* rewards, double gamma);
+
+/*
+ * cpmdp_create_tucker -- an MDP whose transition operators are in Tucker
+ * form over the dimensions (the second decomposition Sec. 5 proposes):
+ *     P_a = sum_{r_0..r_{n-1}} C_a[r_0, .., r_{n-1}] kron_k U^{(k)}_{a, r_k}
+ * with a core C_a of shape R_{a,0} x .. x R_{a,n-1} and R_{a,k} row-stochastic
+ * m_k x m_k factors per dimension.  The CP form is the special case of a
+ * diagonal core.  The library rewrites each action exactly as a Tensor-Train
+ * (path CPMDP_PATH_TT): split at the dim mu that minimises the largest bond,
+ * the bonds left of mu carry (r_0..r_{k-1}), those right of it
+ * (r_k..r_{n-1}), and core mu contracts C_a.
+ *
+ *   n_dims, sizes, n_actions : as cpmdp_create_tt (m_k <= 16)
+ *   core_ranks : int32 [A][n_dims], each in [1, 8]; the rewritten bonds must
+ *                stay <= 8 (else CPMDP_E_UNSUPPORTED)
+ *   cores      : FP64, action-major, C_a row-major (prod_k R_{a,k} entries),
+ *                >= 0, summing to 1 per action
+ *   factors    : FP64, action-major, then k, then r < R_{a,k}: one m_k x m_k
+ *                row-major block U^{(k)}_{a,r} each, rows summing to 1
+ *   rewards, gamma : as cpmdp_create
+ * (the sum conditions are checked on the rewritten operator, every row
+ * within 1e-9).  Returns as cpmdp_create_tt.
+ */
+int cpmdp_create_tucker(cpmdp_t** out, int32_t n_dims, const int64_t* sizes,
+                        int32_t n_actions, const int32_t* core_ranks,
+                        const double* cores, const double* factors,
+                        const double* rewards, double gamma);
 
 /* Terminal states (Sec. 3.2): mask [S], nonzero = terminal (V(s) = R(s), no
  * continuation).  Must be called before cpmdp_bind; default: none. */

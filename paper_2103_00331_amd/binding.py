@@ -27,7 +27,7 @@ CPMDP_E_UNSUPPORTED = -6
 CPMDP_E_STATE = -7
 
 CPMDP_FP64, CPMDP_FP32, CPMDP_BF16 = 0, 1, 2
-CPMDP_PATH_STENCIL, CPMDP_PATH_DENSE, CPMDP_PATH_LISTS = 0, 1, 2
+CPMDP_PATH_STENCIL, CPMDP_PATH_DENSE, CPMDP_PATH_LISTS, CPMDP_PATH_TT = 0, 1, 2, 3
 PRECISIONS = {"fp64": CPMDP_FP64, "fp32": CPMDP_FP32, "bf16": CPMDP_BF16}
 
 if not os.path.exists(LIB_PATH):
@@ -53,6 +53,10 @@ _SIGS = {
                                 _dp, C.c_double]),
     "cpmdp_create_lists": (C.c_int, [C.POINTER(_p), C.c_int64, C.c_int32, _i64p, _i64p, _dp,
                                       _dp, C.c_double]),
+    "cpmdp_create_tt": (C.c_int, [C.POINTER(_p), C.c_int32, _i64p, C.c_int32, _i32p, _dp, _dp,
+                                   C.c_double]),
+    "cpmdp_create_tucker": (C.c_int, [C.POINTER(_p), C.c_int32, _i64p, C.c_int32, _i32p, _dp,
+                                       _dp, _dp, C.c_double]),
     "cpmdp_set_terminal": (C.c_int, [_p, _u8p]),
     "cpmdp_set_obstacles": (C.c_int, [_p, _u8p]),
     "cpmdp_get_path": (C.c_int, [_p, _i32p]),
@@ -152,6 +156,34 @@ def cpmdp_create_lists(n_states: int, n_actions: int, row_ptr, succ, prob, rewar
                                   row_ptr.ctypes.data_as(_i64p), succ.ctypes.data_as(_i64p),
                                   prob.ctypes.data_as(_dp), rewards.ctypes.data_as(_dp),
                                   float(gamma)))
+    return h
+
+
+def cpmdp_create_tt(sizes: Sequence[int], bonds, cores, rewards, gamma: float):
+    sizes = np.ascontiguousarray(sizes, np.int64)
+    bonds = np.ascontiguousarray(bonds, np.int32)
+    cores = np.ascontiguousarray(cores, np.float64)
+    rewards = np.ascontiguousarray(rewards, np.float64)
+    h = _p()
+    _check(lib.cpmdp_create_tt(C.byref(h), int(sizes.size), sizes.ctypes.data_as(_i64p),
+                               int(bonds.shape[0]), bonds.ctypes.data_as(_i32p),
+                               cores.ctypes.data_as(_dp), rewards.ctypes.data_as(_dp),
+                               float(gamma)))
+    return h
+
+
+def cpmdp_create_tucker(sizes: Sequence[int], core_ranks, cores, factors, rewards,
+                        gamma: float):
+    sizes = np.ascontiguousarray(sizes, np.int64)
+    core_ranks = np.ascontiguousarray(core_ranks, np.int32)
+    cores = np.ascontiguousarray(cores, np.float64)
+    factors = np.ascontiguousarray(factors, np.float64)
+    rewards = np.ascontiguousarray(rewards, np.float64)
+    h = _p()
+    _check(lib.cpmdp_create_tucker(C.byref(h), int(sizes.size), sizes.ctypes.data_as(_i64p),
+                                   int(core_ranks.shape[0]), core_ranks.ctypes.data_as(_i32p),
+                                   cores.ctypes.data_as(_dp), factors.ctypes.data_as(_dp),
+                                   rewards.ctypes.data_as(_dp), float(gamma)))
     return h
 
 
@@ -317,6 +349,12 @@ class Model:
         if hasattr(inst, "row_ptr"):          # an MDP given as Def. 3 lists
             self.h = cpmdp_create_lists(inst.n_states, inst.n_actions, inst.row_ptr,
                                         inst.succ, inst.prob, inst.rewards, inst.gamma)
+        elif hasattr(inst, "bonds"):          # Tensor-Train cores
+            self.h = cpmdp_create_tt(inst.sizes, inst.bonds, inst.cores, inst.rewards,
+                                     inst.gamma)
+        elif hasattr(inst, "core_ranks"):     # Tucker core and factors
+            self.h = cpmdp_create_tucker(inst.sizes, inst.core_ranks, inst.cores,
+                                         inst.factors, inst.rewards, inst.gamma)
         else:
             self.h = cpmdp_create(inst.sizes, inst.ranks, inst.factors, inst.lambdas,
                                   inst.rewards, inst.gamma)

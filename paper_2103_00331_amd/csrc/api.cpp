@@ -212,6 +212,13 @@ void layout(const cpmdp_t* h, DevPtrs* dp, char* base, size_t* total) {
     d.l_p32 = cv.take<float>(ent);
     d.parts = cv.take<double>(static_cast<size_t>(kSlots) * h->l_blocks);
     d.W = nullptr;
+  } else if (h->path == CPMDP_PATH_TT) {
+    d.t_core64 = cv.take<double>(h->t_core.size());
+    d.t_core32 = cv.take<float>(h->t_core.size());
+    d.t_X0 = cv.take<char>(static_cast<size_t>(h->t_maxb) * S * sizeof(double));
+    d.t_X1 = cv.take<char>(static_cast<size_t>(h->t_maxb) * S * sizeof(double));
+    d.t_Y = cv.take<char>(A * S * sizeof(double));
+    d.W = nullptr;
   } else if (h->path == CPMDP_PATH_STENCIL) {
     const size_t P = 2 * static_cast<size_t>(h->n) + 1;
     d.w64 = cv.take<double>(3 * A * P);   // w, wdiff [A][P], then wbase [P]
@@ -304,6 +311,65 @@ static StencilArgs<T> stencil_args(cpmdp_t* h, const void* V, void* Vout, const 
   return a;
 }
 
+// One Tensor-Train sweep: per action the chain of bonded mode products
+// (last dim first, the bond channels ping-ponging between X0 and X1, the
+// last step writing Y[a] = P_a V), then the Eq. 1 epilogue over all Y[a].
+// Timing events, when given, span the first step to the epilogue.
+template <typename T>
+static void tt_sweep(cpmdp_t* h, int mode, const void* V, void* Vout, const void* R,
+                     const int32_t* pi_in, int32_t* pi_out, float* r_out,
+                     unsigned long long* slot, unsigned int* ctr, const LaunchTiming* tm) {
+  constexpr bool f64 = std::is_same<T, double>::value;
+  const T* cores = f64 ? reinterpret_cast<const T*>(h->d.t_core64)
+                       : reinterpret_cast<const T*>(h->d.t_core32);
+  T* X[2] = {reinterpret_cast<T*>(h->d.t_X0), reinterpret_cast<T*>(h->d.t_X1)};
+  T* Y = reinterpret_cast<T*>(h->d.t_Y);
+  const int n = h->n;
+  const int32_t S = static_cast<int32_t>(h->S);
+  const LaunchTiming t_first{tm ? tm->start : nullptr, nullptr};
+  const LaunchTiming t_last{nullptr, tm ? tm->stop : nullptr};
+  bool first = true;
+  for (int a = 0; a < h->A; ++a) {
+    const T* cur = static_cast<const T*>(V);
+    int which = 0;
+    for (int k = n - 1; k >= 0; --k) {
+      TTStepArgs<T> s{};
+      s.in = cur;
+      s.out = k == 0 ? Y + static_cast<size_t>(a) * S : X[which];
+      s.core = cores + h->t_off[static_cast<size_t>(a) * n + k];
+      s.S = S;
+      s.m = static_cast<int32_t>(h->sizes[k]);
+      s.mm = h->t_mm[k];
+      s.post = h->geom.stride[k];
+      s.post_div = make_fastdiv(static_cast<uint32_t>(s.post));
+      s.positions = S / s.m;
+      s.b_in = h->t_bonds[static_cast<size_t>(a) * (n + 1) + k + 1];
+      s.b_out = h->t_bonds[static_cast<size_t>(a) * (n + 1) + k];
+      s.lpad = (s.b_out + 3) & ~3;
+      launch_tt_step<T>(s, h->stream, (tm && first) ? &t_first : nullptr);
+      first = false;
+      cur = s.out;
+      which ^= 1;
+    }
+  }
+  TTEpiArgs<T> e{};
+  e.S = S;
+  e.A = h->A;
+  e.Y = Y;
+  e.V = static_cast<const T*>(V);
+  e.Vout = static_cast<T*>(Vout);
+  e.R = static_cast<const T*>(R);
+  e.term_bits = h->d.tbits;
+  e.gamma = static_cast<T>(h->gamma);
+  e.pi_in = pi_in;
+  e.pi_out = pi_out;
+  e.r_out = r_out;
+  e.vmax_bits = h->d.vmax;
+  e.res_slot = slot;
+  e.change_count = ctr;
+  launch_tt_epilogue<T>(e, mode, h->stream, tm ? &t_last : nullptr);
+}
+
 int stencil_grid(const cpmdp_t* h) {
   if (h->path == CPMDP_PATH_LISTS) return h->l_blocks;
   return (h->st_march && h->opt_march) ? h->st_march_blocks : h->st_blocks;
@@ -316,6 +382,11 @@ void sweep(cpmdp_t* h, bool prec64, int mode, const void* V, void* Vout, const v
            unsigned long long* slot, unsigned int* ctr, bool bf16, const LaunchTiming* tm,
            double* part) {
   const hipStream_t st = h->stream;
+  if (h->path == CPMDP_PATH_TT) {
+    if (prec64) tt_sweep<double>(h, mode, V, Vout, R, pi_in, pi_out, r_out, slot, ctr, tm);
+    else tt_sweep<float>(h, mode, V, Vout, R, pi_in, pi_out, r_out, slot, ctr, tm);
+    return;
+  }
   if (h->path == CPMDP_PATH_LISTS) {
     auto fill = [&](auto& a, auto* prob) {
       using T = std::remove_pointer_t<decltype(prob)>;
@@ -506,7 +577,7 @@ static int run_sweeps(cpmdp_t* h, bool prec64, int mode, P*& cur, P*& alt, const
   *done = false;
   // stencil and list sweeps leave one residual word per block, reduced per
   // chunk
-  const bool parts = h->path != CPMDP_PATH_DENSE;
+  const bool parts = h->path == CPMDP_PATH_STENCIL || h->path == CPMDP_PATH_LISTS;
   const int nb = parts ? stencil_grid(h) : 0;
   struct Chunk {
     int half, k;
@@ -675,6 +746,144 @@ void split_axis_weights(cpmdp_t* h) {
     }
   }
   h->kw32.assign(h->kw64.begin(), h->kw64.end());
+}
+
+// ------------------------------------------------- Tensor-Train / Tucker
+
+constexpr int kTTMaxBond = 8;
+constexpr int kTTMaxMode = 16;
+
+// Checks shared by the Tensor-Train and Tucker create calls.
+static int check_grid_args(int32_t n_dims, const int64_t* sizes, int32_t n_actions,
+                           const double* rewards, double gamma, int64_t* S_out) {
+  if (!sizes || !rewards) return fail(nullptr, CPMDP_E_ARG, "NULL input array");
+  if (n_dims < 1 || n_dims > kMaxDims) return fail(nullptr, CPMDP_E_ARG, "n_dims must be in [1, 8]");
+  if (n_actions < 1 || n_actions > kMaxActions)
+    return fail(nullptr, CPMDP_E_ARG, "n_actions must be in [1, 255]");
+  int64_t S = 1;
+  for (int k = 0; k < n_dims; ++k) {
+    if (sizes[k] < 1) return fail(nullptr, CPMDP_E_ARG, "sizes must be >= 1");
+    if (sizes[k] > kTTMaxMode)
+      return fail(nullptr, CPMDP_E_UNSUPPORTED, "Tensor-Train / Tucker models need every m_k <= 16");
+    S *= sizes[k];
+    if (S >= (int64_t(1) << 31)) return fail(nullptr, CPMDP_E_ARG, "state count must be < 2^31");
+  }
+  if (!std::isfinite(gamma)) return fail(nullptr, CPMDP_E_NONFINITE, "gamma is not finite");
+  if (gamma < 0.0 || gamma >= 1.0) return fail(nullptr, CPMDP_E_ARG, "gamma must be in [0, 1)");
+  for (int64_t s = 0; s < S; ++s)
+    if (!std::isfinite(rewards[s])) return fail(nullptr, CPMDP_E_NONFINITE, "non-finite reward");
+  *S_out = S;
+  return CPMDP_OK;
+}
+
+// Validates Tensor-Train bonds [A][n+1] and cores (C ABI layout) and
+// builds the handle: row sums of every P_a from the cores (the bond
+// matrices M_k(i) = sum_j G_k[:, i, j, :] multiplied from the last dim, one
+// vector per state), then the padded device layout of tt.hip.
+static int create_tt_impl(cpmdp_t** out, int32_t n, const int64_t* sizes, int32_t A,
+                          const int32_t* bonds, const double* cores, const double* rewards,
+                          double gamma, int64_t S) {
+  for (int a = 0; a < A; ++a) {
+    const int32_t* b = bonds + static_cast<size_t>(a) * (n + 1);
+    if (b[0] != 1 || b[n] != 1) return fail(nullptr, CPMDP_E_ARG, "bonds[a][0] and bonds[a][n] must be 1");
+    for (int k = 0; k <= n; ++k) {
+      if (b[k] < 1) return fail(nullptr, CPMDP_E_ARG, "bonds must be >= 1");
+      if (b[k] > kTTMaxBond) {
+        char buf[128];
+        std::snprintf(buf, sizeof buf, "bond %d of action %d is %d; at most %d is supported", k, a,
+                      b[k], kTTMaxBond);
+        return fail(nullptr, CPMDP_E_UNSUPPORTED, buf);
+      }
+    }
+  }
+  std::vector<int64_t> off(static_cast<size_t>(A) * n);
+  int64_t count = 0;
+  for (int a = 0; a < A; ++a)
+    for (int k = 0; k < n; ++k) {
+      off[static_cast<size_t>(a) * n + k] = count;
+      count += static_cast<int64_t>(bonds[a * (n + 1) + k]) * sizes[k] * sizes[k] *
+               bonds[a * (n + 1) + k + 1];
+    }
+  for (int64_t i = 0; i < count; ++i) {
+    if (!std::isfinite(cores[i])) return fail(nullptr, CPMDP_E_NONFINITE, "non-finite core entry");
+    if (cores[i] < 0.0) return fail(nullptr, CPMDP_E_NOT_STOCHASTIC, "negative core entry");
+  }
+  for (int a = 0; a < A; ++a) {
+    // w[(rest) * br + r]: row sums of the trailing dims' operator with open bond r
+    std::vector<double> w(1, 1.0), nw;
+    int64_t rest = 1;
+    for (int k = n - 1; k >= 0; --k) {
+      const int64_t m = sizes[k];
+      const int bl = bonds[a * (n + 1) + k], br = bonds[a * (n + 1) + k + 1];
+      const double* G = cores + off[static_cast<size_t>(a) * n + k];
+      std::vector<double> M(static_cast<size_t>(bl) * m * br, 0.0);   // [l][i][r]
+      for (int l = 0; l < bl; ++l)
+        for (int64_t i = 0; i < m; ++i)
+          for (int64_t j = 0; j < m; ++j)
+            for (int r = 0; r < br; ++r)
+              M[(l * m + i) * br + r] += G[((l * m + i) * m + j) * br + r];
+      nw.assign(static_cast<size_t>(m * rest * bl), 0.0);
+      for (int64_t i = 0; i < m; ++i)
+        for (int64_t q = 0; q < rest; ++q)
+          for (int l = 0; l < bl; ++l) {
+            double acc = 0.0;
+            for (int r = 0; r < br; ++r) acc += M[(l * m + i) * br + r] * w[q * br + r];
+            nw[(i * rest + q) * bl + l] = acc;
+          }
+      w.swap(nw);
+      rest *= m;
+    }
+    for (int64_t s = 0; s < S; ++s)
+      if (std::fabs(w[s] - 1.0) > 1e-9) {
+        char buf[160];
+        std::snprintf(buf, sizeof buf, "row %lld of the operator of action %d sums to %.17g",
+                      (long long)s, a, w[s]);
+        return fail(nullptr, CPMDP_E_NOT_STOCHASTIC, buf);
+      }
+  }
+  cpmdp_t* h = new (std::nothrow) cpmdp_t();
+  if (!h) return fail(nullptr, CPMDP_E_ARG, "out of host memory");
+  h->n = n;
+  h->S = S;
+  h->A = A;
+  h->gamma = gamma;
+  h->sizes.assign(sizes, sizes + n);
+  h->rewards.assign(rewards, rewards + S);
+  for (int64_t s = 0; s < S; ++s) h->rmax = std::max(h->rmax, std::fabs(rewards[s]));
+  h->terminal.assign(static_cast<size_t>(S), 0);
+  h->path = CPMDP_PATH_TT;
+  h->geom = make_geom(h);
+  h->t_bonds.assign(bonds, bonds + static_cast<size_t>(A) * (n + 1));
+  h->t_mm.resize(n);
+  for (int k = 0; k < n; ++k) h->t_mm[k] = sizes[k] <= 4 ? 4 : (sizes[k] <= 8 ? 8 : 16);
+  h->t_maxb = 1;
+  for (int32_t b : h->t_bonds) h->t_maxb = std::max(h->t_maxb, b);
+  // padded device layout Gd[r][j][l][i] per (action, dim)
+  h->t_off.resize(static_cast<size_t>(A) * n);
+  int64_t dcount = 0;
+  for (int a = 0; a < A; ++a)
+    for (int k = 0; k < n; ++k) {
+      const int64_t mm = h->t_mm[k];
+      const int64_t lp = (bonds[a * (n + 1) + k] + 3) & ~3;
+      h->t_off[static_cast<size_t>(a) * n + k] = dcount;
+      dcount += bonds[a * (n + 1) + k + 1] * mm * lp * mm;
+    }
+  h->t_core.assign(static_cast<size_t>(dcount), 0.0);
+  for (int a = 0; a < A; ++a)
+    for (int k = 0; k < n; ++k) {
+      const int64_t m = sizes[k], mm = h->t_mm[k];
+      const int bl = bonds[a * (n + 1) + k], br = bonds[a * (n + 1) + k + 1];
+      const int64_t lp = (bl + 3) & ~3;
+      const double* G = cores + off[static_cast<size_t>(a) * n + k];
+      double* D = h->t_core.data() + h->t_off[static_cast<size_t>(a) * n + k];
+      for (int l = 0; l < bl; ++l)
+        for (int64_t i = 0; i < m; ++i)
+          for (int64_t j = 0; j < m; ++j)
+            for (int r = 0; r < br; ++r)
+              D[((r * mm + j) * lp + l) * mm + i] = G[((l * m + i) * m + j) * br + r];
+    }
+  *out = h;
+  return CPMDP_OK;
 }
 
 }  // namespace cpm
@@ -937,6 +1146,138 @@ int cpmdp_create_lists(cpmdp_t** out, int64_t n_states, int32_t n_actions,
   return CPMDP_OK;
 }
 
+int cpmdp_create_tt(cpmdp_t** out, int32_t n_dims, const int64_t* sizes, int32_t n_actions,
+                    const int32_t* bonds, const double* cores, const double* rewards,
+                    double gamma) {
+  if (!out) return fail(nullptr, CPMDP_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (!bonds || !cores) return fail(nullptr, CPMDP_E_ARG, "NULL input array");
+  int64_t S = 0;
+  const int rc = check_grid_args(n_dims, sizes, n_actions, rewards, gamma, &S);
+  if (rc) return rc;
+  return create_tt_impl(out, n_dims, sizes, n_actions, bonds, cores, rewards, gamma, S);
+}
+
+int cpmdp_create_tucker(cpmdp_t** out, int32_t n_dims, const int64_t* sizes, int32_t n_actions,
+                        const int32_t* core_ranks, const double* cores, const double* factors,
+                        const double* rewards, double gamma) {
+  if (!out) return fail(nullptr, CPMDP_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (!core_ranks || !cores || !factors) return fail(nullptr, CPMDP_E_ARG, "NULL input array");
+  int64_t S = 0;
+  int rc = check_grid_args(n_dims, sizes, n_actions, rewards, gamma, &S);
+  if (rc) return rc;
+  const int n = n_dims, A = n_actions;
+  int64_t ccount = 0, fcount = 0;
+  for (int a = 0; a < A; ++a) {
+    int64_t c = 1;
+    for (int k = 0; k < n; ++k) {
+      const int32_t R = core_ranks[a * n + k];
+      if (R < 1) return fail(nullptr, CPMDP_E_ARG, "core ranks must be >= 1");
+      if (R > kTTMaxBond) return fail(nullptr, CPMDP_E_UNSUPPORTED, "core ranks must be <= 8");
+      c *= R;
+      fcount += R * sizes[k] * sizes[k];
+    }
+    ccount += c;
+  }
+  for (int64_t i = 0; i < ccount; ++i) {
+    if (!std::isfinite(cores[i])) return fail(nullptr, CPMDP_E_NONFINITE, "non-finite core entry");
+    if (cores[i] < 0.0) return fail(nullptr, CPMDP_E_NOT_STOCHASTIC, "negative core entry");
+  }
+  for (int64_t i = 0; i < fcount; ++i) {
+    if (!std::isfinite(factors[i])) return fail(nullptr, CPMDP_E_NONFINITE, "non-finite factor entry");
+    if (factors[i] < 0.0) return fail(nullptr, CPMDP_E_NOT_STOCHASTIC, "negative probability");
+  }
+  // Rewrite each action as a Tensor-Train, splitting at dim mu: the bond
+  // left of dim k <= mu carries (r_0..r_{k-1}), the bond left of dim k > mu
+  // carries (r_k..r_{n-1}); core mu contracts the Tucker core:
+  //   k < mu : G_k[(r_<k), i, j, (r_<k, r_k)]   = U^(k)_{r_k}[i, j]
+  //   k = mu : G_mu[(r_<mu), i, j, (r_>mu)]     = sum_{r_mu} C[r] U^(mu)_{r_mu}[i, j]
+  //   k > mu : G_k[(r_k, r_>k), i, j, (r_>k)]   = U^(k)_{r_k}[i, j]
+  // so the bond products enforce equal indices and sum C[r] kron_k U.  mu
+  // minimises the largest bond (then the flop count of a sweep).
+  std::vector<int32_t> bonds(static_cast<size_t>(A) * (n + 1));
+  std::vector<double> tt;
+  const double* C = cores;
+  const double* U = factors;
+  for (int a = 0; a < A; ++a) {
+    const int32_t* R = core_ranks + static_cast<size_t>(a) * n;
+    int best_mu = 0;
+    int64_t best_max = INT64_MAX, best_cost = INT64_MAX;
+    std::vector<int64_t> bb(n + 1);
+    for (int mu = 0; mu < n; ++mu) {
+      bb[0] = bb[n] = 1;
+      for (int k = 1; k < n; ++k) {
+        int64_t p = 1;
+        if (k <= mu) for (int l = 0; l < k; ++l) p *= R[l];
+        else for (int l = k; l < n; ++l) p *= R[l];
+        bb[k] = p;
+      }
+      int64_t mx = 0, cost = 0;
+      for (int k = 0; k <= n; ++k) mx = std::max(mx, bb[k]);
+      for (int k = 0; k < n; ++k) cost += bb[k] * bb[k + 1] * sizes[k];
+      if (mx < best_max || (mx == best_max && cost < best_cost)) {
+        best_mu = mu;
+        best_max = mx;
+        best_cost = cost;
+      }
+    }
+    const int mu = best_mu;
+    if (best_max > kTTMaxBond) {
+      char buf[160];
+      std::snprintf(buf, sizeof buf, "the core of action %d needs a Tensor-Train bond of %lld; "
+                    "at most %d is supported", a, (long long)best_max, kTTMaxBond);
+      return fail(nullptr, CPMDP_E_UNSUPPORTED, buf);
+    }
+    std::vector<int64_t> pre(n + 1, 1), suf(n + 1, 1);   // prod R[0..k), prod R[k..n)
+    for (int k = 0; k < n; ++k) pre[k + 1] = pre[k] * R[k];
+    for (int k = n - 1; k >= 0; --k) suf[k] = suf[k + 1] * R[k];
+    int32_t* b = bonds.data() + static_cast<size_t>(a) * (n + 1);
+    for (int k = 0; k <= n; ++k)
+      b[k] = static_cast<int32_t>(k == 0 || k == n ? 1 : (k <= mu ? pre[k] : suf[k]));
+    std::vector<const double*> Uk(n);   // factor blocks of action a, dim k
+    {
+      const double* u = U;
+      for (int k = 0; k < n; ++k) {
+        Uk[k] = u;
+        u += R[k] * sizes[k] * sizes[k];
+      }
+      U = u;
+    }
+    for (int k = 0; k < n; ++k) {
+      const int64_t m = sizes[k];
+      const int64_t bl = b[k], br = b[k + 1];
+      const size_t base = tt.size();
+      tt.resize(base + static_cast<size_t>(bl * m * m * br), 0.0);
+      double* G = tt.data() + base;
+      auto at = [&](int64_t l, int64_t i, int64_t j, int64_t r) -> double& {
+        return G[((l * m + i) * m + j) * br + r];
+      };
+      if (k < mu) {
+        for (int64_t l = 0; l < bl; ++l)
+          for (int64_t rk = 0; rk < R[k]; ++rk)
+            for (int64_t i = 0; i < m; ++i)
+              for (int64_t j = 0; j < m; ++j) at(l, i, j, l * R[k] + rk) = Uk[k][(rk * m + i) * m + j];
+      } else if (k > mu) {
+        for (int64_t rk = 0; rk < R[k]; ++rk)
+          for (int64_t r = 0; r < br; ++r)
+            for (int64_t i = 0; i < m; ++i)
+              for (int64_t j = 0; j < m; ++j) at(rk * br + r, i, j, r) = Uk[k][(rk * m + i) * m + j];
+      } else {
+        for (int64_t l = 0; l < bl; ++l)
+          for (int64_t rk = 0; rk < R[k]; ++rk)
+            for (int64_t r = 0; r < br; ++r) {
+              const double cw = C[(l * R[k] + rk) * br + r];
+              for (int64_t i = 0; i < m; ++i)
+                for (int64_t j = 0; j < m; ++j) at(l, i, j, r) += cw * Uk[k][(rk * m + i) * m + j];
+            }
+      }
+    }
+    C += pre[n];
+  }
+  return create_tt_impl(out, n, sizes, A, bonds.data(), tt.data(), rewards, gamma, S);
+}
+
 int cpmdp_set_terminal(cpmdp_t* h, const uint8_t* mask) {
   if (!h) return fail(nullptr, CPMDP_E_ARG, "handle is NULL");
   if (!mask) return fail(h, CPMDP_E_ARG, "mask is NULL");
@@ -957,9 +1298,9 @@ int cpmdp_set_obstacles(cpmdp_t* h, const uint8_t* mask) {
   }
   if (h->path != CPMDP_PATH_STENCIL)
     return fail(h, CPMDP_E_UNSUPPORTED,
-                "obstacles need shift/identity factors: with dense factors the blocked "
-                "moves are not a sparse correction of the Kronecker form, and successor "
-                "lists encode blocked moves themselves");
+                "obstacles need shift/identity factors: with dense factors or Tensor-Train / "
+                "Tucker cores the blocked moves are not a sparse correction of the operator, "
+                "and successor lists encode blocked moves themselves");
   h->obstacle.assign(static_cast<size_t>(h->S), 0);
   for (int64_t s = 0; s < h->S; ++s) h->obstacle[s] = mask[s] ? 1 : 0;
   return CPMDP_OK;
@@ -1069,7 +1410,14 @@ int cpmdp_bind(cpmdp_t* h, void* ws, size_t bytes, void* stream) {
   std::vector<uint16_t> facbf;
   std::vector<int32_t> ts;
   std::vector<float> lp32;
-  if (h->path == CPMDP_PATH_LISTS) {
+  std::vector<float> tc32;
+  if (h->path == CPMDP_PATH_TT) {
+    const size_t nc = h->t_core.size();
+    tc32.resize(nc);
+    for (size_t i = 0; i < nc; ++i) tc32[i] = static_cast<float>(h->t_core[i]);
+    HIP_TRY(h, hipMemcpyAsync(h->d.t_core64, h->t_core.data(), nc * 8, hipMemcpyHostToDevice, st));
+    HIP_TRY(h, hipMemcpyAsync(h->d.t_core32, tc32.data(), nc * 4, hipMemcpyHostToDevice, st));
+  } else if (h->path == CPMDP_PATH_LISTS) {
     const size_t ent = h->l_succ.size();
     lp32.resize(ent);
     for (size_t i = 0; i < ent; ++i) lp32[i] = static_cast<float>(h->l_prob[i]);
@@ -1137,6 +1485,8 @@ static int check_common(cpmdp_t* h, int precision) {
     return fail(h, CPMDP_E_ARG, "unknown precision");
   if (precision == CPMDP_BF16 && h->path == CPMDP_PATH_LISTS)
     return fail(h, CPMDP_E_UNSUPPORTED, "successor lists run in FP64 or FP32 (no matrix product)");
+  if (precision == CPMDP_BF16 && h->path == CPMDP_PATH_TT)
+    return fail(h, CPMDP_E_UNSUPPORTED, "Tensor-Train / Tucker models run in FP64 or FP32");
   return CPMDP_OK;
 }
 
@@ -1444,7 +1794,8 @@ int cpmdp_time_sweeps(cpmdp_t* h, void* V_a, void* V_b, int32_t n, int precision
     sweep(h, p64, mode == 0 ? MODE_MAX : MODE_EVAL, cur, alt,
           p64 ? static_cast<const void*>(h->d.R64) : h->d.R32, pi, nullptr, nullptr, h->d.slots,
           nullptr, precision == CPMDP_BF16, &tm,
-          h->path != CPMDP_PATH_DENSE ? h->d.parts : nullptr);
+          (h->path == CPMDP_PATH_STENCIL || h->path == CPMDP_PATH_LISTS) ? h->d.parts
+                                                                          : nullptr);
     std::swap(cur, alt);
   }
   rc = check_device(h);

@@ -102,6 +102,48 @@ template <typename T>
 void launch_stencil(const StencilArgs<T>& a, int mode, hipStream_t st,
                     const LaunchTiming* tm = nullptr);
 
+// ------------------------------------------- Tensor-Train transition models
+// One bonded mode product X^{(k+1)} (b_in channels of S) -> X^{(k)} (b_out
+// channels) along dim k; core in the padded device layout Gd[r][j][l][i]
+// (i, j padded to mm, l to lpad, zeros in the padding).
+template <typename T>
+struct TTStepArgs {
+  const T* in;
+  T* out;
+  const T* core;
+  int32_t S;
+  int32_t m, mm;                // m_k and its padded size (4, 8 or 16)
+  int32_t post;                 // prod_{j>k} m_j (stride of dim k)
+  FastDiv post_div;
+  int32_t positions;            // S / m_k fiber positions
+  int32_t b_in, b_out, lpad;    // bonds b_{k+1}, b_k; b_k padded to a multiple of 4
+};
+
+// Eq. 1 over Y[a] = P_a V, fused with the max / argmax, policy value or
+// policy residual (modes as for the other sweeps).
+template <typename T>
+struct TTEpiArgs {
+  int32_t S, A;
+  const T* Y;                   // [A][S]
+  const T* V;
+  T* Vout;
+  const T* R;
+  const uint32_t* term_bits;
+  T gamma;
+  const int32_t* pi_in;
+  int32_t* pi_out;
+  float* r_out;
+  const unsigned long long* vmax_bits;
+  unsigned long long* res_slot;
+  unsigned int* change_count;
+};
+
+template <typename T>
+void launch_tt_step(const TTStepArgs<T>& a, hipStream_t st, const LaunchTiming* tm = nullptr);
+template <typename T>
+void launch_tt_epilogue(const TTEpiArgs<T>& a, int mode, hipStream_t st,
+                        const LaunchTiming* tm = nullptr);
+
 // ---------------------------------------------------- Def. 3 successor lists
 // Sliced layout with 64-state slices (one slice per wave): for slice q and
 // action a the columns col_ptr[q*A + a] .. col_ptr[q*A + a + 1] hold the

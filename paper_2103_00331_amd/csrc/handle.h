@@ -39,6 +39,11 @@ struct DevPtrs {
   int32_t* l_succ = nullptr;             // lists: successors [columns * 64]
   double* l_p64 = nullptr;               // lists: probabilities [columns * 64]
   float* l_p32 = nullptr;
+  double* t_core64 = nullptr;            // TT: padded cores of every (action, dim)
+  float* t_core32 = nullptr;
+  char* t_X0 = nullptr;                  // TT: bond channels [maxb][S], ping-pong
+  char* t_X1 = nullptr;
+  char* t_Y = nullptr;                   // TT: P_a V per action [A][S]
 };
 
 }  // namespace cpm
@@ -70,6 +75,13 @@ struct cpmdp {
   int32_t l_nslices = 0, l_blocks = 0, l_slices_per_block = 0;
   std::vector<int32_t> l_cols, l_succ;
   std::vector<double> l_prob;
+  // Tensor-Train path: bonds [A][n+1]; padded cores (see tt.hip) and the
+  // offset of each (action, dim) block in them; padded mode sizes per dim
+  std::vector<int32_t> t_bonds;
+  std::vector<double> t_core;
+  std::vector<int64_t> t_off;
+  std::vector<int32_t> t_mm;
+  int32_t t_maxb = 1;
   bool opt_march = true;                 // CPMDP_OPT_MARCH
   cpm::GridGeom geom{};
   cpm::ChainGeom cg64{}, cg32{};

@@ -189,3 +189,78 @@ def test_create_lists_valid_and_rejects_invalid():
     rw = m.rewards.copy()
     rw[1] = np.inf
     expect(B.CPMDP_E_NONFINITE, rewards=rw)
+
+
+def test_create_tt_valid_and_rejects_invalid():
+    t = I.random_tt([3, 4, 2], 2, 3, seed=3)
+    h = B.cpmdp_create_tt(t.sizes, t.bonds, t.cores, t.rewards, t.gamma)
+    assert B.cpmdp_get_path(h) == B.CPMDP_PATH_TT
+    assert B.cpmdp_workspace_bytes(h) > 0
+    mask = np.zeros(t.n_states, np.uint8)
+    mask[2] = 1
+    B.cpmdp_set_terminal(h, mask)
+    with pytest.raises(B.CpmdpError) as e:
+        B.cpmdp_set_obstacles(h, mask)
+    assert e.value.code == B.CPMDP_E_UNSUPPORTED
+    with pytest.raises(B.CpmdpError) as e:
+        B.cpmdp_batch_create([h])
+    assert e.value.code == B.CPMDP_E_UNSUPPORTED
+    B.cpmdp_destroy(h)
+
+    def expect(code, sizes=t.sizes, bonds=t.bonds, cores=t.cores, rewards=t.rewards,
+               gamma=t.gamma):
+        with pytest.raises(B.CpmdpError) as e:
+            B.cpmdp_create_tt(sizes, bonds, cores, rewards, gamma)
+        assert e.value.code == code, str(e.value)
+
+    c = t.cores.copy()
+    c[5] *= 1.001
+    expect(B.CPMDP_E_NOT_STOCHASTIC, cores=c)                  # a row of P off by ~1e-4
+    c = t.cores.copy()
+    c[0] = -c[0]
+    expect(B.CPMDP_E_NOT_STOCHASTIC, cores=c)                  # negative entry
+    c = t.cores.copy()
+    c[7] = np.nan
+    expect(B.CPMDP_E_NONFINITE, cores=c)
+    b = t.bonds.copy()
+    b[0, 0] = 2
+    expect(B.CPMDP_E_ARG, bonds=b)                             # end bonds must be 1
+    big = I.random_tt([2, 2], 1, 9, seed=4)
+    expect(B.CPMDP_E_UNSUPPORTED, sizes=big.sizes, bonds=big.bonds, cores=big.cores,
+           rewards=big.rewards)                                # bond 9 > 8
+    wide = I.random_tt([17, 2], 1, 2, seed=5)
+    expect(B.CPMDP_E_UNSUPPORTED, sizes=wide.sizes, bonds=wide.bonds, cores=wide.cores,
+           rewards=wide.rewards)                               # m_k = 17 > 16
+    expect(B.CPMDP_E_ARG, gamma=1.0)
+
+
+def test_create_tucker_valid_and_rejects_invalid():
+    u = I.random_tucker([3, 2, 4], 2, [2, 3, 2], seed=6)
+    args = dict(sizes=u.sizes, core_ranks=u.core_ranks, cores=u.cores, factors=u.factors,
+                rewards=u.rewards, gamma=u.gamma)
+    h = B.cpmdp_create_tucker(**args)
+    assert B.cpmdp_get_path(h) == B.CPMDP_PATH_TT
+    B.cpmdp_destroy(h)
+
+    def expect(code, **kw):
+        a = dict(args)
+        a.update(kw)
+        with pytest.raises(B.CpmdpError) as e:
+            B.cpmdp_create_tucker(**a)
+        assert e.value.code == code, str(e.value)
+
+    c = u.cores.copy()
+    c[0] += 1e-6
+    expect(B.CPMDP_E_NOT_STOCHASTIC, cores=c)                  # core sum off
+    f = u.factors.copy()
+    f[3] = -0.1
+    expect(B.CPMDP_E_NOT_STOCHASTIC, factors=f)
+    f = u.factors.copy()
+    f[0] += 1e-3
+    expect(B.CPMDP_E_NOT_STOCHASTIC, factors=f)                # factor row sum off
+    r = u.core_ranks.copy()
+    r[0, 0] = 0
+    expect(B.CPMDP_E_ARG, core_ranks=r)
+    wide = I.random_tucker([2, 2, 2, 2], 1, [3, 3, 3, 3], seed=7)
+    expect(B.CPMDP_E_UNSUPPORTED, sizes=wide.sizes, core_ranks=wide.core_ranks,
+           cores=wide.cores, factors=wide.factors, rewards=wide.rewards)   # bond 9 > 8
