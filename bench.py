@@ -17,7 +17,8 @@ Other workloads (--workload): grid4d_96 (96^4, HBM-resident), dense6_16
 (16^6, dense 16x16 factors, 12 actions of rank 8), batch512 (512 mixed
 GridWorlds), warm64 (learned warm start on 64^3) and paper2d_1000 (the
 1000 x 1000 GridWorld of Table 1 with 22 terminals and 800 obstacles) and
-paper2d_lists (the same problem given as Def. 3 successor lists).
+paper2d_lists (the same problem given as Def. 3 successor lists) and tt6_16
+(16^6, 12 actions with Tensor-Train transitions of bond 4).
 """
 import argparse
 import hashlib
@@ -55,6 +56,7 @@ CHAIN_SRC = ["paper_2103_00331_amd/csrc/chain.hip", "paper_2103_00331_amd/csrc/c
 BATCH_SRC = ["paper_2103_00331_amd/csrc/batch.hip", "paper_2103_00331_amd/csrc/stencil_core.cuh",
              "paper_2103_00331_amd/csrc/common.cuh"]
 LISTS_SRC = ["paper_2103_00331_amd/csrc/lists.hip", "paper_2103_00331_amd/csrc/common.cuh"]
+TT_SRC = ["paper_2103_00331_amd/csrc/tt.hip", "paper_2103_00331_amd/csrc/common.cuh"]
 PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp64": 78.6}
 
 
@@ -399,6 +401,109 @@ def bench_dense(args):
     return out
 
 
+def tt_sweep_cost(inst, word):
+    """Algorithmic flops and HBM bytes of one Tensor-Train sweep: per action
+    and dim k a bonded mode product (2 S m_k b_k b_{k+1} flops; reads
+    b_{k+1} S words, writes b_k S words), then the epilogue (reads A S words
+    of P_a V plus V and R, writes V'; one terminal bit per state)."""
+    S, A, n = inst.n_states, inst.n_actions, inst.n_dims
+    flops = 0.0
+    words = 0.0
+    for a in range(A):
+        for k in range(n):
+            bl, br = int(inst.bonds[a, k]), int(inst.bonds[a, k + 1])
+            flops += 2.0 * S * int(inst.sizes[k]) * bl * br
+            words += (bl + br) * S
+    words += (A + 3) * S
+    return flops, words * word + S / 8.0
+
+
+def _cpu_baseline_tt(inst, budget_s=12.0):
+    """FP64 Q-values of the Tensor-Train oracle (O4), one state at a time
+    (each row of every P_a rebuilt from the cores), over seeded states."""
+    import numpy as np
+
+    from oracle import tt as O4
+    rng = np.random.default_rng(12)
+    V = rng.normal(0.0, 1.0, inst.n_states)
+    done, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        O4.tt_q_at_states(inst, V, [int(rng.integers(inst.n_states))])
+        done += 1
+    secs = time.perf_counter() - t0
+    return {"value": done * inst.n_actions / secs, "unit": "state-action backups/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{done} seeded states x {inst.n_actions} actions of the same {inst.name} "
+                      f"instance: each P_a row rebuilt from the cores and dotted with V, "
+                      f"{secs:.1f} s, numpy, one thread"}
+
+
+def bench_tt(args):
+    import torch
+
+    from paper_2103_00331_amd import binding as B
+    from paper_2103_00331_amd import instances as I
+
+    _log("building the 16^6 Tensor-Train instance")
+    inst = I.tt_grid()
+    S, A = inst.n_states, inst.n_actions
+    model = B.Model(inst)
+    prec = {"fp32": B.CPMDP_FP32, "fp64": B.CPMDP_FP64}[args.precision]
+    word = 8 if prec == B.CPMDP_FP64 else 4
+    Va = torch.zeros(S, dtype=torch.float32 if prec else torch.float64, device="cuda")
+    Vb = torch.zeros_like(Va)
+    B.cpmdp_time_sweeps(model.h, Va, Vb, 2, prec, 0)
+    ms = B.cpmdp_time_sweeps(model.h, Va, Vb, 10, prec, 0)
+    del Va, Vb
+    flops, nbytes = tt_sweep_cost(inst, word)
+    eps = 1e-6
+    V = torch.zeros(S, dtype=torch.float64, device="cuda")
+    pi = torch.zeros(S, dtype=torch.int32, device="cuda")
+    for _ in range(args.warmup):
+        V.zero_()
+        B.cpmdp_value_iteration(model.h, V, pi, eps, 100000, prec)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tot = 0
+    for _ in range(args.steps):
+        V.zero_()
+        code, sweeps, res = B.cpmdp_value_iteration(model.h, V, pi, eps, 100000, prec)
+        tot += sweeps
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    V.zero_()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    pcode, plain_sweeps, pres = B.cpmdp_value_iteration(model.h, V, pi, eps, 100000, B.CPMDP_FP64)
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t1
+    _log(f"chosen {args.precision}: {1e3 * el / args.steps:.1f} ms; plain FP64 VI {1e3 * plain_s:.1f} ms; "
+         f"sweep {ms:.3f} ms")
+    out = {"metric": METRIC, "value": tot * S * A / el, "unit": "state-action backups/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": 1e3 * el / args.steps, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": args.precision, "data": "synthetic",
+           "config": {"workload": f"tt_16^6: {S} states, {A} actions, Tensor-Train transitions "
+                                  "of bond 4, Dirichlet(0.5) coordinate rows, gamma 0.95",
+                      "method": f"vi {args.precision} sweeps, FP64 tail sweeps and certificate",
+                      "eps": eps, "sweeps_per_solve": tot / args.steps},
+           "time_to_eps_s": el / args.steps, "plain_vi_time_to_eps_s": plain_s,
+           "plain_vi_sweeps": plain_sweeps, "speedup_vs_plain_vi": plain_s / (el / args.steps),
+           "roofline": {"bound": "hbm", "achieved": nbytes / (ms * 1e-3) / 1e9,
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                        "traffic": _traffic(f"tt_{args.precision}_tt6_16.md", TT_SRC),
+                        "kernel": "tt_step_vec + tt_step_mfma + tt_epilogue (one sweep)",
+                        "kernel_ms": ms, "algorithmic_bytes_per_launch": nbytes,
+                        "algorithmic_flops_per_launch": flops,
+                        "flop_rate_tflops": flops / (ms * 1e-3) / 1e12,
+                        "flop_frac": flops / (ms * 1e-3) / 1e12 / PEAK_TFLOPS[args.precision]}}
+    model.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = _cpu_baseline_tt(inst)
+    return out
+
+
 def bench_batch(args):
     """512 mixed GridWorlds solved together (FP32 sweeps, FP64 tail and
     certificate per instance, autotuned tiles / sweeps per graph) vs plain
@@ -596,6 +701,8 @@ def kernel_only(args):
         return
     if args.workload == "dense6_16":
         inst = I.dense_grid(16, seed=I.SEED_DENSE6)
+    elif args.workload == "tt6_16":
+        inst = I.tt_grid()
     elif args.workload == "paper2d_1000":
         inst = I.named("paper2d_1000")
     elif args.workload == "paper2d_lists":
@@ -627,7 +734,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="grid4d_32",
                     choices=["grid4d_32", "grid4d_96", "dense6_16", "batch512", "warm64",
-                             "paper2d_1000", "paper2d_lists"])
+                             "paper2d_1000", "paper2d_lists", "tt6_16"])
     ap.add_argument("--method", default="vi", choices=["vi", "pi"])
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -659,6 +766,8 @@ def main():
         out = bench_warm(args)
     elif args.workload == "paper2d_lists":
         out = bench_lists(args)
+    elif args.workload == "tt6_16":
+        out = bench_tt(args)
     else:
         out, inst = bench_grid(args, 32 if args.workload == "grid4d_32" else 96)
         if args.workload in ("grid4d_32", "paper2d_1000") and not args.no_cpu_baseline:

@@ -11,10 +11,10 @@
 // One launch per (action, dimension) streams X^{(k+1)} (b_{k+1} channels)
 // to X^{(k)} (b_k channels): for each fiber position (all coordinates but
 // i_k) it is a small matrix product (b_k m_k) x (b_{k+1} m_k), i.e. a GEMM
-// over the S / m_k fiber positions.  With m_k = 16 and a fiber stride that
-// is a multiple of 16 it runs on the matrix cores (16 positions per matrix
-// tile, the cores held in registers for the whole launch); otherwise on the
-// vector ALUs with the cores read as wave-uniform scalars.  The last launch
+// over the S / m_k fiber positions.  With m_k = 16 it runs on the matrix
+// cores (16 positions per matrix tile, the cores held in registers for the
+// whole launch, 16-byte loads and stores where the layout allows); otherwise
+// on the vector ALUs with the cores read as wave-uniform scalars.  The last launch
 // of each action writes Y[a] = P_a V; one epilogue kernel then fuses Eq. 1:
 // the max / argmax over actions, the fixed-policy value or the FP64 policy
 // residual, and the sup-norm residual.
@@ -86,103 +86,258 @@ __global__ __launch_bounds__(kBlock) void tt_step_vec(TTStepArgs<T> a) {
   }
 }
 
-// Matrix-core bonded mode product for m_k = 16 and a fiber stride (post)
-// that is a multiple of 16: a tile of 16 consecutive fiber positions shares
-// its leading coordinates, so lane (g, c) reads X[r][base_c + (4q + g) post]
-// for k-block (r, q) -- 16 consecutive words per lane group -- and writes
-// its result rows the same way.  The A operands (the cores of BO output
-// channels, BI >= b_in input channels) stay in registers; each wave walks
-// tiles with a grid stride.
-template <typename T, int BO, int BI>
+// Matrix-core bonded mode products for m_k = 16.  The A operands (the cores
+// of BO output channels and BI >= b_in input channels) stay in registers for
+// the whole launch; each wave walks tiles of 16 fiber positions (the matrix
+// columns n) with a grid stride (two waves per SIMD overlap one's loads with
+// the other's matrix products).  Three layouts of a tile in memory:
+//   TT_ROWS  (fiber stride post % 16 == 0): the 16 positions of a tile are
+//            consecutive words of each of the 16 rows j; lane (g, c) reads
+//            row j = 4q + g of position c (4-byte accesses).
+//   TT_WIDE  (FP32, post % U == 0, U = 16 bytes / word): a wave step takes U
+//            interleaved tiles, lane c holding U consecutive positions of
+//            every row in one 16-byte load, and writes its U results of each
+//            output row with one 16-byte store.
+//   TT_INNER (post == 1, the last dimension): the 16 values of a fiber are
+//            consecutive; lane (g, c) loads j = 4g .. 4g + 3 of fiber c in one
+//            16-byte access (k-block q then holds j = 4g + q) and stores its
+//            4 output rows i = 4g .. 4g + 3 the same way (FP64 results come out
+//            as rows g + 4r, so the A rows are permuted to make them 4g + r).
+enum { TT_ROWS = 0, TT_WIDE = 1, TT_INNER = 2 };
+
+template <typename T>
+struct TTVec;
+template <>
+struct TTVec<float> {
+  typedef float type __attribute__((ext_vector_type(4)));
+};
+template <>
+struct TTVec<double> {
+  typedef double type __attribute__((ext_vector_type(2)));
+};
+
+template <typename T, int BO, int BI, int LAYOUT>
 __global__ __launch_bounds__(kBlock) void tt_step_mfma(TTStepArgs<T> a) {
   using Acc = typename TTAcc<T>::type;
+  using V16 = typename TTVec<T>::type;
   constexpr bool f64 = sizeof(T) == 8;
+  constexpr int W = 16 / sizeof(T);                   // words per 16-byte access
+  constexpr int U = LAYOUT == TT_WIDE ? W : 1;        // tiles per wave step
   const int lane = threadIdx.x & 63;
   const int c = lane & 15, g = lane >> 4;
   const int l0 = blockIdx.y * BO;
+  // A row held by lane c (TT_INNER, FP64: row permutation, see above)
+  const int arow = (LAYOUT == TT_INNER && f64) ? 4 * (c & 3) + (c >> 2) : c;
   T aw[BO][BI][4];
 #pragma unroll
   for (int b = 0; b < BO; ++b)
 #pragma unroll
     for (int r = 0; r < BI; ++r)
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        aw[b][r][q] = r < a.b_in ? a.core[((r * 16 + 4 * q + g) * a.lpad + l0 + b) * 16 + c]
-                                 : T(0);
-  const int ntiles = a.positions >> 4;
+      for (int q = 0; q < 4; ++q) {
+        const int j = LAYOUT == TT_INNER ? 4 * g + q : 4 * q + g;
+        aw[b][r][q] = r < a.b_in ? a.core[((r * 16 + j) * a.lpad + l0 + b) * 16 + arow] : T(0);
+      }
+  const int nsteps = a.positions / (16 * U);
   const int wave = __builtin_amdgcn_readfirstlane(
       xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + (threadIdx.x >> 6));
   const int nwaves = gridDim.x * (kBlock / 64);
-  for (int t = wave; t < ntiles; t += nwaves) {
-    const int pos = t * 16 + c;
+  // TT_ROWS / TT_WIDE: offset of this lane's first position of step t, and
+  // the load of a step's operands (rows j = 4q + g of every input channel)
+  auto base_of = [&](int t) {
+    const int pos = (t * 16 + c) * U;
     const int p = static_cast<int>(fdiv(static_cast<uint32_t>(pos), a.post_div));
-    const int base = p * 16 * a.post + (pos - p * a.post);
-    T x[BI][4];
+    return p * 16 * a.post + (pos - p * a.post);
+  };
+  auto load_step = [&](int base, T (&x)[BI][4][U]) {
 #pragma unroll
     for (int r = 0; r < BI; ++r)
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        x[r][q] = r < a.b_in ? a.in[static_cast<size_t>(r) * a.S + base + (4 * q + g) * a.post]
-                             : T(0);
+      for (int q = 0; q < 4; ++q) {
+        const T* src = a.in + static_cast<size_t>(r) * a.S + base + (4 * q + g) * a.post;
+        if (r >= a.b_in) {
 #pragma unroll
-    for (int b = 0; b < BO; ++b) {
-      if (l0 + b >= a.b_out) break;
-      Acc acc = {T(0), T(0), T(0), T(0)};
+          for (int u = 0; u < U; ++u) x[r][q][u] = T(0);
+        } else if constexpr (U == 1) {
+          x[r][q][0] = *src;
+        } else {
+          const V16 v = *reinterpret_cast<const V16*>(src);
 #pragma unroll
-      for (int r = 0; r < BI; ++r)
+          for (int u = 0; u < U; ++u) x[r][q][u] = v[u];
+        }
+      }
+  };
+  for (int t = wave; t < nsteps; t += nwaves) {
+    if constexpr (LAYOUT == TT_INNER) {
+      const size_t base = static_cast<size_t>(t * 16 + c) * 16 + 4 * g;
+      T x[BI][4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc = tt_mfma(aw[b][r][q], x[r][q], acc);
-      T* __restrict__ dst = a.out + static_cast<size_t>(l0 + b) * a.S + base;
+      for (int r = 0; r < BI; ++r) {
+        if (r < a.b_in) {
+          const T* src = a.in + static_cast<size_t>(r) * a.S + base;
 #pragma unroll
-      for (int rr = 0; rr < 4; ++rr) dst[(f64 ? g + 4 * rr : 4 * g + rr) * a.post] = acc[rr];
+          for (int h = 0; h < 4; h += W) {
+            const V16 v = *reinterpret_cast<const V16*>(src + h);
+#pragma unroll
+            for (int e = 0; e < W; ++e) x[r][h + e] = v[e];
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) x[r][q] = T(0);
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < BO; ++b) {
+        if (l0 + b >= a.b_out) break;
+        Acc acc = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+        for (int r = 0; r < BI; ++r)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc = tt_mfma(aw[b][r][q], x[r][q], acc);
+        T* dst = a.out + static_cast<size_t>(l0 + b) * a.S + base;
+#pragma unroll
+        for (int h = 0; h < 4; h += W) {
+          V16 v;
+#pragma unroll
+          for (int e = 0; e < W; ++e) v[e] = acc[h + e];
+          *reinterpret_cast<V16*>(dst + h) = v;
+        }
+      }
+    } else {
+      const int base = base_of(t);
+      T x[BI][4][U];
+      load_step(base, x);
+#pragma unroll
+      for (int b = 0; b < BO; ++b) {
+        if (l0 + b >= a.b_out) break;
+        Acc acc[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          acc[u] = Acc{T(0), T(0), T(0), T(0)};
+#pragma unroll
+          for (int r = 0; r < BI; ++r)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[u] = tt_mfma(aw[b][r][q], x[r][q][u], acc[u]);
+        }
+        T* dst = a.out + static_cast<size_t>(l0 + b) * a.S + base;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          T* d = dst + (f64 ? g + 4 * rr : 4 * g + rr) * a.post;
+          if constexpr (U == 1) {
+            *d = acc[0][rr];
+          } else {
+            V16 v;
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] = acc[u][rr];
+            *reinterpret_cast<V16*>(d) = v;
+          }
+        }
+      }
     }
   }
 }
 
 // Eq. 1 over Y[a] = P_a V (a < A): Q_a(s) = R(s) + gamma (1 - tau(s)) Y[a](s).
-template <typename T, int MODE>
+// E consecutive states per thread (E = 16 bytes / word when S allows: every
+// stream is then read with 16-byte loads).
+template <typename T, int MODE, int E>
 __global__ __launch_bounds__(kBlock) void tt_epilogue(TTEpiArgs<T> a) {
+  using V16 = typename TTVec<T>::type;
+  auto load = [&](const T* p, T (&v)[E]) {
+    if constexpr (E == 1) {
+      v[0] = *p;
+    } else {
+      const V16 w = *reinterpret_cast<const V16*>(p);
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[e] = w[e];
+    }
+  };
   T tol = T(0);
   if (MODE == MODE_GREEDY) tol = static_cast<T>(tie_tol(a.vmax_bits));
   T res = T(0);
   double res_d = 0.0;
   unsigned changed = 0;
+  const int64_t nv = a.S / E;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
-  for (int64_t s = blockIdx.x * kBlock + threadIdx.x; s < a.S; s += stride) {
-    const T c = a.V[s];
-    const T rs = a.R[s];
-    const T gm = is_terminal(a.term_bits, static_cast<int>(s)) ? T(0) : a.gamma;
-    T out;
-    int pnew = 0;
+  for (int64_t v = blockIdx.x * kBlock + threadIdx.x; v < nv; v += stride) {
+    const int64_t s0 = v * E;
+    T c[E], rs[E], gm[E], out[E];
+    int pnew[E];
+    load(a.V + s0, c);
+    load(a.R + s0, rs);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      gm[e] = is_terminal(a.term_bits, static_cast<int>(s0 + e)) ? T(0) : a.gamma;
+      pnew[e] = 0;
+    }
     if (MODE == MODE_MAX) {
-      T best = -INFINITY;
-      for (int act = 0; act < a.A; ++act)
-        best = fmax(best, a.Y[static_cast<size_t>(act) * a.S + s]);   // a NaN in V shows via c
-      out = fma(gm, best, rs);
-    } else if (MODE == MODE_GREEDY) {
-      const int pold = a.pi_in ? a.pi_in[s] : -1;
-      T best = -INFINITY, qold = -INFINITY;
-      int bi = 0;
+      T best[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) best[e] = -INFINITY;
       for (int act = 0; act < a.A; ++act) {
-        const T qv = fma(gm, a.Y[static_cast<size_t>(act) * a.S + s], rs);
-        tie_update(qv, act, tol, best, bi);
-        if (act == pold) qold = qv;
+        T y[E];
+        load(a.Y + static_cast<size_t>(act) * a.S + s0, y);
+#pragma unroll
+        for (int e = 0; e < E; ++e) best[e] = fmax(best[e], y[e]);   // a NaN in V shows via c
       }
-      pnew = bi;
-      if (pold >= 0 && qold >= best - tol) pnew = pold;
-      changed += (pold >= 0 && pnew != pold) ? 1u : 0u;
-      out = best;
+#pragma unroll
+      for (int e = 0; e < E; ++e) out[e] = fma(gm[e], best[e], rs[e]);
+    } else if (MODE == MODE_GREEDY) {
+      int pold[E], bi[E];
+      T best[E], qold[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        pold[e] = a.pi_in ? a.pi_in[s0 + e] : -1;
+        best[e] = -INFINITY;
+        qold[e] = -INFINITY;
+        bi[e] = 0;
+      }
+      for (int act = 0; act < a.A; ++act) {
+        T y[E];
+        load(a.Y + static_cast<size_t>(act) * a.S + s0, y);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const T qv = fma(gm[e], y[e], rs[e]);
+          tie_update(qv, act, tol, best[e], bi[e]);
+          if (act == pold[e]) qold[e] = qv;
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        pnew[e] = bi[e];
+        if (pold[e] >= 0 && qold[e] >= best[e] - tol) pnew[e] = pold[e];
+        changed += (pold[e] >= 0 && pnew[e] != pold[e]) ? 1u : 0u;
+        out[e] = best[e];
+      }
     } else {
-      out = fma(gm, a.Y[static_cast<size_t>(a.pi_in[s]) * a.S + s], rs);
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+        out[e] = fma(gm[e], a.Y[static_cast<size_t>(a.pi_in[s0 + e]) * a.S + s0 + e], rs[e]);
     }
     if (MODE == MODE_RESID) {
-      const double d = static_cast<double>(out) - static_cast<double>(c);
-      a.r_out[s] = static_cast<float>(d);
-      res_d = nanmax(res_d, fabs(d));
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const double d = static_cast<double>(out[e]) - static_cast<double>(c[e]);
+        a.r_out[s0 + e] = static_cast<float>(d);
+        res_d = nanmax(res_d, fabs(d));
+      }
     } else {
-      res = nanmax_t(res, static_cast<T>(fabs(out - c)));
-      if (a.Vout) a.Vout[s] = out;
-      if (MODE == MODE_GREEDY && a.pi_out) a.pi_out[s] = pnew;
+#pragma unroll
+      for (int e = 0; e < E; ++e) res = nanmax_t(res, static_cast<T>(fabs(out[e] - c[e])));
+      if (a.Vout) {
+        if constexpr (E == 1) {
+          a.Vout[s0] = out[0];
+        } else {
+          V16 w;
+#pragma unroll
+          for (int e = 0; e < E; ++e) w[e] = out[e];
+          *reinterpret_cast<V16*>(a.Vout + s0) = w;
+        }
+      }
+      if (MODE == MODE_GREEDY && a.pi_out) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) a.pi_out[s0 + e] = pnew[e];
+      }
     }
   }
   if constexpr (MODE == MODE_RESID) block_max_to_slot(res_d, a.res_slot);
@@ -190,19 +345,53 @@ __global__ __launch_bounds__(kBlock) void tt_epilogue(TTEpiArgs<T> a) {
   if (MODE == MODE_GREEDY && a.change_count) block_sum_to_counter(changed, a.change_count);
 }
 
-// Which kernel runs a step.
+// Which kernel runs a step: the matrix cores when m_k = 16 and the tiles of
+// one of the three layouts cover the fiber positions exactly, else the
+// vector kernel.
 template <typename T>
-static bool step_on_mfma(const TTStepArgs<T>& a) {
-  return a.mm == 16 && a.m == 16 && a.post % 16 == 0 && a.b_in >= 2 && a.b_in <= 8;
+static int mfma_layout(const TTStepArgs<T>& a) {
+  constexpr int W = 16 / static_cast<int>(sizeof(T));
+  if (a.m != 16 || a.mm != 16 || a.b_in > 8) return -1;
+  // 16-byte accesses need 16-byte aligned channels (the caller's V may not be)
+  const bool al = ((reinterpret_cast<uintptr_t>(a.in) | reinterpret_cast<uintptr_t>(a.out)) & 15) == 0;
+  if (a.post == 1) return (al && a.positions % 16 == 0) ? TT_INNER : -1;
+  // FP64 keeps the row layout: the wide one holds half the output channels
+  // per block there (registers), which reads every input twice
+  if (sizeof(T) == 4 && al && a.post % W == 0 && a.positions % (16 * W) == 0) return TT_WIDE;
+  if (a.post % 16 == 0) return TT_ROWS;
+  return -1;
 }
 
-template <typename T, int BO>
-static void launch_mfma_bi(const TTStepArgs<T>& a, dim3 grid, hipStream_t st,
-                           const LaunchTiming* tm) {
-  if (a.b_in <= 2) klaunch(tt_step_mfma<T, BO, 2>, grid, dim3(kBlock), 0, st, tm, a);
-  else if (a.b_in <= 4) klaunch(tt_step_mfma<T, BO, 4>, grid, dim3(kBlock), 0, st, tm, a);
-  else klaunch(tt_step_mfma<T, (sizeof(T) == 8 && BO > 2 ? 2 : BO), 8>, grid, dim3(kBlock), 0, st,
-               tm, a);
+// Output channels per block: as many as the registers hold beside the
+// operands (more input channels or wider tiles leave room for fewer).
+template <typename T>
+static int mfma_bo_cap(int bi, int layout) {
+  if (layout == TT_WIDE) return bi == 8 ? 1 : 4;
+  return bi == 8 ? 2 : 4;
+}
+
+template <typename T, int LAYOUT, int BI>
+static void launch_mfma_bo(const TTStepArgs<T>& a, int bo, hipStream_t st, const LaunchTiming* tm) {
+  constexpr int U = LAYOUT == TT_WIDE ? 16 / static_cast<int>(sizeof(T)) : 1;
+  const int steps = a.positions / (16 * U);
+  const int blocks = (steps + 3) / 4 < kMaxBlocks ? (steps + 3) / 4 : kMaxBlocks;
+  const dim3 grid(blocks, (a.b_out + bo - 1) / bo), block(kBlock);
+  if (bo >= 4) klaunch(tt_step_mfma<T, 4, BI, LAYOUT>, grid, block, 0, st, tm, a);
+  else if (bo == 2) klaunch(tt_step_mfma<T, 2, BI, LAYOUT>, grid, block, 0, st, tm, a);
+  else klaunch(tt_step_mfma<T, 1, BI, LAYOUT>, grid, block, 0, st, tm, a);
+}
+
+template <typename T, int LAYOUT>
+static void launch_mfma(const TTStepArgs<T>& a, hipStream_t st, const LaunchTiming* tm) {
+  const int bi = a.b_in <= 1 ? 1 : a.b_in <= 2 ? 2 : a.b_in <= 4 ? 4 : 8;
+  const int cap = mfma_bo_cap<T>(bi, LAYOUT);
+  const int bo = a.b_out >= cap ? cap : (a.b_out >= 2 ? 2 : 1);
+  switch (bi) {
+    case 1: launch_mfma_bo<T, LAYOUT, 1>(a, bo, st, tm); break;
+    case 2: launch_mfma_bo<T, LAYOUT, 2>(a, bo, st, tm); break;
+    case 4: launch_mfma_bo<T, LAYOUT, 4>(a, bo, st, tm); break;
+    default: launch_mfma_bo<T, LAYOUT, 8>(a, bo, st, tm); break;
+  }
 }
 
 template <typename T, int MM>
@@ -216,16 +405,13 @@ static void launch_vec_mm(const TTStepArgs<T>& a, hipStream_t st, const LaunchTi
 
 template <typename T>
 void launch_tt_step(const TTStepArgs<T>& a, hipStream_t st, const LaunchTiming* tm) {
-  if (step_on_mfma(a)) {
-    const int bo = (sizeof(T) == 8 && a.b_in > 4) ? 2 : 4;
-    const int bo_used = a.b_out >= bo ? bo : (a.b_out >= 2 ? 2 : 1);
-    const int tiles = a.positions / 16;
-    const int blocks = (tiles + 3) / 4 < kMaxBlocks ? (tiles + 3) / 4 : kMaxBlocks;
-    const dim3 grid(blocks, (a.b_out + bo_used - 1) / bo_used);
-    if (bo_used == 4) launch_mfma_bi<T, 4>(a, grid, st, tm);
-    else if (bo_used == 2) launch_mfma_bi<T, 2>(a, grid, st, tm);
-    else launch_mfma_bi<T, 1>(a, grid, st, tm);
-    return;
+  switch (mfma_layout(a)) {
+    case TT_ROWS: return launch_mfma<T, TT_ROWS>(a, st, tm);
+    case TT_WIDE:
+      if constexpr (sizeof(T) == 4) return launch_mfma<T, TT_WIDE>(a, st, tm);
+      break;
+    case TT_INNER: return launch_mfma<T, TT_INNER>(a, st, tm);
+    default: break;
   }
   switch (a.mm) {
     case 4: launch_vec_mm<T, 4>(a, st, tm); break;
@@ -234,16 +420,27 @@ void launch_tt_step(const TTStepArgs<T>& a, hipStream_t st, const LaunchTiming* 
   }
 }
 
-template <typename T>
-void launch_tt_epilogue(const TTEpiArgs<T>& a, int mode, hipStream_t st, const LaunchTiming* tm) {
-  const int blocks = (a.S + kBlock - 1) / kBlock < kMaxBlocks ? (a.S + kBlock - 1) / kBlock : kMaxBlocks;
+template <typename T, int E>
+static void launch_epi_e(const TTEpiArgs<T>& a, int mode, hipStream_t st, const LaunchTiming* tm) {
+  const int64_t nv = a.S / E;
+  const int blocks = (nv + kBlock - 1) / kBlock < kMaxBlocks ? static_cast<int>((nv + kBlock - 1) / kBlock)
+                                                             : kMaxBlocks;
   const dim3 grid(blocks), block(kBlock);
   switch (mode) {
-    case MODE_MAX: klaunch(tt_epilogue<T, MODE_MAX>, grid, block, 0, st, tm, a); break;
-    case MODE_GREEDY: klaunch(tt_epilogue<T, MODE_GREEDY>, grid, block, 0, st, tm, a); break;
-    case MODE_EVAL: klaunch(tt_epilogue<T, MODE_EVAL>, grid, block, 0, st, tm, a); break;
-    default: klaunch(tt_epilogue<T, MODE_RESID>, grid, block, 0, st, tm, a); break;
+    case MODE_MAX: klaunch(tt_epilogue<T, MODE_MAX, E>, grid, block, 0, st, tm, a); break;
+    case MODE_GREEDY: klaunch(tt_epilogue<T, MODE_GREEDY, E>, grid, block, 0, st, tm, a); break;
+    case MODE_EVAL: klaunch(tt_epilogue<T, MODE_EVAL, E>, grid, block, 0, st, tm, a); break;
+    default: klaunch(tt_epilogue<T, MODE_RESID, E>, grid, block, 0, st, tm, a); break;
   }
+}
+
+template <typename T>
+void launch_tt_epilogue(const TTEpiArgs<T>& a, int mode, hipStream_t st, const LaunchTiming* tm) {
+  constexpr int W = 16 / static_cast<int>(sizeof(T));
+  const uintptr_t ptrs = reinterpret_cast<uintptr_t>(a.V) | reinterpret_cast<uintptr_t>(a.R) |
+                         reinterpret_cast<uintptr_t>(a.Vout);
+  if (a.S % W == 0 && (ptrs & 15) == 0) launch_epi_e<T, W>(a, mode, st, tm);
+  else launch_epi_e<T, 1>(a, mode, st, tm);
 }
 
 template void launch_tt_step<double>(const TTStepArgs<double>&, hipStream_t, const LaunchTiming*);

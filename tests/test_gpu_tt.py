@@ -1,10 +1,9 @@
 """GPU parity of the Tensor-Train / Tucker path (cpmdp_create_tt,
 cpmdp_create_tucker) against the FP64 oracle O4 (operators expanded from
 their definitions, then Eq. 1 by O1), through the C ABI.  The cases cover
-both step kernels (matrix cores: m_k = 16 with a fiber stride that is a
-multiple of 16 and an input bond >= 2; vector ALUs: everything else), bonds
-1..8, ragged mode sizes, one dimension, terminals, and the 16^6 workload at
-sampled states."""
+both step kernels (matrix cores for m_k = 16, in the row, wide and
+last-dimension layouts; vector ALUs otherwise), bonds 1..8, ragged mode
+sizes, one dimension, terminals, and the 16^6 workload at sampled states."""
 import numpy as np
 import pytest
 
@@ -33,6 +32,8 @@ def _dt(prec):
 CASES = {
     # m = 16 everywhere: dims 0 and 1 on the matrix cores (bond 3 pads to 4)
     "tt_16x16x16_b3": lambda: I.random_tt([16, 16, 16], 2, 3, seed=91, n_terminal=5),
+    # bond 8: the wide layout with 8 input channels (fewer outputs per block)
+    "tt_16x16x16_b8": lambda: I.random_tt([16, 16, 16], 2, 8, seed=90),
     # bond 5 (matrix-core kernel with 8 input channels, FP64 in pairs of outputs)
     "tt_16x16_b5": lambda: I.random_tt([16, 16], 3, 5, seed=92, gamma=0.95),
     # bond 8, mixed sizes: m = 8 and ragged 5, 3, 7 on the vector kernel
