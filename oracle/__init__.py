@@ -19,6 +19,8 @@ Representations of the operator P_a, all in FP64:
                     (numpy tensordot), one rank term at a time; any factors.
   * ``tt``         (O4) -- Tensor-Train and Tucker transition models (Sec. 5)
                     expanded to dense P_a from their definitions, for O1.
+  * ``cpfit``      (O5) -- CP-ALS (Kolda & Bader 2009) fitting rank-R CP
+                    factors to a tabular P_a (the decomposition step of Sec. 3).
 
 Readings of the paper that the oracle fixes (the paper is silent on them):
   * state order of Def. 2 = row-major, last dimension fastest;
@@ -30,5 +32,5 @@ Readings of the paper that the oracle fixes (the paper is silent on them):
     it by more than tol; policy iteration stops when the policy is unchanged
     (Sec. 2.1).
 """
-from . import common, dense, mlp, sparse, structured, tt  # noqa: F401
+from . import common, cpfit, dense, mlp, sparse, structured, tt  # noqa: F401
 from .common import greedy, improve, tie_tolerance  # noqa: F401

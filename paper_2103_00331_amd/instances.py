@@ -674,3 +674,58 @@ def random_tucker(sizes, n_actions: int, core_ranks, seed: int, gamma: float = 0
     return TuckerInstance(np.asarray(sizes, np.int64), cr, np.concatenate(cores),
                           np.concatenate(facs), rng.normal(0.0, 1.0, S), float(gamma), term,
                           name)
+
+
+# ------------------------------------------------------- CP fitting inputs
+
+def transition_coo(inst: Instance, a: int):
+    """The transition matrix P_a of a shift/identity (GridWorld) instance as
+    COO triples (s, s', P(s'|s,a)), one per successor, rows in state order:
+    the tabular input that CP fitting starts from.  Built by moving an agent
+    (no Kronecker product is formed)."""
+    sizes = [int(m) for m in inst.sizes]
+    n = len(sizes)
+    S = inst.n_states
+    strides = [int(np.prod(sizes[k + 1:])) for k in range(n)]
+    coords = np.stack(np.unravel_index(np.arange(S), sizes), axis=1)
+    src = np.arange(S, dtype=np.int64)
+    rows, cols, vals = [], [], []
+    for t in inst.terms_of(a):
+        tgt = src.copy()
+        for k in range(n):
+            T = inst.factor(t, k)
+            m = sizes[k]
+            if np.array_equal(T, np.eye(m)):
+                continue
+            step = +1 if np.array_equal(T, shift_matrix(m, 1)) else -1
+            assert np.array_equal(T, shift_matrix(m, step)), "shift/identity factors only"
+            c = np.clip(coords[:, k] + step, 0, m - 1)
+            tgt = tgt + (c - coords[:, k]) * strides[k]
+        rows.append(src)
+        cols.append(tgt)
+        vals.append(np.full(S, float(inst.lambdas[t])))
+    rows, cols, vals = np.concatenate(rows), np.concatenate(cols), np.concatenate(vals)
+    key, inv = np.unique(rows * S + cols, return_inverse=True)
+    merged = np.zeros(key.size)
+    np.add.at(merged, inv, vals)
+    return key // S, key % S, merged
+
+
+def random_sparse_coo(sizes, nnz_per_row: int, seed: int):
+    """A random row-stochastic sparse S x S matrix (nnz_per_row distinct
+    successors per state, Dirichlet(1) weights) as COO triples."""
+    rng = np.random.default_rng(seed)
+    S = int(np.prod([int(m) for m in sizes]))
+    k = min(nnz_per_row, S)
+    rows = np.repeat(np.arange(S, dtype=np.int64), k)
+    cols = np.concatenate([np.sort(rng.choice(S, k, replace=False)) for _ in range(S)])
+    vals = rng.dirichlet(np.ones(k), size=S).ravel()
+    return rows, cols, vals
+
+
+def cp_fit_init(sizes, rank: int, seed: int) -> np.ndarray:
+    """Seeded starting factors for CP fitting, in the flat term layout of
+    cpmdp_create (term r, dim k, one m_k x m_k block): entries U(0.1, 1)."""
+    rng = np.random.default_rng(seed)
+    stride = sum(int(m) * int(m) for m in sizes)
+    return rng.uniform(0.1, 1.0, rank * stride)
