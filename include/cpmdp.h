@@ -197,6 +197,54 @@ int cpmdp_create_tucker(cpmdp_t** out, int32_t n_dims, const int64_t* sizes,
                         const double* cores, const double* factors,
                         const double* rewards, double gamma);
 
+/*
+ * cpmdp_cp_fit -- fit rank-R CP factors to one action's tabular transition
+ * matrix (the decomposition step behind the CP form of Sec. 2.2 / Sec. 3,
+ * whose method the paper leaves open): alternating least squares (Kolda &
+ * Bader, SIAM Review 51(3), 2009, Sec. 3.4) on the n-way tensor
+ *     X[u_0, .., u_{n-1}] = P(s' | s),   u_k = i_k m_k + j_k
+ * (s = (i_0..i_{n-1}), s' = (j_0..j_{n-1}) in the order of Def. 2).  One
+ * iteration updates k = 0..n-1 in turn: A^(k) = M V^+, with M the sparse
+ * matricised tensor times the Khatri-Rao product of the other factors
+ * (computed on the device over the entries) and V the Hadamard product of
+ * their Gram matrices (R x R, on the host), then scales each column of
+ * A^(k) to unit 2-norm; the norms of the last update are the weights.  The
+ * result is the unconstrained least-squares model (factors may be negative
+ * and rows need not sum to 1).
+ *
+ *   n_dims, sizes : the grid (Def. 1), 1 <= n <= 8, S < 2^31; every
+ *                   m_k^2 * rank <= 8192 (else CPMDP_E_UNSUPPORTED)
+ *   nnz, rows, cols, vals : DEVICE arrays of the nnz COO entries (s, s',
+ *                   P(s'|s)), int32 / int32 / FP64; repeated (s, s') add up;
+ *                   coordinates outside [0, S) give CPMDP_E_ARG
+ *   rank          : R in [1, 32]
+ *   max_iter, tol : stop after max_iter iterations, or when the relative error
+ *                   ||X - X_hat|| / ||X|| changes by <= tol between iterations
+ *   factors       : HOST FP64 [R * sum_k m_k^2], in: the starting factors,
+ *                   out: the fitted ones, in the term layout of cpmdp_create
+ *                   (term r, dim k, one m_k x m_k block row-major = u_k)
+ *   lambdas       : HOST FP64 [R] out: the weights
+ *   errors        : HOST FP64 [max_iter] out (may be NULL): the relative error
+ *                   after every iteration
+ *   iters_out     : iterations run (may be NULL)
+ *   mttkrp_ms     : out (may be NULL): mean device time of one mode's
+ *                   Khatri-Rao product (its kernel and partial-sum reduction)
+ *   workspace, ws_bytes : device, 256-byte aligned, at least
+ *                   cpmdp_cp_fit_workspace_bytes
+ *   stream        : the HIP stream for every device step
+ * Returns CPMDP_OK, or CPMDP_E_ARG, CPMDP_E_UNSUPPORTED, CPMDP_E_WORKSPACE,
+ * CPMDP_E_NONFINITE (start factors, entries or the fit), CPMDP_E_DEVICE.
+ * The call synchronises the stream once per mode update.
+ */
+int cpmdp_cp_fit_workspace_bytes(int32_t n_dims, const int64_t* sizes,
+                                 int64_t nnz, int32_t rank, size_t* bytes);
+int cpmdp_cp_fit(int32_t n_dims, const int64_t* sizes, int64_t nnz,
+                 const int32_t* rows, const int32_t* cols, const double* vals,
+                 int32_t rank, int32_t max_iter, double tol, double* factors,
+                 double* lambdas, double* errors, int32_t* iters_out,
+                 double* mttkrp_ms, void* workspace, size_t ws_bytes,
+                 void* stream);
+
 /* Terminal states (Sec. 3.2): mask [S], nonzero = terminal (V(s) = R(s), no
  * continuation).  Must be called before cpmdp_bind; default: none. */
 int cpmdp_set_terminal(cpmdp_t* h, const uint8_t* mask);

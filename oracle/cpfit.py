@@ -119,3 +119,35 @@ def als(X, A0, iters):
             A[k] = Ak / np.where(lam > 0, lam, 1.0)
         errs.append(np.linalg.norm(X - reconstruct(A, lam)) / normX)
     return A, lam, np.asarray(errs)
+
+
+def als_sparse(sizes, rows, cols, vals, A0, iters):
+    """The same iterations as ``als`` with the Khatri-Rao product taken over
+    COO entries, for P too large to form X.  The error comes from
+    ||X - X_hat||^2 = ||X||^2 - 2 <X, X_hat> + ||X_hat||^2, with <X, X_hat> =
+    sum_r lambda_r <M_r, a^(n-1)_r> (M of the last update, whose factor is
+    the only one changed since) and ||X_hat||^2 = lambda^T (Hadamard of the
+    Gram matrices) lambda."""
+    A = [np.array(Ak, np.float64) for Ak in A0]
+    n = len(A)
+    R = A[0].shape[1]
+    lam = np.ones(R)
+    vals = np.asarray(vals, np.float64)
+    normX2 = float(vals @ vals)
+    errs = []
+    for _ in range(iters):
+        for k in range(n):
+            V = np.ones((R, R))
+            for l in range(n):
+                if l != k:
+                    V *= A[l].T @ A[l]
+            M = mttkrp_sparse(sizes, rows, cols, vals, A, k)
+            Ak = M @ np.linalg.pinv(V)
+            lam = np.linalg.norm(Ak, axis=0)
+            A[k] = Ak / np.where(lam > 0, lam, 1.0)
+        inner = float(lam @ np.sum(M * A[n - 1], axis=0))
+        H = np.ones((R, R))
+        for Ak in A:
+            H *= Ak.T @ Ak
+        errs.append(np.sqrt(max(0.0, normX2 - 2 * inner + lam @ H @ lam)) / np.sqrt(normX2))
+    return A, lam, np.asarray(errs)

@@ -57,6 +57,9 @@ _SIGS = {
                                    C.c_double]),
     "cpmdp_create_tucker": (C.c_int, [C.POINTER(_p), C.c_int32, _i64p, C.c_int32, _i32p, _dp,
                                        _dp, _dp, C.c_double]),
+    "cpmdp_cp_fit_workspace_bytes": (C.c_int, [C.c_int32, _i64p, C.c_int64, C.c_int32, _szp]),
+    "cpmdp_cp_fit": (C.c_int, [C.c_int32, _i64p, C.c_int64, _p, _p, _p, C.c_int32, C.c_int32,
+                                C.c_double, _dp, _dp, _dp, _i32p, _dp, _p, C.c_size_t, _p]),
     "cpmdp_set_terminal": (C.c_int, [_p, _u8p]),
     "cpmdp_set_obstacles": (C.c_int, [_p, _u8p]),
     "cpmdp_get_path": (C.c_int, [_p, _i32p]),
@@ -185,6 +188,40 @@ def cpmdp_create_tucker(sizes: Sequence[int], core_ranks, cores, factors, reward
                                    cores.ctypes.data_as(_dp), factors.ctypes.data_as(_dp),
                                    rewards.ctypes.data_as(_dp), float(gamma)))
     return h
+
+
+def cpmdp_cp_fit_workspace_bytes(sizes, nnz, rank) -> int:
+    sizes = np.ascontiguousarray(sizes, np.int64)
+    out = C.c_size_t()
+    _check(lib.cpmdp_cp_fit_workspace_bytes(int(sizes.size), sizes.ctypes.data_as(_i64p),
+                                            int(nnz), int(rank), C.byref(out)))
+    return out.value
+
+
+def cpmdp_cp_fit(sizes, rows, cols, vals, rank, factors0, max_iter=50, tol=0.0, workspace=None,
+                 stream=None, timing=False):
+    """rows, cols (int32) and vals (FP64) are device tensors; factors0 a host
+    array in the term layout.  Returns (factors, lambdas, errors, iters[,
+    mttkrp_ms])."""
+    import torch
+    sizes = np.ascontiguousarray(sizes, np.int64)
+    nnz = int(vals.numel())
+    if workspace is None:
+        nbytes = cpmdp_cp_fit_workspace_bytes(sizes, nnz, rank)
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=vals.device)
+    fac = np.array(factors0, np.float64, copy=True)
+    lam = np.zeros(int(rank))
+    errs = np.zeros(int(max_iter))
+    it = C.c_int32(0)
+    ms = C.c_double(0.0)
+    _check(lib.cpmdp_cp_fit(int(sizes.size), sizes.ctypes.data_as(_i64p), nnz, _ptr(rows),
+                            _ptr(cols), _ptr(vals), int(rank), int(max_iter), float(tol),
+                            fac.ctypes.data_as(_dp), lam.ctypes.data_as(_dp),
+                            errs.ctypes.data_as(_dp), C.byref(it),
+                            C.byref(ms) if timing else None, workspace.data_ptr(),
+                            workspace.numel() * workspace.element_size(), _stream_ptr(stream)))
+    out = (fac, lam, errs[:it.value], it.value)
+    return out + (ms.value,) if timing else out
 
 
 def cpmdp_set_terminal(h, mask):

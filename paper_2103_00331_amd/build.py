@@ -16,7 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libcpmdp.so")
 
-SOURCES = ["api.cpp", "batch.hip", "stencil.hip", "chain.hip", "util.hip", "lists.hip", "tt.hip",
+SOURCES = ["api.cpp", "batch.hip", "stencil.hip", "chain.hip", "util.hip", "lists.hip", "tt.hip", "cpfit.hip",
            "mlp.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

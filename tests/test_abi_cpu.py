@@ -264,3 +264,15 @@ def test_create_tucker_valid_and_rejects_invalid():
     wide = I.random_tucker([2, 2, 2, 2], 1, [3, 3, 3, 3], seed=7)
     expect(B.CPMDP_E_UNSUPPORTED, sizes=wide.sizes, core_ranks=wide.core_ranks,
            cores=wide.cores, factors=wide.factors, rewards=wide.rewards)   # bond 9 > 8
+
+
+def test_cp_fit_rejects_before_device_work():
+    """Argument checks of cpmdp_cp_fit that run before any device call."""
+    assert B.cpmdp_cp_fit_workspace_bytes([4, 3], 100, 3) > 0
+    for sizes, nnz, rank, code in [([4, 3], 100, 0, B.CPMDP_E_ARG), ([4, 3], 100, 33, B.CPMDP_E_ARG),
+                                   ([4, 3], 0, 3, B.CPMDP_E_ARG),
+                                   ([32, 3], 100, 9, B.CPMDP_E_UNSUPPORTED),  # 32^2 * 9 > 8192
+                                   ([0, 3], 100, 3, B.CPMDP_E_ARG)]:
+        with pytest.raises(B.CpmdpError) as e:
+            B.cpmdp_cp_fit_workspace_bytes(sizes, nnz, rank)
+        assert e.value.code == code

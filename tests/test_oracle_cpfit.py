@@ -166,3 +166,16 @@ def test_planted_mistakes_fail_the_pins(monkeypatch):
             caught |= not np.allclose(upd, sol, rtol=1e-8, atol=1e-10)
         assert caught, bad.__name__
     monkeypatch.setattr(O5, "mttkrp", good)
+
+
+def test_sparse_als_matches_dense_als():
+    sizes = [3, 2, 3]
+    coo = I.random_sparse_coo(sizes, 4, seed=14)
+    X = O5.dense_tensor(sizes, *coo)
+    A0 = O5.factors_from_flat(sizes, 3, I.cp_fit_init(sizes, 3, seed=15))
+    Ad, ld, ed = O5.als(X, A0, 6)
+    As, ls, es = O5.als_sparse(sizes, *coo, A0, 6)
+    for a, b in zip(Ad, As):
+        np.testing.assert_allclose(a, b, rtol=1e-9, atol=1e-11)
+    np.testing.assert_allclose(ls, ld, rtol=1e-10)
+    np.testing.assert_allclose(es, ed, rtol=0, atol=1e-8)
