@@ -18,7 +18,8 @@ Other workloads (--workload): grid4d_96 (96^4, HBM-resident), dense6_16
 GridWorlds), warm64 (learned warm start on 64^3) and paper2d_1000 (the
 1000 x 1000 GridWorld of Table 1 with 22 terminals and 800 obstacles) and
 paper2d_lists (the same problem given as Def. 3 successor lists) and tt6_16
-(16^6, 12 actions with Tensor-Train transitions of bond 4).
+(16^6, 12 actions with Tensor-Train transitions of bond 4) and cpfit_grid4d_32
+(CP-ALS fit at rank 7 of one action's 32^4 transition matrix, 7.3 M entries).
 """
 import argparse
 import hashlib
@@ -57,6 +58,7 @@ BATCH_SRC = ["paper_2103_00331_amd/csrc/batch.hip", "paper_2103_00331_amd/csrc/s
              "paper_2103_00331_amd/csrc/common.cuh"]
 LISTS_SRC = ["paper_2103_00331_amd/csrc/lists.hip", "paper_2103_00331_amd/csrc/common.cuh"]
 TT_SRC = ["paper_2103_00331_amd/csrc/tt.hip", "paper_2103_00331_amd/csrc/common.cuh"]
+CPFIT_SRC = ["paper_2103_00331_amd/csrc/cpfit.hip", "paper_2103_00331_amd/csrc/common.cuh"]
 PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp64": 78.6}
 
 
@@ -504,6 +506,69 @@ def bench_tt(args):
     return out
 
 
+def _cpfit_problem():
+    """Action 0 of the 32^4 GridWorld as COO entries (moves simulated) and a
+    seeded rank-7 start."""
+    from paper_2103_00331_amd import instances as I
+    inst = I.grid4d(32, I.SEED_GRID4)
+    rows, cols, vals = I.transition_coo(inst, 0)
+    sizes = [32] * 4
+    return inst, sizes, (rows, cols, vals), 7, I.cp_fit_init(sizes, 7, seed=20210008)
+
+
+def bench_cpfit(args):
+    """CP-ALS (rank 7) on one action's transition matrix of the 32^4
+    GridWorld, entries resident in device memory; one step = one ALS
+    iteration (all four modes)."""
+    import numpy as np
+    import torch
+
+    from paper_2103_00331_amd import binding as B
+
+    _log("building the 32^4 action-0 transition matrix")
+    inst, sizes, coo, R, init = _cpfit_problem()
+    rows = torch.as_tensor(coo[0].astype(np.int32), device="cuda")
+    cols = torch.as_tensor(coo[1].astype(np.int32), device="cuda")
+    vals = torch.as_tensor(coo[2], device="cuda")
+    nnz = vals.numel()
+    ws = torch.empty(B.cpmdp_cp_fit_workspace_bytes(sizes, nnz, R), dtype=torch.uint8, device="cuda")
+    for _ in range(args.warmup):
+        B.cpmdp_cp_fit(sizes, rows, cols, vals, R, init, max_iter=2, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fac, lam, errs, it, mttkrp_ms = B.cpmdp_cp_fit(sizes, rows, cols, vals, R, init,
+                                                    max_iter=args.steps, workspace=ws, timing=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    nbytes = nnz * (4 + 4 + 8)
+    _log(f"cp-als: {1e3 * el / it:.2f} ms per iteration, MTTKRP {mttkrp_ms * 1e3:.1f} us per mode, "
+         f"error {errs[-1]:.3e}")
+    out = {"metric": "CP-ALS iterations/s (rank-7 CP fit of one action's tabular transition matrix)",
+           "value": it / el, "unit": "iterations/s", "n_gpus": 1, "steps": it,
+           "warmup": args.warmup, "ms_per_step": 1e3 * el / it, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "fp64", "data": "synthetic",
+           "config": {"workload": f"cpfit_grid4d_32: action 0 of the 32^4 GridWorld, {nnz} entries "
+                                  "(s, s', P), rank 7, seeded U(0.1, 1) start",
+                      "final_relative_error": float(errs[-1])},
+           "roofline": {"bound": "hbm", "achieved": nbytes / (mttkrp_ms * 1e-3) / 1e9,
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": nbytes / (mttkrp_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                        "traffic": _traffic("cpfit_mttkrp_grid4d_32.md", CPFIT_SRC),
+                        "kernel": "cp_mttkrp_kernel + cp_reduce_kernel (one mode)",
+                        "kernel_ms": mttkrp_ms, "algorithmic_bytes_per_launch": nbytes,
+                        "lds_fp64_atomics_per_launch": nnz * R}}
+    if not args.no_cpu_baseline:
+        from oracle import cpfit as O5
+        t1 = time.perf_counter()
+        O5.als_sparse(sizes, *coo, O5.factors_from_flat(sizes, R, init), 1)
+        secs = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": 1.0 / secs, "unit": "iterations/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"one CP-ALS iteration of the sparse oracle (numpy, "
+                                         f"{nnz} entries) on the same problem, {secs:.1f} s"}
+    return out
+
+
 def bench_batch(args):
     """512 mixed GridWorlds solved together (FP32 sweeps, FP64 tail and
     certificate per instance, autotuned tiles / sweeps per graph) vs plain
@@ -685,6 +750,21 @@ def kernel_only(args):
     from paper_2103_00331_amd import binding as B
     from paper_2103_00331_amd import instances as I
 
+    if args.workload == "cpfit_grid4d_32":
+        import numpy as np
+        _, sizes, coo, R, init = _cpfit_problem()
+        rows = torch.as_tensor(coo[0].astype(np.int32), device="cuda")
+        cols = torch.as_tensor(coo[1].astype(np.int32), device="cuda")
+        vals = torch.as_tensor(coo[2], device="cuda")
+        out = B.cpmdp_cp_fit(sizes, rows, cols, vals, R, init, max_iter=max(1, args.sweeps // 4),
+                             timing=True)
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
+        dst = torch.empty_like(src)
+        torch.mul(src, 2.0, out=dst)
+        torch.cuda.synchronize()
+        print(json.dumps({"kernel_only": args.workload, "iterations": out[3],
+                          "kernel_ms": out[4], "copy_bytes": src.numel() * 4}), flush=True)
+        return
     if args.workload == "batch512":
         insts = [I.batch_instance(i) for i in range(512)]
         bm = B.BatchModel(insts)
@@ -734,7 +814,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="grid4d_32",
                     choices=["grid4d_32", "grid4d_96", "dense6_16", "batch512", "warm64",
-                             "paper2d_1000", "paper2d_lists", "tt6_16"])
+                             "paper2d_1000", "paper2d_lists", "tt6_16", "cpfit_grid4d_32"])
     ap.add_argument("--method", default="vi", choices=["vi", "pi"])
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -768,6 +848,8 @@ def main():
         out = bench_lists(args)
     elif args.workload == "tt6_16":
         out = bench_tt(args)
+    elif args.workload == "cpfit_grid4d_32":
+        out = bench_cpfit(args)
     else:
         out, inst = bench_grid(args, 32 if args.workload == "grid4d_32" else 96)
         if args.workload in ("grid4d_32", "paper2d_1000") and not args.no_cpu_baseline:

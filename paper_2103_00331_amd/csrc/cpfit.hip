@@ -38,7 +38,8 @@ namespace cpm {
 
 constexpr int kCPMaxRank = 32;
 constexpr int kCPMaxLds = 8192;     // m_k^2 R FP64 words of M per block
-constexpr int kCPBlocks = 512;      // two 64 KB blocks per CU
+constexpr int kCPBlocks = 256;      // one block per CU (up to 64 KB of LDS each)
+constexpr int kCPThreads = 1024;    // 16 waves per block, 4 per SIMD
 
 struct CPArgs {
   const int32_t* rows;
@@ -53,17 +54,64 @@ struct CPArgs {
   double* partial;                  // [blocks][m_k^2 R]
 };
 
+// Each thread takes runs of 4 consecutive entries (one 16-byte load of the
+// states, one of the successors, two of the values: a wave reads 1 KB of
+// each array contiguously) and keeps the rows of M it adds to in a few
+// register slots (round-robin replacement), so the LDS atomics happen only
+// when a row leaves the slots: entries sorted by state reach the same few
+// rows of M many times in a row (for the leading dimensions of a grid, a
+// whole wave's entries share one or two rows, and per-entry atomics on one
+// LDS word serialise).
+constexpr int kCPRun = 4;
+
 template <int RMAX>
-__global__ __launch_bounds__(kBlock) void cp_mttkrp_kernel(CPArgs a) {
+__global__ __launch_bounds__(kCPThreads) void cp_mttkrp_kernel(CPArgs a) {
+  constexpr int kCPSlots = RMAX <= 8 ? 4 : (RMAX <= 16 ? 2 : 1);   // registers
   extern __shared__ double Ml[];
   const int len = a.m[a.k] * a.m[a.k] * a.R;
-  for (int i = threadIdx.x; i < len; i += kBlock) Ml[i] = 0.0;
+  for (int i = threadIdx.x; i < len; i += kCPThreads) Ml[i] = 0.0;
   __syncthreads();
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
-  for (int64_t e = blockIdx.x * kBlock + threadIdx.x; e < a.nnz; e += stride) {
-    uint32_t s = static_cast<uint32_t>(a.rows[e]);
-    uint32_t t = static_cast<uint32_t>(a.cols[e]);
-    const double v = a.vals[e];
+  int key[kCPSlots];
+  double acc[kCPSlots][RMAX];
+#pragma unroll
+  for (int q = 0; q < kCPSlots; ++q) key[q] = -1;
+  int victim = 0;
+  auto flush = [&](int q) {
+    if (key[q] >= 0) {
+#pragma unroll
+      for (int r = 0; r < RMAX; ++r)
+        if (r < a.R) atomicAdd(&Ml[key[q] * a.R + r], acc[q][r]);
+    }
+  };
+  const int64_t runs = (a.nnz + kCPRun - 1) / kCPRun;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kCPThreads;
+  for (int64_t c = blockIdx.x * kCPThreads + threadIdx.x; c < runs; c += stride) {
+  const int64_t e0 = c * kCPRun;
+  const bool full = e0 + kCPRun <= a.nnz;
+  int32_t rs[kCPRun], cs[kCPRun];
+  double vs[kCPRun];
+  if (full) {
+    const int4 r4 = *reinterpret_cast<const int4*>(a.rows + e0);
+    const int4 c4 = *reinterpret_cast<const int4*>(a.cols + e0);
+    const double2 v0 = *reinterpret_cast<const double2*>(a.vals + e0);
+    const double2 v1 = *reinterpret_cast<const double2*>(a.vals + e0 + 2);
+    rs[0] = r4.x; rs[1] = r4.y; rs[2] = r4.z; rs[3] = r4.w;
+    cs[0] = c4.x; cs[1] = c4.y; cs[2] = c4.z; cs[3] = c4.w;
+    vs[0] = v0.x; vs[1] = v0.y; vs[2] = v1.x; vs[3] = v1.y;
+  } else {
+#pragma unroll
+    for (int q = 0; q < kCPRun; ++q) {
+      const bool in = e0 + q < a.nnz;
+      rs[q] = in ? a.rows[e0 + q] : 0;
+      cs[q] = in ? a.cols[e0 + q] : 0;
+      vs[q] = in ? a.vals[e0 + q] : 0.0;     // a zero entry adds nothing
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kCPRun; ++q) {
+    uint32_t s = static_cast<uint32_t>(rs[q]);
+    uint32_t t = static_cast<uint32_t>(cs[q]);
+    const double v = vs[q];
     double prod[RMAX];
 #pragma unroll
     for (int r = 0; r < RMAX; ++r) prod[r] = v;
@@ -83,23 +131,52 @@ __global__ __launch_bounds__(kBlock) void cp_mttkrp_kernel(CPArgs a) {
       for (int r = 0; r < RMAX; ++r)
         if (r < a.R) prod[r] *= row[r];
     }
+    bool hit = false;
 #pragma unroll
-    for (int r = 0; r < RMAX; ++r)
-      if (r < a.R) atomicAdd(&Ml[uk * a.R + r], prod[r]);
+    for (int q = 0; q < kCPSlots; ++q)
+      if (key[q] == uk) {
+        hit = true;
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) acc[q][r] += prod[r];
+      }
+    if (!hit) {
+#pragma unroll
+      for (int q = 0; q < kCPSlots; ++q)
+        if (q == victim) {
+          flush(q);
+          key[q] = uk;
+#pragma unroll
+          for (int r = 0; r < RMAX; ++r) acc[q][r] = prod[r];
+        }
+      victim = victim + 1 == kCPSlots ? 0 : victim + 1;
+    }
   }
+  }
+#pragma unroll
+  for (int q = 0; q < kCPSlots; ++q) flush(q);
   __syncthreads();
   double* dst = a.partial + static_cast<size_t>(blockIdx.x) * len;
-  for (int i = threadIdx.x; i < len; i += kBlock) dst[i] = Ml[i];
+  for (int i = threadIdx.x; i < len; i += kCPThreads) dst[i] = Ml[i];
 }
 
-// out[i] = sum_b partial[b * len + i], b in increasing order.
+// out[i] = sum_b partial[b * len + i] in a fixed order: a block covers 64
+// consecutive i, its 4 waves take b = w, w + 4, ... (coalesced rows of 64
+// words), and the four wave sums are added in wave order.
 __global__ __launch_bounds__(kBlock) void cp_reduce_kernel(const double* partial, int nb, int len,
                                                            double* out) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= len) return;
+  __shared__ double part[kBlock / 64][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane;
   double acc = 0.0;
-  for (int b = 0; b < nb; ++b) acc += partial[static_cast<size_t>(b) * len + i];
-  out[i] = acc;
+  if (i < len)
+    for (int b = w; b < nb; b += kBlock / 64) acc += partial[static_cast<size_t>(b) * len + i];
+  part[w][lane] = acc;
+  __syncthreads();
+  if (w == 0 && i < len) {
+    double s = part[0][lane];
+    for (int q = 1; q < kBlock / 64; ++q) s += part[q][lane];
+    out[i] = s;
+  }
 }
 
 // flag = 1 if an entry's state or successor lies outside [0, S) (the MTTKRP
@@ -211,7 +288,7 @@ static int cp_geom(int32_t n_dims, const int64_t* sizes, int64_t nnz, int32_t ra
   g->S = S;
   g->rows_total = static_cast<int>(rows);
   g->len_max = len_max;
-  const int64_t want = (nnz + 4 * kBlock - 1) / (4 * kBlock);
+  const int64_t want = (nnz + 4 * kCPThreads - 1) / (4 * kCPThreads);   // >= 4 entries per thread
   g->blocks = static_cast<int>(std::min<int64_t>(std::max<int64_t>(want, 1), kCPBlocks));
   return CPMDP_OK;
 }
@@ -250,6 +327,9 @@ int cpmdp_cp_fit(int32_t n_dims, const int64_t* sizes, int64_t nnz, const int32_
   if (rc) return rc;
   if (!rows || !cols || !vals || !factors || !lambdas)
     return fail(nullptr, CPMDP_E_ARG, "NULL input or output array");
+  if (((reinterpret_cast<uintptr_t>(rows) | reinterpret_cast<uintptr_t>(cols) |
+        reinterpret_cast<uintptr_t>(vals)) & 15) != 0)
+    return fail(nullptr, CPMDP_E_ARG, "rows, cols and vals must be 16-byte aligned");
   if (max_iter < 1) return fail(nullptr, CPMDP_E_ARG, "max_iter must be >= 1");
   if (!(tol >= 0.0)) return fail(nullptr, CPMDP_E_ARG, "tol must be >= 0");
   if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
@@ -344,10 +424,10 @@ int cpmdp_cp_fit(int32_t n_dims, const int64_t* sizes, int64_t nnz, const int32_
       const size_t sh = static_cast<size_t>(len) * 8;
       const LaunchTiming t0{ev0, nullptr}, t1{nullptr, ev1};
       const LaunchTiming* tm0 = mttkrp_ms ? &t0 : nullptr;
-      if (R <= 8) klaunch(cp_mttkrp_kernel<8>, dim3(g.blocks), dim3(kBlock), sh, st, tm0, a);
-      else if (R <= 16) klaunch(cp_mttkrp_kernel<16>, dim3(g.blocks), dim3(kBlock), sh, st, tm0, a);
-      else klaunch(cp_mttkrp_kernel<32>, dim3(g.blocks), dim3(kBlock), sh, st, tm0, a);
-      klaunch(cp_reduce_kernel, dim3((len + kBlock - 1) / kBlock), dim3(kBlock), 0, st,
+      if (R <= 8) klaunch(cp_mttkrp_kernel<8>, dim3(g.blocks), dim3(kCPThreads), sh, st, tm0, a);
+      else if (R <= 16) klaunch(cp_mttkrp_kernel<16>, dim3(g.blocks), dim3(kCPThreads), sh, st, tm0, a);
+      else klaunch(cp_mttkrp_kernel<32>, dim3(g.blocks), dim3(kCPThreads), sh, st, tm0, a);
+      klaunch(cp_reduce_kernel, dim3((len + 63) / 64), dim3(kBlock), 0, st,
               mttkrp_ms ? &t1 : nullptr, static_cast<const double*>(dP), g.blocks, len, dM);
       M.assign(static_cast<size_t>(len), 0.0);
       CP_TRY(hipMemcpyAsync(M.data(), dM, static_cast<size_t>(len) * 8,
