@@ -407,7 +407,9 @@ def tt_sweep_cost(inst, word):
     """Algorithmic flops and HBM bytes of one Tensor-Train sweep: per action
     and dim k a bonded mode product (2 S m_k b_k b_{k+1} flops; reads
     b_{k+1} S words, writes b_k S words), then the epilogue (reads A S words
-    of P_a V plus V and R, writes V'; one terminal bit per state)."""
+    of P_a V plus V and R, writes V'; one terminal bit per state).  In FP32
+    with two trailing modes of 16 and bonds <= 4 the last two products run
+    in one launch and the b_{n-1} channels between them stay on chip."""
     S, A, n = inst.n_states, inst.n_actions, inst.n_dims
     flops = 0.0
     words = 0.0
@@ -416,6 +418,11 @@ def tt_sweep_cost(inst, word):
             bl, br = int(inst.bonds[a, k]), int(inst.bonds[a, k + 1])
             flops += 2.0 * S * int(inst.sizes[k]) * bl * br
             words += (bl + br) * S
+        fused = (word == 4 and n >= 2 and int(inst.sizes[n - 1]) == 16 and
+                 int(inst.sizes[n - 2]) == 16 and S % 256 == 0 and
+                 int(inst.bonds[a, n - 1]) <= 4 and int(inst.bonds[a, n - 2]) <= 4)
+        if fused:
+            words -= 2 * int(inst.bonds[a, n - 1]) * S
     words += (A + 3) * S
     return flops, words * word + S / 8.0
 

@@ -332,7 +332,30 @@ static void tt_sweep(cpmdp_t* h, int mode, const void* V, void* Vout, const void
   for (int a = 0; a < h->A; ++a) {
     const T* cur = static_cast<const T*>(V);
     int which = 0;
-    for (int k = n - 1; k >= 0; --k) {
+    int k = n - 1;
+    if constexpr (!f64) {
+      // FP32 with two trailing modes of 16: both products in one launch
+      if (n >= 2 && h->sizes[n - 1] == 16 && h->sizes[n - 2] == 16) {
+        TTStep2Args s2{};
+        s2.in = cur;
+        s2.out = n == 2 ? Y + static_cast<size_t>(a) * S : X[which];
+        s2.core1 = cores + h->t_off[static_cast<size_t>(a) * n + n - 1];
+        s2.core2 = cores + h->t_off[static_cast<size_t>(a) * n + n - 2];
+        s2.S = S;
+        s2.b_mid = h->t_bonds[static_cast<size_t>(a) * (n + 1) + n - 1];
+        s2.b_out = h->t_bonds[static_cast<size_t>(a) * (n + 1) + n - 2];
+        s2.lpad1 = (s2.b_mid + 3) & ~3;
+        s2.lpad2 = (s2.b_out + 3) & ~3;
+        if (tt_last2_fits(s2)) {
+          launch_tt_last2(s2, h->stream, (tm && first) ? &t_first : nullptr);
+          first = false;
+          cur = s2.out;
+          which ^= 1;
+          k = n - 3;
+        }
+      }
+    }
+    for (; k >= 0; --k) {
       TTStepArgs<T> s{};
       s.in = cur;
       s.out = k == 0 ? Y + static_cast<size_t>(a) * S : X[which];

@@ -140,6 +140,20 @@ struct TTEpiArgs {
 
 template <typename T>
 void launch_tt_step(const TTStepArgs<T>& a, hipStream_t st, const LaunchTiming* tm = nullptr);
+
+// The last two bonded mode products in one launch (FP32, m_{n-1} = m_{n-2}
+// = 16): V (one channel) -> b_{n-2} channels, the b_{n-1} channels between
+// them kept on chip.  Cores in the padded device layout of TTStepArgs.
+struct TTStep2Args {
+  const float* in;
+  float* out;
+  const float* core1;           // G_{n-1}: [1][16][lpad1][16]
+  const float* core2;           // G_{n-2}: [b_mid][16][lpad2][16]
+  int32_t S;
+  int32_t b_mid, b_out, lpad1, lpad2;   // b_{n-1}, b_{n-2}, padded to multiples of 4
+};
+bool tt_last2_fits(const TTStep2Args& a);
+void launch_tt_last2(const TTStep2Args& a, hipStream_t st, const LaunchTiming* tm = nullptr);
 template <typename T>
 void launch_tt_epilogue(const TTEpiArgs<T>& a, int mode, hipStream_t st,
                         const LaunchTiming* tm = nullptr);

@@ -237,6 +237,80 @@ __global__ __launch_bounds__(kBlock) void tt_step_mfma(TTStepArgs<T> a) {
   }
 }
 
+// The last two dimensions in one launch (FP32, m_{n-1} = m_{n-2} = 16, bonds
+// b_{n-1}, b_{n-2} <= 4): a wave takes a block of 256 states (fixed leading
+// coordinates), runs the last-dimension product as TT_INNER (16 fibers, one
+// 16-byte load each), which leaves lane (g, c) with
+// Y[l][j_{n-2} = c][i_{n-1} = 4g + r] for every middle bond value l, passes
+// those through its own LDS slab to read them back transposed, and runs the
+// dim n-2 product with the data as the A operand (rows i_{n-1}) and the core
+// as the B operand (columns i_{n-2}), so that lane (g, c) ends with
+// out[i_{n-2} = c][i_{n-1} = 4g .. 4g + 3] and stores it in 16 bytes.  The
+// b_{n-1} intermediate channels never reach HBM.
+constexpr int kTT2Row = 20;          // LDS words per 16-value row (+4: no bank conflicts)
+
+__device__ __forceinline__ void tt_wave_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int BB, int BO>
+__global__ __launch_bounds__(kBlock) void tt_step_last2(TTStep2Args a) {
+  __shared__ float slab[kBlock / 64][BB * 16 * kTT2Row];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int c = lane & 15, g = lane >> 4;
+  float* Ys = slab[wv];
+  float aw[BB][4], bw[BO][BB][4];
+#pragma unroll
+  for (int l = 0; l < BB; ++l)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      aw[l][q] = l < a.b_mid ? a.core1[((4 * g + q) * a.lpad1 + l) * 16 + c] : 0.f;
+#pragma unroll
+  for (int o = 0; o < BO; ++o)
+#pragma unroll
+    for (int l = 0; l < BB; ++l)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        bw[o][l][q] = (l < a.b_mid && o < a.b_out)
+                          ? a.core2[((l * 16 + 4 * q + g) * a.lpad2 + o) * 16 + c] : 0.f;
+  const int nblk = a.S >> 8;
+  const int wave = __builtin_amdgcn_readfirstlane(
+      xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + wv);
+  const int nwaves = gridDim.x * (kBlock / 64);
+  for (int t = wave; t < nblk; t += nwaves) {
+    const size_t base = static_cast<size_t>(t) * 256;
+    const tt_f4 x = *reinterpret_cast<const tt_f4*>(a.in + base + c * 16 + 4 * g);
+#pragma unroll
+    for (int l = 0; l < BB; ++l) {
+      if (l >= a.b_mid) break;
+      tt_f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc = tt_mfma(aw[l][q], x[q], acc);
+      *reinterpret_cast<tt_f4*>(Ys + (l * 16 + c) * kTT2Row + 4 * g) = acc;
+    }
+    tt_wave_fence();
+    float y[BB][4];
+#pragma unroll
+    for (int l = 0; l < BB; ++l)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        y[l][q] = l < a.b_mid ? Ys[(l * 16 + 4 * q + g) * kTT2Row + c] : 0.f;
+    tt_wave_fence();     // the next block's writes come after these reads
+#pragma unroll
+    for (int o = 0; o < BO; ++o) {
+      if (o >= a.b_out) break;
+      tt_f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int l = 0; l < BB; ++l)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc = tt_mfma(y[l][q], bw[o][l][q], acc);
+      *reinterpret_cast<tt_f4*>(a.out + static_cast<size_t>(o) * a.S + base + c * 16 + 4 * g) = acc;
+    }
+  }
+}
+
 // Eq. 1 over Y[a] = P_a V (a < A): Q_a(s) = R(s) + gamma (1 - tau(s)) Y[a](s).
 // E consecutive states per thread (E = 16 bytes / word when S allows: every
 // stream is then read with 16-byte loads).
@@ -441,6 +515,25 @@ void launch_tt_epilogue(const TTEpiArgs<T>& a, int mode, hipStream_t st, const L
                          reinterpret_cast<uintptr_t>(a.Vout);
   if (a.S % W == 0 && (ptrs & 15) == 0) launch_epi_e<T, W>(a, mode, st, tm);
   else launch_epi_e<T, 1>(a, mode, st, tm);
+}
+
+bool tt_last2_fits(const TTStep2Args& a) {
+  const uintptr_t ptrs = reinterpret_cast<uintptr_t>(a.in) | reinterpret_cast<uintptr_t>(a.out);
+  return a.S % 256 == 0 && a.b_mid >= 1 && a.b_mid <= 4 && a.b_out >= 1 && a.b_out <= 4 &&
+         (ptrs & 15) == 0;
+}
+
+void launch_tt_last2(const TTStep2Args& a, hipStream_t st, const LaunchTiming* tm) {
+  const int waves = a.S / 256;
+  const int blocks = (waves + 3) / 4 < kMaxBlocks ? (waves + 3) / 4 : kMaxBlocks;
+  const dim3 grid(blocks), block(kBlock);
+  const int bb = a.b_mid <= 1 ? 1 : a.b_mid <= 2 ? 2 : 4;
+  const int bo = a.b_out <= 1 ? 1 : a.b_out <= 2 ? 2 : 4;
+#define TT2_CASE(B1, B2) \
+  if (bb == B1 && bo == B2) return klaunch(tt_step_last2<B1, B2>, grid, block, 0, st, tm, a);
+  TT2_CASE(1, 1) TT2_CASE(1, 2) TT2_CASE(1, 4) TT2_CASE(2, 1) TT2_CASE(2, 2) TT2_CASE(2, 4)
+  TT2_CASE(4, 1) TT2_CASE(4, 2) TT2_CASE(4, 4)
+#undef TT2_CASE
 }
 
 template void launch_tt_step<double>(const TTStepArgs<double>&, hipStream_t, const LaunchTiming*);

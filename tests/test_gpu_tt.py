@@ -2,8 +2,9 @@
 cpmdp_create_tucker) against the FP64 oracle O4 (operators expanded from
 their definitions, then Eq. 1 by O1), through the C ABI.  The cases cover
 both step kernels (matrix cores for m_k = 16, in the row, wide and
-last-dimension layouts; vector ALUs otherwise), bonds 1..8, ragged mode
-sizes, one dimension, terminals, and the 16^6 workload at sampled states."""
+last-dimension layouts, and the fused launch of the last two dimensions in
+FP32; vector ALUs otherwise), bonds 1..8, ragged mode sizes, one dimension,
+terminals, and the 16^6 workload at sampled states."""
 import numpy as np
 import pytest
 
@@ -32,6 +33,9 @@ def _dt(prec):
 CASES = {
     # m = 16 everywhere: dims 0 and 1 on the matrix cores (bond 3 pads to 4)
     "tt_16x16x16_b3": lambda: I.random_tt([16, 16, 16], 2, 3, seed=91, n_terminal=5),
+    # two dims of 16: in FP32 both products run in the fused launch, which
+    # writes P_a V itself
+    "tt_16x16_b3": lambda: I.random_tt([16, 16], 3, 3, seed=89, n_terminal=4),
     # bond 8: the wide layout with 8 input channels (fewer outputs per block)
     "tt_16x16x16_b8": lambda: I.random_tt([16, 16, 16], 2, 8, seed=90),
     # bond 5 (matrix-core kernel with 8 input channels, FP64 in pairs of outputs)
