@@ -64,28 +64,40 @@ struct CPArgs {
 // LDS word serialise).
 constexpr int kCPRun = 4;
 
-template <int RMAX>
-__global__ __launch_bounds__(kCPThreads) void cp_mttkrp_kernel(CPArgs a) {
-  constexpr int kCPSlots = RMAX <= 8 ? 4 : (RMAX <= 16 ? 2 : 1);   // registers
+template <int RMAX, int NT>
+__global__ __launch_bounds__(NT) void cp_mttkrp_kernel(CPArgs a) {
+  constexpr int kCPSlots = RMAX <= 8 ? 2 : 1;   // registers
   extern __shared__ double Ml[];
   const int len = a.m[a.k] * a.m[a.k] * a.R;
-  for (int i = threadIdx.x; i < len; i += kCPThreads) Ml[i] = 0.0;
+  for (int i = threadIdx.x; i < len; i += NT) Ml[i] = 0.0;
   __syncthreads();
   int key[kCPSlots];
   double acc[kCPSlots][RMAX];
 #pragma unroll
   for (int q = 0; q < kCPSlots; ++q) key[q] = -1;
   int victim = 0;
-  auto flush = [&](int q) {
-    if (key[q] >= 0) {
+  // one masked set of R atomics for the lanes whose slot vq is taken
+  auto flush = [&](int vq) {
+    int vkey = -1;
+    double vacc[RMAX];
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r) vacc[r] = 0.0;
+#pragma unroll
+    for (int q = 0; q < kCPSlots; ++q)
+      if (q == vq) {
+        vkey = key[q];
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) vacc[r] = acc[q][r];
+      }
+    if (vkey >= 0) {
 #pragma unroll
       for (int r = 0; r < RMAX; ++r)
-        if (r < a.R) atomicAdd(&Ml[key[q] * a.R + r], acc[q][r]);
+        if (r < a.R) atomicAdd(&Ml[vkey * a.R + r], vacc[r]);
     }
   };
   const int64_t runs = (a.nnz + kCPRun - 1) / kCPRun;
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * kCPThreads;
-  for (int64_t c = blockIdx.x * kCPThreads + threadIdx.x; c < runs; c += stride) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * NT;
+  for (int64_t c = blockIdx.x * NT + threadIdx.x; c < runs; c += stride) {
   const int64_t e0 = c * kCPRun;
   const bool full = e0 + kCPRun <= a.nnz;
   int32_t rs[kCPRun], cs[kCPRun];
@@ -131,32 +143,34 @@ __global__ __launch_bounds__(kCPThreads) void cp_mttkrp_kernel(CPArgs a) {
       for (int r = 0; r < RMAX; ++r)
         if (r < a.R) prod[r] *= row[r];
     }
-    bool hit = false;
+    // the slot holding uk, else the victim (flushed first); selects, no
+    // per-slot branches, so a wave issues one set of atomics per miss
+    int hitq = -1;
 #pragma unroll
-    for (int q = 0; q < kCPSlots; ++q)
-      if (key[q] == uk) {
-        hit = true;
-#pragma unroll
-        for (int r = 0; r < RMAX; ++r) acc[q][r] += prod[r];
-      }
-    if (!hit) {
+    for (int q = 0; q < kCPSlots; ++q) hitq = key[q] == uk ? q : hitq;
+    if (hitq < 0) {
+      flush(victim);
+      hitq = victim;
+      victim = victim + 1 == kCPSlots ? 0 : victim + 1;
 #pragma unroll
       for (int q = 0; q < kCPSlots; ++q)
-        if (q == victim) {
-          flush(q);
+        if (q == hitq) {
           key[q] = uk;
 #pragma unroll
-          for (int r = 0; r < RMAX; ++r) acc[q][r] = prod[r];
+          for (int r = 0; r < RMAX; ++r) acc[q][r] = 0.0;
         }
-      victim = victim + 1 == kCPSlots ? 0 : victim + 1;
     }
+#pragma unroll
+    for (int q = 0; q < kCPSlots; ++q)
+#pragma unroll
+      for (int r = 0; r < RMAX; ++r) acc[q][r] += q == hitq ? prod[r] : 0.0;
   }
   }
 #pragma unroll
   for (int q = 0; q < kCPSlots; ++q) flush(q);
   __syncthreads();
   double* dst = a.partial + static_cast<size_t>(blockIdx.x) * len;
-  for (int i = threadIdx.x; i < len; i += kCPThreads) dst[i] = Ml[i];
+  for (int i = threadIdx.x; i < len; i += NT) dst[i] = Ml[i];
 }
 
 // out[i] = sum_b partial[b * len + i] in a fixed order: a block covers 64
@@ -424,9 +438,9 @@ int cpmdp_cp_fit(int32_t n_dims, const int64_t* sizes, int64_t nnz, const int32_
       const size_t sh = static_cast<size_t>(len) * 8;
       const LaunchTiming t0{ev0, nullptr}, t1{nullptr, ev1};
       const LaunchTiming* tm0 = mttkrp_ms ? &t0 : nullptr;
-      if (R <= 8) klaunch(cp_mttkrp_kernel<8>, dim3(g.blocks), dim3(kCPThreads), sh, st, tm0, a);
-      else if (R <= 16) klaunch(cp_mttkrp_kernel<16>, dim3(g.blocks), dim3(kCPThreads), sh, st, tm0, a);
-      else klaunch(cp_mttkrp_kernel<32>, dim3(g.blocks), dim3(kCPThreads), sh, st, tm0, a);
+      if (R <= 8) klaunch(cp_mttkrp_kernel<8, kCPThreads>, dim3(g.blocks), dim3(kCPThreads), sh, st, tm0, a);
+      else if (R <= 16) klaunch(cp_mttkrp_kernel<16, kCPThreads>, dim3(g.blocks), dim3(kCPThreads), sh, st, tm0, a);
+      else klaunch(cp_mttkrp_kernel<32, kCPThreads / 2>, dim3(g.blocks), dim3(kCPThreads / 2), sh, st, tm0, a);
       klaunch(cp_reduce_kernel, dim3((len + 63) / 64), dim3(kBlock), 0, st,
               mttkrp_ms ? &t1 : nullptr, static_cast<const double*>(dP), g.blocks, len, dM);
       M.assign(static_cast<size_t>(len), 0.0);

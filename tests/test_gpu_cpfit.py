@@ -44,6 +44,9 @@ CASES = {
     "grid_6x5_r4": ([6, 5], 4, 6, lambda s: I.transition_coo(I.grid_small(s, slip=0.2, seed=24), 1)),
     "grid_32x3_r8": ([32, 3], 8, 5, lambda s: I.transition_coo(I.grid_small(s, slip=0.1, seed=25), 0)),
     "random_2x2x2x2x2_r5": ([2, 2, 2, 2, 2], 5, 6, lambda s: I.random_sparse_coo(s, 6, seed=26)),
+    # ranks above 8 and above 16 (the wider register layouts of the kernel)
+    "random_6x5x4_r12": ([6, 5, 4], 12, 4, lambda s: I.random_sparse_coo(s, 6, seed=4)),
+    "random_5x4x4_r20": ([5, 4, 4], 20, 4, lambda s: I.random_sparse_coo(s, 6, seed=3)),
 }
 
 
