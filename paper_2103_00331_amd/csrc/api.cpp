@@ -711,6 +711,22 @@ static int run_sweeps(cpmdp_t* h, bool prec64, int mode, P*& cur, P*& alt, const
   return CPMDP_OK;
 }
 
+// ||v||_inf of an FP32 vector (keys of max v and max -v, read on the host).
+static int maxabs_f32(cpmdp_t* h, const float* v, double* out) {
+  const hipStream_t st = h->stream;
+  launch_fill_u64(h->d.vmax + 4, 2, 0ull, st);
+  launch_minmax_keys_f32(v, h->S, h->d.vmax + 4, st);
+  HIP_TRY(h, hipMemcpyAsync(h->host_slots, h->d.vmax + 4, 16, hipMemcpyDeviceToHost, st));
+  HIP_TRY(h, hipStreamSynchronize(st));
+  auto undo = [](unsigned long long k) {
+    const unsigned long long b = (k >> 63) ? (k & 0x7FFFFFFFFFFFFFFFull) : ~k;
+    return bits_to_double(b);
+  };
+  *out = std::max(std::fabs(undo(h->host_slots[0])), std::fabs(undo(h->host_slots[1])));
+  if (!std::isfinite(*out)) return fail(h, CPMDP_E_NONFINITE, "non-finite value during sweeps");
+  return CPMDP_OK;
+}
+
 // Greedy / certificate pass in FP64 over V: residual ||BV - V|| and policy.
 static int certify(cpmdp_t* h, const double* V, int32_t* pi_out, const int32_t* pi_in,
                    double* res, unsigned* changes) {
@@ -1589,10 +1605,12 @@ int cpmdp_value_iteration(cpmdp_t* h, double* V, int32_t* pi_out, double eps, in
   double last = INFINITY;
   const hipStream_t st = h->stream;
   SweepTrend trend;   // carried across the precision stages
+  bool low_done = false;   // the low-precision sweeps reached eps / 2 themselves
   if (precision != CPMDP_FP64) {
     // Low-precision sweeps until their own rounding floor, then FP64.
+    const double ulp = std::ldexp(1.0, -24);
     const double vbound = h->rmax / (1.0 - h->gamma);
-    const double floor32 = 8.0 * std::ldexp(1.0, -24) * std::max(1.0, vbound);
+    const double floor32 = 8.0 * ulp * std::max(1.0, vbound);
     launch_f64_to_f32(V, h->d.Va32, h->S, st);
     float* cur = h->d.Va32;
     float* alt = h->d.Vb32;
@@ -1602,12 +1620,39 @@ int cpmdp_value_iteration(cpmdp_t* h, double* V, int32_t* pi_out, double eps, in
                              &last, true, &trend);
       if (rc) return rc;
     }
+    double tol32 = std::max(0.5 * eps, floor32);
+    double cert_target = 0.5 * eps;   // FP32 residual from which the certificate is tried first
     if (!done) {
-      rc = run_sweeps<float>(h, false, MODE_MAX, cur, alt, h->d.R32, nullptr,
-                             std::max(eps, floor32), floor32 * 4, max_iter - 1, &sweeps, &done,
-                             &last, false, &trend);
+      rc = run_sweeps<float>(h, false, MODE_MAX, cur, alt, h->d.R32, nullptr, tol32,
+                             floor32 * 4, max_iter - 1, &sweeps, &done, &last, false, &trend);
       if (rc) return rc;
+      // rmax / (1 - gamma) bounds ||V*|| loosely when rewards take both signs:
+      // take the FP32 rounding floor from the iterate instead,
+      // ||V*|| <= ||V|| + r / (1 - gamma), and go on in FP32 while that floor
+      // lies well below the first one (12 ulp of the bound: FP32 sweeps stall
+      // at 2-7 ulp of ||V|| on the GridWorlds measured).  Only on instances
+      // large enough for an FP64 sweep to cost about twice an FP32 one (on
+      // cache-resident ones the two cost the same and the extra round trip
+      // is the larger cost).
+      const bool large = static_cast<double>(h->S) * h->A >= 16777216.0;
+      if (large && std::isfinite(last) && last > 0.5 * eps && sweeps < max_iter - 1) {
+        double vm = 0.0;
+        rc = maxabs_f32(h, cur, &vm);
+        if (rc) return rc;
+        const double bound = std::max(1.0, vm + last / (1.0 - h->gamma));
+        const double f2 = 12.0 * ulp * bound;
+        // the FP64 residual of an FP32 iterate exceeds its FP32 residual by
+        // a few ulp of ||V||: stop FP32 that far below eps
+        cert_target = eps - 4.0 * ulp * bound;
+        if (f2 < 0.5 * floor32 && last > std::max(cert_target, f2)) {
+          tol32 = std::max(cert_target > 0.0 ? cert_target : 0.5 * eps, f2);
+          rc = run_sweeps<float>(h, false, MODE_MAX, cur, alt, h->d.R32, nullptr, tol32, f2 * 4,
+                                 max_iter - 1, &sweeps, &done, &last, false, &trend);
+          if (rc) return rc;
+        }
+      }
     }
+    low_done = done && tol32 <= cert_target;
     launch_f32_to_f64(cur, V, h->S, st);
   }
   double cert = INFINITY;
@@ -1646,13 +1691,19 @@ int cpmdp_value_iteration(cpmdp_t* h, double* V, int32_t* pi_out, double eps, in
       launch_add_f32_to_f64(V, cur, h->S, st);
     }
   } else {
+    // low-precision sweeps that reached eps / 2 usually leave an FP64
+    // residual below eps: certify before any FP64 sweep
+    bool sweep64 = !low_done;
     for (;;) {
-      double* cur = V;
-      double* alt = h->d.Va64;
-      rc = run_sweeps<double>(h, true, MODE_MAX, cur, alt, h->d.R64, nullptr, eps, 0.0,
-                              max_iter - 1, &sweeps, &done, &last, false, &trend);
-      if (rc) return rc;
-      if (cur != V) HIP_TRY(h, hipMemcpyAsync(V, cur, h->S * 8, hipMemcpyDeviceToDevice, st));
+      if (sweep64) {
+        double* cur = V;
+        double* alt = h->d.Va64;
+        rc = run_sweeps<double>(h, true, MODE_MAX, cur, alt, h->d.R64, nullptr, eps, 0.0,
+                                max_iter - 1, &sweeps, &done, &last, false, &trend);
+        if (rc) return rc;
+        if (cur != V) HIP_TRY(h, hipMemcpyAsync(V, cur, h->S * 8, hipMemcpyDeviceToDevice, st));
+      }
+      sweep64 = true;
       rc = certify(h, V, pi_out, nullptr, &cert, nullptr);
       if (rc) return rc;
       ++sweeps;
