@@ -215,9 +215,9 @@ int cpmdp_create_tucker(cpmdp_t** out, int32_t n_dims, const int64_t* sizes,
  *   n_dims, sizes : the grid (Def. 1), 1 <= n <= 8, S < 2^31; every
  *                   m_k^2 * rank <= 8192 (else CPMDP_E_UNSUPPORTED)
  *   nnz, rows, cols, vals : DEVICE arrays of the nnz COO entries (s, s',
- *                   P(s'|s)), int32 / int32 / FP64, each 16-byte aligned;
- *                   repeated (s, s') add up; coordinates outside [0, S)
- *                   give CPMDP_E_ARG
+ *                   P(s'|s)), int32 / int32 / FP64, each 16-byte aligned,
+ *                   distinct and sorted by (s, s') (row-major); coordinates
+ *                   outside [0, S) or entries out of order give CPMDP_E_ARG
  *   rank          : R in [1, 32]
  *   max_iter, tol : stop after max_iter iterations, or when the relative error
  *                   ||X - X_hat|| / ||X|| changes by <= tol between iterations

@@ -123,7 +123,7 @@ def als(X, A0, iters):
 
 def als_sparse(sizes, rows, cols, vals, A0, iters):
     """The same iterations as ``als`` with the Khatri-Rao product taken over
-    COO entries, for P too large to form X.  The error comes from
+    COO entries (distinct (s, s') pairs), for P too large to form X.  The error comes from
     ||X - X_hat||^2 = ||X||^2 - 2 <X, X_hat> + ||X_hat||^2, with <X, X_hat> =
     sum_r lambda_r <M_r, a^(n-1)_r> (M of the last update, whose factor is
     the only one changed since) and ||X_hat||^2 = lambda^T (Hadamard of the

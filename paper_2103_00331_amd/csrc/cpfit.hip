@@ -193,15 +193,24 @@ __global__ __launch_bounds__(kBlock) void cp_reduce_kernel(const double* partial
   }
 }
 
-// flag = 1 if an entry's state or successor lies outside [0, S) (the MTTKRP
-// kernel takes every coordinate in range).
+// flag bit 0: an entry's state or successor lies outside [0, S) (the MTTKRP
+// kernel takes every coordinate in range); bit 1: the entries are not
+// strictly increasing in (s, s') (so some pair repeats, which ||X||^2 of the
+// reported error does not merge).
 __global__ __launch_bounds__(kBlock) void cp_check_kernel(const int32_t* rows, const int32_t* cols,
                                                           int64_t nnz, int32_t S, unsigned* flag) {
-  bool bad = false;
+  unsigned bad = 0;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
-  for (int64_t e = blockIdx.x * kBlock + threadIdx.x; e < nnz; e += stride)
-    bad |= rows[e] < 0 || rows[e] >= S || cols[e] < 0 || cols[e] >= S;
-  if (bad) atomicOr(flag, 1u);
+  for (int64_t e = blockIdx.x * kBlock + threadIdx.x; e < nnz; e += stride) {
+    const int32_t r = rows[e], c = cols[e];
+    if (r < 0 || r >= S || c < 0 || c >= S) bad |= 1u;
+    if (e + 1 < nnz) {
+      const int64_t k0 = static_cast<int64_t>(r) * S + c;
+      const int64_t k1 = static_cast<int64_t>(rows[e + 1]) * S + cols[e + 1];
+      if (k1 <= k0) bad |= 2u;
+    }
+  }
+  if (bad) atomicOr(flag, bad);
 }
 
 // Per-block sums of squares of the entry values (||X||^2 in two passes).
@@ -396,7 +405,9 @@ int cpmdp_cp_fit(int32_t n_dims, const int64_t* sizes, int64_t nnz, const int32_
   CP_TRY(hipMemcpyAsync(&flag, dflag, 4, hipMemcpyDeviceToHost, st));
   CP_TRY(hipStreamSynchronize(st));
   CP_TRY(hipGetLastError());
-  if (flag) return fail(nullptr, CPMDP_E_ARG, "an entry's state or successor is outside [0, S)");
+  if (flag & 1u) return fail(nullptr, CPMDP_E_ARG, "an entry's state or successor is outside [0, S)");
+  if (flag & 2u)
+    return fail(nullptr, CPMDP_E_ARG, "entries must be distinct and sorted by (state, successor)");
   if (!std::isfinite(normX2)) return fail(nullptr, CPMDP_E_NONFINITE, "non-finite entry value");
   if (normX2 <= 0.0) return fail(nullptr, CPMDP_E_ARG, "all entry values are zero");
   CPArgs a{};

@@ -132,3 +132,75 @@ def test_lists_with_repeated_successors(B):
     assert code == B.CPMDP_OK and res <= 1e-11
     assert_close(V, Vs, 1e-9, "V*")
     compare_policy(pi, oracle.sparse.q_values(dup, mats, Vs), 1e-9)
+
+
+# ------------------------------------------- Tensor-Train / Tucker, CP fitting
+
+def _tt_vi(B, inst, prec, eps):
+    return _vi(B, inst, prec, eps)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_tt_no_discount_and_all_terminal(B, prec):
+    """Tensor-Train operators at the degenerate ends: gamma = 0 gives V* = R
+    with action 0 everywhere; every state terminal gives the same after one
+    sweep."""
+    from oracle import tt as O4  # noqa: F401  (operators are irrelevant here)
+    t0 = I.random_tt([16, 16, 3], 3, 2, seed=71, gamma=0.0)
+    log(f"[edge] tt gamma = 0, prec={prec}")
+    V, pi, code, sweeps, res = _tt_vi(B, t0, prec, 1e-12)
+    assert code == B.CPMDP_OK and res <= 1e-12
+    np.testing.assert_array_equal(V, t0.rewards)
+    assert np.all(pi == 0)
+    t1 = I.random_tt([5, 4], 2, 3, seed=72, gamma=0.9)
+    t1.terminal[:] = 1
+    V, pi, code, sweeps, res = _tt_vi(B, t1, prec, 1e-12)
+    assert code == B.CPMDP_OK and res == 0.0
+    np.testing.assert_array_equal(V, t1.rewards)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_tt_eight_dimensions(B, prec):
+    """n = 8 (the most the library takes) with bond 2 and mixed sizes."""
+    from oracle import tt as O4
+    t = I.random_tt([2, 3, 2, 2, 3, 2, 2, 2], 2, 2, seed=73, gamma=0.9, n_terminal=3)
+    log(f"[edge] tt 8 dimensions, prec={prec}")
+    P = O4.tt_transition_matrices(t)
+    Vs, _, _, _ = oracle.dense.value_iteration(t, P=P)
+    eps = 0.5 * tol_for(prec, Vs) * (1 - t.gamma)
+    V, pi, code, sweeps, res = _tt_vi(B, t, prec, eps)
+    assert code == B.CPMDP_OK and res <= eps
+    assert_close(V, Vs, tol_for(prec, Vs), "V*")
+    compare_policy(pi, oracle.dense.q_values(t, P, Vs), eps / (1 - t.gamma) + 1e-12)
+
+
+def _cp_dev(coo):
+    r, c, v = coo
+    return (torch.as_tensor(np.asarray(r, np.int32), device="cuda"),
+            torch.as_tensor(np.asarray(c, np.int32), device="cuda"),
+            torch.as_tensor(np.asarray(v, np.float64), device="cuda"))
+
+
+def test_cp_fit_rank_one_eight_dims_and_entry_order(B):
+    """CP fitting at rank 1 and on an 8-dimensional grid against the oracle
+    from the same start; repeated or unsorted entries are rejected (the
+    reported error needs distinct entries)."""
+    from oracle import cpfit as O5
+    sizes = [3, 4, 2]
+    r, c, v = I.random_sparse_coo(sizes, 4, seed=74)
+    log("[edge] cp fit: rank 1, 8 dims, entry order")
+    for bad in ((np.repeat(r, 2), np.repeat(c, 2), np.repeat(v / 2.0, 2)),
+                (r[::-1].copy(), c[::-1].copy(), v[::-1].copy())):
+        with pytest.raises(B.CpmdpError) as e:
+            B.cpmdp_cp_fit(sizes, *_cp_dev(bad), 2, I.cp_fit_init(sizes, 2, seed=76), max_iter=2)
+        assert e.value.code == B.CPMDP_E_ARG
+    for coo, R, sz in (((r, c, v), 1, sizes),
+                       (I.random_sparse_coo([2] * 8, 3, seed=75), 2, [2] * 8)):
+        init = I.cp_fit_init(sz, R, seed=76)
+        fac, lam, errs, it = B.cpmdp_cp_fit(sz, *_cp_dev(coo), R, init, max_iter=5)
+        A_ref, l_ref, e_ref = O5.als(O5.dense_tensor(sz, *coo), O5.factors_from_flat(sz, R, init), it)
+        A = O5.factors_from_flat(sz, R, fac)
+        for a, b in zip(A, A_ref):
+            assert np.abs(a - b).max() <= 1e-9
+        assert np.abs(lam - l_ref).max() <= 1e-9 * max(1.0, l_ref.max())
+        assert np.abs(errs - e_ref).max() <= 1e-7
