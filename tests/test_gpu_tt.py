@@ -36,6 +36,8 @@ CASES = {
     # two dims of 16: in FP32 both products run in the fused launch, which
     # writes P_a V itself
     "tt_16x16_b3": lambda: I.random_tt([16, 16], 3, 3, seed=89, n_terminal=4),
+    # bond 4: the first dimension (4 -> 1) through the LDS-shared tile kernel
+    "tt_16x16x16_b4": lambda: I.random_tt([16, 16, 16], 2, 4, seed=88, n_terminal=2),
     # bond 8: the wide layout with 8 input channels (fewer outputs per block)
     "tt_16x16x16_b8": lambda: I.random_tt([16, 16, 16], 2, 8, seed=90),
     # bond 5 (matrix-core kernel with 8 input channels, FP64 in pairs of outputs)
