@@ -684,9 +684,16 @@ def bench_warm(args):
     torch.cuda.synchronize()
     t_solve = time.perf_counter() - t0
     t0 = time.perf_counter()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()          # the library runs on the current stream (see binding)
     losses = w.train(args.train_steps, lr=1e-3, lr_final=1e-4, log_every=max(1, args.train_steps // 5))
+    e1.record()
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
+    step_ms = e0.elapsed_time(e1) / max(args.train_steps, 1)
+    # forward 2 (130*256 + 256*256 + 256) flop per sample, backward the weight
+    # gradients (as many) and the input gradients of the two upper layers
+    step_flops = 4096 * (2 * 2 * (130 * 256 + 256 * 256 + 256) + 2 * (256 * 256 + 256))
     _log(f"training: {len(train)} instances generated {t_gen:.1f}s solved {t_solve:.1f}s, "
          f"{args.train_steps} steps {t_train:.1f}s, losses {losses}")
     test = [I.warm_instance(2, i) for i in range(args.test_instances)]
@@ -745,7 +752,15 @@ def bench_warm(args):
             "time_to_eps_s": chosen_s, "plain_vi_time_to_eps_s": plain_s,
             "speedup_vs_plain_vi": plain_s / chosen_s,
             "sweeps_plain": plain_sw, "sweeps_warm_fp64": warm_sw,
-            "warm_fp64_time_s": warm_s, "sweeps_chosen": [int(v) for v in chosen_sw]}
+            "warm_fp64_time_s": warm_s, "sweeps_chosen": [int(v) for v in chosen_sw],
+            "roofline": {"bound": "alu", "achieved": step_flops / (step_ms * 1e-3) / 1e12,
+                         "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": step_flops / (step_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS,
+                         "traffic": None,
+                         "kernel": "one MLP train step (feature gather, 3 forward and 5 backward "
+                                   "GEMMs, loss, Adam) on 4096 sampled states, events around "
+                                   "all training steps on the library's stream",
+                         "kernel_ms": step_ms, "algorithmic_flops_per_launch": step_flops}}
 
 
 def kernel_only(args):

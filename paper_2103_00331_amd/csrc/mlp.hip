@@ -52,24 +52,28 @@ enum { EPI_NONE = 0, EPI_BIAS = 1, EPI_BIAS_RELU = 2, EPI_MASK = 3 };
 
 // C[M x N] = op(A) op(B) (+ epilogue).  op(A) is M x K: A[m*lda + k], or
 // A[k*lda + m] when TA.  op(B) is K x N: B[k*ldb + n], or B[n*ldb + k] when TB.
+// Split over K (gridDim.z > 1, EPI_NONE only): slice z sums k in
+// [z kc, (z + 1) kc) and writes its partial product to C + z * M * ldc.
 template <bool TA, bool TB, int EPI>
 __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, const float* __restrict__ A,
                                                    int lda, const float* __restrict__ B, int ldb,
                                                    float* __restrict__ C, int ldc,
                                                    const float* __restrict__ bias,
-                                                   const float* __restrict__ mask, int ldm) {
+                                                   const float* __restrict__ mask, int ldm, int kc) {
   __shared__ float As[16][64 + 4];
   __shared__ float Bs[16][64 + 4];
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  const int kb = blockIdx.z * kc, ke = min(K, kb + kc);
+  C += static_cast<int64_t>(blockIdx.z) * M * ldc;
   float acc[4][4] = {};
-  for (int k0 = 0; k0 < K; k0 += 16) {
+  for (int k0 = kb; k0 < ke; k0 += 16) {
     for (int i = threadIdx.x; i < 64 * 16; i += 256) {
       const int r = TA ? (i & 63) : (i >> 4);      // m within tile
       const int c = TA ? (i >> 6) : (i & 15);      // k within tile
       const int gm = m0 + r, gk = k0 + c;
       float v = 0.f;
-      if (gm < M && gk < K) v = TA ? A[static_cast<int64_t>(gk) * lda + gm] : A[static_cast<int64_t>(gm) * lda + gk];
+      if (gm < M && gk < ke) v = TA ? A[static_cast<int64_t>(gk) * lda + gm] : A[static_cast<int64_t>(gm) * lda + gk];
       As[c][r] = v;
     }
     for (int i = threadIdx.x; i < 64 * 16; i += 256) {
@@ -77,7 +81,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, const fl
       const int c = TB ? (i >> 4) : (i & 63);      // n within tile
       const int gk = k0 + r, gn = n0 + c;
       float v = 0.f;
-      if (gk < K && gn < N) v = TB ? B[static_cast<int64_t>(gn) * ldb + gk] : B[static_cast<int64_t>(gk) * ldb + gn];
+      if (gk < ke && gn < N) v = TB ? B[static_cast<int64_t>(gn) * ldb + gk] : B[static_cast<int64_t>(gk) * ldb + gn];
       Bs[r][c] = v;
     }
     __syncthreads();
@@ -112,12 +116,47 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, const fl
   }
 }
 
+// C[i] = sum over z < ks of P[z * len + i], z in increasing order.
+__global__ __launch_bounds__(256) void split_sum_kernel(const float* P, int ks, int len, float* C) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= len) return;
+  float s = 0.f;
+  for (int z = 0; z < ks; ++z) s += P[static_cast<int64_t>(z) * len + i];
+  C[i] = s;
+}
+
+constexpr int kSplitMax = 32;          // K slices of a split product
+constexpr int kSplitWords = kSplitMax * kH * kH;
+
+// Products with few output tiles and a long K (the weight and bias
+// gradients, K = batch) are split over K into slices of at most 256 blocks
+// in all, the partials (in part, kSplitWords floats) summed in slice order.
 template <bool TA, bool TB, int EPI>
 static void gemm(int M, int N, int K, const float* A, int lda, const float* B, int ldb, float* C,
-                 int ldc, const float* bias, const float* mask, int ldm, hipStream_t st) {
-  const dim3 grid((N + 63) / 64, (M + 63) / 64);
+                 int ldc, const float* bias, const float* mask, int ldm, hipStream_t st,
+                 float* part = nullptr) {
+  const int tiles = ((N + 63) / 64) * ((M + 63) / 64);
+  int ks = 1;
+  if (EPI == EPI_NONE && part && tiles < 64 && K >= 2048 && ldc == N) {
+    ks = 256 / tiles;
+    if (ks > kSplitMax) ks = kSplitMax;
+    if (ks > K / 128) ks = K / 128;
+    if (static_cast<int64_t>(ks) * M * N > kSplitWords) ks = static_cast<int>(kSplitWords / (M * N));
+  }
+  if (ks <= 1) {
+    const dim3 grid((N + 63) / 64, (M + 63) / 64);
+    hipLaunchKernelGGL((gemm_kernel<TA, TB, EPI>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb,
+                       C, ldc, bias, mask, ldm, K);
+    return;
+  }
+  const int kc = ((K + ks - 1) / ks + 15) & ~15;
+  ks = (K + kc - 1) / kc;
+  const dim3 grid((N + 63) / 64, (M + 63) / 64, ks);
   hipLaunchKernelGGL((gemm_kernel<TA, TB, EPI>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb,
-                     C, ldc, bias, mask, ldm);
+                     part, N, bias, mask, ldm, kc);
+  const int len = M * N;
+  hipLaunchKernelGGL(split_sum_kernel, dim3((len + 255) / 256), dim3(256), 0, st,
+                     static_cast<const float*>(part), ks, len, C);
 }
 
 // -------------------------------------------------------------- features
@@ -234,13 +273,15 @@ __global__ void to_values_kernel(const float* y, int count, double inv_scale, do
 struct MlpWs {
   float *X, *H1, *H2, *y, *t, *dy, *dH1, *dH2, *ones;
   double* loss;
+  float* part;                      // split-K partial products
 };
 
 static size_t al(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
 size_t mlp_ws_bytes(int B) {
   const size_t b = static_cast<size_t>(B);
-  return al(b * kF * 4) + 4 * al(b * kH * 4) + 4 * al(b * 4) + al(b * 4) + al(64);
+  return al(b * kF * 4) + 4 * al(b * kH * 4) + 4 * al(b * 4) + al(b * 4) + al(64) +
+         al(static_cast<size_t>(kSplitWords) * 4);
 }
 
 MlpWs carve(void* ws, int B) {
@@ -262,6 +303,7 @@ MlpWs carve(void* ws, int B) {
   w.dy = reinterpret_cast<float*>(take(b * 4));
   w.ones = reinterpret_cast<float*>(take(b * 4));
   w.loss = reinterpret_cast<double*>(take(64));
+  w.part = reinterpret_cast<float*>(take(static_cast<size_t>(kSplitWords) * 4));
   return w;
 }
 
@@ -277,16 +319,16 @@ void backward(const float* P, const float* X, int B, const MlpWs& w, float* G, h
   hipLaunchKernelGGL(fill_kernel, dim3(nb), dim3(256), 0, st, w.ones, static_cast<int64_t>(B), 1.0f);
   hipLaunchKernelGGL(mse_kernel, dim3(nb), dim3(256), 0, st, w.y, w.t, B, w.dy, w.loss);
   // layer 3: dw3 = H2^T dy, db3 = 1^T dy, dH2 = (dy w3^T) .* [H2 > 0]
-  gemm<true, false, EPI_NONE>(kH, 1, B, w.H2, kH, w.dy, 1, G + kOffW3, 1, nullptr, nullptr, 0, st);
-  gemm<false, false, EPI_NONE>(1, 1, B, w.ones, B, w.dy, 1, G + kOffB3, 1, nullptr, nullptr, 0, st);
+  gemm<true, false, EPI_NONE>(kH, 1, B, w.H2, kH, w.dy, 1, G + kOffW3, 1, nullptr, nullptr, 0, st, w.part);
+  gemm<false, false, EPI_NONE>(1, 1, B, w.ones, B, w.dy, 1, G + kOffB3, 1, nullptr, nullptr, 0, st, w.part);
   gemm<false, false, EPI_MASK>(B, kH, 1, w.dy, 1, P + kOffW3, kH, w.dH2, kH, nullptr, w.H2, kH, st);
   // layer 2: dW2 = H1^T dH2, db2 = 1^T dH2, dH1 = (dH2 W2^T) .* [H1 > 0]
-  gemm<true, false, EPI_NONE>(kH, kH, B, w.H1, kH, w.dH2, kH, G + kOffW2, kH, nullptr, nullptr, 0, st);
-  gemm<false, false, EPI_NONE>(1, kH, B, w.ones, B, w.dH2, kH, G + kOffB2, kH, nullptr, nullptr, 0, st);
+  gemm<true, false, EPI_NONE>(kH, kH, B, w.H1, kH, w.dH2, kH, G + kOffW2, kH, nullptr, nullptr, 0, st, w.part);
+  gemm<false, false, EPI_NONE>(1, kH, B, w.ones, B, w.dH2, kH, G + kOffB2, kH, nullptr, nullptr, 0, st, w.part);
   gemm<false, true, EPI_MASK>(B, kH, kH, w.dH2, kH, P + kOffW2, kH, w.dH1, kH, nullptr, w.H1, kH, st);
   // layer 1: dW1 = X^T dH1, db1 = 1^T dH1
-  gemm<true, false, EPI_NONE>(kF, kH, B, X, kF, w.dH1, kH, G + kOffW1, kH, nullptr, nullptr, 0, st);
-  gemm<false, false, EPI_NONE>(1, kH, B, w.ones, B, w.dH1, kH, G + kOffB1, kH, nullptr, nullptr, 0, st);
+  gemm<true, false, EPI_NONE>(kF, kH, B, X, kF, w.dH1, kH, G + kOffW1, kH, nullptr, nullptr, 0, st, w.part);
+  gemm<false, false, EPI_NONE>(1, kH, B, w.ones, B, w.dH1, kH, G + kOffB1, kH, nullptr, nullptr, 0, st, w.part);
 }
 
 int mfail(const std::string& m) { return fail(nullptr, CPMDP_E_ARG, m); }
