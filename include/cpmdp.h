@@ -327,8 +327,12 @@ int cpmdp_policy_backup(cpmdp_t* h, const void* V_in, void* V_out,
  *   eps       : absolute residual target (> 0).
  *   max_iter  : cap on backup sweeps (>= 1).
  *   precision : sweep arithmetic; FP32/BF16 sweeps run until they reach their
- *               rounding floor, then FP64 sweeps continue until the FP64
- *               residual meets eps (shift/identity path); on the dense path,
+ *               rounding floor (8 ulp of rmax / (1 - gamma); on instances
+ *               with S * A >= 2^24 then 12 ulp of ||V|| + r / (1 - gamma)
+ *               measured on the iterate) or eps / 2, then FP64 sweeps
+ *               continue until the FP64 residual meets eps (when the FP32
+ *               residual already lies 4 ulp below eps the FP64 certificate
+ *               is tried first); on the dense path,
  *               whose FP64 chain runs on the vector ALUs, the tail instead
  *               refines the greedy policy's evaluation: FP64 residual, low-
  *               precision correction sweeps, V += e, FP64 certificate.
