@@ -1729,7 +1729,9 @@ int cpmdp_policy_iteration(cpmdp_t* h, double* V, int32_t* pi, double eps, int64
   int64_t sweeps = 0, outer = 0;
   const double rmax = h->rmax;
   const double eps_floor = 0.5 * eps * (1.0 - h->gamma);
-  double eps_eval = std::max(eps_floor, 1e-2 * std::max(rmax, 1e-300));
+  // the first policy is usually far from optimal: evaluate it loosely (a
+  // tenth of the reward scale), later ones to 0.05 of the certificate
+  double eps_eval = std::max(eps_floor, 1e-1 * std::max(rmax, 1e-300));
   double cert = INFINITY;
   bool converged = false;
   int certified = 0;

@@ -595,7 +595,7 @@ int batch_pi(cpmdp_batch_t* b, double* const* V_devs, int32_t* const* pi_devs, d
     d.pi_out = pi_devs[i];
     const double rmax = h->rmax;
     eps_floor[i] = 0.5 * eps * (1.0 - h->gamma);
-    eps_eval[i] = std::max(eps_floor[i], 1e-2 * std::max(rmax, 1e-300));
+    eps_eval[i] = std::max(eps_floor[i], 1e-1 * std::max(rmax, 1e-300));   // first policy: loosely
   }
   // every policy entry must name an action (the evaluation sweeps index the
   // weight table with it)
