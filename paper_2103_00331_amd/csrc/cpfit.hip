@@ -17,7 +17,8 @@
 // p prod_{l != k} A^(l)[u_l, :] to row u_k of M.  Blocks accumulate M in LDS
 // (FP64 LDS atomics; M has m_k^2 R <= 8192 words) and store one partial per
 // block; a second kernel sums the partials in a fixed order.  The factors
-// (sum_k m_k^2 R words) are read through the caches.
+// (sum_k m_k^2 R words, each row padded to an even count so that it is read
+// as 16-byte pairs) are read through the caches.
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -40,6 +41,7 @@ constexpr int kCPMaxRank = 32;
 constexpr int kCPMaxLds = 8192;     // m_k^2 R FP64 words of M per block
 constexpr int kCPBlocks = 256;      // one block per CU (up to 64 KB of LDS each)
 constexpr int kCPThreads = 1024;    // 16 waves per block, 4 per SIMD
+constexpr int kCPReduceThreads = 1024;
 
 struct CPArgs {
   const int32_t* rows;
@@ -47,10 +49,11 @@ struct CPArgs {
   const double* vals;
   int64_t nnz;
   int32_t n, k, R;
+  int32_t RP;                       // row stride of A: R rounded up to even
   int32_t m[kMaxDims];
   FastDiv mdiv[kMaxDims];
   int32_t aoff[kMaxDims];           // first row of A^(l) in A (rows of R words)
-  const double* A;                  // [sum_l m_l^2][R]
+  const double* A;                  // [sum_l m_l^2][RP], 16-byte aligned
   double* partial;                  // [blocks][m_k^2 R]
 };
 
@@ -138,10 +141,15 @@ __global__ __launch_bounds__(NT) void cp_mttkrp_kernel(CPArgs a) {
         uk = u;
         continue;
       }
-      const double* row = a.A + static_cast<size_t>(a.aoff[l] + u) * a.R;
+      const double2* row =
+          reinterpret_cast<const double2*>(a.A + static_cast<size_t>(a.aoff[l] + u) * a.RP);
 #pragma unroll
-      for (int r = 0; r < RMAX; ++r)
-        if (r < a.R) prod[r] *= row[r];
+      for (int r = 0; r < RMAX; r += 2)
+        if (r < a.R) {
+          const double2 f = row[r >> 1];
+          prod[r] *= f.x;
+          prod[r + 1] *= f.y;   // the padding word when r + 1 == R
+        }
     }
     // the slot holding uk, else the victim (flushed first); selects, no
     // per-slot branches, so a wave issues one set of atomics per miss
@@ -174,21 +182,22 @@ __global__ __launch_bounds__(NT) void cp_mttkrp_kernel(CPArgs a) {
 }
 
 // out[i] = sum_b partial[b * len + i] in a fixed order: a block covers 64
-// consecutive i, its 4 waves take b = w, w + 4, ... (coalesced rows of 64
-// words), and the four wave sums are added in wave order.
-__global__ __launch_bounds__(kBlock) void cp_reduce_kernel(const double* partial, int nb, int len,
-                                                           double* out) {
-  __shared__ double part[kBlock / 64][64];
+// consecutive i, its 16 waves take b = w, w + 16, ... (coalesced rows of 64
+// words), and the wave sums are added in wave order.
+__global__ __launch_bounds__(kCPReduceThreads) void cp_reduce_kernel(const double* partial, int nb,
+                                                                     int len, double* out) {
+  constexpr int kW = kCPReduceThreads / 64;
+  __shared__ double part[kW][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int i = blockIdx.x * 64 + lane;
   double acc = 0.0;
   if (i < len)
-    for (int b = w; b < nb; b += kBlock / 64) acc += partial[static_cast<size_t>(b) * len + i];
+    for (int b = w; b < nb; b += kW) acc += partial[static_cast<size_t>(b) * len + i];
   part[w][lane] = acc;
   __syncthreads();
   if (w == 0 && i < len) {
     double s = part[0][lane];
-    for (int q = 1; q < kBlock / 64; ++q) s += part[q][lane];
+    for (int q = 1; q < kW; ++q) s += part[q][lane];
     out[i] = s;
   }
 }
@@ -316,11 +325,12 @@ static int cp_geom(int32_t n_dims, const int64_t* sizes, int64_t nnz, int32_t ra
   return CPMDP_OK;
 }
 
-// Workspace: A [rows][R], partials [blocks][len_max], M [len_max] (FP64),
+// Workspace: A [rows][RP], partials [blocks][len_max], M [len_max] (FP64),
 // one flag word.
+static int cp_row_stride(int R) { return (R + 1) & ~1; }
 static size_t cp_ws_bytes(const CPGeom& g) {
   auto al = [](size_t x) { return (x + 255) & ~static_cast<size_t>(255); };
-  return al(static_cast<size_t>(g.rows_total) * g.R * 8) +
+  return al(static_cast<size_t>(g.rows_total) * cp_row_stride(g.R) * 8) +
          al(static_cast<size_t>(g.blocks) * g.len_max * 8) + al(static_cast<size_t>(g.len_max) * 8) +
          256;
 }
@@ -358,7 +368,7 @@ int cpmdp_cp_fit(int32_t n_dims, const int64_t* sizes, int64_t nnz, const int32_
   if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
     return fail(nullptr, CPMDP_E_WORKSPACE, "workspace must be non-NULL and 256-byte aligned");
   if (ws_bytes < cp_ws_bytes(g)) return fail(nullptr, CPMDP_E_WORKSPACE, "workspace too small");
-  const int n = g.n, R = g.R;
+  const int n = g.n, R = g.R, RP = cp_row_stride(R);
   int64_t stride = 0;
   for (int k = 0; k < n; ++k) stride += g.m[k] * g.m[k];
   for (int64_t i = 0; i < R * stride; ++i)
@@ -367,8 +377,8 @@ int cpmdp_cp_fit(int32_t n_dims, const int64_t* sizes, int64_t nnz, const int32_
   char* base = static_cast<char*>(workspace);
   auto al = [](size_t x) { return (x + 255) & ~static_cast<size_t>(255); };
   double* dA = reinterpret_cast<double*>(base);
-  double* dP = reinterpret_cast<double*>(base + al(static_cast<size_t>(g.rows_total) * R * 8));
-  double* dM = reinterpret_cast<double*>(base + al(static_cast<size_t>(g.rows_total) * R * 8) +
+  double* dP = reinterpret_cast<double*>(base + al(static_cast<size_t>(g.rows_total) * RP * 8));
+  double* dM = reinterpret_cast<double*>(base + al(static_cast<size_t>(g.rows_total) * RP * 8) +
                                          al(static_cast<size_t>(g.blocks) * g.len_max * 8));
   unsigned* dflag = reinterpret_cast<unsigned*>(reinterpret_cast<char*>(dM) +
                                                 al(static_cast<size_t>(g.len_max) * 8));
@@ -380,8 +390,14 @@ int cpmdp_cp_fit(int32_t n_dims, const int64_t* sizes, int64_t nnz, const int32_
     for (int r = 0; r < R; ++r)
       for (int u = 0; u < rk; ++u) A[k][u * R + r] = factors[r * stride + (g.aoff[k]) + u];
   }
-  std::vector<double> flatA(static_cast<size_t>(g.rows_total) * R);
-  for (int k = 0; k < n; ++k) std::copy(A[k].begin(), A[k].end(), flatA.begin() + g.aoff[k] * R);
+  // device copy with rows padded to RP words (the padding stays zero)
+  std::vector<double> flatA(static_cast<size_t>(g.rows_total) * RP, 0.0);
+  auto pad_rows = [&](int k, double* dst) {
+    const int rk = g.m[k] * g.m[k];
+    for (int u = 0; u < rk; ++u)
+      for (int r = 0; r < R; ++r) dst[static_cast<size_t>(u) * RP + r] = A[k][u * R + r];
+  };
+  for (int k = 0; k < n; ++k) pad_rows(k, flatA.data() + static_cast<size_t>(g.aoff[k]) * RP);
   CP_TRY(hipMemcpyAsync(dA, flatA.data(), flatA.size() * 8, hipMemcpyHostToDevice, st));
   auto gram = [&](int k) {
     const int rk = g.m[k] * g.m[k];
@@ -398,7 +414,7 @@ int cpmdp_cp_fit(int32_t n_dims, const int64_t* sizes, int64_t nnz, const int32_
   hipLaunchKernelGGL(cp_check_kernel, dim3(g.blocks), dim3(kBlock), 0, st, rows, cols, g.nnz,
                      static_cast<int32_t>(g.S), dflag);
   hipLaunchKernelGGL(cp_sumsq_kernel, dim3(g.blocks), dim3(kBlock), 0, st, vals, g.nnz, dP);
-  hipLaunchKernelGGL(cp_reduce_kernel, dim3(1), dim3(kBlock), 0, st, dP, g.blocks, 1, dM);
+  hipLaunchKernelGGL(cp_reduce_kernel, dim3(1), dim3(kCPReduceThreads), 0, st, dP, g.blocks, 1, dM);
   double normX2 = 0.0;
   unsigned flag = 0;
   CP_TRY(hipMemcpyAsync(&normX2, dM, 8, hipMemcpyDeviceToHost, st));
@@ -417,6 +433,7 @@ int cpmdp_cp_fit(int32_t n_dims, const int64_t* sizes, int64_t nnz, const int32_
   a.nnz = g.nnz;
   a.n = n;
   a.R = R;
+  a.RP = RP;
   for (int k = 0; k < n; ++k) {
     a.m[k] = g.m[k];
     a.mdiv[k] = make_fastdiv(static_cast<uint32_t>(g.m[k]));
@@ -452,7 +469,7 @@ int cpmdp_cp_fit(int32_t n_dims, const int64_t* sizes, int64_t nnz, const int32_
       if (R <= 8) klaunch(cp_mttkrp_kernel<8, kCPThreads>, dim3(g.blocks), dim3(kCPThreads), sh, st, tm0, a);
       else if (R <= 16) klaunch(cp_mttkrp_kernel<16, kCPThreads>, dim3(g.blocks), dim3(kCPThreads), sh, st, tm0, a);
       else klaunch(cp_mttkrp_kernel<32, kCPThreads / 2>, dim3(g.blocks), dim3(kCPThreads / 2), sh, st, tm0, a);
-      klaunch(cp_reduce_kernel, dim3((len + 63) / 64), dim3(kBlock), 0, st,
+      klaunch(cp_reduce_kernel, dim3((len + 63) / 64), dim3(kCPReduceThreads), 0, st,
               mttkrp_ms ? &t1 : nullptr, static_cast<const double*>(dP), g.blocks, len, dM);
       M.assign(static_cast<size_t>(len), 0.0);
       CP_TRY(hipMemcpyAsync(M.data(), dM, static_cast<size_t>(len) * 8,
@@ -485,8 +502,10 @@ int cpmdp_cp_fit(int32_t n_dims, const int64_t* sizes, int64_t nnz, const int32_
           for (int u = 0; u < rk; ++u) A[k][u * R + r] /= lam[r];
       }
       G[k] = gram(k);
-      CP_TRY(hipMemcpyAsync(dA + static_cast<size_t>(g.aoff[k]) * R, A[k].data(),
-                                      A[k].size() * 8, hipMemcpyHostToDevice, st));
+      double* hk = flatA.data() + static_cast<size_t>(g.aoff[k]) * RP;
+      pad_rows(k, hk);
+      CP_TRY(hipMemcpyAsync(dA + static_cast<size_t>(g.aoff[k]) * RP, hk,
+                            static_cast<size_t>(rk) * RP * 8, hipMemcpyHostToDevice, st));
     }
     // relative error from ||X||^2, <X, X_hat> (the last mode's M against its
     // new factor) and ||X_hat||^2 = lambda^T (Hadamard of all Grams) lambda
@@ -515,7 +534,11 @@ int cpmdp_cp_fit(int32_t n_dims, const int64_t* sizes, int64_t nnz, const int32_
     }
     prev = err;
   }
+  // the factor uploads read flatA, which ends with this call
+  const hipError_t se = hipStreamSynchronize(st);
   if (out_rc) return out_rc;
+  if (se != hipSuccess)
+    return fail(nullptr, CPMDP_E_DEVICE, std::string("hipStreamSynchronize: ") + hipGetErrorString(se));
   for (int k = 0; k < n; ++k) {
     const int rk = g.m[k] * g.m[k];
     for (int r = 0; r < R; ++r)
