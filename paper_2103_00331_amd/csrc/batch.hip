@@ -94,7 +94,7 @@ __device__ __forceinline__ void tile_states(const GridGeom& g, const StencilIO<T
                                             const StencilW<T>& W, int s0, int s1, T tol,
                                             T& res, double& res_d, unsigned& ch) {
   for (int s = s0 + threadIdx.x * VEC; s < s1; s += kBBlock * VEC)
-    stencil_chunk<T, N, MODE, VEC, AXIS>(g, io, W, s, tol, res, res_d, ch);
+    stencil_chunk<T, N, MODE, VEC, AXIS, true>(g, io, W, s, tol, res, res_d, ch);
 }
 
 template <typename T, int MODE, int N>

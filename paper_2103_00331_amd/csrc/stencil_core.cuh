@@ -130,11 +130,33 @@ __device__ __forceinline__ void stencil_state(const StencilW<T>& W, const T (&nb
   if (MODE != MODE_RESID) res = tnanmax(res, fabs(out - c));
 }
 
+// 4-word load / store marked non-temporal: the reward words and V' of a
+// sweep too large for the caches are touched once, and marking them keeps
+// the L2 for the V words that neighbouring tiles read again.
+template <typename V4, typename T>
+__device__ __forceinline__ V4 load4_stream(const T* p) {
+  typedef T nv4 __attribute__((ext_vector_type(4)));
+  const nv4 v = __builtin_nontemporal_load(reinterpret_cast<const nv4*>(p));
+  V4 o;
+  o.x = v.x;
+  o.y = v.y;
+  o.z = v.z;
+  o.w = v.w;
+  return o;
+}
+template <typename V4, typename T>
+__device__ __forceinline__ void store4_stream(T* p, const V4& o) {
+  typedef T nv4 __attribute__((ext_vector_type(4)));
+  const nv4 v = {o.x, o.y, o.z, o.w};
+  __builtin_nontemporal_store(v, reinterpret_cast<nv4*>(p));
+}
+
 // States s .. s+3 along the last dimension (m_last % 4 == 0, s % 4 == 0)
 // given their values c4 and the vectors of their +-e_k neighbours for
 // k < n-1 (clamped): the last-dimension neighbours come from c4 and the two
-// adjacent scalars; then per-state work and stores.
-template <typename T, int N, int MODE, bool AXIS>
+// adjacent scalars; then per-state work and stores (R loads and V' stores
+// non-temporal when STREAM).
+template <typename T, int N, int MODE, bool AXIS, bool STREAM = false>
 __device__ __forceinline__ void stencil_vec4(const GridGeom& g, const StencilIO<T>& io,
                                              const StencilW<T>& W, int s, int il,
                                              const typename VecOf<T, 4>::type& c4,
@@ -146,7 +168,7 @@ __device__ __forceinline__ void stencil_vec4(const GridGeom& g, const StencilIO<
   constexpr int P = 2 * N + 1;
   const T left = io.V[s - ((il > 0) ? 1 : 0)];
   const T right = io.V[s + ((il + 4 < g.size[N - 1]) ? 4 : 3)];
-  const V4 r4 = *reinterpret_cast<const V4*>(io.R + s);
+  const V4 r4 = STREAM ? load4_stream<V4>(io.R + s) : *reinterpret_cast<const V4*>(io.R + s);
   const uint32_t tw = io.tbits[s >> 5] >> (s & 31);
   int4 p4 = make_int4(-1, -1, -1, -1);
   if (MODE != MODE_MAX && io.pi_in) p4 = *reinterpret_cast<const int4*>(io.pi_in + s);
@@ -194,7 +216,8 @@ __device__ __forceinline__ void stencil_vec4(const GridGeom& g, const StencilIO<
       o.y = outv[1];
       o.z = outv[2];
       o.w = outv[3];
-      *reinterpret_cast<V4*>(io.Vout + s) = o;
+      if (STREAM) store4_stream(io.Vout + s, o);
+      else *reinterpret_cast<V4*>(io.Vout + s) = o;
     }
     if (MODE == MODE_GREEDY && io.pi_out)
       *reinterpret_cast<int4*>(io.pi_out + s) = make_int4(pnv[0], pnv[1], pnv[2], pnv[3]);
@@ -204,7 +227,8 @@ __device__ __forceinline__ void stencil_vec4(const GridGeom& g, const StencilIO<
 // The VEC states s .. s+VEC-1 (VEC = 4 needs m_last % 4 == 0 and s % 4 == 0):
 // loads, per-state work, stores.  Loads use clamped addresses (at the grid
 // edge the neighbour is the state itself), so every load is unconditional.
-template <typename T, int N, int MODE, int VEC, bool AXIS>
+// STREAM: R loads and V' stores non-temporal (VEC = 4).
+template <typename T, int N, int MODE, int VEC, bool AXIS, bool STREAM = false>
 __device__ __forceinline__ void stencil_chunk(const GridGeom& g, const StencilIO<T>& io,
                                               const StencilW<T>& W, int s, T tol, T& res,
                                               double& res_d, unsigned& changed,
@@ -257,8 +281,8 @@ __device__ __forceinline__ void stencil_chunk(const GridGeom& g, const StencilIO
       plus4[k] = *reinterpret_cast<const V4*>(io.V + s + ((idx[k] < g.size[k] - 1) ? st : 0));
       minus4[k] = *reinterpret_cast<const V4*>(io.V + s - ((idx[k] > 0) ? st : 0));
     }
-    stencil_vec4<T, N, MODE, AXIS>(g, io, W, s, idx[N - 1], c4, plus4, minus4, tol, res, res_d,
-                                   changed, live);
+    stencil_vec4<T, N, MODE, AXIS, STREAM>(g, io, W, s, idx[N - 1], c4, plus4, minus4, tol, res,
+                                           res_d, changed, live);
   }
 }
 
@@ -299,7 +323,7 @@ __device__ __forceinline__ void march_column(const GridGeom& g, const StencilIO<
       plus4[k] = *reinterpret_cast<const V4*>(io.V + s + ((idx[k] < g.size[k] - 1) ? st : 0));
       minus4[k] = *reinterpret_cast<const V4*>(io.V + s - ((idx[k] > 0) ? st : 0));
     }
-    stencil_vec4<T, N, MODE, AXIS>(g, io, W, s, idx[N - 1], cur, plus4, minus4, tol, res, res_d,
+    stencil_vec4<T, N, MODE, AXIS, true>(g, io, W, s, idx[N - 1], cur, plus4, minus4, tol, res, res_d,
                                    changed);
     prev = cur;
     cur = nxt;
