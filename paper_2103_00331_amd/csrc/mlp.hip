@@ -116,6 +116,141 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, const fl
   }
 }
 
+// C[M x N] = A B (+ bias, ReLU) on the FP32 matrix cores
+// (v_mfma_f32_16x16x4f32), for the forward layers (A row-major M x K, B
+// row-major K x N).  Four waves in a 2 x 2 grid each compute WM x WN tiles of
+// 16 x 16; the block's A (BM x 16) and B (16 x BN) slices go through LDS, k
+// in steps of 16 (zero-padded past K, M and N).  The next slices are loaded
+// into registers while the matrix cores work on the current ones; a slice
+// inside the matrix is loaded without per-element guards, so that its loads
+// issue together.  Lane l = 16 g + c of one
+// 16x16x4 product supplies A[i = c][k = g] and B[k = g][n = c]; its result
+// register r holds D[i = 4 g + r][n = c].
+typedef float mlp_f4 __attribute__((ext_vector_type(4)));
+
+template <int WM, int WN, int EPI>
+__global__ __launch_bounds__(256) void gemm_mfma_kernel(int M, int N, int K,
+                                                        const float* __restrict__ A, int lda,
+                                                        const float* __restrict__ B, int ldb,
+                                                        float* __restrict__ C, int ldc,
+                                                        const float* __restrict__ bias) {
+  constexpr int BM = 32 * WM, BN = 32 * WN, KT = 16;
+  constexpr int LA = BM * KT / 256, LB = KT * BN / 256;   // slice words per thread
+  __shared__ float As[KT][BM + 4];
+  __shared__ float Bs[KT][BN + 4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int g = lane >> 4, c = lane & 15;
+  const int wm = wv >> 1, wn = wv & 1;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  mlp_f4 acc[WM][WN];
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j) acc[i][j] = mlp_f4{0.f, 0.f, 0.f, 0.f};
+  float ra[LA], rb[LB];
+  auto fetch = [&](int k0) {
+    if (m0 + BM <= M && k0 + KT <= K) {
+#pragma unroll
+      for (int q = 0; q < LA; ++q) {
+        const int i = threadIdx.x + q * 256;
+        const int r = i / KT, kk = i % KT;   // 16 threads read 16 consecutive k of a row
+        ra[q] = A[static_cast<int64_t>(m0 + r) * lda + k0 + kk];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < LA; ++q) {
+        const int i = threadIdx.x + q * 256;
+        const int r = i / KT, kk = i % KT;
+        const int gm = m0 + r, gk = k0 + kk;
+        ra[q] = (gm < M && gk < K) ? A[static_cast<int64_t>(gm) * lda + gk] : 0.f;
+      }
+    }
+    if (k0 + KT <= K && n0 + BN <= N) {
+#pragma unroll
+      for (int q = 0; q < LB; ++q) {
+        const int i = threadIdx.x + q * 256;
+        rb[q] = B[static_cast<int64_t>(k0 + i / BN) * ldb + n0 + i % BN];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < LB; ++q) {
+        const int i = threadIdx.x + q * 256;
+        const int gk = k0 + i / BN, gn = n0 + i % BN;
+        rb[q] = (gk < K && gn < N) ? B[static_cast<int64_t>(gk) * ldb + gn] : 0.f;
+      }
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < K; k0 += KT) {
+#pragma unroll
+    for (int q = 0; q < LA; ++q) {
+      const int i = threadIdx.x + q * 256;
+      As[i % KT][i / KT] = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < LB; ++q) {
+      const int i = threadIdx.x + q * 256;
+      Bs[i / BN][i % BN] = rb[q];
+    }
+    __syncthreads();
+    if (k0 + KT < K) fetch(k0 + KT);
+#pragma unroll
+    for (int ks = 0; ks < KT; ks += 4) {
+      float a[WM], b[WN];
+#pragma unroll
+      for (int i = 0; i < WM; ++i) a[i] = As[ks + g][(wm * WM + i) * 16 + c];
+#pragma unroll
+      for (int j = 0; j < WN; ++j) b[j] = Bs[ks + g][(wn * WN + j) * 16 + c];
+#pragma unroll
+      for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j) {
+      const int gn = n0 + (wn * WN + j) * 16 + c;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + (wm * WM + i) * 16 + 4 * g + r;
+        if (gm >= M || gn >= N) continue;
+        float v = acc[i][j][r];
+        if (EPI == EPI_BIAS || EPI == EPI_BIAS_RELU) v += bias[gn];
+        if (EPI == EPI_BIAS_RELU) v = fmaxf(v, 0.f);
+        C[static_cast<int64_t>(gm) * ldc + gn] = v;
+      }
+    }
+}
+
+// y[i] = A[i, :] w + b (the output layer, N = 1): one wave per row, each
+// lane a 16-byte piece of the row (rows 16-byte aligned, K % 4 == 0), then a
+// butterfly sum across the wave.
+__global__ __launch_bounds__(256) void gemv_bias_kernel(int M, int K, const float* __restrict__ A,
+                                                        int lda, const float* __restrict__ w,
+                                                        const float* __restrict__ b,
+                                                        float* __restrict__ y) {
+  const int lane = threadIdx.x & 63;
+  const int nw = gridDim.x * 4;
+  for (int i = blockIdx.x * 4 + (threadIdx.x >> 6); i < M; i += nw) {
+    const float* row = A + static_cast<int64_t>(i) * lda;
+    float acc = 0.f;
+    for (int k = lane * 4; k < K; k += 256) {
+      const float4 a = *reinterpret_cast<const float4*>(row + k);
+      acc = fmaf(a.x, w[k], acc);
+      acc = fmaf(a.y, w[k + 1], acc);
+      acc = fmaf(a.z, w[k + 2], acc);
+      acc = fmaf(a.w, w[k + 3], acc);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) y[i] = acc + b[0];
+  }
+}
+
 // C[i] = sum over z < ks of P[z * len + i], z in increasing order.
 __global__ __launch_bounds__(256) void split_sum_kernel(const float* P, int ks, int len, float* C) {
   const int i = blockIdx.x * 256 + threadIdx.x;
@@ -135,6 +270,26 @@ template <bool TA, bool TB, int EPI>
 static void gemm(int M, int N, int K, const float* A, int lda, const float* B, int ldb, float* C,
                  int ldc, const float* bias, const float* mask, int ldm, hipStream_t st,
                  float* part = nullptr) {
+  if (!TA && !TB && EPI == EPI_BIAS && N == 1 && ldb == 1 && K % 4 == 0 && lda % 4 == 0 &&
+      (reinterpret_cast<uintptr_t>(A) & 15) == 0) {
+    const int blocks = std::min((M + 3) / 4, 8192);
+    hipLaunchKernelGGL(gemv_bias_kernel, dim3(blocks), dim3(256), 0, st, M, K, A, lda, B, bias, C);
+    return;
+  }
+  if (!TA && !TB && (EPI == EPI_BIAS || EPI == EPI_BIAS_RELU) && N >= 64) {
+    // forward layers: matrix cores, 128 x 128 tiles when there are enough
+    // rows to fill the chip with them, else 64 x 64
+    if (M >= 32768) {
+      const dim3 grid((N + 127) / 128, (M + 127) / 128);
+      hipLaunchKernelGGL((gemm_mfma_kernel<4, 4, EPI>), grid, dim3(256), 0, st, M, N, K, A, lda, B,
+                         ldb, C, ldc, bias);
+    } else {
+      const dim3 grid((N + 63) / 64, (M + 63) / 64);
+      hipLaunchKernelGGL((gemm_mfma_kernel<2, 2, EPI>), grid, dim3(256), 0, st, M, N, K, A, lda, B,
+                         ldb, C, ldc, bias);
+    }
+    return;
+  }
   const int tiles = ((N + 63) / 64) * ((M + 63) / 64);
   int ks = 1;
   if (EPI == EPI_NONE && part && tiles < 64 && K >= 2048 && ldc == N) {
@@ -165,51 +320,61 @@ static void gemm(int M, int N, int K, const float* A, int lda, const float* B, i
 //   [3..127]  10 * R(clamp(i + d)) for d in {-2..2}^3, d_0 slowest
 //   [128]     (gamma - 0.945) / 0.026
 //   [129]     (slip - 0.175) / 0.072
-__device__ __forceinline__ void feature_row(const float* R, int m, float gamma, float slip, int s,
-                                            float* x) {
+// computed one feature at a time.
+__device__ __forceinline__ float feature_at(const float* R, int m, float gamma, float slip, int s,
+                                            int f) {
   const int i2 = s % m, i1 = (s / m) % m, i0 = s / (m * m);
-  const float inv = m > 1 ? 1.0f / static_cast<float>(m - 1) : 0.f;
-  x[0] = i0 * inv;
-  x[1] = i1 * inv;
-  x[2] = i2 * inv;
-  int f = 3;
-  for (int d0 = -2; d0 <= 2; ++d0) {
-    const int j0 = min(max(i0 + d0, 0), m - 1);
-    for (int d1 = -2; d1 <= 2; ++d1) {
-      const int j1 = min(max(i1 + d1, 0), m - 1);
-      for (int d2 = -2; d2 <= 2; ++d2) {
-        const int j2 = min(max(i2 + d2, 0), m - 1);
-        x[f++] = kRScale * R[(j0 * m + j1) * m + j2];
-      }
-    }
+  if (f < 3) {
+    const float inv = m > 1 ? 1.0f / static_cast<float>(m - 1) : 0.f;
+    return (f == 0 ? i0 : (f == 1 ? i1 : i2)) * inv;
   }
-  x[128] = (gamma - kGammaMean) * kGammaScale;
-  x[129] = (slip - kSlipMean) * kSlipScale;
+  if (f == 128) return (gamma - kGammaMean) * kGammaScale;
+  if (f == 129) return (slip - kSlipMean) * kSlipScale;
+  const int j = f - 3;
+  const int j0 = min(max(i0 + j / 25 - 2, 0), m - 1);
+  const int j1 = min(max(i1 + (j / 5) % 5 - 2, 0), m - 1);
+  const int j2 = min(max(i2 + j % 5 - 2, 0), m - 1);
+  return kRScale * R[(j0 * m + j1) * m + j2];
 }
 
-// All states s0 .. s0+count-1 of one instance.
+// All states s0 .. s0+count-1 of one instance, one thread per (state,
+// feature): consecutive threads write consecutive words of X.
 __global__ void features_range_kernel(const float* R, int m, float gamma, float slip, int s0,
                                       int count, float* X) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) feature_row(R, m, gamma, slip, s0 + i, X + static_cast<int64_t>(i) * kF);
+  const int64_t total = static_cast<int64_t>(count) * kF;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < total; e += stride) {
+    const int i = static_cast<int>(e / kF), f = static_cast<int>(e - static_cast<int64_t>(i) * kF);
+    X[e] = feature_at(R, m, gamma, slip, s0 + i, f);
+  }
+}
+
+static int feature_blocks(int rows) {
+  return static_cast<int>(std::min<int64_t>((static_cast<int64_t>(rows) * kF + 255) / 256, 16384));
 }
 
 // Minibatch: sample i -> (instance, state) drawn with SplitMix64 from
 // (seed, step, i); features and the target (1 - gamma) V*(s).
+// One thread per (sample, feature); every thread of a sample draws the same
+// (instance, state), the feature-0 thread also writes the target.
 __global__ void features_sample_kernel(const float* const* R_ptrs, const double* const* V_ptrs,
                                        const double* gammas, const double* slips, int n_inst,
                                        int m, uint64_t seed, int64_t step, int count, float* X,
                                        float* t) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= count) return;
-  const uint64_t r = splitmix64(seed ^ splitmix64(static_cast<uint64_t>(step) * 0x100000001B3ull +
-                                                  static_cast<uint64_t>(i)));
+  const int64_t total = static_cast<int64_t>(count) * kF;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
   const int S = m * m * m;
-  const int inst = static_cast<int>((r >> 32) % static_cast<uint64_t>(n_inst));
-  const int s = static_cast<int>((r & 0xFFFFFFFFull) % static_cast<uint64_t>(S));
-  const float g = static_cast<float>(gammas[inst]);
-  feature_row(R_ptrs[inst], m, g, static_cast<float>(slips[inst]), s, X + static_cast<int64_t>(i) * kF);
-  t[i] = static_cast<float>(((1.0 - gammas[inst]) * V_ptrs[inst][s] - kOutMean) / kOutScale);
+  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < total; e += stride) {
+    const int i = static_cast<int>(e / kF), f = static_cast<int>(e - static_cast<int64_t>(i) * kF);
+    const uint64_t r = splitmix64(seed ^ splitmix64(static_cast<uint64_t>(step) * 0x100000001B3ull +
+                                                    static_cast<uint64_t>(i)));
+    const int inst = static_cast<int>((r >> 32) % static_cast<uint64_t>(n_inst));
+    const int s = static_cast<int>((r & 0xFFFFFFFFull) % static_cast<uint64_t>(S));
+    X[e] = feature_at(R_ptrs[inst], m, static_cast<float>(gammas[inst]),
+                      static_cast<float>(slips[inst]), s, f);
+    if (f == 0)
+      t[i] = static_cast<float>(((1.0 - gammas[inst]) * V_ptrs[inst][s] - kOutMean) / kOutScale);
+  }
 }
 
 // -------------------------------------------------------------- loss, misc
@@ -364,7 +529,7 @@ int cpmdp_mlp_features(const float* R, int32_t m, double gamma, double slip, int
       static_cast<int64_t>(s0) + count > static_cast<int64_t>(m) * m * m)
     return mfail("bad feature arguments");
   if (count == 0) return CPMDP_OK;
-  hipLaunchKernelGGL(features_range_kernel, dim3((count + 255) / 256), dim3(256), 0,
+  hipLaunchKernelGGL(features_range_kernel, dim3(feature_blocks(count)), dim3(256), 0,
                      static_cast<hipStream_t>(stream), R, m, static_cast<float>(gamma),
                      static_cast<float>(slip), s0, count, X);
   return hipGetLastError() == hipSuccess ? CPMDP_OK : fail(nullptr, CPMDP_E_DEVICE, "features launch");
@@ -424,7 +589,7 @@ int cpmdp_mlp_train_step(float* params, float* adam_m, float* adam_v, float* gra
   const hipStream_t st = static_cast<hipStream_t>(stream);
   MlpWs w = carve(ws, batch);
   hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, st, reinterpret_cast<float*>(w.loss), 2, 0.0f);
-  hipLaunchKernelGGL(features_sample_kernel, dim3((batch + 255) / 256), dim3(256), 0, st, R_ptrs,
+  hipLaunchKernelGGL(features_sample_kernel, dim3(feature_blocks(batch)), dim3(256), 0, st, R_ptrs,
                      Vstar_ptrs, gammas, slips, n_inst, m, seed, step, batch, w.X, w.t);
   forward(params, w.X, batch, w, st);
   backward(params, w.X, batch, w, grad, st);
@@ -449,7 +614,7 @@ int cpmdp_mlp_predict(const float* params, const float* R, int32_t m, double gam
   MlpWs w = carve(ws, chunk);
   for (int s0 = 0; s0 < S; s0 += chunk) {
     const int cnt = std::min(chunk, S - s0);
-    hipLaunchKernelGGL(features_range_kernel, dim3((cnt + 255) / 256), dim3(256), 0, st, R, m,
+    hipLaunchKernelGGL(features_range_kernel, dim3(feature_blocks(cnt)), dim3(256), 0, st, R, m,
                        static_cast<float>(gamma), static_cast<float>(slip), s0, cnt, w.X);
     forward(params, w.X, cnt, w, st);
     hipLaunchKernelGGL(to_values_kernel, dim3((cnt + 255) / 256), dim3(256), 0, st, w.y, cnt,

@@ -28,6 +28,7 @@ class WarmStart:
         self.grad = torch.zeros(n, dtype=torch.float32, device=device)
         B.cpmdp_mlp_init(self.params, seed)
         self.ws = torch.empty(B.cpmdp_mlp_workspace_bytes(batch), dtype=torch.uint8, device=device)
+        self.infer_ws, self.infer_chunk = None, 0     # inference workspace, sized on first use
         self.step = 0
         self.R, self.Vstar, self.gammas, self.slips = [], [], [], []
         self.solve_sweeps = []
@@ -78,15 +79,22 @@ class WarmStart:
 
     # ------------------------------------------------------------ inference
     def predict(self, inst, chunk: int | None = None):
-        """V0 (FP64, device) for one m^3 instance."""
+        """V0 (FP64, device) for one m^3 instance; by default all states in
+        one forward pass (up to 2^18 per pass), so that the forward products
+        fill the chip."""
         torch = self.torch
-        chunk = chunk or self.batch
+        chunk = chunk or min(inst.n_states, 1 << 18)
         R = torch.as_tensor(inst.rewards, dtype=torch.float32, device=self.device)
         V0 = torch.empty(inst.n_states, dtype=torch.float64, device=self.device)
-        B.cpmdp_mlp_predict(self.params, R, self.m, inst.gamma, inst.meta["slip"], V0, chunk,
-                            self.ws if chunk <= self.batch else
-                            torch.empty(B.cpmdp_mlp_workspace_bytes(chunk), dtype=torch.uint8,
-                                        device=self.device))
+        if chunk <= self.batch:
+            ws = self.ws
+        else:
+            if chunk > self.infer_chunk:
+                self.infer_ws = torch.empty(B.cpmdp_mlp_workspace_bytes(chunk), dtype=torch.uint8,
+                                            device=self.device)
+                self.infer_chunk = chunk
+            ws = self.infer_ws
+        B.cpmdp_mlp_predict(self.params, R, self.m, inst.gamma, inst.meta["slip"], V0, chunk, ws)
         return V0
 
     # ------------------------------------------------------------ checkpoint

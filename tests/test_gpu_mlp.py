@@ -55,9 +55,12 @@ def test_features_match_oracle(B, m):
     np.testing.assert_allclose(X.cpu().numpy(), ref, rtol=2e-6, atol=2e-6)
 
 
-def test_forward_and_gradient_match_oracle(B):
+# 700 rows: the 64 x 64 matrix-core tiles with a ragged tail; 32,845 rows:
+# the 128 x 128 tiles (from 32,768 rows) with a ragged tail
+@pytest.mark.parametrize("n", [700, 32845])
+def test_forward_and_gradient_match_oracle(B, n):
+    log(f"[mlp] forward + gradient rows={n}")
     rng = np.random.default_rng(4)
-    n = 700                                 # ragged against the 64-row tiles
     X = rng.normal(0, 1, (n, 130)).astype(np.float32)
     t = rng.normal(0, 1, n).astype(np.float32)
     p = _params(B, 5)
