@@ -116,24 +116,27 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, const fl
   }
 }
 
-// C[M x N] = A B (+ bias, ReLU) on the FP32 matrix cores
-// (v_mfma_f32_16x16x4f32), for the forward layers (A row-major M x K, B
-// row-major K x N).  Four waves in a 2 x 2 grid each compute WM x WN tiles of
-// 16 x 16; the block's A (BM x 16) and B (16 x BN) slices go through LDS, k
-// in steps of 16 (zero-padded past K, M and N).  The next slices are loaded
-// into registers while the matrix cores work on the current ones; a slice
-// inside the matrix is loaded without per-element guards, so that its loads
-// issue together.  Lane l = 16 g + c of one
-// 16x16x4 product supplies A[i = c][k = g] and B[k = g][n = c]; its result
-// register r holds D[i = 4 g + r][n = c].
+// C[M x N] = op(A) op(B) (+ epilogue) on the FP32 matrix cores
+// (v_mfma_f32_16x16x4f32); operands and epilogues as in gemm_kernel, split
+// over K the same way.  Four waves in a 2 x 2 grid each compute WM x WN tiles
+// of 16 x 16; the block's op(A) (BM x 16) and op(B) (16 x BN) slices go
+// through LDS, k in steps of 16 (zero-padded past K, M and N), each read from
+// global memory along its contiguous index.  The next slices are loaded into
+// registers while the matrix cores work on the current ones; a slice inside
+// the matrix is loaded without per-element guards, so that its loads issue
+// together.  Lane l = 16 g + c of one 16x16x4 product supplies
+// A[i = c][k = g] and B[k = g][n = c]; its result register r holds
+// D[i = 4 g + r][n = c].
 typedef float mlp_f4 __attribute__((ext_vector_type(4)));
 
-template <int WM, int WN, int EPI>
+template <bool TA, bool TB, int WM, int WN, int EPI>
 __global__ __launch_bounds__(256) void gemm_mfma_kernel(int M, int N, int K,
                                                         const float* __restrict__ A, int lda,
                                                         const float* __restrict__ B, int ldb,
                                                         float* __restrict__ C, int ldc,
-                                                        const float* __restrict__ bias) {
+                                                        const float* __restrict__ bias,
+                                                        const float* __restrict__ mask, int ldm,
+                                                        int kc) {
   constexpr int BM = 32 * WM, BN = 32 * WN, KT = 16;
   constexpr int LA = BM * KT / 256, LB = KT * BN / 256;   // slice words per thread
   __shared__ float As[KT][BM + 4];
@@ -142,6 +145,22 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(int M, int N, int K,
   const int g = lane >> 4, c = lane & 15;
   const int wm = wv >> 1, wn = wv & 1;
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int kb = blockIdx.z * kc, ke = min(K, kb + kc);
+  C += static_cast<int64_t>(blockIdx.z) * M * ldc;
+  // slice word i -> (row or column within the tile, k within the slice),
+  // consecutive i along the operand's contiguous index
+  auto amap = [](int i, int& r, int& kk) {
+    if (TA) { r = i % BM; kk = i / BM; } else { r = i / KT; kk = i % KT; }
+  };
+  auto bmap = [](int i, int& kk, int& cc) {
+    if (TB) { kk = i % KT; cc = i / KT; } else { kk = i / BN; cc = i % BN; }
+  };
+  auto aidx = [&](int gm, int gk) {
+    return TA ? static_cast<int64_t>(gk) * lda + gm : static_cast<int64_t>(gm) * lda + gk;
+  };
+  auto bidx = [&](int gk, int gn) {
+    return TB ? static_cast<int64_t>(gn) * ldb + gk : static_cast<int64_t>(gk) * ldb + gn;
+  };
   mlp_f4 acc[WM][WN];
 #pragma unroll
   for (int i = 0; i < WM; ++i)
@@ -149,51 +168,56 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(int M, int N, int K,
     for (int j = 0; j < WN; ++j) acc[i][j] = mlp_f4{0.f, 0.f, 0.f, 0.f};
   float ra[LA], rb[LB];
   auto fetch = [&](int k0) {
-    if (m0 + BM <= M && k0 + KT <= K) {
+    const bool ka = k0 + KT <= ke;
+    if (ka && m0 + BM <= M) {
 #pragma unroll
       for (int q = 0; q < LA; ++q) {
-        const int i = threadIdx.x + q * 256;
-        const int r = i / KT, kk = i % KT;   // 16 threads read 16 consecutive k of a row
-        ra[q] = A[static_cast<int64_t>(m0 + r) * lda + k0 + kk];
+        int r, kk;
+        amap(threadIdx.x + q * 256, r, kk);
+        ra[q] = A[aidx(m0 + r, k0 + kk)];
       }
     } else {
 #pragma unroll
       for (int q = 0; q < LA; ++q) {
-        const int i = threadIdx.x + q * 256;
-        const int r = i / KT, kk = i % KT;
+        int r, kk;
+        amap(threadIdx.x + q * 256, r, kk);
         const int gm = m0 + r, gk = k0 + kk;
-        ra[q] = (gm < M && gk < K) ? A[static_cast<int64_t>(gm) * lda + gk] : 0.f;
+        ra[q] = (gm < M && gk < ke) ? A[aidx(gm, gk)] : 0.f;
       }
     }
-    if (k0 + KT <= K && n0 + BN <= N) {
+    if (ka && n0 + BN <= N) {
 #pragma unroll
       for (int q = 0; q < LB; ++q) {
-        const int i = threadIdx.x + q * 256;
-        rb[q] = B[static_cast<int64_t>(k0 + i / BN) * ldb + n0 + i % BN];
+        int kk, cc;
+        bmap(threadIdx.x + q * 256, kk, cc);
+        rb[q] = B[bidx(k0 + kk, n0 + cc)];
       }
     } else {
 #pragma unroll
       for (int q = 0; q < LB; ++q) {
-        const int i = threadIdx.x + q * 256;
-        const int gk = k0 + i / BN, gn = n0 + i % BN;
-        rb[q] = (gk < K && gn < N) ? B[static_cast<int64_t>(gk) * ldb + gn] : 0.f;
+        int kk, cc;
+        bmap(threadIdx.x + q * 256, kk, cc);
+        const int gk = k0 + kk, gn = n0 + cc;
+        rb[q] = (gk < ke && gn < N) ? B[bidx(gk, gn)] : 0.f;
       }
     }
   };
-  fetch(0);
-  for (int k0 = 0; k0 < K; k0 += KT) {
+  if (kb < ke) fetch(kb);
+  for (int k0 = kb; k0 < ke; k0 += KT) {
 #pragma unroll
     for (int q = 0; q < LA; ++q) {
-      const int i = threadIdx.x + q * 256;
-      As[i % KT][i / KT] = ra[q];
+      int r, kk;
+      amap(threadIdx.x + q * 256, r, kk);
+      As[kk][r] = ra[q];
     }
 #pragma unroll
     for (int q = 0; q < LB; ++q) {
-      const int i = threadIdx.x + q * 256;
-      Bs[i / BN][i % BN] = rb[q];
+      int kk, cc;
+      bmap(threadIdx.x + q * 256, kk, cc);
+      Bs[kk][cc] = rb[q];
     }
     __syncthreads();
-    if (k0 + KT < K) fetch(k0 + KT);
+    if (k0 + KT < ke) fetch(k0 + KT);
 #pragma unroll
     for (int ks = 0; ks < KT; ks += 4) {
       float a[WM], b[WN];
@@ -221,6 +245,7 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(int M, int N, int K,
         float v = acc[i][j][r];
         if (EPI == EPI_BIAS || EPI == EPI_BIAS_RELU) v += bias[gn];
         if (EPI == EPI_BIAS_RELU) v = fmaxf(v, 0.f);
+        if (EPI == EPI_MASK) v = mask[static_cast<int64_t>(gm) * ldm + gn] > 0.f ? v : 0.f;
         C[static_cast<int64_t>(gm) * ldc + gn] = v;
       }
     }
@@ -276,21 +301,13 @@ static void gemm(int M, int N, int K, const float* A, int lda, const float* B, i
     hipLaunchKernelGGL(gemv_bias_kernel, dim3(blocks), dim3(256), 0, st, M, K, A, lda, B, bias, C);
     return;
   }
-  if (!TA && !TB && (EPI == EPI_BIAS || EPI == EPI_BIAS_RELU) && N >= 64) {
-    // forward layers: matrix cores, 128 x 128 tiles when there are enough
-    // rows to fill the chip with them, else 64 x 64
-    if (M >= 32768) {
-      const dim3 grid((N + 127) / 128, (M + 127) / 128);
-      hipLaunchKernelGGL((gemm_mfma_kernel<4, 4, EPI>), grid, dim3(256), 0, st, M, N, K, A, lda, B,
-                         ldb, C, ldc, bias);
-    } else {
-      const dim3 grid((N + 63) / 64, (M + 63) / 64);
-      hipLaunchKernelGGL((gemm_mfma_kernel<2, 2, EPI>), grid, dim3(256), 0, st, M, N, K, A, lda, B,
-                         ldb, C, ldc, bias);
-    }
-    return;
-  }
-  const int tiles = ((N + 63) / 64) * ((M + 63) / 64);
+  // matrix cores for every product with at least 64 rows, 64 columns and a
+  // 16-deep k (128 x 128 tiles for the large forward products, else 64 x 64);
+  // the rest (bias gradients, rank-1 updates) on the vector tile kernel
+  const bool mfma = M >= 64 && N >= 64 && K >= 16;
+  const bool big = mfma && !TA && M >= 32768;
+  const int TM = big ? 128 : 64, TN = big ? 128 : 64;
+  const int tiles = ((N + TN - 1) / TN) * ((M + TM - 1) / TM);
   int ks = 1;
   if (EPI == EPI_NONE && part && tiles < 64 && K >= 2048 && ldc == N) {
     ks = 256 / tiles;
@@ -298,17 +315,24 @@ static void gemm(int M, int N, int K, const float* A, int lda, const float* B, i
     if (ks > K / 128) ks = K / 128;
     if (static_cast<int64_t>(ks) * M * N > kSplitWords) ks = static_cast<int>(kSplitWords / (M * N));
   }
+  auto launch = [&](dim3 grid, float* out, int ldo, int kc) {
+    if (big)
+      hipLaunchKernelGGL((gemm_mfma_kernel<TA, TB, 4, 4, EPI>), grid, dim3(256), 0, st, M, N, K, A,
+                         lda, B, ldb, out, ldo, bias, mask, ldm, kc);
+    else if (mfma)
+      hipLaunchKernelGGL((gemm_mfma_kernel<TA, TB, 2, 2, EPI>), grid, dim3(256), 0, st, M, N, K, A,
+                         lda, B, ldb, out, ldo, bias, mask, ldm, kc);
+    else
+      hipLaunchKernelGGL((gemm_kernel<TA, TB, EPI>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb,
+                         out, ldo, bias, mask, ldm, kc);
+  };
   if (ks <= 1) {
-    const dim3 grid((N + 63) / 64, (M + 63) / 64);
-    hipLaunchKernelGGL((gemm_kernel<TA, TB, EPI>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb,
-                       C, ldc, bias, mask, ldm, K);
+    launch(dim3((N + TN - 1) / TN, (M + TM - 1) / TM), C, ldc, K);
     return;
   }
   const int kc = ((K + ks - 1) / ks + 15) & ~15;
   ks = (K + kc - 1) / kc;
-  const dim3 grid((N + 63) / 64, (M + 63) / 64, ks);
-  hipLaunchKernelGGL((gemm_kernel<TA, TB, EPI>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb,
-                     part, N, bias, mask, ldm, kc);
+  launch(dim3((N + TN - 1) / TN, (M + TM - 1) / TM, ks), part, N, kc);
   const int len = M * N;
   hipLaunchKernelGGL(split_sum_kernel, dim3((len + 255) / 256), dim3(256), 0, st,
                      static_cast<const float*>(part), ks, len, C);
