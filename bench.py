@@ -757,8 +757,8 @@ def bench_warm(args):
                          "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                          "frac": step_flops / (step_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS,
                          "traffic": None,
-                         "kernel": "one MLP train step (feature gather, 3 forward and 5 backward "
-                                   "GEMMs, loss, Adam) on 4096 sampled states, events around "
+                         "kernel": "one MLP train step (feature gather, 3 forward and 8 backward "
+                                   "products, loss, Adam) on 4096 sampled states, events around "
                                    "all training steps on the library's stream",
                          "kernel_ms": step_ms, "algorithmic_flops_per_launch": step_flops}}
 
