@@ -731,7 +731,7 @@ def bench_warm(args):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for x, V in zip(test, Vs):
-            V.copy_(w.predict(x))
+            V.copy_(w.predict(x, bf16=True))
         code, sw, res = B.cpmdp_batch_solve(bm.b, Vs, None, eps, 100000, B.CPMDP_FP32, 0)
         torch.cuda.synchronize()
         if step == args.warmup:

@@ -467,9 +467,12 @@ int cpmdp_mlp_init(float* params, uint64_t seed, void* stream);
  * [m^3] (FP32). */
 int cpmdp_mlp_features(const float* R, int32_t m, double gamma, double slip, int32_t s0,
                        int32_t count, float* X, void* stream);
-/* y [count] = MLP(X). */
-int cpmdp_mlp_forward(const float* params, const float* X, int32_t count, float* y, void* ws,
-                      size_t ws_bytes, void* stream);
+/* y [count] = MLP(X).  precision: CPMDP_FP32 (every product in FP32) or
+ * CPMDP_BF16 (the two hidden-layer products take BF16 operands, rounded to
+ * nearest even, on the matrix cores with FP32 accumulation, bias and ReLU;
+ * the output layer stays FP32); other values: CPMDP_E_ARG. */
+int cpmdp_mlp_forward(const float* params, const float* X, int32_t count, float* y,
+                      int32_t precision, void* ws, size_t ws_bytes, void* stream);
 /* Gradient of mean((MLP(X) - t)^2) into grad [99,585]; loss_out (nullable,
  * synchronizes the stream). */
 int cpmdp_mlp_loss_grad(const float* params, const float* X, const float* t, int32_t count,
@@ -489,9 +492,10 @@ int cpmdp_mlp_train_step(float* params, float* adam_m, float* adam_v, float* gra
                          int32_t batch, uint64_t seed, double lr, void* ws, size_t ws_bytes,
                          void* stream, double* loss_out);
 /* V0 [m^3] (FP64) = MLP prediction / (1 - gamma), in chunks of `chunk`
- * states (workspace sized for chunk). */
+ * states (workspace sized for chunk); precision as in cpmdp_mlp_forward. */
 int cpmdp_mlp_predict(const float* params, const float* R, int32_t m, double gamma, double slip,
-                      double* V0, int32_t chunk, void* ws, size_t ws_bytes, void* stream);
+                      double* V0, int32_t chunk, int32_t precision, void* ws, size_t ws_bytes,
+                      void* stream);
 
 #ifdef __cplusplus
 }

@@ -91,14 +91,14 @@ _SIGS = {
     "cpmdp_mlp_init": (C.c_int, [_p, C.c_uint64, _p]),
     "cpmdp_mlp_features": (C.c_int, [_p, C.c_int32, C.c_double, C.c_double, C.c_int32,
                                      C.c_int32, _p, _p]),
-    "cpmdp_mlp_forward": (C.c_int, [_p, _p, C.c_int32, _p, _p, C.c_size_t, _p]),
+    "cpmdp_mlp_forward": (C.c_int, [_p, _p, C.c_int32, _p, C.c_int32, _p, C.c_size_t, _p]),
     "cpmdp_mlp_loss_grad": (C.c_int, [_p, _p, _p, C.c_int32, _p, _dp, _p, C.c_size_t, _p]),
     "cpmdp_mlp_adam": (C.c_int, [_p, _p, _p, _p, C.c_int64, C.c_double, _p]),
     "cpmdp_mlp_train_step": (C.c_int, [_p, _p, _p, _p, C.c_int64, _p, _p, _p, _p, C.c_int32,
                                        C.c_int32, C.c_int32, C.c_uint64, C.c_double, _p,
                                        C.c_size_t, _p, _dp]),
     "cpmdp_mlp_predict": (C.c_int, [_p, _p, C.c_int32, C.c_double, C.c_double, _p, C.c_int32,
-                                    _p, C.c_size_t, _p]),
+                                    C.c_int32, _p, C.c_size_t, _p]),
 }
 
 EXPORTED = sorted(_SIGS)
@@ -484,9 +484,10 @@ def cpmdp_mlp_features(R, m, gamma, slip, s0, count, X, stream=None):
                                          int(count), _ptr(X), _stream_ptr(stream)))
 
 
-def cpmdp_mlp_forward(params, X, count, y, ws, stream=None):
-    return _check(lib.cpmdp_mlp_forward(_ptr(params), _ptr(X), int(count), _ptr(y), _ptr(ws),
-                                        ws.numel() * ws.element_size(), _stream_ptr(stream)))
+def cpmdp_mlp_forward(params, X, count, y, ws, stream=None, precision=CPMDP_FP32):
+    return _check(lib.cpmdp_mlp_forward(_ptr(params), _ptr(X), int(count), _ptr(y), int(precision),
+                                        _ptr(ws), ws.numel() * ws.element_size(),
+                                        _stream_ptr(stream)))
 
 
 def cpmdp_mlp_loss_grad(params, X, t, count, grad, ws, stream=None):
@@ -513,7 +514,8 @@ def cpmdp_mlp_train_step(params, adam_m, adam_v, grad, step, R_ptrs, V_ptrs, gam
     return loss.value if want_loss else None
 
 
-def cpmdp_mlp_predict(params, R, m, gamma, slip, V0, chunk, ws, stream=None):
+def cpmdp_mlp_predict(params, R, m, gamma, slip, V0, chunk, ws, stream=None,
+                      precision=CPMDP_FP32):
     return _check(lib.cpmdp_mlp_predict(_ptr(params), _ptr(R), int(m), float(gamma), float(slip),
-                                        _ptr(V0), int(chunk), _ptr(ws),
+                                        _ptr(V0), int(chunk), int(precision), _ptr(ws),
                                         ws.numel() * ws.element_size(), _stream_ptr(stream)))

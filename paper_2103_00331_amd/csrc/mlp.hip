@@ -251,6 +251,115 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(int M, int N, int K,
     }
 }
 
+// C[M x N] = A B + bias (+ ReLU) with BF16 operands on the matrix cores
+// (v_mfma_f32_16x16x16bf16_1k), FP32 accumulation and epilogue: the hidden
+// layers of a BF16 forward pass (A row-major M x K, B row-major K x N).
+// Tiles, staging and prefetch as in gemm_mfma_kernel; the FP32 slices are
+// rounded to BF16 (round to nearest even) on their way to LDS, stored with
+// k contiguous per row of A and per column of B, so that lane l = 16 g + c
+// reads its 4 operands A[i = c][k = 4g .. 4g+3] and B[k = 4g .. 4g+3][n = c]
+// as one 8-byte word; its result register r holds D[i = 4 g + r][n = c].
+typedef short mlp_s4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short to_bf16(float x) {
+  return __builtin_bit_cast(unsigned short, static_cast<__bf16>(x));
+}
+
+template <int WM, int WN, int EPI>
+__global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K,
+                                                        const float* __restrict__ A, int lda,
+                                                        const float* __restrict__ B, int ldb,
+                                                        float* __restrict__ C, int ldc,
+                                                        const float* __restrict__ bias) {
+  constexpr int BM = 32 * WM, BN = 32 * WN, KT = 16, KP = KT + 4;   // KP: padded k stride
+  constexpr int LA = BM * KT / 256, LB = KT * BN / 256;
+  __shared__ __align__(16) unsigned short As[BM][KP];
+  __shared__ __align__(16) unsigned short Bs[BN][KP];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int g = lane >> 4, c = lane & 15;
+  const int wm = wv >> 1, wn = wv & 1;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  mlp_f4 acc[WM][WN];
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j) acc[i][j] = mlp_f4{0.f, 0.f, 0.f, 0.f};
+  float ra[LA], rb[LB];
+  auto fetch = [&](int k0) {
+    const bool ka = k0 + KT <= K;
+    if (ka && m0 + BM <= M) {
+#pragma unroll
+      for (int q = 0; q < LA; ++q) {
+        const int i = threadIdx.x + q * 256;
+        ra[q] = A[static_cast<int64_t>(m0 + i / KT) * lda + k0 + i % KT];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < LA; ++q) {
+        const int i = threadIdx.x + q * 256;
+        const int gm = m0 + i / KT, gk = k0 + i % KT;
+        ra[q] = (gm < M && gk < K) ? A[static_cast<int64_t>(gm) * lda + gk] : 0.f;
+      }
+    }
+    if (ka && n0 + BN <= N) {
+#pragma unroll
+      for (int q = 0; q < LB; ++q) {
+        const int i = threadIdx.x + q * 256;
+        rb[q] = B[static_cast<int64_t>(k0 + i / BN) * ldb + n0 + i % BN];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < LB; ++q) {
+        const int i = threadIdx.x + q * 256;
+        const int gk = k0 + i / BN, gn = n0 + i % BN;
+        rb[q] = (gk < K && gn < N) ? B[static_cast<int64_t>(gk) * ldb + gn] : 0.f;
+      }
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < K; k0 += KT) {
+#pragma unroll
+    for (int q = 0; q < LA; ++q) {
+      const int i = threadIdx.x + q * 256;
+      As[i / KT][i % KT] = to_bf16(ra[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < LB; ++q) {
+      const int i = threadIdx.x + q * 256;
+      Bs[i % BN][i / BN] = to_bf16(rb[q]);
+    }
+    __syncthreads();
+    if (k0 + KT < K) fetch(k0 + KT);
+    mlp_s4 a[WM], b[WN];
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+      a[i] = *reinterpret_cast<const mlp_s4*>(&As[(wm * WM + i) * 16 + c][4 * g]);
+#pragma unroll
+    for (int j = 0; j < WN; ++j)
+      b[j] = *reinterpret_cast<const mlp_s4*>(&Bs[(wn * WN + j) * 16 + c][4 * g]);
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+      for (int j = 0; j < WN; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j) {
+      const int gn = n0 + (wn * WN + j) * 16 + c;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + (wm * WM + i) * 16 + 4 * g + r;
+        if (gm >= M || gn >= N) continue;
+        float v = acc[i][j][r] + bias[gn];
+        if (EPI == EPI_BIAS_RELU) v = fmaxf(v, 0.f);
+        C[static_cast<int64_t>(gm) * ldc + gn] = v;
+      }
+    }
+}
+
 // y[i] = A[i, :] w + b (the output layer, N = 1): one wave per row, each
 // lane a 16-byte piece of the row (rows 16-byte aligned, K % 4 == 0), then a
 // butterfly sum across the wave.
@@ -496,9 +605,25 @@ MlpWs carve(void* ws, int B) {
   return w;
 }
 
-void forward(const float* P, const float* X, int B, const MlpWs& w, hipStream_t st) {
-  gemm<false, false, EPI_BIAS_RELU>(B, kH, kF, X, kF, P + kOffW1, kH, w.H1, kH, P + kOffB1, nullptr, 0, st);
-  gemm<false, false, EPI_BIAS_RELU>(B, kH, kH, w.H1, kH, P + kOffW2, kH, w.H2, kH, P + kOffB2, nullptr, 0, st);
+// A hidden layer with BF16 operands (FP32 accumulation, bias and ReLU).
+static void hidden_bf16(int M, int K, const float* A, int lda, const float* W, const float* b,
+                        float* H, hipStream_t st) {
+  if (M >= 32768)
+    hipLaunchKernelGGL((gemm_bf16_kernel<4, 4, EPI_BIAS_RELU>), dim3(kH / 128, (M + 127) / 128),
+                       dim3(256), 0, st, M, kH, K, A, lda, W, kH, H, kH, b);
+  else
+    hipLaunchKernelGGL((gemm_bf16_kernel<2, 2, EPI_BIAS_RELU>), dim3(kH / 64, (M + 63) / 64),
+                       dim3(256), 0, st, M, kH, K, A, lda, W, kH, H, kH, b);
+}
+
+void forward(const float* P, const float* X, int B, const MlpWs& w, hipStream_t st, bool bf16) {
+  if (bf16) {
+    hidden_bf16(B, kF, X, kF, P + kOffW1, P + kOffB1, w.H1, st);
+    hidden_bf16(B, kH, w.H1, kH, P + kOffW2, P + kOffB2, w.H2, st);
+  } else {
+    gemm<false, false, EPI_BIAS_RELU>(B, kH, kF, X, kF, P + kOffW1, kH, w.H1, kH, P + kOffB1, nullptr, 0, st);
+    gemm<false, false, EPI_BIAS_RELU>(B, kH, kH, w.H1, kH, P + kOffW2, kH, w.H2, kH, P + kOffB2, nullptr, 0, st);
+  }
   gemm<false, false, EPI_BIAS>(B, 1, kH, w.H2, kH, P + kOffW3, 1, w.y, 1, P + kOffB3, nullptr, 0, st);
 }
 
@@ -559,13 +684,15 @@ int cpmdp_mlp_features(const float* R, int32_t m, double gamma, double slip, int
   return hipGetLastError() == hipSuccess ? CPMDP_OK : fail(nullptr, CPMDP_E_DEVICE, "features launch");
 }
 
-int cpmdp_mlp_forward(const float* params, const float* X, int32_t count, float* y, void* ws,
-                      size_t ws_bytes, void* stream) {
+int cpmdp_mlp_forward(const float* params, const float* X, int32_t count, float* y,
+                      int32_t precision, void* ws, size_t ws_bytes, void* stream) {
   if (!params || !X || !y || !ws || count < 1) return mfail("bad forward arguments");
+  if (precision != CPMDP_FP32 && precision != CPMDP_BF16)
+    return mfail("precision must be CPMDP_FP32 or CPMDP_BF16");
   if (ws_bytes < mlp_ws_bytes(count)) return fail(nullptr, CPMDP_E_WORKSPACE, "MLP workspace too small");
   const hipStream_t st = static_cast<hipStream_t>(stream);
   MlpWs w = carve(ws, count);
-  forward(params, X, count, w, st);
+  forward(params, X, count, w, st, precision == CPMDP_BF16);
   (void)hipMemcpyAsync(y, w.y, count * 4, hipMemcpyDeviceToDevice, st);
   return hipGetLastError() == hipSuccess ? CPMDP_OK : fail(nullptr, CPMDP_E_DEVICE, "forward launch");
 }
@@ -578,7 +705,7 @@ int cpmdp_mlp_loss_grad(const float* params, const float* X, const float* t, int
   MlpWs w = carve(ws, count);
   (void)hipMemcpyAsync(w.t, t, count * 4, hipMemcpyDeviceToDevice, st);
   hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, st, reinterpret_cast<float*>(w.loss), 2, 0.0f);
-  forward(params, X, count, w, st);
+  forward(params, X, count, w, st, false);
   backward(params, X, count, w, grad, st);
   if (hipGetLastError() != hipSuccess) return fail(nullptr, CPMDP_E_DEVICE, "loss_grad launch");
   if (loss_out) {
@@ -615,7 +742,7 @@ int cpmdp_mlp_train_step(float* params, float* adam_m, float* adam_v, float* gra
   hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, st, reinterpret_cast<float*>(w.loss), 2, 0.0f);
   hipLaunchKernelGGL(features_sample_kernel, dim3(feature_blocks(batch)), dim3(256), 0, st, R_ptrs,
                      Vstar_ptrs, gammas, slips, n_inst, m, seed, step, batch, w.X, w.t);
-  forward(params, w.X, batch, w, st);
+  forward(params, w.X, batch, w, st, false);
   backward(params, w.X, batch, w, grad, st);
   int rc = cpmdp_mlp_adam(params, adam_m, adam_v, grad, step, lr, stream);
   if (rc) return rc;
@@ -629,9 +756,12 @@ int cpmdp_mlp_train_step(float* params, float* adam_m, float* adam_v, float* gra
 }
 
 int cpmdp_mlp_predict(const float* params, const float* R, int32_t m, double gamma, double slip,
-                      double* V0, int32_t chunk, void* ws, size_t ws_bytes, void* stream) {
+                      double* V0, int32_t chunk, int32_t precision, void* ws, size_t ws_bytes,
+                      void* stream) {
   if (!params || !R || !V0 || m < 1 || chunk < 1 || !ws || !(gamma < 1.0))
     return mfail("bad predict arguments");
+  if (precision != CPMDP_FP32 && precision != CPMDP_BF16)
+    return mfail("precision must be CPMDP_FP32 or CPMDP_BF16");
   if (ws_bytes < mlp_ws_bytes(chunk)) return fail(nullptr, CPMDP_E_WORKSPACE, "MLP workspace too small");
   const hipStream_t st = static_cast<hipStream_t>(stream);
   const int S = m * m * m;
@@ -640,7 +770,7 @@ int cpmdp_mlp_predict(const float* params, const float* R, int32_t m, double gam
     const int cnt = std::min(chunk, S - s0);
     hipLaunchKernelGGL(features_range_kernel, dim3(feature_blocks(cnt)), dim3(256), 0, st, R, m,
                        static_cast<float>(gamma), static_cast<float>(slip), s0, cnt, w.X);
-    forward(params, w.X, cnt, w, st);
+    forward(params, w.X, cnt, w, st, precision == CPMDP_BF16);
     hipLaunchKernelGGL(to_values_kernel, dim3((cnt + 255) / 256), dim3(256), 0, st, w.y, cnt,
                        1.0 / (1.0 - gamma), V0 + s0);
   }

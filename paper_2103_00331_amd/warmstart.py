@@ -78,10 +78,11 @@ class WarmStart:
         return losses
 
     # ------------------------------------------------------------ inference
-    def predict(self, inst, chunk: int | None = None):
+    def predict(self, inst, chunk: int | None = None, bf16: bool = False):
         """V0 (FP64, device) for one m^3 instance; by default all states in
         one forward pass (up to 2^18 per pass), so that the forward products
-        fill the chip."""
+        fill the chip.  bf16: hidden layers with BF16 operands (FP32
+        accumulation)."""
         torch = self.torch
         chunk = chunk or min(inst.n_states, 1 << 18)
         R = torch.as_tensor(inst.rewards, dtype=torch.float32, device=self.device)
@@ -94,7 +95,8 @@ class WarmStart:
                                             device=self.device)
                 self.infer_chunk = chunk
             ws = self.infer_ws
-        B.cpmdp_mlp_predict(self.params, R, self.m, inst.gamma, inst.meta["slip"], V0, chunk, ws)
+        B.cpmdp_mlp_predict(self.params, R, self.m, inst.gamma, inst.meta["slip"], V0, chunk, ws,
+                            precision=B.CPMDP_BF16 if bf16 else B.CPMDP_FP32)
         return V0
 
     # ------------------------------------------------------------ checkpoint

@@ -276,3 +276,12 @@ def test_cp_fit_rejects_before_device_work():
         with pytest.raises(B.CpmdpError) as e:
             B.cpmdp_cp_fit_workspace_bytes(sizes, nnz, rank)
         assert e.value.code == code
+
+
+def test_mlp_precision_rejected():
+    # argument checks run before any device work: host buffers stand in
+    buf = np.zeros(16, np.float32)
+    p = buf.ctypes.data
+    assert B.lib.cpmdp_mlp_forward(p, p, 4, p, 5, p, 64, None) == B.CPMDP_E_ARG
+    assert B.lib.cpmdp_mlp_forward(p, p, 4, p, B.CPMDP_FP64, p, 64, None) == B.CPMDP_E_ARG
+    assert B.lib.cpmdp_mlp_predict(p, p, 4, 0.9, 0.1, p, 64, 9, p, 64, None) == B.CPMDP_E_ARG

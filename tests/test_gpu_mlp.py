@@ -93,6 +93,41 @@ def _slices():
     return out
 
 
+def _bf16(a):
+    """Round float32 values to the nearest BF16 (ties to even), as float64."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+# The BF16 forward pass against the oracle's forward pass on BF16-rounded
+# operands (features, W1, W2 and the hidden activations H1): what remains is
+# FP32 accumulation and the rare H1 value whose FP32 sum rounds to the other
+# BF16 neighbour, far below the BF16 rounding itself.
+@pytest.mark.parametrize("n", [700, 32845])
+def test_forward_bf16_matches_rounded_oracle(B, n):
+    log(f"[mlp] bf16 forward rows={n}")
+    rng = np.random.default_rng(6)
+    X = rng.normal(0, 1, (n, 130)).astype(np.float32)
+    p = _params(B, 7)
+    p += 0.05 * torch.randn(p.numel(), device="cuda", generator=torch.Generator("cuda").manual_seed(2))
+    q = OM.unpack(p.cpu().numpy().astype(np.float64))
+    ws = _ws(B, n)
+    y = torch.empty(n, dtype=torch.float32, device="cuda")
+    B.cpmdp_mlp_forward(p, torch.as_tensor(X, device="cuda"), n, y, ws, precision=B.CPMDP_BF16)
+    y32 = torch.empty_like(y)
+    B.cpmdp_mlp_forward(p, torch.as_tensor(X, device="cuda"), n, y32, ws)
+    torch.cuda.synchronize()
+    f32 = lambda a: a.astype(np.float32)
+    H1 = np.maximum(_bf16(X) @ _bf16(f32(q["W1"])) + q["b1"], 0.0)
+    H2 = np.maximum(_bf16(f32(H1)) @ _bf16(f32(q["W2"])) + q["b2"], 0.0)
+    y_ref = H2 @ q["w3"] + q["b3"][0]
+    scale = np.abs(y_ref).max()
+    np.testing.assert_allclose(y.cpu().numpy(), y_ref, rtol=0, atol=2e-3 * scale)
+    # and it is a BF16 result: farther from the FP32 pass than FP32 rounding
+    assert np.abs(y.cpu().numpy() - y32.cpu().numpy()).max() > 1e-5 * scale
+
+
 def test_train_step_matches_oracle(B):
     """One training step (SplitMix64 sampling, features, forward, backward,
     Adam) against the oracle reproducing the same samples."""
