@@ -251,30 +251,39 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(int M, int N, int K,
     }
 }
 
-// C[M x N] = A B + bias (+ ReLU) with BF16 operands on the matrix cores
-// (v_mfma_f32_16x16x16bf16_1k), FP32 accumulation and epilogue: the hidden
-// layers of a BF16 forward pass (A row-major M x K, B row-major K x N).
-// Tiles, staging and prefetch as in gemm_mfma_kernel; the FP32 slices are
-// rounded to BF16 (round to nearest even) on their way to LDS, stored with
-// k contiguous per row of A and per column of B, so that lane l = 16 g + c
-// reads its 4 operands A[i = c][k = 4g .. 4g+3] and B[k = 4g .. 4g+3][n = c]
-// as one 8-byte word; its result register r holds D[i = 4 g + r][n = c].
+// A hidden layer of the BF16 forward pass on the matrix cores
+// (v_mfma_f32_16x16x16bf16_1k): relu(A B + bias) with BF16 operands, FP32
+// accumulation, bias and ReLU (A row-major M x K, B = the layer's FP32
+// weights, row-major K x N).  A is FP32 (the features; rounded to BF16, to
+// nearest even, on its way to LDS) or already BF16 (IN16: the first hidden
+// layer's output).  OUT16: the result is stored as BF16.  FUSE: the result
+// is not stored; instead each row's dot product with the output weights w3
+// over the block's columns goes to ypart[(blockIdx.x * 2 + wave column) * M
+// + row] (the output layer, summed by sum_parts_kernel).  Tiles, staging and
+// prefetch as in gemm_mfma_kernel; LDS holds k contiguous per row of A and
+// per column of B, so that lane l = 16 g + c reads its 4 operands
+// A[i = c][k = 4g .. 4g+3] and B[k = 4g .. 4g+3][n = c] as one 8-byte word;
+// its result register r holds D[i = 4 g + r][n = c].
 typedef short mlp_s4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ unsigned short to_bf16(float x) {
   return __builtin_bit_cast(unsigned short, static_cast<__bf16>(x));
 }
 
-template <int WM, int WN, int EPI>
+template <int WM, int WN, bool IN16, bool OUT16, bool FUSE>
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K,
-                                                        const float* __restrict__ A, int lda,
+                                                        const void* __restrict__ Av, int lda,
                                                         const float* __restrict__ B, int ldb,
-                                                        float* __restrict__ C, int ldc,
-                                                        const float* __restrict__ bias) {
+                                                        void* __restrict__ Cv, int ldc,
+                                                        const float* __restrict__ bias,
+                                                        const float* __restrict__ w3,
+                                                        float* __restrict__ ypart) {
   constexpr int BM = 32 * WM, BN = 32 * WN, KT = 16, KP = KT + 4;   // KP: padded k stride
   constexpr int LA = BM * KT / 256, LB = KT * BN / 256;
   __shared__ __align__(16) unsigned short As[BM][KP];
   __shared__ __align__(16) unsigned short Bs[BN][KP];
+  const float* A32 = static_cast<const float*>(Av);
+  const unsigned short* A16 = static_cast<const unsigned short*>(Av);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int g = lane >> 4, c = lane & 15;
   const int wm = wv >> 1, wn = wv & 1;
@@ -285,20 +294,26 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K,
 #pragma unroll
     for (int j = 0; j < WN; ++j) acc[i][j] = mlp_f4{0.f, 0.f, 0.f, 0.f};
   float ra[LA], rb[LB];
+  unsigned short ra16[LA];
   auto fetch = [&](int k0) {
     const bool ka = k0 + KT <= K;
     if (ka && m0 + BM <= M) {
 #pragma unroll
       for (int q = 0; q < LA; ++q) {
         const int i = threadIdx.x + q * 256;
-        ra[q] = A[static_cast<int64_t>(m0 + i / KT) * lda + k0 + i % KT];
+        const int64_t e = static_cast<int64_t>(m0 + i / KT) * lda + k0 + i % KT;
+        if (IN16) ra16[q] = A16[e];
+        else ra[q] = A32[e];
       }
     } else {
 #pragma unroll
       for (int q = 0; q < LA; ++q) {
         const int i = threadIdx.x + q * 256;
         const int gm = m0 + i / KT, gk = k0 + i % KT;
-        ra[q] = (gm < M && gk < K) ? A[static_cast<int64_t>(gm) * lda + gk] : 0.f;
+        const bool in = gm < M && gk < K;
+        const int64_t e = static_cast<int64_t>(gm) * lda + gk;
+        if (IN16) ra16[q] = in ? A16[e] : static_cast<unsigned short>(0);
+        else ra[q] = in ? A32[e] : 0.f;
       }
     }
     if (ka && n0 + BN <= N) {
@@ -321,7 +336,7 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K,
 #pragma unroll
     for (int q = 0; q < LA; ++q) {
       const int i = threadIdx.x + q * 256;
-      As[i / KT][i % KT] = to_bf16(ra[q]);
+      As[i / KT][i % KT] = IN16 ? ra16[q] : to_bf16(ra[q]);
     }
 #pragma unroll
     for (int q = 0; q < LB; ++q) {
@@ -344,6 +359,36 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K,
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
     __syncthreads();
   }
+  if (FUSE) {
+    // rows 4g + r of tile i: dot with w3 over this lane's columns, then over
+    // the 16 lanes of the group (xor 1 .. 8 stays inside the group)
+    float part[WM][4];
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) part[i][r] = 0.f;
+#pragma unroll
+    for (int j = 0; j < WN; ++j) {
+      const int gn = n0 + (wn * WN + j) * 16 + c;
+      if (gn >= N) continue;
+      const float bn = bias[gn], wo = w3[gn];
+#pragma unroll
+      for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) part[i][r] = fmaf(fmaxf(acc[i][j][r] + bn, 0.f), wo, part[i][r]);
+    }
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        float v = part[i][r];
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) v += __shfl_xor(v, off);
+        const int gm = m0 + (wm * WM + i) * 16 + 4 * g + r;
+        if (c == 0 && gm < M) ypart[static_cast<int64_t>(blockIdx.x * 2 + wn) * M + gm] = v;
+      }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < WM; ++i)
 #pragma unroll
@@ -353,11 +398,22 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K,
       for (int r = 0; r < 4; ++r) {
         const int gm = m0 + (wm * WM + i) * 16 + 4 * g + r;
         if (gm >= M || gn >= N) continue;
-        float v = acc[i][j][r] + bias[gn];
-        if (EPI == EPI_BIAS_RELU) v = fmaxf(v, 0.f);
-        C[static_cast<int64_t>(gm) * ldc + gn] = v;
+        const float v = fmaxf(acc[i][j][r] + bias[gn], 0.f);
+        const int64_t e = static_cast<int64_t>(gm) * ldc + gn;
+        if (OUT16) static_cast<unsigned short*>(Cv)[e] = to_bf16(v);
+        else static_cast<float*>(Cv)[e] = v;
       }
     }
+}
+
+// y[i] = b + sum over p < np of part[p * M + i], p in increasing order.
+__global__ __launch_bounds__(256) void sum_parts_kernel(const float* part, int np, int M,
+                                                        const float* b, float* y) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= M) return;
+  float s = 0.f;
+  for (int p = 0; p < np; ++p) s += part[static_cast<int64_t>(p) * M + i];
+  y[i] = s + b[0];
 }
 
 // y[i] = A[i, :] w + b (the output layer, N = 1): one wave per row, each
@@ -605,25 +661,39 @@ MlpWs carve(void* ws, int B) {
   return w;
 }
 
-// A hidden layer with BF16 operands (FP32 accumulation, bias and ReLU).
-static void hidden_bf16(int M, int K, const float* A, int lda, const float* W, const float* b,
-                        float* H, hipStream_t st) {
-  if (M >= 32768)
-    hipLaunchKernelGGL((gemm_bf16_kernel<4, 4, EPI_BIAS_RELU>), dim3(kH / 128, (M + 127) / 128),
-                       dim3(256), 0, st, M, kH, K, A, lda, W, kH, H, kH, b);
-  else
-    hipLaunchKernelGGL((gemm_bf16_kernel<2, 2, EPI_BIAS_RELU>), dim3(kH / 64, (M + 63) / 64),
-                       dim3(256), 0, st, M, kH, K, A, lda, W, kH, H, kH, b);
+// BF16 forward pass: first hidden layer stored as BF16 (in H1's space), the
+// second fused with the output layer (row partials in H2's space).
+static void forward_bf16(const float* P, const float* X, int M, const MlpWs& w, hipStream_t st) {
+  float* ypart = w.H2;
+  if (M >= 32768) {
+    const dim3 grid(kH / 128, (M + 127) / 128);
+    hipLaunchKernelGGL((gemm_bf16_kernel<4, 4, false, true, false>), grid, dim3(256), 0, st, M, kH,
+                       kF, static_cast<const void*>(X), kF, P + kOffW1, kH, static_cast<void*>(w.H1),
+                       kH, P + kOffB1, nullptr, nullptr);
+    hipLaunchKernelGGL((gemm_bf16_kernel<4, 4, true, false, true>), grid, dim3(256), 0, st, M, kH,
+                       kH, static_cast<const void*>(w.H1), kH, P + kOffW2, kH, nullptr, 0, P + kOffB2,
+                       P + kOffW3, ypart);
+  } else {
+    const dim3 grid(kH / 64, (M + 63) / 64);
+    hipLaunchKernelGGL((gemm_bf16_kernel<2, 2, false, true, false>), grid, dim3(256), 0, st, M, kH,
+                       kF, static_cast<const void*>(X), kF, P + kOffW1, kH, static_cast<void*>(w.H1),
+                       kH, P + kOffB1, nullptr, nullptr);
+    hipLaunchKernelGGL((gemm_bf16_kernel<2, 2, true, false, true>), grid, dim3(256), 0, st, M, kH,
+                       kH, static_cast<const void*>(w.H1), kH, P + kOffW2, kH, nullptr, 0, P + kOffB2,
+                       P + kOffW3, ypart);
+  }
+  const int np = 2 * (M >= 32768 ? kH / 128 : kH / 64);
+  hipLaunchKernelGGL(sum_parts_kernel, dim3((M + 255) / 256), dim3(256), 0, st,
+                     static_cast<const float*>(ypart), np, M, P + kOffB3, w.y);
 }
 
 void forward(const float* P, const float* X, int B, const MlpWs& w, hipStream_t st, bool bf16) {
   if (bf16) {
-    hidden_bf16(B, kF, X, kF, P + kOffW1, P + kOffB1, w.H1, st);
-    hidden_bf16(B, kH, w.H1, kH, P + kOffW2, P + kOffB2, w.H2, st);
-  } else {
-    gemm<false, false, EPI_BIAS_RELU>(B, kH, kF, X, kF, P + kOffW1, kH, w.H1, kH, P + kOffB1, nullptr, 0, st);
-    gemm<false, false, EPI_BIAS_RELU>(B, kH, kH, w.H1, kH, P + kOffW2, kH, w.H2, kH, P + kOffB2, nullptr, 0, st);
+    forward_bf16(P, X, B, w, st);
+    return;
   }
+  gemm<false, false, EPI_BIAS_RELU>(B, kH, kF, X, kF, P + kOffW1, kH, w.H1, kH, P + kOffB1, nullptr, 0, st);
+  gemm<false, false, EPI_BIAS_RELU>(B, kH, kH, w.H1, kH, P + kOffW2, kH, w.H2, kH, P + kOffB2, nullptr, 0, st);
   gemm<false, false, EPI_BIAS>(B, 1, kH, w.H2, kH, P + kOffW3, 1, w.y, 1, P + kOffB3, nullptr, 0, st);
 }
 

@@ -55,9 +55,12 @@ def test_features_match_oracle(B, m):
     np.testing.assert_allclose(X.cpu().numpy(), ref, rtol=2e-6, atol=2e-6)
 
 
-# 700 rows: the 64 x 64 matrix-core tiles with a ragged tail; 32,845 rows:
-# the 128 x 128 tiles (from 32,768 rows) with a ragged tail
-@pytest.mark.parametrize("n", [700, 32845])
+# 1 row: every product on the vector tile kernel (fewer than 64 rows);
+# 64 rows: one whole 64 x 64 matrix-core tile; 700 rows: 64 x 64 tiles with
+# a ragged tail; 4,099 rows: weight gradients split over K with a ragged
+# last slice; 32,845 rows: the 128 x 128 tiles (from 32,768 rows) with a
+# ragged tail
+@pytest.mark.parametrize("n", [1, 64, 700, 4099, 32845])
 def test_forward_and_gradient_match_oracle(B, n):
     log(f"[mlp] forward + gradient rows={n}")
     rng = np.random.default_rng(4)
@@ -104,7 +107,7 @@ def _bf16(a):
 # operands (features, W1, W2 and the hidden activations H1): what remains is
 # FP32 accumulation and the rare H1 value whose FP32 sum rounds to the other
 # BF16 neighbour, far below the BF16 rounding itself.
-@pytest.mark.parametrize("n", [700, 32845])
+@pytest.mark.parametrize("n", [1, 700, 32845])
 def test_forward_bf16_matches_rounded_oracle(B, n):
     log(f"[mlp] bf16 forward rows={n}")
     rng = np.random.default_rng(6)
