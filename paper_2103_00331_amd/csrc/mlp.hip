@@ -14,6 +14,7 @@
 #include <cstring>
 #include <string>
 
+#include "common.cuh"
 #include "cpmdp_internal.h"
 #include "handle.h"
 
@@ -503,6 +504,10 @@ static void gemm(int M, int N, int K, const float* A, int lda, const float* B, i
                      static_cast<const float*>(part), ks, len, C);
 }
 
+static int feature_blocks(int rows) {
+  return static_cast<int>(std::min<int64_t>((static_cast<int64_t>(rows) * kF + 255) / 256, 16384));
+}
+
 // -------------------------------------------------------------- features
 // Row i of X for state s of an m^3 grid:
 //   [0..2]    i_k / (m - 1)
@@ -510,9 +515,11 @@ static void gemm(int M, int N, int K, const float* A, int lda, const float* B, i
 //   [128]     (gamma - 0.945) / 0.026
 //   [129]     (slip - 0.175) / 0.072
 // computed one feature at a time.
-__device__ __forceinline__ float feature_at(const float* R, int m, float gamma, float slip, int s,
-                                            int f) {
-  const int i2 = s % m, i1 = (s / m) % m, i0 = s / (m * m);
+__device__ __forceinline__ float feature_at(const float* R, int m, FastDiv dm, float gamma,
+                                            float slip, int s, int f) {
+  const uint32_t q1 = fdiv(static_cast<uint32_t>(s), dm), q2 = fdiv(q1, dm);
+  const int i2 = s - static_cast<int>(q1) * m, i1 = static_cast<int>(q1 - q2 * m),
+            i0 = static_cast<int>(q2);
   if (f < 3) {
     const float inv = m > 1 ? 1.0f / static_cast<float>(m - 1) : 0.f;
     return (f == 0 ? i0 : (f == 1 ? i1 : i2)) * inv;
@@ -527,19 +534,29 @@ __device__ __forceinline__ float feature_at(const float* R, int m, float gamma, 
 }
 
 // All states s0 .. s0+count-1 of one instance, one thread per (state,
-// feature): consecutive threads write consecutive words of X.
-__global__ void features_range_kernel(const float* R, int m, float gamma, float slip, int s0,
-                                      int count, float* X) {
-  const int64_t total = static_cast<int64_t>(count) * kF;
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < total; e += stride) {
-    const int i = static_cast<int>(e / kF), f = static_cast<int>(e - static_cast<int64_t>(i) * kF);
-    X[e] = feature_at(R, m, gamma, slip, s0 + i, f);
+// feature): consecutive threads write consecutive words of X.  IDX is the
+// word-index type (32-bit while count * 130 < 2^31).
+template <typename IDX>
+__global__ void features_range_kernel(const float* R, int m, FastDiv dm, float gamma, float slip,
+                                      int s0, int count, float* X) {
+  const IDX total = static_cast<IDX>(count) * kF;
+  const IDX stride = static_cast<IDX>(gridDim.x) * blockDim.x;
+  for (IDX e = static_cast<IDX>(blockIdx.x) * blockDim.x + threadIdx.x; e < total; e += stride) {
+    const IDX i = e / kF;
+    X[e] = feature_at(R, m, dm, gamma, slip, s0 + static_cast<int>(i), static_cast<int>(e - i * kF));
   }
 }
 
-static int feature_blocks(int rows) {
-  return static_cast<int>(std::min<int64_t>((static_cast<int64_t>(rows) * kF + 255) / 256, 16384));
+static void launch_features_range(const float* R, int m, float gamma, float slip, int s0, int count,
+                                  float* X, hipStream_t st) {
+  const FastDiv dm = make_fastdiv(static_cast<uint32_t>(m));
+  const int blocks = feature_blocks(count);
+  if (static_cast<int64_t>(count) * kF < (int64_t{1} << 31))
+    hipLaunchKernelGGL(features_range_kernel<uint32_t>, dim3(blocks), dim3(256), 0, st, R, m, dm,
+                       gamma, slip, s0, count, X);
+  else
+    hipLaunchKernelGGL(features_range_kernel<int64_t>, dim3(blocks), dim3(256), 0, st, R, m, dm,
+                       gamma, slip, s0, count, X);
 }
 
 // Minibatch: sample i -> (instance, state) drawn with SplitMix64 from
@@ -548,8 +565,8 @@ static int feature_blocks(int rows) {
 // (instance, state), the feature-0 thread also writes the target.
 __global__ void features_sample_kernel(const float* const* R_ptrs, const double* const* V_ptrs,
                                        const double* gammas, const double* slips, int n_inst,
-                                       int m, uint64_t seed, int64_t step, int count, float* X,
-                                       float* t) {
+                                       int m, FastDiv dm, uint64_t seed, int64_t step, int count,
+                                       float* X, float* t) {
   const int64_t total = static_cast<int64_t>(count) * kF;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
   const int S = m * m * m;
@@ -559,7 +576,7 @@ __global__ void features_sample_kernel(const float* const* R_ptrs, const double*
                                                     static_cast<uint64_t>(i)));
     const int inst = static_cast<int>((r >> 32) % static_cast<uint64_t>(n_inst));
     const int s = static_cast<int>((r & 0xFFFFFFFFull) % static_cast<uint64_t>(S));
-    X[e] = feature_at(R_ptrs[inst], m, static_cast<float>(gammas[inst]),
+    X[e] = feature_at(R_ptrs[inst], m, dm, static_cast<float>(gammas[inst]),
                       static_cast<float>(slips[inst]), s, f);
     if (f == 0)
       t[i] = static_cast<float>(((1.0 - gammas[inst]) * V_ptrs[inst][s] - kOutMean) / kOutScale);
@@ -748,9 +765,8 @@ int cpmdp_mlp_features(const float* R, int32_t m, double gamma, double slip, int
       static_cast<int64_t>(s0) + count > static_cast<int64_t>(m) * m * m)
     return mfail("bad feature arguments");
   if (count == 0) return CPMDP_OK;
-  hipLaunchKernelGGL(features_range_kernel, dim3(feature_blocks(count)), dim3(256), 0,
-                     static_cast<hipStream_t>(stream), R, m, static_cast<float>(gamma),
-                     static_cast<float>(slip), s0, count, X);
+  launch_features_range(R, m, static_cast<float>(gamma), static_cast<float>(slip), s0, count, X,
+                        static_cast<hipStream_t>(stream));
   return hipGetLastError() == hipSuccess ? CPMDP_OK : fail(nullptr, CPMDP_E_DEVICE, "features launch");
 }
 
@@ -811,7 +827,8 @@ int cpmdp_mlp_train_step(float* params, float* adam_m, float* adam_v, float* gra
   MlpWs w = carve(ws, batch);
   hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, st, reinterpret_cast<float*>(w.loss), 2, 0.0f);
   hipLaunchKernelGGL(features_sample_kernel, dim3(feature_blocks(batch)), dim3(256), 0, st, R_ptrs,
-                     Vstar_ptrs, gammas, slips, n_inst, m, seed, step, batch, w.X, w.t);
+                     Vstar_ptrs, gammas, slips, n_inst, m, make_fastdiv(static_cast<uint32_t>(m)),
+                     seed, step, batch, w.X, w.t);
   forward(params, w.X, batch, w, st, false);
   backward(params, w.X, batch, w, grad, st);
   int rc = cpmdp_mlp_adam(params, adam_m, adam_v, grad, step, lr, stream);
@@ -838,8 +855,8 @@ int cpmdp_mlp_predict(const float* params, const float* R, int32_t m, double gam
   MlpWs w = carve(ws, chunk);
   for (int s0 = 0; s0 < S; s0 += chunk) {
     const int cnt = std::min(chunk, S - s0);
-    hipLaunchKernelGGL(features_range_kernel, dim3(feature_blocks(cnt)), dim3(256), 0, st, R, m,
-                       static_cast<float>(gamma), static_cast<float>(slip), s0, cnt, w.X);
+    launch_features_range(R, m, static_cast<float>(gamma), static_cast<float>(slip), s0, cnt, w.X,
+                          st);
     forward(params, w.X, cnt, w, st, precision == CPMDP_BF16);
     hipLaunchKernelGGL(to_values_kernel, dim3((cnt + 255) / 256), dim3(256), 0, st, w.y, cnt,
                        1.0 / (1.0 - gamma), V0 + s0);
