@@ -442,20 +442,24 @@ __global__ __launch_bounds__(256) void gemv_bias_kernel(int M, int K, const floa
   }
 }
 
-// Column sums of D [rows][N] (the bias gradients), in two fixed-order
-// stages: block (x, y) sums rows [y rc, (y + 1) rc) of columns
-// [64 x, 64 x + 64), each of its 4 waves every 4th row, the wave sums added
-// in wave order into part[y * N + column]; split_sum_kernel then adds the
-// row chunks in order.
-__global__ __launch_bounds__(256) void colsum_kernel(const float* D, int rows, int N, int rc,
-                                                     float* part) {
+// Column sums of D [rows][N], each row weighted by wr[row] when wr is not
+// null (the bias gradients, and the output layer's weight gradient
+// H2^T dy), in two fixed-order stages: block (x, y) sums rows
+// [y rc, (y + 1) rc) of columns [64 x, 64 x + 64), each of its 4 waves every
+// 4th row, the wave sums added in wave order into part[y * N + column];
+// split_sum_kernel then adds the row chunks in order.
+__global__ __launch_bounds__(256) void colsum_kernel(const float* D, const float* wr, int rows,
+                                                     int N, int rc, float* part) {
   __shared__ float ws[4][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int col = blockIdx.x * 64 + lane;
   const int r0 = blockIdx.y * rc, r1 = min(rows, r0 + rc);
   float s = 0.f;
   if (col < N)
-    for (int r = r0 + w; r < r1; r += 4) s += D[static_cast<int64_t>(r) * N + col];
+    for (int r = r0 + w; r < r1; r += 4) {
+      const float d = D[static_cast<int64_t>(r) * N + col];
+      s = wr ? fmaf(d, wr[r], s) : s + d;
+    }
   ws[w][lane] = s;
   __syncthreads();
   if (w == 0 && col < N) part[static_cast<int64_t>(blockIdx.y) * N + col] = ((ws[0][lane] + ws[1][lane]) + ws[2][lane]) + ws[3][lane];
@@ -527,12 +531,15 @@ static int feature_blocks(int rows) {
   return static_cast<int>(std::min<int64_t>((static_cast<int64_t>(rows) * kF + 255) / 256, 16384));
 }
 
-// db [N] = column sums of D [rows][N] (part: kSplitWords floats).
-static void colsum(const float* D, int rows, int N, float* db, float* part, hipStream_t st) {
+// db [N] = column sums of D [rows][N], rows weighted by wr if not null
+// (part: kSplitWords floats).
+static void colsum(const float* D, const float* wr, int rows, int N, float* db, float* part,
+                   hipStream_t st) {
   int ks = std::max(1, std::min(kSplitMax, rows / 128));
   const int rc = (rows + ks - 1) / ks;
   ks = (rows + rc - 1) / rc;
-  hipLaunchKernelGGL(colsum_kernel, dim3((N + 63) / 64, ks), dim3(256), 0, st, D, rows, N, rc, part);
+  hipLaunchKernelGGL(colsum_kernel, dim3((N + 63) / 64, ks), dim3(256), 0, st, D, wr, rows, N, rc,
+                     part);
   hipLaunchKernelGGL(split_sum_kernel, dim3((N + 255) / 256), dim3(256), 0, st,
                      static_cast<const float*>(part), ks, N, db);
 }
@@ -747,16 +754,16 @@ void backward(const float* P, const float* X, int B, const MlpWs& w, float* G, h
   const int nb = (B + 255) / 256;
   hipLaunchKernelGGL(mse_kernel, dim3(nb), dim3(256), 0, st, w.y, w.t, B, w.dy, w.loss);
   // layer 3: dw3 = H2^T dy, db3 = 1^T dy, dH2 = (dy w3^T) .* [H2 > 0]
-  gemm<true, false, EPI_NONE>(kH, 1, B, w.H2, kH, w.dy, 1, G + kOffW3, 1, nullptr, nullptr, 0, st, w.part);
-  colsum(w.dy, B, 1, G + kOffB3, w.part, st);
+  colsum(w.H2, w.dy, B, kH, G + kOffW3, w.part, st);
+  colsum(w.dy, nullptr, B, 1, G + kOffB3, w.part, st);
   gemm<false, false, EPI_MASK>(B, kH, 1, w.dy, 1, P + kOffW3, kH, w.dH2, kH, nullptr, w.H2, kH, st);
   // layer 2: dW2 = H1^T dH2, db2 = 1^T dH2, dH1 = (dH2 W2^T) .* [H1 > 0]
   gemm<true, false, EPI_NONE>(kH, kH, B, w.H1, kH, w.dH2, kH, G + kOffW2, kH, nullptr, nullptr, 0, st, w.part);
-  colsum(w.dH2, B, kH, G + kOffB2, w.part, st);
+  colsum(w.dH2, nullptr, B, kH, G + kOffB2, w.part, st);
   gemm<false, true, EPI_MASK>(B, kH, kH, w.dH2, kH, P + kOffW2, kH, w.dH1, kH, nullptr, w.H1, kH, st);
   // layer 1: dW1 = X^T dH1, db1 = 1^T dH1
   gemm<true, false, EPI_NONE>(kF, kH, B, X, kF, w.dH1, kH, G + kOffW1, kH, nullptr, nullptr, 0, st, w.part);
-  colsum(w.dH1, B, kH, G + kOffB1, w.part, st);
+  colsum(w.dH1, nullptr, B, kH, G + kOffB1, w.part, st);
 }
 
 int mfail(const std::string& m) { return fail(nullptr, CPMDP_E_ARG, m); }
