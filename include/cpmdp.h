@@ -464,7 +464,7 @@ int cpmdp_mlp_workspace_bytes(int32_t batch, size_t* bytes);
 /* He-normal hidden weights from `seed`; zero biases and output layer. */
 int cpmdp_mlp_init(float* params, uint64_t seed, void* stream);
 /* X [count][130] for states s0 .. s0+count-1 of an m^3 grid with rewards R
- * [m^3] (FP32). */
+ * [m^3] (FP32).  m^3 >= 2^31 or a range past m^3: CPMDP_E_ARG. */
 int cpmdp_mlp_features(const float* R, int32_t m, double gamma, double slip, int32_t s0,
                        int32_t count, float* X, void* stream);
 /* y [count] = MLP(X).  precision: CPMDP_FP32 (every product in FP32) or
@@ -485,14 +485,19 @@ int cpmdp_mlp_adam(float* params, float* m, float* v, const float* grad, int64_t
  * rewards, FP64 solutions), gammas / slips device FP64 [n_inst]; sample i
  * of step k is SplitMix64(seed ^ SplitMix64(k * 0x100000001B3 + i)) ->
  * (instance = high 32 bits mod n_inst, state = low 32 bits mod m^3).
- * Then forward, backward and Adam.  loss_out nullable (synchronizes). */
+ * Then forward, backward and Adam.  loss_out nullable (synchronizes).
+ * Every R_ptrs[i] must hold m^3 floats and every Vstar_ptrs[i] m^3 doubles
+ * (the kernels index them up to m^3 - 1 and cannot check their extent);
+ * m^3 >= 2^31: CPMDP_E_ARG. */
 int cpmdp_mlp_train_step(float* params, float* adam_m, float* adam_v, float* grad, int64_t step,
                          const float* const* R_ptrs, const double* const* Vstar_ptrs,
                          const double* gammas, const double* slips, int32_t n_inst, int32_t m,
                          int32_t batch, uint64_t seed, double lr, void* ws, size_t ws_bytes,
                          void* stream, double* loss_out);
 /* V0 [m^3] (FP64) = MLP prediction / (1 - gamma), in chunks of `chunk`
- * states (workspace sized for chunk); precision as in cpmdp_mlp_forward. */
+ * states (workspace sized for chunk); precision as in cpmdp_mlp_forward.
+ * R must hold m^3 floats and V0 m^3 doubles (not checkable here: the
+ * caller's extents are unknown to the library); m^3 >= 2^31: CPMDP_E_ARG. */
 int cpmdp_mlp_predict(const float* params, const float* R, int32_t m, double gamma, double slip,
                       double* V0, int32_t chunk, int32_t precision, void* ws, size_t ws_bytes,
                       void* stream);

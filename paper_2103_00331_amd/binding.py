@@ -516,6 +516,9 @@ def cpmdp_mlp_train_step(params, adam_m, adam_v, grad, step, R_ptrs, V_ptrs, gam
 
 def cpmdp_mlp_predict(params, R, m, gamma, slip, V0, chunk, ws, stream=None,
                       precision=CPMDP_FP32):
+    S = int(m) ** 3
+    if R.numel() != S or V0.numel() != S or R.dtype != torch.float32 or V0.dtype != torch.float64:
+        raise ValueError(f"predict on an {m}^3 grid needs float32 R and float64 V0 of {S} elements")
     return _check(lib.cpmdp_mlp_predict(_ptr(params), _ptr(R), int(m), float(gamma), float(slip),
                                         _ptr(V0), int(chunk), int(precision), _ptr(ws),
                                         ws.numel() * ws.element_size(), _stream_ptr(stream)))

@@ -796,6 +796,7 @@ int cpmdp_mlp_init(float* params, uint64_t seed, void* stream) {
 int cpmdp_mlp_features(const float* R, int32_t m, double gamma, double slip, int32_t s0,
                        int32_t count, float* X, void* stream) {
   if (!R || !X || m < 1 || count < 0 || s0 < 0 ||
+      static_cast<int64_t>(m) * m * m >= (int64_t{1} << 31) ||
       static_cast<int64_t>(s0) + count > static_cast<int64_t>(m) * m * m)
     return mfail("bad feature arguments");
   if (count == 0) return CPMDP_OK;
@@ -856,6 +857,8 @@ int cpmdp_mlp_train_step(float* params, float* adam_m, float* adam_v, float* gra
   if (!params || !adam_m || !adam_v || !grad || !R_ptrs || !Vstar_ptrs || !gammas || !slips ||
       n_inst < 1 || m < 1 || batch < 1 || step < 1 || !ws)
     return mfail("bad train_step arguments");
+  if (static_cast<int64_t>(m) * m * m >= (int64_t{1} << 31))
+    return mfail("train_step: m^3 must be below 2^31");
   if (ws_bytes < mlp_ws_bytes(batch)) return fail(nullptr, CPMDP_E_WORKSPACE, "MLP workspace too small");
   const hipStream_t st = static_cast<hipStream_t>(stream);
   MlpWs w = carve(ws, batch);
@@ -881,6 +884,8 @@ int cpmdp_mlp_predict(const float* params, const float* R, int32_t m, double gam
                       void* stream) {
   if (!params || !R || !V0 || m < 1 || chunk < 1 || !ws || !(gamma < 1.0))
     return mfail("bad predict arguments");
+  if (static_cast<int64_t>(m) * m * m >= (int64_t{1} << 31))
+    return mfail("predict: m^3 must be below 2^31");
   if (precision != CPMDP_FP32 && precision != CPMDP_BF16)
     return mfail("precision must be CPMDP_FP32 or CPMDP_BF16");
   if (ws_bytes < mlp_ws_bytes(chunk)) return fail(nullptr, CPMDP_E_WORKSPACE, "MLP workspace too small");

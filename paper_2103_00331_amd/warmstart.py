@@ -34,10 +34,21 @@ class WarmStart:
         self.solve_sweeps = []
 
     # ------------------------------------------------------------ data
+    def _check(self, inst):
+        """The kernels index R, V* and V0 up to m^3 - 1: refuse any instance
+        that is not an m x m x m grid before a pointer reaches them."""
+        m = self.m
+        if list(inst.sizes) != [m, m, m] or inst.n_states != m ** 3 or \
+                np.asarray(inst.rewards).size != m ** 3:
+            raise ValueError(f"warm start for {m}^3 grids got an instance of sizes "
+                             f"{list(inst.sizes)} with {np.asarray(inst.rewards).size} rewards")
+
     def add_instances(self, insts, eps: float = 1e-6, chunk: int = 256):
         """Solve the instances with the batched solver (FP32 sweeps, FP64
         certificate) and keep (R, V*) on the device as training data."""
         torch = self.torch
+        for x in insts:
+            self._check(x)
         for c0 in range(0, len(insts), chunk):
             part = insts[c0:c0 + chunk]
             bm = B.BatchModel(part)
@@ -84,6 +95,7 @@ class WarmStart:
         fill the chip.  bf16: hidden layers with BF16 operands (FP32
         accumulation)."""
         torch = self.torch
+        self._check(inst)
         chunk = chunk or min(inst.n_states, 1 << 18)
         R = torch.as_tensor(inst.rewards, dtype=torch.float32, device=self.device)
         V0 = torch.empty(inst.n_states, dtype=torch.float64, device=self.device)

@@ -285,3 +285,29 @@ def test_mlp_precision_rejected():
     assert B.lib.cpmdp_mlp_forward(p, p, 4, p, 5, p, 64, None) == B.CPMDP_E_ARG
     assert B.lib.cpmdp_mlp_forward(p, p, 4, p, B.CPMDP_FP64, p, 64, None) == B.CPMDP_E_ARG
     assert B.lib.cpmdp_mlp_predict(p, p, 4, 0.9, 0.1, p, 64, 9, p, 64, None) == B.CPMDP_E_ARG
+
+
+def test_mlp_rejects_oversized_grid():
+    """m^3 >= 2^31 would overflow the kernels' 32-bit state index: the entry
+    points refuse it before any device work (host buffers stand in)."""
+    buf = np.zeros(16, np.float32)
+    p = buf.ctypes.data
+    m = 1291                                     # 1291^3 > 2^31
+    assert B.lib.cpmdp_mlp_predict(p, p, m, 0.9, 0.1, p, 64, B.CPMDP_FP32, p, 1 << 40,
+                                   None) == B.CPMDP_E_ARG
+    assert B.lib.cpmdp_mlp_features(p, m, 0.9, 0.1, 0, 4, p, None) == B.CPMDP_E_ARG
+    assert B.lib.cpmdp_mlp_train_step(p, p, p, p, 1, p, p, p, p, 1, m, 64, 1, 1e-3, p, 1 << 40,
+                                      None, None) == B.CPMDP_E_ARG
+
+
+def test_warm_start_refuses_other_grid_sizes():
+    """WarmStart indexes R, V* and V0 as m^3 arrays: an instance of another
+    shape is refused before any pointer reaches a kernel."""
+    import types
+    from paper_2103_00331_amd.warmstart import WarmStart
+    w = types.SimpleNamespace(m=8)
+    WarmStart._check(w, I.warm_instance(2, 0, m=8))          # the right shape passes
+    for bad in (I.warm_instance(2, 0, m=6), I.grid_small([8, 8], seed=0),
+                I.grid_small([8, 8, 9], seed=0)):
+        with pytest.raises(ValueError):
+            WarmStart._check(w, bad)
