@@ -1,19 +1,25 @@
 #!/usr/bin/env python3
 """Benchmark of the CP-structured Bellman backup on one MI355X.
 
-Default workload: the 4-D GridWorld 32^4 (1,048,576 states, 8 actions, CP rank
-7 per action, rewards N(0, 0.1) plus a +1 terminal goal corner, gamma = 0.99).
-One step = one complete solve from V0 = 0 to a certified FP64 Bellman
-residual <= 1e-6 by the chosen form (FP32 value-iteration sweeps, FP64 tail
-sweeps, FP64 certificate).  The metric is state-action backups per second over
-the timed steps; time-to-eps of the chosen form and of plain FP64 value
-iteration from V0 = 0 on the same instance are reported beside it.
+Default workload: the batch of 512 GridWorlds (n uniform in {2, 3, 4}, side
+m uniform in [8, 48], slip U[0.05, 0.3], gamma U[0.9, 0.99], rewards
+N(0, 0.1) plus a +1 terminal goal corner; 219,514,047 states in total), the
+largest single-GPU workload.  One step = one complete solve of all 512
+instances from V0 = 0 to a certified FP64 Bellman residual <= 1e-6 per
+instance by the chosen form (batched FP32 value-iteration sweeps in graph
+replays, FP64 tail sweeps, FP64 certificate).  The metric is state-action
+backups per second over the timed steps; time-to-eps of the chosen form and
+of plain FP64 value iteration of each instance on its own from V0 = 0 are
+reported beside it, with the error against the FP64 oracle on sampled
+instances.
 
 Also printed (one JSON line): the roofline of the dominant kernel (the FP32
-stencil sweep), timed live with HIP events on the library's stream, and the
-FP64 CPU oracle timed on a bounded sample of the same workload.
+whole-batch sweep), timed live with HIP events on the library's stream, and
+the FP64 CPU oracle timed on a bounded sample of the same workload on the
+host's cores and on one core.
 
-Other workloads (--workload): grid4d_96 (96^4, HBM-resident), dense6_16
+Other workloads (--workload): grid4d_32 (32^4, cache-resident), grid4d_96
+(96^4, HBM-resident), dense6_16
 (16^6, dense 16x16 factors, 12 actions of rank 8), batch512 (512 mixed
 GridWorlds), warm64 (learned warm start on 64^3) and paper2d_1000 (the
 1000 x 1000 GridWorld of Table 1 with 22 terminals and 800 obstacles) and
@@ -129,6 +135,122 @@ def _cpu_baseline_grid(inst, budget_s=15.0):
             "sample": f"{sweeps} FP64 value-iteration sweeps of the successor-list (Def. 3) "
                       f"oracle on the same {inst.name} instance from V0 = 0, {secs:.1f} s; "
                       "successor-list construction excluded; scipy CSR matvec, one thread"}
+
+
+def _host_cpu():
+    """CPU model and the cores this process may use (affinity), capped at the
+    16-core share of one GPU on the GPU machines."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return model, int(avail), int(min(avail, 16))
+
+
+def _oracle_batch_worker(arg):
+    """One process: FP64 value-iteration sweeps of the Def. 3 successor-list
+    oracle on batch instance idx from V0 = 0 for about `budget` seconds
+    (list construction excluded)."""
+    idx, budget = arg
+    import numpy as np
+
+    import oracle
+    from paper_2103_00331_amd import instances as I
+    x = I.batch_instance(idx)
+    mats = oracle.sparse.transition_csr(x)
+    V = np.zeros(x.n_states)
+    sweeps = 0
+    t0 = time.perf_counter()
+    while True:
+        V = oracle.sparse.q_values(x, mats, V).max(axis=0)
+        sweeps += 1
+        el = time.perf_counter() - t0
+        if el >= budget:
+            break
+    return idx, sweeps * x.n_states * x.n_actions, el, sweeps
+
+
+def _cpu_baseline_batch(budget_s=8.0, max_states=1 << 20):
+    """The oracle on a seeded sample of the batch's instances: one process per
+    core (the oracle itself is single-threaded), then one core alone.  Runs
+    before the GPU is touched (the pool forks)."""
+    import multiprocessing as mp
+
+    import numpy as np
+
+    from paper_2103_00331_amd import instances as I
+    model, avail, cores = _host_cpu()
+    shapes = I.batch_shapes()
+    pool_idx = [i for i, (n, m) in enumerate(shapes) if m ** n <= max_states]
+    rng = np.random.default_rng(2021_0099)
+    sample = [int(i) for i in rng.choice(pool_idx, size=cores, replace=len(pool_idx) < cores)]
+    env_keep = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS",
+                                                "MKL_NUM_THREADS")}
+    for k in env_keep:
+        os.environ[k] = "1"
+    try:
+        ctx = mp.get_context("fork")
+        _log(f"cpu baseline: oracle on {cores} batch instances, {cores} processes")
+        with ctx.Pool(cores) as pool:
+            multi = pool.map(_oracle_batch_worker, [(i, budget_s) for i in sample])
+        _log("cpu baseline: one core")
+        with ctx.Pool(1) as pool:
+            one = pool.map(_oracle_batch_worker, [(i, budget_s / len(sample)) for i in sample])
+    finally:
+        for k, v in env_keep.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    rate_multi = sum(b / el for _, b, el, _ in multi)
+    rate_one = sum(b for _, b, _, _ in one) / sum(el for _, _, el, _ in one)
+    sizes = sorted(shapes[i][1] ** shapes[i][0] for i in sample)
+    return {"value": rate_multi, "unit": "state-action backups/s", "cores": cores,
+            "kind": "oracle", "cpu_model": model, "host_cpus_available": avail,
+            "one_core_value": rate_one,
+            "sample": (f"FP64 value-iteration sweeps of the successor-list (Def. 3) oracle from "
+                       f"V0 = 0, about {budget_s:.0f} s per process: {cores} seeded batch "
+                       f"instances of {sizes[0]}..{sizes[-1]} states (those <= {max_states} "
+                       f"states), one single-threaded process each, summed; one_core_value = "
+                       f"the same instances one after another in one process; list "
+                       f"construction excluded")}
+
+
+def _batch_oracle_check(insts, Vs, pis, res, count=6):
+    """Error of the batched result against the FP64 oracle on a seeded sample
+    of instances (the oracle's own value iteration to 1e-13), and the
+    certified bound max_i res_i / (1 - gamma_i) over all instances."""
+    import numpy as np
+
+    import oracle
+    rng = np.random.default_rng(2021_0098)
+    small = [i for i, x in enumerate(insts) if x.n_states <= 60000]
+    pick = sorted(int(i) for i in rng.choice(small, size=min(count, len(small)), replace=False))
+    err, clear_bad, near = 0.0, 0, 0
+    for i in pick:
+        x = insts[i]
+        mats = oracle.sparse.transition_csr(x)
+        Vs_o, _, _, _ = oracle.sparse.value_iteration(x, mats=mats)
+        V = Vs[i].cpu().numpy()
+        err = max(err, float(np.max(np.abs(V - Vs_o))))
+        Q = oracle.sparse.q_values(x, mats, Vs_o)
+        srt = np.sort(Q, axis=0)
+        gap = srt[-1] - srt[-2]
+        tol = 2 * float(res[i]) / (1 - x.gamma) + 1e-12
+        clear = gap > 2 * tol
+        pi = pis[i].cpu().numpy()
+        clear_bad += int(np.sum(clear & (pi != np.argmax(Q, axis=0))))
+        near += int(np.sum(~clear))
+    bound = max(float(r) / (1 - x.gamma) for r, x in zip(res, insts))
+    return {"max_abs_err_sampled": err, "sampled_instances": pick,
+            "policy_mismatch_clear_states": clear_bad, "near_tie_states": near,
+            "certified_bound_all": bound}
 
 
 def bench_grid(args, m):
@@ -608,6 +730,7 @@ def bench_batch(args):
     pis = [torch.zeros(x.n_states, dtype=torch.int32, device="cuda") for x in insts]
 
     method = 1 if args.method == "pi" else 0
+    last = {}
 
     def solve():
         for V, p in zip(Vs, pis):
@@ -618,6 +741,7 @@ def bench_batch(args):
             bad = np.nonzero(~(res <= eps))[0]
             raise RuntimeError(f"batched solve: code {code}, {bad.size} instances above eps, "
                                f"e.g. {[(int(i), float(res[i]), int(sweeps[i])) for i in bad[:5]]}")
+        last["res"] = res
         return sweeps
 
     for _ in range(args.warmup):
@@ -634,6 +758,8 @@ def bench_batch(args):
     el = time.perf_counter() - t0
     bm.close()
     _log(f"batched {args.method}: {1e3 * el / args.steps:.1f} ms per batch solve (tile {ts}, k {k})")
+    check = _batch_oracle_check(insts, Vs, pis, last["res"])
+    _log(f"oracle check: {check}")
     # plain GPU VI: each instance alone, FP64 sweeps from V0 = 0
     plain = 0.0
     plain_sweeps = 0
@@ -660,7 +786,8 @@ def bench_batch(args):
                        "tile_states": ts, "sweeps_per_graph": k, "autotune_s": tune_s},
             "time_to_eps_s": el / args.steps, "plain_vi_time_to_eps_s": plain,
             "plain_vi_sweeps": plain_sweeps,
-            "speedup_vs_plain_vi": plain / (el / args.steps), "roofline": roof}
+            "speedup_vs_plain_vi": plain / (el / args.steps), "err_vs_oracle": check,
+            "roofline": roof}
 
 
 def bench_warm(args):
@@ -834,7 +961,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="grid4d_32",
+    ap.add_argument("--workload", default="batch512",
                     choices=["grid4d_32", "grid4d_96", "dense6_16", "batch512", "warm64",
                              "paper2d_1000", "paper2d_lists", "tt6_16", "cpfit_grid4d_32"])
     ap.add_argument("--method", default="vi", choices=["vi", "pi"])
@@ -854,6 +981,9 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE "
               f"{world}); this build has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
+    cpu_base = None
+    if args.workload == "batch512" and not args.kernel_only and not args.no_cpu_baseline:
+        cpu_base = _cpu_baseline_batch()        # forks workers: before the GPU is touched
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
@@ -864,6 +994,8 @@ def main():
         out = bench_dense(args)
     elif args.workload == "batch512":
         out = bench_batch(args)
+        if cpu_base is not None:
+            out["cpu_baseline"] = cpu_base
     elif args.workload == "warm64":
         out = bench_warm(args)
     elif args.workload == "paper2d_lists":

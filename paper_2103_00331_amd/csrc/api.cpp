@@ -259,6 +259,7 @@ GridGeom make_geom(const cpmdp_t* h) {
     g.div[k] = make_fastdiv(static_cast<uint32_t>(h->sizes[k]));
     st *= h->sizes[k];
   }
+  g.last = g.size[h->n - 1];
   return g;
 }
 

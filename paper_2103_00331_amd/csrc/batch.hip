@@ -273,15 +273,36 @@ __global__ __launch_bounds__(kBBlock) void batch_util_kernel(BatchArgs a, int op
     const int s0 = tl.y;
     const int s1 = min(s0 + a.tile_states, d.g.S);
     const int p = d.parity;
+    const int nl = d.g.n - 1;
     double m = 0.0;
     for (int s = s0 + threadIdx.x; s < s1; s += kBBlock) {
       if (op == 0) d.V32[p][s] = static_cast<float>(d.V64[p][s]);
       else if (op == 1) d.V64[p][s] = static_cast<double>(d.V32[p][s]);
-      else if (op == 2) m = nanmax(m, fabs(d.V64[p][s]));
+      else if (op == 2) {
+        const uint32_t row = fdiv(static_cast<uint32_t>(s), d.g.div[nl]);
+        if (s - static_cast<int>(row) * d.g.size[nl] < d.g.last) m = nanmax(m, fabs(d.V64[p][s]));
+      }
       else if (op == 3) d.V64[p][s] += static_cast<double>(d.V32[d.eparity][s]);
       else d.V32[0][s] = 0.f;
     }
     if (op == 2) block_max_to_slot(m, a.vmax + tl.x, 0u);
+  }
+}
+
+// Copy between a caller's row-major array (rows of L entries) and the
+// batch's padded layout (rows of Lp >= L entries): to_padded != 0 writes
+// every padded entry (fill beyond L), otherwise only the real ones.
+template <typename E>
+__global__ __launch_bounds__(kBBlock) void pad_rows_kernel(const E* __restrict__ src,
+                                                          E* __restrict__ dst, int64_t rows, int L,
+                                                          int Lp, int to_padded, E fill) {
+  const int64_t total = rows * Lp;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < total; e += stride) {
+    const int64_t r = e / Lp;
+    const int c = static_cast<int>(e - r * Lp);
+    if (to_padded) dst[e] = c < L ? src[r * L + c] : fill;
+    else if (c < L) dst[r * L + c] = src[e];
   }
 }
 
@@ -291,8 +312,19 @@ using namespace cpm;
 
 // ------------------------------------------------------------------- host
 
+// Stored layout of one instance: rows of the last dimension padded to a
+// multiple of 4 (Lp > L) so that every instance runs the 4-wide and
+// marching forms; pi is then the batch's own padded policy buffer.
+struct BLayout {
+  int64_t S = 0, Sp = 0;              // real / stored states
+  int32_t L = 0, Lp = 0;
+  int32_t* pi = nullptr;
+  bool padded() const { return Lp != L; }
+};
+
 struct cpmdp_batch {
   std::vector<cpmdp_t*> hs;
+  std::vector<BLayout> lay;           // per instance: stored layout
   std::vector<BInst> hd;              // host copy of the descriptors
   std::vector<int64_t> off;           // per instance: element offset of its arrays
   int64_t total_states = 0;
@@ -347,12 +379,40 @@ int bfail(cpmdp_batch_t* b, int code, const std::string& msg) {
 
 size_t al(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
-// Per-instance arrays: R64, R32, tbits, V32[2], V64[2], weights, r32.
+BLayout layout_of(const cpmdp_t* h) {
+  BLayout l;
+  l.S = h->S;
+  l.L = static_cast<int32_t>(h->sizes[h->n - 1]);
+  l.Lp = (l.L + 3) & ~3;
+  l.Sp = h->S / l.L * l.Lp;
+  return l;
+}
+
+// Stored geometry: the instance's own, with the last size padded to Lp.
+GridGeom padded_geom(const cpmdp_t* h, const BLayout& l) {
+  GridGeom g = h->geom;
+  g.last = l.L;
+  if (!l.padded()) return g;
+  const int n = h->n;
+  g.size[n - 1] = l.Lp;
+  g.div[n - 1] = make_fastdiv(static_cast<uint32_t>(l.Lp));
+  int64_t st = 1;
+  for (int k = n - 1; k >= 0; --k) {
+    g.stride[k] = static_cast<int32_t>(st);
+    st *= g.size[k];
+  }
+  g.S = static_cast<int32_t>(st);
+  return g;
+}
+
+// Per-instance arrays (stored layout): R64, R32, tbits, V32[2], V64[2],
+// weights, r32, and the padded policy when padded.
 size_t inst_bytes(const cpmdp_t* h) {
-  const size_t S = static_cast<size_t>(h->S);
+  const BLayout l = layout_of(h);
+  const size_t S = static_cast<size_t>(l.Sp);
   const size_t P = 2 * static_cast<size_t>(h->n) + 1;
   return al(S * 8) + al(S * 4) + al((S + 31) / 32 * 4 + 4) + 2 * al(S * 4) + 2 * al(S * 8) +
-         al(h->A * P * 4) + al(h->A * P * 8) + al(S * 4);
+         al(h->A * P * 4) + al(h->A * P * 8) + al(S * 4) + (l.padded() ? al(S * 4) : 0);
 }
 
 size_t fixed_bytes(const cpmdp_batch_t* b, int64_t max_tiles) {
@@ -364,8 +424,55 @@ size_t fixed_bytes(const cpmdp_batch_t* b, int64_t max_tiles) {
 
 int64_t count_tiles(const cpmdp_batch_t* b, int ts) {
   int64_t t = 0;
-  for (auto* h : b->hs) t += (h->S + ts - 1) / ts;
+  for (auto* h : b->hs) t += (layout_of(h).Sp + ts - 1) / ts;
   return t;
+}
+
+int pad_grid(int64_t n) {
+  return static_cast<int>(std::min<int64_t>((n + kBBlock - 1) / kBBlock, 4096));
+}
+
+// Caller's V (FP64, real layout) -> stored V64[0] of instance i.
+int copy_in_values(cpmdp_batch_t* b, size_t i, const double* V) {
+  const BLayout& l = b->lay[i];
+  double* dst = b->hd[i].V64[0];
+  if (!l.padded()) {
+    BHIP(b, hipMemcpyAsync(dst, V, l.S * 8, hipMemcpyDeviceToDevice, b->stream));
+    return CPMDP_OK;
+  }
+  hipLaunchKernelGGL(pad_rows_kernel<double>, dim3(pad_grid(l.Sp)), dim3(kBBlock), 0, b->stream, V,
+                     dst, l.S / l.L, l.L, l.Lp, 1, 0.0);
+  BHIP(b, hipGetLastError());
+  return CPMDP_OK;
+}
+
+// Stored V64[parity] (and the padded policy) of instance i -> caller's buffers.
+int copy_out(cpmdp_batch_t* b, size_t i, double* V, int32_t* pi) {
+  const BLayout& l = b->lay[i];
+  const BInst& d = b->hd[i];
+  if (!l.padded()) {
+    BHIP(b, hipMemcpyAsync(V, d.V64[d.parity], l.S * 8, hipMemcpyDeviceToDevice, b->stream));
+    return CPMDP_OK;
+  }
+  hipLaunchKernelGGL(pad_rows_kernel<double>, dim3(pad_grid(l.Sp)), dim3(kBBlock), 0, b->stream,
+                     d.V64[d.parity], V, l.S / l.L, l.L, l.Lp, 0, 0.0);
+  if (pi)
+    hipLaunchKernelGGL(pad_rows_kernel<int32_t>, dim3(pad_grid(l.Sp)), dim3(kBBlock), 0, b->stream,
+                       l.pi, pi, l.S / l.L, l.L, l.Lp, 0, 0);
+  BHIP(b, hipGetLastError());
+  return CPMDP_OK;
+}
+
+// The policy the kernels read and write for instance i: the caller's buffer,
+// or the padded copy (filled from the caller's when `load`).
+int32_t* policy_buffer(cpmdp_batch_t* b, size_t i, int32_t* caller, bool load) {
+  const BLayout& l = b->lay[i];
+  if (!caller) return nullptr;
+  if (!l.padded()) return caller;
+  if (load)
+    hipLaunchKernelGGL(pad_rows_kernel<int32_t>, dim3(pad_grid(l.Sp)), dim3(kBBlock), 0, b->stream,
+                       caller, l.pi, l.S / l.L, l.L, l.Lp, 1, 0);
+  return l.pi;
 }
 
 double bits_to_double(unsigned long long u) {
@@ -411,7 +518,7 @@ int upload_tiles(cpmdp_batch_t* b, const std::vector<char>& want, int64_t* count
     for (size_t i = 0; i < b->hs.size(); ++i) {
       if (want[i] != grp) continue;
       const BInst& d = b->hd[i];
-      const int64_t S = b->hs[i]->S;
+      const int64_t S = b->lay[i].Sp;
       if (march && d.mtiles > 0) {
         const int64_t planes = d.g.size[0];
         for (int q = 0; q < d.mtiles; ++q) {
@@ -589,10 +696,10 @@ int batch_pi(cpmdp_batch_t* b, double* const* V_devs, int32_t* const* pi_devs, d
   for (size_t i = 0; i < n; ++i) {
     cpmdp_t* h = b->hs[i];
     BInst& d = b->hd[i];
-    BHIP(b, hipMemcpyAsync(d.V64[0], V_devs[i], h->S * 8, hipMemcpyDeviceToDevice, b->stream));
+    int rc0 = copy_in_values(b, i, V_devs[i]);
+    if (rc0) return rc0;
     d.parity = 0;
     d.eparity = 0;
-    d.pi_out = pi_devs[i];
     const double rmax = h->rmax;
     eps_floor[i] = 0.5 * eps * (1.0 - h->gamma);
     eps_eval[i] = std::max(eps_floor[i], 1e-1 * std::max(rmax, 1e-300));   // first policy: loosely
@@ -607,6 +714,9 @@ int batch_pi(cpmdp_batch_t* b, double* const* V_devs, int32_t* const* pi_devs, d
   BHIP(b, hipStreamSynchronize(b->stream));
   for (size_t i = 0; i < n; ++i)
     if (b->h_changes[i] != 0) return bfail(b, CPMDP_E_ARG, "policy holds actions outside [0, A)");
+  // padded instances evaluate and improve a padded copy (padded entries: action 0)
+  for (size_t i = 0; i < n; ++i) b->hd[i].pi_out = policy_buffer(b, i, pi_devs[i], true);
+  BHIP(b, hipGetLastError());
   int rc = upload_descs(b);
   if (rc) return rc;
   std::vector<double> res;
@@ -750,8 +860,8 @@ int batch_pi(cpmdp_batch_t* b, double* const* V_devs, int32_t* const* pi_devs, d
   }
   bool all_ok = true;
   for (size_t i = 0; i < n; ++i) {
-    const BInst& d = b->hd[i];
-    BHIP(b, hipMemcpyAsync(V_devs[i], d.V64[d.parity], b->hs[i]->S * 8, hipMemcpyDeviceToDevice, b->stream));
+    rc = copy_out(b, i, V_devs[i], pi_devs[i]);
+    if (rc) return rc;
     if (sweeps_out) sweeps_out[i] = sweeps[i];
     if (residual_out) residual_out[i] = cert[i];
     all_ok = all_ok && converged[i];
@@ -844,19 +954,24 @@ int cpmdp_batch_bind(cpmdp_batch_t* b, void* ws, size_t bytes, void* stream) {
     BHIP(b, hipHostMalloc(reinterpret_cast<void**>(&b->h_ntiles), 64, hipHostMallocDefault));
   }
   b->hd.assign(n, BInst{});
+  b->lay.assign(n, BLayout{});
   for (size_t i = 0; i < n; ++i) {
     cpmdp_t* h = b->hs[i];
     BInst& d = b->hd[i];
-    const size_t S = static_cast<size_t>(h->S);
+    BLayout& l = b->lay[i];
+    l = layout_of(h);
+    if (l.Sp >= (int64_t{1} << 31))
+      return bfail(b, CPMDP_E_UNSUPPORTED, "padded instance exceeds 2^31 states");
+    const size_t S = static_cast<size_t>(l.Sp);
     const int P = 2 * h->n + 1;
-    d.g = h->geom;
+    d.g = padded_geom(h, l);
     d.A = h->A;
-    d.vec = h->st_vec;
+    d.vec = 4;                          // every stored row holds a multiple of 4 entries
     d.axis = h->st_axis;
     d.stage = B_F32;
     // marching tiles when the planes of fixed i_0 are large
-    const int64_t plane = h->S / h->sizes[0];
-    d.mtiles = (h->n >= 2 && h->st_vec == 4 && plane >= kBMarchMinPlane && h->sizes[0] >= 8)
+    const int64_t plane = l.Sp / h->sizes[0];
+    d.mtiles = (h->n >= 2 && plane >= kBMarchMinPlane && h->sizes[0] >= 8)
                    ? static_cast<int32_t>((plane + kBBlock * 4 - 1) / (kBBlock * 4))
                    : 0;
     d.parity = 0;
@@ -882,18 +997,25 @@ int cpmdp_batch_bind(cpmdp_batch_t* b, void* ws, size_t bytes, void* stream) {
     float* w32 = reinterpret_cast<float*>(take(h->A * P * 4));
     double* w64 = reinterpret_cast<double*>(take(h->A * P * 8));
     d.r32 = reinterpret_cast<float*>(take(S * 4));
+    if (l.padded()) l.pi = reinterpret_cast<int32_t*>(take(S * 4));
     d.R64 = R64;
     d.R32 = R32;
     d.tbits = tb;
     d.w32 = w32;
     d.w64 = w64;
-    std::vector<float> r32(S), ww32(h->w.size());
-    for (size_t s = 0; s < S; ++s) r32[s] = static_cast<float>(h->rewards[s]);
-    for (size_t q = 0; q < h->w.size(); ++q) ww32[q] = static_cast<float>(h->w[q]);
+    // rewards and terminal bits in the stored layout (padded entries: 0)
+    std::vector<double> r64(S, 0.0);
+    std::vector<float> r32(S, 0.f), ww32(h->w.size());
     std::vector<uint32_t> bits((S + 31) / 32 + 1, 0u);
-    for (size_t s = 0; s < S; ++s)
-      if (h->terminal[s]) bits[s >> 5] |= 1u << (s & 31);
-    BHIP(b, hipMemcpyAsync(R64, h->rewards.data(), S * 8, hipMemcpyHostToDevice, b->stream));
+    for (int64_t row = 0; row < l.S / l.L; ++row)
+      for (int c = 0; c < l.L; ++c) {
+        const size_t src = static_cast<size_t>(row * l.L + c), dst = static_cast<size_t>(row * l.Lp + c);
+        r64[dst] = h->rewards[src];
+        r32[dst] = static_cast<float>(h->rewards[src]);
+        if (h->terminal[src]) bits[dst >> 5] |= 1u << (dst & 31);
+      }
+    for (size_t q = 0; q < h->w.size(); ++q) ww32[q] = static_cast<float>(h->w[q]);
+    BHIP(b, hipMemcpyAsync(R64, r64.data(), S * 8, hipMemcpyHostToDevice, b->stream));
     BHIP(b, hipMemcpyAsync(R32, r32.data(), S * 4, hipMemcpyHostToDevice, b->stream));
     BHIP(b, hipMemcpyAsync(tb, bits.data(), bits.size() * 4, hipMemcpyHostToDevice, b->stream));
     BHIP(b, hipMemcpyAsync(w32, ww32.data(), ww32.size() * 4, hipMemcpyHostToDevice, b->stream));
@@ -943,10 +1065,11 @@ int cpmdp_batch_solve(cpmdp_batch_t* b, double* const* V_devs, int32_t* const* p
   for (size_t i = 0; i < n; ++i) {
     cpmdp_t* h = b->hs[i];
     BInst& d = b->hd[i];
-    BHIP(b, hipMemcpyAsync(d.V64[0], V_devs[i], h->S * 8, hipMemcpyDeviceToDevice, b->stream));
+    int rc0 = copy_in_values(b, i, V_devs[i]);
+    if (rc0) return rc0;
     d.parity = 0;
     d.stage = precision == CPMDP_FP64 ? B_F64 : B_F32;
-    d.pi_out = pi_devs ? pi_devs[i] : nullptr;
+    d.pi_out = policy_buffer(b, i, pi_devs ? pi_devs[i] : nullptr, false);
     const double rmax = h->rmax;
     floor32[i] = 8.0 * std::ldexp(1.0, -24) * std::max(1.0, rmax / (1.0 - h->gamma));
     d.stop = d.stage == B_F32 ? std::max(eps, floor32[i]) : eps;
@@ -1055,8 +1178,8 @@ int cpmdp_batch_solve(cpmdp_batch_t* b, double* const* V_devs, int32_t* const* p
   }
   bool all_ok = true;
   for (size_t i = 0; i < n; ++i) {
-    const BInst& d = b->hd[i];
-    BHIP(b, hipMemcpyAsync(V_devs[i], d.V64[d.parity], b->hs[i]->S * 8, hipMemcpyDeviceToDevice, b->stream));
+    rc = copy_out(b, i, V_devs[i], pi_devs ? pi_devs[i] : nullptr);
+    if (rc) return rc;
     if (sweeps_out) sweeps_out[i] = sweeps[i];
     if (residual_out) residual_out[i] = cert[i];
     all_ok = all_ok && cert[i] <= eps;

@@ -45,12 +45,18 @@ struct FastDiv {
 
 FastDiv make_fastdiv(uint32_t d);
 
+// Row-major grid geometry.  size[] and stride[] describe the stored layout;
+// `last` is the number of real states along the last dimension: a layout
+// whose rows are padded to a multiple of 4 has size[n-1] > last, the padded
+// entries are never read by a real state and never count in a residual.
 struct GridGeom {
   int32_t n;
   int32_t S;
   int32_t size[kMaxDims];
   int32_t stride[kMaxDims];
   FastDiv div[kMaxDims];
+  int32_t last;
+  int32_t pad_;
 };
 
 // Optional events around one launch (hipExtLaunchKernelGGL records the

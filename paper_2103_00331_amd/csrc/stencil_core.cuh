@@ -151,11 +151,14 @@ __device__ __forceinline__ void store4_stream(T* p, const V4& o) {
   __builtin_nontemporal_store(v, reinterpret_cast<nv4*>(p));
 }
 
-// States s .. s+3 along the last dimension (m_last % 4 == 0, s % 4 == 0)
+// States s .. s+3 along the last dimension (size[n-1] % 4 == 0, s % 4 == 0)
 // given their values c4 and the vectors of their +-e_k neighbours for
 // k < n-1 (clamped): the last-dimension neighbours come from c4 and the two
 // adjacent scalars; then per-state work and stores (R loads and V' stores
-// non-temporal when STREAM).
+// non-temporal when STREAM).  In a row padded past g.last the real state
+// g.last - 1 takes itself as its +e_last neighbour (the clamp of the grid
+// edge), and the padded lanes are computed but left out of the residual and
+// the change count (their stored values are never read by a real state).
 template <typename T, int N, int MODE, bool AXIS, bool STREAM = false>
 __device__ __forceinline__ void stencil_vec4(const GridGeom& g, const StencilIO<T>& io,
                                              const StencilW<T>& W, int s, int il,
@@ -167,7 +170,7 @@ __device__ __forceinline__ void stencil_vec4(const GridGeom& g, const StencilIO<
   using V4 = typename VecOf<T, 4>::type;
   constexpr int P = 2 * N + 1;
   const T left = io.V[s - ((il > 0) ? 1 : 0)];
-  const T right = io.V[s + ((il + 4 < g.size[N - 1]) ? 4 : 3)];
+  const T right = io.V[s + ((il + 4 < g.last) ? 4 : 3)];
   const V4 r4 = STREAM ? load4_stream<V4>(io.R + s) : *reinterpret_cast<const V4*>(io.R + s);
   const uint32_t tw = io.tbits[s >> 5] >> (s & 31);
   int4 p4 = make_int4(-1, -1, -1, -1);
@@ -186,13 +189,21 @@ __device__ __forceinline__ void stencil_vec4(const GridGeom& g, const StencilIO<
       nb[1 + 2 * k] = comp<T>(plus4[k], q);
       nb[2 + 2 * k] = comp<T>(minus4[k], q);
     }
-    nb[1 + 2 * (N - 1)] = q < 3 ? comp<T>(c4, q + 1) : right;
+    const bool real = il + q < g.last;
+    nb[1 + 2 * (N - 1)] = (il + q + 1 < g.last) ? (q < 3 ? comp<T>(c4, q + 1) : right)
+                                                : comp<T>(c4, q);
     nb[2 + 2 * (N - 1)] = q > 0 ? comp<T>(c4, q - 1) : left;
     if (io.obs) block_points<T, P>(nb, ((q < 2 ? ob.x : ob.y) >> (16 * (q & 1))) & 0xFFFFu);
     const int pold = q == 0 ? p4.x : (q == 1 ? p4.y : (q == 2 ? p4.z : p4.w));
     pnv[q] = 0;
+    T rq = res;
+    unsigned cq = 0;
     stencil_state<T, N, MODE, AXIS>(W, nb, comp<T>(r4, q), (tw >> q) & 1u, pold, tol, outv[q],
-                                    pnv[q], res, ch);
+                                    pnv[q], rq, cq);
+    if (real) {
+      res = rq;
+      ch += cq;
+    }
   }
   if (!live) return;   // a recomputed chunk: its residual terms repeat a live one's
   changed += ch;
@@ -202,7 +213,7 @@ __device__ __forceinline__ void stencil_vec4(const GridGeom& g, const StencilIO<
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       d[q] = static_cast<double>(outv[q]) - static_cast<double>(comp<T>(c4, q));
-      res_d = nanmax(res_d, fabs(d[q]));
+      if (il + q < g.last) res_d = nanmax(res_d, fabs(d[q]));
     }
     r.x = static_cast<float>(d[0]);
     r.y = static_cast<float>(d[1]);
