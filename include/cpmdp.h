@@ -424,12 +424,28 @@ int cpmdp_batch_solve(cpmdp_batch_t* b, double* const* V_devs,
                       int precision, int method, int64_t* sweeps_out,
                       double* residual_out);
 
-/* Autotuner control: tune = 1 times candidate tile sizes and sweeps per graph
- * on the bound batch and keeps the fastest; cache_path (nullable) is a text
- * file of size class -> choice read before and written after tuning. */
+/* Autotuner control: tune = 1 times candidate tile sizes, grid sizes, tile
+ * forms (marching tiles where an instance allows them, or one-pass tiles
+ * only) and tile schedules (a contiguous range of tiles per block, or a range
+ * per XCD taken in turn by its blocks) on the bound batch, keeps the fastest
+ * and sizes the sweeps per graph from the host round trip; cache_path
+ * (nullable) is a text file of size class -> choice read before and written
+ * after tuning. */
 int cpmdp_batch_autotune(cpmdp_batch_t* b, int tune, const char* cache_path);
+/* The current choice: states per one-pass tile and sweeps per graph. */
 int cpmdp_batch_config(const cpmdp_batch_t* b, int32_t* tile_states,
                        int32_t* sweeps_per_graph);
+/* Set the choice by hand (tests, measurements): states per one-pass tile (a
+ * multiple of 1024 in [1024, 65536]), blocks per launch (a multiple of 8 in
+ * [8, 2048]), marching tiles (1) or one-pass tiles only (0), tile schedule
+ * (0: range per block, 1: range per XCD, interleaved); other values:
+ * CPMDP_E_ARG.  Results do not depend on the choice. */
+int cpmdp_batch_set_schedule(cpmdp_batch_t* b, int32_t tile_states, int32_t grid, int32_t march,
+                             int32_t sched);
+/* The current choice: blocks per launch, marching tiles on (1) / off (0),
+ * tile schedule (0: range per block, 1: range per XCD, interleaved). */
+int cpmdp_batch_schedule(const cpmdp_batch_t* b, int32_t* grid, int32_t* march,
+                         int32_t* sched);
 /* Measurement helper: n FP32 value-iteration sweeps over the whole bound
  * batch (every instance active, values in the internal FP32 buffers, so the
  * results are meaningless), each launched with events that record the sweep

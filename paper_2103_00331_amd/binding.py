@@ -84,6 +84,8 @@ _SIGS = {
                                     C.c_int, C.c_int, _i64p, _dp]),
     "cpmdp_batch_autotune": (C.c_int, [_p, C.c_int, C.c_char_p]),
     "cpmdp_batch_config": (C.c_int, [_p, _i32p, _i32p]),
+    "cpmdp_batch_schedule": (C.c_int, [_p, _i32p, _i32p, _i32p]),
+    "cpmdp_batch_set_schedule": (C.c_int, [_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     "cpmdp_batch_time_sweeps": (C.c_int, [_p, C.c_int32, _dp]),
     "cpmdp_batch_destroy": (None, [_p]),
     "cpmdp_mlp_param_count": (C.c_int, [_i64p]),
@@ -366,6 +368,17 @@ def cpmdp_batch_config(b):
     k = C.c_int32()
     _check(lib.cpmdp_batch_config(b, C.byref(t), C.byref(k)))
     return t.value, k.value
+
+
+def cpmdp_batch_set_schedule(b, tile_states, grid, march, sched):
+    return _check(lib.cpmdp_batch_set_schedule(b, int(tile_states), int(grid), int(march),
+                                               int(sched)))
+
+
+def cpmdp_batch_schedule(b):
+    g, m, sc = C.c_int32(), C.c_int32(), C.c_int32()
+    _check(lib.cpmdp_batch_schedule(b, C.byref(g), C.byref(m), C.byref(sc)))
+    return g.value, m.value, sc.value
 
 
 def cpmdp_batch_destroy(b):

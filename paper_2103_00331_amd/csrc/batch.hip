@@ -70,8 +70,9 @@ struct BatchArgs {
   const BInst* insts;
   const int2* tiles;
   const int* ntiles;            // device-resident count (graphs stay valid)
-  const int* starts;            // [2][gridDim.x + 1] first tile of each block, per group
+  const int* starts;            // [2][gridDim.x + 1] tile ranges per group (see tile_iter)
   int32_t tile_states;
+  int32_t sched;                // 0: a contiguous range per block; 1: per XCD, interleaved
   int32_t ninst;
   unsigned long long* res;      // [kBMaxK][ninst][kBSpread] FP64 bits
   unsigned long long* vmax;     // [ninst] ||V||_inf FP64 bits (certificate)
@@ -97,16 +98,81 @@ __device__ __forceinline__ void tile_states(const GridGeom& g, const StencilIO<T
     stencil_chunk<T, N, MODE, VEC, AXIS, true>(g, io, W, s, tol, res, res_d, ch);
 }
 
+// The descriptor sits in LDS, so every value read from it would occupy a
+// vector register per lane.  The per-state code reads the geometry, the
+// weights and the array pointers in every iteration: copy them once per tile
+// through readfirstlane into wave-uniform values (scalar registers), as the
+// single-instance kernels get them from their kernel arguments.
+__device__ __forceinline__ int ufirst(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint32_t ufirst(uint32_t v) {
+  return static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(v)));
+}
+__device__ __forceinline__ float ufirst(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ double ufirst(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readfirstlane(static_cast<int>(b & 0xFFFFFFFFll));
+  const int hi = __builtin_amdgcn_readfirstlane(static_cast<int>(b >> 32));
+  return __longlong_as_double((static_cast<long long>(hi) << 32) |
+                              static_cast<long long>(static_cast<uint32_t>(lo)));
+}
+template <typename P>
+__device__ __forceinline__ P* ufirst_ptr(P* p) {
+  const uint64_t b = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = ufirst(static_cast<uint32_t>(b)), hi = ufirst(static_cast<uint32_t>(b >> 32));
+  return reinterpret_cast<P*>((static_cast<uint64_t>(hi) << 32) | lo);
+}
+
+template <int N>
+__device__ __forceinline__ GridGeom ugeom(const GridGeom& s) {
+  GridGeom g;
+  g.n = N;
+  g.S = ufirst(s.S);
+  g.last = ufirst(s.last);
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    g.size[k] = ufirst(s.size[k]);
+    g.stride[k] = ufirst(s.stride[k]);
+    g.div[k].magic = ufirst(s.div[k].magic);
+    g.div[k].shift = ufirst(s.div[k].shift);
+  }
+  return g;
+}
+
+template <typename T>
+__device__ __forceinline__ StencilIO<T> uio(const StencilIO<T>& s) {
+  return StencilIO<T>{ufirst_ptr(s.V), ufirst_ptr(s.Vout), ufirst_ptr(s.R), ufirst_ptr(s.tbits),
+                      ufirst_ptr(s.pi_in), ufirst_ptr(s.pi_out), ufirst_ptr(s.r_out), nullptr};
+}
+
+// Axis-form weights of an N-dim instance as wave-uniform values.
+template <typename T, int N>
+struct UWeights {
+  T base[2 * N + 1];
+  T axis[6 * N];
+  __device__ __forceinline__ StencilW<T> load(const StencilW<T>& W) {
+#pragma unroll
+    for (int p = 0; p < 2 * N + 1; ++p) base[p] = ufirst(W.base[p]);
+#pragma unroll
+    for (int q = 0; q < 6 * N; ++q) axis[q] = ufirst(W.axis[q]);
+    return StencilW<T>{base, axis, W.full, W.eval, ufirst(W.A), ufirst(W.gamma)};
+  }
+};
+
 template <typename T, int MODE, int N>
-__device__ __forceinline__ void tile_dispatch_n(const BInst& d, const StencilIO<T>& io,
-                                                const StencilW<T>& W, int s0, int s1, T tol,
+__device__ __forceinline__ void tile_dispatch_n(const BInst& d, const StencilIO<T>& io_l,
+                                                const StencilW<T>& W_l, int s0, int s1, T tol,
                                                 T& res, double& res_d, unsigned& ch) {
-  if (d.vec == 4) {
-    if (d.axis) tile_states<T, N, MODE, 4, true>(d.g, io, W, s0, s1, tol, res, res_d, ch);
-    else tile_states<T, N, MODE, 4, false>(d.g, io, W, s0, s1, tol, res, res_d, ch);
+  const GridGeom g = ugeom<N>(d.g);
+  const StencilIO<T> io = uio(io_l);
+  // every stored row holds a multiple of 4 states (padded layout): 4 per lane
+  if (d.axis) {
+    UWeights<T, N> uw;
+    const StencilW<T> W = uw.load(W_l);
+    tile_states<T, N, MODE, 4, true>(g, io, W, s0, s1, tol, res, res_d, ch);
   } else {
-    if (d.axis) tile_states<T, N, MODE, 1, true>(d.g, io, W, s0, s1, tol, res, res_d, ch);
-    else tile_states<T, N, MODE, 1, false>(d.g, io, W, s0, s1, tol, res, res_d, ch);
+    tile_states<T, N, MODE, 4, false>(g, io, W_l, s0, s1, tol, res, res_d, ch);
   }
 }
 
@@ -123,36 +189,45 @@ __device__ __forceinline__ void tile_dispatch(const BInst& d, const StencilIO<T>
 }
 
 // The tiles of one group (0: FP32 or the only group, 1: FP64, listed after
-// group 0) are split into contiguous ranges of about equal work, one per
-// block (numbered XCD-aware), by the host: starts[group][b].
-__device__ __forceinline__ void tile_range(const BatchArgs& a, int which, int& t0, int& t1) {
-  const int blk = xcd_block(blockIdx.x, gridDim.x);
+// group 0), in the order of the tile table, go to the blocks of a launch in
+// one of two schedules chosen by the autotuner:
+//   sched 0: contiguous ranges of about equal work, one per block (numbered
+//            XCD-aware), starts[group][b];
+//   sched 1: contiguous ranges of about equal work, one per XCD,
+//            starts[group][x]; the blocks of XCD x (b % 8 == x, the
+//            hardware's round-robin dispatch) take its tiles in turn, so
+//            the tiles in flight on one XCD form one window of the table and
+//            neighbours along the outer dimensions are still in that XCD's
+//            L2 when the next tiles read them.
+struct TileIter {
+  int t, end, step;
+};
+__device__ __forceinline__ TileIter tile_iter(const BatchArgs& a, int which) {
   const int* st = a.starts + which * (gridDim.x + 1);
-  t0 = st[blk];
-  t1 = st[blk + 1];
-}
-
-template <typename T, int MODE, int N>
-__device__ __forceinline__ void march_dispatch_n(const BInst& d, const StencilIO<T>& io,
-                                                 const StencilW<T>& W, int p, T& res,
-                                                 double& res_d, unsigned& ch) {
-  if constexpr (N >= 2) {
-    if (d.axis) march_column<T, N, MODE, true>(d.g, io, W, p, 0, d.g.size[0], T(0), res, res_d, ch);
-    else march_column<T, N, MODE, false>(d.g, io, W, p, 0, d.g.size[0], T(0), res, res_d, ch);
+  if (a.sched == 0) {
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    return TileIter{st[blk], st[blk + 1], 1};
   }
+  const int x = blockIdx.x % kXcds;
+  return TileIter{st[x] + static_cast<int>(blockIdx.x) / kXcds, st[x + 1],
+                  static_cast<int>(gridDim.x) / kXcds};
 }
 
-// Marching tile: thread handles plane offset p for every plane.
+// Marching tile: thread handles plane offset p for every plane.  Only 4-D
+// instances in the axis form march (the host gives no other instance
+// marching tiles): one marching path keeps the kernel's register count low
+// enough for 6 waves per SIMD; smaller instances have planes too small to
+// march anyway.
 template <typename T, int MODE>
-__device__ __forceinline__ void march_dispatch(const BInst& d, const StencilIO<T>& io,
-                                               const StencilW<T>& W, int q, T& res, double& res_d,
+__device__ __forceinline__ void march_dispatch(const BInst& d, const StencilIO<T>& io_l,
+                                               const StencilW<T>& W_l, int q, T& res, double& res_d,
                                                unsigned& ch) {
   const int p = (q % d.mtiles) * (kBBlock * 4) + threadIdx.x * 4;
-  switch (d.g.n) {
-    case 2: march_dispatch_n<T, MODE, 2>(d, io, W, p, res, res_d, ch); break;
-    case 3: march_dispatch_n<T, MODE, 3>(d, io, W, p, res, res_d, ch); break;
-    default: march_dispatch_n<T, MODE, 4>(d, io, W, p, res, res_d, ch); break;
-  }
+  const GridGeom g = ugeom<4>(d.g);
+  const StencilIO<T> io = uio(io_l);
+  UWeights<T, 4> uw;
+  const StencilW<T> W = uw.load(W_l);
+  march_column<T, 4, MODE, true>(g, io, W, p, 0, g.size[0], T(0), res, res_d, ch);
 }
 
 template <typename T>
@@ -179,9 +254,8 @@ __device__ __forceinline__ double* const* vals(const BInst& d, double) { return 
 template <typename T, int MODE>
 __global__ __launch_bounds__(kBBlock) void batch_sweep_kernel(BatchArgs a, int j) {
   __shared__ BInst d;
-  int t0, t1;
-  tile_range(a, sizeof(T) == 8 ? 1 : 0, t0, t1);
-  for (int t = t0; t < t1; ++t) {
+  const TileIter it = tile_iter(a, sizeof(T) == 8 ? 1 : 0);
+  for (int t = it.t; t < it.end; t += it.step) {
     const int2 tl = load_tile(a, t, d);
     // Early exit inside a graph replay: once a sweep of this instance has
     // met its stop threshold, its later sweeps in the replay are skipped and
@@ -224,9 +298,8 @@ __global__ __launch_bounds__(kBBlock) void batch_sweep_kernel(BatchArgs a, int j
 // unless beaten by more than the tie tolerance; changed states are counted.
 __global__ __launch_bounds__(kBBlock) void batch_cert_kernel(BatchArgs a, int keep) {
   __shared__ BInst d;
-  int t0, t1;
-  tile_range(a, 0, t0, t1);
-  for (int t = t0; t < t1; ++t) {
+  const TileIter it = tile_iter(a, 0);
+  for (int t = it.t; t < it.end; t += it.step) {
     const int2 tl = load_tile(a, t, d);
     const int s0 = tl.y;
     const int s1 = min(s0 + a.tile_states, d.g.S);
@@ -246,9 +319,8 @@ __global__ __launch_bounds__(kBBlock) void batch_cert_kernel(BatchArgs a, int ke
 // r32 (FP32) and max |r| into residual slot 0.
 __global__ __launch_bounds__(kBBlock) void batch_resid_kernel(BatchArgs a) {
   __shared__ BInst d;
-  int t0, t1;
-  tile_range(a, 0, t0, t1);
-  for (int t = t0; t < t1; ++t) {
+  const TileIter it = tile_iter(a, 0);
+  for (int t = it.t; t < it.end; t += it.step) {
     const int2 tl = load_tile(a, t, d);
     const int s0 = tl.y;
     const int s1 = min(s0 + a.tile_states, d.g.S);
@@ -266,9 +338,8 @@ __global__ __launch_bounds__(kBBlock) void batch_resid_kernel(BatchArgs a) {
 // op 3: V64[p] += V32[e] (e = PI correction parity);  op 4: V32[0] <- 0.
 __global__ __launch_bounds__(kBBlock) void batch_util_kernel(BatchArgs a, int op) {
   __shared__ BInst d;
-  int t0, t1;
-  tile_range(a, 0, t0, t1);
-  for (int t = t0; t < t1; ++t) {
+  const TileIter it = tile_iter(a, 0);
+  for (int t = it.t; t < it.end; t += it.step) {
     const int2 tl = load_tile(a, t, d);
     const int s0 = tl.y;
     const int s1 = min(s0 + a.tile_states, d.g.S);
@@ -356,7 +427,9 @@ struct cpmdp_batch {
   int tile_states = 2048;
   int grid = kMaxBlocks;
   int k = 32;
-  std::map<std::pair<int, int>, hipGraphExec_t> graphs;   // (mode, k, tile; grid) -> exec
+  int march = 1;                      // marching tiles for instances that allow them
+  int sched = 1;                      // tile schedule (see tile_iter)
+  std::map<std::pair<int64_t, int>, hipGraphExec_t> graphs;   // (config key; grid) -> exec
   unsigned int* h_changes = nullptr;
   std::string err;
 };
@@ -488,6 +561,7 @@ BatchArgs make_args(cpmdp_batch_t* b) {
   a.ntiles = b->d_ntiles;
   a.starts = b->d_starts;
   a.tile_states = b->tile_states;
+  a.sched = b->sched;
   a.ninst = static_cast<int32_t>(b->hs.size());
   a.res = b->d_res;
   a.vmax = b->d_vmax;
@@ -497,10 +571,12 @@ BatchArgs make_args(cpmdp_batch_t* b) {
 
 // Upload the tile table: first the tiles of instances with want == 1 (the
 // FP32 group, or the only group), then those with want == 2 (FP64 group);
-// with march, instances that allow it get marching tiles.  Each group is
-// split into b->grid contiguous ranges of about equal state counts.
+// with march (and b->march), instances that allow it get marching tiles.
+// Each group is split into contiguous ranges of about equal state counts:
+// b->grid of them (schedule 0) or one per XCD (schedule 1).
 int upload_tiles(cpmdp_batch_t* b, const std::vector<char>& want, int64_t* count,
                  bool march = false) {
+  march = march && b->march;
   // h_tiles / h_ntiles / h_starts are pinned: the previous asynchronous copy
   // out of them must have run before they are refilled
   if (b->tiles_pending) {
@@ -537,14 +613,15 @@ int upload_tiles(cpmdp_batch_t* b, const std::vector<char>& want, int64_t* count
     int64_t total = 0;
     for (int64_t t = first; t < nt; ++t) total += weight[t];
     int* st = b->h_starts + (grp - 1) * (G + 1);
+    const int parts = b->sched == 0 ? G : kXcds;
     int64_t acc = 0, t = first;
     st[0] = static_cast<int>(first);
-    for (int k = 1; k <= G; ++k) {
-      const int64_t target = total * k / G;
+    for (int k = 1; k <= parts; ++k) {
+      const int64_t target = total * k / parts;
       while (t < nt && acc + weight[t] / 2 < target) acc += weight[t++];
       st[k] = static_cast<int>(t);
     }
-    st[G] = static_cast<int>(nt);
+    st[parts] = static_cast<int>(nt);
   }
   b->h_ntiles[0] = cnt[0];
   b->h_ntiles[1] = cnt[1];
@@ -575,7 +652,9 @@ int upload_descs(cpmdp_batch_t* b) {
 // k sweeps captured as one graph: value iteration (FP32 tiles, then FP64
 // tiles, per sweep) or policy-iteration correction sweeps (FP32).
 int graph_for(cpmdp_batch_t* b, int k, hipGraphExec_t* out, bool eval = false) {
-  auto key = std::make_pair((eval ? 10000000 : 0) + k * 100000 + b->tile_states, b->grid);
+  // the launches capture their arguments (tile size, schedule) and grid
+  const int64_t cfg = ((static_cast<int64_t>(eval) * 2 + b->sched) * 1000 + k) * 100000 + b->tile_states;
+  auto key = std::make_pair(cfg, b->grid);
   auto it = b->graphs.find(key);
   if (it != b->graphs.end()) {
     *out = it->second;
@@ -641,9 +720,12 @@ int launch_util(cpmdp_batch_t* b, const std::vector<char>& want, int op) {
 }
 
 // Time `reps` graph replays of k sweeps over the full batch (FP32 stage).
-int time_config(cpmdp_batch_t* b, int ts, int grid, int k, int reps, double* ms_per_sweep) {
+int time_config(cpmdp_batch_t* b, int ts, int grid, int march, int sched, int k, int reps,
+                double* ms_per_sweep) {
   b->tile_states = ts;
   b->grid = grid;
+  b->march = march;
+  b->sched = sched;
   std::vector<char> all(b->hs.size(), 1);
   for (auto& d : b->hd) {
     d.stage = B_F32;
@@ -969,9 +1051,9 @@ int cpmdp_batch_bind(cpmdp_batch_t* b, void* ws, size_t bytes, void* stream) {
     d.vec = 4;                          // every stored row holds a multiple of 4 entries
     d.axis = h->st_axis;
     d.stage = B_F32;
-    // marching tiles when the planes of fixed i_0 are large
+    // marching tiles for 4-D axis-form instances whose planes of fixed i_0 are large
     const int64_t plane = l.Sp / h->sizes[0];
-    d.mtiles = (h->n >= 2 && plane >= kBMarchMinPlane && h->sizes[0] >= 8)
+    d.mtiles = (h->n == 4 && h->st_axis && plane >= kBMarchMinPlane && h->sizes[0] >= 8)
                    ? static_cast<int32_t>((plane + kBBlock * 4 - 1) / (kBBlock * 4))
                    : 0;
     d.parity = 0;
@@ -1197,11 +1279,17 @@ int cpmdp_batch_autotune(cpmdp_batch_t* b, int tune, const char* cache_path) {
     std::string line;
     while (std::getline(f, line)) {
       std::istringstream ss(line);
-      int c, ts, grid, k;
-      if (ss >> c >> ts >> grid >> k && c == cls) {
+      int c, ts, grid, k, march = 1, sched = 0;
+      if (ss >> c >> ts >> grid >> k && c == cls && grid % kXcds == 0) {
+        if (!(ss >> march >> sched)) {
+          march = 1;
+          sched = 0;
+        }
         b->tile_states = ts;
         b->grid = grid;
         b->k = k;
+        b->march = march != 0;
+        b->sched = sched != 0;
         if (!tune) return CPMDP_OK;
       }
     }
@@ -1209,23 +1297,33 @@ int cpmdp_batch_autotune(cpmdp_batch_t* b, int tune, const char* cache_path) {
   if (!tune) return CPMDP_OK;
   // Stage-free timing on the full batch: V32 holds whatever is there (the
   // values only feed a timing run; a solve starts from the caller's V).
+  // Candidates: tile size x grid x (marching tiles or one-pass tiles only)
+  // x tile schedule.
   const int kt = 8;
   double best = INFINITY;
-  int best_ts = b->tile_states, best_grid = b->grid;
-  for (int ts : {1024, 2048, 4096, 8192}) {
-    for (int grid : {1024, 2048}) {
-      double ms = 0;
-      int rc = time_config(b, ts, grid, kt, 3, &ms);
-      if (rc) return rc;
-      if (ms < best) {
-        best = ms;
-        best_ts = ts;
-        best_grid = grid;
+  int best_ts = b->tile_states, best_grid = b->grid, best_march = b->march, best_sched = b->sched;
+  for (int sched : {0, 1}) {
+    for (int march : {1, 0}) {
+      for (int ts : {1024, 2048, 4096, 8192}) {
+        for (int grid : {1024, 2048}) {
+          double ms = 0;
+          int rc = time_config(b, ts, grid, march, sched, kt, 3, &ms);
+          if (rc) return rc;
+          if (ms < best) {
+            best = ms;
+            best_ts = ts;
+            best_grid = grid;
+            best_march = march;
+            best_sched = sched;
+          }
+        }
       }
     }
   }
   b->tile_states = best_ts;
   b->grid = best_grid;
+  b->march = best_march;
+  b->sched = best_sched;
   // host round trip (tile upload + residual read) in ms
   std::vector<double> res;
   auto t0 = std::chrono::steady_clock::now();
@@ -1249,7 +1347,8 @@ int cpmdp_batch_autotune(cpmdp_batch_t* b, int tune, const char* cache_path) {
   for (auto& d : b->hd) d.stage = B_F32;
   if (cache_path) {
     std::ofstream f(cache_path, std::ios::app);
-    f << cls << " " << b->tile_states << " " << b->grid << " " << b->k << "\n";
+    f << cls << " " << b->tile_states << " " << b->grid << " " << b->k << " " << b->march << " "
+      << b->sched << "\n";
   }
   return CPMDP_OK;
 }
@@ -1292,6 +1391,30 @@ int cpmdp_batch_config(const cpmdp_batch_t* b, int32_t* tile_states, int32_t* sw
   if (!b || !tile_states || !sweeps_per_graph) return cpm::fail(nullptr, CPMDP_E_ARG, "NULL argument");
   *tile_states = b->tile_states;
   *sweeps_per_graph = b->k;
+  return CPMDP_OK;
+}
+
+int cpmdp_batch_set_schedule(cpmdp_batch_t* b, int32_t tile_states, int32_t grid, int32_t march,
+                             int32_t sched) {
+  if (!b) return cpm::fail(nullptr, CPMDP_E_ARG, "batch is NULL");
+  if (tile_states < kMinTile || tile_states > (1 << 16) || tile_states % kMinTile ||
+      grid < kXcds || grid > kMaxBlocks || grid % kXcds || (march != 0 && march != 1) ||
+      (sched != 0 && sched != 1))
+    return bfail(b, CPMDP_E_ARG,
+                 "schedule: tile_states a multiple of 1024 in [1024, 65536], grid a multiple of "
+                 "8 in [8, 2048], march and sched 0 or 1");
+  b->tile_states = tile_states;
+  b->grid = grid;
+  b->march = march;
+  b->sched = sched;
+  return CPMDP_OK;
+}
+
+int cpmdp_batch_schedule(const cpmdp_batch_t* b, int32_t* grid, int32_t* march, int32_t* sched) {
+  if (!b || !grid || !march || !sched) return cpm::fail(nullptr, CPMDP_E_ARG, "NULL argument");
+  *grid = b->grid;
+  *march = b->march;
+  *sched = b->sched;
   return CPMDP_OK;
 }
 

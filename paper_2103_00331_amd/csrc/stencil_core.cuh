@@ -334,8 +334,8 @@ __device__ __forceinline__ void march_column(const GridGeom& g, const StencilIO<
       plus4[k] = *reinterpret_cast<const V4*>(io.V + s + ((idx[k] < g.size[k] - 1) ? st : 0));
       minus4[k] = *reinterpret_cast<const V4*>(io.V + s - ((idx[k] > 0) ? st : 0));
     }
-    stencil_vec4<T, N, MODE, AXIS, true>(g, io, W, s, idx[N - 1], cur, plus4, minus4, tol, res, res_d,
-                                   changed);
+    stencil_vec4<T, N, MODE, AXIS, true>(g, io, W, s, idx[N - 1], cur, plus4, minus4, tol, res,
+                                         res_d, changed);
     prev = cur;
     cur = nxt;
     nxt = nn;

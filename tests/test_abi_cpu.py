@@ -136,6 +136,25 @@ def test_batch_rejects_obstacles():
     B.cpmdp_destroy(h)
 
 
+def test_batch_schedule_setter_validates():
+    """Host-only: the schedule setter takes the documented values and refuses
+    others before any device work."""
+    g = I.grid_small([4, 8], seed=0)
+    h = B.cpmdp_create(*_args(g))
+    b = B.cpmdp_batch_create([h])
+    B.cpmdp_batch_set_schedule(b, 2048, 1024, 0, 1)
+    assert B.cpmdp_batch_config(b)[0] == 2048
+    assert B.cpmdp_batch_schedule(b) == (1024, 0, 1)
+    for bad in [(1000, 1024, 1, 0), (2048, 1020, 1, 0), (2048, 4096, 1, 0), (2048, 1024, 2, 0),
+                (2048, 1024, 1, 3), (1 << 17, 1024, 1, 0)]:
+        with pytest.raises(B.CpmdpError) as e:
+            B.cpmdp_batch_set_schedule(b, *bad)
+        assert e.value.code == B.CPMDP_E_ARG
+    assert B.cpmdp_batch_schedule(b) == (1024, 0, 1)
+    B.cpmdp_batch_destroy(b)
+    B.cpmdp_destroy(h)
+
+
 def test_dense_factor_size_limit():
     d = I.random_dense([40, 2], 1, 1, seed=3)
     with pytest.raises(B.CpmdpError) as e:

@@ -35,10 +35,13 @@ def _small_batch(count=14, seed=7):
     return out
 
 
-def _solve_batch(B, insts, prec, eps, tune=False, max_iter=200000, V0=None, method=0):
+def _solve_batch(B, insts, prec, eps, tune=False, max_iter=200000, V0=None, method=0,
+                 sched=None):
     bm = B.BatchModel(insts)
     if tune:
         B.cpmdp_batch_autotune(bm.b, True, None)
+    if sched is not None:
+        B.cpmdp_batch_set_schedule(bm.b, *sched)
     Vs = [torch.zeros(x.n_states, dtype=torch.float64, device="cuda") if V0 is None else
           torch.as_tensor(V0[i], dtype=torch.float64, device="cuda").clone()
           for i, x in enumerate(insts)]
@@ -135,16 +138,21 @@ def march_batch():
     return insts, refs
 
 
+# (tile states, grid, march, sched): marching tiles with either schedule,
+# one-pass tiles only with the interleaved schedule, and small tiles and grid
+@pytest.mark.parametrize("sched", [(4096, 2048, 1, 0), (4096, 2048, 1, 1), (8192, 1024, 0, 1),
+                                   (1024, 64, 1, 1)])
 @pytest.mark.parametrize("method", [0, 1])
-def test_batch_marching_tiles_match_oracle(B, march_batch, method):
-    """Instances whose planes of fixed i_0 hold >= 16384 states and whose
-    last side is a multiple of 4 get marching tiles (the whole dim-0 column of
-    1024 plane offsets per tile) next to ordinary tiles of small instances and
-    of large ones with one state per lane: VI and PI against the oracle."""
+def test_batch_marching_tiles_match_oracle(B, march_batch, method, sched):
+    """Instances whose planes of fixed i_0 hold >= 16384 states get marching
+    tiles (the whole dim-0 column of 1024 plane offsets per tile) next to
+    one-pass tiles of small instances; rows whose last side is not a multiple
+    of 4 are padded in the batch's layout.  Every tile schedule: VI and PI
+    against the oracle."""
     insts, refs = march_batch
-    log(f"[batch] marching tiles, method {method}")
+    log(f"[batch] marching tiles, method {method}, schedule {sched}")
     eps = 1e-7
-    code, out, sweeps, res = _solve_batch(B, insts, 1, eps, tune=True, method=method)
+    code, out, sweeps, res = _solve_batch(B, insts, 1, eps, method=method, sched=sched)
     assert code == B.CPMDP_OK and np.all(res <= eps)
     for x, (mats, Vs), (V, pi) in zip(insts, refs, out):
         assert_close(V, Vs, eps / (1 - x.gamma) + 1e-10, x.name)
@@ -175,11 +183,13 @@ def test_autotune_cache_roundtrip(B):
         bm = B.BatchModel(insts)
         B.cpmdp_batch_autotune(bm.b, True, path)
         cfg = B.cpmdp_batch_config(bm.b)
+        sched = B.cpmdp_batch_schedule(bm.b)
         bm.close()
         assert os.path.exists(path)
         bm2 = B.BatchModel(insts)
         B.cpmdp_batch_autotune(bm2.b, False, path)
         assert B.cpmdp_batch_config(bm2.b) == cfg
+        assert B.cpmdp_batch_schedule(bm2.b) == sched
         bm2.close()
 
 
