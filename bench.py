@@ -737,7 +737,7 @@ def bench_batch(args):
             V.zero_()
             p.zero_()
         code, sweeps, res = B.cpmdp_batch_solve(bm.b, Vs, pis, eps, 100000, B.CPMDP_FP32, method)
-        if code != B.CPMDP_OK or not np.all(res <= eps):
+        if code not in (B.CPMDP_OK, B.CPMDP_POLICY_UNSETTLED) or not np.all(res <= eps):
             bad = np.nonzero(~(res <= eps))[0]
             raise RuntimeError(f"batched solve: code {code}, {bad.size} instances above eps, "
                                f"e.g. {[(int(i), float(res[i]), int(sweeps[i])) for i in bad[:5]]}")
@@ -792,8 +792,11 @@ def bench_batch(args):
 
 def bench_warm(args):
     """64^3 GridWorlds: train the warm-start network on solver-generated
-    instances, then on held-out instances compare plain FP64 VI from V0 = 0
-    with the chosen form (network V0 + bound shift, batched FP32/FP64 solve)."""
+    instances, then on held-out instances compare, with the same solvers:
+    plain FP64 VI from V0 = 0 per instance; the chosen form (the network's
+    value level as V0, BF16 inference, one batched FP32/FP64 solve); and two
+    controls without the network, the same batched solve from V0 = 0 and
+    from V0 = 0 moved by one backup and the McQueen bound shift."""
     import numpy as np
     import torch
 
@@ -810,6 +813,7 @@ def bench_warm(args):
     w.add_instances(train, eps=eps)
     torch.cuda.synchronize()
     t_solve = time.perf_counter() - t0
+    del train
     t0 = time.perf_counter()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()          # the library runs on the current stream (see binding)
@@ -821,65 +825,76 @@ def bench_warm(args):
     # forward 2 (130*256 + 256*256 + 256) flop per sample, backward the weight
     # gradients (as many) and the input gradients of the two upper layers
     step_flops = 4096 * (2 * 2 * (130 * 256 + 256 * 256 + 256) + 2 * (256 * 256 + 256))
-    _log(f"training: {len(train)} instances generated {t_gen:.1f}s solved {t_solve:.1f}s, "
+    _log(f"training: {args.train_instances} instances generated {t_gen:.1f}s solved {t_solve:.1f}s, "
          f"{args.train_steps} steps {t_train:.1f}s, losses {losses}")
     test = [I.warm_instance(2, i) for i in range(args.test_instances)]
-    # plain GPU VI from zero, each instance alone
-    plain_s, plain_sw, models = 0.0, [], []
-    for x in test:
-        m = B.Model(x)
-        models.append(m)
-        V = torch.zeros(x.n_states, dtype=torch.float64, device="cuda")
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        code, sw, res = B.cpmdp_value_iteration(m.h, V, None, eps, 100000, B.CPMDP_FP64)
-        torch.cuda.synchronize()
-        plain_s += time.perf_counter() - t1
-        plain_sw.append(sw)
-    # warm start alone: network V0 + bound shift, FP64 VI per instance
-    warm_s, warm_sw = 0.0, []
+    models = [B.Model(x) for x in test]
+    # per instance, FP64 value iteration: plain (V0 = 0), cold + shift, network level
+    per = {"plain": [0.0, []], "shift": [0.0, []], "warm": [0.0, []]}
     for x, m in zip(test, models):
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        V = w.predict(x)
-        B.cpmdp_bound_shift(m.h, V)
-        code, sw, res = B.cpmdp_value_iteration(m.h, V, None, eps, 100000, B.CPMDP_FP64)
-        torch.cuda.synchronize()
-        warm_s += time.perf_counter() - t1
-        warm_sw.append(sw + 1)
-        assert code == B.CPMDP_OK
-    for m in models:
-        m.close()
-    # chosen: network V0 for all, then one batched mixed-precision solve
+        for kind in per:
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            V = w.predict(x) if kind == "warm" else \
+                torch.zeros(x.n_states, dtype=torch.float64, device="cuda")
+            if kind == "shift":
+                B.cpmdp_bound_shift(m.h, V)
+            code, sw, res = B.cpmdp_value_iteration(m.h, V, None, eps, 100000, B.CPMDP_FP64)
+            torch.cuda.synchronize()
+            assert code == B.CPMDP_OK
+            per[kind][0] += time.perf_counter() - t1
+            per[kind][1].append(int(sw) + (1 if kind == "shift" else 0))
+    # batched mixed-precision solves of all held-out instances from three starts
     bm = B.BatchModel(test)
     B.cpmdp_batch_autotune(bm.b, True, None)
     Vs = [torch.empty(x.n_states, dtype=torch.float64, device="cuda") for x in test]
-    for step in range(args.warmup + args.steps):
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for x, V in zip(test, Vs):
-            V.copy_(w.predict(x, bf16=True))
-        code, sw, res = B.cpmdp_batch_solve(bm.b, Vs, None, eps, 100000, B.CPMDP_FP32, 0)
-        torch.cuda.synchronize()
-        if step == args.warmup:
-            chosen_s = time.perf_counter() - t1
-            chosen_sw = sw
-        assert code == B.CPMDP_OK and np.all(res <= eps)
+    legs = {}
+    for kind in ("chosen", "cold", "cold+shift"):
+        for step in range(args.warmup + 1):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for x, V, m in zip(test, Vs, models):
+                if kind == "chosen":
+                    V.copy_(w.predict(x, bf16=True))
+                else:
+                    V.zero_()
+                    if kind == "cold+shift":
+                        B.cpmdp_bound_shift(m.h, V)
+            code, sw, res = B.cpmdp_batch_solve(bm.b, Vs, None, eps, 100000, B.CPMDP_FP32, 0)
+            torch.cuda.synchronize()
+            assert code == B.CPMDP_OK and np.all(res <= eps)
+            legs[kind] = (time.perf_counter() - t1,
+                          [int(v) + (1 if kind == "cold+shift" else 0) for v in sw])
     bm.close()
+    for m in models:
+        m.close()
+    chosen_s, chosen_sw = legs["chosen"]
+    plain_s = per["plain"][0]
     S, A = test[0].n_states, test[0].n_actions
+    _log(f"held-out sweeps (FP64 per instance): plain {sum(per['plain'][1])}, cold+shift "
+         f"{sum(per['shift'][1])}, network level {sum(per['warm'][1])}; batched: "
+         + ", ".join(f"{k} {sum(v[1])} sweeps {1e3 * v[0]:.1f} ms" for k, v in legs.items()))
     return {"metric": METRIC, "value": float(np.sum(chosen_sw)) * S * A / chosen_s,
             "unit": "state-action backups/s", "n_gpus": 1, "steps": 1, "warmup": args.warmup,
             "ms_per_step": chosen_s * 1e3, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": f"warm start on 64^3 GridWorlds ({S} states, {A} actions): "
-                                   f"{len(train)} training instances, {args.train_steps} Adam "
-                                   f"steps of 4096 samples, {len(test)} held-out instances",
+                                   f"{args.train_instances} training instances (the 20,000 of "
+                                   f"the workload's description scaled to the run), "
+                                   f"{args.train_steps} Adam steps of 4096 samples, "
+                                   f"{len(test)} held-out instances",
                        "eps": eps, "train_loss": losses[-1][1],
                        "train_seconds": {"generate": t_gen, "solve": t_solve, "train": t_train}},
             "time_to_eps_s": chosen_s, "plain_vi_time_to_eps_s": plain_s,
             "speedup_vs_plain_vi": plain_s / chosen_s,
-            "sweeps_plain": plain_sw, "sweeps_warm_fp64": warm_sw,
-            "warm_fp64_time_s": warm_s, "sweeps_chosen": [int(v) for v in chosen_sw],
+            "network_gain": {
+                "batched_time_s": {k: v[0] for k, v in legs.items()},
+                "batched_sweeps": {k: sum(v[1]) for k, v in legs.items()},
+                "speedup_vs_batched_cold_shift": legs["cold+shift"][0] / chosen_s,
+                "fp64_sweeps": {"plain": sum(per["plain"][1]), "cold+shift": sum(per["shift"][1]),
+                                "network_level": sum(per["warm"][1])},
+                "fp64_time_s": {k: v[0] for k, v in per.items()}},
+            "sweeps_plain": per["plain"][1], "sweeps_chosen": chosen_sw,
             "roofline": {"bound": "alu", "achieved": step_flops / (step_ms * 1e-3) / 1e12,
                          "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                          "frac": step_flops / (step_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS,
@@ -972,7 +987,7 @@ def main():
     ap.add_argument("--sweeps", type=int, default=20)
     ap.add_argument("--one-pass", action="store_true",
                     help="shift/identity grids: force the one-pass stencil form (no marching)")
-    ap.add_argument("--train-instances", type=int, default=512)
+    ap.add_argument("--train-instances", type=int, default=2048)
     ap.add_argument("--train-steps", type=int, default=3000)
     ap.add_argument("--test-instances", type=int, default=16)
     args = ap.parse_args()

@@ -56,6 +56,10 @@ typedef struct cpmdp_batch cpmdp_batch_t;
 typedef enum cpmdp_status {
   CPMDP_OK = 0,
   CPMDP_NOT_CONVERGED = 1,     /* warning: max_iter reached, outputs valid */
+  CPMDP_POLICY_UNSETTLED = 2,  /* warning (policy iteration): V certified, but
+                                  the last improvements still swapped actions
+                                  whose Q-values differ by less than the
+                                  evaluation error; outputs valid          */
   CPMDP_E_ARG = -1,            /* bad argument (null, size, range)          */
   CPMDP_E_NOT_STOCHASTIC = -2, /* factor row or lambda sum != 1 (1e-12)     */
   CPMDP_E_DEVICE = -3,         /* a HIP runtime call failed                 */
@@ -355,6 +359,12 @@ int cpmdp_value_iteration(cpmdp_t* h, double* V_dev, int32_t* pi_out,
  *   pi_dev : device int32 [S]; in: initial policy, out: the final policy.
  *   max_iter: cap on the total number of sweeps of any kind.
  *   outer_iters_out, sweeps_out, residual_out: nullable statistics.
+ * Returns CPMDP_OK when an improvement left pi unchanged and V is certified;
+ * CPMDP_POLICY_UNSETTLED when V was certified in three improvement rounds in
+ * a row but each still changed the policy (the evaluation is iterative, so
+ * actions whose Q-values differ by less than its error can keep swapping):
+ * V is certified and every returned action is within the tie tolerance of
+ * the best Q of the returned V; CPMDP_NOT_CONVERGED at max_iter; or an error.
  */
 int cpmdp_policy_iteration(cpmdp_t* h, double* V_dev, int32_t* pi_dev,
                            double eps, int64_t max_iter, int precision,
@@ -416,8 +426,9 @@ int cpmdp_batch_bind(cpmdp_batch_t* b, void* dev_workspace, size_t bytes,
  *   method : 0 = value iteration, 1 = policy iteration.
  *   sweeps_out   : [count] int64 sweeps per instance, or NULL.
  *   residual_out : [count] FP64 certificate per instance, or NULL.
- * Returns CPMDP_OK, CPMDP_NOT_CONVERGED if any instance hit max_iter, or an
- * error.
+ * Returns CPMDP_OK, CPMDP_NOT_CONVERGED if any instance hit max_iter, else
+ * CPMDP_POLICY_UNSETTLED if policy iteration stopped so on any instance (as
+ * in cpmdp_policy_iteration), or an error.
  */
 int cpmdp_batch_solve(cpmdp_batch_t* b, double* const* V_devs,
                       int32_t* const* pi_devs, double eps, int64_t max_iter,
@@ -512,11 +523,16 @@ int cpmdp_mlp_train_step(float* params, float* adam_m, float* adam_v, float* gra
                          void* stream, double* loss_out);
 /* V0 [m^3] (FP64) = MLP prediction / (1 - gamma), in chunks of `chunk`
  * states (workspace sized for chunk); precision as in cpmdp_mlp_forward.
- * R must hold m^3 floats and V0 m^3 doubles (not checkable here: the
- * caller's extents are unknown to the library); m^3 >= 2^31: CPMDP_E_ARG. */
+ * level = 1: the network runs on n = min(m^3, chunk, 4096) states spread
+ * evenly over the grid (state floor(j m^3 / n) for j < n) and every entry of
+ * V0 is set to the mean of their predicted values (summed in a fixed order),
+ * the instance's predicted value level; level = 0: the per-state
+ * predictions.  R must hold m^3 floats and V0 m^3
+ * doubles (not checkable here: the caller's extents are unknown to the
+ * library); m^3 >= 2^31 or level outside {0, 1}: CPMDP_E_ARG. */
 int cpmdp_mlp_predict(const float* params, const float* R, int32_t m, double gamma, double slip,
-                      double* V0, int32_t chunk, int32_t precision, void* ws, size_t ws_bytes,
-                      void* stream);
+                      double* V0, int32_t chunk, int32_t precision, int32_t level, void* ws,
+                      size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

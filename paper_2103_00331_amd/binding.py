@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libcpmdp.so")
 
 CPMDP_OK = 0
 CPMDP_NOT_CONVERGED = 1
+CPMDP_POLICY_UNSETTLED = 2
 CPMDP_E_ARG = -1
 CPMDP_E_NOT_STOCHASTIC = -2
 CPMDP_E_DEVICE = -3
@@ -100,7 +101,7 @@ _SIGS = {
                                        C.c_int32, C.c_int32, C.c_uint64, C.c_double, _p,
                                        C.c_size_t, _p, _dp]),
     "cpmdp_mlp_predict": (C.c_int, [_p, _p, C.c_int32, C.c_double, C.c_double, _p, C.c_int32,
-                                    C.c_int32, _p, C.c_size_t, _p]),
+                                    C.c_int32, C.c_int32, _p, C.c_size_t, _p]),
 }
 
 EXPORTED = sorted(_SIGS)
@@ -528,10 +529,12 @@ def cpmdp_mlp_train_step(params, adam_m, adam_v, grad, step, R_ptrs, V_ptrs, gam
 
 
 def cpmdp_mlp_predict(params, R, m, gamma, slip, V0, chunk, ws, stream=None,
-                      precision=CPMDP_FP32):
+                      precision=CPMDP_FP32, level=False):
     S = int(m) ** 3
     if R.numel() != S or V0.numel() != S or R.dtype != torch.float32 or V0.dtype != torch.float64:
         raise ValueError(f"predict on an {m}^3 grid needs float32 R and float64 V0 of {S} elements")
     return _check(lib.cpmdp_mlp_predict(_ptr(params), _ptr(R), int(m), float(gamma), float(slip),
-                                        _ptr(V0), int(chunk), int(precision), _ptr(ws),
+                                        _ptr(V0), int(chunk), int(precision), int(bool(level)),
+                                        _ptr(ws),
                                         ws.numel() * ws.element_size(), _stream_ptr(stream)))
+

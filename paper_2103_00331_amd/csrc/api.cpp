@@ -1734,7 +1734,7 @@ int cpmdp_policy_iteration(cpmdp_t* h, double* V, int32_t* pi, double eps, int64
   // tenth of the reward scale), later ones to 0.05 of the certificate
   double eps_eval = std::max(eps_floor, 1e-1 * std::max(rmax, 1e-300));
   double cert = INFINITY;
-  bool converged = false;
+  bool converged = false, unsettled = false;
   int certified = 0;
   const bool low = precision != CPMDP_FP64;
   const double floor32 =
@@ -1795,6 +1795,7 @@ int cpmdp_policy_iteration(cpmdp_t* h, double* V, int32_t* pi, double eps, int64
     if (cert <= eps) ++certified;
     if (cert <= eps && (changes == 0 || certified >= kCertifiedRounds)) {
       converged = true;
+      unsettled = changes != 0;
       break;
     }
     if (changes == 0) eps_eval = std::max(eps_floor, 0.05 * cert);
@@ -1803,7 +1804,8 @@ int cpmdp_policy_iteration(cpmdp_t* h, double* V, int32_t* pi, double eps, int64
   if (outer_out) *outer_out = outer;
   if (sweeps_out) *sweeps_out = sweeps;
   if (residual_out) *residual_out = cert;
-  return converged ? CPMDP_OK : CPMDP_NOT_CONVERGED;
+  if (!converged) return CPMDP_NOT_CONVERGED;
+  return unsettled ? CPMDP_POLICY_UNSETTLED : CPMDP_OK;
 }
 
 int cpmdp_bound_shift(cpmdp_t* h, double* V, double* lo_out, double* hi_out) {

@@ -773,7 +773,7 @@ int batch_pi(cpmdp_batch_t* b, double* const* V_devs, int32_t* const* pi_devs, d
   std::vector<int> st(n, P_RESID);
   std::vector<int64_t> sweeps(n, 0);
   std::vector<double> cert(n, INFINITY), eps_eval(n), eps_floor(n);
-  std::vector<char> converged(n, 0);
+  std::vector<char> converged(n, 0), unsettled(n, 0);
   std::vector<int> certified(n, 0);
   for (size_t i = 0; i < n; ++i) {
     cpmdp_t* h = b->hs[i];
@@ -929,6 +929,7 @@ int batch_pi(cpmdp_batch_t* b, double* const* V_devs, int32_t* const* pi_devs, d
         if (cert[i] <= eps && (changes == 0 || certified[i] >= kCertifiedRounds)) {
           st[i] = P_DONE;
           converged[i] = 1;
+          unsettled[i] = changes != 0;
         } else {
           eps_eval[i] = changes == 0 ? std::max(eps_floor[i], 0.05 * cert[i])
                                      : std::max(eps_floor[i], std::min(eps_eval[i], 0.05 * cert[i]));
@@ -940,16 +941,18 @@ int batch_pi(cpmdp_batch_t* b, double* const* V_devs, int32_t* const* pi_devs, d
     for (size_t i = 0; i < n; ++i) all_done = all_done && st[i] == P_DONE;
     if (all_done) break;
   }
-  bool all_ok = true;
+  bool all_ok = true, any_unsettled = false;
   for (size_t i = 0; i < n; ++i) {
     rc = copy_out(b, i, V_devs[i], pi_devs[i]);
     if (rc) return rc;
     if (sweeps_out) sweeps_out[i] = sweeps[i];
     if (residual_out) residual_out[i] = cert[i];
     all_ok = all_ok && converged[i];
+    any_unsettled = any_unsettled || unsettled[i];
   }
   BHIP(b, hipStreamSynchronize(b->stream));
-  return all_ok ? CPMDP_OK : CPMDP_NOT_CONVERGED;
+  if (!all_ok) return CPMDP_NOT_CONVERGED;
+  return any_unsettled ? CPMDP_POLICY_UNSETTLED : CPMDP_OK;
 }
 
 int size_class(const cpmdp_batch_t* b) {

@@ -595,6 +595,19 @@ static void launch_features_range(const float* R, int m, float gamma, float slip
                        gamma, slip, s0, count, X);
 }
 
+// n states spread evenly over an instance of S states: sample j is state
+// floor(j S / n); one thread per (sample, feature).
+__global__ void features_spread_kernel(const float* R, int m, FastDiv dm, float gamma, float slip,
+                                       int S, int n, float* X) {
+  const int64_t total = static_cast<int64_t>(n) * kF;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < total; e += stride) {
+    const int64_t j = e / kF;
+    const int st = static_cast<int>(j * S / n);
+    X[e] = feature_at(R, m, dm, gamma, slip, st, static_cast<int>(e - j * kF));
+  }
+}
+
 // Minibatch: sample i -> (instance, state) drawn with SplitMix64 from
 // (seed, step, i); features and the target (1 - gamma) V*(s).
 // One thread per (sample, feature); every thread of a sample draws the same
@@ -676,6 +689,36 @@ __global__ void to_values_kernel(const float* y, int count, double inv_scale, do
   if (i < count) V[i] = (kOutMean + kOutScale * static_cast<double>(y[i])) * inv_scale;
 }
 
+// Level of a prediction: the mean of the network's values over n sampled
+// states (the outputs y of one forward pass), summed in a fixed order
+// (kLevelBlocks strided partial sums, then the partials in order by every
+// block of the fill kernel), so repeated predictions agree bit for bit; then
+// every entry of V is set to it.
+constexpr int kLevelBlocks = 16;
+constexpr int kLevelSamples = 4096;
+
+__global__ __launch_bounds__(256) void level_partial_kernel(const float* y, int n, double* part) {
+  __shared__ double red[4];
+  double acc = 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256)
+    acc += kOutMean + kOutScale * static_cast<double>(y[i]);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+__global__ __launch_bounds__(256) void level_fill_kernel(double* V, int64_t S, const double* part,
+                                                         int nparts, int n, double inv_scale) {
+  double tot = 0.0;
+  for (int b = 0; b < nparts; ++b) tot += part[b];     // same order in every thread
+  const double level = tot / static_cast<double>(n) * inv_scale;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(256) + threadIdx.x; i < S;
+       i += static_cast<int64_t>(gridDim.x) * 256)
+    V[i] = level;
+}
+
 // ----------------------------------------------------------- workspace
 struct MlpWs {
   float *X, *H1, *H2, *y, *t, *dy, *dH1, *dH2;
@@ -683,9 +726,9 @@ struct MlpWs {
   float* part;                      // split-K partial products
 };
 
-static size_t al(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+static constexpr size_t al(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
-size_t mlp_ws_bytes(int B) {
+constexpr size_t mlp_ws_bytes(int B) {
   const size_t b = static_cast<size_t>(B);
   return al(b * kF * 4) + 4 * al(b * kH * 4) + 3 * al(b * 4) + al(b * 4) + al(64) +
          al(static_cast<size_t>(kSplitWords) * 4);
@@ -880,9 +923,10 @@ int cpmdp_mlp_train_step(float* params, float* adam_m, float* adam_v, float* gra
 }
 
 int cpmdp_mlp_predict(const float* params, const float* R, int32_t m, double gamma, double slip,
-                      double* V0, int32_t chunk, int32_t precision, void* ws, size_t ws_bytes,
-                      void* stream) {
-  if (!params || !R || !V0 || m < 1 || chunk < 1 || !ws || !(gamma < 1.0))
+                      double* V0, int32_t chunk, int32_t precision, int32_t level, void* ws,
+                      size_t ws_bytes, void* stream) {
+  if (!params || !R || !V0 || m < 1 || chunk < 1 || !ws || !(gamma < 1.0) ||
+      (level != 0 && level != 1))
     return mfail("bad predict arguments");
   if (static_cast<int64_t>(m) * m * m >= (int64_t{1} << 31))
     return mfail("predict: m^3 must be below 2^31");
@@ -892,6 +936,21 @@ int cpmdp_mlp_predict(const float* params, const float* R, int32_t m, double gam
   const hipStream_t st = static_cast<hipStream_t>(stream);
   const int S = m * m * m;
   MlpWs w = carve(ws, chunk);
+  if (level) {
+    // the network on n states spread over the grid; V0 = their mean everywhere
+    const int n = std::min(std::min(S, chunk), kLevelSamples);
+    hipLaunchKernelGGL(features_spread_kernel, dim3(feature_blocks(n)), dim3(256), 0, st, R, m,
+                       make_fastdiv(static_cast<uint32_t>(m)), static_cast<float>(gamma),
+                       static_cast<float>(slip), S, n, w.X);
+    forward(params, w.X, n, w, st, precision == CPMDP_BF16);
+    // the split-K partial area is free once the forward pass is done
+    double* part = reinterpret_cast<double*>(w.part);
+    hipLaunchKernelGGL(level_partial_kernel, dim3(kLevelBlocks), dim3(256), 0, st, w.y, n, part);
+    hipLaunchKernelGGL(level_fill_kernel, dim3(std::min(1024, (S + 255) / 256)), dim3(256), 0, st,
+                       V0, static_cast<int64_t>(S), part, kLevelBlocks, n, 1.0 / (1.0 - gamma));
+    return hipGetLastError() == hipSuccess ? CPMDP_OK
+                                           : fail(nullptr, CPMDP_E_DEVICE, "predict launch");
+  }
   for (int s0 = 0; s0 < S; s0 += chunk) {
     const int cnt = std::min(chunk, S - s0);
     launch_features_range(R, m, static_cast<float>(gamma), static_cast<float>(slip), s0, cnt, w.X,

@@ -4,8 +4,14 @@ Orchestration only: every step runs in the library's kernels (batched
 solver for the training targets, feature gather / forward / backward / Adam
 for training, forward for prediction).  Training instances come from the
 seeded generator (split 0 = train, 1 = validation, 2 = test); their solved
-values V* stay on the device.  The trained network gives V0 = MLP / (1 -
-gamma); value iteration from V0 keeps its FP64 certificate, and plain value
+values V* stay on the device.  The trained network gives per-state values
+MLP / (1 - gamma).  By default the warm start is their mean, the instance's
+predicted value level, in every state: on these GridWorlds the error that
+value iteration removes slowest from V0 = 0 is almost all a constant offset
+(rewards are i.i.d. per state, so V* sits near one level set by the best
+reward pairs anywhere in the grid), while the per-state part of a
+prediction from a 5x5x5 reward window is noise that decays only at rate
+gamma.  Value iteration from V0 keeps its FP64 certificate, and plain value
 iteration from V0 = 0 remains the fallback.
 """
 from __future__ import annotations
@@ -89,11 +95,12 @@ class WarmStart:
         return losses
 
     # ------------------------------------------------------------ inference
-    def predict(self, inst, chunk: int | None = None, bf16: bool = False):
+    def predict(self, inst, chunk: int | None = None, bf16: bool = False, level: bool = True):
         """V0 (FP64, device) for one m^3 instance; by default all states in
         one forward pass (up to 2^18 per pass), so that the forward products
         fill the chip.  bf16: hidden layers with BF16 operands (FP32
-        accumulation)."""
+        accumulation).  level: every state gets the mean prediction (see the
+        module docstring); False: the per-state predictions."""
         torch = self.torch
         self._check(inst)
         chunk = chunk or min(inst.n_states, 1 << 18)
@@ -108,7 +115,7 @@ class WarmStart:
                 self.infer_chunk = chunk
             ws = self.infer_ws
         B.cpmdp_mlp_predict(self.params, R, self.m, inst.gamma, inst.meta["slip"], V0, chunk, ws,
-                            precision=B.CPMDP_BF16 if bf16 else B.CPMDP_FP32)
+                            precision=B.CPMDP_BF16 if bf16 else B.CPMDP_FP32, level=level)
         return V0
 
     # ------------------------------------------------------------ checkpoint

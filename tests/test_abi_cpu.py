@@ -303,7 +303,10 @@ def test_mlp_precision_rejected():
     p = buf.ctypes.data
     assert B.lib.cpmdp_mlp_forward(p, p, 4, p, 5, p, 64, None) == B.CPMDP_E_ARG
     assert B.lib.cpmdp_mlp_forward(p, p, 4, p, B.CPMDP_FP64, p, 64, None) == B.CPMDP_E_ARG
-    assert B.lib.cpmdp_mlp_predict(p, p, 4, 0.9, 0.1, p, 64, 9, p, 64, None) == B.CPMDP_E_ARG
+    assert B.lib.cpmdp_mlp_predict(p, p, 4, 0.9, 0.1, p, 64, 9, 0, p, 64, None) == B.CPMDP_E_ARG
+    # level must be 0 or 1
+    assert B.lib.cpmdp_mlp_predict(p, p, 4, 0.9, 0.1, p, 64, B.CPMDP_FP32, 2, p, 1 << 40,
+                                   None) == B.CPMDP_E_ARG
 
 
 def test_mlp_rejects_oversized_grid():
@@ -312,7 +315,7 @@ def test_mlp_rejects_oversized_grid():
     buf = np.zeros(16, np.float32)
     p = buf.ctypes.data
     m = 1291                                     # 1291^3 > 2^31
-    assert B.lib.cpmdp_mlp_predict(p, p, m, 0.9, 0.1, p, 64, B.CPMDP_FP32, p, 1 << 40,
+    assert B.lib.cpmdp_mlp_predict(p, p, m, 0.9, 0.1, p, 64, B.CPMDP_FP32, 0, p, 1 << 40,
                                    None) == B.CPMDP_E_ARG
     assert B.lib.cpmdp_mlp_features(p, m, 0.9, 0.1, 0, 4, p, None) == B.CPMDP_E_ARG
     assert B.lib.cpmdp_mlp_train_step(p, p, p, p, 1, p, p, p, p, 1, m, 64, 1, 1e-3, p, 1 << 40,

@@ -82,6 +82,7 @@ def _solve(B, model, method, prec, eps, max_iter=200000):
         code, sweeps, res = B.cpmdp_value_iteration(model.h, V, pi, eps, max_iter, prec)
     else:
         code, _, sweeps, res = B.cpmdp_policy_iteration(model.h, V, pi, eps, max_iter, prec)
+        code = B.CPMDP_OK if code == B.CPMDP_POLICY_UNSETTLED else code   # V certified; pi checked below
     torch.cuda.synchronize()
     return V.cpu().numpy(), pi.cpu().numpy(), code, sweeps, res
 

@@ -169,9 +169,57 @@ def test_train_step_matches_oracle(B):
     np.testing.assert_allclose(p1[big], p1_ref[big], rtol=0, atol=2e-6)
 
 
+def _ab_sweeps(B, w, x, kinds=("cold", "shift", "warm", "warm+shift")):
+    """FP64 value iteration of instance x from several starts: cold (V0 = 0),
+    shift (V0 = 0, one backup and the McQueen bound shift: the method without
+    the network), warm (the network's value level), warm+shift.  Returns
+    {kind: (V, sweeps incl. the shift's backup, certificate)}."""
+    model = B.Model(x)
+    runs = {}
+    for kind in kinds:
+        V = w.predict(x) if kind.startswith("warm") else \
+            torch.zeros(x.n_states, dtype=torch.float64, device="cuda")
+        extra = 0
+        if kind.endswith("shift"):
+            B.cpmdp_bound_shift(model.h, V)
+            extra = 1
+        c, sw, r = B.cpmdp_value_iteration(model.h, V, None, 1e-6, 100000, B.CPMDP_FP64)
+        assert c == B.CPMDP_OK and r <= 1e-6
+        runs[kind] = (V, sw + extra, r)
+    model.close()
+    for kind in kinds[1:]:
+        diff = float((runs[kinds[0]][0] - runs[kind][0]).abs().max())
+        assert diff <= 2e-6 / (1 - x.gamma)
+    return runs
+
+
+@pytest.mark.parametrize("m,chunk", [(9, None), (9, 100), (20, None)])
+def test_predict_level_is_mean_of_sampled_states(B, m, chunk):
+    """Level mode: every state holds the mean of the network's predictions at
+    the n = min(S, chunk, 4096) states floor(j S / n); the same network's
+    per-state predictions at those states give the same mean."""
+    from paper_2103_00331_amd.warmstart import WarmStart
+    w = WarmStart(m=m, batch=256, seed=3)
+    w.params += 0.05 * torch.randn(w.params.numel(), device="cuda",
+                                   generator=torch.Generator("cuda").manual_seed(4))
+    x = I.warm_instance(2, 1, m=m)
+    S = x.n_states
+    per = w.predict(x, level=False)
+    lev = w.predict(x, chunk=chunk)
+    again = w.predict(x, chunk=chunk)
+    torch.cuda.synchronize()
+    n = min(S, chunk or S, 4096)
+    idx = (np.arange(n, dtype=np.int64) * S) // n
+    mean = float(per.cpu().numpy()[idx].mean())
+    assert float((lev - mean).abs().max()) <= 1e-5 * max(1.0, abs(mean))
+    assert torch.equal(lev, again)                     # fixed summation order
+    assert float(lev.max() - lev.min()) == 0.0
+
+
 def test_warm_start_reduces_sweeps(B):
     """Train on solved instances of the generator (small grids), then solve
-    held-out instances from V0 = 0 and from the network's V0."""
+    held-out instances from V0 = 0, from V0 = 0 with the bound shift (the
+    method without the network) and from the network's value level."""
     from paper_2103_00331_amd.warmstart import WarmStart, training_instances
     m = 12
     log("[mlp] warm start: building training set")
@@ -180,29 +228,51 @@ def test_warm_start_reduces_sweeps(B):
     losses = w.train(800, lr=1e-3, lr_final=1e-4, log_every=100)
     log(f"   losses {losses}")
     assert losses[-1][1] < 0.6 * losses[0][1]
-    cold, shifted, warm = [], [], []
+    sweeps = {k: [] for k in ("cold", "shift", "warm", "warm+shift")}
     for i in range(6):
+        runs = _ab_sweeps(B, w, I.warm_instance(2, i, m=m))
+        for k in sweeps:
+            sweeps[k].append(runs[k][1])
+    log(f"   sweeps {sweeps}")
+    # the network's own gain: fewer sweeps than the method without it
+    assert np.mean(sweeps["warm"]) < np.mean(sweeps["shift"])
+    assert np.mean(sweeps["warm"]) < np.mean(sweeps["cold"])
+
+
+def test_warm_start_64_held_out(B):
+    """The learned warm start at the workload's size (64^3, 262,144 states):
+    trained on solver-generated instances, then held-out instances solved
+    from the network's V0.  Each solve is certified; the oracle recomputes
+    the Bellman residual of the returned V and checks the returned policy;
+    and the network saves sweeps over the method without it."""
+    import oracle
+    from paper_2103_00331_amd.warmstart import WarmStart, training_instances
+    from tests.parity import compare_policy
+    m = 64
+    log("[mlp] 64^3 warm start: training set")
+    w = WarmStart(m=m, batch=4096, seed=11)
+    w.add_instances(training_instances(128, m=m, split=0))
+    losses = w.train(1500, lr=1e-3, lr_final=1e-4, log_every=500)
+    log(f"   losses {losses}")
+    cold_shift, warm = [], []
+    for i in range(3):
         x = I.warm_instance(2, i, m=m)
-        model = B.Model(x)
-        runs = {}
-        for kind in ("cold", "shift", "warm"):
-            V = w.predict(x) if kind == "warm" else \
-                torch.zeros(x.n_states, dtype=torch.float64, device="cuda")
-            extra = 0
-            if kind != "cold":
-                B.cpmdp_bound_shift(model.h, V)       # one backup + McQueen shift
-                extra = 1
-            c, sw, r = B.cpmdp_value_iteration(model.h, V, None, 1e-6, 100000, B.CPMDP_FP64)
-            assert c == B.CPMDP_OK and r <= 1e-6
-            runs[kind] = (V, sw + extra)
-        for kind in ("shift", "warm"):
-            diff = float((runs["cold"][0] - runs[kind][0]).abs().max())
-            assert diff <= 2e-6 / (1 - x.gamma)
-        cold.append(runs["cold"][1])
-        shifted.append(runs["shift"][1])
+        runs = _ab_sweeps(B, w, x, kinds=("warm", "shift"))
+        cold_shift.append(runs["shift"][1])
         warm.append(runs["warm"][1])
-        model.close()
-    log(f"   sweeps cold {cold} cold+shift {shifted} warm+shift {warm}")
-    # The gain is logarithmic in the start error (sweeps saved ~ ln(error
-    # ratio) / ln(1/gamma)); with this training set it is a few percent.
-    assert np.mean(warm) < np.mean(cold)
+        if i == 0:
+            # greedy policy of the warm-started solve, then the oracle's check
+            model = B.Model(x)
+            V = w.predict(x)
+            pi = torch.zeros(x.n_states, dtype=torch.int32, device="cuda")
+            c, sw, r = B.cpmdp_value_iteration(model.h, V, pi, 1e-6, 100000, B.CPMDP_FP64)
+            model.close()
+            assert c == B.CPMDP_OK and r <= 1e-6
+            Vh = V.cpu().numpy()
+            mats = oracle.sparse.transition_csr(x)
+            Q = oracle.sparse.q_values(x, mats, Vh)
+            r_or = float(np.max(np.abs(Q.max(0) - Vh)))
+            assert abs(r_or - r) <= 1e-12
+            compare_policy(pi.cpu().numpy(), Q, 1e-9)
+    log(f"   sweeps cold+shift {cold_shift} warm {warm}")
+    assert np.mean(warm) < np.mean(cold_shift)

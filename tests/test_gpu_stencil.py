@@ -44,6 +44,7 @@ def _solve(B, model, method, prec, eps, V0=None, pi0=None, max_iter=200000):
         outer = 0
     else:
         code, outer, sweeps, res = B.cpmdp_policy_iteration(model.h, V, pi, eps, max_iter, prec)
+        code = B.CPMDP_OK if code == B.CPMDP_POLICY_UNSETTLED else code   # V certified; pi checked below
     torch.cuda.synchronize()
     return V.cpu().numpy(), pi.cpu().numpy(), code, sweeps, res, outer
 
