@@ -533,6 +533,18 @@ int cpmdp_mlp_train_step(float* params, float* adam_m, float* adam_v, float* gra
 int cpmdp_mlp_predict(const float* params, const float* R, int32_t m, double gamma, double slip,
                       double* V0, int32_t chunk, int32_t precision, int32_t level, void* ws,
                       size_t ws_bytes, void* stream);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * prediction as cpmdp_mlp_predict, with the workspace in the library's own
+ * static device array (26.1 MiB per GPU, the workspace of 4096 rows, held
+ * until the process ends) instead of an argument.  No allocation of any
+ * kind.  chunk must be in [1, 4096], else CPMDP_E_ARG; other arguments and
+ * results as in cpmdp_mlp_predict.  Every call on one GPU uses that GPU's one
+ * array: calls that overlap on one GPU (other threads, other streams) race
+ * and must be serialized by the caller. */
+int cpmdp_mlp_predict_noalloc(const float* params, const float* R, int32_t m, double gamma,
+                              double slip, double* V0, int32_t chunk, int32_t precision,
+                              int32_t level, void* stream);
 
 #ifdef __cplusplus
 }

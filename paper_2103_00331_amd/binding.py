@@ -102,6 +102,8 @@ _SIGS = {
                                        C.c_size_t, _p, _dp]),
     "cpmdp_mlp_predict": (C.c_int, [_p, _p, C.c_int32, C.c_double, C.c_double, _p, C.c_int32,
                                     C.c_int32, C.c_int32, _p, C.c_size_t, _p]),
+    "cpmdp_mlp_predict_noalloc": (C.c_int, [_p, _p, C.c_int32, C.c_double, C.c_double, _p,
+                                            C.c_int32, C.c_int32, C.c_int32, _p]),
 }
 
 EXPORTED = sorted(_SIGS)
@@ -538,3 +540,12 @@ def cpmdp_mlp_predict(params, R, m, gamma, slip, V0, chunk, ws, stream=None,
                                         _ptr(ws),
                                         ws.numel() * ws.element_size(), _stream_ptr(stream)))
 
+
+def cpmdp_mlp_predict_noalloc(params, R, m, gamma, slip, V0, chunk, stream=None,
+                              precision=CPMDP_FP32, level=False):
+    S = int(m) ** 3
+    if R.numel() != S or V0.numel() != S or R.dtype != torch.float32 or V0.dtype != torch.float64:
+        raise ValueError(f"predict on an {m}^3 grid needs float32 R and float64 V0 of {S} elements")
+    return _check(lib.cpmdp_mlp_predict_noalloc(_ptr(params), _ptr(R), int(m), float(gamma),
+                                                float(slip), _ptr(V0), int(chunk), int(precision),
+                                                int(bool(level)), _stream_ptr(stream)))

@@ -12,6 +12,7 @@
 // Lea & Flood, OOPSLA 2014) with the Box-Muller transform for normals.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "common.cuh"
@@ -811,6 +812,38 @@ void backward(const float* P, const float* X, int B, const MlpWs& w, float* G, h
 
 int mfail(const std::string& m) { return fail(nullptr, CPMDP_E_ARG, m); }
 
+// Scratch of the allocation-free prediction (cpmdp_mlp_predict_noalloc):
+// the MLP workspace for chunks of up to kStaticRows rows, 26.1 MiB, held by
+// every GPU the library runs on until the process ends.  Host code never
+// passes `scratch` itself (its host-side name is no device address): the
+// device address comes from hipGetSymbolAddress, once per device.
+constexpr int kStaticRows = 4096;
+constexpr size_t kStaticBytes = mlp_ws_bytes(kStaticRows);
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of the current device's scratch (looked up on the first
+// call on that device, with that device current).
+int scratch_address(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxScratchDevices)
+    return fail(nullptr, CPMDP_E_DEVICE, "no current device for the static scratch");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(nullptr, CPMDP_E_DEVICE,
+                  std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return CPMDP_OK;
+}
+
 }  // namespace cpm
 
 using namespace cpm;
@@ -960,6 +993,19 @@ int cpmdp_mlp_predict(const float* params, const float* R, int32_t m, double gam
                        1.0 / (1.0 - gamma), V0 + s0);
   }
   return hipGetLastError() == hipSuccess ? CPMDP_OK : fail(nullptr, CPMDP_E_DEVICE, "predict launch");
+}
+
+int cpmdp_mlp_predict_noalloc(const float* params, const float* R, int32_t m, double gamma,
+                              double slip, double* V0, int32_t chunk, int32_t precision,
+                              int32_t level, void* stream) {
+  if (chunk < 1 || chunk > kStaticRows)
+    return mfail("predict_noalloc: chunk must be in [1, 4096] (the static scratch holds the "
+                 "workspace of 4096 rows)");
+  void* ws = nullptr;
+  const int rc = scratch_address(&ws);
+  if (rc) return rc;
+  return cpmdp_mlp_predict(params, R, m, gamma, slip, V0, chunk, precision, level, ws,
+                           kStaticBytes, stream);
 }
 
 }  // extern "C"
