@@ -1615,11 +1615,15 @@ int cpmdp_value_iteration(cpmdp_t* h, double* V, int32_t* pi_out, double eps, in
     launch_f64_to_f32(V, h->d.Va32, h->S, st);
     float* cur = h->d.Va32;
     float* alt = h->d.Vb32;
-    if (precision == CPMDP_BF16) {   // BF16 sweeps until they stall, then FP32
-      rc = run_sweeps<float>(h, false, MODE_MAX, cur, alt, h->d.R32, nullptr,
-                             std::max(eps, floor32), INFINITY, max_iter - 1, &sweeps, &done,
-                             &last, true, &trend);
+    if (precision == CPMDP_BF16) {
+      // BF16 sweeps down to about ten times their own rounding noise (the
+      // BF16 operands and intermediate leave about 1e-4 of the value scale
+      // per sweep), or until they stall, then FP32
+      const double tol16 = std::max(std::max(eps, floor32), 1e-3 * std::max(1.0, vbound));
+      rc = run_sweeps<float>(h, false, MODE_MAX, cur, alt, h->d.R32, nullptr, tol16, INFINITY,
+                             max_iter - 1, &sweeps, &done, &last, true, &trend);
       if (rc) return rc;
+      done = done && tol16 <= std::max(eps, floor32);
     }
     double tol32 = std::max(0.5 * eps, floor32);
     double cert_target = 0.5 * eps;   // FP32 residual from which the certificate is tried first
@@ -1685,9 +1689,11 @@ int cpmdp_value_iteration(cpmdp_t* h, double* V, int32_t* pi_out, double eps, in
       float* cur = h->d.E0;
       float* alt = h->d.E1;
       const double tol_e = std::max(0.25 * eps, 1e-3 * r[0]);
-      rc = run_sweeps<float>(h, false, MODE_EVAL, cur, alt, h->d.r32, pol, tol_e,
-                             precision == CPMDP_BF16 ? INFINITY : 0.0, max_iter - 1, &sweeps,
-                             &done, &last, precision == CPMDP_BF16);
+      // FP32 chains whatever the precision: each round must resolve e to
+      // 1e-3 of ||r||, about the relative rounding of a BF16 chain, which
+      // would stall there (BF16 pays in the value-iteration sweeps above)
+      rc = run_sweeps<float>(h, false, MODE_EVAL, cur, alt, h->d.r32, pol, tol_e, 0.0,
+                             max_iter - 1, &sweeps, &done, &last, false);
       if (rc) return rc;
       launch_add_f32_to_f64(V, cur, h->S, st);
     }

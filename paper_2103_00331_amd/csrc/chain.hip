@@ -92,7 +92,13 @@ typedef short s4v __attribute__((ext_vector_type(4)));
 
 // MM_F64: FP64 chains on the FP64 16x16x4 matrix product: operands as the
 // FP32 one, but result register r of lane (g, c) holds D[i = g + 4r][fiber c].
-enum { MM_VALU = 0, MM_F32 = 1, MM_BF16 = 2, MM_F64 = 3 };
+// MM_BF16 splits factor and fiber into hi + lo BF16 parts (three products);
+// MM_BF16S splits the factor only (two products on the BF16-rounded fiber)
+// and keeps the pass-1 intermediate in BF16 as well (see launch_chain).
+enum { MM_VALU = 0, MM_F32 = 1, MM_BF16 = 2, MM_F64 = 3, MM_BF16S = 4 };
+
+// The BF16 units share the operand layout of the 16x16x16 product.
+constexpr bool bf_unit(int mm) { return mm == MM_BF16 || mm == MM_BF16S; }
 
 template <typename T>
 struct AccOf;
@@ -100,6 +106,11 @@ template <>
 struct AccOf<float> { using type = f4v; };
 template <>
 struct AccOf<double> { using type = d4v; };
+
+// BF16 bit pattern of x, rounded to nearest even (hardware conversion).
+__device__ __forceinline__ uint32_t bf16_bits(float x) {
+  return static_cast<uint32_t>(__builtin_bit_cast(uint16_t, static_cast<__bf16>(x)));
+}
 
 // BF16 hi + lo split of four FP32 values (hardware round to nearest even).
 __device__ __forceinline__ void split_bf16(const float (&x)[4], s4v& hi, s4v& lo) {
@@ -123,6 +134,14 @@ __device__ __forceinline__ typename AccOf<T>::type mfma_block(const T (&x)[4], c
   } else if constexpr (MM == MM_F32) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(aw[q], x[q], acc, 0, 0, 0);
+  } else if constexpr (MM == MM_BF16S) {
+    // the factor keeps its hi + lo parts (its rounding would be the same
+    // for every fiber, a fixed error of the operator); the fiber is rounded
+    s4v bhi;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) bhi[r] = __builtin_bit_cast(short, static_cast<__bf16>(x[r]));
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo, bhi, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, bhi, acc, 0, 0, 0);
   } else {
     s4v bhi, blo;
     split_bf16(x, bhi, blo);
@@ -145,7 +164,7 @@ __device__ __forceinline__ void mode_product_mfma(const T* Xs, T* X, int outer, 
   const int nblk = (F + 15) >> 4;
   T aw[4];
   s4v ahi, alo;
-  if (MM != MM_BF16) {
+  if (!bf_unit(MM)) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int k = 4 * q + g;
@@ -161,7 +180,7 @@ __device__ __forceinline__ void mode_product_mfma(const T* Xs, T* X, int outer, 
     }
   }
   // row of the B operand held in x[j] / row of the result in acc[r]
-  auto rd_row = [&](int j) { return MM != MM_BF16 ? 4 * j + g : 4 * g + j; };
+  auto rd_row = [&](int j) { return !bf_unit(MM) ? 4 * j + g : 4 * g + j; };
   auto wr_row = [&](int r) { return MM == MM_F64 ? g + 4 * r : 4 * g + r; };
   auto block_base = [&](int b) {
     const int f = b * 16 + c;
@@ -237,7 +256,7 @@ __device__ __forceinline__ void mode_product_mfma16(const T* Xs, T* X, int outer
   const int nblk = (outer * IN) >> 4;
   T aw[4];
   s4v ahi, alo;
-  if (MM != MM_BF16) {
+  if (!bf_unit(MM)) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) aw[q] = Tk[c * 16 + 4 * q + g];
   } else {
@@ -249,7 +268,7 @@ __device__ __forceinline__ void mode_product_mfma16(const T* Xs, T* X, int outer
   }
   // rd_row(j) = 4j + g (FP32, FP64) | 4g + j (BF16);
   // wr_row(r) = g + 4r (FP64)        | 4g + r (FP32, BF16)
-  constexpr bool RD_J_HIGH = MM != MM_BF16, WR_R_HIGH = MM == MM_F64;
+  constexpr bool RD_J_HIGH = !bf_unit(MM), WR_R_HIGH = MM == MM_F64;
   constexpr int KS = IN == 1 ? 1 : IN + IN / 16;   // lpad step per row (IN != 4)
   // padded offset of row 4x + y: IN = 4: 17 x + 4 y; else (4 x + y) KS
   constexpr int HI = IN == 4 ? 17 : 4 * KS, LO = IN == 4 ? 4 : KS;
@@ -401,7 +420,7 @@ __global__ __launch_bounds__(kPass1RowsBlock) void chain_pass1_rows(ChainArgs<T>
       for (int j = 0; j < 4; ++j) {
         const int i = threadIdx.x + j * blockDim.x;
         if (i < cols_len) {
-          if (MM != MM_BF16) {
+          if (!bf_unit(MM)) {
             nf[j] = a.fac[fb + i];
           } else {
             nh[j] = a.facbf[fb + i];
@@ -418,7 +437,7 @@ __global__ __launch_bounds__(kPass1RowsBlock) void chain_pass1_rows(ChainArgs<T>
       for (int j = 0; j < 4; ++j) {
         const int i = threadIdx.x + j * blockDim.x;
         if (i < cols_len) {
-          if (MM != MM_BF16) {
+          if (!bf_unit(MM)) {
             Fs[i] = nf[j];
           } else {
             Fh[i] = nh[j];
@@ -456,7 +475,28 @@ __global__ __launch_bounds__(kPass1RowsBlock) void chain_pass1_rows(ChainArgs<T>
     // W_t[tile][r0 .. r0 + R1)[0 .. CT): q runs over whole chunks of R1 * CT
     T* Wt = a.W + static_cast<int64_t>(t) * a.g.w_term_stride;
     constexpr int VW = 16 / sizeof(T), LOG_VW = sizeof(T) == 4 ? 2 : 1;
-    if (a.g.CT >= VW && C % a.g.CT == 0) {
+    if constexpr (MM == MM_BF16S) {
+      // BF16 intermediate: units of 8 consecutive values of one chunk (R1
+      // rows x CT columns of a tile), rounded to nearest even, one 16-byte
+      // store each (the host guarantees whole chunks of a multiple of 8
+      // values, every row of the block in range and whole tiles)
+      uint16_t* Wb = reinterpret_cast<uint16_t*>(a.W) + static_cast<int64_t>(t) * a.g.w_term_stride;
+      const int ushift = chunk_shift - 3;
+      for (int qv = threadIdx.x; qv < (total >> 3); qv += blockDim.x) {
+        const int tile = qv >> ushift;
+        const int rem = (qv & ((1 << ushift) - 1)) << 3;
+        uint32_t pk[4];
+#pragma unroll
+        for (int e = 0; e < 8; e += 2) {
+          const int q0 = rem + e, q1 = rem + e + 1;
+          const T v0 = base[(q0 >> a.g.ct_shift) * slab + lpad(tile * a.g.CT + (q0 & (a.g.CT - 1)))];
+          const T v1 = base[(q1 >> a.g.ct_shift) * slab + lpad(tile * a.g.CT + (q1 & (a.g.CT - 1)))];
+          pk[e >> 1] = bf16_bits(static_cast<float>(v0)) | (bf16_bits(static_cast<float>(v1)) << 16);
+        }
+        *reinterpret_cast<uint4*>(Wb + (static_cast<int64_t>(tile) * Rr + r0) * a.g.CT + rem) =
+            make_uint4(pk[0], pk[1], pk[2], pk[3]);
+      }
+    } else if (a.g.CT >= VW && C % a.g.CT == 0) {
       // 16-byte units: VW consecutive columns of one row of one tile, one
       // vector store (the units never cross a tile, and with one pad word per
       // 16 never a pad word in LDS)
@@ -504,6 +544,33 @@ __device__ __forceinline__ void load_run(const T* __restrict__ p, T (&d)[EPT]) {
   } else {
 #pragma unroll
     for (int j = 0; j < EPT; ++j) d[j] = p[j];
+  }
+}
+
+// EPT consecutive BF16 values from p (aligned to 2 EPT bytes, at most 16)
+// widened to FP32.
+template <int EPT>
+__device__ __forceinline__ void load_run_bf16(const uint16_t* __restrict__ p, float (&d)[EPT]) {
+  auto put = [&](int j, uint32_t w) {
+    d[j] = __uint_as_float(w << 16);
+    d[j + 1] = __uint_as_float(w & 0xFFFF0000u);
+  };
+  if constexpr (EPT % 8 == 0) {
+#pragma unroll
+    for (int q = 0; q < EPT / 8; ++q) {
+      const uint4 v = reinterpret_cast<const uint4*>(p)[q];
+      put(8 * q, v.x);
+      put(8 * q + 2, v.y);
+      put(8 * q + 4, v.z);
+      put(8 * q + 6, v.w);
+    }
+  } else if constexpr (EPT == 4) {
+    const uint2 v = *reinterpret_cast<const uint2*>(p);
+    put(0, v.x);
+    put(2, v.y);
+  } else {
+    static_assert(EPT == 2, "EPT of a BF16 run: 2, 4 or a multiple of 8");
+    put(0, *reinterpret_cast<const uint32_t*>(p));
   }
 }
 
@@ -587,12 +654,29 @@ __global__ __launch_bounds__(kPass2Block) void chain_pass2(ChainArgs<T> a) {
   };
   T nx[EPT];
   auto load_tile = [&](int t) {
-    const T* Wt = a.W + static_cast<int64_t>(t) * a.g.w_term_stride + tile_off + e0;
-    if (full && vec_ok) {
-      load_run<T, EPT>(Wt, nx);
-    } else {
+    if constexpr (MM == MM_BF16S) {
+      // BF16 intermediate (pass 1 of the same unit wrote it)
+      const uint16_t* Wb = reinterpret_cast<const uint16_t*>(a.W) +
+                           static_cast<int64_t>(t) * a.g.w_term_stride + tile_off + e0;
+      if (full) {
+        float f[EPT];
+        load_run_bf16<EPT>(Wb, f);
 #pragma unroll
-      for (int j = 0; j < EPT; ++j) nx[j] = (e0 + j < TE) ? Wt[j] : T(0);
+        for (int j = 0; j < EPT; ++j) nx[j] = static_cast<T>(f[j]);
+      } else {
+#pragma unroll
+        for (int j = 0; j < EPT; ++j)
+          nx[j] = (e0 + j < TE) ? static_cast<T>(__uint_as_float(static_cast<uint32_t>(Wb[j]) << 16))
+                                : T(0);
+      }
+    } else {
+      const T* Wt = a.W + static_cast<int64_t>(t) * a.g.w_term_stride + tile_off + e0;
+      if (full && vec_ok) {
+        load_run<T, EPT>(Wt, nx);
+      } else {
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) nx[j] = (e0 + j < TE) ? Wt[j] : T(0);
+      }
     }
   };
   auto load_fac = [&](int t) {
@@ -602,7 +686,7 @@ __global__ __launch_bounds__(kPass2Block) void chain_pass2(ChainArgs<T> a) {
       for (int i = 0; i < kStageRegs; ++i) {
         const int idx = threadIdx.x + i * kPass2Block;
         if (idx < rows_len) {
-          if (MM != MM_BF16) {
+          if (!bf_unit(MM)) {
             nf[i] = a.fac[base + idx];
           } else {
             nh[i] = a.facbf[base + idx];
@@ -624,7 +708,7 @@ __global__ __launch_bounds__(kPass2Block) void chain_pass2(ChainArgs<T> a) {
       for (int i = 0; i < kStageRegs; ++i) {
         const int idx = threadIdx.x + i * kPass2Block;
         if (idx < rows_len) {
-          if (MM != MM_BF16) {
+          if (!bf_unit(MM)) {
             Fs[idx] = nf[i];
           } else {
             Fh[idx] = nh[i];
@@ -814,6 +898,7 @@ static void launch_pass1(const ChainArgs<T>& a, int mm, hipStream_t st, const La
   if constexpr (std::is_same<T, float>::value) {
     if (mm == MM_F32) return launch_pass1_m<T, 16, MM_F32>(a, st, tm);
     if (mm == MM_BF16) return launch_pass1_m<T, 16, MM_BF16>(a, st, tm);
+    if (mm == MM_BF16S) return launch_pass1_m<T, 16, MM_BF16S>(a, st, tm);
   } else {
     if (mm == MM_F64) return launch_pass1_m<T, 16, MM_F64>(a, st, tm);
   }
@@ -830,6 +915,7 @@ static void launch_pass2(const ChainArgs<T>& a, int mode, int mm, hipStream_t st
   if constexpr (std::is_same<T, float>::value) {
     if (mm == MM_F32) return launch_pass2_m<T, 16, MM_F32>(a, mode, st, tm);
     if (mm == MM_BF16) return launch_pass2_m<T, 16, MM_BF16>(a, mode, st, tm);
+    if (mm == MM_BF16S) return launch_pass2_m<T, 16, MM_BF16S>(a, mode, st, tm);
   } else {
     if (mm == MM_F64) return launch_pass2_m<T, 16, MM_F64>(a, mode, st, tm);
   }
@@ -840,6 +926,20 @@ static void launch_pass2(const ChainArgs<T>& a, int mode, int mm, hipStream_t st
   }
 }
 
+// The single-product BF16 unit (one BF16 product per block, intermediate in
+// BF16) runs when both passes exist and every mode has 8 to 16 states (the
+// relative rounding of the smaller factors' few entries would reach the BF16
+// tolerance; they keep the hi + lo split and an FP32 intermediate), and when
+// pass 1 writes whole 16-byte units: one row per wave, every row of every
+// block in range, whole tiles, 8 | R1 CT.
+static bool bf16_single_ok(const ChainGeom& g) {
+  if (g.n1 >= g.n || g.r1 <= 0) return false;
+  for (int k = 0; k < g.n; ++k)
+    if (g.size[k] < 8 || g.size[k] > 16) return false;
+  return g.Rr % g.r1 == 0 && g.C % g.CT == 0 && (g.r1 * g.CT) % 8 == 0 &&
+         (static_cast<int64_t>(g.Rr) * g.CT) % 8 == 0;
+}
+
 // tm: start recorded at the first pass, stop after the second.
 template <typename T>
 void launch_chain(const ChainArgs<T>& a, int mode, int unit, hipStream_t st,
@@ -847,8 +947,11 @@ void launch_chain(const ChainArgs<T>& a, int mode, int unit, hipStream_t st,
   const bool two = a.g.n1 < a.g.n;
   const LaunchTiming t1{tm ? tm->start : nullptr, nullptr};
   const LaunchTiming t2{two ? nullptr : (tm ? tm->start : nullptr), tm ? tm->stop : nullptr};
-  if (two) launch_pass1(a, pick_unit(a.g.mmax_col, unit), st, tm ? &t1 : nullptr);
-  launch_pass2(a, mode, pick_unit(a.g.mmax_row, unit), st, tm ? &t2 : nullptr);
+  int mm1 = pick_unit(a.g.mmax_col, unit), mm2 = pick_unit(a.g.mmax_row, unit);
+  if (std::is_same<T, float>::value && unit == CHAIN_BF16 && bf16_single_ok(a.g))
+    mm1 = mm2 = MM_BF16S;
+  if (two) launch_pass1(a, mm1, st, tm ? &t1 : nullptr);
+  launch_pass2(a, mode, mm2, st, tm ? &t2 : nullptr);
 }
 
 template void launch_chain<double>(const ChainArgs<double>&, int, int, hipStream_t,
