@@ -806,7 +806,7 @@ def bench_warm(args):
 
     eps = 1e-6
     t0 = time.perf_counter()
-    w = WarmStart(m=64, batch=4096, seed=11)
+    w = WarmStart(m=64, batch=args.train_batch, seed=11)
     train = training_instances(args.train_instances, m=64, split=0)
     t_gen = time.perf_counter() - t0
     t0 = time.perf_counter()
@@ -824,7 +824,7 @@ def bench_warm(args):
     step_ms = e0.elapsed_time(e1) / max(args.train_steps, 1)
     # forward 2 (130*256 + 256*256 + 256) flop per sample, backward the weight
     # gradients (as many) and the input gradients of the two upper layers
-    step_flops = 4096 * (2 * 2 * (130 * 256 + 256 * 256 + 256) + 2 * (256 * 256 + 256))
+    step_flops = args.train_batch * (2 * 2 * (130 * 256 + 256 * 256 + 256) + 2 * (256 * 256 + 256))
     _log(f"training: {args.train_instances} instances generated {t_gen:.1f}s solved {t_solve:.1f}s, "
          f"{args.train_steps} steps {t_train:.1f}s, losses {losses}")
     test = [I.warm_instance(2, i) for i in range(args.test_instances)]
@@ -881,7 +881,7 @@ def bench_warm(args):
             "config": {"workload": f"warm start on 64^3 GridWorlds ({S} states, {A} actions): "
                                    f"{args.train_instances} training instances (the 20,000 of "
                                    f"the workload's description scaled to the run), "
-                                   f"{args.train_steps} Adam steps of 4096 samples, "
+                                   f"{args.train_steps} Adam steps of {args.train_batch} samples, "
                                    f"{len(test)} held-out instances",
                        "eps": eps, "train_loss": losses[-1][1],
                        "train_seconds": {"generate": t_gen, "solve": t_solve, "train": t_train}},
@@ -900,7 +900,7 @@ def bench_warm(args):
                          "frac": step_flops / (step_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS,
                          "traffic": None,
                          "kernel": "one MLP train step (feature gather, 3 forward and 8 backward "
-                                   "products, loss, Adam) on 4096 sampled states, events around "
+                                   f"products, loss, Adam) on {args.train_batch} sampled states, events around "
                                    "all training steps on the library's stream",
                          "kernel_ms": step_ms, "algorithmic_flops_per_launch": step_flops}}
 
@@ -988,7 +988,8 @@ def main():
     ap.add_argument("--one-pass", action="store_true",
                     help="shift/identity grids: force the one-pass stencil form (no marching)")
     ap.add_argument("--train-instances", type=int, default=2048)
-    ap.add_argument("--train-steps", type=int, default=3000)
+    ap.add_argument("--train-steps", type=int, default=1000)
+    ap.add_argument("--train-batch", type=int, default=16384)
     ap.add_argument("--test-instances", type=int, default=16)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))

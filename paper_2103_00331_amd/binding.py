@@ -14,7 +14,9 @@ from typing import Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libcpmdp.so")
+# CPMDP_LIBRARY selects another build of the library (the sanitizer build
+# for host-side checks); by default the in-tree libcpmdp.so
+LIB_PATH = os.environ.get("CPMDP_LIBRARY") or os.path.join(_HERE, "libcpmdp.so")
 
 CPMDP_OK = 0
 CPMDP_NOT_CONVERGED = 1
