@@ -445,25 +445,73 @@ __global__ __launch_bounds__(256) void gemv_bias_kernel(int M, int K, const floa
 
 // Column sums of D [rows][N], each row weighted by wr[row] when wr is not
 // null (the bias gradients, and the output layer's weight gradient
-// H2^T dy), in two fixed-order stages: block (x, y) sums rows
-// [y rc, (y + 1) rc) of columns [64 x, 64 x + 64), each of its 4 waves every
-// 4th row, the wave sums added in wave order into part[y * N + column];
-// split_sum_kernel then adds the row chunks in order.
-__global__ __launch_bounds__(256) void colsum_kernel(const float* D, const float* wr, int rows,
-                                                     int N, int rc, float* part) {
-  __shared__ float ws[4][64];
+// H2^T dy), in two fixed-order stages.  Stage 1, N = 256 (colsum4_kernel):
+// block y sums rows [y rc, (y + 1) rc) of every column; lane l of each of its
+// 16 waves owns columns 4l .. 4l+3 (one 16-byte load per row), wave w takes
+// rows r0 + w + 16i with four rows in flight, and the wave sums are added in
+// wave order into part[y * N + column].  N = 1 (colsum1_kernel): every thread
+// of block y sums rows r0 + t + 256 i in order, then the block's threads in
+// a fixed tree.  Stage 2: split_sum_kernel adds the row chunks in order.
+constexpr int kColsumWaves = 16;
+__global__ __launch_bounds__(64 * kColsumWaves) void colsum4_kernel(const float* D, const float* wr,
+                                                                    int rows, int rc, float* part) {
+  constexpr int NW = kColsumWaves;
+  __shared__ float4 ws[NW][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int col = blockIdx.x * 64 + lane;
   const int r0 = blockIdx.y * rc, r1 = min(rows, r0 + rc);
-  float s = 0.f;
-  if (col < N)
-    for (int r = r0 + w; r < r1; r += 4) {
-      const float d = D[static_cast<int64_t>(r) * N + col];
-      s = wr ? fmaf(d, wr[r], s) : s + d;
+  float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+  const float4* D4 = reinterpret_cast<const float4*>(D) + lane;
+  auto add = [&](int r) {
+    const float4 d = D4[static_cast<int64_t>(r) * 64];
+    if (wr) {
+      const float q = wr[r];
+      s.x = fmaf(d.x, q, s.x);
+      s.y = fmaf(d.y, q, s.y);
+      s.z = fmaf(d.z, q, s.z);
+      s.w = fmaf(d.w, q, s.w);
+    } else {
+      s.x += d.x;
+      s.y += d.y;
+      s.z += d.z;
+      s.w += d.w;
     }
+  };
+  int r = r0 + w;
+  for (; r + 3 * NW < r1; r += 4 * NW) {      // four rows of this wave in flight
+    add(r);
+    add(r + NW);
+    add(r + 2 * NW);
+    add(r + 3 * NW);
+  }
+  for (; r < r1; r += NW) add(r);
   ws[w][lane] = s;
   __syncthreads();
-  if (w == 0 && col < N) part[static_cast<int64_t>(blockIdx.y) * N + col] = ((ws[0][lane] + ws[1][lane]) + ws[2][lane]) + ws[3][lane];
+  if (w == 0) {
+    float4 t = ws[0][lane];
+#pragma unroll
+    for (int q = 1; q < NW; ++q) {
+      t.x += ws[q][lane].x;
+      t.y += ws[q][lane].y;
+      t.z += ws[q][lane].z;
+      t.w += ws[q][lane].w;
+    }
+    reinterpret_cast<float4*>(part + static_cast<int64_t>(blockIdx.y) * 256)[lane] = t;
+  }
+}
+
+__global__ __launch_bounds__(256) void colsum1_kernel(const float* D, const float* wr, int rows,
+                                                      int rc, float* part) {
+  __shared__ float red[256];
+  const int r0 = blockIdx.y * rc, r1 = min(rows, r0 + rc);
+  float s = 0.f;
+  for (int r = r0 + threadIdx.x; r < r1; r += 256) s = wr ? fmaf(D[r], wr[r], s) : s + D[r];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.y] = red[0];
 }
 
 // C[i] = sum over z < ks of P[z * len + i], z in increasing order.
@@ -471,16 +519,19 @@ __global__ __launch_bounds__(256) void split_sum_kernel(const float* P, int ks, 
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= len) return;
   float s = 0.f;
-  for (int z = 0; z < ks; ++z) s += P[static_cast<int64_t>(z) * len + i];
+#pragma unroll 8
+  for (int z = 0; z < ks; ++z) s += P[static_cast<int64_t>(z) * len + i];   // loads ahead, adds in order
   C[i] = s;
 }
 
 constexpr int kSplitMax = 32;          // K slices of a split product
 constexpr int kSplitWords = kSplitMax * kH * kH;
+constexpr int kColsumChunks = 64;      // row chunks of a column sum (<= kSplitWords / kH)
 
 // Products with few output tiles and a long K (the weight and bias
-// gradients, K = batch) are split over K into slices of at most 256 blocks
-// in all, the partials (in part, kSplitWords floats) summed in slice order.
+// gradients, K = batch) are split over K into slices of at most 512 blocks
+// in all (two per CU), the partials (in part, kSplitWords floats) summed in
+// slice order.
 template <bool TA, bool TB, int EPI>
 static void gemm(int M, int N, int K, const float* A, int lda, const float* B, int ldb, float* C,
                  int ldc, const float* bias, const float* mask, int ldm, hipStream_t st,
@@ -500,7 +551,7 @@ static void gemm(int M, int N, int K, const float* A, int lda, const float* B, i
   const int tiles = ((N + TN - 1) / TN) * ((M + TM - 1) / TM);
   int ks = 1;
   if (EPI == EPI_NONE && part && tiles < 64 && K >= 2048 && ldc == N) {
-    ks = 256 / tiles;
+    ks = 512 / tiles;
     if (ks > kSplitMax) ks = kSplitMax;
     if (ks > K / 128) ks = K / 128;
     if (static_cast<int64_t>(ks) * M * N > kSplitWords) ks = static_cast<int>(kSplitWords / (M * N));
@@ -536,11 +587,15 @@ static int feature_blocks(int rows) {
 // (part: kSplitWords floats).
 static void colsum(const float* D, const float* wr, int rows, int N, float* db, float* part,
                    hipStream_t st) {
-  int ks = std::max(1, std::min(kSplitMax, rows / 128));
+  // N is 256 (the hidden layers; D 16-byte aligned) or 1 (the output layer)
+  int ks = std::max(1, std::min(kColsumChunks, rows / 256));
   const int rc = (rows + ks - 1) / ks;
   ks = (rows + rc - 1) / rc;
-  hipLaunchKernelGGL(colsum_kernel, dim3((N + 63) / 64, ks), dim3(256), 0, st, D, wr, rows, N, rc,
-                     part);
+  if (N == kH)
+    hipLaunchKernelGGL(colsum4_kernel, dim3(1, ks), dim3(64 * kColsumWaves), 0, st, D, wr, rows, rc,
+                       part);
+  else
+    hipLaunchKernelGGL(colsum1_kernel, dim3(1, ks), dim3(256), 0, st, D, wr, rows, rc, part);
   hipLaunchKernelGGL(split_sum_kernel, dim3((N + 255) / 256), dim3(256), 0, st,
                      static_cast<const float*>(part), ks, N, db);
 }
