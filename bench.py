@@ -790,6 +790,53 @@ def bench_batch(args):
             "roofline": roof}
 
 
+def _warm_leg(train_instances=512, train_steps=500, test_instances=8):
+    """Short warm-start comparison for the default line: train on solver-
+    generated 64^3 instances, then batched solves of held-out instances from
+    the network's value level, from V0 = 0 and from V0 = 0 + bound shift."""
+    import numpy as np
+    import torch
+
+    from paper_2103_00331_amd import binding as B
+    from paper_2103_00331_amd import instances as I
+    from paper_2103_00331_amd.warmstart import WarmStart, training_instances
+
+    eps = 1e-6
+    w = WarmStart(m=64, batch=16384, seed=11)
+    w.add_instances(training_instances(train_instances, m=64, split=0), eps=eps)
+    w.train(train_steps, lr=1e-3, lr_final=1e-4)
+    test = [I.warm_instance(2, i) for i in range(test_instances)]
+    models = [B.Model(x) for x in test]
+    bm = B.BatchModel(test)
+    B.cpmdp_batch_autotune(bm.b, True, None)
+    Vs = [torch.empty(x.n_states, dtype=torch.float64, device="cuda") for x in test]
+    legs = {}
+    for kind in ("warm", "cold", "cold+shift"):
+        for _ in range(2):                      # the second run is timed
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for x, V, m in zip(test, Vs, models):
+                if kind == "warm":
+                    V.copy_(w.predict(x, bf16=True))
+                else:
+                    V.zero_()
+                    if kind == "cold+shift":
+                        B.cpmdp_bound_shift(m.h, V)
+            code, sw, res = B.cpmdp_batch_solve(bm.b, Vs, None, eps, 100000, B.CPMDP_FP32, 0)
+            torch.cuda.synchronize()
+            assert code == B.CPMDP_OK and np.all(res <= eps)
+            legs[kind] = (time.perf_counter() - t1,
+                          int(np.sum(sw)) + (len(test) if kind == "cold+shift" else 0))
+    bm.close()
+    for m in models:
+        m.close()
+    return {"workload": f"64^3 GridWorlds, {train_instances} training instances, {train_steps} "
+                        f"Adam steps of 16384 samples, {test_instances} held-out instances, "
+                        "batched FP32/FP64 solves to eps = 1e-6",
+            "time_to_eps_s": {k: v[0] for k, v in legs.items()},
+            "sweeps": {k: v[1] for k, v in legs.items()}}
+
+
 def bench_warm(args):
     """64^3 GridWorlds: train the warm-start network on solver-generated
     instances, then on held-out instances compare, with the same solvers:
@@ -982,6 +1029,8 @@ def main():
     ap.add_argument("--method", default="vi", choices=["vi", "pi"])
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-warm-leg", action="store_true",
+                    help="batch512: skip the short warm-start comparison")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only the dominant kernel and a 1 GiB copy (counter passes)")
     ap.add_argument("--sweeps", type=int, default=20)
@@ -1012,6 +1061,9 @@ def main():
         out = bench_batch(args)
         if cpu_base is not None:
             out["cpu_baseline"] = cpu_base
+        if not args.no_warm_leg:
+            _log("warm-start leg")
+            out["warm_start_64"] = _warm_leg()
     elif args.workload == "warm64":
         out = bench_warm(args)
     elif args.workload == "paper2d_lists":

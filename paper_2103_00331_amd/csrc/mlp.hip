@@ -421,10 +421,16 @@ __global__ __launch_bounds__(256) void sum_parts_kernel(const float* part, int n
 // y[i] = A[i, :] w + b (the output layer, N = 1): one wave per row, each
 // lane a 16-byte piece of the row (rows 16-byte aligned, K % 4 == 0), then a
 // butterfly sum across the wave.
+// y[i] = A[i, :] . w + b; with t given also dy[i] = dscale (y[i] - t[i]), the
+// gradient of the mean squared error (fused into the output layer when the
+// training step does not report its loss).
 __global__ __launch_bounds__(256) void gemv_bias_kernel(int M, int K, const float* __restrict__ A,
                                                         int lda, const float* __restrict__ w,
                                                         const float* __restrict__ b,
-                                                        float* __restrict__ y) {
+                                                        float* __restrict__ y,
+                                                        const float* __restrict__ t = nullptr,
+                                                        float* __restrict__ dy = nullptr,
+                                                        float dscale = 0.f) {
   const int lane = threadIdx.x & 63;
   const int nw = gridDim.x * 4;
   for (int i = blockIdx.x * 4 + (threadIdx.x >> 6); i < M; i += nw) {
@@ -439,7 +445,11 @@ __global__ __launch_bounds__(256) void gemv_bias_kernel(int M, int K, const floa
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-    if (lane == 0) y[i] = acc + b[0];
+    if (lane == 0) {
+      const float yi = acc + b[0];
+      y[i] = yi;
+      if (t) dy[i] = dscale * (yi - t[i]);
+    }
   }
 }
 
@@ -671,7 +681,8 @@ __global__ void features_spread_kernel(const float* R, int m, FastDiv dm, float 
 __global__ void features_sample_kernel(const float* const* R_ptrs, const double* const* V_ptrs,
                                        const double* gammas, const double* slips, int n_inst,
                                        int m, FastDiv dm, uint64_t seed, int64_t step, int count,
-                                       float* X, float* t) {
+                                       float* X, float* t, double* loss) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *loss = 0.0;   // the step's loss accumulates later
   const int64_t total = static_cast<int64_t>(count) * kF;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
   const int S = m * m * m;
@@ -780,6 +791,7 @@ struct MlpWs {
   float *X, *H1, *H2, *y, *t, *dy, *dH1, *dH2;
   double* loss;
   float* part;                      // split-K partial products
+  float* part2;                     // column-sum partials (the side stream's)
 };
 
 static constexpr size_t al(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
@@ -787,7 +799,7 @@ static constexpr size_t al(size_t x) { return (x + 255) & ~static_cast<size_t>(2
 constexpr size_t mlp_ws_bytes(int B) {
   const size_t b = static_cast<size_t>(B);
   return al(b * kF * 4) + 4 * al(b * kH * 4) + 3 * al(b * 4) + al(b * 4) + al(64) +
-         al(static_cast<size_t>(kSplitWords) * 4);
+         al(static_cast<size_t>(kSplitWords) * 4) + al(static_cast<size_t>(kColsumChunks) * kH * 4);
 }
 
 MlpWs carve(void* ws, int B) {
@@ -809,6 +821,7 @@ MlpWs carve(void* ws, int B) {
   w.dy = reinterpret_cast<float*>(take(b * 4));
   w.loss = reinterpret_cast<double*>(take(64));
   w.part = reinterpret_cast<float*>(take(static_cast<size_t>(kSplitWords) * 4));
+  w.part2 = reinterpret_cast<float*>(take(static_cast<size_t>(kColsumChunks) * kH * 4));
   return w;
 }
 
@@ -838,31 +851,117 @@ static void forward_bf16(const float* P, const float* X, int M, const MlpWs& w, 
                      static_cast<const float*>(ypart), np, M, P + kOffB3, w.y);
 }
 
-void forward(const float* P, const float* X, int B, const MlpWs& w, hipStream_t st, bool bf16) {
+// with_dy: the output layer also writes dy, the loss gradient against w.t
+// (training steps whose loss is not read)
+void forward(const float* P, const float* X, int B, const MlpWs& w, hipStream_t st, bool bf16,
+             bool with_dy = false) {
   if (bf16) {
     forward_bf16(P, X, B, w, st);
     return;
   }
   gemm<false, false, EPI_BIAS_RELU>(B, kH, kF, X, kF, P + kOffW1, kH, w.H1, kH, P + kOffB1, nullptr, 0, st);
   gemm<false, false, EPI_BIAS_RELU>(B, kH, kH, w.H1, kH, P + kOffW2, kH, w.H2, kH, P + kOffB2, nullptr, 0, st);
+  if (with_dy) {
+    const int blocks = std::min((B + 3) / 4, 8192);
+    hipLaunchKernelGGL(gemv_bias_kernel, dim3(blocks), dim3(256), 0, st, B, kH,
+                       static_cast<const float*>(w.H2), kH, P + kOffW3, P + kOffB3, w.y,
+                       static_cast<const float*>(w.t), w.dy, 2.0f / static_cast<float>(B));
+    return;
+  }
   gemm<false, false, EPI_BIAS>(B, 1, kH, w.H2, kH, P + kOffW3, 1, w.y, 1, P + kOffB3, nullptr, 0, st);
 }
 
-// Gradient of the mean squared error (y - t)^2 over the B rows of X.
-void backward(const float* P, const float* X, int B, const MlpWs& w, float* G, hipStream_t st) {
+// dH2 = (dy w3^T) .* [H2 > 0]: the output layer's input gradient, a rank-1
+// product masked by the ReLU, as an elementwise pass over H2 (four columns
+// per thread, 16-byte loads and stores).
+__global__ __launch_bounds__(256) void rank1_mask_kernel(const float* __restrict__ dy,
+                                                         const float* __restrict__ w3,
+                                                         const float* __restrict__ H2, int rows,
+                                                         float* __restrict__ dH2) {
+  const int64_t total = static_cast<int64_t>(rows) * (kH / 4);
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < total; e += stride) {
+    const int64_t r = e / (kH / 4);
+    const int c4 = static_cast<int>(e - r * (kH / 4));
+    const float d = dy[r];
+    const float4 h = reinterpret_cast<const float4*>(H2)[e];
+    const float4 w = reinterpret_cast<const float4*>(w3)[c4];
+    float4 o;
+    o.x = h.x > 0.f ? d * w.x : 0.f;
+    o.y = h.y > 0.f ? d * w.y : 0.f;
+    o.z = h.z > 0.f ? d * w.z : 0.f;
+    o.w = h.w > 0.f ? d * w.w : 0.f;
+    reinterpret_cast<float4*>(dH2)[e] = o;
+  }
+}
+
+// Second stream of the backward pass, one per device (default priority, like
+// every stream here): the column sums run there beside the products.
+struct SideStream {
+  hipStream_t s = nullptr;
+  hipEvent_t ev[4] = {};
+};
+constexpr int kMaxSideDevices = 64;
+std::mutex g_side_mu;
+SideStream g_side[kMaxSideDevices];
+
+// The current device's side stream, created on first use; nullptr if it
+// cannot be had (the caller then runs everything on its own stream).
+SideStream* side_stream() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxSideDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_side_mu);
+  SideStream& ss = g_side[dev];
+  if (!ss.s) {
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    for (auto& e : ss.ev)
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+    ss.s = s;
+  }
+  return &ss;
+}
+
+// Gradient of the mean squared error (y - t)^2 over the B rows of X.  The
+// column sums (dw3, db3, db2, db1) read activations that are final once the
+// products before them have run, so they go to the side stream, forked and
+// joined with events, with their own partial area; the products keep the
+// caller's stream.  The same kernels in the same order per stream: the
+// result does not depend on how the two streams interleave.
+// have_dy: the forward pass already wrote dy (and the loss is not wanted).
+void backward(const float* P, const float* X, int B, const MlpWs& w, float* G, hipStream_t st,
+              bool have_dy = false) {
   const int nb = (B + 255) / 256;
-  hipLaunchKernelGGL(mse_kernel, dim3(nb), dim3(256), 0, st, w.y, w.t, B, w.dy, w.loss);
+  if (!have_dy)
+    hipLaunchKernelGGL(mse_kernel, dim3(nb), dim3(256), 0, st, w.y, w.t, B, w.dy, w.loss);
+  SideStream* ss = side_stream();
+  const hipStream_t so = ss ? ss->s : st;
+  auto fork = [&](int i) {
+    if (!ss) return;
+    (void)hipEventRecord(ss->ev[i], st);
+    (void)hipStreamWaitEvent(so, ss->ev[i], 0);
+  };
   // layer 3: dw3 = H2^T dy, db3 = 1^T dy, dH2 = (dy w3^T) .* [H2 > 0]
-  colsum(w.H2, w.dy, B, kH, G + kOffW3, w.part, st);
-  colsum(w.dy, nullptr, B, 1, G + kOffB3, w.part, st);
-  gemm<false, false, EPI_MASK>(B, kH, 1, w.dy, 1, P + kOffW3, kH, w.dH2, kH, nullptr, w.H2, kH, st);
+  fork(0);
+  colsum(w.H2, w.dy, B, kH, G + kOffW3, w.part2, so);
+  colsum(w.dy, nullptr, B, 1, G + kOffB3, w.part2, so);
+  hipLaunchKernelGGL(rank1_mask_kernel,
+                     dim3(static_cast<unsigned>(std::min<int64_t>(
+                         (static_cast<int64_t>(B) * (kH / 4) + 255) / 256, 8192))),
+                     dim3(256), 0, st, w.dy, P + kOffW3, w.H2, B, w.dH2);
   // layer 2: dW2 = H1^T dH2, db2 = 1^T dH2, dH1 = (dH2 W2^T) .* [H1 > 0]
+  fork(1);
+  colsum(w.dH2, nullptr, B, kH, G + kOffB2, w.part2, so);
   gemm<true, false, EPI_NONE>(kH, kH, B, w.H1, kH, w.dH2, kH, G + kOffW2, kH, nullptr, nullptr, 0, st, w.part);
-  colsum(w.dH2, nullptr, B, kH, G + kOffB2, w.part, st);
   gemm<false, true, EPI_MASK>(B, kH, kH, w.dH2, kH, P + kOffW2, kH, w.dH1, kH, nullptr, w.H1, kH, st);
   // layer 1: dW1 = X^T dH1, db1 = 1^T dH1
+  fork(2);
+  colsum(w.dH1, nullptr, B, kH, G + kOffB1, w.part2, so);
   gemm<true, false, EPI_NONE>(kF, kH, B, X, kF, w.dH1, kH, G + kOffW1, kH, nullptr, nullptr, 0, st, w.part);
-  colsum(w.dH1, nullptr, B, kH, G + kOffB1, w.part, st);
+  if (ss) {   // join: the caller's stream waits for the side stream's sums
+    (void)hipEventRecord(ss->ev[3], so);
+    (void)hipStreamWaitEvent(st, ss->ev[3], 0);
+  }
 }
 
 int mfail(const std::string& m) { return fail(nullptr, CPMDP_E_ARG, m); }
@@ -993,12 +1092,12 @@ int cpmdp_mlp_train_step(float* params, float* adam_m, float* adam_v, float* gra
   if (ws_bytes < mlp_ws_bytes(batch)) return fail(nullptr, CPMDP_E_WORKSPACE, "MLP workspace too small");
   const hipStream_t st = static_cast<hipStream_t>(stream);
   MlpWs w = carve(ws, batch);
-  hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, st, reinterpret_cast<float*>(w.loss), 2, 0.0f);
   hipLaunchKernelGGL(features_sample_kernel, dim3(feature_blocks(batch)), dim3(256), 0, st, R_ptrs,
                      Vstar_ptrs, gammas, slips, n_inst, m, make_fastdiv(static_cast<uint32_t>(m)),
-                     seed, step, batch, w.X, w.t);
-  forward(params, w.X, batch, w, st, false);
-  backward(params, w.X, batch, w, grad, st);
+                     seed, step, batch, w.X, w.t, w.loss);
+  // without a loss to report, the output layer writes the loss gradient too
+  forward(params, w.X, batch, w, st, false, loss_out == nullptr);
+  backward(params, w.X, batch, w, grad, st, loss_out == nullptr);
   int rc = cpmdp_mlp_adam(params, adam_m, adam_v, grad, step, lr, stream);
   if (rc) return rc;
   if (hipGetLastError() != hipSuccess) return fail(nullptr, CPMDP_E_DEVICE, "train_step launch");

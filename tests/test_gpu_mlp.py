@@ -169,6 +169,39 @@ def test_train_step_matches_oracle(B):
     np.testing.assert_allclose(p1[big], p1_ref[big], rtol=0, atol=2e-6)
 
 
+def test_train_step_without_loss_matches_with_loss(B):
+    """A training step that does not report its loss computes the loss
+    gradient inside the output layer; from the same state it must update the
+    parameters as the step that reports the loss (same samples, same
+    kernels otherwise)."""
+    m, n_inst, batch, seed, lr = 7, 3, 1000, 5, 1e-3
+    insts = [I.warm_instance(1, i, m=m) for i in range(n_inst)]
+    rng = np.random.default_rng(8)
+    R = [torch.as_tensor(x.rewards, dtype=torch.float32, device="cuda") for x in insts]
+    V = [torch.as_tensor(rng.normal(0, 3, x.n_states), dtype=torch.float64, device="cuda")
+         for x in insts]
+    Rp = torch.tensor([r.data_ptr() for r in R], dtype=torch.int64, device="cuda")
+    Vp = torch.tensor([v.data_ptr() for v in V], dtype=torch.int64, device="cuda")
+    gam = torch.tensor([x.gamma for x in insts], dtype=torch.float64, device="cuda")
+    slp = torch.tensor([x.meta["slip"] for x in insts], dtype=torch.float64, device="cuda")
+    p0 = _params(B, 9)
+    p0 += 0.05 * torch.randn(p0.numel(), device="cuda", generator=torch.Generator("cuda").manual_seed(3))
+    out = []
+    for want in (True, False):
+        p = p0.clone()
+        mm, vv, gg = torch.zeros_like(p), torch.zeros_like(p), torch.zeros_like(p)
+        B.cpmdp_mlp_train_step(p, mm, vv, gg, 1, Rp, Vp, gam, slp, n_inst, m, batch, seed, lr,
+                               _ws(B, batch), want_loss=want)
+        torch.cuda.synchronize()
+        out.append((p.cpu().numpy(), gg.cpu().numpy()))
+    (pa, ga), (pb, gb) = out
+    np.testing.assert_allclose(gb, ga, rtol=1e-5, atol=1e-6 * np.abs(ga).max())
+    # Adam moves a weight by about lr * sign(g): where g is within rounding of
+    # 0 the sign (and so the update) follows the rounding; compare elsewhere
+    big = np.abs(ga) > 1e-3 * np.abs(ga).max()
+    np.testing.assert_allclose(pb[big], pa[big], rtol=0, atol=1e-6)
+
+
 def _ab_sweeps(B, w, x, kinds=("cold", "shift", "warm", "warm+shift")):
     """FP64 value iteration of instance x from several starts: cold (V0 = 0),
     shift (V0 = 0, one backup and the McQueen bound shift: the method without
