@@ -967,7 +967,7 @@ void backward(const float* P, const float* X, int B, const MlpWs& w, float* G, h
 int mfail(const std::string& m) { return fail(nullptr, CPMDP_E_ARG, m); }
 
 // Scratch of the allocation-free prediction (cpmdp_mlp_predict_noalloc):
-// the MLP workspace for chunks of up to kStaticRows rows, 26.1 MiB, held by
+// the MLP workspace for chunks of up to kStaticRows rows, 26.2 MiB, held by
 // every GPU the library runs on until the process ends.  Host code never
 // passes `scratch` itself (its host-side name is no device address): the
 // device address comes from hipGetSymbolAddress, once per device.
