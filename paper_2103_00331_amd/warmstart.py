@@ -95,17 +95,22 @@ class WarmStart:
         return losses
 
     # ------------------------------------------------------------ inference
-    def predict(self, inst, chunk: int | None = None, bf16: bool = False, level: bool = True):
+    def predict(self, inst, chunk: int | None = None, bf16: bool = False, level: bool = True,
+                R=None, out=None):
         """V0 (FP64, device) for one m^3 instance; by default all states in
         one forward pass (up to 2^18 per pass), so that the forward products
         fill the chip.  bf16: hidden layers with BF16 operands (FP32
         accumulation).  level: every state gets the mean prediction (see the
-        module docstring); False: the per-state predictions."""
+        module docstring); False: the per-state predictions.  R: the
+        instance's rewards already on the device (FP32), else uploaded here;
+        out: an FP64 device buffer of m^3 values to write V0 into."""
         torch = self.torch
         self._check(inst)
         chunk = chunk or min(inst.n_states, 1 << 18)
-        R = torch.as_tensor(inst.rewards, dtype=torch.float32, device=self.device)
-        V0 = torch.empty(inst.n_states, dtype=torch.float64, device=self.device)
+        if R is None:
+            R = torch.as_tensor(inst.rewards, dtype=torch.float32, device=self.device)
+        V0 = out if out is not None else \
+            torch.empty(inst.n_states, dtype=torch.float64, device=self.device)
         if chunk <= self.batch:
             ws = self.ws
         else:
