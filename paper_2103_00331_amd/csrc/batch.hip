@@ -117,11 +117,19 @@ __device__ __forceinline__ double ufirst(double v) {
   return __longlong_as_double((static_cast<long long>(hi) << 32) |
                               static_cast<long long>(static_cast<uint32_t>(lo)));
 }
+// The descriptor's pointers all address global memory, but read back from
+// LDS they are generic to the compiler, which then emits flat loads: those
+// count against the LDS / scalar wait counter as well, so every wait for a
+// scalar or LDS value also drains the V loads in flight.  Rebuilding the
+// pointer in the global address space (then casting to generic) lets the
+// compiler emit global loads and stores.
 template <typename P>
 __device__ __forceinline__ P* ufirst_ptr(P* p) {
   const uint64_t b = reinterpret_cast<uint64_t>(p);
   const uint32_t lo = ufirst(static_cast<uint32_t>(b)), hi = ufirst(static_cast<uint32_t>(b >> 32));
-  return reinterpret_cast<P*>((static_cast<uint64_t>(hi) << 32) | lo);
+  using GP = __attribute__((address_space(1))) P*;
+  const GP g = (GP)((static_cast<uint64_t>(hi) << 32) | lo);
+  return (P*)g;
 }
 
 template <int N>
@@ -156,7 +164,8 @@ struct UWeights {
     for (int p = 0; p < 2 * N + 1; ++p) base[p] = ufirst(W.base[p]);
 #pragma unroll
     for (int q = 0; q < 6 * N; ++q) axis[q] = ufirst(W.axis[q]);
-    return StencilW<T>{base, axis, W.full, W.eval, ufirst(W.A), ufirst(W.gamma)};
+    return StencilW<T>{base, axis, ufirst_ptr(W.full), ufirst_ptr(W.eval), ufirst(W.A),
+                       ufirst(W.gamma)};
   }
 };
 
@@ -172,7 +181,9 @@ __device__ __forceinline__ void tile_dispatch_n(const BInst& d, const StencilIO<
     const StencilW<T> W = uw.load(W_l);
     tile_states<T, N, MODE, 4, true>(g, io, W, s0, s1, tol, res, res_d, ch);
   } else {
-    tile_states<T, N, MODE, 4, false>(g, io, W_l, s0, s1, tol, res, res_d, ch);
+    const StencilW<T> W{W_l.base, W_l.axis, ufirst_ptr(W_l.full), ufirst_ptr(W_l.eval), W_l.A,
+                        W_l.gamma};
+    tile_states<T, N, MODE, 4, false>(g, io, W, s0, s1, tol, res, res_d, ch);
   }
 }
 
