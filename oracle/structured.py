@@ -132,3 +132,43 @@ def q_at_states(inst, V, states):
                 tot += inst.lambdas[t] * float(U)
             Q[a, col] = inst.rewards[s] + cont * tot
     return Q
+
+
+def q_on_slab(inst, V, fixed):
+    """Q[a, j] for every state whose coordinate k equals fixed[k] (for each k
+    in the dict `fixed`), and those states' indices (row-major order of the
+    free coordinates, Def. 2).  Straight from the definition
+    (P_a V)(s) = sum_r lambda_{a,r} sum_j prod_k T^(k)_{a,r}[i_k, j_k] V[j]:
+    per term, V is contracted with row fixed[k] of the factor of every fixed
+    coordinate k, and the remaining factors are applied as mode products,
+    which gives the term on all states of the slab at once.  For checks of
+    whole rows or columns of instances too large for a full oracle backup."""
+    _refuse_obstacles(inst)
+    shape = tuple(int(m) for m in inst.sizes)
+    fdims = sorted(int(k) for k in fixed)
+    free = [k for k in range(inst.n_dims) if k not in fixed]
+    # fixed coordinates first (one copy), so each contraction is over axis 0
+    Vt = np.ascontiguousarray(np.moveaxis(np.asarray(V, np.float64).reshape(shape),
+                                          fdims, list(range(len(fdims)))))
+    grid = np.indices([shape[k] for k in free]).reshape(len(free), -1) if free \
+        else np.zeros((0, 1), np.int64)
+    coords = np.empty((inst.n_dims, grid.shape[1]), np.int64)
+    for k in fdims:
+        coords[k] = int(fixed[k])
+    for pos, k in enumerate(free):
+        coords[k] = grid[pos]
+    states = np.ravel_multi_index(tuple(coords), shape) if inst.n_dims else np.zeros(1, np.int64)
+    cont = inst.gamma * (1.0 - inst.terminal[states].astype(np.float64))
+    Q = np.empty((inst.n_actions, states.size))
+    for a in range(inst.n_actions):
+        tot = np.zeros([shape[k] for k in free])
+        for t in inst.terms_of(a):
+            U = Vt
+            for k in fdims:
+                U = np.tensordot(inst.factor(t, k)[int(fixed[k])], U, axes=([0], [0]))
+            for pos, k in enumerate(free):
+                U = mode_product(U, inst.factor(t, k), pos)
+            tot = tot + inst.lambdas[t] * U
+        Q[a] = inst.rewards[states] + cont * np.ravel(tot)
+    return Q, states
+

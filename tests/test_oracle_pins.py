@@ -240,6 +240,24 @@ def test_per_state_q_matches_dense(maker):
     np.testing.assert_allclose(sparse.q_at_states(inst, V, states), Qd, atol=1e-14)
 
 
+@pytest.mark.parametrize("fixed", [{0: 1, 1: 2}, {2: 1, 3: 0}, {1: 3, 3: 2}, {0: 0, 1: 1, 2: 1, 3: 2},
+                                   {}])
+def test_slab_q_matches_dense(fixed):
+    """The slab spot check (fixed coordinates contracted with factor rows,
+    the rest applied as mode products) against O1's reconstructed dense P_a,
+    on leading, trailing, interleaved, complete and empty sets of fixed
+    coordinates."""
+    inst = I.random_dense([2, 4, 3, 3], 3, [2, 1, 3], seed=15, n_terminal=3)
+    V = I.seeded_values(inst.n_states, 16)
+    Qd = dense.q_values(inst, dense.transition_matrices(inst), V)
+    Q, states = structured.q_on_slab(inst, V, fixed)
+    coords = np.array([_coords(inst.sizes, int(s)) for s in range(inst.n_states)])
+    want = np.nonzero(np.all([coords[:, k] == v for k, v in fixed.items()], axis=0))[0] \
+        if fixed else np.arange(inst.n_states)
+    np.testing.assert_array_equal(np.sort(states), want)
+    np.testing.assert_allclose(Q, Qd[:, states], atol=1e-14)
+
+
 def test_greedy_rule_ties_and_incumbent():
     Q = np.array([[1.0, 2.0, 3.0], [1.0, 2.5, 3.0 - 1e-13], [0.5, 2.5, 2.0]])
     V = np.zeros(3)
