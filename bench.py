@@ -60,6 +60,8 @@ def _sha(paths):
 STENCIL_SRC = ["paper_2103_00331_amd/csrc/stencil.hip", "paper_2103_00331_amd/csrc/stencil_core.cuh",
                "paper_2103_00331_amd/csrc/common.cuh"]
 CHAIN_SRC = ["paper_2103_00331_amd/csrc/chain.hip", "paper_2103_00331_amd/csrc/common.cuh"]
+# BF16 max sweeps of 16^6 grids run the register-resident unit
+CHAIN16_SRC = ["paper_2103_00331_amd/csrc/chain16.hip", "paper_2103_00331_amd/csrc/common.cuh"]
 BATCH_SRC = ["paper_2103_00331_amd/csrc/batch.hip", "paper_2103_00331_amd/csrc/stencil_core.cuh",
              "paper_2103_00331_amd/csrc/common.cuh"]
 LISTS_SRC = ["paper_2103_00331_amd/csrc/lists.hip", "paper_2103_00331_amd/csrc/common.cuh"]
@@ -475,9 +477,11 @@ def bench_dense(args):
     Vb = torch.zeros_like(Va)
     ms = B.cpmdp_time_sweeps(model.h, Va, Vb, 10, prec, 0)
     flops = 2.0 * inst.n_terms * sum(int(m) for m in inst.sizes) * S
-    # HBM: every term's intermediate written by pass 1 and read by pass 2,
-    # plus V (both passes), R and V'
-    w_bytes = (2.0 * inst.n_terms + 4.0) * S * (8 if prec == B.CPMDP_FP64 else 4)
+    # HBM: every term's intermediate written by pass 1 and read by pass 2
+    # (BF16 values in the BF16 unit), plus V (both passes), R and V'
+    word = 8 if prec == B.CPMDP_FP64 else 4
+    w_bytes = (2.0 * inst.n_terms * (2 if prec == B.CPMDP_BF16 else word) + 4.0 * word) * S
+    bf16r = prec == B.CPMDP_BF16   # 16^6 split 3 + 3: the register-resident BF16 unit
     peak = PEAK_TFLOPS[args.precision]
     eps = 1e-6
     V = torch.zeros(S, dtype=torch.float64, device="cuda")
@@ -516,8 +520,10 @@ def bench_dense(args):
            "roofline": {"bound": "mfma", "achieved": flops / (ms * 1e-3) / 1e12,
                         "peak": peak, "unit": "TFLOP/s",
                         "frac": flops / (ms * 1e-3) / 1e12 / peak,
-                        "traffic": _traffic(f"chain_{args.precision}_dense6_16.md", CHAIN_SRC),
-                        "kernel": "chain_pass1_rows + chain_pass2 (one sweep)",
+                        "traffic": _traffic(f"chain_{args.precision}_dense6_16.md",
+                                            CHAIN16_SRC if bf16r else CHAIN_SRC),
+                        "kernel": ("chain16_pass1 + chain16_pass2 (one sweep)" if bf16r
+                                   else "chain_pass1_rows + chain_pass2 (one sweep)"),
                         "kernel_ms": ms, "algorithmic_flops_per_launch": flops,
                         "intermediate_bytes_per_launch": w_bytes,
                         "hbm_rate_gbs": w_bytes / (ms * 1e-3) / 1e9}}

@@ -27,7 +27,7 @@ SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=und
              "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer",
              "-Xarch_host", "-g"]
 
-SOURCES = ["api.cpp", "batch.hip", "stencil.hip", "chain.hip", "util.hip", "lists.hip", "tt.hip", "cpfit.hip",
+SOURCES = ["api.cpp", "batch.hip", "stencil.hip", "chain.hip", "chain16.hip", "util.hip", "lists.hip", "tt.hip", "cpfit.hip",
            "mlp.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

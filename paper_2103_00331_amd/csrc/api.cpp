@@ -1619,10 +1619,27 @@ int cpmdp_value_iteration(cpmdp_t* h, double* V, int32_t* pi_out, double eps, in
       // BF16 sweeps down to about ten times their own rounding noise (the
       // BF16 operands and intermediate leave about 1e-4 of the value scale
       // per sweep), or until they stall, then FP32
-      const double tol16 = std::max(std::max(eps, floor32), 1e-3 * std::max(1.0, vbound));
+      double tol16 = std::max(std::max(eps, floor32), 1e-3 * std::max(1.0, vbound));
       rc = run_sweeps<float>(h, false, MODE_MAX, cur, alt, h->d.R32, nullptr, tol16, INFINITY,
                              max_iter - 1, &sweeps, &done, &last, true, &trend);
       if (rc) return rc;
+      // rmax / (1 - gamma) overstates ||V*|| when rewards take both signs:
+      // bound it from the iterate, ||V*|| <= ||V|| + r / (1 - gamma), and go
+      // on in BF16 to 1e-3 of that bound (still about ten times the noise)
+      // while it lies well below the first tolerance
+      if (done && std::isfinite(last) && sweeps < max_iter - 1) {
+        double vm = 0.0;
+        rc = maxabs_f32(h, cur, &vm);
+        if (rc) return rc;
+        const double tol16b = std::max(std::max(eps, floor32),
+                                       1e-3 * std::max(1.0, vm + last / (1.0 - h->gamma)));
+        if (tol16b < 0.5 * tol16) {
+          tol16 = tol16b;
+          rc = run_sweeps<float>(h, false, MODE_MAX, cur, alt, h->d.R32, nullptr, tol16, INFINITY,
+                                 max_iter - 1, &sweeps, &done, &last, true, &trend);
+          if (rc) return rc;
+        }
+      }
       done = done && tol16 <= std::max(eps, floor32);
     }
     double tol32 = std::max(0.5 * eps, floor32);

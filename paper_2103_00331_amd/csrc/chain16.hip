@@ -1,0 +1,362 @@
+// K2, register-resident BF16 unit for grids of six modes of 16 states (both
+// groups three modes of 16, so one row of pass 1 and one column of pass 2 is
+// a 16 x 16 x 16 tensor of 4096 values).
+//
+// The operator is the one of the two-pass chain: pass 1 applies the column
+// group's factors of every term to each row of V (minus the midrange shift),
+// pass 2 the row group's factors to each column of the intermediate, scales
+// by the term weight, sums the terms of an action and takes the max over
+// actions, then forms Eq. 1's V' and the sup-norm residual (the CP form of
+// Sec. 2.2 applied without forming P_a).  The BF16 rounding points are those
+// of the single-product BF16 unit: each mode product rounds its input fiber
+// to BF16 once and multiplies it by the factor in hi + lo parts with FP32
+// accumulation; the intermediate is held in BF16.
+//
+// Instead of running each mode product through LDS with a barrier between
+// modes, a wave keeps its whole 16^3 tensor in registers (64 BF16 values per
+// lane, packed in pairs) and chains the matrix products directly.  With the
+// 16 x 16 x 16 BF16 product (lane l = 16 g + c holds A[c][4g..4g+3],
+// B[4g..4g+3][c] and returns D[4g..4g+3][c]), a block X[p][q] held as
+// "lane (g, c), register i = X[4g + i][c]" is both a valid A operand (as
+// X^T) and a valid B operand:
+//   A form  D = X^T F^T : contracts p, result block (q, new index);
+//   B form  D = F X     : contracts p, result block (new index, q);
+// the factor registers (F[c][4g..4g+3]) are the same in both.  Two A-form
+// products contract the two in-block indices; the third index is the block
+// number (16 blocks per lane), which a 4 x 4 exchange of lane groups against
+// block numbers (v_permlane32_swap / v_permlane16_swap, plus a swap of BF16
+// halves) moves into the block's row, where the last product contracts it.
+//
+//   pass 1 (8 rows per block, one per wave): row r's tensor Z[x3][x4][x5]
+//     starts as blocks b = x3, X[p = x4][q = x5]; A(T4), A(T5), exchange,
+//     A(T3) leave y[y3][y4][y5] with y3 = c, y4 = b, y5 = 4g + i: four
+//     consecutive columns per lane and block, stored to the wave's LDS row
+//     (8-byte stores, padded by 8 values per 256 so the 64 lanes hit distinct
+//     banks); the block then writes the intermediate tile by tile, 8 rows x
+//     8 columns = one 128-byte line per tile: layout [term][tile][row][8].
+//     (Tiles of 4 columns would need 16 rows per block for whole lines, and
+//     a 16-row block fills a CU's LDS alone; half-line writes measured worse.)
+//   pass 2 (half a tile, 4 columns, per block, one column per wave; two blocks
+//     per CU, so one computes while the other waits for its next tile; the
+//     two halves of a tile are neighbouring blocks on one XCD and share its
+//     lines in L2): the 8-byte halves of the tile's rows are copied into 4 LDS
+//     column arrays (padded as above); column cc's tensor
+//     X[x0][x1][x2] is read as blocks b = x1, X[p = x2][q = x0] (four
+//     consecutive rows per 8-byte LDS read); A(T2), A(T0), exchange, then
+//     B(lambda T1) accumulates straight into the action's FP32 sum (the
+//     matrix product's accumulator input), which leaves y0 = c, y1 = 4g + i,
+//     y2 = b.
+#include "common.cuh"
+
+namespace cpm {
+
+namespace {
+
+typedef short s4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
+typedef uint32_t u2v __attribute__((ext_vector_type(2)));
+
+constexpr int kFib = 4096;      // values of one row (pass 1) / one column (pass 2)
+constexpr int kP1Rows = 8;      // pass 1: rows per block, one per wave
+constexpr int kTile = 8;        // columns per tile of the intermediate
+constexpr int kP2Cols = 4;      // pass 2: columns per block (half a tile), one per wave
+// LDS arrays: 4096 values + 8 per 256 (pad16); the pass-1 rows get a few more
+// so that the rows of an 8-byte read by half a wave fall on distinct banks.
+constexpr int kColArr = kFib + 16 * 8;                        // 4224
+constexpr int kSlab = kColArr + (kP1Rows == 16 ? 8 : 16);     // 4232 / 4240
+
+__device__ __forceinline__ int pad16(int v) { return v + ((v >> 8) << 3); }
+
+// Two FP32 values as a packed BF16 pair (round to nearest even), a low.
+__device__ __forceinline__ uint32_t pk(float a, float b) {
+  const bf2v p = {static_cast<__bf16>(a), static_cast<__bf16>(b)};
+  return __builtin_bit_cast(uint32_t, p);
+}
+
+__device__ __forceinline__ s4v op(uint32_t lo, uint32_t hi) {
+  const u2v v = {lo, hi};
+  return __builtin_bit_cast(s4v, v);
+}
+
+__device__ __forceinline__ f4v mfma(s4v a, s4v b, f4v c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// Factor registers of mode k of term t: F[c][4g .. 4g + 3] as BF16 hi and lo.
+struct Fac16 {
+  s4v hi, lo;
+};
+
+__device__ __forceinline__ Fac16 fac16(const ChainArgs<float>& a, int t, int k, int lane) {
+  const int64_t o = static_cast<int64_t>(t) * a.g.term_stride + a.g.fac_off[k] + (lane & 15) * 16 +
+                    4 * (lane >> 4);
+  Fac16 f;
+  f.hi = *reinterpret_cast<const s4v*>(a.facbf + o);
+  f.lo = *reinterpret_cast<const s4v*>(a.facbf_lo + o);
+  return f;
+}
+
+// The FP32 factor values F[c][4g .. 4g + 3] of mode k of term t.
+__device__ __forceinline__ float4 fac32(const ChainArgs<float>& a, int t, int k, int lane) {
+  const int64_t o = static_cast<int64_t>(t) * a.g.term_stride + a.g.fac_off[k] + (lane & 15) * 16 +
+                    4 * (lane >> 4);
+  return *reinterpret_cast<const float4*>(a.fac + o);
+}
+
+// lambda times the FP32 factor values v, split into BF16 hi + lo.
+__device__ __forceinline__ Fac16 split_scaled(float4 v, float lam) {
+  const float x[4] = {lam * v.x, lam * v.y, lam * v.z, lam * v.w};
+  Fac16 f;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const __bf16 h = static_cast<__bf16>(x[r]);
+    f.hi[r] = __builtin_bit_cast(short, h);
+    f.lo[r] = __builtin_bit_cast(short, static_cast<__bf16>(x[r] - static_cast<float>(h)));
+  }
+  return f;
+}
+
+// One A-form product per block: u[b] <- BF16(X_b^T F^T) in place.
+__device__ __forceinline__ void aform16(uint32_t (&u)[16][2], const Fac16& f) {
+#pragma unroll
+  for (int b = 0; b < 16; ++b) {
+    const s4v x = op(u[b][0], u[b][1]);
+    f4v d = {0.f, 0.f, 0.f, 0.f};
+    d = mfma(x, f.lo, d);
+    d = mfma(x, f.hi, d);
+    u[b][0] = pk(d[0], d[1]);
+    u[b][1] = pk(d[2], d[3]);
+  }
+}
+
+// u[b][h] holds X[b][p][c] for p = 4g + 2h + e (BF16 half e).  Afterwards it
+// holds X'[b][p][c] = X[p][b][c]: block number and block row trade places.
+// (a) for each (b mod 4, h), the four registers b = 4m + b mod 4 are
+//     transposed against the four lane groups (32-lane, then 16-lane swaps);
+// (b) BF16 halves are exchanged between register pairs.
+__device__ __forceinline__ void exchange16(uint32_t (&u)[16][2]) {
+  uint32_t R[4][2][4];
+#pragma unroll
+  for (int bl = 0; bl < 4; ++bl) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      uint32_t x0 = u[bl][h], x1 = u[4 + bl][h], x2 = u[8 + bl][h], x3 = u[12 + bl][h];
+      auto s02 = __builtin_amdgcn_permlane32_swap(x0, x2, false, false);
+      auto s13 = __builtin_amdgcn_permlane32_swap(x1, x3, false, false);
+      auto s01 = __builtin_amdgcn_permlane16_swap(s02[0], s13[0], false, false);
+      auto s23 = __builtin_amdgcn_permlane16_swap(s02[1], s13[1], false, false);
+      R[bl][h][0] = s01[0];
+      R[bl][h][1] = s01[1];
+      R[bl][h][2] = s23[0];
+      R[bl][h][3] = s23[1];
+    }
+  }
+#pragma unroll
+  for (int bh = 0; bh < 4; ++bh) {
+#pragma unroll
+    for (int bm = 0; bm < 2; ++bm) {
+#pragma unroll
+      for (int H = 0; H < 2; ++H) {
+        const uint32_t lo = R[2 * H][bm][bh], hi = R[2 * H + 1][bm][bh];
+        u[4 * bh + 2 * bm][H] = (lo & 0xFFFFu) | (hi << 16);
+        u[4 * bh + 2 * bm + 1][H] = (lo >> 16) | (hi & 0xFFFF0000u);
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(kP1Rows * 64) void chain16_pass1(ChainArgs<float> a) {
+  __shared__ __align__(16) uint16_t slab[kP1Rows * kSlab];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int c = lane & 15, g = lane >> 4;
+  const int r0 = xcd_block(blockIdx.x, gridDim.x) * kP1Rows;
+  const float cs = a.shift_keys ? midrange(a.shift_keys) : 0.f;
+  // row r0 + w of V - cs, blocks b = x3 with X[p = x4][q = x5]: lane (g, c)
+  // register (b, i) holds offset 256 b + 16 (4 g + i) + c
+  uint32_t v[16][2];
+  {
+    const float* Vr = a.V + static_cast<int64_t>(r0 + w) * kFib + 64 * g + c;
+#pragma unroll
+    for (int b = 0; b < 16; ++b) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        v[b][h] = pk(Vr[256 * b + 32 * h] - cs, Vr[256 * b + 32 * h + 16] - cs);
+    }
+  }
+  uint16_t* my = slab + w * kSlab + pad16(256 * c + 4 * g);
+  uint16_t* Wb = reinterpret_cast<uint16_t*>(a.W);
+  const int64_t S = a.g.S, Rr = a.g.Rr;
+  // The next term's factors are loaded just before this term's stores: loads
+  // and stores retire in order, so waiting for the factors never waits for
+  // the stores (the scheduling barriers keep that order).
+  Fac16 f3 = fac16(a, 0, 3, lane), f4 = fac16(a, 0, 4, lane), f5 = fac16(a, 0, 5, lane);
+  for (int t = 0; t < a.nterms; ++t) {
+    uint32_t u[16][2];
+#pragma unroll
+    for (int b = 0; b < 16; ++b) {     // A(T4): (p = x5, q = y4)
+      const s4v x = op(v[b][0], v[b][1]);
+      f4v d = {0.f, 0.f, 0.f, 0.f};
+      d = mfma(x, f4.lo, d);
+      d = mfma(x, f4.hi, d);
+      u[b][0] = pk(d[0], d[1]);
+      u[b][1] = pk(d[2], d[3]);
+    }
+    aform16(u, f5);                    // (p = y4, q = y5)
+    exchange16(u);                     // blocks y4, (p = x3, q = y5)
+#pragma unroll
+    for (int b = 0; b < 16; ++b) {     // A(T3): (p = y5, q = y3); column 256 c + 16 b + 4 g + i
+      const s4v x = op(u[b][0], u[b][1]);
+      f4v d = {0.f, 0.f, 0.f, 0.f};
+      d = mfma(x, f3.lo, d);
+      d = mfma(x, f3.hi, d);
+      const u2v p = {pk(d[0], d[1]), pk(d[2], d[3])};
+      *reinterpret_cast<u2v*>(my + 16 * b) = p;
+    }
+    __syncthreads();
+    {
+      const int tn = min(t + 1, a.nterms - 1);
+      f3 = fac16(a, tn, 3, lane);
+      f4 = fac16(a, tn, 4, lane);
+      f5 = fac16(a, tn, 5, lane);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // the block's rows, tile by tile: unit q = (tile, row), 16 bytes each
+    uint16_t* Wt = Wb + static_cast<int64_t>(t) * S;
+    constexpr int kUnits = (kFib / kTile) * kP1Rows;   // 16-byte units of the block
+#pragma unroll
+    for (int j = 0; j < kUnits / (kP1Rows * 64); ++j) {
+      const int q = threadIdx.x + j * (kP1Rows * 64);
+      const int tl = q / kP1Rows, ww = q % kP1Rows;
+      const uint4 val = *reinterpret_cast<const uint4*>(slab + ww * kSlab + pad16(kTile * tl));
+      *reinterpret_cast<uint4*>(Wt + (static_cast<int64_t>(tl) * Rr + r0 + ww) * kTile) = val;
+    }
+    __syncthreads();
+  }
+}
+
+// two waves per SIMD: two blocks of four waves per CU
+__global__ __launch_bounds__(kP2Cols * 64, 2) void chain16_pass2(ChainArgs<float> a) {
+  __shared__ __align__(16) uint16_t cols[kP2Cols * kColArr];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int c = lane & 15, g = lane >> 4;
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int tile = blk >> 1, half = blk & 1;
+  const int64_t S = a.g.S;
+  const uint16_t* Wb = reinterpret_cast<const uint16_t*>(a.W) + static_cast<int64_t>(tile) * kFib * kTile +
+                       threadIdx.x * 2 * kTile + half * kP2Cols;
+  // this block's halves of rows 2u and 2u + 1 of the tile, u = j * 256 + thread
+  constexpr int kLoads = kFib / 2 / (kP2Cols * 64);
+  uint4 nx[kLoads];
+  auto load = [&](int t) {
+    const uint16_t* p = Wb + static_cast<int64_t>(t) * S;
+#pragma unroll
+    for (int j = 0; j < kLoads; ++j) {
+      const u2v r0h = *reinterpret_cast<const u2v*>(p + j * (kP2Cols * 64) * 2 * kTile);
+      const u2v r1h = *reinterpret_cast<const u2v*>(p + j * (kP2Cols * 64) * 2 * kTile + kTile);
+      nx[j] = make_uint4(r0h[0], r0h[1], r1h[0], r1h[1]);
+    }
+  };
+  f4v acc[16], best[16];
+#pragma unroll
+  for (int b = 0; b < 16; ++b) {
+    acc[b] = f4v{0.f, 0.f, 0.f, 0.f};
+    best[b] = f4v{-INFINITY, -INFINITY, -INFINITY, -INFINITY};
+  }
+  const float cs = a.shift_keys ? midrange(a.shift_keys) : 0.f;
+  const uint16_t* mc = cols + w * kColArr + pad16(256 * c + 4 * g);
+  int act = 0;
+  if (a.nterms > 0) load(0);
+  for (int t = 0; t < a.nterms; ++t) {
+    __syncthreads();   // the previous term's column reads are done
+#pragma unroll
+    for (int j = 0; j < kLoads; ++j) {
+      // rows 2u (words x, y) and 2u + 1 (words z, w), columns 0..3; column e
+      // gets the pair (row 2u, row 2u + 1) as one 4-byte store
+      const int pr = pad16(2 * (j * (kP2Cols * 64) + static_cast<int>(threadIdx.x)));
+      const uint32_t r0w[2] = {nx[j].x, nx[j].y}, r1w[2] = {nx[j].z, nx[j].w};
+#pragma unroll
+      for (int e = 0; e < kP2Cols; ++e) {
+        const uint32_t lo = (e & 1) ? (r0w[e >> 1] >> 16) : (r0w[e >> 1] & 0xFFFFu);
+        const uint32_t hi = (e & 1) ? (r1w[e >> 1] & 0xFFFF0000u) : (r1w[e >> 1] << 16);
+        *reinterpret_cast<uint32_t*>(cols + e * kColArr + pr) = lo | hi;
+      }
+    }
+    __syncthreads();
+    // the term's factors are loaded before the next tile (loads retire in
+    // order), so the products wait for them and not for the prefetch, which
+    // overlaps them (the scheduling barriers keep that order)
+    const Fac16 f2 = fac16(a, t, 2, lane), f0 = fac16(a, t, 0, lane);
+    const float4 f1v = fac32(a, t, 1, lane);
+    __builtin_amdgcn_sched_barrier(0);
+    load(min(t + 1, a.nterms - 1));   // branch-free: a wait after a branch would drain all loads
+    __builtin_amdgcn_sched_barrier(0);
+    const Fac16 f1 = split_scaled(f1v, a.lam[t]);
+    // column w: blocks b = x1 with X[p = x2][q = x0], rows 256 c + 16 b + 4 g + i
+    uint32_t u[16][2];
+#pragma unroll
+    for (int b = 0; b < 16; ++b) {
+      const u2v x = *reinterpret_cast<const u2v*>(mc + 16 * b);
+      u[b][0] = x[0];
+      u[b][1] = x[1];
+    }
+    aform16(u, f2);                    // (p = x0, q = y2)
+    aform16(u, f0);                    // (p = y2, q = y0)
+    exchange16(u);                     // blocks y2, (p = x1, q = y0)
+#pragma unroll
+    for (int b = 0; b < 16; ++b) {     // B(lambda T1) into the action's sum: (p = y1, q = y0)
+      const s4v x = op(u[b][0], u[b][1]);
+      acc[b] = mfma(f1.lo, x, acc[b]);
+      acc[b] = mfma(f1.hi, x, acc[b]);
+    }
+    if (t + 1 == a.term_start[act + 1]) {
+#pragma unroll
+      for (int b = 0; b < 16; ++b) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) best[b][i] = acc[b][i] > best[b][i] ? acc[b][i] : best[b][i];
+        acc[b] = f4v{0.f, 0.f, 0.f, 0.f};
+      }
+      ++act;
+    }
+  }
+  // Eq. 1: V' = R + gamma (1 - terminal) (max_a P_a (V - cs) + cs); state of
+  // lane (g, c), register (b, i): row 256 c + 16 (4 g + i) + b, column
+  // tile * 8 + w
+  double res = 0.0;
+  const int col = tile * kTile + half * kP2Cols + w;
+#pragma unroll
+  for (int b = 0; b < 16; ++b) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int s = (256 * c + 16 * (4 * g + i) + b) * kFib + col;
+      const float gm = is_terminal(a.term_bits, s) ? 0.f : a.gamma;
+      const float vnew = fmaf(gm, best[b][i] + cs, a.R[s]);
+      const double d = static_cast<double>(vnew) - static_cast<double>(a.V[s]);
+      a.Vout[s] = vnew;
+      res = nanmax(res, fabs(d));
+    }
+  }
+  block_max_to_slot(res, a.res_slot);
+}
+
+}  // namespace
+
+// Both groups three modes of exactly 16 states (16^6 grid split 3 + 3), the
+// factors packed as 16 x 16 blocks, every action with at least one term.
+bool chain16_bf16_ok(const ChainGeom& g) {
+  if (g.n != 6 || g.n1 != 3 || g.Rr != kFib || g.C != kFib) return false;
+  for (int k = 0; k < 6; ++k)
+    if (g.size[k] != 16 || g.fac_off[k] != 256 * k) return false;
+  return g.term_stride == 6 * 256;
+}
+
+// The intermediate needs nterms * S BF16 values (the FP32 chain's buffer
+// holds twice that).  tm: start at pass 1, stop after pass 2.
+void launch_chain16_bf16(const ChainArgs<float>& a, hipStream_t st, const LaunchTiming* tm) {
+  const LaunchTiming t1{tm ? tm->start : nullptr, nullptr};
+  const LaunchTiming t2{nullptr, tm ? tm->stop : nullptr};
+  klaunch(chain16_pass1, dim3(kFib / kP1Rows), dim3(kP1Rows * 64), 0, st, tm ? &t1 : nullptr, a);
+  klaunch(chain16_pass2, dim3(kFib / kP2Cols), dim3(kP2Cols * 64), 0, st, tm ? &t2 : nullptr, a);   // two per tile
+}
+
+}  // namespace cpm
