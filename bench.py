@@ -60,7 +60,7 @@ def _sha(paths):
 STENCIL_SRC = ["paper_2103_00331_amd/csrc/stencil.hip", "paper_2103_00331_amd/csrc/stencil_core.cuh",
                "paper_2103_00331_amd/csrc/common.cuh"]
 CHAIN_SRC = ["paper_2103_00331_amd/csrc/chain.hip", "paper_2103_00331_amd/csrc/common.cuh"]
-# BF16 max sweeps of 16^6 grids run the register-resident unit
+# FP32 and BF16 max sweeps of 16^6 grids run the register-resident units
 CHAIN16_SRC = ["paper_2103_00331_amd/csrc/chain16.hip", "paper_2103_00331_amd/csrc/common.cuh"]
 BATCH_SRC = ["paper_2103_00331_amd/csrc/batch.hip", "paper_2103_00331_amd/csrc/stencil_core.cuh",
              "paper_2103_00331_amd/csrc/common.cuh"]
@@ -481,7 +481,8 @@ def bench_dense(args):
     # (BF16 values in the BF16 unit), plus V (both passes), R and V'
     word = 8 if prec == B.CPMDP_FP64 else 4
     w_bytes = (2.0 * inst.n_terms * (2 if prec == B.CPMDP_BF16 else word) + 4.0 * word) * S
-    bf16r = prec == B.CPMDP_BF16   # 16^6 split 3 + 3: the register-resident BF16 unit
+    # 16^6 split 3 + 3: FP32 and BF16 max sweeps run the register-resident units
+    reg16 = prec in (B.CPMDP_BF16, B.CPMDP_FP32)
     peak = PEAK_TFLOPS[args.precision]
     eps = 1e-6
     V = torch.zeros(S, dtype=torch.float64, device="cuda")
@@ -521,9 +522,10 @@ def bench_dense(args):
                         "peak": peak, "unit": "TFLOP/s",
                         "frac": flops / (ms * 1e-3) / 1e12 / peak,
                         "traffic": _traffic(f"chain_{args.precision}_dense6_16.md",
-                                            CHAIN16_SRC if bf16r else CHAIN_SRC),
-                        "kernel": ("chain16_pass1 + chain16_pass2 (one sweep)" if bf16r
-                                   else "chain_pass1_rows + chain_pass2 (one sweep)"),
+                                            CHAIN16_SRC if reg16 else CHAIN_SRC),
+                        "kernel": {B.CPMDP_BF16: "chain16_pass1 + chain16_pass2 (one sweep)",
+                                   B.CPMDP_FP32: "chain16f_pass1 + chain16f_pass2 (one sweep)"}.get(
+                                       prec, "chain_pass1_rows + chain_pass2 (one sweep)"),
                         "kernel_ms": ms, "algorithmic_flops_per_launch": flops,
                         "intermediate_bytes_per_launch": w_bytes,
                         "hbm_rate_gbs": w_bytes / (ms * 1e-3) / 1e9}}

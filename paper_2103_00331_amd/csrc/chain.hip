@@ -945,9 +945,11 @@ template <typename T>
 void launch_chain(const ChainArgs<T>& a, int mode, int unit, hipStream_t st,
                   const LaunchTiming* tm) {
   if constexpr (std::is_same<T, float>::value) {
-    // BF16 max sweeps of 16^6 grids: every mode product in registers
-    if (unit == CHAIN_BF16 && mode == MODE_MAX && chain16_bf16_ok(a.g))
-      return launch_chain16_bf16(a, st, tm);
+    // BF16 and FP32 max sweeps of 16^6 grids: every mode product in registers
+    if (mode == MODE_MAX && chain16_bf16_ok(a.g)) {
+      if (unit == CHAIN_BF16) return launch_chain16_bf16(a, st, tm);
+      if (unit == CHAIN_F32_MFMA) return launch_chain16_f32(a, st, tm);
+    }
   }
   const bool two = a.g.n1 < a.g.n;
   const LaunchTiming t1{tm ? tm->start : nullptr, nullptr};

@@ -339,6 +339,237 @@ __global__ __launch_bounds__(kP2Cols * 64, 2) void chain16_pass2(ChainArgs<float
   block_max_to_slot(res, a.res_slot);
 }
 
+// ------------------------------------------------------------------ FP32
+// The same chain in FP32 on the 16 x 16 x 4 FP32 product (lane (g, c) gives
+// A[c][g] and B[g][c] of a K = 4 slice; four slices make a 16 x 16 x 16
+// product).  A block X[p][q] in the result layout (register i = X[4g + i][c])
+// serves as slice q = i of either operand if the factor's slice q holds
+// F[c][4g + q]: the product then contracts p in the order 4g + q, which is
+// only a permutation of the summation.  Those factor registers are the same
+// four values F[c][4g .. 4g + 3] as in the BF16 unit.  The exchange moves
+// whole FP32 registers (no halves).  The intermediate is FP32 in tiles of 4
+// columns (8 rows x 16 bytes = one line per pass-1 block and tile).
+//   pass 1: 8 rows per block (LDS rows of 4096 + 4 per 256 floats, 16-byte
+//     stores); pass 2: one tile (4 columns) per block, two blocks per CU, the
+//     tile loaded at the start of each term (no register prefetch: at 64 FP32
+//     values per lane it would not fit next to the sums; the other block's
+//     matrix products cover the load).
+
+constexpr int kTile32 = 4;                       // columns per FP32 tile
+constexpr int kColArr32 = kFib + 16 * 4;         // 4160 floats
+constexpr int kSlab32 = kColArr32 + 8;           // 4168: 8 rows x 2 tiles of a read on distinct banks
+
+__device__ __forceinline__ int padf(int v) { return v + ((v >> 8) << 2); }
+
+__device__ __forceinline__ f4v mfma4(float a, float b, f4v c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// A form, u[b] <- X_b^T F^T (F as four slices f[q] = F[c][4g + q]).
+__device__ __forceinline__ void aform32(float (&u)[16][4], const float4& f) {
+#pragma unroll
+  for (int b = 0; b < 16; ++b) {
+    f4v d = {0.f, 0.f, 0.f, 0.f};
+    d = mfma4(u[b][0], f.x, d);
+    d = mfma4(u[b][1], f.y, d);
+    d = mfma4(u[b][2], f.z, d);
+    d = mfma4(u[b][3], f.w, d);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) u[b][i] = d[i];
+  }
+}
+
+// 4 x 4 transpose of lane groups against the four registers.
+__device__ __forceinline__ void lane_group_transpose(float (&x)[4]) {
+  uint32_t y[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) y[m] = __float_as_uint(x[m]);
+  auto s02 = __builtin_amdgcn_permlane32_swap(y[0], y[2], false, false);
+  auto s13 = __builtin_amdgcn_permlane32_swap(y[1], y[3], false, false);
+  auto s01 = __builtin_amdgcn_permlane16_swap(s02[0], s13[0], false, false);
+  auto s23 = __builtin_amdgcn_permlane16_swap(s02[1], s13[1], false, false);
+  x[0] = __uint_as_float(s01[0]);
+  x[1] = __uint_as_float(s01[1]);
+  x[2] = __uint_as_float(s23[0]);
+  x[3] = __uint_as_float(s23[1]);
+}
+
+// u[b][i] = X[b][4g + i][c]  ->  X'[b][p][c] = X[p][b][c].  Group (I, L):
+// registers u[4m + I][L] (m = 0..3) transposed against the lane groups land
+// in u[4k + L][I]; groups (I, L) and (L, I) trade places, (I, I) stay.
+__device__ __forceinline__ void exchange32(float (&u)[16][4]) {
+#pragma unroll
+  for (int I = 0; I < 4; ++I) {
+#pragma unroll
+    for (int L = I; L < 4; ++L) {
+      float x[4], y[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        x[m] = u[4 * m + I][L];
+        y[m] = u[4 * m + L][I];
+      }
+      lane_group_transpose(x);
+      if (L != I) lane_group_transpose(y);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        u[4 * k + L][I] = x[k];
+        if (L != I) u[4 * k + I][L] = y[k];
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(kP1Rows * 64) void chain16f_pass1(ChainArgs<float> a) {
+  __shared__ __align__(16) float slab[kP1Rows * kSlab32];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int c = lane & 15, g = lane >> 4;
+  const int r0 = xcd_block(blockIdx.x, gridDim.x) * kP1Rows;
+  const float cs = a.shift_keys ? midrange(a.shift_keys) : 0.f;
+  float v[16][4];   // row r0 + w: blocks b = x3, X[p = x4][q = x5]
+  {
+    const float* Vr = a.V + static_cast<int64_t>(r0 + w) * kFib + 64 * g + c;
+#pragma unroll
+    for (int b = 0; b < 16; ++b) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v[b][i] = Vr[256 * b + 16 * i] - cs;
+    }
+  }
+  float* my = slab + w * kSlab32 + padf(256 * c + 4 * g);
+  const int64_t S = a.g.S, Rr = a.g.Rr;
+  // the next term's factors are loaded just before this term's stores (see
+  // the BF16 pass 1)
+  float4 f3 = fac32(a, 0, 3, lane), f4 = fac32(a, 0, 4, lane), f5 = fac32(a, 0, 5, lane);
+  for (int t = 0; t < a.nterms; ++t) {
+    float u[16][4];
+#pragma unroll
+    for (int b = 0; b < 16; ++b) {     // A(T4): (p = x5, q = y4)
+      f4v d = {0.f, 0.f, 0.f, 0.f};
+      d = mfma4(v[b][0], f4.x, d);
+      d = mfma4(v[b][1], f4.y, d);
+      d = mfma4(v[b][2], f4.z, d);
+      d = mfma4(v[b][3], f4.w, d);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) u[b][i] = d[i];
+    }
+    aform32(u, f5);                    // (p = y4, q = y5)
+    exchange32(u);                     // blocks y4, (p = x3, q = y5)
+    aform32(u, f3);                    // (p = y5, q = y3): column 256 c + 16 b + 4 g + i
+#pragma unroll
+    for (int b = 0; b < 16; ++b)
+      *reinterpret_cast<float4*>(my + 16 * b) = make_float4(u[b][0], u[b][1], u[b][2], u[b][3]);
+    __syncthreads();
+    {
+      const int tn = min(t + 1, a.nterms - 1);
+      f3 = fac32(a, tn, 3, lane);
+      f4 = fac32(a, tn, 4, lane);
+      f5 = fac32(a, tn, 5, lane);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    float* Wt = a.W + static_cast<int64_t>(t) * S;
+    constexpr int kUnits = (kFib / kTile32) * kP1Rows;   // 16-byte units of the block
+#pragma unroll
+    for (int j = 0; j < kUnits / (kP1Rows * 64); ++j) {
+      const int q = threadIdx.x + j * (kP1Rows * 64);
+      const int tl = q / kP1Rows, ww = q % kP1Rows;
+      const float4 val = *reinterpret_cast<const float4*>(slab + ww * kSlab32 + padf(kTile32 * tl));
+      *reinterpret_cast<float4*>(Wt + (static_cast<int64_t>(tl) * Rr + r0 + ww) * kTile32) = val;
+    }
+    __syncthreads();
+  }
+}
+
+// two waves per SIMD: two blocks of four waves per CU
+__global__ __launch_bounds__(kTile32 * 64, 2) void chain16f_pass2(ChainArgs<float> a) {
+  __shared__ __align__(16) float cols[kTile32 * kColArr32];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int c = lane & 15, g = lane >> 4;
+  const int tile = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t S = a.g.S;
+  // rows 2u and 2u + 1 of the tile (32 contiguous bytes), u = j * 256 + thread
+  const float* Wb = a.W + static_cast<int64_t>(tile) * kFib * kTile32 + threadIdx.x * 2 * kTile32;
+  constexpr int kUnits = kFib / 2 / (kTile32 * 64);
+  f4v acc[16], best[16];
+#pragma unroll
+  for (int b = 0; b < 16; ++b) {
+    acc[b] = f4v{0.f, 0.f, 0.f, 0.f};
+    best[b] = f4v{-INFINITY, -INFINITY, -INFINITY, -INFINITY};
+  }
+  const float cs = a.shift_keys ? midrange(a.shift_keys) : 0.f;
+  const float* mc = cols + w * kColArr32 + padf(256 * c + 4 * g);
+  int act = 0;
+  for (int t = 0; t < a.nterms; ++t) {
+    // factors first (loads retire in order), then the tile
+    const float4 f2 = fac32(a, t, 2, lane), f0 = fac32(a, t, 0, lane), f1v = fac32(a, t, 1, lane);
+    __builtin_amdgcn_sched_barrier(0);
+    float4 ld[kUnits][2];
+    {
+      const float* p = Wb + static_cast<int64_t>(t) * S;
+#pragma unroll
+      for (int j = 0; j < kUnits; ++j) {
+        ld[j][0] = *reinterpret_cast<const float4*>(p + j * (kTile32 * 64) * 2 * kTile32);
+        ld[j][1] = *reinterpret_cast<const float4*>(p + j * (kTile32 * 64) * 2 * kTile32 + kTile32);
+      }
+    }
+    __syncthreads();   // the previous term's column reads are done
+#pragma unroll
+    for (int j = 0; j < kUnits; ++j) {
+      const int pr = padf(2 * (j * (kTile32 * 64) + static_cast<int>(threadIdx.x)));
+      *reinterpret_cast<float2*>(cols + 0 * kColArr32 + pr) = make_float2(ld[j][0].x, ld[j][1].x);
+      *reinterpret_cast<float2*>(cols + 1 * kColArr32 + pr) = make_float2(ld[j][0].y, ld[j][1].y);
+      *reinterpret_cast<float2*>(cols + 2 * kColArr32 + pr) = make_float2(ld[j][0].z, ld[j][1].z);
+      *reinterpret_cast<float2*>(cols + 3 * kColArr32 + pr) = make_float2(ld[j][0].w, ld[j][1].w);
+    }
+    __syncthreads();
+    const float lam = a.lam[t];
+    const float4 f1 = make_float4(lam * f1v.x, lam * f1v.y, lam * f1v.z, lam * f1v.w);
+    // column w: blocks b = x1 with X[p = x2][q = x0], rows 256 c + 16 b + 4 g + i
+    float u[16][4];
+#pragma unroll
+    for (int b = 0; b < 16; ++b) {
+      const float4 x = *reinterpret_cast<const float4*>(mc + 16 * b);
+      u[b][0] = x.x;
+      u[b][1] = x.y;
+      u[b][2] = x.z;
+      u[b][3] = x.w;
+    }
+    aform32(u, f2);                    // (p = x0, q = y2)
+    aform32(u, f0);                    // (p = y2, q = y0)
+    exchange32(u);                     // blocks y2, (p = x1, q = y0)
+#pragma unroll
+    for (int b = 0; b < 16; ++b) {     // B(lambda T1) into the action's sum: (p = y1, q = y0)
+      acc[b] = mfma4(f1.x, u[b][0], acc[b]);
+      acc[b] = mfma4(f1.y, u[b][1], acc[b]);
+      acc[b] = mfma4(f1.z, u[b][2], acc[b]);
+      acc[b] = mfma4(f1.w, u[b][3], acc[b]);
+    }
+    if (t + 1 == a.term_start[act + 1]) {
+#pragma unroll
+      for (int b = 0; b < 16; ++b) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) best[b][i] = acc[b][i] > best[b][i] ? acc[b][i] : best[b][i];
+        acc[b] = f4v{0.f, 0.f, 0.f, 0.f};
+      }
+      ++act;
+    }
+  }
+  // Eq. 1, as in the BF16 pass 2
+  double res = 0.0;
+  const int col = tile * kTile32 + w;
+#pragma unroll
+  for (int b = 0; b < 16; ++b) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int s = (256 * c + 16 * (4 * g + i) + b) * kFib + col;
+      const float gm = is_terminal(a.term_bits, s) ? 0.f : a.gamma;
+      const float vnew = fmaf(gm, best[b][i] + cs, a.R[s]);
+      const double d = static_cast<double>(vnew) - static_cast<double>(a.V[s]);
+      a.Vout[s] = vnew;
+      res = nanmax(res, fabs(d));
+    }
+  }
+  block_max_to_slot(res, a.res_slot);
+}
+
 }  // namespace
 
 // Both groups three modes of exactly 16 states (16^6 grid split 3 + 3), the
@@ -348,6 +579,15 @@ bool chain16_bf16_ok(const ChainGeom& g) {
   for (int k = 0; k < 6; ++k)
     if (g.size[k] != 16 || g.fac_off[k] != 256 * k) return false;
   return g.term_stride == 6 * 256;
+}
+
+// The intermediate needs nterms * S FP32 values (the FP32 chain's buffer).
+// tm: start at pass 1, stop after pass 2.
+void launch_chain16_f32(const ChainArgs<float>& a, hipStream_t st, const LaunchTiming* tm) {
+  const LaunchTiming t1{tm ? tm->start : nullptr, nullptr};
+  const LaunchTiming t2{nullptr, tm ? tm->stop : nullptr};
+  klaunch(chain16f_pass1, dim3(kFib / kP1Rows), dim3(kP1Rows * 64), 0, st, tm ? &t1 : nullptr, a);
+  klaunch(chain16f_pass2, dim3(kFib / kTile32), dim3(kTile32 * 64), 0, st, tm ? &t2 : nullptr, a);
 }
 
 // The intermediate needs nterms * S BF16 values (the FP32 chain's buffer

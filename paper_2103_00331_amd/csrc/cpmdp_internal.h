@@ -254,10 +254,11 @@ template <typename T>
 void launch_chain(const ChainArgs<T>& a, int mode, int unit, hipStream_t st,
                   const LaunchTiming* tm = nullptr);
 
-// Register-resident BF16 chain (max sweeps of 16^6 grids, split 3 + 3): its
-// geometry test and launcher (chain16.hip).
+// Register-resident BF16 and FP32 chains (max sweeps of 16^6 grids, split
+// 3 + 3): their geometry test and launchers (chain16.hip).
 bool chain16_bf16_ok(const ChainGeom& g);
 void launch_chain16_bf16(const ChainArgs<float>& a, hipStream_t st, const LaunchTiming* tm);
+void launch_chain16_f32(const ChainArgs<float>& a, hipStream_t st, const LaunchTiming* tm);
 
 // ---------------------------------------------------------------- helpers
 void launch_fill_u64(unsigned long long* p, int n, unsigned long long v, hipStream_t st);

@@ -168,32 +168,34 @@ def test_dense16_6_sampled_states_and_closed_form(B):
     cmodel.close()
 
 
-def test_bf16_register_chain_dense16_6_slabs(B):
-    """Full 16^6 instance, BF16 max sweep (the register-resident unit of
-    16^6 grids): one backup against the oracle on two rows and two columns of
-    the 3 + 3 split (4096 states each; a row spans every column tile, a
-    column every row block), the reported residual against max |V' - V| over
-    all states, and a BF16 value-iteration solve certified to 1e-6 whose
-    Bellman residual the oracle recomputes on the same rows and columns."""
+@pytest.mark.parametrize("prec", [1, 2])
+def test_register_chain_dense16_6_slabs(B, prec):
+    """Full 16^6 instance, FP32 and BF16 max sweeps (the register-resident
+    units of 16^6 grids): one backup against the oracle on two rows and two
+    columns of the 3 + 3 split (4096 states each; a row spans every column
+    tile, a column every row block), the reported residual against
+    max |V' - V| over all states, and a value-iteration solve certified to
+    1e-6 whose Bellman residual the oracle recomputes on the same rows and
+    columns."""
     inst = I.dense_grid(16, seed=I.SEED_DENSE6)
     model = B.Model(inst)
     V = I.seeded_values(inst.n_states, 10, scale=3.0).astype(np.float32).astype(np.float64)
     slabs = [{0: 0, 1: 0, 2: 0}, {0: 15, 1: 7, 2: 9}, {3: 0, 4: 0, 5: 0}, {3: 15, 4: 8, 5: 3}]
     log("[dense 16^6] slab oracle")
     ref = [oracle.structured.q_on_slab(inst, V, f) for f in slabs]
-    log("[dense 16^6] gpu bf16 backup (max sweep)")
+    log(f"[dense 16^6] gpu backup (max sweep) prec={prec}")
     Vin = torch.as_tensor(V, dtype=torch.float32, device="cuda")
     Vout = torch.empty_like(Vin)
-    r = B.cpmdp_backup(model.h, Vin, Vout, None, residual=True, precision=2)
+    r = B.cpmdp_backup(model.h, Vin, Vout, None, residual=True, precision=prec)
     torch.cuda.synchronize()
     Vg = Vout.cpu().numpy().astype(np.float64)
-    tol = tol_for(2, np.abs(V).max())
     for f, (Q, st) in zip(slabs, ref):
-        err = assert_close(Vg[st], Q.max(0), tol, f"V' bf16 on slab {f}")
-        log(f"   slab {f}: bf16 error {err:.3e} (tolerance {tol:.3e})")
+        tol = tol_for(2, np.abs(V).max()) if prec == 2 else tol_for(1, Q.max(0))
+        err = assert_close(Vg[st], Q.max(0), tol, f"V' prec={prec} on slab {f}")
+        log(f"   slab {f}: error {err:.3e} (tolerance {tol:.3e})")
     assert r == np.abs(Vg - V).max()
-    log("[dense 16^6] bf16 value iteration")
-    Vs, _, code, sweeps, res = _solve(B, model, "vi", 2, 1e-6)
+    log(f"[dense 16^6] value iteration prec={prec}")
+    Vs, _, code, sweeps, res = _solve(B, model, "vi", prec, 1e-6)
     assert code == B.CPMDP_OK and res <= 1e-6
     for f in slabs[1:3]:
         Q, st = oracle.structured.q_on_slab(inst, Vs, f)
