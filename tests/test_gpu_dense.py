@@ -202,6 +202,25 @@ def test_register_chain_dense16_6_slabs(B, prec):
         assert np.abs(Q.max(0) - Vs[st]).max() <= 1e-6 + 1e-12 * np.abs(Vs).max()
     log(f"   {sweeps} sweeps, certified residual {res:.3e}")
     model.close()
+    # terminal states inside the checked rows and columns (and elsewhere)
+    term = np.zeros(inst.n_states, bool)
+    term[np.random.default_rng(12).integers(0, inst.n_states, 50000)] = True
+    for _, st in ref:
+        term[st[::7]] = True
+    tinst = I.with_rewards(inst, inst.rewards, terminal=term)
+    tmodel = B.Model(tinst)
+    log(f"[dense 16^6] terminal states, backup prec={prec}")
+    r = B.cpmdp_backup(tmodel.h, Vin, Vout, None, residual=True, precision=prec)
+    torch.cuda.synchronize()
+    Vg = Vout.cpu().numpy().astype(np.float64)
+    for f in slabs[:3]:
+        Q, st = oracle.structured.q_on_slab(tinst, V, f)
+        assert term[st].sum() > 500
+        tol = tol_for(2, np.abs(V).max()) if prec == 2 else tol_for(1, Q.max(0))
+        assert_close(Vg[st], Q.max(0), tol, f"V' prec={prec} with terminals on slab {f}")
+        np.testing.assert_array_equal(Vg[st][term[st]], tinst.rewards[st][term[st]].astype(np.float32))
+    assert r == np.abs(Vg - V).max()
+    tmodel.close()
 
 
 def test_bf16_dense12_6_vi_iterate(B):
