@@ -790,8 +790,9 @@ __global__ __launch_bounds__(256) void level_fill_kernel(double* V, int64_t S, c
 struct MlpWs {
   float *X, *H1, *H2, *y, *t, *dy, *dH1, *dH2;
   double* loss;
-  float* part;                      // split-K partial products
+  float* part;                      // split-K partials (dW2, on the side stream in training)
   float* part2;                     // column-sum partials (the side stream's)
+  float* part3;                     // split-K partials of dW1 (the caller's stream)
 };
 
 static constexpr size_t al(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
@@ -799,7 +800,8 @@ static constexpr size_t al(size_t x) { return (x + 255) & ~static_cast<size_t>(2
 constexpr size_t mlp_ws_bytes(int B) {
   const size_t b = static_cast<size_t>(B);
   return al(b * kF * 4) + 4 * al(b * kH * 4) + 3 * al(b * 4) + al(b * 4) + al(64) +
-         al(static_cast<size_t>(kSplitWords) * 4) + al(static_cast<size_t>(kColsumChunks) * kH * 4);
+         al(static_cast<size_t>(kSplitWords) * 4) + al(static_cast<size_t>(kColsumChunks) * kH * 4) +
+         al(static_cast<size_t>(kSplitMax) * kF * kH * 4);
 }
 
 MlpWs carve(void* ws, int B) {
@@ -822,6 +824,7 @@ MlpWs carve(void* ws, int B) {
   w.loss = reinterpret_cast<double*>(take(64));
   w.part = reinterpret_cast<float*>(take(static_cast<size_t>(kSplitWords) * 4));
   w.part2 = reinterpret_cast<float*>(take(static_cast<size_t>(kColsumChunks) * kH * 4));
+  w.part3 = reinterpret_cast<float*>(take(static_cast<size_t>(kSplitMax) * kF * kH * 4));
   return w;
 }
 
@@ -925,9 +928,10 @@ SideStream* side_stream() {
 // Gradient of the mean squared error (y - t)^2 over the B rows of X.  The
 // column sums (dw3, db3, db2, db1) read activations that are final once the
 // products before them have run, so they go to the side stream, forked and
-// joined with events, with their own partial area; the products keep the
-// caller's stream.  The same kernels in the same order per stream: the
-// result does not depend on how the two streams interleave.
+// joined with events, with their own partial area; so does dW2 = H1^T dH2,
+// which needs only dH2 and runs beside the product for dH1 (each split-K
+// product has its own partial area).  The same kernels in the same order per
+// stream: the result does not depend on how the two streams interleave.
 // have_dy: the forward pass already wrote dy (and the loss is not wanted).
 void backward(const float* P, const float* X, int B, const MlpWs& w, float* G, hipStream_t st,
               bool have_dy = false) {
@@ -952,12 +956,12 @@ void backward(const float* P, const float* X, int B, const MlpWs& w, float* G, h
   // layer 2: dW2 = H1^T dH2, db2 = 1^T dH2, dH1 = (dH2 W2^T) .* [H1 > 0]
   fork(1);
   colsum(w.dH2, nullptr, B, kH, G + kOffB2, w.part2, so);
-  gemm<true, false, EPI_NONE>(kH, kH, B, w.H1, kH, w.dH2, kH, G + kOffW2, kH, nullptr, nullptr, 0, st, w.part);
+  gemm<true, false, EPI_NONE>(kH, kH, B, w.H1, kH, w.dH2, kH, G + kOffW2, kH, nullptr, nullptr, 0, so, w.part);
   gemm<false, true, EPI_MASK>(B, kH, kH, w.dH2, kH, P + kOffW2, kH, w.dH1, kH, nullptr, w.H1, kH, st);
   // layer 1: dW1 = X^T dH1, db1 = 1^T dH1
   fork(2);
   colsum(w.dH1, nullptr, B, kH, G + kOffB1, w.part2, so);
-  gemm<true, false, EPI_NONE>(kF, kH, B, X, kF, w.dH1, kH, G + kOffW1, kH, nullptr, nullptr, 0, st, w.part);
+  gemm<true, false, EPI_NONE>(kF, kH, B, X, kF, w.dH1, kH, G + kOffW1, kH, nullptr, nullptr, 0, st, w.part3);
   if (ss) {   // join: the caller's stream waits for the side stream's sums
     (void)hipEventRecord(ss->ev[3], so);
     (void)hipStreamWaitEvent(st, ss->ev[3], 0);
@@ -967,7 +971,7 @@ void backward(const float* P, const float* X, int B, const MlpWs& w, float* G, h
 int mfail(const std::string& m) { return fail(nullptr, CPMDP_E_ARG, m); }
 
 // Scratch of the allocation-free prediction (cpmdp_mlp_predict_noalloc):
-// the MLP workspace for chunks of up to kStaticRows rows, 26.2 MiB, held by
+// the MLP workspace for chunks of up to kStaticRows rows, 30.2 MiB, held by
 // every GPU the library runs on until the process ends.  Host code never
 // passes `scratch` itself (its host-side name is no device address): the
 // device address comes from hipGetSymbolAddress, once per device.
