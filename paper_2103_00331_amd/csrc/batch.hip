@@ -1167,8 +1167,13 @@ int cpmdp_batch_solve(cpmdp_batch_t* b, double* const* V_devs, int32_t* const* p
     d.stage = precision == CPMDP_FP64 ? B_F64 : B_F32;
     d.pi_out = policy_buffer(b, i, pi_devs ? pi_devs[i] : nullptr, false);
     const double rmax = h->rmax;
+    // FP32 sweeps run until they stop contracting (the stall test below, in
+    // the zone of 8 x an 8-ulp bound of ||V*||): a stop threshold at that
+    // bound ended them well above their floor (FP32 sweeps stall at a few
+    // ulp of ||V||), leaving more of the tail to FP64 sweeps that move
+    // twice the bytes
     floor32[i] = 8.0 * std::ldexp(1.0, -24) * std::max(1.0, rmax / (1.0 - h->gamma));
-    d.stop = d.stage == B_F32 ? std::max(eps, floor32[i]) : eps;
+    d.stop = d.stage == B_F32 ? std::max(eps, floor32[i] / 16.0) : eps;
   }
   int rc = upload_descs(b);
   if (rc) return rc;
