@@ -223,6 +223,38 @@ def test_register_chain_dense16_6_slabs(B, prec):
     tmodel.close()
 
 
+def test_register_chain_dense16_6_mixed_terms(B):
+    """16^6 with uneven ranks (1, 3, 8 and 2 terms per action), identity and
+    shift factors among the dense ones and terminal states: one FP32 and one
+    BF16 max sweep of the register-resident units against the oracle on a
+    row and a column of the 3 + 3 split."""
+    inst = I.random_dense([16] * 6, 4, [1, 3, 8, 2], seed=51, gamma=0.95, alpha=0.5,
+                          n_terminal=2000, reward_scale=0.1)
+    eye = np.eye(16)
+    shift = 0.8 * np.eye(16, k=1) + 0.2 * eye
+    shift[15, 15] = 1.0
+    for t, k, T in [(0, 2, eye), (1, 5, shift), (4, 0, shift.T / shift.T.sum(1, keepdims=True)),
+                    (7, 3, eye), (7, 4, eye), (12, 1, shift)]:
+        inst.factor(t, k)[:] = T
+    model = B.Model(inst)
+    V = I.seeded_values(inst.n_states, 17, scale=2.0).astype(np.float32).astype(np.float64)
+    slabs = [{0: 3, 1: 14, 2: 6}, {3: 9, 4: 2, 5: 11}]
+    log("[dense 16^6 mixed] slab oracle")
+    ref = [oracle.structured.q_on_slab(inst, V, f) for f in slabs]
+    Vin = torch.as_tensor(V, dtype=torch.float32, device="cuda")
+    Vout = torch.empty_like(Vin)
+    for prec in (1, 2):
+        log(f"[dense 16^6 mixed] gpu backup (max sweep) prec={prec}")
+        B.cpmdp_backup(model.h, Vin, Vout, None, residual=True, precision=prec)
+        torch.cuda.synchronize()
+        Vg = Vout.cpu().numpy().astype(np.float64)
+        for f, (Q, st) in zip(slabs, ref):
+            tol = tol_for(2, np.abs(V).max()) if prec == 2 else tol_for(1, Q.max(0))
+            err = assert_close(Vg[st], Q.max(0), tol, f"V' prec={prec} on slab {f}")
+            log(f"   slab {f}: error {err:.3e} (tolerance {tol:.3e})")
+    model.close()
+
+
 def test_bf16_dense12_6_vi_iterate(B):
     """12^6: one BF16 backup from an iterate of value iteration (three
     oracle sweeps from zero) against the oracle, at 1e-3 max(1, ||V||)."""
