@@ -1,6 +1,8 @@
-// K2, register-resident BF16 unit for grids of six modes of 16 states (both
-// groups three modes of 16, so one row of pass 1 and one column of pass 2 is
-// a 16 x 16 x 16 tensor of 4096 values).
+// K2, register-resident BF16 and FP32 units for grids of six modes of 16
+// states (both groups three modes of 16, so one row of pass 1 and one column
+// of pass 2 is a 16 x 16 x 16 tensor of 4096 values).  The BF16 unit is
+// described here; the FP32 unit, further down, follows it with the FP32
+// matrix product.
 //
 // The operator is the one of the two-pass chain: pass 1 applies the column
 // group's factors of every term to each row of V (minus the midrange shift),
@@ -61,10 +63,11 @@ constexpr int kFib = 4096;      // values of one row (pass 1) / one column (pass
 constexpr int kP1Rows = 8;      // pass 1: rows per block, one per wave
 constexpr int kTile = 8;        // columns per tile of the intermediate
 constexpr int kP2Cols = 4;      // pass 2: columns per block (half a tile), one per wave
-// LDS arrays: 4096 values + 8 per 256 (pad16); the pass-1 rows get a few more
-// so that the rows of an 8-byte read by half a wave fall on distinct banks.
-constexpr int kColArr = kFib + 16 * 8;                        // 4224
-constexpr int kSlab = kColArr + (kP1Rows == 16 ? 8 : 16);     // 4232 / 4240
+// LDS arrays: 4096 values + 8 per 256 (pad16); the pass-1 rows get 16 more
+// (a row stride of 8 words mod 64 banks) so that the 8 rows x 2 tiles of a
+// 16-byte read by 16 lanes fall on distinct banks.
+constexpr int kColArr = kFib + 16 * 8;    // 4224
+constexpr int kSlab = kColArr + 16;       // 4240
 
 __device__ __forceinline__ int pad16(int v) { return v + ((v >> 8) << 3); }
 
