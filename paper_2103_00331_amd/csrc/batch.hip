@@ -36,6 +36,7 @@ constexpr int kBSpread = 4;      // residual words per (sweep, instance)
 constexpr int kBMaxK = 64;       // sweeps per graph, at most
 constexpr int kBBlock = 256;
 constexpr int64_t kBMarchMinPlane = 16384;   // plane size from which instances march
+constexpr int kBMinSegment = 4;               // planes per marching segment, at least
 
 enum BStage : int32_t { B_F32 = 0, B_F64 = 1, B_CERT = 2, B_DONE = 3 };
 
@@ -43,7 +44,8 @@ struct BInst {
   GridGeom g;
   int32_t A, vec, axis, stage;
   int32_t parity, eparity;     // V ping-pong; PI correction (V32 = e) ping-pong
-  int32_t mtiles, pad_m;        // > 0: marching tiles of 1024 plane offsets per plane
+  int32_t mtiles;               // > 0: marching tiles of 1024 plane offsets per plane
+  int32_t mseg;                 // planes per marching segment (0: all planes)
   float gamma32, pad1;
   double gamma64;
   float base32[2 * kBMaxN + 1];
@@ -65,7 +67,8 @@ static_assert(sizeof(BInst) % 4 == 0, "descriptor copied as words");
 
 // Tile (instance, y): y >= 0: states [y, y + tile_states) of the instance;
 // y < 0: marching tile q = -1 - y, plane offsets [1024 (q % mtiles), + 1024)
-// over all planes of the instance (see march_column).
+// over planes [z mseg, (z + 1) mseg), z = q / mtiles (all planes when mseg
+// is 0; see march_column).
 struct BatchArgs {
   const BInst* insts;
   const int2* tiles;
@@ -235,10 +238,12 @@ __device__ __forceinline__ void march_dispatch(const BInst& d, const StencilIO<T
                                                unsigned& ch) {
   const int p = (q % d.mtiles) * (kBBlock * 4) + threadIdx.x * 4;
   const GridGeom g = ugeom<4>(d.g);
+  const int i0 = d.mseg > 0 ? (q / d.mtiles) * d.mseg : 0;
+  const int i1 = d.mseg > 0 ? min(i0 + d.mseg, g.size[0]) : g.size[0];
   const StencilIO<T> io = uio(io_l);
   UWeights<T, 4> uw;
   const StencilW<T> W = uw.load(W_l);
-  march_column<T, 4, MODE, true>(g, io, W, p, 0, g.size[0], T(0), res, res_d, ch);
+  march_column<T, 4, MODE, true>(g, io, W, p, i0, i1, T(0), res, res_d, ch);
 }
 
 template <typename T>
@@ -585,6 +590,8 @@ BatchArgs make_args(cpmdp_batch_t* b) {
 // with march (and b->march), instances that allow it get marching tiles.
 // Each group is split into contiguous ranges of about equal state counts:
 // b->grid of them (schedule 0) or one per XCD (schedule 1).
+int upload_descs(cpmdp_batch_t* b);
+
 int upload_tiles(cpmdp_batch_t* b, const std::vector<char>& want, int64_t* count,
                  bool march = false) {
   march = march && b->march;
@@ -600,6 +607,32 @@ int upload_tiles(cpmdp_batch_t* b, const std::vector<char>& want, int64_t* count
   int cnt[2] = {0, 0};
   std::vector<int64_t> weight;
   weight.reserve(static_cast<size_t>(b->max_tiles));
+  // Few tiles in the set (the last instances of a solve): split each march
+  // along dimension 0 into segments of at least kBMinSegment planes, so that
+  // the set still gives about 2 tiles per block.
+  int64_t n_march = 0, n_other = 0;
+  for (size_t i = 0; i < b->hs.size(); ++i) {
+    if (!want[i]) continue;
+    if (march && b->hd[i].mtiles > 0) n_march += b->hd[i].mtiles;
+    else n_other += (b->lay[i].Sp + ts - 1) / ts;
+  }
+  const int64_t goal = 2 * static_cast<int64_t>(G);
+  const int64_t nseg_want =
+      (n_march > 0 && n_march + n_other < goal) ? (goal - n_other + n_march - 1) / n_march : 1;
+  bool seg_changed = false;
+  for (size_t i = 0; i < b->hs.size(); ++i) {
+    BInst& d = b->hd[i];
+    if (!want[i] || !march || d.mtiles <= 0) continue;
+    const int m0 = d.g.size[0];
+    const int64_t nseg = std::max<int64_t>(1, std::min<int64_t>(nseg_want, m0 / kBMinSegment));
+    const int mseg = nseg > 1 ? static_cast<int>((m0 + nseg - 1) / nseg) : 0;
+    seg_changed = seg_changed || d.mseg != mseg;
+    d.mseg = mseg;
+  }
+  if (seg_changed) {
+    int rc = upload_descs(b);
+    if (rc) return rc;
+  }
   for (int grp = 1; grp <= 2; ++grp) {
     const int64_t first = nt;
     for (size_t i = 0; i < b->hs.size(); ++i) {
@@ -608,9 +641,15 @@ int upload_tiles(cpmdp_batch_t* b, const std::vector<char>& want, int64_t* count
       const int64_t S = b->lay[i].Sp;
       if (march && d.mtiles > 0) {
         const int64_t planes = d.g.size[0];
-        for (int q = 0; q < d.mtiles; ++q) {
-          b->h_tiles[nt++] = make_int2(static_cast<int>(i), -1 - q);
-          weight.push_back(planes * kBBlock * 4);
+        const int64_t seg = d.mseg > 0 ? d.mseg : planes;
+        const int64_t nseg = (planes + seg - 1) / seg;
+        if (nt + nseg * d.mtiles > b->max_tiles)
+          return bfail(b, CPMDP_E_STATE, "batch tile table overflow");
+        for (int64_t z = 0; z < nseg; ++z) {
+          for (int q = 0; q < d.mtiles; ++q) {
+            b->h_tiles[nt++] = make_int2(static_cast<int>(i), static_cast<int>(-1 - (z * d.mtiles + q)));
+            weight.push_back(std::min(seg, planes - z * seg) * kBBlock * 4);
+          }
         }
       } else {
         for (int64_t s = 0; s < S; s += ts) {
@@ -1070,6 +1109,7 @@ int cpmdp_batch_bind(cpmdp_batch_t* b, void* ws, size_t bytes, void* stream) {
     d.mtiles = (h->n == 4 && h->st_axis && plane >= kBMarchMinPlane && h->sizes[0] >= 8)
                    ? static_cast<int32_t>((plane + kBBlock * 4 - 1) / (kBBlock * 4))
                    : 0;
+    d.mseg = 0;
     d.parity = 0;
     d.gamma32 = static_cast<float>(h->gamma);
     d.gamma64 = h->gamma;
