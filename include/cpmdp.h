@@ -533,6 +533,19 @@ int cpmdp_mlp_train_step(float* params, float* adam_m, float* adam_v, float* gra
 int cpmdp_mlp_predict(const float* params, const float* R, int32_t m, double gamma, double slip,
                       double* V0, int32_t chunk, int32_t precision, int32_t level, void* ws,
                       size_t ws_bytes, void* stream);
+/* The value levels of n_inst instances of one grid size in one pass (the
+ * level = 1 prediction of cpmdp_mlp_predict, each instance on its
+ * n = min(m^3, 4096) spread states, one forward pass over all n_inst * n
+ * rows): V0[i] (m^3 doubles) is set to instance i's level.  R and V0 are
+ * HOST arrays of n_inst device pointers (m^3 floats / m^3 doubles each; their
+ * extents cannot be checked), gammas and slips host arrays of n_inst.  The
+ * workspace is sized for n_inst * n rows (cpmdp_mlp_workspace_bytes).
+ * Levels agree with per-instance calls to FP32 rounding (the forward pass
+ * may group its sums differently for more rows).  n_inst * n > 2^24, a null
+ * pointer or gamma >= 1: CPMDP_E_ARG. */
+int cpmdp_mlp_predict_levels(const float* params, const float* const* R, const double* gammas,
+                             const double* slips, int32_t n_inst, int32_t m, double* const* V0,
+                             int32_t precision, void* ws, size_t ws_bytes, void* stream);
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid allocation): the same
  * prediction as cpmdp_mlp_predict, with the workspace in the library's own

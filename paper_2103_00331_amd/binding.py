@@ -106,6 +106,8 @@ _SIGS = {
                                     C.c_int32, C.c_int32, _p, C.c_size_t, _p]),
     "cpmdp_mlp_predict_noalloc": (C.c_int, [_p, _p, C.c_int32, C.c_double, C.c_double, _p,
                                             C.c_int32, C.c_int32, C.c_int32, _p]),
+    "cpmdp_mlp_predict_levels": (C.c_int, [_p, _p, _p, _p, C.c_int32, C.c_int32, _p, C.c_int32,
+                                           _p, C.c_size_t, _p]),
 }
 
 EXPORTED = sorted(_SIGS)
@@ -541,6 +543,25 @@ def cpmdp_mlp_predict(params, R, m, gamma, slip, V0, chunk, ws, stream=None,
                                         _ptr(V0), int(chunk), int(precision), int(bool(level)),
                                         _ptr(ws),
                                         ws.numel() * ws.element_size(), _stream_ptr(stream)))
+
+
+def cpmdp_mlp_predict_levels(params, Rs, gammas, slips, m, V0s, ws, stream=None,
+                             precision=CPMDP_FP32):
+    n = len(Rs)
+    S = int(m) ** 3
+    if len(V0s) != n or len(gammas) != n or len(slips) != n or n < 1:
+        raise ValueError("predict_levels needs equal numbers (>= 1) of R, V0, gammas and slips")
+    for R, V0 in zip(Rs, V0s):
+        if R.numel() != S or V0.numel() != S or R.dtype != torch.float32 or V0.dtype != torch.float64:
+            raise ValueError(f"predict_levels on {m}^3 grids needs float32 R and float64 V0 of {S} "
+                             "elements")
+    rarr = (_p * n)(*[R.data_ptr() for R in Rs])
+    varr = (_p * n)(*[V.data_ptr() for V in V0s])
+    garr = (C.c_double * n)(*[float(g) for g in gammas])
+    sarr = (C.c_double * n)(*[float(x) for x in slips])
+    return _check(lib.cpmdp_mlp_predict_levels(_ptr(params), rarr, garr, sarr, n, int(m), varr,
+                                               int(precision), _ptr(ws),
+                                               ws.numel() * ws.element_size(), _stream_ptr(stream)))
 
 
 def cpmdp_mlp_predict_noalloc(params, R, m, gamma, slip, V0, chunk, stream=None,

@@ -1153,6 +1153,47 @@ int cpmdp_mlp_predict(const float* params, const float* R, int32_t m, double gam
   return hipGetLastError() == hipSuccess ? CPMDP_OK : fail(nullptr, CPMDP_E_DEVICE, "predict launch");
 }
 
+int cpmdp_mlp_predict_levels(const float* params, const float* const* R, const double* gammas,
+                             const double* slips, int32_t n_inst, int32_t m, double* const* V0,
+                             int32_t precision, void* ws, size_t ws_bytes, void* stream) {
+  if (!params || !R || !gammas || !slips || !V0 || n_inst < 1 || m < 1 || !ws)
+    return mfail("bad predict_levels arguments");
+  if (static_cast<int64_t>(m) * m * m >= (int64_t{1} << 31))
+    return mfail("predict_levels: m^3 must be below 2^31");
+  if (precision != CPMDP_FP32 && precision != CPMDP_BF16)
+    return mfail("precision must be CPMDP_FP32 or CPMDP_BF16");
+  const int S = m * m * m;
+  const int n = std::min(S, kLevelSamples);
+  // the rows of one forward pass, and each instance's kLevelBlocks partial
+  // sums (FP64) in the split-K partial area
+  if (static_cast<int64_t>(n) * n_inst > (int64_t{1} << 24) ||
+      static_cast<int64_t>(n_inst) * kLevelBlocks * 2 > kSplitWords)
+    return mfail("predict_levels: too many instances for one pass (n_inst * min(m^3, 4096) > 2^24)");
+  for (int i = 0; i < n_inst; ++i)
+    if (!R[i] || !V0[i] || !(gammas[i] < 1.0))
+      return mfail("predict_levels: null R or V0, or gamma >= 1, for an instance");
+  const int rows = n * n_inst;
+  if (ws_bytes < mlp_ws_bytes(rows)) return fail(nullptr, CPMDP_E_WORKSPACE, "MLP workspace too small");
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  MlpWs w = carve(ws, rows);
+  const FastDiv dm = make_fastdiv(static_cast<uint32_t>(m));
+  for (int i = 0; i < n_inst; ++i)
+    hipLaunchKernelGGL(features_spread_kernel, dim3(feature_blocks(n)), dim3(256), 0, st, R[i], m, dm,
+                       static_cast<float>(gammas[i]), static_cast<float>(slips[i]), S, n,
+                       w.X + static_cast<size_t>(i) * n * kF);
+  forward(params, w.X, rows, w, st, precision == CPMDP_BF16);
+  double* part = reinterpret_cast<double*>(w.part);
+  for (int i = 0; i < n_inst; ++i)
+    hipLaunchKernelGGL(level_partial_kernel, dim3(kLevelBlocks), dim3(256), 0, st,
+                       w.y + static_cast<size_t>(i) * n, n, part + i * kLevelBlocks);
+  for (int i = 0; i < n_inst; ++i)
+    hipLaunchKernelGGL(level_fill_kernel, dim3(std::min(1024, (S + 255) / 256)), dim3(256), 0, st,
+                       V0[i], static_cast<int64_t>(S), part + i * kLevelBlocks, kLevelBlocks, n,
+                       1.0 / (1.0 - gammas[i]));
+  return hipGetLastError() == hipSuccess ? CPMDP_OK
+                                         : fail(nullptr, CPMDP_E_DEVICE, "predict_levels launch");
+}
+
 int cpmdp_mlp_predict_noalloc(const float* params, const float* R, int32_t m, double gamma,
                               double slip, double* V0, int32_t chunk, int32_t precision,
                               int32_t level, void* stream) {

@@ -123,6 +123,29 @@ class WarmStart:
                             precision=B.CPMDP_BF16 if bf16 else B.CPMDP_FP32, level=level)
         return V0
 
+    def predict_levels(self, insts, Rs=None, outs=None, bf16: bool = False):
+        """The value levels of several m^3 instances in one library call (one
+        forward pass over every instance's 4096 spread states; see
+        cpmdp_mlp_predict_levels): V0 (FP64, device) per instance, written
+        into `outs` when given.  Rs: the instances' rewards on the device
+        (FP32), else uploaded here."""
+        torch = self.torch
+        for x in insts:
+            self._check(x)
+        if Rs is None:
+            Rs = [torch.as_tensor(x.rewards, dtype=torch.float32, device=self.device) for x in insts]
+        if outs is None:
+            outs = [torch.empty(x.n_states, dtype=torch.float64, device=self.device) for x in insts]
+        rows = len(insts) * min(self.m ** 3, 4096)
+        if rows > self.infer_chunk:
+            self.infer_ws = torch.empty(B.cpmdp_mlp_workspace_bytes(rows), dtype=torch.uint8,
+                                        device=self.device)
+            self.infer_chunk = rows
+        B.cpmdp_mlp_predict_levels(self.params, Rs, [x.gamma for x in insts],
+                                   [x.meta["slip"] for x in insts], self.m, outs, self.infer_ws,
+                                   precision=B.CPMDP_BF16 if bf16 else B.CPMDP_FP32)
+        return outs
+
     # ------------------------------------------------------------ checkpoint
     def save(self, path):
         np.savez(path, params=self.params.cpu().numpy(), adam_m=self.adam_m.cpu().numpy(),

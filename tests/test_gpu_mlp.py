@@ -249,6 +249,36 @@ def test_predict_level_is_mean_of_sampled_states(B, m, chunk):
     assert float(lev.max() - lev.min()) == 0.0
 
 
+@pytest.mark.parametrize("m", [9, 20])
+@pytest.mark.parametrize("bf16", [False, True])
+def test_predict_levels_match_single_predictions(B, m, bf16):
+    """The batched level prediction (one forward pass over every instance's
+    spread states) gives each instance the level of its own level-mode
+    prediction (to FP32 rounding: the forward pass may group its sums
+    differently for more rows), the same bits on a repeat, and rejects
+    mismatched argument lists."""
+    from paper_2103_00331_amd.warmstart import WarmStart
+    w = WarmStart(m=m, batch=256, seed=5)
+    w.params += 0.05 * torch.randn(w.params.numel(), device="cuda",
+                                   generator=torch.Generator("cuda").manual_seed(6))
+    insts = [I.warm_instance(2, i, m=m) for i in range(9)]
+    single = [w.predict(x, bf16=bf16) for x in insts]
+    lev = w.predict_levels(insts, bf16=bf16)
+    again = w.predict_levels(insts, bf16=bf16)
+    torch.cuda.synchronize()
+    for x, a, b, c in zip(insts, single, lev, again):
+        ref = float(a[0])
+        assert float(a.max() - a.min()) == 0.0
+        assert float(b.max() - b.min()) == 0.0
+        assert abs(float(b[0]) - ref) <= 1e-5 * max(1.0, abs(ref)), (x.gamma, float(b[0]), ref)
+        assert torch.equal(b, c)
+    # the levels differ between instances (the call does not mix them up)
+    assert len({round(float(v[0]), 9) for v in lev}) == len(insts)
+    with pytest.raises(ValueError):
+        B.cpmdp_mlp_predict_levels(w.params, [torch.zeros(m ** 3, device="cuda")], [0.9, 0.9], [0.1],
+                                   m, [lev[0]], w.infer_ws)
+
+
 def test_warm_start_reduces_sweeps(B):
     """Train on solved instances of the generator (small grids), then solve
     held-out instances from V0 = 0, from V0 = 0 with the bound shift (the
