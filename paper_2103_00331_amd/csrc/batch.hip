@@ -420,6 +420,7 @@ struct cpmdp_batch {
   char* ws = nullptr;
   hipStream_t user_stream = nullptr;
   hipStream_t stream = nullptr;       // private capture stream (default priority)
+  hipStream_t stream64 = nullptr;     // the FP64 sweeps' branch of a captured replay
   bool bound = false;
   // device carve
   BInst* d_insts = nullptr;
@@ -715,20 +716,36 @@ int graph_for(cpmdp_batch_t* b, int k, hipGraphExec_t* out, bool eval = false) {
     return CPMDP_OK;
   }
   const BatchArgs a = make_args(b);
+  // Value iteration: the FP32 and the FP64 instances are disjoint, so their k
+  // sweeps are two independent chains (a fork onto stream64 and a join), and
+  // the launches of one precision need not wait for the other's.
+  hipEvent_t fork = nullptr, join = nullptr;
+  if (!eval) {
+    BHIP(b, hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+    BHIP(b, hipEventCreateWithFlags(&join, hipEventDisableTiming));
+  }
   BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-  for (int j = 0; j < k; ++j) {
-    if (eval) {
+  if (eval) {
+    for (int j = 0; j < k; ++j)
       hipLaunchKernelGGL((batch_sweep_kernel<float, MODE_EVAL>), dim3(b->grid), dim3(kBBlock), 0,
                          b->stream, a, j);
-    } else {
+  } else {
+    (void)hipEventRecord(fork, b->stream);
+    (void)hipStreamWaitEvent(b->stream64, fork, 0);
+    for (int j = 0; j < k; ++j)
       hipLaunchKernelGGL((batch_sweep_kernel<float, MODE_MAX>), dim3(b->grid), dim3(kBBlock), 0,
                          b->stream, a, j);
+    for (int j = 0; j < k; ++j)
       hipLaunchKernelGGL((batch_sweep_kernel<double, MODE_MAX>), dim3(b->grid), dim3(kBBlock), 0,
-                         b->stream, a, j);
-    }
+                         b->stream64, a, j);
+    (void)hipEventRecord(join, b->stream64);
+    (void)hipStreamWaitEvent(b->stream, join, 0);
   }
   hipGraph_t g = nullptr;
-  BHIP(b, hipStreamEndCapture(b->stream, &g));
+  const hipError_t ce = hipStreamEndCapture(b->stream, &g);
+  if (fork) (void)hipEventDestroy(fork);
+  if (join) (void)hipEventDestroy(join);
+  BHIP(b, ce);
   hipGraphExec_t ex = nullptr;
   BHIP(b, hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
   (void)hipGraphDestroy(g);
@@ -1064,6 +1081,7 @@ int cpmdp_batch_bind(cpmdp_batch_t* b, void* ws, size_t bytes, void* stream) {
     return bfail(b, CPMDP_E_WORKSPACE, "batch workspace missing, misaligned or too small");
   b->user_stream = static_cast<hipStream_t>(stream);
   if (!b->stream) BHIP(b, hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+  if (!b->stream64) BHIP(b, hipStreamCreateWithFlags(&b->stream64, hipStreamNonBlocking));
   if (!b->tiles_copied) BHIP(b, hipEventCreateWithFlags(&b->tiles_copied, hipEventDisableTiming));
   if (!b->descs_copied) BHIP(b, hipEventCreateWithFlags(&b->descs_copied, hipEventDisableTiming));
   b->tiles_pending = false;
@@ -1485,6 +1503,7 @@ void cpmdp_batch_destroy(cpmdp_batch_t* b) {
   if (!b) return;
   clear_graphs(b);
   if (b->stream) (void)hipStreamDestroy(b->stream);
+  if (b->stream64) (void)hipStreamDestroy(b->stream64);
   if (b->h_res) (void)hipHostFree(b->h_res);
   if (b->h_tiles) (void)hipHostFree(b->h_tiles);
   if (b->h_ntiles) (void)hipHostFree(b->h_ntiles);
