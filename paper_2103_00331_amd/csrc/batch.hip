@@ -1260,7 +1260,15 @@ int cpmdp_batch_solve(cpmdp_batch_t* b, double* const* V_devs, int32_t* const* p
       if (rc) return rc;
       rc = upload_tiles(b, active, &nt, true);
       if (rc) return rc;
-      int64_t left = b->k;
+      // Longer replays once few states are left: their sweeps take a few
+      // microseconds, the host round trip between replays far more (an
+      // instance that stops early skips the rest of the replay on the device)
+      int64_t act_states = 0;
+      for (size_t i = 0; i < n; ++i)
+        if (active[i]) act_states += b->lay[i].Sp;
+      const int kk = act_states * 100 < b->total_states ? 4 * b->k
+                     : act_states * 10 < b->total_states ? 2 * b->k : b->k;
+      int64_t left = std::min(kk, kBMaxK);
       for (size_t i = 0; i < n; ++i)
         if (active[i]) left = std::min<int64_t>(left, max_iter - 1 - sweeps[i]);
       const int k = static_cast<int>(std::max<int64_t>(left, 1));
