@@ -131,7 +131,10 @@ def march_batch():
              I.grid_small([6, 7, 5], slip=0.1, gamma=0.95, seed=44),
              # last side not a multiple of 4: one state per lane, one-pass tiles
              I.grid_small([8, 21, 25, 35], slip=0.1, gamma=0.9, seed=45),
-             I.grid_small([9, 130, 131], slip=0.2, gamma=0.9, seed=46)]
+             I.grid_small([9, 130, 131], slip=0.2, gamma=0.9, seed=46),
+             # 16 planes of 17,280 states: with few tiles in the batch, four
+             # marching segments of 4 planes
+             I.grid_small([16, 18, 30, 32], slip=0.12, gamma=0.9, seed=47)]
     log("[batch] oracle for the marching batch")
     refs = []
     for x in insts:
@@ -148,10 +151,11 @@ def march_batch():
 @pytest.mark.parametrize("method", [0, 1])
 def test_batch_marching_tiles_match_oracle(B, march_batch, method, sched):
     """Instances whose planes of fixed i_0 hold >= 16384 states get marching
-    tiles (the whole dim-0 column of 1024 plane offsets per tile) next to
-    one-pass tiles of small instances; rows whose last side is not a multiple
-    of 4 are padded in the batch's layout.  Every tile schedule: VI and PI
-    against the oracle."""
+    tiles (1024 plane offsets per tile; a batch this small cuts each dim-0
+    column into segments of at least 4 planes) next to one-pass tiles of
+    small instances; rows whose last side is not a multiple of 4 are padded
+    in the batch's layout.  Every tile schedule: VI and PI against the
+    oracle."""
     insts, refs = march_batch
     log(f"[batch] marching tiles, method {method}, schedule {sched}")
     eps = 1e-7
