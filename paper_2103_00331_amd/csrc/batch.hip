@@ -45,8 +45,9 @@ struct BInst {
   GridGeom g;
   int32_t A, vec, axis, stage;
   int32_t parity, eparity;     // V ping-pong; PI correction (V32 = e) ping-pong
-  int32_t mtiles;               // > 0: marching tiles of 1024 plane offsets per plane
+  int32_t mtiles;               // > 0: FP32 marching tiles of 1024 plane offsets per plane
   int32_t mseg;                 // planes per marching segment (0: all planes)
+  int32_t mtiles64, pad_m;      // FP64 marching tiles (512 plane offsets: 2 states per thread)
   float gamma32, pad1;
   double gamma64;
   float base32[2 * kBMaxN + 1];
@@ -69,7 +70,8 @@ static_assert(sizeof(BInst) % 4 == 0, "descriptor copied as words");
 // Tile (instance, y): y >= 0: states [y, y + tile_states) of the instance;
 // y < 0: marching tile q = -1 - y, plane offsets [1024 (q % mtiles), + 1024)
 // over planes [z mseg, (z + 1) mseg), z = q / mtiles (all planes when mseg
-// is 0; see march_column).
+// is 0; see march_column); FP64 tiles the same with 512 offsets and
+// mtiles64.
 struct BatchArgs {
   const BInst* insts;
   const int2* tiles;
@@ -180,14 +182,16 @@ __device__ __forceinline__ void tile_dispatch_n(const BInst& d, const StencilIO<
   const GridGeom g = ugeom<N>(d.g);
   const StencilIO<T> io = uio(io_l);
   // every stored row holds a multiple of 4 states (padded layout): 4 per lane
+  // in FP32, 2 in FP64 (half the value registers)
+  constexpr int VEC = sizeof(T) == 8 ? 2 : 4;
   if (d.axis) {
     UWeights<T, N> uw;
     const StencilW<T> W = uw.load(W_l);
-    tile_states<T, N, MODE, 4, true>(g, io, W, s0, s1, tol, res, res_d, ch);
+    tile_states<T, N, MODE, VEC, true>(g, io, W, s0, s1, tol, res, res_d, ch);
   } else {
     const StencilW<T> W{W_l.base, W_l.axis, ufirst_ptr(W_l.full), ufirst_ptr(W_l.eval), W_l.A,
                         W_l.gamma};
-    tile_states<T, N, MODE, 4, false>(g, io, W, s0, s1, tol, res, res_d, ch);
+    tile_states<T, N, MODE, VEC, false>(g, io, W, s0, s1, tol, res, res_d, ch);
   }
 }
 
@@ -237,14 +241,17 @@ template <typename T, int MODE>
 __device__ __forceinline__ void march_dispatch(const BInst& d, const StencilIO<T>& io_l,
                                                const StencilW<T>& W_l, int q, T& res, double& res_d,
                                                unsigned& ch) {
-  const int p = (q % d.mtiles) * (kBBlock * 4) + threadIdx.x * 4;
+  // FP64 marches 2 states per thread (half the value registers of 4)
+  constexpr int VEC = sizeof(T) == 8 ? 2 : 4;
+  const int mt = VEC == 2 ? d.mtiles64 : d.mtiles;
+  const int p = (q % mt) * (kBBlock * VEC) + threadIdx.x * VEC;
   const GridGeom g = ugeom<4>(d.g);
-  const int i0 = d.mseg > 0 ? (q / d.mtiles) * d.mseg : 0;
+  const int i0 = d.mseg > 0 ? (q / mt) * d.mseg : 0;
   const int i1 = d.mseg > 0 ? min(i0 + d.mseg, g.size[0]) : g.size[0];
   const StencilIO<T> io = uio(io_l);
   UWeights<T, 4> uw;
   const StencilW<T> W = uw.load(W_l);
-  march_column<T, 4, MODE, true>(g, io, W, p, i0, i1, T(0), res, res_d, ch);
+  march_column<T, 4, MODE, true, VEC>(g, io, W, p, i0, i1, T(0), res, res_d, ch);
 }
 
 template <typename T>
@@ -618,7 +625,7 @@ int upload_tiles(cpmdp_batch_t* b, const std::vector<char>& want, int64_t* count
   int64_t n_march = 0, n_other = 0;
   for (size_t i = 0; i < b->hs.size(); ++i) {
     if (!want[i]) continue;
-    if (march && b->hd[i].mtiles > 0) n_march += b->hd[i].mtiles;
+    if (march && b->hd[i].mtiles > 0) n_march += want[i] == 2 ? b->hd[i].mtiles64 : b->hd[i].mtiles;
     else n_other += (b->lay[i].Sp + ts - 1) / ts;
   }
   const int64_t goal = kBSegGoal * static_cast<int64_t>(G);
@@ -648,12 +655,14 @@ int upload_tiles(cpmdp_batch_t* b, const std::vector<char>& want, int64_t* count
         const int64_t planes = d.g.size[0];
         const int64_t seg = d.mseg > 0 ? d.mseg : planes;
         const int64_t nseg = (planes + seg - 1) / seg;
-        if (nt + nseg * d.mtiles > b->max_tiles)
+        const int mt = grp == 2 ? d.mtiles64 : d.mtiles;
+        const int64_t offs = grp == 2 ? kBBlock * 2 : kBBlock * 4;   // plane offsets per tile
+        if (nt + nseg * mt > b->max_tiles)
           return bfail(b, CPMDP_E_STATE, "batch tile table overflow");
         for (int64_t z = 0; z < nseg; ++z) {
-          for (int q = 0; q < d.mtiles; ++q) {
-            b->h_tiles[nt++] = make_int2(static_cast<int>(i), static_cast<int>(-1 - (z * d.mtiles + q)));
-            weight.push_back(std::min(seg, planes - z * seg) * kBBlock * 4);
+          for (int q = 0; q < mt; ++q) {
+            b->h_tiles[nt++] = make_int2(static_cast<int>(i), static_cast<int>(-1 - (z * mt + q)));
+            weight.push_back(std::min(seg, planes - z * seg) * offs);
           }
         }
       } else {
@@ -1132,6 +1141,7 @@ int cpmdp_batch_bind(cpmdp_batch_t* b, void* ws, size_t bytes, void* stream) {
                    ? static_cast<int32_t>((plane + kBBlock * 4 - 1) / (kBBlock * 4))
                    : 0;
     d.mseg = 0;
+    d.mtiles64 = d.mtiles > 0 ? static_cast<int32_t>((plane + kBBlock * 2 - 1) / (kBBlock * 2)) : 0;
     d.parity = 0;
     d.gamma32 = static_cast<float>(h->gamma);
     d.gamma64 = h->gamma;

@@ -22,11 +22,29 @@ template <>
 struct VecOf<float, 4> { using type = float4; };
 template <>
 struct VecOf<double, 4> { using type = double4; };
+template <>
+struct VecOf<float, 2> { using type = float2; };
+template <>
+struct VecOf<double, 2> { using type = double2; };
+template <int VEC>
+struct IntVec;
+template <>
+struct IntVec<4> { using type = int4; };
+template <>
+struct IntVec<2> { using type = int2; };
 
 template <typename T>
 __device__ __forceinline__ T comp(const typename VecOf<T, 4>::type& v, int q) {
   return q == 0 ? v.x : (q == 1 ? v.y : (q == 2 ? v.z : v.w));
 }
+template <typename T>
+__device__ __forceinline__ T comp(const typename VecOf<T, 2>::type& v, int q) {
+  return q == 0 ? v.x : v.y;
+}
+__device__ __forceinline__ int icomp(const int4& v, int q) {
+  return q == 0 ? v.x : (q == 1 ? v.y : (q == 2 ? v.z : v.w));
+}
+__device__ __forceinline__ int icomp(const int2& v, int q) { return q == 0 ? v.x : v.y; }
 
 template <typename T>
 __device__ __forceinline__ T tnanmax(T a, T b) {
@@ -150,6 +168,46 @@ __device__ __forceinline__ void store4_stream(T* p, const V4& o) {
   const nv4 v = {o.x, o.y, o.z, o.w};
   __builtin_nontemporal_store(v, reinterpret_cast<nv4*>(p));
 }
+template <typename V2, typename T>
+__device__ __forceinline__ V2 load2_stream(const T* p) {
+  typedef T nv2 __attribute__((ext_vector_type(2)));
+  const nv2 v = __builtin_nontemporal_load(reinterpret_cast<const nv2*>(p));
+  V2 o;
+  o.x = v.x;
+  o.y = v.y;
+  return o;
+}
+template <typename V2, typename T>
+__device__ __forceinline__ void store2_stream(T* p, const V2& o) {
+  typedef T nv2 __attribute__((ext_vector_type(2)));
+  const nv2 v = {o.x, o.y};
+  __builtin_nontemporal_store(v, reinterpret_cast<nv2*>(p));
+}
+// VEC values of a state run as one vector (nontemporal when STREAM)
+template <typename T, int VEC, bool STREAM>
+__device__ __forceinline__ typename VecOf<T, VEC>::type loadv(const T* p) {
+  using VV = typename VecOf<T, VEC>::type;
+  if constexpr (!STREAM) return *reinterpret_cast<const VV*>(p);
+  else if constexpr (VEC == 4) return load4_stream<VV>(p);
+  else return load2_stream<VV>(p);
+}
+template <typename T, int VEC, bool STREAM>
+__device__ __forceinline__ void storev(T* p, const T (&v)[VEC]) {
+  using VV = typename VecOf<T, VEC>::type;
+  VV o;
+  if constexpr (VEC == 4) {
+    o.x = v[0];
+    o.y = v[1];
+    o.z = v[2];
+    o.w = v[3];
+  } else {
+    o.x = v[0];
+    o.y = v[1];
+  }
+  if constexpr (!STREAM) *reinterpret_cast<VV*>(p) = o;
+  else if constexpr (VEC == 4) store4_stream(p, o);
+  else store2_stream(p, o);
+}
 
 // States s .. s+3 along the last dimension (size[n-1] % 4 == 0, s % 4 == 0)
 // given their values c4 and the vectors of their +-e_k neighbours for
@@ -235,7 +293,78 @@ __device__ __forceinline__ void stencil_vec4(const GridGeom& g, const StencilIO<
   }
 }
 
-// The VEC states s .. s+VEC-1 (VEC = 4 needs m_last % 4 == 0 and s % 4 == 0):
+// The 2-wide form of stencil_vec4: states s and s + 1 (size[n-1] % 2 == 0,
+// s % 2 == 0), half the value registers per thread (the FP64 marching
+// sweep, whose 4-wide form holds 120 VGPRs).  Same neighbours, padding and
+// residual rules as stencil_vec4.
+template <typename T, int N, int MODE, bool AXIS, bool STREAM = false>
+__device__ __forceinline__ void stencil_vec2(const GridGeom& g, const StencilIO<T>& io,
+                                             const StencilW<T>& W, int s, int il,
+                                             const typename VecOf<T, 2>::type& c2,
+                                             const typename VecOf<T, 2>::type (&plus2)[N > 1 ? N - 1 : 1],
+                                             const typename VecOf<T, 2>::type (&minus2)[N > 1 ? N - 1 : 1],
+                                             T tol, T& res, double& res_d, unsigned& changed,
+                                             bool live = true) {
+  using V2 = typename VecOf<T, 2>::type;
+  constexpr int P = 2 * N + 1;
+  const T left = io.V[s - ((il > 0) ? 1 : 0)];
+  const T right = io.V[s + ((il + 2 < g.last) ? 2 : 1)];
+  const V2 r2 = loadv<T, 2, STREAM>(io.R + s);
+  const uint32_t tw = io.tbits[s >> 5] >> (s & 31);
+  int2 p2 = make_int2(-1, -1);
+  if (MODE != MODE_MAX && io.pi_in) p2 = *reinterpret_cast<const int2*>(io.pi_in + s);
+  uint32_t ob = 0u;   // 2 x 16-bit blocked-direction masks
+  if (io.obs) ob = *reinterpret_cast<const uint32_t*>(io.obs + s);
+  T outv[2];
+  int pnv[2];
+  unsigned ch = 0;
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    T nb[P];
+    nb[0] = comp<T>(c2, q);
+#pragma unroll
+    for (int k = 0; k < N - 1; ++k) {
+      nb[1 + 2 * k] = comp<T>(plus2[k], q);
+      nb[2 + 2 * k] = comp<T>(minus2[k], q);
+    }
+    const bool real = il + q < g.last;
+    nb[1 + 2 * (N - 1)] = (il + q + 1 < g.last) ? (q < 1 ? comp<T>(c2, q + 1) : right)
+                                                : comp<T>(c2, q);
+    nb[2 + 2 * (N - 1)] = q > 0 ? comp<T>(c2, q - 1) : left;
+    if (io.obs) block_points<T, P>(nb, (ob >> (16 * q)) & 0xFFFFu);
+    const int pold = icomp(p2, q);
+    pnv[q] = 0;
+    T rq = res;
+    unsigned cq = 0;
+    stencil_state<T, N, MODE, AXIS>(W, nb, comp<T>(r2, q), (tw >> q) & 1u, pold, tol, outv[q],
+                                    pnv[q], rq, cq);
+    if (real) {
+      res = rq;
+      ch += cq;
+    }
+  }
+  if (!live) return;
+  changed += ch;
+  if constexpr (MODE == MODE_RESID) {
+    float2 r;
+    double d[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      d[q] = static_cast<double>(outv[q]) - static_cast<double>(comp<T>(c2, q));
+      if (il + q < g.last) res_d = nanmax(res_d, fabs(d[q]));
+    }
+    r.x = static_cast<float>(d[0]);
+    r.y = static_cast<float>(d[1]);
+    *reinterpret_cast<float2*>(io.r_out + s) = r;
+  } else {
+    if (io.Vout) storev<T, 2, STREAM>(io.Vout + s, outv);
+    if (MODE == MODE_GREEDY && io.pi_out)
+      *reinterpret_cast<int2*>(io.pi_out + s) = make_int2(pnv[0], pnv[1]);
+  }
+}
+
+// The VEC states s .. s+VEC-1 (VEC = 2 or 4 needs m_last % VEC == 0 and
+// s % VEC == 0):
 // loads, per-state work, stores.  Loads use clamped addresses (at the grid
 // edge the neighbour is the state itself), so every load is unconditional.
 // STREAM: R loads and V' stores non-temporal (VEC = 4).
@@ -255,7 +384,7 @@ __device__ __forceinline__ void stencil_chunk(const GridGeom& g, const StencilIO
   }
   idx[0] = static_cast<int>(rem);
 
-  if (VEC == 1) {
+  if constexpr (VEC == 1) {
     T nb[P];
     const T c = io.V[s];
     nb[0] = c;
@@ -282,6 +411,18 @@ __device__ __forceinline__ void stencil_chunk(const GridGeom& g, const StencilIO
       if (io.Vout) io.Vout[s] = out;
       if (MODE == MODE_GREEDY && io.pi_out) io.pi_out[s] = pnew;
     }
+  } else if constexpr (VEC == 2) {
+    using V2 = typename VecOf<T, 2>::type;
+    const V2 c2 = *reinterpret_cast<const V2*>(io.V + s);
+    V2 plus2[N > 1 ? N - 1 : 1], minus2[N > 1 ? N - 1 : 1];
+#pragma unroll
+    for (int k = 0; k < N - 1; ++k) {
+      const int st = g.stride[k];
+      plus2[k] = *reinterpret_cast<const V2*>(io.V + s + ((idx[k] < g.size[k] - 1) ? st : 0));
+      minus2[k] = *reinterpret_cast<const V2*>(io.V + s - ((idx[k] > 0) ? st : 0));
+    }
+    stencil_vec2<T, N, MODE, AXIS, STREAM>(g, io, W, s, idx[N - 1], c2, plus2, minus2, tol, res,
+                                           res_d, changed, live);
   } else {
     using V4 = typename VecOf<T, 4>::type;
     const V4 c4 = *reinterpret_cast<const V4*>(io.V + s);
@@ -297,16 +438,17 @@ __device__ __forceinline__ void stencil_chunk(const GridGeom& g, const StencilIO
   }
 }
 
-// Marching form: the 4 states at plane offset p (p % 4 == 0) of planes
-// i_0 in [i_begin, i_end) (a plane = the S / m_0 states of one i_0), in
-// order, with the previous, current and next plane's values in registers so
-// that the dim-0 neighbours are not fetched again; the plane after next is
-// prefetched.  Needs n >= 2 and m_last % 4 == 0; p >= S / m_0 is a no-op.
-template <typename T, int N, int MODE, bool AXIS>
+// Marching form: the VEC (4 or 2) states at plane offset p (p % VEC == 0)
+// of planes i_0 in [i_begin, i_end) (a plane = the S / m_0 states of one
+// i_0), in order, with the previous, current and next plane's values in
+// registers so that the dim-0 neighbours are not fetched again; the plane
+// after next is prefetched.  Needs n >= 2 and m_last % VEC == 0; p >= S / m_0
+// is a no-op.
+template <typename T, int N, int MODE, bool AXIS, int VEC = 4>
 __device__ __forceinline__ void march_column(const GridGeom& g, const StencilIO<T>& io,
                                              const StencilW<T>& W, int p, int i_begin, int i_end,
                                              T tol, T& res, double& res_d, unsigned& changed) {
-  using V4 = typename VecOf<T, 4>::type;
+  using VV = typename VecOf<T, VEC>::type;
   const int PL = g.stride[0], m0 = g.size[0];
   if (p >= PL || i_begin >= i_end) return;
   int idx[N];
@@ -319,23 +461,27 @@ __device__ __forceinline__ void march_column(const GridGeom& g, const StencilIO<
   }
   idx[0] = 0;
   const T* Vp = io.V + p;
-  V4 prev = *reinterpret_cast<const V4*>(Vp + max(i_begin - 1, 0) * PL);
-  V4 cur = *reinterpret_cast<const V4*>(Vp + i_begin * PL);
-  V4 nxt = *reinterpret_cast<const V4*>(Vp + min(i_begin + 1, m0 - 1) * PL);
+  VV prev = *reinterpret_cast<const VV*>(Vp + max(i_begin - 1, 0) * PL);
+  VV cur = *reinterpret_cast<const VV*>(Vp + i_begin * PL);
+  VV nxt = *reinterpret_cast<const VV*>(Vp + min(i_begin + 1, m0 - 1) * PL);
   for (int i0 = i_begin; i0 < i_end; ++i0) {
-    const V4 nn = *reinterpret_cast<const V4*>(Vp + min(i0 + 2, m0 - 1) * PL);   // prefetch
+    const VV nn = *reinterpret_cast<const VV*>(Vp + min(i0 + 2, m0 - 1) * PL);   // prefetch
     const int s = i0 * PL + p;
-    V4 plus4[N - 1], minus4[N - 1];
-    plus4[0] = nxt;
-    minus4[0] = prev;
+    VV plusv[N - 1], minusv[N - 1];
+    plusv[0] = nxt;
+    minusv[0] = prev;
 #pragma unroll
     for (int k = 1; k < N - 1; ++k) {
       const int st = g.stride[k];
-      plus4[k] = *reinterpret_cast<const V4*>(io.V + s + ((idx[k] < g.size[k] - 1) ? st : 0));
-      minus4[k] = *reinterpret_cast<const V4*>(io.V + s - ((idx[k] > 0) ? st : 0));
+      plusv[k] = *reinterpret_cast<const VV*>(io.V + s + ((idx[k] < g.size[k] - 1) ? st : 0));
+      minusv[k] = *reinterpret_cast<const VV*>(io.V + s - ((idx[k] > 0) ? st : 0));
     }
-    stencil_vec4<T, N, MODE, AXIS, true>(g, io, W, s, idx[N - 1], cur, plus4, minus4, tol, res,
-                                         res_d, changed);
+    if constexpr (VEC == 4)
+      stencil_vec4<T, N, MODE, AXIS, true>(g, io, W, s, idx[N - 1], cur, plusv, minusv, tol, res,
+                                           res_d, changed);
+    else
+      stencil_vec2<T, N, MODE, AXIS, true>(g, io, W, s, idx[N - 1], cur, plusv, minusv, tol, res,
+                                           res_d, changed);
     prev = cur;
     cur = nxt;
     nxt = nn;
