@@ -734,16 +734,20 @@ def bench_batch(args):
             "traffic": _traffic("batch_sweep_fp32_batch512.md", BATCH_SRC),
             "kernel": "batch_sweep_kernel<float, MODE_MAX> (all 512 instances)",
             "kernel_ms": sweep_ms, "algorithmic_bytes_per_launch": algo_bytes}
-    Vs = [torch.zeros(x.n_states, dtype=torch.float64, device="cuda") for x in insts]
-    pis = [torch.zeros(x.n_states, dtype=torch.int32, device="cuda") for x in insts]
+    # one allocation per array kind, a contiguous view per instance: V0 = 0 and
+    # the policies are reset with one fill each
+    sizes = [x.n_states for x in insts]
+    V_all = torch.zeros(tot_states, dtype=torch.float64, device="cuda")
+    pi_all = torch.zeros(tot_states, dtype=torch.int32, device="cuda")
+    Vs = list(torch.split(V_all, sizes))
+    pis = list(torch.split(pi_all, sizes))
 
     method = 1 if args.method == "pi" else 0
     last = {}
 
     def solve():
-        for V, p in zip(Vs, pis):
-            V.zero_()
-            p.zero_()
+        V_all.zero_()
+        pi_all.zero_()
         code, sweeps, res = B.cpmdp_batch_solve(bm.b, Vs, pis, eps, 100000, B.CPMDP_FP32, method)
         if code not in (B.CPMDP_OK, B.CPMDP_POLICY_UNSETTLED) or not np.all(res <= eps):
             bad = np.nonzero(~(res <= eps))[0]
