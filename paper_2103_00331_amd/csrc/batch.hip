@@ -401,6 +401,36 @@ __global__ __launch_bounds__(kBBlock) void pad_rows_kernel(const E* __restrict__
   }
 }
 
+// Many copies between callers' row-major arrays and the batch's padded
+// layout in one launch: job blockIdx.y, the blocks of a job striding over
+// its stored entries (as pad_rows_kernel; rows with L == Lp copy straight).
+struct CopyJob {
+  const void* src;
+  void* dst;
+  int64_t rows;
+  int32_t L, Lp;
+  int32_t to_padded, pad;
+};
+template <typename E>
+__global__ __launch_bounds__(kBBlock) void batch_copy_kernel(const CopyJob* __restrict__ jobs) {
+  const CopyJob j = jobs[blockIdx.y];
+  const E* __restrict__ src = static_cast<const E*>(j.src);
+  E* __restrict__ dst = static_cast<E*>(j.dst);
+  const int64_t total = j.rows * j.Lp;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (j.L == j.Lp) {
+    for (; e < total; e += stride) dst[e] = src[e];
+    return;
+  }
+  for (; e < total; e += stride) {
+    const int64_t r = e / j.Lp;
+    const int c = static_cast<int>(e - r * j.Lp);
+    if (j.to_padded) dst[e] = c < j.L ? src[r * j.L + c] : E(0);
+    else if (c < j.L) dst[r * j.L + c] = src[e];
+  }
+}
+
 }  // namespace cpm
 
 using namespace cpm;
@@ -448,6 +478,10 @@ struct cpmdp_batch {
   BInst* h_descs = nullptr;           // pinned staging copy of hd
   hipEvent_t descs_copied = nullptr;
   bool descs_pending = false;
+  CopyJob* d_jobs = nullptr;          // copy jobs (values, then policies): 2 n
+  CopyJob* h_jobs = nullptr;          // pinned staging copy
+  hipEvent_t jobs_copied = nullptr;
+  bool jobs_pending = false;
   // tuning
   int tile_states = 2048;
   int grid = kMaxBlocks;
@@ -517,7 +551,7 @@ size_t fixed_bytes(const cpmdp_batch_t* b, int64_t max_tiles) {
   const size_t n = b->hs.size();
   return al(n * sizeof(BInst)) + al(max_tiles * sizeof(int2)) + al(64) +
          al(static_cast<size_t>(kBMaxK) * n * kBSpread * 8) + al(n * 8) + al(n * 4) +
-         al(2 * (kMaxBlocks + 1) * sizeof(int));
+         al(2 * (kMaxBlocks + 1) * sizeof(int)) + al(2 * n * sizeof(CopyJob));
 }
 
 int64_t count_tiles(const cpmdp_batch_t* b, int ts) {
@@ -530,37 +564,6 @@ int pad_grid(int64_t n) {
   return static_cast<int>(std::min<int64_t>((n + kBBlock - 1) / kBBlock, 4096));
 }
 
-// Caller's V (FP64, real layout) -> stored V64[0] of instance i.
-int copy_in_values(cpmdp_batch_t* b, size_t i, const double* V) {
-  const BLayout& l = b->lay[i];
-  double* dst = b->hd[i].V64[0];
-  if (!l.padded()) {
-    BHIP(b, hipMemcpyAsync(dst, V, l.S * 8, hipMemcpyDeviceToDevice, b->stream));
-    return CPMDP_OK;
-  }
-  hipLaunchKernelGGL(pad_rows_kernel<double>, dim3(pad_grid(l.Sp)), dim3(kBBlock), 0, b->stream, V,
-                     dst, l.S / l.L, l.L, l.Lp, 1, 0.0);
-  BHIP(b, hipGetLastError());
-  return CPMDP_OK;
-}
-
-// Stored V64[parity] (and the padded policy) of instance i -> caller's buffers.
-int copy_out(cpmdp_batch_t* b, size_t i, double* V, int32_t* pi) {
-  const BLayout& l = b->lay[i];
-  const BInst& d = b->hd[i];
-  if (!l.padded()) {
-    BHIP(b, hipMemcpyAsync(V, d.V64[d.parity], l.S * 8, hipMemcpyDeviceToDevice, b->stream));
-    return CPMDP_OK;
-  }
-  hipLaunchKernelGGL(pad_rows_kernel<double>, dim3(pad_grid(l.Sp)), dim3(kBBlock), 0, b->stream,
-                     d.V64[d.parity], V, l.S / l.L, l.L, l.Lp, 0, 0.0);
-  if (pi)
-    hipLaunchKernelGGL(pad_rows_kernel<int32_t>, dim3(pad_grid(l.Sp)), dim3(kBBlock), 0, b->stream,
-                       l.pi, pi, l.S / l.L, l.L, l.Lp, 0, 0);
-  BHIP(b, hipGetLastError());
-  return CPMDP_OK;
-}
-
 // The policy the kernels read and write for instance i: the caller's buffer,
 // or the padded copy (filled from the caller's when `load`).
 int32_t* policy_buffer(cpmdp_batch_t* b, size_t i, int32_t* caller, bool load) {
@@ -571,6 +574,56 @@ int32_t* policy_buffer(cpmdp_batch_t* b, size_t i, int32_t* caller, bool load) {
     hipLaunchKernelGGL(pad_rows_kernel<int32_t>, dim3(pad_grid(l.Sp)), dim3(kBBlock), 0, b->stream,
                        caller, l.pi, l.S / l.L, l.L, l.Lp, 1, 0);
   return l.pi;
+}
+
+// Every instance's copy at once: values (FP64) jobs first, then policy
+// (int32) jobs, through the pinned staging table; one launch per kind.
+int launch_copies(cpmdp_batch_t* b, const std::vector<CopyJob>& vj, const std::vector<CopyJob>& pj) {
+  if (vj.empty() && pj.empty()) return CPMDP_OK;
+  if (b->jobs_pending) {
+    BHIP(b, hipEventSynchronize(b->jobs_copied));
+    b->jobs_pending = false;
+  }
+  std::copy(vj.begin(), vj.end(), b->h_jobs);
+  std::copy(pj.begin(), pj.end(), b->h_jobs + vj.size());
+  const size_t nj = vj.size() + pj.size();
+  BHIP(b, hipMemcpyAsync(b->d_jobs, b->h_jobs, nj * sizeof(CopyJob), hipMemcpyHostToDevice, b->stream));
+  BHIP(b, hipEventRecord(b->jobs_copied, b->stream));
+  b->jobs_pending = true;
+  constexpr size_t kMaxY = 65535;   // jobs per launch (grid y)
+  for (size_t j0 = 0; j0 < vj.size(); j0 += kMaxY)
+    hipLaunchKernelGGL(batch_copy_kernel<double>,
+                       dim3(128, static_cast<unsigned>(std::min(kMaxY, vj.size() - j0))),
+                       dim3(kBBlock), 0, b->stream, b->d_jobs + j0);
+  for (size_t j0 = 0; j0 < pj.size(); j0 += kMaxY)
+    hipLaunchKernelGGL(batch_copy_kernel<int32_t>,
+                       dim3(128, static_cast<unsigned>(std::min(kMaxY, pj.size() - j0))),
+                       dim3(kBBlock), 0, b->stream, b->d_jobs + vj.size() + j0);
+  BHIP(b, hipGetLastError());
+  return CPMDP_OK;
+}
+
+// Callers' V -> stored V64[0] of every instance.
+int copy_in_all(cpmdp_batch_t* b, double* const* V_devs) {
+  std::vector<CopyJob> vj;
+  for (size_t i = 0; i < b->hs.size(); ++i) {
+    const BLayout& l = b->lay[i];
+    vj.push_back(CopyJob{V_devs[i], b->hd[i].V64[0], l.S / l.L, l.L, l.Lp, 1, 0});
+  }
+  return launch_copies(b, vj, {});
+}
+
+// Stored V64[parity] (and the padded policies) -> callers' buffers.
+int copy_out_all(cpmdp_batch_t* b, double* const* V_devs, int32_t* const* pi_devs) {
+  std::vector<CopyJob> vj, pj;
+  for (size_t i = 0; i < b->hs.size(); ++i) {
+    const BLayout& l = b->lay[i];
+    const BInst& d = b->hd[i];
+    vj.push_back(CopyJob{d.V64[d.parity], V_devs[i], l.S / l.L, l.L, l.Lp, 0, 0});
+    if (pi_devs && pi_devs[i] && l.padded())
+      pj.push_back(CopyJob{l.pi, pi_devs[i], l.S / l.L, l.L, l.Lp, 0, 0});
+  }
+  return launch_copies(b, vj, pj);
 }
 
 double bits_to_double(unsigned long long u) {
@@ -858,13 +911,15 @@ int batch_pi(cpmdp_batch_t* b, double* const* V_devs, int32_t* const* pi_devs, d
   for (size_t i = 0; i < n; ++i) {
     cpmdp_t* h = b->hs[i];
     BInst& d = b->hd[i];
-    int rc0 = copy_in_values(b, i, V_devs[i]);
-    if (rc0) return rc0;
     d.parity = 0;
     d.eparity = 0;
     const double rmax = h->rmax;
     eps_floor[i] = 0.5 * eps * (1.0 - h->gamma);
     eps_eval[i] = std::max(eps_floor[i], 1e-1 * std::max(rmax, 1e-300));   // first policy: loosely
+  }
+  {
+    const int rc0 = copy_in_all(b, V_devs);
+    if (rc0) return rc0;
   }
   // every policy entry must name an action (the evaluation sweeps index the
   // weight table with it)
@@ -1022,9 +1077,9 @@ int batch_pi(cpmdp_batch_t* b, double* const* V_devs, int32_t* const* pi_devs, d
     if (all_done) break;
   }
   bool all_ok = true, any_unsettled = false;
+  rc = copy_out_all(b, V_devs, pi_devs);
+  if (rc) return rc;
   for (size_t i = 0; i < n; ++i) {
-    rc = copy_out(b, i, V_devs[i], pi_devs[i]);
-    if (rc) return rc;
     if (sweeps_out) sweeps_out[i] = sweeps[i];
     if (residual_out) residual_out[i] = cert[i];
     all_ok = all_ok && converged[i];
@@ -1093,6 +1148,7 @@ int cpmdp_batch_bind(cpmdp_batch_t* b, void* ws, size_t bytes, void* stream) {
   if (!b->stream64) BHIP(b, hipStreamCreateWithFlags(&b->stream64, hipStreamNonBlocking));
   if (!b->tiles_copied) BHIP(b, hipEventCreateWithFlags(&b->tiles_copied, hipEventDisableTiming));
   if (!b->descs_copied) BHIP(b, hipEventCreateWithFlags(&b->descs_copied, hipEventDisableTiming));
+  if (!b->jobs_copied) BHIP(b, hipEventCreateWithFlags(&b->jobs_copied, hipEventDisableTiming));
   b->tiles_pending = false;
   b->descs_pending = false;
   clear_graphs(b);
@@ -1111,7 +1167,9 @@ int cpmdp_batch_bind(cpmdp_batch_t* b, void* ws, size_t bytes, void* stream) {
   b->d_vmax = reinterpret_cast<unsigned long long*>(take(n * 8));
   b->d_changes = reinterpret_cast<unsigned int*>(take(n * 4));
   b->d_starts = reinterpret_cast<int*>(take(2 * (kMaxBlocks + 1) * sizeof(int)));
+  b->d_jobs = reinterpret_cast<CopyJob*>(take(2 * n * sizeof(CopyJob)));
   if (!b->h_res) {
+    BHIP(b, hipHostMalloc(reinterpret_cast<void**>(&b->h_jobs), 2 * n * sizeof(CopyJob), hipHostMallocDefault));
     BHIP(b, hipHostMalloc(reinterpret_cast<void**>(&b->h_changes), n * 4, hipHostMallocDefault));
     BHIP(b, hipHostMalloc(reinterpret_cast<void**>(&b->h_descs), n * sizeof(BInst), hipHostMallocDefault));
     BHIP(b, hipHostMalloc(reinterpret_cast<void**>(&b->h_starts), 2 * (kMaxBlocks + 1) * sizeof(int), hipHostMallocDefault));
@@ -1226,15 +1284,12 @@ int cpmdp_batch_solve(cpmdp_batch_t* b, double* const* V_devs, int32_t* const* p
     (void)hipEventDestroy(ready);
   }
   if (method == 1) return batch_pi(b, V_devs, pi_devs, eps, max_iter, sweeps_out, residual_out);
-  // inputs -> internal FP64 buffer 0
   std::vector<int64_t> sweeps(n, 0);
   std::vector<double> cert(n, INFINITY);
   std::vector<double> floor32(n, 0.0);
   for (size_t i = 0; i < n; ++i) {
     cpmdp_t* h = b->hs[i];
     BInst& d = b->hd[i];
-    int rc0 = copy_in_values(b, i, V_devs[i]);
-    if (rc0) return rc0;
     d.parity = 0;
     d.stage = precision == CPMDP_FP64 ? B_F64 : B_F32;
     d.pi_out = policy_buffer(b, i, pi_devs ? pi_devs[i] : nullptr, false);
@@ -1247,7 +1302,9 @@ int cpmdp_batch_solve(cpmdp_batch_t* b, double* const* V_devs, int32_t* const* p
     floor32[i] = 8.0 * std::ldexp(1.0, -24) * std::max(1.0, rmax / (1.0 - h->gamma));
     d.stop = d.stage == B_F32 ? std::max(eps, floor32[i] / 16.0) : eps;
   }
-  int rc = upload_descs(b);
+  int rc = copy_in_all(b, V_devs);   // inputs -> internal FP64 buffer 0
+  if (rc) return rc;
+  rc = upload_descs(b);
   if (rc) return rc;
   if (precision != CPMDP_FP64) {
     rc = launch_util(b, std::vector<char>(n, 1), 0);   // V32 <- V64
@@ -1358,9 +1415,9 @@ int cpmdp_batch_solve(cpmdp_batch_t* b, double* const* V_devs, int32_t* const* p
     }
   }
   bool all_ok = true;
+  rc = copy_out_all(b, V_devs, pi_devs);
+  if (rc) return rc;
   for (size_t i = 0; i < n; ++i) {
-    rc = copy_out(b, i, V_devs[i], pi_devs ? pi_devs[i] : nullptr);
-    if (rc) return rc;
     if (sweeps_out) sweeps_out[i] = sweeps[i];
     if (residual_out) residual_out[i] = cert[i];
     all_ok = all_ok && cert[i] <= eps;
@@ -1528,6 +1585,8 @@ void cpmdp_batch_destroy(cpmdp_batch_t* b) {
   if (b->h_changes) (void)hipHostFree(b->h_changes);
   if (b->tiles_copied) (void)hipEventDestroy(b->tiles_copied);
   if (b->descs_copied) (void)hipEventDestroy(b->descs_copied);
+  if (b->jobs_copied) (void)hipEventDestroy(b->jobs_copied);
+  if (b->h_jobs) (void)hipHostFree(b->h_jobs);
   if (b->h_descs) (void)hipHostFree(b->h_descs);
   if (b->h_starts) (void)hipHostFree(b->h_starts);
   delete b;
