@@ -464,20 +464,30 @@ struct cpmdp_batch {
   int2* d_tiles = nullptr;
   int* d_ntiles = nullptr;
   int* d_starts = nullptr;            // [2][kMaxBlocks + 1]
-  unsigned long long* d_res = nullptr;
+  unsigned long long* d_res = nullptr;    // [kBMaxK][n][kBSpread]: a replay's sweeps
+  unsigned long long* d_cres = nullptr;   // [n][kBSpread]: certificates, just ahead of d_res
   unsigned long long* d_vmax = nullptr;
   unsigned int* d_changes = nullptr;
   int64_t max_tiles = 0;
   // host pinned
   unsigned long long* h_res = nullptr;
-  int2* h_tiles = nullptr;
-  int* h_ntiles = nullptr;
-  int* h_starts = nullptr;
-  hipEvent_t tiles_copied = nullptr;  // the last tile-table copy out of h_tiles / h_ntiles
-  bool tiles_pending = false;
-  BInst* h_descs = nullptr;           // pinned staging copy of hd
+  // tile tables are staged in two pinned buffers used in turn, so that one is
+  // refilled while the copy out of the other may still be in flight
+  int2* h_tiles[2] = {nullptr, nullptr};
+  int* h_ntiles[2] = {nullptr, nullptr};
+  int* h_starts[2] = {nullptr, nullptr};
+  hipEvent_t tiles_copied[2] = {nullptr, nullptr};   // the last copy out of each buffer
+  bool tiles_pending[2] = {false, false};
+  int tslot = 0;
+  // what the device's tile table holds: an upload of the same table is skipped
+  std::vector<char> tiles_want;
+  int tiles_key[4] = {0, 0, 0, 0};    // march, tile size, grid, schedule
+  int64_t tiles_nt = 0;
+  bool tiles_valid = false;
+  BInst* h_descs = nullptr;           // pinned staging copy of hd (= the device's descriptors)
   hipEvent_t descs_copied = nullptr;
   bool descs_pending = false;
+  bool descs_valid = false;
   CopyJob* d_jobs = nullptr;          // copy jobs (values, then policies): 2 n
   CopyJob* h_jobs = nullptr;          // pinned staging copy
   hipEvent_t jobs_copied = nullptr;
@@ -550,7 +560,7 @@ size_t inst_bytes(const cpmdp_t* h) {
 size_t fixed_bytes(const cpmdp_batch_t* b, int64_t max_tiles) {
   const size_t n = b->hs.size();
   return al(n * sizeof(BInst)) + al(max_tiles * sizeof(int2)) + al(64) +
-         al(static_cast<size_t>(kBMaxK) * n * kBSpread * 8) + al(n * 8) + al(n * 4) +
+         al(static_cast<size_t>(kBMaxK + 1) * n * kBSpread * 8) + al(n * 8) + al(n * 4) +
          al(2 * (kMaxBlocks + 1) * sizeof(int)) + al(2 * n * sizeof(CopyJob));
 }
 
@@ -657,12 +667,22 @@ int upload_descs(cpmdp_batch_t* b);
 int upload_tiles(cpmdp_batch_t* b, const std::vector<char>& want, int64_t* count,
                  bool march = false) {
   march = march && b->march;
-  // h_tiles / h_ntiles / h_starts are pinned: the previous asynchronous copy
-  // out of them must have run before they are refilled
-  if (b->tiles_pending) {
-    BHIP(b, hipEventSynchronize(b->tiles_copied));
-    b->tiles_pending = false;
+  const int key[4] = {march ? 1 : 0, b->tile_states, b->grid, b->sched};
+  if (b->tiles_valid && b->tiles_want == want && std::equal(key, key + 4, b->tiles_key)) {
+    *count = b->tiles_nt;   // the device holds this table (and the segments it was cut with)
+    return CPMDP_OK;
   }
+  b->tiles_valid = false;
+  // the staging buffers are pinned: the asynchronous copy out of this one
+  // (two uploads ago) must have run before it is refilled
+  const int slot = b->tslot;
+  if (b->tiles_pending[slot]) {
+    BHIP(b, hipEventSynchronize(b->tiles_copied[slot]));
+    b->tiles_pending[slot] = false;
+  }
+  int2* const h_tiles = b->h_tiles[slot];
+  int* const h_ntiles = b->h_ntiles[slot];
+  int* const h_starts = b->h_starts[slot];
   int64_t nt = 0;
   const int ts = b->tile_states;
   const int G = b->grid;
@@ -714,13 +734,13 @@ int upload_tiles(cpmdp_batch_t* b, const std::vector<char>& want, int64_t* count
           return bfail(b, CPMDP_E_STATE, "batch tile table overflow");
         for (int64_t z = 0; z < nseg; ++z) {
           for (int q = 0; q < mt; ++q) {
-            b->h_tiles[nt++] = make_int2(static_cast<int>(i), static_cast<int>(-1 - (z * mt + q)));
+            h_tiles[nt++] = make_int2(static_cast<int>(i), static_cast<int>(-1 - (z * mt + q)));
             weight.push_back(std::min(seg, planes - z * seg) * offs);
           }
         }
       } else {
         for (int64_t s = 0; s < S; s += ts) {
-          b->h_tiles[nt++] = make_int2(static_cast<int>(i), static_cast<int>(s));
+          h_tiles[nt++] = make_int2(static_cast<int>(i), static_cast<int>(s));
           weight.push_back(std::min<int64_t>(ts, S - s));
         }
       }
@@ -729,7 +749,7 @@ int upload_tiles(cpmdp_batch_t* b, const std::vector<char>& want, int64_t* count
     // contiguous ranges of about equal weight
     int64_t total = 0;
     for (int64_t t = first; t < nt; ++t) total += weight[t];
-    int* st = b->h_starts + (grp - 1) * (G + 1);
+    int* st = h_starts + (grp - 1) * (G + 1);
     const int parts = b->sched == 0 ? G : kXcds;
     int64_t acc = 0, t = first;
     st[0] = static_cast<int>(first);
@@ -740,37 +760,49 @@ int upload_tiles(cpmdp_batch_t* b, const std::vector<char>& want, int64_t* count
     }
     st[parts] = static_cast<int>(nt);
   }
-  b->h_ntiles[0] = cnt[0];
-  b->h_ntiles[1] = cnt[1];
-  if (nt) BHIP(b, hipMemcpyAsync(b->d_tiles, b->h_tiles, nt * sizeof(int2), hipMemcpyHostToDevice, b->stream));
-  BHIP(b, hipMemcpyAsync(b->d_ntiles, b->h_ntiles, 2 * sizeof(int), hipMemcpyHostToDevice, b->stream));
-  BHIP(b, hipMemcpyAsync(b->d_starts, b->h_starts, 2 * (G + 1) * sizeof(int), hipMemcpyHostToDevice,
+  h_ntiles[0] = cnt[0];
+  h_ntiles[1] = cnt[1];
+  if (nt) BHIP(b, hipMemcpyAsync(b->d_tiles, h_tiles, nt * sizeof(int2), hipMemcpyHostToDevice, b->stream));
+  BHIP(b, hipMemcpyAsync(b->d_ntiles, h_ntiles, 2 * sizeof(int), hipMemcpyHostToDevice, b->stream));
+  BHIP(b, hipMemcpyAsync(b->d_starts, h_starts, 2 * (G + 1) * sizeof(int), hipMemcpyHostToDevice,
                          b->stream));
-  BHIP(b, hipEventRecord(b->tiles_copied, b->stream));
-  b->tiles_pending = true;
+  BHIP(b, hipEventRecord(b->tiles_copied[slot], b->stream));
+  b->tiles_pending[slot] = true;
+  b->tslot = slot ^ 1;
+  b->tiles_want = want;
+  std::copy(key, key + 4, b->tiles_key);
+  b->tiles_nt = nt;
+  b->tiles_valid = true;
   *count = nt;
   return CPMDP_OK;
 }
 
 // Descriptors go through a pinned staging copy guarded like the tile table.
+// The staging copy is what the device holds (the kernels only read the
+// descriptors), so an unchanged set is not copied again.
 int upload_descs(cpmdp_batch_t* b) {
+  const size_t bytes = b->hd.size() * sizeof(BInst);
+  if (b->descs_valid && std::memcmp(b->h_descs, b->hd.data(), bytes) == 0) return CPMDP_OK;
   if (b->descs_pending) {
     BHIP(b, hipEventSynchronize(b->descs_copied));
     b->descs_pending = false;
   }
-  std::memcpy(b->h_descs, b->hd.data(), b->hd.size() * sizeof(BInst));
-  BHIP(b, hipMemcpyAsync(b->d_insts, b->h_descs, b->hd.size() * sizeof(BInst),
-                         hipMemcpyHostToDevice, b->stream));
+  b->descs_valid = false;
+  std::memcpy(b->h_descs, b->hd.data(), bytes);
+  BHIP(b, hipMemcpyAsync(b->d_insts, b->h_descs, bytes, hipMemcpyHostToDevice, b->stream));
   BHIP(b, hipEventRecord(b->descs_copied, b->stream));
   b->descs_pending = true;
+  b->descs_valid = true;
   return CPMDP_OK;
 }
 
-// k sweeps captured as one graph: value iteration (FP32 tiles, then FP64
-// tiles, per sweep) or policy-iteration correction sweeps (FP32).
-int graph_for(cpmdp_batch_t* b, int k, hipGraphExec_t* out, bool eval = false) {
+// k sweeps captured as one graph: value iteration (the FP32 tiles' sweeps
+// with groups & 1, the FP64 tiles' with groups & 2) or policy-iteration
+// correction sweeps (FP32).
+int graph_for(cpmdp_batch_t* b, int k, hipGraphExec_t* out, bool eval = false, int groups = 3) {
   // the launches capture their arguments (tile size, schedule) and grid
-  const int64_t cfg = ((static_cast<int64_t>(eval) * 2 + b->sched) * 1000 + k) * 100000 + b->tile_states;
+  const int64_t cfg =
+      (((static_cast<int64_t>(groups) * 2 + eval) * 2 + b->sched) * 1000 + k) * 100000 + b->tile_states;
   auto key = std::make_pair(cfg, b->grid);
   auto it = b->graphs.find(key);
   if (it != b->graphs.end()) {
@@ -782,7 +814,7 @@ int graph_for(cpmdp_batch_t* b, int k, hipGraphExec_t* out, bool eval = false) {
   // sweeps are two independent chains (a fork onto stream64 and a join), and
   // the launches of one precision need not wait for the other's.
   hipEvent_t fork = nullptr, join = nullptr;
-  if (!eval) {
+  if (!eval && groups == 3) {
     BHIP(b, hipEventCreateWithFlags(&fork, hipEventDisableTiming));
     BHIP(b, hipEventCreateWithFlags(&join, hipEventDisableTiming));
   }
@@ -791,6 +823,16 @@ int graph_for(cpmdp_batch_t* b, int k, hipGraphExec_t* out, bool eval = false) {
     for (int j = 0; j < k; ++j)
       hipLaunchKernelGGL((batch_sweep_kernel<float, MODE_EVAL>), dim3(b->grid), dim3(kBBlock), 0,
                          b->stream, a, j);
+  } else if (groups != 3) {
+    // one precision active: a single chain, without the other's empty launches
+    for (int j = 0; j < k; ++j) {
+      if (groups == 1)
+        hipLaunchKernelGGL((batch_sweep_kernel<float, MODE_MAX>), dim3(b->grid), dim3(kBBlock), 0,
+                           b->stream, a, j);
+      else
+        hipLaunchKernelGGL((batch_sweep_kernel<double, MODE_MAX>), dim3(b->grid), dim3(kBBlock), 0,
+                           b->stream, a, j);
+    }
   } else {
     (void)hipEventRecord(fork, b->stream);
     (void)hipStreamWaitEvent(b->stream64, fork, 0);
@@ -821,22 +863,33 @@ void clear_graphs(cpmdp_batch_t* b) {
   b->graphs.clear();
 }
 
-int zero_res(cpmdp_batch_t* b, int k) {
-  launch_fill_u64(b->d_res, k * static_cast<int>(b->hs.size()) * kBSpread, 0ull, b->stream);
+// Zero k sweeps' residual slots, and with cert the certificate slot ahead of them.
+int zero_res(cpmdp_batch_t* b, int k, bool cert = false) {
+  const int c = cert ? 1 : 0;
+  launch_fill_u64(cert ? b->d_cres : b->d_res, (k + c) * static_cast<int>(b->hs.size()) * kBSpread,
+                  0ull, b->stream);
   return CPMDP_OK;
 }
 
-// Max over each (sweep, instance) slot's kBSpread words.
-int read_res(cpmdp_batch_t* b, int k, std::vector<double>& out) {
+// Max over each (sweep, instance) slot's kBSpread words: k sweeps' slots into
+// out and, with cert, the certificate slot into *cert (one copy, one wait).
+int read_res(cpmdp_batch_t* b, int k, std::vector<double>& out, std::vector<double>* cert = nullptr) {
   const size_t n = b->hs.size();
-  BHIP(b, hipMemcpyAsync(b->h_res, b->d_res, k * n * kBSpread * 8, hipMemcpyDeviceToHost, b->stream));
+  const size_t c = cert ? 1 : 0;
+  BHIP(b, hipMemcpyAsync(b->h_res, cert ? b->d_cres : b->d_res, (k + c) * n * kBSpread * 8,
+                         hipMemcpyDeviceToHost, b->stream));
   BHIP(b, hipStreamSynchronize(b->stream));
-  out.assign(k * n, 0.0);
-  for (size_t i = 0; i < k * n; ++i) {
-    unsigned long long m = 0;
-    for (int w = 0; w < kBSpread; ++w) m = std::max(m, b->h_res[i * kBSpread + w]);
-    out[i] = bits_to_double(m);
-  }
+  auto reduce = [&](size_t first, size_t slots, std::vector<double>& o) {
+    o.assign(slots * n, 0.0);
+    const unsigned long long* src = b->h_res + first * n * kBSpread;
+    for (size_t i = 0; i < slots * n; ++i) {
+      unsigned long long m = 0;
+      for (int w = 0; w < kBSpread; ++w) m = std::max(m, src[i * kBSpread + w]);
+      o[i] = bits_to_double(m);
+    }
+  };
+  if (cert) reduce(0, 1, *cert);
+  reduce(c, static_cast<size_t>(k), out);
   return CPMDP_OK;
 }
 
@@ -870,7 +923,7 @@ int time_config(cpmdp_batch_t* b, int ts, int grid, int march, int sched, int k,
   rc = upload_tiles(b, all, &nt, true);
   if (rc) return rc;
   hipGraphExec_t ex;
-  rc = graph_for(b, k, &ex);
+  rc = graph_for(b, k, &ex, false, 1);
   if (rc) return rc;
   zero_res(b, k);
   BHIP(b, hipGraphLaunch(ex, b->stream));   // warm
@@ -1146,11 +1199,14 @@ int cpmdp_batch_bind(cpmdp_batch_t* b, void* ws, size_t bytes, void* stream) {
   b->user_stream = static_cast<hipStream_t>(stream);
   if (!b->stream) BHIP(b, hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
   if (!b->stream64) BHIP(b, hipStreamCreateWithFlags(&b->stream64, hipStreamNonBlocking));
-  if (!b->tiles_copied) BHIP(b, hipEventCreateWithFlags(&b->tiles_copied, hipEventDisableTiming));
+  for (auto& ev : b->tiles_copied)
+    if (!ev) BHIP(b, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
   if (!b->descs_copied) BHIP(b, hipEventCreateWithFlags(&b->descs_copied, hipEventDisableTiming));
   if (!b->jobs_copied) BHIP(b, hipEventCreateWithFlags(&b->jobs_copied, hipEventDisableTiming));
-  b->tiles_pending = false;
+  b->tiles_pending[0] = b->tiles_pending[1] = false;
+  b->tiles_valid = false;
   b->descs_pending = false;
+  b->descs_valid = false;
   clear_graphs(b);
   const size_t n = b->hs.size();
   b->max_tiles = count_tiles(b, kMinTile);
@@ -1163,7 +1219,8 @@ int cpmdp_batch_bind(cpmdp_batch_t* b, void* ws, size_t bytes, void* stream) {
   b->d_insts = reinterpret_cast<BInst*>(take(n * sizeof(BInst)));
   b->d_tiles = reinterpret_cast<int2*>(take(b->max_tiles * sizeof(int2)));
   b->d_ntiles = reinterpret_cast<int*>(take(64));
-  b->d_res = reinterpret_cast<unsigned long long*>(take(static_cast<size_t>(kBMaxK) * n * kBSpread * 8));
+  b->d_cres = reinterpret_cast<unsigned long long*>(take(static_cast<size_t>(kBMaxK + 1) * n * kBSpread * 8));
+  b->d_res = b->d_cres + n * kBSpread;
   b->d_vmax = reinterpret_cast<unsigned long long*>(take(n * 8));
   b->d_changes = reinterpret_cast<unsigned int*>(take(n * 4));
   b->d_starts = reinterpret_cast<int*>(take(2 * (kMaxBlocks + 1) * sizeof(int)));
@@ -1172,10 +1229,12 @@ int cpmdp_batch_bind(cpmdp_batch_t* b, void* ws, size_t bytes, void* stream) {
     BHIP(b, hipHostMalloc(reinterpret_cast<void**>(&b->h_jobs), 2 * n * sizeof(CopyJob), hipHostMallocDefault));
     BHIP(b, hipHostMalloc(reinterpret_cast<void**>(&b->h_changes), n * 4, hipHostMallocDefault));
     BHIP(b, hipHostMalloc(reinterpret_cast<void**>(&b->h_descs), n * sizeof(BInst), hipHostMallocDefault));
-    BHIP(b, hipHostMalloc(reinterpret_cast<void**>(&b->h_starts), 2 * (kMaxBlocks + 1) * sizeof(int), hipHostMallocDefault));
-    BHIP(b, hipHostMalloc(reinterpret_cast<void**>(&b->h_res), static_cast<size_t>(kBMaxK) * n * kBSpread * 8, hipHostMallocDefault));
-    BHIP(b, hipHostMalloc(reinterpret_cast<void**>(&b->h_tiles), b->max_tiles * sizeof(int2), hipHostMallocDefault));
-    BHIP(b, hipHostMalloc(reinterpret_cast<void**>(&b->h_ntiles), 64, hipHostMallocDefault));
+    for (int q = 0; q < 2; ++q) {
+      BHIP(b, hipHostMalloc(reinterpret_cast<void**>(&b->h_starts[q]), 2 * (kMaxBlocks + 1) * sizeof(int), hipHostMallocDefault));
+      BHIP(b, hipHostMalloc(reinterpret_cast<void**>(&b->h_tiles[q]), b->max_tiles * sizeof(int2), hipHostMallocDefault));
+      BHIP(b, hipHostMalloc(reinterpret_cast<void**>(&b->h_ntiles[q]), 64, hipHostMallocDefault));
+    }
+    BHIP(b, hipHostMalloc(reinterpret_cast<void**>(&b->h_res), static_cast<size_t>(kBMaxK + 1) * n * kBSpread * 8, hipHostMallocDefault));
   }
   b->hd.assign(n, BInst{});
   b->lay.assign(n, BLayout{});
@@ -1310,108 +1369,104 @@ int cpmdp_batch_solve(cpmdp_batch_t* b, double* const* V_devs, int32_t* const* p
     rc = launch_util(b, std::vector<char>(n, 1), 0);   // V32 <- V64
     if (rc) return rc;
   }
-  std::vector<double> res;
+  std::vector<double> res, cres;
   for (;;) {
     std::vector<char> active(n, 0), conv(n, 0), certq(n, 0);
     bool any_active = false, any_cert = false;
+    int64_t act_states = 0;
     for (size_t i = 0; i < n; ++i) {
       active[i] = b->hd[i].stage == B_F32 ? 1 : (b->hd[i].stage == B_F64 ? 2 : 0);
       any_active = any_active || active[i];
+      if (active[i]) act_states += b->lay[i].Sp;
       certq[i] = b->hd[i].stage == B_CERT;
       any_cert = any_cert || certq[i];
     }
     if (!any_active && !any_cert) break;
+    // Longer replays once few states are left: their sweeps take a few
+    // microseconds, the host round trip between replays far more (an
+    // instance that stops early skips the rest of the replay on the device)
+    int k = 0, groups = 0;
+    for (size_t i = 0; i < n; ++i) groups |= active[i];   // 1: FP32 tiles, 2: FP64 tiles
     if (any_active) {
-      int64_t nt = 0;
-      rc = upload_descs(b);
-      if (rc) return rc;
-      rc = upload_tiles(b, active, &nt, true);
-      if (rc) return rc;
-      // Longer replays once few states are left: their sweeps take a few
-      // microseconds, the host round trip between replays far more (an
-      // instance that stops early skips the rest of the replay on the device)
-      int64_t act_states = 0;
-      for (size_t i = 0; i < n; ++i)
-        if (active[i]) act_states += b->lay[i].Sp;
       const int kk = act_states * 100 < b->total_states ? 4 * b->k
                      : act_states * 10 < b->total_states ? 2 * b->k : b->k;
       int64_t left = std::min(kk, kBMaxK);
       for (size_t i = 0; i < n; ++i)
         if (active[i]) left = std::min<int64_t>(left, max_iter - 1 - sweeps[i]);
-      const int k = static_cast<int>(std::max<int64_t>(left, 1));
-      hipGraphExec_t ex;
-      rc = graph_for(b, k, &ex);
-      if (rc) return rc;
-      zero_res(b, k);
-      BHIP(b, hipGraphLaunch(ex, b->stream));
-      rc = read_res(b, k, res);
-      if (rc) return rc;
-      for (size_t i = 0; i < n; ++i) {
-        if (!active[i]) continue;
-        BInst& d = b->hd[i];
-        // sweeps run in this replay: up to and including the first one whose
-        // residual met the stop threshold (later ones were skipped)
-        int ran = k;
-        for (int j = 0; j < k; ++j)
-          if (res[static_cast<size_t>(j) * n + i] <= d.stop) {
-            ran = j + 1;
-            break;
-          }
-        sweeps[i] += ran;
-        d.parity ^= (ran & 1);
-        const double r_first = res[i];
-        const double r = res[static_cast<size_t>(ran - 1) * n + i];
-        if (!std::isfinite(r)) return bfail(b, CPMDP_E_NONFINITE, "non-finite value in a batched sweep");
-        const bool capped = sweeps[i] >= max_iter - 1;
-        if (d.stage == B_F32) {
-          const double gk = std::pow(b->hs[i]->gamma, 0.5 * (ran - 1));
-          const bool at_floor = r <= d.stop ||
-                                (r <= 8.0 * floor32[i] && ran >= 8 && r > gk * r_first);
-          if (at_floor || capped) {
-            conv[i] = 1;
-            d.stage = capped ? B_CERT : B_F64;
-            d.stop = eps;
-          }
-        } else if (r <= eps || capped) {
-          d.stage = B_CERT;
-        }
-      }
-      bool any_conv = false;
-      for (size_t i = 0; i < n; ++i) any_conv = any_conv || conv[i];
-      if (any_conv) {
-        rc = upload_descs(b);
-        if (rc) return rc;
-        rc = launch_util(b, conv, 1);   // V64 <- V32 for instances leaving FP32
-        if (rc) return rc;
-      }
+      k = static_cast<int>(std::max<int64_t>(left, 1));
     }
-    // certificates
-    std::vector<char> cq(n, 0);
-    bool any = false;
-    for (size_t i = 0; i < n; ++i) {
-      cq[i] = b->hd[i].stage == B_CERT;
-      any = any || cq[i];
-    }
-    if (any) {
-      rc = upload_descs(b);
-      if (rc) return rc;
-      rc = launch_util(b, cq, 2);   // vmax
+    // One round trip: the certificates of the instances whose sweeps ended
+    // in the last replay go on the stream ahead of the next replay of the
+    // others (disjoint instances), and one read returns both results.
+    zero_res(b, k, any_cert);
+    rc = upload_descs(b);
+    if (rc) return rc;
+    if (any_cert) {
+      rc = launch_util(b, certq, 2);   // vmax
       if (rc) return rc;
       int64_t nt = 0;
-      rc = upload_tiles(b, cq, &nt);
+      rc = upload_tiles(b, certq, &nt);   // the table launch_util left on the device
       if (rc) return rc;
-      zero_res(b, 1);
-      hipLaunchKernelGGL(batch_cert_kernel, dim3(b->grid), dim3(kBBlock), 0, b->stream, make_args(b), 0);
+      BatchArgs ca = make_args(b);
+      ca.res = b->d_cres;
+      hipLaunchKernelGGL(batch_cert_kernel, dim3(b->grid), dim3(kBBlock), 0, b->stream, ca, 0);
       BHIP(b, hipGetLastError());
-      rc = read_res(b, 1, res);
+    }
+    if (any_active) {
+      int64_t nt = 0;
+      rc = upload_tiles(b, active, &nt, true);
       if (rc) return rc;
-      for (size_t i = 0; i < n; ++i) {
-        if (!cq[i]) continue;
-        sweeps[i] += 1;
-        cert[i] = res[i];
-        if (!std::isfinite(cert[i])) return bfail(b, CPMDP_E_NONFINITE, "non-finite certificate");
-        b->hd[i].stage = (cert[i] <= eps || sweeps[i] >= max_iter) ? B_DONE : B_F64;
+      hipGraphExec_t ex;
+      rc = graph_for(b, k, &ex, false, groups);
+      if (rc) return rc;
+      BHIP(b, hipGraphLaunch(ex, b->stream));
+    }
+    rc = read_res(b, k, res, any_cert ? &cres : nullptr);
+    if (rc) return rc;
+    for (size_t i = 0; i < n; ++i) {
+      if (!certq[i]) continue;
+      sweeps[i] += 1;
+      cert[i] = cres[i];
+      if (!std::isfinite(cert[i])) return bfail(b, CPMDP_E_NONFINITE, "non-finite certificate");
+      b->hd[i].stage = (cert[i] <= eps || sweeps[i] >= max_iter) ? B_DONE : B_F64;
+    }
+    for (size_t i = 0; i < n; ++i) {
+      if (!active[i]) continue;
+      BInst& d = b->hd[i];
+      // sweeps run in this replay: up to and including the first one whose
+      // residual met the stop threshold (later ones were skipped)
+      int ran = k;
+      for (int j = 0; j < k; ++j)
+        if (res[static_cast<size_t>(j) * n + i] <= d.stop) {
+          ran = j + 1;
+          break;
+        }
+      sweeps[i] += ran;
+      d.parity ^= (ran & 1);
+      const double r_first = res[i];
+      const double r = res[static_cast<size_t>(ran - 1) * n + i];
+      if (!std::isfinite(r)) return bfail(b, CPMDP_E_NONFINITE, "non-finite value in a batched sweep");
+      const bool capped = sweeps[i] >= max_iter - 1;
+      if (d.stage == B_F32) {
+        const double gk = std::pow(b->hs[i]->gamma, 0.5 * (ran - 1));
+        const bool at_floor = r <= d.stop ||
+                              (r <= 8.0 * floor32[i] && ran >= 8 && r > gk * r_first);
+        if (at_floor || capped) {
+          conv[i] = 1;
+          d.stage = capped ? B_CERT : B_F64;
+          d.stop = eps;
+        }
+      } else if (r <= eps || capped) {
+        d.stage = B_CERT;
       }
+    }
+    bool any_conv = false;
+    for (size_t i = 0; i < n; ++i) any_conv = any_conv || conv[i];
+    if (any_conv) {
+      rc = upload_descs(b);
+      if (rc) return rc;
+      rc = launch_util(b, conv, 1);   // V64 <- V32 for instances leaving FP32
+      if (rc) return rc;
     }
   }
   bool all_ok = true;
@@ -1580,15 +1635,17 @@ void cpmdp_batch_destroy(cpmdp_batch_t* b) {
   if (b->stream) (void)hipStreamDestroy(b->stream);
   if (b->stream64) (void)hipStreamDestroy(b->stream64);
   if (b->h_res) (void)hipHostFree(b->h_res);
-  if (b->h_tiles) (void)hipHostFree(b->h_tiles);
-  if (b->h_ntiles) (void)hipHostFree(b->h_ntiles);
+  for (int q = 0; q < 2; ++q) {
+    if (b->h_tiles[q]) (void)hipHostFree(b->h_tiles[q]);
+    if (b->h_ntiles[q]) (void)hipHostFree(b->h_ntiles[q]);
+    if (b->h_starts[q]) (void)hipHostFree(b->h_starts[q]);
+    if (b->tiles_copied[q]) (void)hipEventDestroy(b->tiles_copied[q]);
+  }
   if (b->h_changes) (void)hipHostFree(b->h_changes);
-  if (b->tiles_copied) (void)hipEventDestroy(b->tiles_copied);
   if (b->descs_copied) (void)hipEventDestroy(b->descs_copied);
   if (b->jobs_copied) (void)hipEventDestroy(b->jobs_copied);
   if (b->h_jobs) (void)hipHostFree(b->h_jobs);
   if (b->h_descs) (void)hipHostFree(b->h_descs);
-  if (b->h_starts) (void)hipHostFree(b->h_starts);
   delete b;
 }
 
