@@ -166,6 +166,45 @@ def test_batch_marching_tiles_match_oracle(B, march_batch, method, sched):
         compare_policy(pi, oracle.sparse.q_values(x, mats, Vs), eps / (1 - x.gamma) + 1e-10)
 
 
+def test_repeated_solves_on_one_batch(B, march_batch):
+    """One bound batch solved again and again with other methods and
+    precisions, a timing run in between: the tile tables and descriptors the
+    batch keeps on the device between calls (and re-copies only when they
+    change) must follow each call's own stages and tile sets."""
+    insts, refs = march_batch
+    log("[batch] repeated solves on one bound batch")
+    eps = 1e-7
+    bm = B.BatchModel(insts)
+    Vs = [torch.zeros(x.n_states, dtype=torch.float64, device="cuda") for x in insts]
+    pis = [torch.zeros(x.n_states, dtype=torch.int32, device="cuda") for x in insts]
+
+    def check(tag, prec, method, reset=True):
+        if reset:
+            for V, p in zip(Vs, pis):
+                V.zero_()
+                p.zero_()
+        code, sweeps, res = B.cpmdp_batch_solve(bm.b, Vs, pis, eps, 200000, prec, method)
+        torch.cuda.synchronize()
+        assert code in (B.CPMDP_OK, B.CPMDP_POLICY_UNSETTLED), (tag, code)
+        assert np.all(res <= eps), (tag, res)
+        for x, (mats, Vr), V, p in zip(insts, refs, Vs, pis):
+            assert_close(V.cpu().numpy(), Vr, eps / (1 - x.gamma) + 1e-10, f"{tag} {x.name}")
+            compare_policy(p.cpu().numpy(), oracle.sparse.q_values(x, mats, Vr),
+                           eps / (1 - x.gamma) + 1e-10)
+        return sweeps
+
+    first = check("vi fp32", 1, 0)
+    B.cpmdp_batch_time_sweeps(bm.b, 3)          # stages and tables of a timing run
+    assert np.array_equal(check("vi fp32 again", 1, 0), first)
+    check("pi", 1, 1)
+    check("vi fp64", 0, 0)
+    # from the converged values: far fewer sweeps than from V0 = 0 (the FP32
+    # stage rounds V, which a few FP64 sweeps take back below eps)
+    warm = check("vi fp32 warm", 1, 0, reset=False)
+    assert np.all(warm < 0.5 * first), (warm, first)
+    bm.close()
+
+
 def test_batch_equals_single_solves_and_autotune(B):
     insts = _small_batch(count=9, seed=11)
     log("[batch] vs single-instance solves, autotuned")
