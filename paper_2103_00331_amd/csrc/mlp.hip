@@ -131,7 +131,11 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, const fl
 // D[i = 4 g + r][n = c].
 typedef float mlp_f4 __attribute__((ext_vector_type(4)));
 
-template <bool TA, bool TB, int WM, int WN, int EPI>
+// VA / VB: the operand's leading dimension is a multiple of 4 and its base
+// 16-byte aligned, so a full tile's slice of it is read with 16-byte loads
+// (four consecutive words along the operand's contiguous index) instead of
+// one word per load.
+template <bool TA, bool TB, int WM, int WN, int EPI, bool VA, bool VB>
 __global__ __launch_bounds__(256) void gemm_mfma_kernel(int M, int N, int K,
                                                         const float* __restrict__ A, int lda,
                                                         const float* __restrict__ B, int ldb,
@@ -169,9 +173,24 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(int M, int N, int K,
 #pragma unroll
     for (int j = 0; j < WN; ++j) acc[i][j] = mlp_f4{0.f, 0.f, 0.f, 0.f};
   float ra[LA], rb[LB];
+  bool va = false, vb = false;   // the slice in ra / rb was read in groups of 4
   auto fetch = [&](int k0) {
     const bool ka = k0 + KT <= ke;
-    if (ka && m0 + BM <= M) {
+    va = VA && ka && m0 + BM <= M;
+    vb = VB && ka && n0 + BN <= N;
+    if (va) {
+      // group i of 4 words -> (row or column, k) of its first word, the 4
+      // words consecutive along the contiguous index (m for TA, else k)
+#pragma unroll
+      for (int q = 0; q < LA / 4; ++q) {
+        const int i = threadIdx.x + q * 256;
+        int r, kk;
+        if (TA) { r = (i % (BM / 4)) * 4; kk = i / (BM / 4); }
+        else { r = i / (KT / 4); kk = (i % (KT / 4)) * 4; }
+        const float4 v = *reinterpret_cast<const float4*>(A + aidx(m0 + r, k0 + kk));
+        ra[4 * q] = v.x; ra[4 * q + 1] = v.y; ra[4 * q + 2] = v.z; ra[4 * q + 3] = v.w;
+      }
+    } else if (ka && m0 + BM <= M) {
 #pragma unroll
       for (int q = 0; q < LA; ++q) {
         int r, kk;
@@ -187,7 +206,17 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(int M, int N, int K,
         ra[q] = (gm < M && gk < ke) ? A[aidx(gm, gk)] : 0.f;
       }
     }
-    if (ka && n0 + BN <= N) {
+    if (vb) {
+#pragma unroll
+      for (int q = 0; q < LB / 4; ++q) {
+        const int i = threadIdx.x + q * 256;
+        int kk, cc;
+        if (TB) { kk = (i % (KT / 4)) * 4; cc = i / (KT / 4); }
+        else { kk = i / (BN / 4); cc = (i % (BN / 4)) * 4; }
+        const float4 v = *reinterpret_cast<const float4*>(B + bidx(k0 + kk, n0 + cc));
+        rb[4 * q] = v.x; rb[4 * q + 1] = v.y; rb[4 * q + 2] = v.z; rb[4 * q + 3] = v.w;
+      }
+    } else if (ka && n0 + BN <= N) {
 #pragma unroll
       for (int q = 0; q < LB; ++q) {
         int kk, cc;
@@ -206,17 +235,47 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(int M, int N, int K,
   };
   if (kb < ke) fetch(kb);
   for (int k0 = kb; k0 < ke; k0 += KT) {
+    if (VA && va) {
 #pragma unroll
-    for (int q = 0; q < LA; ++q) {
-      int r, kk;
-      amap(threadIdx.x + q * 256, r, kk);
-      As[kk][r] = ra[q];
+      for (int q = 0; q < LA / 4; ++q) {
+        const int i = threadIdx.x + q * 256;
+        int r, kk;
+        if (TA) { r = (i % (BM / 4)) * 4; kk = i / (BM / 4); }
+        else { r = i / (KT / 4); kk = (i % (KT / 4)) * 4; }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          if (TA) As[kk][r + e] = ra[4 * q + e];
+          else As[kk + e][r] = ra[4 * q + e];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < LA; ++q) {
+        int r, kk;
+        amap(threadIdx.x + q * 256, r, kk);
+        As[kk][r] = ra[q];
+      }
     }
+    if (VB && vb) {
 #pragma unroll
-    for (int q = 0; q < LB; ++q) {
-      int kk, cc;
-      bmap(threadIdx.x + q * 256, kk, cc);
-      Bs[kk][cc] = rb[q];
+      for (int q = 0; q < LB / 4; ++q) {
+        const int i = threadIdx.x + q * 256;
+        int kk, cc;
+        if (TB) { kk = (i % (KT / 4)) * 4; cc = i / (KT / 4); }
+        else { kk = i / (BN / 4); cc = (i % (BN / 4)) * 4; }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          if (TB) Bs[kk + e][cc] = rb[4 * q + e];
+          else Bs[kk][cc + e] = rb[4 * q + e];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < LB; ++q) {
+        int kk, cc;
+        bmap(threadIdx.x + q * 256, kk, cc);
+        Bs[kk][cc] = rb[q];
+      }
     }
     __syncthreads();
     if (k0 + KT < ke) fetch(k0 + KT);
@@ -566,17 +625,30 @@ static void gemm(int M, int N, int K, const float* A, int lda, const float* B, i
     if (ks > K / 128) ks = K / 128;
     if (static_cast<int64_t>(ks) * M * N > kSplitWords) ks = static_cast<int>(kSplitWords / (M * N));
   }
+  // 16-byte slice loads for each operand that allows them (not the 130-wide
+  // feature rows)
+  const bool va = lda % 4 == 0 && (reinterpret_cast<uintptr_t>(A) & 15) == 0;
+  const bool vb = ldb % 4 == 0 && (reinterpret_cast<uintptr_t>(B) & 15) == 0;
   auto launch = [&](dim3 grid, float* out, int ldo, int kc) {
-    if (big)
-      hipLaunchKernelGGL((gemm_mfma_kernel<TA, TB, 4, 4, EPI>), grid, dim3(256), 0, st, M, N, K, A,
-                         lda, B, ldb, out, ldo, bias, mask, ldm, kc);
-    else if (mfma)
-      hipLaunchKernelGGL((gemm_mfma_kernel<TA, TB, 2, 2, EPI>), grid, dim3(256), 0, st, M, N, K, A,
-                         lda, B, ldb, out, ldo, bias, mask, ldm, kc);
-    else
+#define CPM_GEMM_MFMA(W, VA_, VB_)                                                            \
+  hipLaunchKernelGGL((gemm_mfma_kernel<TA, TB, W, W, EPI, VA_, VB_>), grid, dim3(256), 0, st, M, N, \
+                     K, A, lda, B, ldb, out, ldo, bias, mask, ldm, kc)
+    if (big) {
+      if (va && vb) CPM_GEMM_MFMA(4, true, true);
+      else if (vb) CPM_GEMM_MFMA(4, false, true);
+      else if (va) CPM_GEMM_MFMA(4, true, false);
+      else CPM_GEMM_MFMA(4, false, false);
+    } else if (mfma) {
+      if (va && vb) CPM_GEMM_MFMA(2, true, true);
+      else if (vb) CPM_GEMM_MFMA(2, false, true);
+      else if (va) CPM_GEMM_MFMA(2, true, false);
+      else CPM_GEMM_MFMA(2, false, false);
+    } else {
       hipLaunchKernelGGL((gemm_kernel<TA, TB, EPI>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb,
                          out, ldo, bias, mask, ldm, kc);
+    }
   };
+#undef CPM_GEMM_MFMA
   if (ks <= 1) {
     launch(dim3((N + TN - 1) / TN, (M + TM - 1) / TM), C, ldc, K);
     return;
