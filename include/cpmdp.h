@@ -549,7 +549,7 @@ int cpmdp_mlp_predict_levels(const float* params, const float* const* R, const d
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid allocation): the same
  * prediction as cpmdp_mlp_predict, with the workspace in the library's own
- * static device array (30.2 MiB per GPU, the workspace of 4096 rows, held
+ * static device array (30.3 MiB per GPU, the workspace of 4096 rows, held
  * until the process ends) instead of an argument.  No allocation of any
  * kind.  chunk must be in [1, 4096], else CPMDP_E_ARG; other arguments and
  * results as in cpmdp_mlp_predict.  Every call on one GPU uses that GPU's one

@@ -22,6 +22,7 @@
 namespace cpm {
 
 constexpr int kF = 130;        // features
+constexpr int kXS = 132;       // row stride of the workspace's feature rows (16-byte aligned rows)
 constexpr int kH = 256;        // hidden width
 constexpr int64_t kOffW1 = 0;
 constexpr int64_t kOffB1 = kOffW1 + kF * kH;
@@ -708,33 +709,35 @@ __device__ __forceinline__ float feature_at(const float* R, int m, FastDiv dm, f
 }
 
 // All states s0 .. s0+count-1 of one instance, one thread per (state,
-// feature): consecutive threads write consecutive words of X.  IDX is the
-// word-index type (32-bit while count * 130 < 2^31).
+// feature): consecutive threads write consecutive words of a row of X (row
+// stride ldx >= 130).  IDX is the word-index type (32-bit while
+// count * ldx < 2^31).
 template <typename IDX>
 __global__ void features_range_kernel(const float* R, int m, FastDiv dm, float gamma, float slip,
-                                      int s0, int count, float* X) {
+                                      int s0, int count, float* X, int ldx) {
   const IDX total = static_cast<IDX>(count) * kF;
   const IDX stride = static_cast<IDX>(gridDim.x) * blockDim.x;
   for (IDX e = static_cast<IDX>(blockIdx.x) * blockDim.x + threadIdx.x; e < total; e += stride) {
     const IDX i = e / kF;
-    X[e] = feature_at(R, m, dm, gamma, slip, s0 + static_cast<int>(i), static_cast<int>(e - i * kF));
+    const int f = static_cast<int>(e - i * kF);
+    X[i * static_cast<IDX>(ldx) + f] = feature_at(R, m, dm, gamma, slip, s0 + static_cast<int>(i), f);
   }
 }
 
 static void launch_features_range(const float* R, int m, float gamma, float slip, int s0, int count,
-                                  float* X, hipStream_t st) {
+                                  float* X, int ldx, hipStream_t st) {
   const FastDiv dm = make_fastdiv(static_cast<uint32_t>(m));
   const int blocks = feature_blocks(count);
-  if (static_cast<int64_t>(count) * kF < (int64_t{1} << 31))
+  if (static_cast<int64_t>(count) * ldx < (int64_t{1} << 31))
     hipLaunchKernelGGL(features_range_kernel<uint32_t>, dim3(blocks), dim3(256), 0, st, R, m, dm,
-                       gamma, slip, s0, count, X);
+                       gamma, slip, s0, count, X, ldx);
   else
     hipLaunchKernelGGL(features_range_kernel<int64_t>, dim3(blocks), dim3(256), 0, st, R, m, dm,
-                       gamma, slip, s0, count, X);
+                       gamma, slip, s0, count, X, ldx);
 }
 
 // n states spread evenly over an instance of S states: sample j is state
-// floor(j S / n); one thread per (sample, feature).
+// floor(j S / n); one thread per (sample, feature); rows of kXS words.
 __global__ void features_spread_kernel(const float* R, int m, FastDiv dm, float gamma, float slip,
                                        int S, int n, float* X) {
   const int64_t total = static_cast<int64_t>(n) * kF;
@@ -742,14 +745,16 @@ __global__ void features_spread_kernel(const float* R, int m, FastDiv dm, float 
   for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < total; e += stride) {
     const int64_t j = e / kF;
     const int st = static_cast<int>(j * S / n);
-    X[e] = feature_at(R, m, dm, gamma, slip, st, static_cast<int>(e - j * kF));
+    const int f = static_cast<int>(e - j * kF);
+    X[j * kXS + f] = feature_at(R, m, dm, gamma, slip, st, f);
   }
 }
 
 // Minibatch: sample i -> (instance, state) drawn with SplitMix64 from
 // (seed, step, i); features and the target (1 - gamma) V*(s).
-// One thread per (sample, feature); every thread of a sample draws the same
-// (instance, state), the feature-0 thread also writes the target.
+// One thread per (sample, feature), rows of kXS words; every thread of a
+// sample draws the same (instance, state), the feature-0 thread also writes
+// the target.
 __global__ void features_sample_kernel(const float* const* R_ptrs, const double* const* V_ptrs,
                                        const double* gammas, const double* slips, int n_inst,
                                        int m, FastDiv dm, uint64_t seed, int64_t step, int count,
@@ -764,8 +769,8 @@ __global__ void features_sample_kernel(const float* const* R_ptrs, const double*
                                                     static_cast<uint64_t>(i)));
     const int inst = static_cast<int>((r >> 32) % static_cast<uint64_t>(n_inst));
     const int s = static_cast<int>((r & 0xFFFFFFFFull) % static_cast<uint64_t>(S));
-    X[e] = feature_at(R_ptrs[inst], m, dm, static_cast<float>(gammas[inst]),
-                      static_cast<float>(slips[inst]), s, f);
+    X[static_cast<int64_t>(i) * kXS + f] = feature_at(R_ptrs[inst], m, dm, static_cast<float>(gammas[inst]),
+                                                      static_cast<float>(slips[inst]), s, f);
     if (f == 0)
       t[i] = static_cast<float>(((1.0 - gammas[inst]) * V_ptrs[inst][s] - kOutMean) / kOutScale);
   }
@@ -871,7 +876,7 @@ static constexpr size_t al(size_t x) { return (x + 255) & ~static_cast<size_t>(2
 
 constexpr size_t mlp_ws_bytes(int B) {
   const size_t b = static_cast<size_t>(B);
-  return al(b * kF * 4) + 4 * al(b * kH * 4) + 3 * al(b * 4) + al(b * 4) + al(64) +
+  return al(b * kXS * 4) + 4 * al(b * kH * 4) + 3 * al(b * 4) + al(b * 4) + al(64) +
          al(static_cast<size_t>(kSplitWords) * 4) + al(static_cast<size_t>(kColsumChunks) * kH * 4) +
          al(static_cast<size_t>(kSplitMax) * kF * kH * 4);
 }
@@ -885,7 +890,7 @@ MlpWs carve(void* ws, int B) {
   };
   const size_t b = static_cast<size_t>(B);
   MlpWs w{};
-  w.X = reinterpret_cast<float*>(take(b * kF * 4));
+  w.X = reinterpret_cast<float*>(take(b * kXS * 4));
   w.H1 = reinterpret_cast<float*>(take(b * kH * 4));
   w.H2 = reinterpret_cast<float*>(take(b * kH * 4));
   w.dH1 = reinterpret_cast<float*>(take(b * kH * 4));
@@ -902,12 +907,13 @@ MlpWs carve(void* ws, int B) {
 
 // BF16 forward pass: first hidden layer stored as BF16 (in H1's space), the
 // second fused with the output layer (row partials in H2's space).
-static void forward_bf16(const float* P, const float* X, int M, const MlpWs& w, hipStream_t st) {
+static void forward_bf16(const float* P, const float* X, int ldx, int M, const MlpWs& w,
+                         hipStream_t st) {
   float* ypart = w.H2;
   if (M >= 32768) {
     const dim3 grid(kH / 128, (M + 127) / 128);
     hipLaunchKernelGGL((gemm_bf16_kernel<4, 4, false, true, false>), grid, dim3(256), 0, st, M, kH,
-                       kF, static_cast<const void*>(X), kF, P + kOffW1, kH, static_cast<void*>(w.H1),
+                       kF, static_cast<const void*>(X), ldx, P + kOffW1, kH, static_cast<void*>(w.H1),
                        kH, P + kOffB1, nullptr, nullptr);
     hipLaunchKernelGGL((gemm_bf16_kernel<4, 4, true, false, true>), grid, dim3(256), 0, st, M, kH,
                        kH, static_cast<const void*>(w.H1), kH, P + kOffW2, kH, nullptr, 0, P + kOffB2,
@@ -915,7 +921,7 @@ static void forward_bf16(const float* P, const float* X, int M, const MlpWs& w, 
   } else {
     const dim3 grid(kH / 64, (M + 63) / 64);
     hipLaunchKernelGGL((gemm_bf16_kernel<2, 2, false, true, false>), grid, dim3(256), 0, st, M, kH,
-                       kF, static_cast<const void*>(X), kF, P + kOffW1, kH, static_cast<void*>(w.H1),
+                       kF, static_cast<const void*>(X), ldx, P + kOffW1, kH, static_cast<void*>(w.H1),
                        kH, P + kOffB1, nullptr, nullptr);
     hipLaunchKernelGGL((gemm_bf16_kernel<2, 2, true, false, true>), grid, dim3(256), 0, st, M, kH,
                        kH, static_cast<const void*>(w.H1), kH, P + kOffW2, kH, nullptr, 0, P + kOffB2,
@@ -928,13 +934,15 @@ static void forward_bf16(const float* P, const float* X, int M, const MlpWs& w, 
 
 // with_dy: the output layer also writes dy, the loss gradient against w.t
 // (training steps whose loss is not read)
-void forward(const float* P, const float* X, int B, const MlpWs& w, hipStream_t st, bool bf16,
-             bool with_dy = false) {
+// X: rows of ldx words (kXS for the workspace's own features, kF for a
+// caller's X [B][130]).
+void forward(const float* P, const float* X, int ldx, int B, const MlpWs& w, hipStream_t st,
+             bool bf16, bool with_dy = false) {
   if (bf16) {
-    forward_bf16(P, X, B, w, st);
+    forward_bf16(P, X, ldx, B, w, st);
     return;
   }
-  gemm<false, false, EPI_BIAS_RELU>(B, kH, kF, X, kF, P + kOffW1, kH, w.H1, kH, P + kOffB1, nullptr, 0, st);
+  gemm<false, false, EPI_BIAS_RELU>(B, kH, kF, X, ldx, P + kOffW1, kH, w.H1, kH, P + kOffB1, nullptr, 0, st);
   gemm<false, false, EPI_BIAS_RELU>(B, kH, kH, w.H1, kH, P + kOffW2, kH, w.H2, kH, P + kOffB2, nullptr, 0, st);
   if (with_dy) {
     const int blocks = std::min((B + 3) / 4, 8192);
@@ -1005,7 +1013,7 @@ SideStream* side_stream() {
 // product has its own partial area).  The same kernels in the same order per
 // stream: the result does not depend on how the two streams interleave.
 // have_dy: the forward pass already wrote dy (and the loss is not wanted).
-void backward(const float* P, const float* X, int B, const MlpWs& w, float* G, hipStream_t st,
+void backward(const float* P, const float* X, int ldx, int B, const MlpWs& w, float* G, hipStream_t st,
               bool have_dy = false) {
   const int nb = (B + 255) / 256;
   if (!have_dy)
@@ -1033,7 +1041,7 @@ void backward(const float* P, const float* X, int B, const MlpWs& w, float* G, h
   // layer 1: dW1 = X^T dH1, db1 = 1^T dH1
   fork(2);
   colsum(w.dH1, nullptr, B, kH, G + kOffB1, w.part2, so);
-  gemm<true, false, EPI_NONE>(kF, kH, B, X, kF, w.dH1, kH, G + kOffW1, kH, nullptr, nullptr, 0, st, w.part3);
+  gemm<true, false, EPI_NONE>(kF, kH, B, X, ldx, w.dH1, kH, G + kOffW1, kH, nullptr, nullptr, 0, st, w.part3);
   if (ss) {   // join: the caller's stream waits for the side stream's sums
     (void)hipEventRecord(ss->ev[3], so);
     (void)hipStreamWaitEvent(st, ss->ev[3], 0);
@@ -1043,7 +1051,7 @@ void backward(const float* P, const float* X, int B, const MlpWs& w, float* G, h
 int mfail(const std::string& m) { return fail(nullptr, CPMDP_E_ARG, m); }
 
 // Scratch of the allocation-free prediction (cpmdp_mlp_predict_noalloc):
-// the MLP workspace for chunks of up to kStaticRows rows, 30.2 MiB, held by
+// the MLP workspace for chunks of up to kStaticRows rows, 30.3 MiB, held by
 // every GPU the library runs on until the process ends.  Host code never
 // passes `scratch` itself (its host-side name is no device address): the
 // device address comes from hipGetSymbolAddress, once per device.
@@ -1106,7 +1114,7 @@ int cpmdp_mlp_features(const float* R, int32_t m, double gamma, double slip, int
       static_cast<int64_t>(s0) + count > static_cast<int64_t>(m) * m * m)
     return mfail("bad feature arguments");
   if (count == 0) return CPMDP_OK;
-  launch_features_range(R, m, static_cast<float>(gamma), static_cast<float>(slip), s0, count, X,
+  launch_features_range(R, m, static_cast<float>(gamma), static_cast<float>(slip), s0, count, X, kF,
                         static_cast<hipStream_t>(stream));
   return hipGetLastError() == hipSuccess ? CPMDP_OK : fail(nullptr, CPMDP_E_DEVICE, "features launch");
 }
@@ -1119,7 +1127,7 @@ int cpmdp_mlp_forward(const float* params, const float* X, int32_t count, float*
   if (ws_bytes < mlp_ws_bytes(count)) return fail(nullptr, CPMDP_E_WORKSPACE, "MLP workspace too small");
   const hipStream_t st = static_cast<hipStream_t>(stream);
   MlpWs w = carve(ws, count);
-  forward(params, X, count, w, st, precision == CPMDP_BF16);
+  forward(params, X, kF, count, w, st, precision == CPMDP_BF16);
   (void)hipMemcpyAsync(y, w.y, count * 4, hipMemcpyDeviceToDevice, st);
   return hipGetLastError() == hipSuccess ? CPMDP_OK : fail(nullptr, CPMDP_E_DEVICE, "forward launch");
 }
@@ -1132,8 +1140,8 @@ int cpmdp_mlp_loss_grad(const float* params, const float* X, const float* t, int
   MlpWs w = carve(ws, count);
   (void)hipMemcpyAsync(w.t, t, count * 4, hipMemcpyDeviceToDevice, st);
   hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, st, reinterpret_cast<float*>(w.loss), 2, 0.0f);
-  forward(params, X, count, w, st, false);
-  backward(params, X, count, w, grad, st);
+  forward(params, X, kF, count, w, st, false);
+  backward(params, X, kF, count, w, grad, st);
   if (hipGetLastError() != hipSuccess) return fail(nullptr, CPMDP_E_DEVICE, "loss_grad launch");
   if (loss_out) {
     if (hipMemcpyAsync(loss_out, w.loss, 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -1172,8 +1180,8 @@ int cpmdp_mlp_train_step(float* params, float* adam_m, float* adam_v, float* gra
                      Vstar_ptrs, gammas, slips, n_inst, m, make_fastdiv(static_cast<uint32_t>(m)),
                      seed, step, batch, w.X, w.t, w.loss);
   // without a loss to report, the output layer writes the loss gradient too
-  forward(params, w.X, batch, w, st, false, loss_out == nullptr);
-  backward(params, w.X, batch, w, grad, st, loss_out == nullptr);
+  forward(params, w.X, kXS, batch, w, st, false, loss_out == nullptr);
+  backward(params, w.X, kXS, batch, w, grad, st, loss_out == nullptr);
   int rc = cpmdp_mlp_adam(params, adam_m, adam_v, grad, step, lr, stream);
   if (rc) return rc;
   if (hipGetLastError() != hipSuccess) return fail(nullptr, CPMDP_E_DEVICE, "train_step launch");
@@ -1205,7 +1213,7 @@ int cpmdp_mlp_predict(const float* params, const float* R, int32_t m, double gam
     hipLaunchKernelGGL(features_spread_kernel, dim3(feature_blocks(n)), dim3(256), 0, st, R, m,
                        make_fastdiv(static_cast<uint32_t>(m)), static_cast<float>(gamma),
                        static_cast<float>(slip), S, n, w.X);
-    forward(params, w.X, n, w, st, precision == CPMDP_BF16);
+    forward(params, w.X, kXS, n, w, st, precision == CPMDP_BF16);
     // the split-K partial area is free once the forward pass is done
     double* part = reinterpret_cast<double*>(w.part);
     hipLaunchKernelGGL(level_partial_kernel, dim3(kLevelBlocks), dim3(256), 0, st, w.y, n, part);
@@ -1217,8 +1225,8 @@ int cpmdp_mlp_predict(const float* params, const float* R, int32_t m, double gam
   for (int s0 = 0; s0 < S; s0 += chunk) {
     const int cnt = std::min(chunk, S - s0);
     launch_features_range(R, m, static_cast<float>(gamma), static_cast<float>(slip), s0, cnt, w.X,
-                          st);
-    forward(params, w.X, cnt, w, st, precision == CPMDP_BF16);
+                          kXS, st);
+    forward(params, w.X, kXS, cnt, w, st, precision == CPMDP_BF16);
     hipLaunchKernelGGL(to_values_kernel, dim3((cnt + 255) / 256), dim3(256), 0, st, w.y, cnt,
                        1.0 / (1.0 - gamma), V0 + s0);
   }
@@ -1252,8 +1260,8 @@ int cpmdp_mlp_predict_levels(const float* params, const float* const* R, const d
   for (int i = 0; i < n_inst; ++i)
     hipLaunchKernelGGL(features_spread_kernel, dim3(feature_blocks(n)), dim3(256), 0, st, R[i], m, dm,
                        static_cast<float>(gammas[i]), static_cast<float>(slips[i]), S, n,
-                       w.X + static_cast<size_t>(i) * n * kF);
-  forward(params, w.X, rows, w, st, precision == CPMDP_BF16);
+                       w.X + static_cast<size_t>(i) * n * kXS);
+  forward(params, w.X, kXS, rows, w, st, precision == CPMDP_BF16);
   double* part = reinterpret_cast<double*>(w.part);
   for (int i = 0; i < n_inst; ++i)
     hipLaunchKernelGGL(level_partial_kernel, dim3(kLevelBlocks), dim3(256), 0, st,
