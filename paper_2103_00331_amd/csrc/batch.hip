@@ -1535,7 +1535,8 @@ int cpmdp_batch_autotune(cpmdp_batch_t* b, int tune, const char* cache_path) {
   b->grid = best_grid;
   b->march = best_march;
   b->sched = best_sched;
-  // host round trip (tile upload + residual read) in ms
+  // host round trip in ms: a residual read, and the tile table's upload,
+  // which (as between the replays of a solve) is only copied the first time
   std::vector<double> res;
   auto t0 = std::chrono::steady_clock::now();
   for (int r = 0; r < 5; ++r) {
