@@ -136,6 +136,17 @@ def test_batch_rejects_obstacles():
     B.cpmdp_destroy(h)
 
 
+def test_batch_rejects_empty_and_null_handles():
+    """A batch needs at least one created handle: an empty list and a NULL
+    handle are argument errors, before any device work."""
+    with pytest.raises(B.CpmdpError) as e:
+        B.cpmdp_batch_create([])
+    assert e.value.code == B.CPMDP_E_ARG
+    with pytest.raises(B.CpmdpError) as e:
+        B.cpmdp_batch_create([None])
+    assert e.value.code == B.CPMDP_E_ARG
+
+
 def test_batch_schedule_setter_validates():
     """Host-only: the schedule setter takes the documented values and refuses
     others before any device work."""

@@ -205,6 +205,24 @@ def test_repeated_solves_on_one_batch(B, march_batch):
     bm.close()
 
 
+@pytest.mark.parametrize("sizes", [[3], [5], [17]])
+def test_batch_of_one_tiny_instance(B, sizes):
+    """The degenerate batch: a single 1-D instance of a few states (one tile,
+    one row, padded to a multiple of 4 in the batch's layout), value and
+    policy iteration against the oracle."""
+    inst = I.grid_small(sizes, slip=0.1, gamma=0.95, seed=3)
+    mats = oracle.sparse.transition_csr(inst)
+    Vs, _, _, _ = oracle.sparse.value_iteration(inst, mats=mats, eps=1e-12)
+    eps = 1e-9
+    for method in (0, 1):
+        log(f"[batch] one instance of sizes {sizes}, method {method}")
+        code, out, sweeps, res = _solve_batch(B, [inst], 1, eps, method=method)
+        assert code == B.CPMDP_OK and np.all(res <= eps), (code, res)
+        V, pi = out[0]
+        assert_close(V, Vs, eps / (1 - inst.gamma) + 1e-10, f"{sizes} method {method}")
+        compare_policy(pi, oracle.sparse.q_values(inst, mats, Vs), eps / (1 - inst.gamma) + 1e-10)
+
+
 def test_batch_equals_single_solves_and_autotune(B):
     insts = _small_batch(count=9, seed=11)
     log("[batch] vs single-instance solves, autotuned")
