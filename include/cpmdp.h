@@ -423,10 +423,20 @@ int cpmdp_batch_bind(cpmdp_batch_t* b, void* dev_workspace, size_t bytes,
  *   V_devs : [count] device FP64 [S_i] buffers; in: V0_i, out: solution.
  *   pi_devs: [count] device int32 [S_i] buffers (policy out; for PI also in)
  *            or NULL.
+ *   eps    : > 0, the FP64 certificate each instance must meet.
+ *   max_iter: >= 1, cap on each instance's sweeps of any kind.
+ *   precision: CPMDP_FP64: FP64 sweeps only; CPMDP_FP32 (or CPMDP_BF16,
+ *            which this stencil path runs as FP32): FP32 sweeps until they
+ *            stop contracting, then FP64 sweeps; the certificate is FP64.
+ *            Policy iteration runs FP32 correction sweeps: with CPMDP_FP64
+ *            it returns CPMDP_E_UNSUPPORTED.
  *   method : 0 = value iteration, 1 = policy iteration.
- *   sweeps_out   : [count] int64 sweeps per instance, or NULL.
+ *   sweeps_out   : [count] int64 sweeps per instance (the certificate's
+ *                  included), or NULL.
  *   residual_out : [count] FP64 certificate per instance, or NULL.
- * Returns CPMDP_OK, CPMDP_NOT_CONVERGED if any instance hit max_iter, else
+ * The work is ordered after everything enqueued on the bound stream so far
+ * and has finished when the call returns.  Returns CPMDP_OK,
+ * CPMDP_NOT_CONVERGED if any instance hit max_iter, else
  * CPMDP_POLICY_UNSETTLED if policy iteration stopped so on any instance (as
  * in cpmdp_policy_iteration), or an error.
  */
