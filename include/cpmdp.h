@@ -410,11 +410,24 @@ const char* cpmdp_last_error(const cpmdp_t* h);
  * and the tile size / sweeps per graph come from a small autotuner.
  */
 
-/* Collect count created handles (not necessarily bound); the handles must
- * outlive the batch. */
+/* Collect count >= 1 created handles (not necessarily bound) into *out;
+ * the handles must outlive the batch, which cpmdp_batch_destroy frees.
+ * Every handle must be on the stencil path (shift / identity factors) with
+ * at most 4 dimensions and no obstacles, else CPMDP_E_UNSUPPORTED; count < 1
+ * or a NULL handle: CPMDP_E_ARG. */
 int cpmdp_batch_create(cpmdp_batch_t** out, cpmdp_t* const* handles,
                        int32_t count);
+/* Device bytes cpmdp_batch_bind needs: the batch's own copy of every
+ * instance (rows padded to a multiple of 4 states; rewards, terminal bits,
+ * two FP32 and two FP64 value buffers) plus tile tables and residual slots. */
 int cpmdp_batch_workspace_bytes(const cpmdp_batch_t* b, size_t* bytes);
+/* Lay the batch out in dev_workspace (caller-owned device memory of at least
+ * cpmdp_batch_workspace_bytes, 256-byte aligned, kept until the batch is
+ * destroyed or bound again; else CPMDP_E_WORKSPACE) and fill it from the
+ * handles' host-side rewards, terminal states and weights (the copies have
+ * finished when the call returns).  hip_stream is the caller's stream (NULL:
+ * the null stream): every later solve is ordered after the work enqueued on
+ * it. */
 int cpmdp_batch_bind(cpmdp_batch_t* b, void* dev_workspace, size_t bytes,
                      void* hip_stream);
 
