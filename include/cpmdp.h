@@ -486,6 +486,8 @@ int cpmdp_batch_schedule(const cpmdp_batch_t* b, int32_t* grid, int32_t* march,
  * kernel's own start and stop; *mean_ms = mean kernel time of one sweep.
  * A later cpmdp_batch_solve starts from the caller's V as usual. */
 int cpmdp_batch_time_sweeps(cpmdp_batch_t* b, int32_t n, double* mean_ms);
+/* Free the batch, its private streams, graphs and pinned staging buffers
+ * (not the handles, nor the caller's workspace); NULL is a no-op. */
 void cpmdp_batch_destroy(cpmdp_batch_t* b);
 
 /* ------------------------------------------------------- learned warm start
